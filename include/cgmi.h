@@ -1,0 +1,157 @@
+/*
+ * cgmi.h -- C ABI of the MI355X sparse conjugate-gradient library (libcgmi.so).
+ *
+ * The library runs the hot path of the paper's sparse CG (Section 3):
+ * CSR SpMV q = A p with the fused p^T q dot (Section 3.3), the fused
+ * x += alpha p, r -= alpha q, r^T r update, and p = r + beta p
+ * (Algorithm 1).  A contiguous block of rows [row_begin, row_end) runs on the
+ * GPU; the remaining rows (the host complement) run on host threads, and the
+ * shared search direction p is exchanged by explicit copies every iteration
+ * (Section 3.2 row split, Section 3.4 explicit-copy mode).
+ *
+ * Conventions for every entry point
+ *   - Matrices: CSR, int32 row pointers and column indices, float64 values,
+ *     square n x n, row_ptr[0] == 0, row_ptr non-decreasing, row_ptr[n] == nnz,
+ *     0 <= col < n, columns strictly increasing inside each row.  Passed as
+ *     HOST pointers, borrowed only for the duration of the call: the library
+ *     copies what it needs.
+ *   - Vectors (b, x, y): DEVICE pointers to n float64 values on the handle's
+ *     device (for example torch.cuda tensors), owned by the caller.
+ *   - Work is ordered on the handle's HIP stream (cg_set_stream; default:
+ *     the null stream).  Calls that say "blocking" return after the stream
+ *     has drained the work they queued.
+ *   - Return codes: CG_OK (0) success / converged, CG_MAXIT (1) the
+ *     iteration limit was reached (not an error; x holds the last iterate),
+ *     negative values are errors; cg_last_error() returns a message for the
+ *     last error on the calling thread.
+ *   - A handle may be used by one host thread at a time.
+ */
+#ifndef CGMI_H
+#define CGMI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    CG_OK = 0,
+    CG_MAXIT = 1,
+    CG_EINVAL = -1,      /* bad argument or malformed CSR                        */
+    CG_ENOMEM = -2,      /* host or device allocation failed                     */
+    CG_EDEVICE = -3,     /* a HIP call failed                                    */
+    CG_EBREAKDOWN = -4   /* p^T q <= 0 or not finite (matrix not SPD, NaN input) */
+};
+
+enum { CG_PREC_FP64 = 0, CG_PREC_MIXED = 1 };         /* cg_opts.precision */
+enum { CG_PC_NONE = 0, CG_PC_FSAI = 1 };              /* cg_opts.precond   */
+enum { CG_EXCHANGE_WHOLE = 0, CG_EXCHANGE_HALO = 1 };  /* cg_opts.exchange  */
+
+typedef struct cg_handle cg_handle;
+
+/* Solver options (cg_set_opts).  cg_default_opts() fills the defaults. */
+typedef struct cg_opts {
+    int32_t precision;     /* CG_PREC_FP64: float64 CG (Algorithm 1).
+                              CG_PREC_MIXED: float32 inner CG; the true residual
+                              b - A x, its norm and x stay float64 (reliable
+                              updates).  GPU-only handles.                       */
+    int32_t precond;       /* CG_PC_NONE, or CG_PC_FSAI: M^-1 = G^T G with the
+                              factor installed by cg_set_fsai.  GPU-only.        */
+    int32_t exchange;      /* split mode: CG_EXCHANGE_WHOLE copies the whole
+                              GPU-owned / host-owned segments of p each
+                              iteration (Section 3.4); CG_EXCHANGE_HALO copies
+                              only the entries the other side's rows read.      */
+    int32_t host_threads;  /* host complement threads (0: all available)        */
+    int32_t check_every;   /* GPU-only: iterations queued between host polls of
+                              the device convergence flag (>= 1)                */
+    int32_t profile;       /* 1: time every SpMV launch of cg_solve with HIP
+                              events (cg_result.t_spmv / n_spmv)                */
+    int32_t small_path;    /* 1 (default): systems that fit one workgroup's LDS
+                              run the whole solve in one single-workgroup kernel */
+    int32_t spmv_grid;     /* workgroups of the SpMV kernels (0: automatic)      */
+    int32_t spmv_kind;     /* SpMV tiling: 0 automatic, 1 vector CSR row-length
+                              bins (L lanes per row), 2 stream tiles (64 short
+                              rows, nonzeros loaded flat; used only when every
+                              tile fits, else 1), 3 sliced tiles (64-row slices
+                              stored slot-major, one lane per row; rows of at
+                              most 64 nonzeros, else 1).  Automatic picks 3
+                              when rows have <= 64 nonzeros and slicing pads by
+                              <= 25%, else 1.                                   */
+    int32_t reserved;      /* must be 0                                         */
+    double refine_delta;   /* mixed precision: a float64 refinement is made
+                              when the float32 residual drops by this factor    */
+} cg_opts;
+
+/* Per-solve record.  Times in seconds.  Fields follow the per-pass record of
+ * Section 4.1: solve time, iterations, convergence, residuals, CPU compute
+ * time, GPU task time, barrier time and D2H / H2D copy times; rows and
+ * nonzeros per side follow Section 3.2. */
+typedef struct cg_result {
+    int32_t status;          /* same value as the return code                    */
+    int32_t iterations;      /* CG iterations (SpMVs inside the loop)            */
+    int32_t converged;       /* 1 if the stop test was met                       */
+    int32_t fp64_residuals;  /* mixed precision: float64 residuals formed        */
+    double rel_res_recur;    /* sqrt(rho)/||b|| of the recurrence at exit        */
+    double rel_res_true;     /* ||b - A x|| / ||b|| recomputed after the solve   */
+    double t_solve;          /* wall time of the solve                           */
+    double t_gpu;            /* GPU kernel time (split mode: summed per phase)   */
+    double t_cpu;            /* host complement compute time                     */
+    double t_barrier;        /* time waiting at CPU/GPU synchronisation points  */
+    double t_d2h, t_h2d;     /* p exchange copy times                            */
+    double t_spmv;           /* summed SpMV kernel time (opts.profile)           */
+    int32_t n_spmv;          /* SpMV launches timed                              */
+    int32_t rows_gpu, rows_cpu;
+    int64_t nnz_gpu, nnz_cpu;
+    int32_t fell_back;       /* 1 if a preconditioned / mixed solve fell back to
+                                plain float64 CG                                 */
+    int32_t reserved;
+} cg_result;
+
+/* Create a solver for the n x n CSR matrix (host arrays, copied).  Rows
+ * [row_begin, row_end) go to the GPU, the others to host threads
+ * (Section 3.2: n_gpu = round(g n) gives [0, n_gpu)); row_begin == row_end
+ * means host only, [0, n) GPU only.  Validates the CSR (CG_EINVAL with a
+ * message on failure).  Uploads the GPU row block with its row pointers
+ * rebased to start at 0 (the matrix is read-only and never re-sent). */
+int cg_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+              const double *val, int32_t row_begin, int32_t row_end, cg_handle **out);
+
+/* Release every host and device resource of h.  NULL is a no-op. */
+void cg_destroy(cg_handle *h);
+
+/* Order the handle's work on this HIP stream (a hipStream_t; NULL = null
+ * stream).  The library also creates private streams for p exchange. */
+int cg_set_stream(cg_handle *h, void *hip_stream);
+
+void cg_default_opts(cg_opts *o);
+int cg_set_opts(cg_handle *h, const cg_opts *o);
+int cg_get_opts(const cg_handle *h, cg_opts *o);
+
+/* y = A x (Section 3.1, q_i = sum_j A_ij p_j) for all n rows.  x, y: device,
+ * n float64 each, must not overlap.  GPU-only handles: queued on the stream
+ * and returns at once.  Otherwise blocking (the host rows are computed on
+ * host threads from a copy of x). */
+int cg_spmv(cg_handle *h, const double *x, double *y);
+
+/* Solve A x = b by CG (Algorithm 1): x (device, in/out) holds the initial
+ * guess and receives the last iterate.  Stops at the top of an iteration when
+ * sqrt(r^T r) < tol * ||b||_2 (tol = 0: fixed work of maxit iterations).
+ * b == 0 gives x = 0.  Blocking.  res (may be NULL) receives the record.
+ * Returns CG_OK, CG_MAXIT, CG_EBREAKDOWN or an error. */
+int cg_solve(cg_handle *h, const double *b, double *x, double tol, int32_t maxit,
+             cg_result *res);
+
+/* Bit-exact readback of the GPU row block as uploaded: rows + 1 rebased row
+ * pointers, nnz_gpu columns and values (host buffers sized by the caller from
+ * cg_result / cg_slice_info).  For checking the row split. */
+int cg_slice_info(const cg_handle *h, int32_t *rows_gpu, int64_t *nnz_gpu);
+int cg_read_slice(const cg_handle *h, int32_t *row_ptr, int32_t *col_idx, double *val);
+
+/* Message for the last error on this thread ("" if none). */
+const char *cg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CGMI_H */

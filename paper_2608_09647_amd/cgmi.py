@@ -1,0 +1,207 @@
+"""Python binding of libcgmi (C ABI in include/cgmi.h): argument marshalling only.
+
+Every step of the solver runs inside libcgmi.so.  torch provides device
+memory and streams; it is imported before the library is loaded so that both
+use the same HIP runtime.  Missing library => ImportError-like RuntimeError:
+there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+import torch  # noqa: F401  (loads the HIP runtime the library links against)
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcgmi.so")
+
+CG_OK, CG_MAXIT, CG_EINVAL, CG_ENOMEM, CG_EDEVICE, CG_EBREAKDOWN = 0, 1, -1, -2, -3, -4
+PREC_FP64, PREC_MIXED = 0, 1
+PC_NONE, PC_FSAI = 0, 1
+EXCHANGE_WHOLE, EXCHANGE_HALO = 0, 1
+
+# Every symbol the public header declares (checked by the tests).
+EXPORTED = ["cg_create", "cg_destroy", "cg_set_stream", "cg_default_opts", "cg_set_opts",
+            "cg_get_opts", "cg_spmv", "cg_solve", "cg_slice_info", "cg_read_slice",
+            "cg_last_error"]
+
+
+class CgOpts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("precond", ctypes.c_int32),
+                ("exchange", ctypes.c_int32), ("host_threads", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("profile", ctypes.c_int32),
+                ("small_path", ctypes.c_int32), ("spmv_grid", ctypes.c_int32),
+                ("spmv_kind", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("refine_delta", ctypes.c_double)]
+
+
+class CgResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("fp64_residuals", ctypes.c_int32),
+                ("rel_res_recur", ctypes.c_double), ("rel_res_true", ctypes.c_double),
+                ("t_solve", ctypes.c_double), ("t_gpu", ctypes.c_double),
+                ("t_cpu", ctypes.c_double), ("t_barrier", ctypes.c_double),
+                ("t_d2h", ctypes.c_double), ("t_h2d", ctypes.c_double),
+                ("t_spmv", ctypes.c_double), ("n_spmv", ctypes.c_int32),
+                ("rows_gpu", ctypes.c_int32), ("rows_cpu", ctypes.c_int32),
+                ("nnz_gpu", ctypes.c_int64), ("nnz_cpu", ctypes.c_int64),
+                ("fell_back", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+class CgError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libcgmi error {code}: {msg}")
+        self.code = code
+
+
+_LIB = None
+_vp = ctypes.c_void_p
+
+
+def lib() -> ctypes.CDLL:
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        L.cg_create.argtypes = [ctypes.c_int32, ctypes.c_int64, _vp, _vp, _vp, ctypes.c_int32,
+                                ctypes.c_int32, ctypes.POINTER(_vp)]
+        L.cg_create.restype = ctypes.c_int
+        L.cg_destroy.argtypes = [_vp]
+        L.cg_destroy.restype = None
+        L.cg_set_stream.argtypes = [_vp, _vp]
+        L.cg_set_stream.restype = ctypes.c_int
+        L.cg_default_opts.argtypes = [ctypes.POINTER(CgOpts)]
+        L.cg_default_opts.restype = None
+        L.cg_set_opts.argtypes = [_vp, ctypes.POINTER(CgOpts)]
+        L.cg_set_opts.restype = ctypes.c_int
+        L.cg_get_opts.argtypes = [_vp, ctypes.POINTER(CgOpts)]
+        L.cg_get_opts.restype = ctypes.c_int
+        L.cg_spmv.argtypes = [_vp, _vp, _vp]
+        L.cg_spmv.restype = ctypes.c_int
+        L.cg_solve.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int32,
+                               ctypes.POINTER(CgResult)]
+        L.cg_solve.restype = ctypes.c_int
+        L.cg_slice_info.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]
+        L.cg_slice_info.restype = ctypes.c_int
+        L.cg_read_slice.argtypes = [_vp, _vp, _vp, _vp]
+        L.cg_read_slice.restype = ctypes.c_int
+        L.cg_last_error.argtypes = []
+        L.cg_last_error.restype = ctypes.c_char_p
+        _LIB = L
+    return _LIB
+
+
+def last_error() -> str:
+    return lib().cg_last_error().decode()
+
+
+def _check(code: int, allow=(CG_OK,)) -> int:
+    if code not in allow:
+        raise CgError(code, last_error())
+    return code
+
+
+def default_opts() -> CgOpts:
+    o = CgOpts()
+    lib().cg_default_opts(ctypes.byref(o))
+    return o
+
+
+def _dev_f64(t, n, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+        raise TypeError(f"{name} must be a CUDA float64 tensor")
+    if not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name} must be contiguous with {n} elements")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """A cg_handle: the matrix on the GPU row block [row_begin, row_end)."""
+
+    def __init__(self, A, row_begin: int = 0, row_end: int | None = None):
+        self.n = int(A.n)
+        self._rp = np.ascontiguousarray(A.row_ptr, dtype=np.int32)
+        self._ci = np.ascontiguousarray(A.col, dtype=np.int32)
+        self._va = np.ascontiguousarray(A.val, dtype=np.float64)
+        self.row_begin = int(row_begin)
+        self.row_end = self.n if row_end is None else int(row_end)
+        h = ctypes.c_void_p()
+        _check(lib().cg_create(self.n, int(self._rp[-1]) if self._rp.size else 0,
+                               self._rp.ctypes.data, self._ci.ctypes.data, self._va.ctypes.data,
+                               self.row_begin, self.row_end, ctypes.byref(h)))
+        self._h = h
+        del self._rp, self._ci, self._va   # the library holds its own copy
+        self.set_stream(torch.cuda.current_stream())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().cg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_stream(self, stream):
+        ptr = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream or 0)
+        _check(lib().cg_set_stream(self._h, ctypes.c_void_p(ptr)))
+
+    @property
+    def opts(self) -> CgOpts:
+        o = CgOpts()
+        _check(lib().cg_get_opts(self._h, ctypes.byref(o)))
+        return o
+
+    def set_opts(self, **kw) -> None:
+        o = self.opts
+        for k, v in kw.items():
+            if not hasattr(o, k):
+                raise KeyError(k)
+            setattr(o, k, v)
+        _check(lib().cg_set_opts(self._h, ctypes.byref(o)))
+
+    def spmv(self, x, y=None):
+        if y is None:
+            y = torch.empty_like(x)
+        _check(lib().cg_spmv(self._h, _dev_f64(x, self.n, "x"), _dev_f64(y, self.n, "y")))
+        return y
+
+    def solve(self, b, x=None, tol: float = 1e-10, maxit: int = 10000, check: bool = True):
+        """Solve A x = b in place of x (zeros if None); returns (x, result dict)."""
+        if x is None:
+            x = torch.zeros_like(b)
+        res = CgResult()
+        code = lib().cg_solve(self._h, _dev_f64(b, self.n, "b"), _dev_f64(x, self.n, "x"),
+                              float(tol), int(maxit), ctypes.byref(res))
+        if check:
+            _check(code, allow=(CG_OK, CG_MAXIT, CG_EBREAKDOWN))
+        out = res.as_dict()
+        out["code"] = code
+        return x, out
+
+    def slice_info(self):
+        rows = ctypes.c_int32()
+        nnz = ctypes.c_int64()
+        _check(lib().cg_slice_info(self._h, ctypes.byref(rows), ctypes.byref(nnz)))
+        return rows.value, nnz.value
+
+    def read_slice(self):
+        rows, nnz = self.slice_info()
+        rp = np.empty(rows + 1, np.int32)
+        ci = np.empty(max(nnz, 1), np.int32)
+        va = np.empty(max(nnz, 1), np.float64)
+        _check(lib().cg_read_slice(self._h, rp.ctypes.data, ci.ctypes.data, va.ctypes.data))
+        return rp, ci[:nnz], va[:nnz]

@@ -1,0 +1,1017 @@
+// cgmi.cpp -- host runtime of libcgmi: C ABI, CSR validation, row split,
+// SpMV schedule, GPU-only solve driver and the split (coscheduled) driver
+// with the host complement on OpenMP threads.
+//
+// Section 3.2: the GPU owns the contiguous row block [row_begin, row_end);
+// the host owns the rest.  Section 3.3: one host thread drives the GPU while
+// host threads compute the host rows; barriers and device synchronisations
+// are kept where a reduction or the visibility of p needs them.
+// Section 3.4 (explicit copy): the GPU-owned segment of p is copied to the
+// host and the host-owned segments to the device after every p update.
+#include <hip/hip_runtime_api.h>
+#include <omp.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/cgmi.h"
+#include "cgmi_internal.h"
+
+using namespace cgmi;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(CG_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));    \
+    } while (0)
+
+double now() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+template <class T>
+hipError_t dmalloc(T **p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    return hipMalloc(reinterpret_cast<void **>(p), sizeof(T) * count);
+}
+
+int lanes_for_length(int64_t len) {
+    int L = 1;
+    while (L < len && L < 64) L <<= 1;
+    return L;
+}
+
+}  // namespace
+
+struct cg_handle {
+    int dev = 0;
+    int32_t n = 0;
+    int64_t nnz = 0;
+    int32_t rb = 0, re = 0, m = 0;
+    int64_t nnz_gpu = 0, nnz_cpu = 0;
+    cg_opts opts{};
+    hipStream_t stream = nullptr;   // caller's stream (or null stream)
+    hipStream_t s_d2h = nullptr, s_h2d = nullptr;
+    int cus = 256;
+
+    // host copy of the matrix (the host complement uses its rows)
+    std::vector<int32_t> h_rp, h_ci;
+    std::vector<double> h_val;
+
+    // device: GPU row block, rebased
+    int32_t *d_rp = nullptr, *d_ci = nullptr, *d_rows = nullptr;
+    double *d_val = nullptr;
+    // sliced (slot-major) copy of the block, built when that tiling is chosen
+    int32_t *d_sell_off = nullptr, *d_sell_ci = nullptr;
+    double *d_sell_val = nullptr;
+    Schedule sched{};
+    int spmv_grid = 0, vec_grid = 0;
+
+    // device vectors
+    double *d_pbuf = nullptr;  // allocation behind d_p
+    double *d_p = nullptr;     // full length n, d_p + rb is 16-byte aligned
+    double *d_x = nullptr, *d_r = nullptr, *d_q = nullptr;  // m each
+    double *d_part_setup = nullptr;  // 2 x spmv_grid: r^T r, b^T b of the residual kernel
+    double *d_part_pq = nullptr;     // spmv_grid
+    double *d_part_rr = nullptr;     // vec_grid
+    int grid_cap = 0;                // capacity of the partial buffers (workgroups)
+    std::vector<double> h_part;      // host copy of partials (split mode, true residual)
+    DevState *d_state = nullptr;
+    DevState *h_state = nullptr;  // pinned
+
+    // split mode
+    double *h_p = nullptr;  // pinned, length n
+    std::vector<double> h_x, h_r, h_q, h_b;
+    std::vector<int32_t> halo_d2h, halo_h2d;  // global column ids
+    int32_t *d_halo_d2h = nullptr, *d_halo_h2d = nullptr;
+    double *d_pack_d2h = nullptr, *d_pack_h2d = nullptr;
+    double *h_pack_d2h = nullptr, *h_pack_h2d = nullptr;  // pinned
+
+    CsrDev csr() const {
+        return CsrDev{m, d_rp, d_ci, d_val, sched.identity ? nullptr : d_rows,
+                      d_sell_off, d_sell_ci, d_sell_val};
+    }
+    bool gpu_only() const { return rb == 0 && re == n && n > 0; }
+    bool host_only() const { return m == 0; }
+};
+
+// ---------------------------------------------------------------------------
+// validation and schedule
+
+static int validate_csr(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *ci,
+                        const double *val) {
+    if (n < 0) return fail(CG_EINVAL, "n must be >= 0 (got %d)", n);
+    if (nnz < 0 || nnz > INT32_MAX) return fail(CG_EINVAL, "nnz out of int32 range");
+    if (n > 0 && !rp) return fail(CG_EINVAL, "row_ptr is NULL");
+    if (nnz > 0 && (!ci || !val)) return fail(CG_EINVAL, "col_idx/val is NULL");
+    if (n == 0) return nnz == 0 ? CG_OK : fail(CG_EINVAL, "n = 0 but nnz != 0");
+    if (rp[0] != 0) return fail(CG_EINVAL, "row_ptr[0] must be 0");
+    if ((int64_t)rp[n] != nnz) return fail(CG_EINVAL, "row_ptr[n] = %d != nnz", rp[n]);
+    for (int32_t i = 0; i < n; ++i) {
+        if (rp[i + 1] < rp[i]) return fail(CG_EINVAL, "row_ptr decreases at row %d", i);
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+            if (ci[k] < 0 || ci[k] >= n)
+                return fail(CG_EINVAL, "column %d out of range in row %d", ci[k], i);
+            if (k > rp[i] && ci[k] <= ci[k - 1])
+                return fail(CG_EINVAL, "columns not strictly increasing in row %d", i);
+        }
+    }
+    return CG_OK;
+}
+
+// Lanes-per-row classes for the GPU rows.  Rows of similar length keep their
+// natural order (one bin, no indirection); spread-out lengths are binned by
+// the power of two covering the row length, with a row list per bin, and rows
+// longer than kHugeRow go to a workgroup-per-row list at the end.
+static void build_schedule(cg_handle *h, std::vector<int32_t> &rows_out) {
+    Schedule S{};
+    const int32_t m = h->m;
+    rows_out.clear();
+    S.identity = 1;
+    if (m == 0) {
+        h->sched = S;
+        return;
+    }
+    auto len = [&](int32_t i) -> int64_t { return h->h_rp[h->rb + i + 1] - h->h_rp[h->rb + i]; };
+    int64_t maxlen = 0;
+    for (int32_t i = 0; i < m; ++i) maxlen = std::max<int64_t>(maxlen, len(i));
+    const double mean = (double)(h->h_rp[h->re] - h->h_rp[h->rb]) / (double)m;
+    if (h->opts.spmv_kind == 3 || (h->opts.spmv_kind == 0 && maxlen <= 64)) {
+        // sliced: 64-row slices padded to their longest row
+        const int32_t nt = (m + kWaveSize - 1) / kWaveSize;
+        int64_t slots = 0;
+        int maxw = 0;
+        for (int32_t t = 0; t < nt; ++t) {
+            int64_t w = 0;
+            for (int32_t i = t * kWaveSize; i < std::min(m, (t + 1) * kWaveSize); ++i) w = std::max(w, len(i));
+            w = std::max<int64_t>(w, 1);
+            slots += w * kWaveSize;
+            maxw = std::max<int>(maxw, (int)w);
+        }
+        const int64_t nnz_b = h->h_rp[h->re] - h->h_rp[h->rb];
+        if (slots < INT32_MAX && (h->opts.spmv_kind == 3 || slots <= nnz_b + nnz_b / 4)) {
+            S.kind = kTileSliced;
+            S.nbins = 1;
+            S.bins[0] = Bin{std::max(1, maxw), 0, m, 0};
+            S.ntiles = nt;
+            h->sched = S;
+            return;
+        }
+    }
+    if (h->opts.spmv_kind == 2 || (h->opts.spmv_kind == 0 && maxlen <= kStreamPerLane)) {
+        // short rows in natural order: stream tiles of 64 rows if every tile fits
+        bool fits = true;
+        for (int32_t r0 = 0; r0 < m && fits; r0 += kWaveSize) {
+            const int32_t r1 = std::min(m, r0 + kWaveSize);
+            const int32_t k0 = h->h_rp[h->rb + r0] - h->h_rp[h->rb];
+            fits = (k0 & 3) + (h->h_rp[h->rb + r1] - h->h_rp[h->rb + r0]) <= kStreamNnz;
+        }
+        if (fits) {
+            S.kind = kTileStream;
+            S.nbins = 1;
+            S.bins[0] = Bin{kWaveSize, 0, m, 0};
+            S.ntiles = (m + kWaveSize - 1) / kWaveSize;
+            h->sched = S;
+            return;
+        }
+    }
+    if (maxlen <= 64 && (double)maxlen <= 2.0 * mean + 1.0) {
+        const int L = lanes_for_length(maxlen);
+        S.nbins = 1;
+        S.bins[0] = Bin{L, 0, m, 0};
+        S.ntiles = (m + rows_per_wave_tile(L) - 1) / rows_per_wave_tile(L);
+        h->sched = S;
+        return;
+    }
+    static const int classes[7] = {1, 2, 4, 8, 16, 32, 64};
+    std::vector<std::vector<int32_t>> lists(7);
+    std::vector<int32_t> huge;
+    for (int32_t i = 0; i < m; ++i) {
+        const int64_t l = len(i);
+        if (l > kHugeRow) {
+            huge.push_back(i);
+            continue;
+        }
+        const int L = lanes_for_length(l);
+        int c = 0;
+        while (classes[c] != L) ++c;
+        lists[c].push_back(i);
+    }
+    S.identity = 0;
+    int nb = 0, tile = 0, pos = 0;
+    for (int c = 0; c < 7; ++c) {
+        if (lists[c].empty()) continue;
+        const int cnt = (int)lists[c].size();
+        S.bins[nb] = Bin{classes[c], pos, cnt, tile};
+        tile += (cnt + rows_per_wave_tile(classes[c]) - 1) / rows_per_wave_tile(classes[c]);
+        rows_out.insert(rows_out.end(), lists[c].begin(), lists[c].end());
+        pos += cnt;
+        ++nb;
+    }
+    S.nbins = nb;
+    S.ntiles = tile;
+    S.huge_first = pos;
+    S.huge_count = (int32_t)huge.size();
+    rows_out.insert(rows_out.end(), huge.begin(), huge.end());
+    h->sched = S;
+}
+
+// Build the SpMV schedule for the current options, upload its row list and
+// size the SpMV grid (a multiple of 8 workgroups: one share per XCD).
+static int build_sliced(cg_handle *h) {
+    if (h->d_sell_off) return CG_OK;  // built once per handle
+    const int32_t m = h->m, nt = h->sched.ntiles, base = h->h_rp[h->rb];
+    std::vector<int32_t> off((size_t)nt + 1, 0);
+    for (int32_t t = 0; t < nt; ++t) {
+        int32_t w = 0;
+        for (int32_t i = t * kWaveSize; i < std::min(m, (t + 1) * kWaveSize); ++i)
+            w = std::max(w, h->h_rp[h->rb + i + 1] - h->h_rp[h->rb + i]);
+        w = std::max(w, 1);  // every slice has a slot: its loads stay inside the allocation
+        off[t + 1] = off[t] + w * kWaveSize;
+    }
+    const size_t slots = (size_t)off[nt];
+    std::vector<int32_t> sci(slots ? slots : 1, 0);
+    std::vector<double> sval(slots ? slots : 1, 0.0);
+    for (int32_t t = 0; t < nt; ++t) {
+        const int32_t w = (off[t + 1] - off[t]) / kWaveSize;
+        for (int32_t l = 0; l < kWaveSize; ++l) {
+            const int32_t i = t * kWaveSize + l;
+            const int32_t b = i < m ? h->h_rp[h->rb + i] - base : 0;
+            const int32_t len = i < m ? h->h_rp[h->rb + i + 1] - h->h_rp[h->rb + i] : 0;
+            // padding slots gather the row's own entry of p (never summed)
+            const int32_t pad_col = i < m ? h->rb + i : 0;
+            for (int32_t j = 0; j < w; ++j) {
+                const size_t k = (size_t)off[t] + (size_t)j * kWaveSize + l;
+                sci[k] = j < len ? h->h_ci[base + b + j] : pad_col;
+                sval[k] = j < len ? h->h_val[base + b + j] : 0.0;
+            }
+        }
+    }
+    hipError_t e = dmalloc(&h->d_sell_off, off.size());
+    if (e == hipSuccess) e = dmalloc(&h->d_sell_ci, sci.size());
+    if (e == hipSuccess) e = dmalloc(&h->d_sell_val, sval.size());
+    if (e == hipSuccess) e = hipMemcpy(h->d_sell_off, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(h->d_sell_ci, sci.data(), sizeof(int32_t) * sci.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(h->d_sell_val, sval.data(), sizeof(double) * sval.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        hipFree(h->d_sell_off); hipFree(h->d_sell_ci); hipFree(h->d_sell_val);
+        h->d_sell_off = h->d_sell_ci = nullptr;
+        h->d_sell_val = nullptr;
+        return fail(CG_ENOMEM, "sliced layout upload failed: %s", hipGetErrorString(e));
+    }
+    return CG_OK;
+}
+
+static int apply_schedule(cg_handle *h) {
+    std::vector<int32_t> rows;
+    build_schedule(h, rows);
+    if (h->sched.kind == kTileSliced) {
+        const int rc = build_sliced(h);
+        if (rc) return rc;
+    }
+    if (!rows.empty()) {
+        const hipError_t e = hipMemcpy(h->d_rows, rows.data(), sizeof(int32_t) * rows.size(),
+                                       hipMemcpyHostToDevice);
+        if (e != hipSuccess) return fail(CG_EDEVICE, "row list upload failed: %s", hipGetErrorString(e));
+    }
+    const int waves_needed = h->sched.ntiles + h->sched.huge_count * (kBlock / kWaveSize);
+    const int auto_grid = ((waves_needed / (kBlock / kWaveSize) + 8) / 8) * 8;
+    int g = h->opts.spmv_grid > 0 ? h->opts.spmv_grid : std::min(h->cus * 8, auto_grid);
+    g = std::min(g, h->grid_cap);
+    h->spmv_grid = std::max(8, (g / 8) * 8);
+    return CG_OK;
+}
+
+static void free_device(cg_handle *h) {
+    hipFree(h->d_rp); hipFree(h->d_ci); hipFree(h->d_rows); hipFree(h->d_val);
+    hipFree(h->d_sell_off); hipFree(h->d_sell_ci); hipFree(h->d_sell_val);
+    hipFree(h->d_pbuf); hipFree(h->d_x); hipFree(h->d_r); hipFree(h->d_q);
+    hipFree(h->d_part_setup); hipFree(h->d_part_pq); hipFree(h->d_part_rr); hipFree(h->d_state);
+    hipFree(h->d_halo_d2h); hipFree(h->d_halo_h2d); hipFree(h->d_pack_d2h); hipFree(h->d_pack_h2d);
+    if (h->h_state) hipHostFree(h->h_state);
+    if (h->h_p) hipHostFree(h->h_p);
+    if (h->h_pack_d2h) hipHostFree(h->h_pack_d2h);
+    if (h->h_pack_h2d) hipHostFree(h->h_pack_h2d);
+    if (h->s_d2h) hipStreamDestroy(h->s_d2h);
+    if (h->s_h2d) hipStreamDestroy(h->s_h2d);
+}
+
+extern "C" void cg_default_opts(cg_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->precision = CG_PREC_FP64;
+    o->precond = CG_PC_NONE;
+    o->exchange = CG_EXCHANGE_WHOLE;
+    o->host_threads = 0;
+    o->check_every = 32;
+    o->profile = 0;
+    o->small_path = 1;
+    o->spmv_grid = 0;
+    o->spmv_kind = 0;
+    o->reserved = 0;
+    o->refine_delta = 0.01;
+}
+
+extern "C" const char *cg_last_error(void) { return g_err.c_str(); }
+
+extern "C" int cg_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                         const double *val, int32_t row_begin, int32_t row_end, cg_handle **out) {
+    g_err.clear();
+    if (!out) return fail(CG_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate_csr(n, nnz, row_ptr, col_idx, val);
+    if (rc) return rc;
+    if (row_begin < 0 || row_end < row_begin || row_end > n)
+        return fail(CG_EINVAL, "row range [%d, %d) not inside [0, %d)", row_begin, row_end, n);
+    cg_handle *h = new (std::nothrow) cg_handle();
+    if (!h) return fail(CG_ENOMEM, "out of host memory");
+    cg_default_opts(&h->opts);
+    h->n = n;
+    h->nnz = nnz;
+    h->rb = row_begin;
+    h->re = row_end;
+    h->m = row_end - row_begin;
+    try {
+        h->h_rp.assign(row_ptr, row_ptr + n + 1);
+        h->h_ci.assign(col_idx, col_idx + nnz);
+        h->h_val.assign(val, val + nnz);
+    } catch (...) {
+        delete h;
+        return fail(CG_ENOMEM, "out of host memory copying the matrix");
+    }
+    h->nnz_gpu = (int64_t)h->h_rp[h->re] - h->h_rp[h->rb];
+    h->nnz_cpu = nnz - h->nnz_gpu;
+    auto bail = [&](int code) {
+        free_device(h);
+        delete h;
+        return code;
+    };
+    if (hipGetDevice(&h->dev) != hipSuccess) return bail(fail(CG_EDEVICE, "no HIP device"));
+    h->cus = device_cu_count();
+    const int m = h->m;
+    // device copy of the GPU row block, row pointers rebased (Section 3.2)
+    std::vector<int32_t> rp_local((size_t)m + 1);
+    for (int32_t i = 0; i <= m; ++i) rp_local[i] = h->h_rp[h->rb + i] - h->h_rp[h->rb];
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+    chk(dmalloc(&h->d_rp, (size_t)m + 1));
+    // padded: 16-byte stream-tile loads may run up to kStreamNnz entries past the end
+    chk(dmalloc(&h->d_ci, (size_t)h->nnz_gpu + kStreamNnz));
+    chk(dmalloc(&h->d_val, (size_t)h->nnz_gpu + kStreamNnz));
+    chk(dmalloc(&h->d_rows, (size_t)m));
+    chk(dmalloc(&h->d_pbuf, (size_t)n + 2));
+    chk(dmalloc(&h->d_x, (size_t)m + 1));
+    chk(dmalloc(&h->d_r, (size_t)m + 1));
+    chk(dmalloc(&h->d_q, (size_t)m + 1));
+    h->vec_grid = std::max(1, std::min(h->cus * 8, (int)(((int64_t)m / 2 + kBlock - 1) / kBlock)));
+    h->grid_cap = std::max(h->cus * 16, 64);
+    chk(dmalloc(&h->d_part_setup, 2 * (size_t)h->grid_cap));
+    chk(dmalloc(&h->d_part_pq, (size_t)h->grid_cap));
+    chk(dmalloc(&h->d_part_rr, (size_t)h->grid_cap));
+    try { h->h_part.assign(2 * (size_t)h->grid_cap, 0.0); } catch (...) { return bail(fail(CG_ENOMEM, "out of host memory")); }
+    chk(dmalloc(&h->d_state, 1));
+    if (e != hipSuccess) return bail(fail(CG_ENOMEM, "device allocation failed: %s", hipGetErrorString(e)));
+    if (hipHostMalloc(reinterpret_cast<void **>(&h->h_state), sizeof(DevState)) != hipSuccess)
+        return bail(fail(CG_ENOMEM, "pinned allocation failed"));
+    // p + rb must be 16-byte aligned for the paired loads of the update kernels
+    h->d_p = h->d_pbuf + (h->rb & 1);
+    chk(hipMemcpy(h->d_rp, rp_local.data(), sizeof(int32_t) * ((size_t)m + 1), hipMemcpyHostToDevice));
+    if (h->nnz_gpu) {
+        chk(hipMemcpy(h->d_ci, h->h_ci.data() + h->h_rp[h->rb], sizeof(int32_t) * h->nnz_gpu,
+                      hipMemcpyHostToDevice));
+        chk(hipMemcpy(h->d_val, h->h_val.data() + h->h_rp[h->rb], sizeof(double) * h->nnz_gpu,
+                      hipMemcpyHostToDevice));
+    }
+    // padding (and entry 0 of an empty block): column 0, value 0
+    chk(hipMemset(h->d_ci + h->nnz_gpu, 0, sizeof(int32_t) * kStreamNnz));
+    chk(hipMemset(h->d_val + h->nnz_gpu, 0, sizeof(double) * kStreamNnz));
+    if (e == hipSuccess) {
+        const int rc2 = apply_schedule(h);
+        if (rc2) return bail(rc2);
+    }
+    chk(hipMemset(h->d_state, 0, sizeof(DevState)));
+    chk(hipMemset(h->d_pbuf, 0, sizeof(double) * ((size_t)n + 2)));
+    if (e != hipSuccess) return bail(fail(CG_EDEVICE, "upload failed: %s", hipGetErrorString(e)));
+
+    if (!h->gpu_only() && n > 0) {
+        // split or host-only: host vectors, pinned p, exchange streams, halo lists
+        try {
+            h->h_x.assign(n, 0.0);
+            h->h_r.assign(n, 0.0);
+            h->h_q.assign(n, 0.0);
+            h->h_b.assign(n, 0.0);
+        } catch (...) {
+            return bail(fail(CG_ENOMEM, "out of host memory"));
+        }
+        if (hipHostMalloc(reinterpret_cast<void **>(&h->h_p), sizeof(double) * (size_t)n) != hipSuccess)
+            return bail(fail(CG_ENOMEM, "pinned allocation failed"));
+        std::memset(h->h_p, 0, sizeof(double) * (size_t)n);
+        if (m > 0) {
+            chk(hipStreamCreateWithFlags(&h->s_d2h, hipStreamNonBlocking));
+            chk(hipStreamCreateWithFlags(&h->s_h2d, hipStreamNonBlocking));
+            // halo: host-owned columns read by GPU rows, GPU-owned columns read by host rows
+            std::vector<char> mark((size_t)n, 0);
+            for (int64_t k = h->h_rp[h->rb]; k < h->h_rp[h->re]; ++k) {
+                const int32_t c = h->h_ci[k];
+                if (c < h->rb || c >= h->re) mark[c] = 1;
+            }
+            for (int32_t c = 0; c < n; ++c) if (mark[c]) h->halo_h2d.push_back(c);
+            std::fill(mark.begin(), mark.end(), 0);
+            for (int32_t i = 0; i < n; ++i) {
+                if (i >= h->rb && i < h->re) continue;
+                for (int32_t k = h->h_rp[i]; k < h->h_rp[i + 1]; ++k) {
+                    const int32_t c = h->h_ci[k];
+                    if (c >= h->rb && c < h->re) mark[c] = 1;
+                }
+            }
+            for (int32_t c = 0; c < n; ++c) if (mark[c]) h->halo_d2h.push_back(c);
+            const size_t a = h->halo_d2h.size(), b = h->halo_h2d.size();
+            chk(dmalloc(&h->d_halo_d2h, a));
+            chk(dmalloc(&h->d_halo_h2d, b));
+            chk(dmalloc(&h->d_pack_d2h, a));
+            chk(dmalloc(&h->d_pack_h2d, b));
+            if (e == hipSuccess && a)
+                chk(hipMemcpy(h->d_halo_d2h, h->halo_d2h.data(), sizeof(int32_t) * a, hipMemcpyHostToDevice));
+            if (e == hipSuccess && b)
+                chk(hipMemcpy(h->d_halo_h2d, h->halo_h2d.data(), sizeof(int32_t) * b, hipMemcpyHostToDevice));
+            if (e == hipSuccess)
+                chk(hipHostMalloc(reinterpret_cast<void **>(&h->h_pack_d2h), sizeof(double) * (a ? a : 1)));
+            if (e == hipSuccess)
+                chk(hipHostMalloc(reinterpret_cast<void **>(&h->h_pack_h2d), sizeof(double) * (b ? b : 1)));
+            if (e != hipSuccess) return bail(fail(CG_EDEVICE, "split-mode setup failed: %s", hipGetErrorString(e)));
+        }
+    }
+    *out = h;
+    return CG_OK;
+}
+
+extern "C" void cg_destroy(cg_handle *h) {
+    if (!h) return;
+    hipSetDevice(h->dev);
+    if (h->stream) hipStreamSynchronize(h->stream);
+    else hipDeviceSynchronize();
+    free_device(h);
+    delete h;
+}
+
+extern "C" int cg_set_stream(cg_handle *h, void *hip_stream) {
+    if (!h) return fail(CG_EINVAL, "handle is NULL");
+    h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    return CG_OK;
+}
+
+extern "C" int cg_set_opts(cg_handle *h, const cg_opts *o) {
+    if (!h || !o) return fail(CG_EINVAL, "NULL argument");
+    if (o->precision != CG_PREC_FP64 && o->precision != CG_PREC_MIXED)
+        return fail(CG_EINVAL, "unknown precision %d", o->precision);
+    if (o->precond != CG_PC_NONE && o->precond != CG_PC_FSAI)
+        return fail(CG_EINVAL, "unknown preconditioner %d", o->precond);
+    if (o->exchange != CG_EXCHANGE_WHOLE && o->exchange != CG_EXCHANGE_HALO)
+        return fail(CG_EINVAL, "unknown exchange mode %d", o->exchange);
+    if (o->check_every < 1) return fail(CG_EINVAL, "check_every must be >= 1");
+    if (o->host_threads < 0) return fail(CG_EINVAL, "host_threads must be >= 0");
+    if (o->spmv_grid < 0) return fail(CG_EINVAL, "spmv_grid must be >= 0");
+    if (!(o->refine_delta > 0.0 && o->refine_delta < 1.0))
+        return fail(CG_EINVAL, "refine_delta must be in (0, 1)");
+    if ((o->precision != CG_PREC_FP64 || o->precond != CG_PC_NONE) && !h->gpu_only())
+        return fail(CG_EINVAL, "mixed precision and preconditioning need a GPU-only handle");
+    if (o->spmv_kind < 0 || o->spmv_kind > 3) return fail(CG_EINVAL, "unknown spmv_kind %d", o->spmv_kind);
+    h->opts = *o;
+    HIP_TRY(hipSetDevice(h->dev));
+    HIP_TRY(h->stream ? hipStreamSynchronize(h->stream) : hipDeviceSynchronize());
+    const int rc = apply_schedule(h);
+    if (rc) return rc;
+    return CG_OK;
+}
+
+extern "C" int cg_get_opts(const cg_handle *h, cg_opts *o) {
+    if (!h || !o) return fail(CG_EINVAL, "NULL argument");
+    *o = h->opts;
+    return CG_OK;
+}
+
+extern "C" int cg_slice_info(const cg_handle *h, int32_t *rows_gpu, int64_t *nnz_gpu) {
+    if (!h) return fail(CG_EINVAL, "handle is NULL");
+    if (rows_gpu) *rows_gpu = h->m;
+    if (nnz_gpu) *nnz_gpu = h->nnz_gpu;
+    return CG_OK;
+}
+
+extern "C" int cg_read_slice(const cg_handle *h, int32_t *row_ptr, int32_t *col_idx, double *val) {
+    if (!h) return fail(CG_EINVAL, "handle is NULL");
+    HIP_TRY(hipSetDevice(h->dev));
+    if (row_ptr) HIP_TRY(hipMemcpy(row_ptr, h->d_rp, sizeof(int32_t) * ((size_t)h->m + 1), hipMemcpyDeviceToHost));
+    if (h->nnz_gpu && col_idx)
+        HIP_TRY(hipMemcpy(col_idx, h->d_ci, sizeof(int32_t) * h->nnz_gpu, hipMemcpyDeviceToHost));
+    if (h->nnz_gpu && val)
+        HIP_TRY(hipMemcpy(val, h->d_val, sizeof(double) * h->nnz_gpu, hipMemcpyDeviceToHost));
+    return CG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// host complement (Section 3.3: host threads share the host rows equally)
+
+namespace {
+
+struct HostRows {
+    int32_t rb, re, n;
+    int32_t count() const { return n - (re - rb); }
+    int32_t row(int32_t v) const { return v < rb ? v : v - rb + re; }
+};
+
+int host_threads(const cg_handle *h) {
+    int t = h->opts.host_threads > 0 ? h->opts.host_threads : omp_get_max_threads();
+    return std::max(1, t);
+}
+
+// Per-thread partial sums are combined in thread order (deterministic for a
+// fixed thread count).
+template <class F>
+double host_reduce(const cg_handle *h, F &&body) {
+    const HostRows hr{h->rb, h->re, h->n};
+    const int T = host_threads(h);
+    std::vector<double> part((size_t)T, 0.0);
+    const int32_t cnt = hr.count();
+#pragma omp parallel num_threads(T)
+    {
+        const int t = omp_get_thread_num();
+        const int nt = omp_get_num_threads();
+        const int32_t lo = (int32_t)((int64_t)cnt * t / nt), hi = (int32_t)((int64_t)cnt * (t + 1) / nt);
+        double acc = 0.0;
+        for (int32_t v = lo; v < hi; ++v) acc += body(hr.row(v));
+        part[t] = acc;
+    }
+    double s = 0.0;
+    for (int t = 0; t < T; ++t) s += part[t];
+    return s;
+}
+
+double host_row_dot(const cg_handle *h, int32_t i, const double *p) {
+    double s = 0.0;
+    for (int32_t k = h->h_rp[i]; k < h->h_rp[i + 1]; ++k) s += h->h_val[k] * p[h->h_ci[k]];
+    return s;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// device helpers
+
+static int gpu_state_init(cg_handle *h, double tol, int32_t maxit) {
+    DevState &s = *h->h_state;
+    std::memset(&s, 0, sizeof s);
+    s.tol = tol;
+    s.maxit = maxit;
+    s.delta = h->opts.refine_delta;
+    HIP_TRY(hipMemcpyAsync(h->d_state, h->h_state, sizeof(DevState), hipMemcpyHostToDevice, h->stream));
+    return CG_OK;
+}
+
+static int gpu_state_read(cg_handle *h) {
+    HIP_TRY(hipMemcpyAsync(h->h_state, h->d_state, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return CG_OK;
+}
+
+// Copy `count` partials (or two interleaved arrays of `count`) to the host and
+// sum each in workgroup order.
+static int sum_partials_host(cg_handle *h, const double *d_part, int count, int arrays, double *s0,
+                             double *s1) {
+    HIP_TRY(hipMemcpyAsync(h->h_part.data(), d_part, sizeof(double) * (size_t)count * arrays,
+                           hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    double a = 0.0, b = 0.0;
+    for (int i = 0; i < count; ++i) a += h->h_part[i];
+    if (arrays > 1)
+        for (int i = 0; i < count; ++i) b += h->h_part[count + i];
+    *s0 = a;
+    if (s1) *s1 = b;
+    return CG_OK;
+}
+
+static Partials no_partials() { return Partials{nullptr, 0}; }
+
+// ||b - A x||^2 and ||b||^2 over the GPU rows (x full length on the device).
+static int gpu_true_residual(cg_handle *h, const double *b_own, const double *x_full, double *rr,
+                             double *bb) {
+    HIP_TRY(launch_spmv(h->csr(), h->sched, h->spmv_grid, x_full, h->d_q, nullptr, b_own, h->d_q,
+                        h->d_part_setup, no_partials(), no_partials(), nullptr, kSpmvResidual, 0,
+                        h->stream));
+    return sum_partials_host(h, h->d_part_setup, h->spmv_grid, 2, rr, bb);
+}
+
+static int status_of(int done) {
+    switch (done) {
+        case kDoneConverged: return CG_OK;
+        case kDoneBreakdown: return CG_EBREAKDOWN;
+        default: return CG_MAXIT;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// GPU-only solve: alpha, beta and the stop test stay on the device; the host
+// queues iterations in chunks and polls the device state between chunks.
+
+static int solve_gpu_only(cg_handle *h, const double *b, double *x, double tol, int32_t maxit,
+                          cg_result *res) {
+    const int32_t n = h->n;
+    hipStream_t st = h->stream;
+    const bool small = h->opts.small_path && n <= small_path_max_rows() &&
+                       h->opts.precision == CG_PREC_FP64 && h->opts.precond == CG_PC_NONE;
+    HIP_TRY(hipMemcpyAsync(h->d_x, x, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    int rc = gpu_state_init(h, tol, maxit);
+    if (rc) return rc;
+    double t_gpu = 0.0, t_spmv = 0.0;
+    int n_spmv = 0;
+    const double t0 = now();
+    if (small) {
+        HIP_TRY(launch_cg_small(n, h->d_rp, h->d_ci, h->d_val, b, h->d_x, tol, maxit, h->d_state, st));
+        rc = gpu_state_read(h);
+        if (rc) return rc;
+    } else {
+        const int Gs = h->spmv_grid, Gv = h->vec_grid;
+        const Partials setup_rr{h->d_part_setup, Gs}, setup_bb{h->d_part_setup + Gs, Gs};
+        const Partials pq{h->d_part_pq, Gs}, rr{h->d_part_rr, Gv};
+        // r = b - A x, p = r (partials of r^T r and b^T b)
+        HIP_TRY(launch_spmv(h->csr(), h->sched, Gs, h->d_x, h->d_r, nullptr, b, h->d_p,
+                            h->d_part_setup, no_partials(), no_partials(), nullptr, kSpmvResidual, 0, st));
+        const int C = h->opts.check_every;
+        std::vector<hipEvent_t> ev;
+        if (h->opts.profile) {
+            ev.resize(2 * (size_t)C);
+            for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+        }
+        int32_t k = 0;
+        bool running = true;
+        while (running) {
+            // iteration k = 0 also runs the initial stop test; maxit = 0 runs only that test
+            const int32_t chunk = maxit == 0 ? 1 : std::min<int32_t>(C, maxit - k);
+            for (int32_t j = 0; j < chunk; ++j) {
+                const int32_t kk = k + j;
+                if (h->opts.profile) HIP_TRY(hipEventRecord(ev[2 * j], st));
+                HIP_TRY(launch_spmv(h->csr(), h->sched, Gs, h->d_p, h->d_q, h->d_p, nullptr, nullptr,
+                                    h->d_part_pq, setup_rr, setup_bb, h->d_state, kSpmvDot, kk == 0, st));
+                if (h->opts.profile) HIP_TRY(hipEventRecord(ev[2 * j + 1], st));
+                if (maxit == 0) break;
+                HIP_TRY(launch_update_xr(n, Gv, h->d_x, h->d_r, h->d_p, h->d_q, h->d_part_rr, pq,
+                                         h->d_state, 1, kk, 0.0, st));
+                HIP_TRY(launch_update_p(n, Gv, h->d_r, h->d_p, rr, h->d_state, 1, kk, 0.0, st));
+            }
+            const int32_t it0 = k;
+            k += chunk;
+            rc = gpu_state_read(h);
+            if (rc) break;
+            running = h->h_state->done == kDoneRunning && k < maxit;
+            if (h->opts.profile) {
+                // time only SpMVs that did work (iterations it0 .. iter, plus a breakdown step)
+                int32_t ran = h->h_state->iter - it0 + (h->h_state->done == kDoneBreakdown ? 1 : 0);
+                ran = std::max(0, std::min<int32_t>(ran, chunk));
+                for (int32_t j = 0; j < ran; ++j) {
+                    float ms = 0.f;
+                    HIP_TRY(hipEventElapsedTime(&ms, ev[2 * j], ev[2 * j + 1]));
+                    t_spmv += 1e-3 * ms;
+                    ++n_spmv;
+                }
+            }
+        }
+        for (auto &e : ev) (void)hipEventDestroy(e);
+        if (rc) return rc;
+    }
+    t_gpu = now() - t0;
+    DevState s = *h->h_state;
+    if (s.bb == 0.0) {  // b = 0: the solution is x = 0
+        HIP_TRY(hipMemsetAsync(x, 0, sizeof(double) * n, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (res) {
+            res->status = CG_OK;
+            res->iterations = 0;
+            res->converged = 1;
+        }
+        return CG_OK;
+    }
+    HIP_TRY(hipMemcpyAsync(x, h->d_x, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    double rr_true = 0.0, bb = 0.0;
+    rc = gpu_true_residual(h, b, x, &rr_true, &bb);
+    if (rc) return rc;
+    const int status = status_of(s.done == kDoneRunning ? kDoneMaxit : s.done);
+    if (res) {
+        res->status = status;
+        res->iterations = s.iter;
+        res->converged = status == CG_OK;
+        res->rel_res_recur = std::sqrt(s.rr) / std::sqrt(s.bb);
+        res->rel_res_true = std::sqrt(rr_true) / std::sqrt(bb);
+        res->t_gpu = t_gpu;
+        res->t_spmv = t_spmv;
+        res->n_spmv = n_spmv;
+    }
+    return status;
+}
+
+// ---------------------------------------------------------------------------
+// split solve: GPU rows [rb, re) and host rows, explicit p exchange
+
+namespace {
+
+struct SplitTimers {
+    double gpu = 0, cpu = 0, barrier = 0, d2h = 0, h2d = 0;
+};
+
+// Make the updated p visible to both sides (Section 3.4, explicit copy).
+int exchange_p(cg_handle *h, SplitTimers &tm) {
+    const int32_t n = h->n, rb = h->rb, re = h->re;
+    const bool halo = h->opts.exchange == CG_EXCHANGE_HALO;
+    double t0 = now();
+    // GPU-owned entries -> host
+    if (halo) {
+        const int32_t a = (int32_t)h->halo_d2h.size();
+        if (a) {
+            HIP_TRY(launch_gather(a, h->d_halo_d2h, h->d_p, h->d_pack_d2h, h->stream));
+            HIP_TRY(hipMemcpyAsync(h->h_pack_d2h, h->d_pack_d2h, sizeof(double) * a,
+                                   hipMemcpyDeviceToHost, h->stream));
+            HIP_TRY(hipStreamSynchronize(h->stream));
+            for (int32_t i = 0; i < a; ++i) h->h_p[h->halo_d2h[i]] = h->h_pack_d2h[i];
+        }
+    } else {
+        HIP_TRY(hipMemcpyAsync(h->h_p + rb, h->d_p + rb, sizeof(double) * (size_t)(re - rb),
+                               hipMemcpyDeviceToHost, h->s_d2h));
+        HIP_TRY(hipStreamSynchronize(h->s_d2h));
+    }
+    double t1 = now();
+    tm.d2h += t1 - t0;
+    // host-owned entries -> GPU
+    if (halo) {
+        const int32_t b = (int32_t)h->halo_h2d.size();
+        if (b) {
+            for (int32_t i = 0; i < b; ++i) h->h_pack_h2d[i] = h->h_p[h->halo_h2d[i]];
+            HIP_TRY(hipMemcpyAsync(h->d_pack_h2d, h->h_pack_h2d, sizeof(double) * b,
+                                   hipMemcpyHostToDevice, h->stream));
+            HIP_TRY(launch_scatter(b, h->d_halo_h2d, h->d_pack_h2d, h->d_p, h->stream));
+            HIP_TRY(hipStreamSynchronize(h->stream));
+        }
+    } else {
+        if (rb > 0)
+            HIP_TRY(hipMemcpyAsync(h->d_p, h->h_p, sizeof(double) * rb, hipMemcpyHostToDevice, h->s_h2d));
+        if (re < n)
+            HIP_TRY(hipMemcpyAsync(h->d_p + re, h->h_p + re, sizeof(double) * (size_t)(n - re),
+                                   hipMemcpyHostToDevice, h->s_h2d));
+        HIP_TRY(hipStreamSynchronize(h->s_h2d));
+    }
+    tm.h2d += now() - t1;
+    return CG_OK;
+}
+
+int wait_gpu(cg_handle *h, SplitTimers &tm, double gpu_started) {
+    const double t0 = now();
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    const double t1 = now();
+    tm.barrier += t1 - t0;
+    tm.gpu += t1 - gpu_started;
+    return CG_OK;
+}
+
+}  // namespace
+
+static int solve_split(cg_handle *h, const double *b, double *x, double tol, int32_t maxit,
+                       cg_result *res) {
+    const int32_t n = h->n, rb = h->rb, re = h->re, m = h->m;
+    const bool gpu = m > 0;
+    hipStream_t st = h->stream;
+    const int Gs = h->spmv_grid, Gv = h->vec_grid;
+    SplitTimers tm;
+    double *hx = h->h_x.data(), *hr = h->h_r.data(), *hq = h->h_q.data(), *hb = h->h_b.data();
+    double *hp = h->h_p;
+    int rc = CG_OK;
+    // initial transfers: b and x to the host, the GPU block of x to the device buffer
+    {
+        const double t0 = now();
+        HIP_TRY(hipMemcpyAsync(hb, b, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(hx, x, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+        if (gpu) HIP_TRY(hipMemcpyAsync(h->d_x, x + rb, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        tm.d2h += now() - t0;
+    }
+    double t_g = now();
+    if (gpu)
+        HIP_TRY(launch_spmv(h->csr(), h->sched, Gs, x, h->d_r, nullptr, b + rb, h->d_p + rb,
+                            h->d_part_setup, no_partials(), no_partials(), nullptr, kSpmvResidual, 0, st));
+    double t_c = now();
+    const double rho_c = host_reduce(h, [&](int32_t i) {
+        const double rv = hb[i] - host_row_dot(h, i, hx);
+        hr[i] = rv;
+        hp[i] = rv;
+        return rv * rv;
+    });
+    const double bb_c = host_reduce(h, [&](int32_t i) { return hb[i] * hb[i]; });
+    tm.cpu += now() - t_c;
+    double rho = rho_c, bb = bb_c;
+    if (gpu) {
+        if ((rc = wait_gpu(h, tm, t_g))) return rc;
+        double rg = 0.0, bg = 0.0;
+        if ((rc = sum_partials_host(h, h->d_part_setup, Gs, 2, &rg, &bg))) return rc;
+        rho = rg + rho_c;
+        bb = bg + bb_c;
+        if ((rc = exchange_p(h, tm))) return rc;
+    }
+    const double bnorm = std::sqrt(bb);
+    int status = CG_MAXIT;
+    int32_t k = 0;
+    if (bnorm == 0.0) {
+        HIP_TRY(hipMemsetAsync(x, 0, sizeof(double) * n, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (res) { res->status = CG_OK; res->converged = 1; }
+        return CG_OK;
+    }
+    for (k = 0; k < maxit; ++k) {
+        if (std::sqrt(rho) < tol * bnorm || rho == 0.0) { status = CG_OK; break; }
+        // q = A p and p^T q: GPU rows and host rows at the same time
+        t_g = now();
+        if (gpu)
+            HIP_TRY(launch_spmv(h->csr(), h->sched, Gs, h->d_p, h->d_q, h->d_p + rb, nullptr, nullptr,
+                                h->d_part_pq, no_partials(), no_partials(), nullptr, kSpmvDot, 0, st));
+        t_c = now();
+        const double pq_c = host_reduce(h, [&](int32_t i) {
+            const double s = host_row_dot(h, i, hp);
+            hq[i] = s;
+            return hp[i] * s;
+        });
+        tm.cpu += now() - t_c;
+        double pq = pq_c;
+        if (gpu) {
+            if ((rc = wait_gpu(h, tm, t_g))) return rc;
+            double pg = 0.0;
+            if ((rc = sum_partials_host(h, h->d_part_pq, Gs, 1, &pg, nullptr))) return rc;
+            pq = pg + pq_c;
+        }
+        if (!(pq > 0.0) || !std::isfinite(pq)) { status = CG_EBREAKDOWN; break; }
+        const double alpha = rho / pq;
+        // x += alpha p, r -= alpha q, r^T r
+        t_g = now();
+        if (gpu)
+            HIP_TRY(launch_update_xr(m, Gv, h->d_x, h->d_r, h->d_p + rb, h->d_q, h->d_part_rr,
+                                     no_partials(), nullptr, 0, k, alpha, st));
+        t_c = now();
+        const double rr_c = host_reduce(h, [&](int32_t i) {
+            hx[i] = std::fma(alpha, hp[i], hx[i]);
+            const double rv = std::fma(-alpha, hq[i], hr[i]);
+            hr[i] = rv;
+            return rv * rv;
+        });
+        tm.cpu += now() - t_c;
+        double rr = rr_c;
+        if (gpu) {
+            if ((rc = wait_gpu(h, tm, t_g))) return rc;
+            double rg = 0.0;
+            if ((rc = sum_partials_host(h, h->d_part_rr, Gv, 1, &rg, nullptr))) return rc;
+            rr = rg + rr_c;
+        }
+        const double beta = rr / rho;
+        rho = rr;
+        if (std::sqrt(rho) < tol * bnorm || rho == 0.0 || k + 1 == maxit) continue;  // p unused
+        // p = r + beta p, then exchange
+        t_g = now();
+        if (gpu)
+            HIP_TRY(launch_update_p(m, Gv, h->d_r, h->d_p + rb, no_partials(), nullptr, 0, k, beta, st));
+        t_c = now();
+        host_reduce(h, [&](int32_t i) {
+            hp[i] = std::fma(beta, hp[i], hr[i]);
+            return 0.0;
+        });
+        tm.cpu += now() - t_c;
+        if (gpu) {
+            if ((rc = wait_gpu(h, tm, t_g))) return rc;
+            if ((rc = exchange_p(h, tm))) return rc;
+        }
+    }
+    if (status == CG_MAXIT && (std::sqrt(rho) < tol * bnorm || rho == 0.0)) status = CG_OK;
+    // final transfers: host rows of x and the GPU block back into the caller's x
+    {
+        const double t0 = now();
+        if (rb > 0) HIP_TRY(hipMemcpyAsync(x, hx, sizeof(double) * rb, hipMemcpyHostToDevice, st));
+        if (re < n) HIP_TRY(hipMemcpyAsync(x + re, hx + re, sizeof(double) * (n - re), hipMemcpyHostToDevice, st));
+        if (gpu) HIP_TRY(hipMemcpyAsync(x + rb, h->d_x, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        tm.h2d += now() - t0;
+    }
+    // true residual from the final x (Section 3.1): GPU rows on the GPU, host rows on the host
+    if (gpu) HIP_TRY(hipMemcpy(hx + rb, h->d_x, sizeof(double) * m, hipMemcpyDeviceToHost));
+    double rr_true = host_reduce(h, [&](int32_t i) {
+        const double rv = hb[i] - host_row_dot(h, i, hx);
+        return rv * rv;
+    });
+    if (gpu) {
+        double rr_g = 0.0, bb_g = 0.0;
+        if ((rc = gpu_true_residual(h, b + rb, x, &rr_g, &bb_g))) return rc;
+        rr_true += rr_g;
+    }
+    if (res) {
+        res->status = status;
+        res->iterations = k;
+        res->converged = status == CG_OK;
+        res->rel_res_recur = std::sqrt(rho) / bnorm;
+        res->rel_res_true = std::sqrt(rr_true) / bnorm;
+        res->t_gpu = tm.gpu;
+        res->t_cpu = tm.cpu;
+        res->t_barrier = tm.barrier;
+        res->t_d2h = tm.d2h;
+        res->t_h2d = tm.h2d;
+    }
+    return status;
+}
+
+extern "C" int cg_solve(cg_handle *h, const double *b, double *x, double tol, int32_t maxit,
+                        cg_result *res) {
+    g_err.clear();
+    if (!h) return fail(CG_EINVAL, "handle is NULL");
+    if (res) std::memset(res, 0, sizeof *res);
+    if (!(tol >= 0.0)) return fail(CG_EINVAL, "tol must be >= 0");
+    if (maxit < 0) return fail(CG_EINVAL, "maxit must be >= 0");
+    if (h->n > 0 && (!b || !x)) return fail(CG_EINVAL, "b/x is NULL");
+    if (res) {
+        res->rows_gpu = h->m;
+        res->rows_cpu = h->n - h->m;
+        res->nnz_gpu = h->nnz_gpu;
+        res->nnz_cpu = h->nnz_cpu;
+    }
+    if (h->n == 0) {
+        if (res) res->converged = 1;
+        return CG_OK;
+    }
+    HIP_TRY(hipSetDevice(h->dev));
+    const double t0 = now();
+    int rc;
+    if (h->gpu_only()) {
+        if (h->nnz == 0) return fail(CG_EINVAL, "matrix has no nonzeros");
+        rc = solve_gpu_only(h, b, x, tol, maxit, res);
+    } else {
+        rc = solve_split(h, b, x, tol, maxit, res);
+    }
+    if (res) {
+        res->t_solve = now() - t0;
+        res->rows_gpu = h->m;
+        res->rows_cpu = h->n - h->m;
+        res->nnz_gpu = h->nnz_gpu;
+        res->nnz_cpu = h->nnz_cpu;
+        if (rc < 0 && res->status == 0) res->status = rc;
+    }
+    if (rc == CG_EBREAKDOWN && g_err.empty()) g_err = "breakdown: p^T q <= 0 or not finite";
+    return rc;
+}
+
+extern "C" int cg_spmv(cg_handle *h, const double *x, double *y) {
+    g_err.clear();
+    if (!h) return fail(CG_EINVAL, "handle is NULL");
+    if (h->n == 0) return CG_OK;
+    if (!x || !y) return fail(CG_EINVAL, "x/y is NULL");
+    HIP_TRY(hipSetDevice(h->dev));
+    const int32_t n = h->n, rb = h->rb, re = h->re, m = h->m;
+    if (h->gpu_only()) {
+        if (h->nnz == 0) {
+            HIP_TRY(hipMemsetAsync(y, 0, sizeof(double) * n, h->stream));
+            return CG_OK;
+        }
+        HIP_TRY(launch_spmv(h->csr(), h->sched, h->spmv_grid, x, y, nullptr, nullptr, nullptr, nullptr,
+                            no_partials(), no_partials(), nullptr, kSpmvPlain, 0, h->stream));
+        return CG_OK;
+    }
+    // split: GPU rows on the device, host rows from a host copy of x
+    double *hx = h->h_x.data(), *hq = h->h_q.data();
+    HIP_TRY(hipMemcpyAsync(hx, x, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (m > 0 && h->nnz_gpu > 0)
+        HIP_TRY(launch_spmv(h->csr(), h->sched, h->spmv_grid, x, y + rb, nullptr, nullptr, nullptr,
+                            nullptr, no_partials(), no_partials(), nullptr, kSpmvPlain, 0, h->stream));
+    else if (m > 0)
+        HIP_TRY(hipMemsetAsync(y + rb, 0, sizeof(double) * m, h->stream));
+    host_reduce(h, [&](int32_t i) {
+        hq[i] = host_row_dot(h, i, hx);
+        return 0.0;
+    });
+    if (rb > 0) HIP_TRY(hipMemcpyAsync(y, hq, sizeof(double) * rb, hipMemcpyHostToDevice, h->stream));
+    if (re < n) HIP_TRY(hipMemcpyAsync(y + re, hq + re, sizeof(double) * (n - re), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return CG_OK;
+}

@@ -1,0 +1,149 @@
+// Internal interface between the host runtime (cgmi.cpp, built by g++) and
+// the HIP kernels (*.hip, built by hipcc for gfx950).  Plain structs only.
+#pragma once
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#if defined(__HIPCC__)
+#define CGMI_HD __host__ __device__
+#else
+#define CGMI_HD
+#endif
+
+namespace cgmi {
+
+constexpr int kBlock = 256;     // threads per workgroup of the streaming kernels
+constexpr int kWaveSize = 64;   // CDNA wavefront
+constexpr int kMaxBins = 8;     // lanes-per-row classes 1,2,4,...,64
+constexpr int kHugeRow = 4096;  // longer rows are reduced by a whole workgroup
+
+// Device-resident solver state.  Each field is written by one workgroup
+// (workgroup 0) of one kernel and read by later kernels or by the host; the
+// coefficient history is double-buffered by iteration parity so a kernel
+// never reads a value its own grid is writing.
+struct DevState {
+    double rho[2];     // rho_k = r_k^T r_k (or r^T z) by iteration parity
+    double bb;         // b^T b
+    double tol;        // relative tolerance
+    double pq;         // last p^T q (diagnostics)
+    double rr;         // last r^T r
+    double delta;      // mixed precision: refinement factor
+    double rmax;       // mixed precision: residual norm at the last refinement
+    int32_t iter;      // completed iterations
+    int32_t maxit;
+    int32_t done;      // 0 running, 1 converged, 2 iteration limit, 3 breakdown
+    int32_t nrefine;   // mixed precision: float64 residuals formed
+};
+
+enum { kDoneRunning = 0, kDoneConverged = 1, kDoneMaxit = 2, kDoneBreakdown = 3 };
+
+// One class of rows processed with the same number of lanes per row.
+struct Bin {
+    int32_t lanes;        // 1..64 lanes per row
+    int32_t first;        // first position in the row list
+    int32_t count;        // rows in the bin
+    int32_t tile_begin;   // first wavefront tile of the bin (numbered over all bins)
+};
+
+// Stream tiles (kind kTileStream): 64 consecutive rows per wavefront tile
+// whose nonzeros are loaded flat by the wavefront in 16-byte groups counted
+// from the tile's first nonzero rounded down to a multiple of 4; a tile fits
+// when (k0 mod 4) + nnz(tile) <= kStreamNnz.  col/val allocations carry
+// kStreamNnz padding entries (column 0, value 0).
+constexpr int kStreamPerLane = 8;
+constexpr int kStreamNnz = kWaveSize * kStreamPerLane;
+// Sliced tiles (kind kTileSliced): the block is re-laid out in slices of 64
+// rows stored slot-major (slot j of every row of the slice, then slot j+1,
+// ...), padded to the slice's longest row; slice t starts at sell_off[t].
+constexpr int kSliceMaxWidth = 8;  // widths up to this take the unrolled path
+enum { kTileVector = 0, kTileStream = 1, kTileSliced = 2 };
+
+struct Schedule {
+    Bin bins[kMaxBins];
+    int32_t nbins;
+    int32_t ntiles;       // wavefront tiles over all bins
+    int32_t identity;     // 1: the row list is 0..m-1 (no indirection)
+    int32_t huge_first;   // rows longer than kHugeRow: positions in the row list
+    int32_t huge_count;
+    int32_t kind;         // kTileVector or kTileStream (identity order only)
+};
+
+// Rows per group of lanes and per wavefront tile for a lanes-per-row class:
+// a wavefront holds 64/lanes groups; each group takes up to 8 rows per tile
+// (at most 64 rows per tile, one row pointer pair per lane).
+CGMI_HD constexpr inline int rows_per_group(int lanes) {
+    return lanes == 1 ? 1 : (lanes < 8 ? lanes : 8);
+}
+CGMI_HD constexpr inline int rows_per_wave_tile(int lanes) {
+    return (kWaveSize / lanes) * rows_per_group(lanes);
+}
+
+// Matrix operand of the SpMV kernels: `m` rows with rebased row pointers;
+// columns index the full length-n vector.
+struct CsrDev {
+    int32_t m;
+    const int32_t *rp;
+    const int32_t *ci;
+    const double *val;
+    const int32_t *rows;     // row list ordered by bin (nullptr when identity)
+    const int32_t *sell_off; // sliced layout: slice offsets (ntiles + 1)
+    const int32_t *sell_ci;  //   slot-major columns
+    const double *sell_val;  //   slot-major values
+};
+
+// Partial sums of one reduction: one value per workgroup of the kernel that
+// produced them, summed in workgroup order by the consumer.
+struct Partials {
+    const double *v;
+    int32_t count;
+};
+
+// ---- launch wrappers (kernels_cg.hip) ------------------------------------
+// Every wrapper returns the hipError_t of the launch.
+
+enum { kSpmvPlain = 0, kSpmvDot = 1, kSpmvResidual = 2 };
+
+// q = A p on the block's rows.
+//   kSpmvPlain:    nothing else.
+//   kSpmvDot:      out_partials[wg] = sum p_own_i q_i.  With `k0_check`
+//                  (first iteration of a device-driven solve) every workgroup
+//                  first reduces the setup partials (r^T r in `in0`, b^T b in
+//                  `in1`), applies the stop test, and workgroup 0 records
+//                  rho_0, b^T b and the outcome in st.
+//   kSpmvResidual: q = b - A p written to q and p_dst; out_partials[wg] =
+//                  sum q_i^2, out_partials[grid + wg] = sum b_i^2.
+hipError_t launch_spmv(const CsrDev &A, const Schedule &S, int grid, const double *p, double *q,
+                       const double *p_own, const double *b, double *p_dst, double *out_partials,
+                       Partials in0, Partials in1, DevState *st, int mode, int k0_check,
+                       hipStream_t s);
+
+// x += alpha p, r -= alpha q; out_partials[wg] = sum r_i^2.
+// device_coef: alpha = rho_k / sum(pq), rho_k = st->rho[k & 1]; a breakdown
+// (p^T q <= 0 or not finite) leaves x, r untouched and sets st->done.
+// Otherwise alpha = alpha_arg.
+hipError_t launch_update_xr(int32_t m, int grid, double *x, double *r, const double *p_own,
+                            const double *q, double *out_partials, Partials pq, DevState *st,
+                            int device_coef, int32_t k, double alpha_arg, hipStream_t s);
+
+// p = r + beta p.  device_coef: rho_{k+1} = sum(rr), beta = rho_{k+1} / rho_k,
+// the stop test, and workgroup 0 records iteration k+1 in st; no update once
+// the solve has stopped.  Otherwise beta = beta_arg.
+hipError_t launch_update_p(int32_t m, int grid, const double *r, double *p_own, Partials rr,
+                           DevState *st, int device_coef, int32_t k, double beta_arg,
+                           hipStream_t s);
+
+// Whole-solve single-workgroup CG for small systems (p held in LDS).
+int small_path_max_rows();
+hipError_t launch_cg_small(int32_t n, const int32_t *rp, const int32_t *ci, const double *val,
+                           const double *b, double *x, double tol, int32_t maxit, DevState *st,
+                           hipStream_t s);
+
+// Gather / scatter of p entries for the halo exchange.
+hipError_t launch_gather(int32_t cnt, const int32_t *idx, const double *src, double *dst,
+                         hipStream_t s);
+hipError_t launch_scatter(int32_t cnt, const int32_t *idx, const double *src, double *dst,
+                          hipStream_t s);
+
+int device_cu_count();
+
+}  // namespace cgmi

@@ -1,0 +1,840 @@
+// kernels_cg.hip -- float64 CG hot path for gfx950 (CDNA4, wave64).
+//
+// SpMV q = A p (Section 3.1) is vector CSR: each row is handled by a group of
+// L lanes (L = 1, 2, ..., 64) chosen per row-length class ("bin"); rows longer
+// than kHugeRow are handled by a whole workgroup.  Work is split into
+// wavefront tiles of up to 64 rows: the wavefront loads the tile's row
+// pointers cooperatively (one row per lane, coalesced) and hands each group
+// its row bounds by cross-lane shuffles, then every group streams
+// consecutive col/val entries of its rows (coalesced) for up to 8 rows at a
+// time, so a lane keeps up to 8 independent gathers in flight.  Tiles of one
+// wavefront never wait for the other wavefronts of the workgroup.
+//
+// Scalar reductions (p^T q fused into the SpMV, r^T r fused into the x/r
+// update: Section 3.3) never use atomics or cache flushes: each workgroup
+// stores its partial sum with a plain store, and the *next* kernel -- whose
+// start is ordered after the producer's completion -- reduces the partials in
+// workgroup order redundantly in every workgroup.  All workgroups therefore
+// derive bit-identical alpha / beta / stop decisions, the results are
+// deterministic for a fixed grid, and workgroup 0 records them in DevState
+// for the host.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "cgmi_internal.h"
+
+namespace cgmi {
+
+namespace {
+
+constexpr int kWave = kWaveSize;
+constexpr int kWavesPerBlock = kBlock / kWave;
+
+enum { kFlagCheckDone = 1, kFlagFirstIter = 2 };
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_down(v, o, kWave);
+    return v;
+}
+
+// Sum over the workgroup; the result is valid in thread 0.  sh: NT/64 doubles.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        s = sh[0];
+#pragma unroll
+        for (int i = 1; i < NT / kWave; ++i) s += sh[i];
+    }
+    __syncthreads();
+    return s;
+}
+
+// Every thread of the workgroup gets the sum.
+template <int NT>
+__device__ __forceinline__ double block_allsum(double v, double *sh, double *bc) {
+    double s = block_sum<NT>(v, sh);
+    if (threadIdx.x == 0) *bc = s;
+    __syncthreads();
+    s = *bc;
+    __syncthreads();
+    return s;
+}
+
+// Sum of a producer kernel's partials in a fixed order (same in every workgroup).
+__device__ __forceinline__ double reduce_partials(const Partials &P, double *sh, double *bc) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < P.count; i += kBlock) v += P.v[i];
+    return block_allsum<kBlock>(v, sh, bc);
+}
+
+__device__ __forceinline__ bool stop_test(double rho, double bb, double tol) {
+    return sqrt(rho) < tol * sqrt(bb) || rho == 0.0;
+}
+
+__device__ __forceinline__ bool is_block0_thread0() { return blockIdx.x == 0 && threadIdx.x == 0; }
+
+template <int L>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+    for (int o = L / 2; o > 0; o >>= 1) v += __shfl_down(v, o, kWave);
+    return v;  // valid in the group's first lane
+}
+
+struct SpmvArgs {
+    const double *__restrict__ p;      // gathered vector (full length)
+    double *__restrict__ q;            // output rows (local)
+    const double *__restrict__ p_own;  // p at the block's own rows (dot)
+    const double *__restrict__ b;      // residual mode: right-hand side (local)
+    double *__restrict__ p_dst;        // residual mode: copy of r (local)
+};
+
+template <int MODE>
+__device__ __forceinline__ void emit_row(const SpmvArgs &a, int row, double s, double &acc0,
+                                         double &acc1) {
+    if (MODE == kSpmvResidual) {
+        const double bv = a.b[row];
+        const double rv = bv - s;
+        a.q[row] = rv;
+        a.p_dst[row] = rv;
+        acc0 = fma(rv, rv, acc0);
+        acc1 = fma(bv, bv, acc1);
+    } else {
+        a.q[row] = s;
+        if (MODE == kSpmvDot) acc0 = fma(a.p_own[row], s, acc0);
+    }
+}
+
+// One wavefront tile: `cnt` (<= 64) rows starting at row-list position pos0,
+// L lanes per row, rows_per_group(L) rows per group.
+template <int L, int MODE>
+__device__ __forceinline__ void spmv_wave_tile(const CsrDev &A, int pos0, int cnt, bool identity,
+                                               const SpmvArgs &a, double &acc0, double &acc1) {
+    constexpr int G = kWave / L;
+    constexpr int U = rows_per_group(L);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int gl = lane & (L - 1), g = lane / L;
+    // unconditional loads (clamped slot) keep the compiler's load counting exact
+    const int slot = pos0 + min(lane, cnt - 1);
+    const int row_c = identity ? slot : A.rows[slot];
+    int beg_l = A.rp[row_c];
+    int end_l = A.rp[row_c + 1];
+    int row_l = row_c;
+    if (lane >= cnt) {
+        row_l = -1;
+        end_l = beg_l;
+    }
+    double sum[U];
+    int rowu[U], endu[U], nextu[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int j = u * G + g;
+        const int row = __shfl(row_l, j, kWave);
+        const int beg = __shfl(beg_l, j, kWave);
+        const int end = __shfl(end_l, j, kWave);
+        const int k = beg + gl;
+        const bool ok = k < end;
+        const int kk = ok ? k : 0;  // entry 0 always holds a valid column
+        const int c = A.ci[kk];
+        const double v = A.val[kk];
+        const double pv = a.p[c];
+        sum[u] = ok ? v * pv : 0.0;
+        rowu[u] = row;
+        endu[u] = end;
+        nextu[u] = k + L;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll 2
+        for (int k = nextu[u]; k < endu[u]; k += L) sum[u] = fma(A.val[k], a.p[A.ci[k]], sum[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const double s = group_sum<L>(sum[u]);
+        if (gl == 0 && rowu[u] >= 0) emit_row<MODE>(a, rowu[u], s, acc0, acc1);
+    }
+}
+
+// Wavefront tiles are dealt out per XCD: workgroup b runs on XCD b mod 8, and
+// XCD x owns the contiguous tile range [x T8, (x+1) T8), walked in order by
+// its wavefronts, so the rows an XCD works on at one time are neighbours
+// (shared L2 for the gathered vector).  gridDim.x is a multiple of 8.
+struct TileWalk {
+    int base, j, stride, end, ntiles;
+    __device__ TileWalk(int ntiles_) : ntiles(ntiles_) {
+        const int xcd = blockIdx.x & 7;
+        const int per = (ntiles_ + 7) >> 3;
+        base = xcd * per;
+        j = __builtin_amdgcn_readfirstlane((int)(blockIdx.x >> 3) * kWavesPerBlock +
+                                           (int)(threadIdx.x / kWave));
+        stride = (int)(gridDim.x >> 3) * kWavesPerBlock;
+        end = per;
+    }
+    __device__ int next() {  // tile id, or -1 when done
+        if (j >= end) return -1;
+        const int t = base + j;
+        j += stride;
+        return t < ntiles ? t : -1;
+    }
+};
+
+// Stream tiles: 64 consecutive rows whose nonzeros (at most kStreamNnz - 3)
+// are loaded flat by the wavefront with 16-byte loads, all independent.  The
+// products go to the wavefront's own LDS region and lane l then sums row r0+l
+// left to right (rounded products added in CSR order).  The loop is
+// software-pipelined over the wavefront's tiles: while the gathers of tile t
+// are in flight, the loads of tile t+1 are issued too.
+// One pipeline stage: a tile's bounds (uniform: scalar loads), the row bounds
+// of the lane's row, and the lane's 8 slots of the tile's col/val.  Slots are
+// counted from kb = k0 rounded down to a multiple of 4, so lane l loads slots
+// 4l..4l+3 and 256+4l..256+4l+3 with 16-byte loads (one int4 of columns and
+// two double2 of values per group); groups past the tile re-read the tile's
+// first group (cached) and their products are never summed.  The arrays are
+// padded so a group never reads past the allocation.
+struct StreamSet {
+    int r0, nrows, kb, rb_raw, re_raw;
+    int4 c[2];
+    double2 v[4];
+};
+
+__device__ __forceinline__ void stream_load(const CsrDev &A, int t, StreamSet &S) {
+    const int lane = threadIdx.x & (kWave - 1);
+    S.r0 = __builtin_amdgcn_readfirstlane(t * kWave);
+    S.nrows = min(kWave, A.m - S.r0);
+    const int k0 = A.rp[S.r0];
+    const int k1 = A.rp[S.r0 + S.nrows];
+    S.kb = k0 & ~3;
+    const int span = k1 - S.kb;  // slots used by the tile
+    const int i = S.r0 + min(lane, S.nrows - 1);
+    S.rb_raw = A.rp[i];
+    S.re_raw = A.rp[i + 1];
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+        const int sb = 4 * lane + g * 4 * kWave;
+        const int k = S.kb + (sb < span ? sb : 0);
+        S.c[g] = *reinterpret_cast<const int4 *>(A.ci + k);
+        S.v[2 * g] = *reinterpret_cast<const double2 *>(A.val + k);
+        S.v[2 * g + 1] = *reinterpret_cast<const double2 *>(A.val + k + 2);
+    }
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Gather for the loaded tile S, issue tile tn's loads into N, then finish S.
+template <int MODE>
+__device__ __forceinline__ void stream_step(const CsrDev &A, const SpmvArgs &a, double *lds,
+                                            const StreamSet &S, int tn, StreamSet &N,
+                                            double &acc0, double &acc1) {
+    const int lane = threadIdx.x & (kWave - 1);
+    double pv[8];
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+        pv[4 * g + 0] = a.p[S.c[g].x];
+        pv[4 * g + 1] = a.p[S.c[g].y];
+        pv[4 * g + 2] = a.p[S.c[g].z];
+        pv[4 * g + 3] = a.p[S.c[g].w];
+    }
+    const int myrow = S.r0 + min(lane, S.nrows - 1);
+    double pown = 0.0, bv = 0.0;
+    if (MODE == kSpmvDot) pown = a.p_own[myrow];
+    if (MODE == kSpmvResidual) bv = a.b[myrow];
+    stream_load(A, tn, N);
+    // products of every slot (slots outside the tile are never read)
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+        double2 *d = reinterpret_cast<double2 *>(lds + 4 * lane + g * 4 * kWave);
+        d[0] = make_double2(S.v[2 * g].x * pv[4 * g + 0], S.v[2 * g].y * pv[4 * g + 1]);
+        d[1] = make_double2(S.v[2 * g + 1].x * pv[4 * g + 2], S.v[2 * g + 1].y * pv[4 * g + 3]);
+    }
+    wave_lds_sync();
+    const int rb = S.rb_raw - S.kb, re = S.re_raw - S.kb;
+    double s = 0.0;
+    for (int k = rb; k < re; ++k) s += lds[k];
+    if (lane < S.nrows) {
+        if (MODE == kSpmvResidual) {
+            const double rv = bv - s;
+            a.q[myrow] = rv;
+            a.p_dst[myrow] = rv;
+            acc0 = fma(rv, rv, acc0);
+            acc1 = fma(bv, bv, acc1);
+        } else {
+            a.q[myrow] = s;
+            if (MODE == kSpmvDot) acc0 = fma(pown, s, acc0);
+        }
+    }
+    wave_lds_sync();
+}
+
+// The wavefront's tiles, two pipeline stages alternating between register
+// sets (no register moves, so no waits on loads still in flight).  Past the
+// last tile the prefetch re-reads the current tile and is discarded.
+template <int MODE>
+__device__ __forceinline__ void spmv_stream_wave(const CsrDev &A, TileWalk &walk,
+                                                 const SpmvArgs &a, double *lds, double &acc0,
+                                                 double &acc1) {
+    int t = walk.next();
+    if (t < 0) return;
+    StreamSet S0, S1;
+    stream_load(A, t, S0);
+    for (;;) {
+        const int t1 = walk.next();
+        stream_step<MODE>(A, a, lds, S0, t1 >= 0 ? t1 : t, S1, acc0, acc1);
+        if (t1 < 0) break;
+        const int t2 = walk.next();
+        stream_step<MODE>(A, a, lds, S1, t2 >= 0 ? t2 : t1, S0, acc0, acc1);
+        if (t2 < 0) break;
+        t = t2;
+    }
+}
+
+// Sliced tiles: lane l owns row r0+l of the 64-row slice; slot j of all 64
+// rows is contiguous, so the j-th col/val loads and the j-th gather of the
+// wavefront each touch 64 consecutive words (for a stencil, 64 consecutive
+// entries of p along one diagonal).  Each lane sums its row left to right
+// with rounded products, the oracle's order.  Two pipeline stages alternate
+// between register sets: the loads of slice t+1 are issued while slice t's
+// gathers are in flight.
+struct SliceSet {
+    int r0, nrows, off, width, len;
+    int c[kSliceMaxWidth];
+    double v[kSliceMaxWidth];
+};
+
+__device__ __forceinline__ void slice_load(const CsrDev &A, int t, SliceSet &S) {
+    const int lane = threadIdx.x & (kWave - 1);
+    S.r0 = __builtin_amdgcn_readfirstlane(t * kWave);
+    S.nrows = min(kWave, A.m - S.r0);
+    S.off = A.sell_off[t];
+    S.width = (A.sell_off[t + 1] - S.off) / kWave;
+    const int i = S.r0 + min(lane, S.nrows - 1);
+    S.len = lane < S.nrows ? A.rp[i + 1] - A.rp[i] : 0;
+#pragma unroll
+    for (int j = 0; j < kSliceMaxWidth; ++j) {
+        const int k = S.off + (j < S.width ? j : 0) * kWave + lane;
+        S.c[j] = A.sell_ci[k];
+        S.v[j] = A.sell_val[k];
+    }
+}
+
+template <int MODE>
+__device__ __forceinline__ void slice_step(const CsrDev &A, const SpmvArgs &a, const SliceSet &S,
+                                           int tn, SliceSet &N, double &acc0, double &acc1) {
+    const int lane = threadIdx.x & (kWave - 1);
+    double pv[kSliceMaxWidth];
+#pragma unroll
+    for (int j = 0; j < kSliceMaxWidth; ++j) pv[j] = a.p[S.c[j]];
+    const int myrow = S.r0 + min(lane, S.nrows - 1);
+    double pown = 0.0, bv = 0.0;
+    if (MODE == kSpmvDot) pown = a.p_own[myrow];
+    if (MODE == kSpmvResidual) bv = a.b[myrow];
+    slice_load(A, tn, N);
+    double s = 0.0;
+    {
+#pragma clang fp contract(off)
+#pragma unroll
+        for (int j = 0; j < kSliceMaxWidth; ++j)
+            if (j < S.len) s = s + S.v[j] * pv[j];  // rounded product, then the sum
+    }
+    if (lane < S.nrows) {
+        if (MODE == kSpmvResidual) {
+            const double rv = bv - s;
+            a.q[myrow] = rv;
+            a.p_dst[myrow] = rv;
+            acc0 = fma(rv, rv, acc0);
+            acc1 = fma(bv, bv, acc1);
+        } else {
+            a.q[myrow] = s;
+            if (MODE == kSpmvDot) acc0 = fma(pown, s, acc0);
+        }
+    }
+}
+
+// A slice wider than kSliceMaxWidth: a plain loop over its slots.
+template <int MODE>
+__device__ __forceinline__ void slice_wide(const CsrDev &A, const SpmvArgs &a, int t,
+                                           double &acc0, double &acc1) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int r0 = t * kWave, nrows = min(kWave, A.m - r0);
+    const int off = A.sell_off[t];
+    const int width = (A.sell_off[t + 1] - off) / kWave;
+    const int i = r0 + min(lane, nrows - 1);
+    const int len = lane < nrows ? A.rp[i + 1] - A.rp[i] : 0;
+    double s = 0.0;
+    for (int j = 0; j < width; ++j) {
+        const int k = off + j * kWave + lane;
+        const double pv = a.p[A.sell_ci[k]];
+        if (j < len) {
+#pragma clang fp contract(off)
+            s = s + A.sell_val[k] * pv;  // rounded product, then the sum
+        }
+    }
+    if (lane < nrows) {
+        if (MODE == kSpmvResidual) {
+            const double bv = a.b[i];
+            const double rv = bv - s;
+            a.q[i] = rv;
+            a.p_dst[i] = rv;
+            acc0 = fma(rv, rv, acc0);
+            acc1 = fma(bv, bv, acc1);
+        } else {
+            a.q[i] = s;
+            if (MODE == kSpmvDot) acc0 = fma(a.p_own[i], s, acc0);
+        }
+    }
+}
+
+template <int MODE>
+__device__ __forceinline__ void spmv_sliced_wave(const CsrDev &A, TileWalk &walk,
+                                                 const SpmvArgs &a, int wide, double &acc0,
+                                                 double &acc1) {
+    if (wide) {
+        for (int t = walk.next(); t >= 0; t = walk.next()) slice_wide<MODE>(A, a, t, acc0, acc1);
+        return;
+    }
+    int t = walk.next();
+    if (t < 0) return;
+    SliceSet S0, S1;
+    slice_load(A, t, S0);
+    for (;;) {
+        const int t1 = walk.next();
+        slice_step<MODE>(A, a, S0, t1 >= 0 ? t1 : t, S1, acc0, acc1);
+        if (t1 < 0) break;
+        const int t2 = walk.next();
+        slice_step<MODE>(A, a, S1, t2 >= 0 ? t2 : t1, S0, acc0, acc1);
+        if (t2 < 0) break;
+        t = t2;
+    }
+}
+
+// A row longer than kHugeRow: all threads of the workgroup on it.
+template <int MODE>
+__device__ __forceinline__ void spmv_row_wg(const CsrDev &A, int pos, bool identity,
+                                            const SpmvArgs &a, double &acc0, double &acc1,
+                                            double *sh) {
+    const int row = identity ? pos : A.rows[pos];
+    const int beg = A.rp[row], end = A.rp[row + 1];
+    double v = 0.0;
+#pragma unroll 4
+    for (int k = beg + (int)threadIdx.x; k < end; k += kBlock) v = fma(A.val[k], a.p[A.ci[k]], v);
+    const double s = block_sum<kBlock>(v, sh);
+    if (threadIdx.x == 0) emit_row<MODE>(a, row, s, acc0, acc1);
+}
+
+// TILE > 0: one bin of TILE lanes per row in natural row order;
+// TILE == 0: binned rows (any order); TILE == -1: stream tiles;
+// TILE == -2: sliced tiles of width <= kSliceMaxWidth; -3: wider slices.
+template <int MODE, int TILE>
+__global__ __launch_bounds__(kBlock) void k_spmv(int32_t m, const int32_t *__restrict__ rp,
+                                                 const int32_t *__restrict__ ci,
+                                                 const double *__restrict__ val,
+                                                 const int32_t *__restrict__ rows,
+                                                 const int32_t *__restrict__ sell_off,
+                                                 const int32_t *__restrict__ sell_ci,
+                                                 const double *__restrict__ sell_val, Schedule S,
+                                                 SpmvArgs a, double *__restrict__ out,
+                                                 Partials in0, Partials in1,
+                                                 DevState *__restrict__ st, int flags) {
+    const CsrDev A{m, rp, ci, val, rows, sell_off, sell_ci, sell_val};
+    __shared__ double sh[kWavesPerBlock];
+    __shared__ double bc;
+    __shared__ double s_prod[TILE == -1 ? kWavesPerBlock * kStreamNnz : 1];
+    if (flags & kFlagCheckDone) {
+        if (st->done) return;
+        if (flags & kFlagFirstIter) {
+            // stop test at the top of iteration 0 from the setup partials
+            const double rr = reduce_partials(in0, sh, &bc);
+            const double bb = reduce_partials(in1, sh, &bc);
+            const bool conv = stop_test(rr, bb, st->tol);
+            const bool stop = conv || st->maxit <= 0;
+            if (is_block0_thread0()) {
+                st->rho[0] = rr;
+                st->rr = rr;
+                st->bb = bb;
+                if (stop) st->done = conv ? kDoneConverged : kDoneMaxit;
+            }
+            if (stop) return;
+        }
+    }
+    double acc0 = 0.0, acc1 = 0.0;
+    const bool identity = S.identity != 0;
+    TileWalk walk(S.ntiles);
+    if (TILE == -2 || TILE == -3) {
+        spmv_sliced_wave<MODE>(A, walk, a, TILE == -3, acc0, acc1);
+    } else if (TILE < 0) {
+        double *lds = s_prod + (threadIdx.x / kWave) * kStreamNnz;
+        spmv_stream_wave<MODE>(A, walk, a, lds, acc0, acc1);
+    } else if (TILE > 0) {
+        constexpr int L = TILE > 0 ? TILE : 1;
+        constexpr int RW = rows_per_wave_tile(L);
+        for (int t = walk.next(); t >= 0; t = walk.next()) {
+            const int pos0 = t * RW;
+            spmv_wave_tile<L, MODE>(A, pos0, min(RW, A.m - pos0), true, a, acc0, acc1);
+        }
+    } else {
+        for (int t = walk.next(); t >= 0; t = walk.next()) {
+            int bi = 0;
+            while (bi + 1 < S.nbins && t >= S.bins[bi + 1].tile_begin) ++bi;
+            const Bin B = S.bins[bi];
+            const int rw = rows_per_wave_tile(B.lanes);
+            const int pos0 = B.first + (t - B.tile_begin) * rw;
+            const int cnt = min(rw, B.first + B.count - pos0);
+            switch (B.lanes) {
+                case 1: spmv_wave_tile<1, MODE>(A, pos0, cnt, identity, a, acc0, acc1); break;
+                case 2: spmv_wave_tile<2, MODE>(A, pos0, cnt, identity, a, acc0, acc1); break;
+                case 4: spmv_wave_tile<4, MODE>(A, pos0, cnt, identity, a, acc0, acc1); break;
+                case 8: spmv_wave_tile<8, MODE>(A, pos0, cnt, identity, a, acc0, acc1); break;
+                case 16: spmv_wave_tile<16, MODE>(A, pos0, cnt, identity, a, acc0, acc1); break;
+                case 32: spmv_wave_tile<32, MODE>(A, pos0, cnt, identity, a, acc0, acc1); break;
+                default: spmv_wave_tile<64, MODE>(A, pos0, cnt, identity, a, acc0, acc1); break;
+            }
+        }
+        for (int hrow = blockIdx.x; hrow < S.huge_count; hrow += gridDim.x)
+            spmv_row_wg<MODE>(A, S.huge_first + hrow, identity, a, acc0, acc1, sh);
+    }
+    if (MODE == kSpmvPlain) return;
+    const double s0 = block_sum<kBlock>(acc0, sh);
+    double s1 = 0.0;
+    if (MODE == kSpmvResidual) s1 = block_sum<kBlock>(acc1, sh);
+    if (threadIdx.x == 0) {
+        out[blockIdx.x] = s0;
+        if (MODE == kSpmvResidual) out[gridDim.x + blockIdx.x] = s1;
+    }
+}
+
+// x += alpha p, r -= alpha q; partial r^T r per workgroup.
+__global__ __launch_bounds__(kBlock) void k_update_xr(int32_t m, double *__restrict__ x,
+                                                      double *__restrict__ r,
+                                                      const double *__restrict__ p,
+                                                      const double *__restrict__ q,
+                                                      double *__restrict__ out, Partials pq_in,
+                                                      DevState *__restrict__ st, int device_coef,
+                                                      int32_t k, double alpha_arg) {
+    __shared__ double sh[kWavesPerBlock];
+    __shared__ double bc;
+    double alpha = alpha_arg;
+    if (device_coef) {
+        if (st->done) return;
+        const double pq = reduce_partials(pq_in, sh, &bc);
+        if (!(pq > 0.0) || !isfinite(pq)) {
+            if (is_block0_thread0()) {
+                st->pq = pq;
+                st->iter = k;
+                st->done = kDoneBreakdown;
+            }
+            return;
+        }
+        alpha = st->rho[k & 1] / pq;
+        if (is_block0_thread0()) st->pq = pq;
+    }
+    double acc = 0.0;
+    const int64_t npair = m >> 1;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    double2 *x2 = reinterpret_cast<double2 *>(x);
+    double2 *r2 = reinterpret_cast<double2 *>(r);
+    const double2 *p2 = reinterpret_cast<const double2 *>(p);
+    const double2 *q2 = reinterpret_cast<const double2 *>(q);
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < npair; i += stride) {
+        const double2 pv = p2[i], qv = q2[i];
+        double2 xv = x2[i], rv = r2[i];
+        xv.x = fma(alpha, pv.x, xv.x);
+        xv.y = fma(alpha, pv.y, xv.y);
+        rv.x = fma(-alpha, qv.x, rv.x);
+        rv.y = fma(-alpha, qv.y, rv.y);
+        x2[i] = xv;
+        r2[i] = rv;
+        acc = fma(rv.x, rv.x, acc);
+        acc = fma(rv.y, rv.y, acc);
+    }
+    if ((m & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        const int32_t i = m - 1;
+        x[i] = fma(alpha, p[i], x[i]);
+        const double rv = fma(-alpha, q[i], r[i]);
+        r[i] = rv;
+        acc = fma(rv, rv, acc);
+    }
+    const double s = block_sum<kBlock>(acc, sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+// p = r + beta p.
+__global__ __launch_bounds__(kBlock) void k_update_p(int32_t m, const double *__restrict__ r,
+                                                     double *__restrict__ p, Partials rr_in,
+                                                     DevState *__restrict__ st, int device_coef,
+                                                     int32_t k, double beta_arg) {
+    __shared__ double sh[kWavesPerBlock];
+    __shared__ double bc;
+    double beta = beta_arg;
+    if (device_coef) {
+        if (st->done) return;
+        const double rr = reduce_partials(rr_in, sh, &bc);
+        const double rho_k = st->rho[k & 1];
+        beta = rr / rho_k;
+        const bool conv = stop_test(rr, st->bb, st->tol);
+        const bool maxed = k + 1 >= st->maxit;
+        if (is_block0_thread0()) {
+            st->rho[(k + 1) & 1] = rr;
+            st->rr = rr;
+            st->iter = k + 1;
+            if (conv) st->done = kDoneConverged;
+            else if (maxed) st->done = kDoneMaxit;
+        }
+        if (conv || maxed) return;
+    }
+    const int64_t npair = m >> 1;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    double2 *p2 = reinterpret_cast<double2 *>(p);
+    const double2 *r2 = reinterpret_cast<const double2 *>(r);
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < npair; i += stride) {
+        const double2 rv = r2[i];
+        double2 pv = p2[i];
+        pv.x = fma(beta, pv.x, rv.x);
+        pv.y = fma(beta, pv.y, rv.y);
+        p2[i] = pv;
+    }
+    if ((m & 1) && blockIdx.x == 0 && threadIdx.x == 0) p[m - 1] = fma(beta, p[m - 1], r[m - 1]);
+}
+
+// ---------------------------------------------------------------------------
+// Small systems: the whole of Algorithm 1 in one workgroup of 1024 threads.
+// p lives in LDS (every row may read any entry); thread t owns rows
+// t, t + 1024, ... and keeps their x, r, q in registers.
+constexpr int kSmallThreads = 1024;
+constexpr int kSmallMaxRpt = 4;  // more rows per thread spill registers at 1024 threads
+
+template <int RPT>
+__global__ __launch_bounds__(kSmallThreads) void k_cg_small(int32_t n, const int32_t *__restrict__ rp,
+                                                            const int32_t *__restrict__ ci,
+                                                            const double *__restrict__ val,
+                                                            const double *__restrict__ b,
+                                                            double *__restrict__ x, double tol,
+                                                            int32_t maxit, DevState *__restrict__ st) {
+    extern __shared__ double s_p[];
+    __shared__ double sh[kSmallThreads / kWave];
+    __shared__ double bc;
+    const int t = threadIdx.x;
+    double xr[RPT], rr[RPT], qq[RPT];
+    double acc_r = 0.0, acc_b = 0.0;
+    // r = b - A x, p = r, rho = r^T r, bb = b^T b
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int i = t + j * kSmallThreads;
+        xr[j] = 0.0;
+        rr[j] = 0.0;
+        if (i < n) {
+            double s = 0.0;
+            for (int k = rp[i]; k < rp[i + 1]; ++k) s = fma(val[k], x[ci[k]], s);
+            xr[j] = x[i];
+            const double bv = b[i];
+            rr[j] = bv - s;
+            acc_r = fma(rr[j], rr[j], acc_r);
+            acc_b = fma(bv, bv, acc_b);
+            s_p[i] = rr[j];
+        }
+    }
+    double rho = block_allsum<kSmallThreads>(acc_r, sh, &bc);
+    const double bb = block_allsum<kSmallThreads>(acc_b, sh, &bc);
+    const double bnorm = sqrt(bb);
+    int status = kDoneMaxit;
+    int k = 0;
+    for (k = 0; k < maxit; ++k) {
+        if (sqrt(rho) < tol * bnorm || rho == 0.0) {
+            status = kDoneConverged;
+            break;
+        }
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            const int i = t + j * kSmallThreads;
+            qq[j] = 0.0;
+            if (i < n) {
+                double s = 0.0;
+                for (int kk = rp[i]; kk < rp[i + 1]; ++kk) s = fma(val[kk], s_p[ci[kk]], s);
+                qq[j] = s;
+                acc = fma(s_p[i], s, acc);
+            }
+        }
+        const double pq = block_allsum<kSmallThreads>(acc, sh, &bc);
+        if (!(pq > 0.0) || !isfinite(pq)) {
+            status = kDoneBreakdown;
+            break;
+        }
+        const double alpha = rho / pq;
+        acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            const int i = t + j * kSmallThreads;
+            if (i < n) {
+                xr[j] = fma(alpha, s_p[i], xr[j]);
+                rr[j] = fma(-alpha, qq[j], rr[j]);
+                acc = fma(rr[j], rr[j], acc);
+            }
+        }
+        const double rho_new = block_allsum<kSmallThreads>(acc, sh, &bc);
+        const double beta = rho_new / rho;
+        rho = rho_new;
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            const int i = t + j * kSmallThreads;
+            if (i < n) s_p[i] = fma(beta, s_p[i], rr[j]);
+        }
+        __syncthreads();
+    }
+    if (status == kDoneMaxit && (sqrt(rho) < tol * bnorm || rho == 0.0)) status = kDoneConverged;
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int i = t + j * kSmallThreads;
+        if (i < n) x[i] = xr[j];
+    }
+    if (t == 0) {
+        st->iter = k;
+        st->done = status;
+        st->rho[0] = rho;
+        st->rr = rho;
+        st->bb = bb;
+    }
+}
+
+__global__ void k_gather(int32_t cnt, const int32_t *__restrict__ idx, const double *__restrict__ src,
+                         double *__restrict__ dst) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cnt) dst[i] = src[idx[i]];
+}
+
+__global__ void k_scatter(int32_t cnt, const int32_t *__restrict__ idx, const double *__restrict__ src,
+                          double *__restrict__ dst) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cnt) dst[idx[i]] = src[i];
+}
+
+template <int MODE>
+void launch_spmv_mode(const CsrDev &A, const Schedule &S, int grid, const SpmvArgs &a, double *out,
+                      Partials in0, Partials in1, DevState *st, int flags, hipStream_t s) {
+    const int L = S.kind == kTileSliced ? (S.bins[0].lanes <= kSliceMaxWidth ? -2 : -3)
+                  : S.kind == kTileStream ? -1
+                  : (S.identity && S.nbins == 1 && S.huge_count == 0) ? S.bins[0].lanes : 0;
+#define CGMI_SPMV(FL)                                                                          \
+    hipLaunchKernelGGL((k_spmv<MODE, FL>), dim3(grid), dim3(kBlock), 0, s, A.m, A.rp, A.ci, \
+                       A.val, A.rows, A.sell_off, A.sell_ci, A.sell_val, S, a, out, in0, in1, st, \
+                       flags)
+    switch (L) {
+        case 1: CGMI_SPMV(1); break;
+        case 2: CGMI_SPMV(2); break;
+        case 4: CGMI_SPMV(4); break;
+        case 8: CGMI_SPMV(8); break;
+        case 16: CGMI_SPMV(16); break;
+        case 32: CGMI_SPMV(32); break;
+        case 64: CGMI_SPMV(64); break;
+        case -1: CGMI_SPMV(-1); break;
+        case -2: CGMI_SPMV(-2); break;
+        case -3: CGMI_SPMV(-3); break;
+        default: CGMI_SPMV(0); break;
+    }
+#undef CGMI_SPMV
+}
+
+}  // namespace
+
+hipError_t launch_spmv(const CsrDev &A, const Schedule &S, int grid, const double *p, double *q,
+                       const double *p_own, const double *b, double *p_dst, double *out_partials,
+                       Partials in0, Partials in1, DevState *st, int mode, int k0_check,
+                       hipStream_t s) {
+    if (A.m == 0) return hipSuccess;
+    SpmvArgs a{p, q, p_own, b, p_dst};
+    switch (mode) {
+        case kSpmvPlain:
+            launch_spmv_mode<kSpmvPlain>(A, S, grid, a, nullptr, in0, in1, nullptr, 0, s);
+            break;
+        case kSpmvDot: {
+            const int flags = st ? (kFlagCheckDone | (k0_check ? kFlagFirstIter : 0)) : 0;
+            launch_spmv_mode<kSpmvDot>(A, S, grid, a, out_partials, in0, in1, st, flags, s);
+            break;
+        }
+        case kSpmvResidual:
+            launch_spmv_mode<kSpmvResidual>(A, S, grid, a, out_partials, in0, in1, nullptr, 0, s);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_update_xr(int32_t m, int grid, double *x, double *r, const double *p_own,
+                            const double *q, double *out_partials, Partials pq, DevState *st,
+                            int device_coef, int32_t k, double alpha_arg, hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_update_xr, dim3(grid), dim3(kBlock), 0, s, m, x, r, p_own, q, out_partials,
+                       pq, st, device_coef, k, alpha_arg);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_p(int32_t m, int grid, const double *r, double *p_own, Partials rr,
+                           DevState *st, int device_coef, int32_t k, double beta_arg,
+                           hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_update_p, dim3(grid), dim3(kBlock), 0, s, m, r, p_own, rr, st, device_coef,
+                       k, beta_arg);
+    return hipGetLastError();
+}
+
+int small_path_max_rows() {
+    static int cached = -1;
+    if (cached < 0) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        size_t lds = 64 * 1024;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            lds = prop.sharedMemPerBlock;
+        const int by_lds = (int)((lds > 1024 ? lds - 1024 : 0) / sizeof(double));
+        cached = by_lds < kSmallThreads * kSmallMaxRpt ? by_lds : kSmallThreads * kSmallMaxRpt;
+    }
+    return cached;
+}
+
+hipError_t launch_cg_small(int32_t n, const int32_t *rp, const int32_t *ci, const double *val,
+                           const double *b, double *x, double tol, int32_t maxit, DevState *st,
+                           hipStream_t s) {
+    if (n <= 0 || n > small_path_max_rows()) return hipErrorInvalidValue;
+    const size_t lds = sizeof(double) * (size_t)n;
+    const int rpt = (n + kSmallThreads - 1) / kSmallThreads;
+#define CGMI_SMALL(R)                                                                               \
+    hipLaunchKernelGGL(k_cg_small<R>, dim3(1), dim3(kSmallThreads), lds, s, n, rp, ci, val, b, x, \
+                       tol, maxit, st)
+    if (rpt <= 1) CGMI_SMALL(1);
+    else if (rpt <= 2) CGMI_SMALL(2);
+    else CGMI_SMALL(4);
+#undef CGMI_SMALL
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(int32_t cnt, const int32_t *idx, const double *src, double *dst,
+                         hipStream_t s) {
+    if (cnt <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather, dim3((cnt + 255) / 256), dim3(256), 0, s, cnt, idx, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(int32_t cnt, const int32_t *idx, const double *src, double *dst,
+                          hipStream_t s) {
+    if (cnt <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter, dim3((cnt + 255) / 256), dim3(256), 0, s, cnt, idx, src, dst);
+    return hipGetLastError();
+}
+
+int device_cu_count() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 256;
+    return prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+}
+
+}  // namespace cgmi

@@ -1,0 +1,105 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+public header declares, and rejects malformed input before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            names |= set(re.findall(r"^\s*(?:const\s+)?[\w\s\*]*?\b(cg_\w+)\s*\(", text, re.M))
+    return names
+
+
+@pytest.fixture(scope="module")
+def cg():
+    from paper_2608_09647_amd import cgmi
+    if not os.path.exists(cgmi.LIB_PATH):
+        pytest.skip("libcgmi.so not built")
+    return cgmi
+
+
+def test_header_symbols_are_exported(cg):
+    declared = _declared_symbols()
+    assert {"cg_create", "cg_solve", "cg_spmv", "cg_destroy"} <= declared
+    L = cg.lib()
+    for name in sorted(declared):
+        assert hasattr(L, name), f"{name} declared in include/ but not exported"
+    assert set(cg.EXPORTED) <= declared
+
+
+def test_default_opts(cg):
+    o = cg.default_opts()
+    assert o.precision == cg.PREC_FP64 and o.precond == cg.PC_NONE
+    assert o.exchange == cg.EXCHANGE_WHOLE and o.check_every >= 1 and 0 < o.refine_delta < 1
+
+
+def _create(cg, n, rp, ci, va, rb=0, re=None):
+    h = ctypes.c_void_p()
+    rp = np.ascontiguousarray(rp, np.int32)
+    ci = np.ascontiguousarray(ci, np.int32)
+    va = np.ascontiguousarray(va, np.float64)
+    code = cg.lib().cg_create(n, int(rp[-1]) if rp.size else 0, rp.ctypes.data, ci.ctypes.data,
+                              va.ctypes.data, rb, n if re is None else re, ctypes.byref(h))
+    return code, h
+
+
+@pytest.mark.parametrize("case", ["unsorted", "duplicate", "col_range", "rp_decrease", "rp0",
+                                  "range", "neg_n"])
+def test_malformed_input_rejected(cg, case):
+    rp, ci, va = [0, 2, 3, 5], [0, 1, 1, 0, 2], [4.0, -1.0, 4.0, -1.0, 4.0]
+    n, rb, re = 3, 0, 3
+    if case == "unsorted":
+        ci = [1, 0, 1, 0, 2]
+    elif case == "duplicate":
+        ci = [0, 0, 1, 0, 2]
+    elif case == "col_range":
+        ci = [0, 3, 1, 0, 2]
+    elif case == "rp_decrease":
+        rp = [0, 3, 2, 5]
+    elif case == "rp0":
+        rp = [1, 2, 3, 5]
+    elif case == "range":
+        rb, re = 2, 1
+    elif case == "neg_n":
+        n = -1
+    code, h = _create(cg, n, rp, ci, va, rb, re)
+    assert code == cg.CG_EINVAL
+    assert not h.value
+    assert cg.last_error() != ""
+
+
+def test_destroy_null_is_noop(cg):
+    cg.lib().cg_destroy(None)
+
+
+def test_null_handle_errors(cg):
+    r = cg.CgResult()
+    assert cg.lib().cg_solve(None, None, None, 1e-10, 10, ctypes.byref(r)) == cg.CG_EINVAL
+    assert cg.lib().cg_spmv(None, None, None) == cg.CG_EINVAL
+    o = cg.default_opts()
+    assert cg.lib().cg_set_opts(None, ctypes.byref(o)) == cg.CG_EINVAL
+
+
+def test_struct_sizes_match_header(cg):
+    # cg_opts: 10 x int32 + double; cg_result: as laid out in include/cgmi.h
+    assert ctypes.sizeof(cg.CgOpts) == 48
+    assert ctypes.sizeof(cg.CgResult) == 128
+
+
+def test_product_path_does_not_reach_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2608_09647_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".cpp", ".hip", ".h")):
+                text = open(os.path.join(dirpath, fn)).read()
+                assert "import oracle" not in text and "from oracle" not in text, fn
+                assert "liboracle" not in text and "cg_oracle" not in text, fn
