@@ -134,6 +134,13 @@ int cg_get_opts(const cg_handle *h, cg_opts *o);
  * host threads from a copy of x). */
 int cg_spmv(cg_handle *h, const double *x, double *y);
 
+/* y = A32 x in float32 (the inner SpMV of mixed precision): float32 copies
+ * of the values, float32 x (device, n), float32 y (device, n); each row summed
+ * in float32.  GPU-only handles with cg_opts.precision = CG_PREC_MIXED set
+ * (which builds the float32 copies); CG_EINVAL otherwise.  Queued on the
+ * stream. */
+int cg_spmv_f32(cg_handle *h, const float *x, float *y);
+
 /* Solve A x = b by CG (Algorithm 1): x (device, in/out) holds the initial
  * guess and receives the last iterate.  Stops at the top of an iteration when
  * sqrt(r^T r) < tol * ||b||_2 (tol = 0: fixed work of maxit iterations).

@@ -23,7 +23,7 @@ EXCHANGE_WHOLE, EXCHANGE_HALO = 0, 1
 
 # Every symbol the public header declares (checked by the tests).
 EXPORTED = ["cg_create", "cg_destroy", "cg_set_stream", "cg_default_opts", "cg_set_opts",
-            "cg_get_opts", "cg_spmv", "cg_solve", "cg_slice_info", "cg_read_slice",
+            "cg_get_opts", "cg_spmv", "cg_spmv_f32", "cg_solve", "cg_slice_info", "cg_read_slice",
             "cg_last_error"]
 
 
@@ -83,6 +83,8 @@ def lib() -> ctypes.CDLL:
         L.cg_get_opts.restype = ctypes.c_int
         L.cg_spmv.argtypes = [_vp, _vp, _vp]
         L.cg_spmv.restype = ctypes.c_int
+        L.cg_spmv_f32.argtypes = [_vp, _vp, _vp]
+        L.cg_spmv_f32.restype = ctypes.c_int
         L.cg_solve.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int32,
                                ctypes.POINTER(CgResult)]
         L.cg_solve.restype = ctypes.c_int
@@ -110,6 +112,14 @@ def default_opts() -> CgOpts:
     o = CgOpts()
     lib().cg_default_opts(ctypes.byref(o))
     return o
+
+
+def _dev_f32(t, n, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32:
+        raise TypeError(f"{name} must be a CUDA float32 tensor")
+    if not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name} must be contiguous with {n} elements")
+    return ctypes.c_void_p(t.data_ptr())
 
 
 def _dev_f64(t, n, name):
@@ -177,6 +187,12 @@ class Solver:
         if y is None:
             y = torch.empty_like(x)
         _check(lib().cg_spmv(self._h, _dev_f64(x, self.n, "x"), _dev_f64(y, self.n, "y")))
+        return y
+
+    def spmv_f32(self, x, y=None):
+        if y is None:
+            y = torch.empty_like(x)
+        _check(lib().cg_spmv_f32(self._h, _dev_f32(x, self.n, "x"), _dev_f32(y, self.n, "y")))
         return y
 
     def solve(self, b, x=None, tol: float = 1e-10, maxit: int = 10000, check: bool = True):

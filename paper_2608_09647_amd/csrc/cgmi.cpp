@@ -88,6 +88,10 @@ struct cg_handle {
     // sliced (slot-major) copy of the block, built when that tiling is chosen
     int32_t *d_sell_off = nullptr, *d_sell_ci = nullptr;
     double *d_sell_val = nullptr;
+    // mixed precision: float32 copies of the values and float32 inner vectors
+    float *d_val32 = nullptr, *d_sell_val32 = nullptr;
+    float *d_r32 = nullptr, *d_p32 = nullptr, *d_q32 = nullptr;
+    size_t sell_slots = 0;
     Schedule sched{};
     int spmv_grid = 0, vec_grid = 0;
 
@@ -113,7 +117,7 @@ struct cg_handle {
 
     CsrDev csr() const {
         return CsrDev{m, d_rp, d_ci, d_val, sched.identity ? nullptr : d_rows,
-                      d_sell_off, d_sell_ci, d_sell_val};
+                      d_sell_off, d_sell_ci, d_sell_val, d_val32, d_sell_val32};
     }
     bool gpu_only() const { return rb == 0 && re == n && n > 0; }
     bool host_only() const { return m == 0; }
@@ -254,6 +258,7 @@ static int build_sliced(cg_handle *h) {
         off[t + 1] = off[t] + w * kWaveSize;
     }
     const size_t slots = (size_t)off[nt];
+    h->sell_slots = slots ? slots : 1;
     std::vector<int32_t> sci(slots ? slots : 1, 0);
     std::vector<double> sval(slots ? slots : 1, 0.0);
     for (int32_t t = 0; t < nt; ++t) {
@@ -279,10 +284,40 @@ static int build_sliced(cg_handle *h) {
     if (e == hipSuccess) e = hipMemcpy(h->d_sell_val, sval.data(), sizeof(double) * sval.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         hipFree(h->d_sell_off); hipFree(h->d_sell_ci); hipFree(h->d_sell_val);
+    hipFree(h->d_val32); hipFree(h->d_sell_val32); hipFree(h->d_r32); hipFree(h->d_p32); hipFree(h->d_q32);
         h->d_sell_off = h->d_sell_ci = nullptr;
         h->d_sell_val = nullptr;
         return fail(CG_ENOMEM, "sliced layout upload failed: %s", hipGetErrorString(e));
     }
+    return CG_OK;
+}
+
+// float32 copies of the block's values (CSR and, if built, sliced) and the
+// float32 inner vectors; built on first use of mixed precision.
+static int ensure_mixed(cg_handle *h) {
+    const size_t nv = (size_t)h->nnz_gpu + kStreamNnz;
+    hipError_t e = hipSuccess;
+    if (!h->d_val32) {
+        std::vector<float> v32(nv, 0.0f);
+        for (int64_t k = 0; k < h->nnz_gpu; ++k) v32[k] = (float)h->h_val[h->h_rp[h->rb] + k];
+        e = dmalloc(&h->d_val32, nv);
+        if (e == hipSuccess) e = hipMemcpy(h->d_val32, v32.data(), sizeof(float) * nv, hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess && h->d_sell_val && !h->d_sell_val32) {
+        std::vector<double> sv(h->sell_slots);
+        e = hipMemcpy(sv.data(), h->d_sell_val, sizeof(double) * sv.size(), hipMemcpyDeviceToHost);
+        std::vector<float> sv32(sv.size());
+        for (size_t k = 0; k < sv.size(); ++k) sv32[k] = (float)sv[k];
+        if (e == hipSuccess) e = dmalloc(&h->d_sell_val32, sv32.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(h->d_sell_val32, sv32.data(), sizeof(float) * sv32.size(), hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess && !h->d_r32) {
+        e = dmalloc(&h->d_r32, (size_t)h->m + 2);
+        if (e == hipSuccess) e = dmalloc(&h->d_p32, (size_t)h->n + 2);
+        if (e == hipSuccess) e = dmalloc(&h->d_q32, (size_t)h->m + 2);
+    }
+    if (e != hipSuccess) return fail(CG_ENOMEM, "mixed-precision buffers: %s", hipGetErrorString(e));
     return CG_OK;
 }
 
@@ -291,6 +326,12 @@ static int apply_schedule(cg_handle *h) {
     build_schedule(h, rows);
     if (h->sched.kind == kTileSliced) {
         const int rc = build_sliced(h);
+        if (rc) return rc;
+    }
+    if (h->opts.precision == CG_PREC_MIXED) {
+        if (h->sched.kind == kTileStream)
+            return fail(CG_EINVAL, "stream tiles have no float32 variant: use spmv_kind 0, 1 or 3");
+        const int rc = ensure_mixed(h);
         if (rc) return rc;
     }
     if (!rows.empty()) {
@@ -309,6 +350,7 @@ static int apply_schedule(cg_handle *h) {
 static void free_device(cg_handle *h) {
     hipFree(h->d_rp); hipFree(h->d_ci); hipFree(h->d_rows); hipFree(h->d_val);
     hipFree(h->d_sell_off); hipFree(h->d_sell_ci); hipFree(h->d_sell_val);
+    hipFree(h->d_val32); hipFree(h->d_sell_val32); hipFree(h->d_r32); hipFree(h->d_p32); hipFree(h->d_q32);
     hipFree(h->d_pbuf); hipFree(h->d_x); hipFree(h->d_r); hipFree(h->d_q);
     hipFree(h->d_part_setup); hipFree(h->d_part_pq); hipFree(h->d_part_rr); hipFree(h->d_state);
     hipFree(h->d_halo_d2h); hipFree(h->d_halo_h2d); hipFree(h->d_pack_d2h); hipFree(h->d_pack_h2d);
@@ -732,6 +774,147 @@ static int solve_gpu_only(cg_handle *h, const double *b, double *x, double tol, 
 }
 
 // ---------------------------------------------------------------------------
+// Mixed precision (GPU-only): float32 inner CG, float64 reliable updates.
+// The device runs inner iterations and stops itself when a refinement is due;
+// the host then forms the float64 true residual b - A x, decides convergence
+// on it, restarts the float32 residual from it and resumes.
+
+static int solve_gpu_mixed(cg_handle *h, const double *b, double *x, double tol, int32_t maxit,
+                           cg_result *res) {
+    const int32_t n = h->n;
+    hipStream_t st = h->stream;
+    const int Gs = h->spmv_grid, Gv = h->vec_grid;
+    const Partials pq{h->d_part_pq, Gs}, rrp{h->d_part_rr, Gv};
+    const double t0 = now();
+    double t_spmv = 0.0;
+    int n_spmv = 0;
+    HIP_TRY(hipMemcpyAsync(h->d_x, x, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    int rc = gpu_state_init(h, tol, maxit);
+    if (rc) return rc;
+    // float64 true residual r64 = b - A x (into d_r) and its norm
+    auto true_residual = [&](double *rr, double *bb) -> int {
+        HIP_TRY(launch_spmv(h->csr(), h->sched, Gs, h->d_x, h->d_r, nullptr, b, h->d_r,
+                            h->d_part_setup, no_partials(), no_partials(), nullptr, kSpmvResidual, 0, st));
+        return sum_partials_host(h, h->d_part_setup, Gs, 2, rr, bb);
+    };
+    double rr_true = 0.0, bb = 0.0;
+    if ((rc = true_residual(&rr_true, &bb))) return rc;
+    int nref = 1;
+    if (bb == 0.0) {
+        HIP_TRY(hipMemsetAsync(x, 0, sizeof(double) * n, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (res) { res->status = CG_OK; res->converged = 1; res->fp64_residuals = nref; }
+        return CG_OK;
+    }
+    const double bnorm = std::sqrt(bb);
+    int status = CG_MAXIT, fell_back = 0;
+    int32_t k = 0;
+    if (std::sqrt(rr_true) < tol * bnorm || rr_true == 0.0) {
+        status = CG_OK;
+    } else {
+        double rho0 = 0.0;
+        HIP_TRY(launch_convert_residual(n, Gv, h->d_r, h->d_r32, h->d_p32, h->d_part_rr, 1, st));
+        if ((rc = sum_partials_host(h, h->d_part_rr, Gv, 1, &rho0, nullptr))) return rc;
+        DevState &S = *h->h_state;
+        S.rho[0] = rho0;
+        S.bb = bb;
+        S.rmax = std::sqrt(rho0);
+        S.done = kDoneRunning;
+        S.iter = 0;
+        HIP_TRY(hipMemcpyAsync(h->d_state, h->h_state, sizeof(DevState), hipMemcpyHostToDevice, st));
+        const int C = h->opts.check_every;
+        std::vector<hipEvent_t> ev;
+        if (h->opts.profile) {
+            ev.resize(2 * (size_t)C);
+            for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+        }
+        double prev_true = std::sqrt(rr_true);
+        int stalls = 0;
+        while (k < maxit) {
+            const int32_t chunk = std::min<int32_t>(C, maxit - k);
+            for (int32_t j = 0; j < chunk; ++j) {
+                if (h->opts.profile) HIP_TRY(hipEventRecord(ev[2 * j], st));
+                HIP_TRY(launch_spmv_f32(h->csr(), h->sched, Gs, h->d_p32, h->d_q32, h->d_p32,
+                                        h->d_part_pq, h->d_state, kSpmvDot, st));
+                if (h->opts.profile) HIP_TRY(hipEventRecord(ev[2 * j + 1], st));
+                HIP_TRY(launch_update_xr_mixed(n, Gv, h->d_x, h->d_r32, h->d_p32, h->d_q32,
+                                               h->d_part_rr, pq, h->d_state, k + j, st));
+                HIP_TRY(launch_update_p_mixed(n, Gv, h->d_r32, h->d_p32, rrp, h->d_state, 1, k + j,
+                                              0.0, st));
+            }
+            if ((rc = gpu_state_read(h))) break;
+            const int32_t it0 = k;
+            k = S.iter;
+            if (h->opts.profile) {
+                const int32_t ran = std::max(0, std::min<int32_t>(chunk, k - it0 + (S.done == kDoneBreakdown ? 1 : 0)));
+                for (int32_t j = 0; j < ran; ++j) {
+                    float ms = 0.f;
+                    HIP_TRY(hipEventElapsedTime(&ms, ev[2 * j], ev[2 * j + 1]));
+                    t_spmv += 1e-3 * ms;
+                    ++n_spmv;
+                }
+            }
+            if (S.done == kDoneBreakdown) { status = CG_EBREAKDOWN; break; }
+            if (S.done == kDoneRefine) {
+                // float64 refinement: true residual, its norm, fresh float32 residual
+                if ((rc = true_residual(&rr_true, &bb))) break;
+                ++nref;
+                const double tn = std::sqrt(rr_true);
+                if (tn < tol * bnorm || rr_true == 0.0) { status = CG_OK; break; }
+                if (k >= maxit) break;
+                // stagnation of the float32 inner solve: hand over to float64 CG
+                stalls = tn > 0.5 * prev_true ? stalls + 1 : 0;
+                prev_true = tn;
+                if (stalls >= 3) { fell_back = 1; break; }
+                double rho_new = 0.0;
+                HIP_TRY(launch_convert_residual(n, Gv, h->d_r, h->d_r32, h->d_p32, h->d_part_rr, 0, st));
+                if ((rc = sum_partials_host(h, h->d_part_rr, Gv, 1, &rho_new, nullptr))) break;
+                const double beta = rho_new / S.rho[(k - 1) & 1];
+                HIP_TRY(launch_update_p_mixed(n, Gv, h->d_r32, h->d_p32, rrp, h->d_state, 0, k, beta, st));
+                S.rho[k & 1] = rho_new;
+                S.rmax = std::sqrt(rho_new);
+                S.done = kDoneRunning;
+                HIP_TRY(hipMemcpyAsync(h->d_state, h->h_state, sizeof(DevState), hipMemcpyHostToDevice, st));
+                continue;
+            }
+            if (S.done != kDoneRunning) break;  // iteration limit
+        }
+        for (auto &e : ev) (void)hipEventDestroy(e);
+        if (rc) return rc;
+    }
+    HIP_TRY(hipMemcpyAsync(x, h->d_x, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (fell_back) {
+        // finish with float64 CG from the current iterate
+        cg_result r64{};
+        const int32_t left = std::max(0, maxit - k);
+        const int prec = h->opts.precision;
+        h->opts.precision = CG_PREC_FP64;
+        rc = solve_gpu_only(h, b, x, tol, left, &r64);
+        h->opts.precision = prec;
+        if (rc < 0) return rc;
+        status = rc;
+        k += r64.iterations;
+        nref += 1;
+    }
+    double rr_fin = 0.0, bb_fin = 0.0;
+    if ((rc = gpu_true_residual(h, b, x, &rr_fin, &bb_fin))) return rc;
+    if (res) {
+        res->status = status;
+        res->iterations = k;
+        res->converged = status == CG_OK;
+        res->fp64_residuals = nref;
+        res->rel_res_recur = std::sqrt(h->h_state->rr) / bnorm;
+        res->rel_res_true = std::sqrt(rr_fin) / std::sqrt(bb_fin);
+        res->t_gpu = now() - t0;
+        res->t_spmv = t_spmv;
+        res->n_spmv = n_spmv;
+        res->fell_back = fell_back;
+    }
+    return status;
+}
+
+// ---------------------------------------------------------------------------
 // split solve: GPU rows [rb, re) and host rows, explicit p exchange
 
 namespace {
@@ -965,7 +1148,8 @@ extern "C" int cg_solve(cg_handle *h, const double *b, double *x, double tol, in
     int rc;
     if (h->gpu_only()) {
         if (h->nnz == 0) return fail(CG_EINVAL, "matrix has no nonzeros");
-        rc = solve_gpu_only(h, b, x, tol, maxit, res);
+        if (h->opts.precision == CG_PREC_MIXED) rc = solve_gpu_mixed(h, b, x, tol, maxit, res);
+        else rc = solve_gpu_only(h, b, x, tol, maxit, res);
     } else {
         rc = solve_split(h, b, x, tol, maxit, res);
     }
@@ -1013,5 +1197,17 @@ extern "C" int cg_spmv(cg_handle *h, const double *x, double *y) {
     if (rb > 0) HIP_TRY(hipMemcpyAsync(y, hq, sizeof(double) * rb, hipMemcpyHostToDevice, h->stream));
     if (re < n) HIP_TRY(hipMemcpyAsync(y + re, hq + re, sizeof(double) * (n - re), hipMemcpyHostToDevice, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
+    return CG_OK;
+}
+
+extern "C" int cg_spmv_f32(cg_handle *h, const float *x, float *y) {
+    g_err.clear();
+    if (!h) return fail(CG_EINVAL, "handle is NULL");
+    if (!h->gpu_only() || h->opts.precision != CG_PREC_MIXED || !h->d_val32)
+        return fail(CG_EINVAL, "cg_spmv_f32 needs a GPU-only handle with mixed precision set");
+    if (!x || !y) return fail(CG_EINVAL, "x/y is NULL");
+    HIP_TRY(hipSetDevice(h->dev));
+    HIP_TRY(launch_spmv_f32(h->csr(), h->sched, h->spmv_grid, x, y, nullptr, nullptr, nullptr,
+                            kSpmvPlain, h->stream));
     return CG_OK;
 }

@@ -35,7 +35,7 @@ struct DevState {
     int32_t nrefine;   // mixed precision: float64 residuals formed
 };
 
-enum { kDoneRunning = 0, kDoneConverged = 1, kDoneMaxit = 2, kDoneBreakdown = 3 };
+enum { kDoneRunning = 0, kDoneConverged = 1, kDoneMaxit = 2, kDoneBreakdown = 3, kDoneRefine = 4 };
 
 // One class of rows processed with the same number of lanes per row.
 struct Bin {
@@ -85,10 +85,12 @@ struct CsrDev {
     const int32_t *rp;
     const int32_t *ci;
     const double *val;
-    const int32_t *rows;     // row list ordered by bin (nullptr when identity)
-    const int32_t *sell_off; // sliced layout: slice offsets (ntiles + 1)
-    const int32_t *sell_ci;  //   slot-major columns
-    const double *sell_val;  //   slot-major values
+    const int32_t *rows;      // row list ordered by bin (nullptr when identity)
+    const int32_t *sell_off;  // sliced layout: slice offsets (ntiles + 1)
+    const int32_t *sell_ci;   //   slot-major columns
+    const double *sell_val;   //   slot-major values
+    const float *val32;       // float32 copies of the values (mixed precision)
+    const float *sell_val32;
 };
 
 // Partial sums of one reduction: one value per workgroup of the kernel that
@@ -116,6 +118,30 @@ hipError_t launch_spmv(const CsrDev &A, const Schedule &S, int grid, const doubl
                        const double *p_own, const double *b, double *p_dst, double *out_partials,
                        Partials in0, Partials in1, DevState *st, int mode, int k0_check,
                        hipStream_t s);
+
+// float32 SpMV (mixed precision): q32 = A32 p32 with kSpmvPlain or kSpmvDot
+// (out_partials[wg] = sum of float64 products p_own_i q_i; with st, an early
+// exit once the solve has stopped).  Vector-bin and sliced tilings only.
+hipError_t launch_spmv_f32(const CsrDev &A, const Schedule &S, int grid, const float *p, float *q,
+                           const float *p_own, double *out_partials, DevState *st, int mode,
+                           hipStream_t s);
+
+// Mixed precision vector kernels (float32 r, p, q; float64 x and sums).
+//   update: alpha = rho_k / sum(pq); x += alpha p; r -= (float)alpha q;
+//           out[wg] = sum r_i^2 (float64).  Breakdown as for launch_update_xr.
+//   p step: rho_{k+1} = sum(rr); a refinement is requested (st->done =
+//           kDoneRefine, no update) when sqrt(rho_{k+1}) < delta * rmax or
+//           < tol ||b||; otherwise p = r + (float)beta p.  device_coef = 0:
+//           p = r + (float)beta_arg p with no test.
+//   convert: r32 = (float) r64, out[wg] = sum r32_i^2; with init, p32 = r32.
+hipError_t launch_update_xr_mixed(int32_t m, int grid, double *x, float *r, const float *p,
+                                  const float *q, double *out_partials, Partials pq, DevState *st,
+                                  int32_t k, hipStream_t s);
+hipError_t launch_update_p_mixed(int32_t m, int grid, const float *r, float *p, Partials rr,
+                                 DevState *st, int device_coef, int32_t k, double beta_arg,
+                                 hipStream_t s);
+hipError_t launch_convert_residual(int32_t m, int grid, const double *r64, float *r32, float *p32,
+                                   double *out_partials, int init_p, hipStream_t s);
 
 // x += alpha p, r -= alpha q; out_partials[wg] = sum r_i^2.
 // device_coef: alpha = rho_k / sum(pq), rho_k = st->rho[k & 1]; a breakdown

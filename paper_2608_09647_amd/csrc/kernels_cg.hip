@@ -79,42 +79,53 @@ __device__ __forceinline__ bool stop_test(double rho, double bb, double tol) {
 
 __device__ __forceinline__ bool is_block0_thread0() { return blockIdx.x == 0 && threadIdx.x == 0; }
 
-template <int L>
-__device__ __forceinline__ double group_sum(double v) {
+template <int L, class T>
+__device__ __forceinline__ T group_sum(T v) {
 #pragma unroll
     for (int o = L / 2; o > 0; o >>= 1) v += __shfl_down(v, o, kWave);
     return v;  // valid in the group's first lane
 }
 
+// T: float64, or float32 for the inner solve of mixed precision.
+template <class T>
 struct SpmvArgs {
-    const double *__restrict__ p;      // gathered vector (full length)
-    double *__restrict__ q;            // output rows (local)
-    const double *__restrict__ p_own;  // p at the block's own rows (dot)
-    const double *__restrict__ b;      // residual mode: right-hand side (local)
-    double *__restrict__ p_dst;        // residual mode: copy of r (local)
+    const T *__restrict__ p;      // gathered vector (full length)
+    T *__restrict__ q;            // output rows (local)
+    const T *__restrict__ p_own;  // p at the block's own rows (dot)
+    const T *__restrict__ b;      // residual mode: right-hand side (local)
+    T *__restrict__ p_dst;        // residual mode: copy of r (local)
 };
 
-template <int MODE>
-__device__ __forceinline__ void emit_row(const SpmvArgs &a, int row, double s, double &acc0,
+template <class T> __device__ __forceinline__ const T *csr_vals(const CsrDev &A);
+template <> __device__ __forceinline__ const double *csr_vals<double>(const CsrDev &A) { return A.val; }
+template <> __device__ __forceinline__ const float *csr_vals<float>(const CsrDev &A) { return A.val32; }
+template <class T> __device__ __forceinline__ const T *sell_vals(const CsrDev &A);
+template <> __device__ __forceinline__ const double *sell_vals<double>(const CsrDev &A) { return A.sell_val; }
+template <> __device__ __forceinline__ const float *sell_vals<float>(const CsrDev &A) { return A.sell_val32; }
+
+// Dot contributions and residual norms are always accumulated in float64.
+template <int MODE, class T>
+__device__ __forceinline__ void emit_row(const SpmvArgs<T> &a, int row, T s, double &acc0,
                                          double &acc1) {
     if (MODE == kSpmvResidual) {
-        const double bv = a.b[row];
-        const double rv = bv - s;
+        const T bv = a.b[row];
+        const T rv = bv - s;
         a.q[row] = rv;
         a.p_dst[row] = rv;
-        acc0 = fma(rv, rv, acc0);
-        acc1 = fma(bv, bv, acc1);
+        acc0 = fma((double)rv, (double)rv, acc0);
+        acc1 = fma((double)bv, (double)bv, acc1);
     } else {
         a.q[row] = s;
-        if (MODE == kSpmvDot) acc0 = fma(a.p_own[row], s, acc0);
+        if (MODE == kSpmvDot) acc0 = fma((double)a.p_own[row], (double)s, acc0);
     }
 }
 
 // One wavefront tile: `cnt` (<= 64) rows starting at row-list position pos0,
 // L lanes per row, rows_per_group(L) rows per group.
-template <int L, int MODE>
+template <int L, int MODE, class T>
 __device__ __forceinline__ void spmv_wave_tile(const CsrDev &A, int pos0, int cnt, bool identity,
-                                               const SpmvArgs &a, double &acc0, double &acc1) {
+                                               const SpmvArgs<T> &a, double &acc0, double &acc1) {
+    const T *__restrict__ vals = csr_vals<T>(A);
     constexpr int G = kWave / L;
     constexpr int U = rows_per_group(L);
     const int lane = threadIdx.x & (kWave - 1);
@@ -129,7 +140,7 @@ __device__ __forceinline__ void spmv_wave_tile(const CsrDev &A, int pos0, int cn
         row_l = -1;
         end_l = beg_l;
     }
-    double sum[U];
+    T sum[U];
     int rowu[U], endu[U], nextu[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -141,9 +152,9 @@ __device__ __forceinline__ void spmv_wave_tile(const CsrDev &A, int pos0, int cn
         const bool ok = k < end;
         const int kk = ok ? k : 0;  // entry 0 always holds a valid column
         const int c = A.ci[kk];
-        const double v = A.val[kk];
-        const double pv = a.p[c];
-        sum[u] = ok ? v * pv : 0.0;
+        const T v = vals[kk];
+        const T pv = a.p[c];
+        sum[u] = ok ? v * pv : T(0);
         rowu[u] = row;
         endu[u] = end;
         nextu[u] = k + L;
@@ -151,12 +162,12 @@ __device__ __forceinline__ void spmv_wave_tile(const CsrDev &A, int pos0, int cn
 #pragma unroll
     for (int u = 0; u < U; ++u) {
 #pragma unroll 2
-        for (int k = nextu[u]; k < endu[u]; k += L) sum[u] = fma(A.val[k], a.p[A.ci[k]], sum[u]);
+        for (int k = nextu[u]; k < endu[u]; k += L) sum[u] = fma(vals[k], a.p[A.ci[k]], sum[u]);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        const double s = group_sum<L>(sum[u]);
-        if (gl == 0 && rowu[u] >= 0) emit_row<MODE>(a, rowu[u], s, acc0, acc1);
+        const T s = group_sum<L, T>(sum[u]);
+        if (gl == 0 && rowu[u] >= 0) emit_row<MODE, T>(a, rowu[u], s, acc0, acc1);
     }
 }
 
@@ -231,7 +242,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // Gather for the loaded tile S, issue tile tn's loads into N, then finish S.
 template <int MODE>
-__device__ __forceinline__ void stream_step(const CsrDev &A, const SpmvArgs &a, double *lds,
+__device__ __forceinline__ void stream_step(const CsrDev &A, const SpmvArgs<double> &a, double *lds,
                                             const StreamSet &S, int tn, StreamSet &N,
                                             double &acc0, double &acc1) {
     const int lane = threadIdx.x & (kWave - 1);
@@ -279,7 +290,7 @@ __device__ __forceinline__ void stream_step(const CsrDev &A, const SpmvArgs &a, 
 // last tile the prefetch re-reads the current tile and is discarded.
 template <int MODE>
 __device__ __forceinline__ void spmv_stream_wave(const CsrDev &A, TileWalk &walk,
-                                                 const SpmvArgs &a, double *lds, double &acc0,
+                                                 const SpmvArgs<double> &a, double *lds, double &acc0,
                                                  double &acc1) {
     int t = walk.next();
     if (t < 0) return;
@@ -303,13 +314,16 @@ __device__ __forceinline__ void spmv_stream_wave(const CsrDev &A, TileWalk &walk
 // with rounded products, the oracle's order.  Two pipeline stages alternate
 // between register sets: the loads of slice t+1 are issued while slice t's
 // gathers are in flight.
+template <class T>
 struct SliceSet {
     int r0, nrows, off, width, len;
     int c[kSliceMaxWidth];
-    double v[kSliceMaxWidth];
+    T v[kSliceMaxWidth];
 };
 
-__device__ __forceinline__ void slice_load(const CsrDev &A, int t, SliceSet &S) {
+template <class T>
+__device__ __forceinline__ void slice_load(const CsrDev &A, int t, SliceSet<T> &S) {
+    const T *__restrict__ svals = sell_vals<T>(A);
     const int lane = threadIdx.x & (kWave - 1);
     S.r0 = __builtin_amdgcn_readfirstlane(t * kWave);
     S.nrows = min(kWave, A.m - S.r0);
@@ -321,23 +335,24 @@ __device__ __forceinline__ void slice_load(const CsrDev &A, int t, SliceSet &S) 
     for (int j = 0; j < kSliceMaxWidth; ++j) {
         const int k = S.off + (j < S.width ? j : 0) * kWave + lane;
         S.c[j] = A.sell_ci[k];
-        S.v[j] = A.sell_val[k];
+        S.v[j] = svals[k];
     }
 }
 
-template <int MODE>
-__device__ __forceinline__ void slice_step(const CsrDev &A, const SpmvArgs &a, const SliceSet &S,
-                                           int tn, SliceSet &N, double &acc0, double &acc1) {
+template <int MODE, class T>
+__device__ __forceinline__ void slice_step(const CsrDev &A, const SpmvArgs<T> &a,
+                                           const SliceSet<T> &S, int tn, SliceSet<T> &N,
+                                           double &acc0, double &acc1) {
     const int lane = threadIdx.x & (kWave - 1);
-    double pv[kSliceMaxWidth];
+    T pv[kSliceMaxWidth];
 #pragma unroll
     for (int j = 0; j < kSliceMaxWidth; ++j) pv[j] = a.p[S.c[j]];
     const int myrow = S.r0 + min(lane, S.nrows - 1);
-    double pown = 0.0, bv = 0.0;
+    T pown = T(0), bv = T(0);
     if (MODE == kSpmvDot) pown = a.p_own[myrow];
     if (MODE == kSpmvResidual) bv = a.b[myrow];
-    slice_load(A, tn, N);
-    double s = 0.0;
+    slice_load<T>(A, tn, N);
+    T s = T(0);
     {
 #pragma clang fp contract(off)
 #pragma unroll
@@ -346,104 +361,102 @@ __device__ __forceinline__ void slice_step(const CsrDev &A, const SpmvArgs &a, c
     }
     if (lane < S.nrows) {
         if (MODE == kSpmvResidual) {
-            const double rv = bv - s;
+            const T rv = bv - s;
             a.q[myrow] = rv;
             a.p_dst[myrow] = rv;
-            acc0 = fma(rv, rv, acc0);
-            acc1 = fma(bv, bv, acc1);
+            acc0 = fma((double)rv, (double)rv, acc0);
+            acc1 = fma((double)bv, (double)bv, acc1);
         } else {
             a.q[myrow] = s;
-            if (MODE == kSpmvDot) acc0 = fma(pown, s, acc0);
+            if (MODE == kSpmvDot) acc0 = fma((double)pown, (double)s, acc0);
         }
     }
 }
 
 // A slice wider than kSliceMaxWidth: a plain loop over its slots.
-template <int MODE>
-__device__ __forceinline__ void slice_wide(const CsrDev &A, const SpmvArgs &a, int t,
+template <int MODE, class T>
+__device__ __forceinline__ void slice_wide(const CsrDev &A, const SpmvArgs<T> &a, int t,
                                            double &acc0, double &acc1) {
+    const T *__restrict__ svals = sell_vals<T>(A);
     const int lane = threadIdx.x & (kWave - 1);
     const int r0 = t * kWave, nrows = min(kWave, A.m - r0);
     const int off = A.sell_off[t];
     const int width = (A.sell_off[t + 1] - off) / kWave;
     const int i = r0 + min(lane, nrows - 1);
     const int len = lane < nrows ? A.rp[i + 1] - A.rp[i] : 0;
-    double s = 0.0;
+    T s = T(0);
     for (int j = 0; j < width; ++j) {
         const int k = off + j * kWave + lane;
-        const double pv = a.p[A.sell_ci[k]];
+        const T pv = a.p[A.sell_ci[k]];
         if (j < len) {
 #pragma clang fp contract(off)
-            s = s + A.sell_val[k] * pv;  // rounded product, then the sum
+            s = s + svals[k] * pv;  // rounded product, then the sum
         }
     }
-    if (lane < nrows) {
-        if (MODE == kSpmvResidual) {
-            const double bv = a.b[i];
-            const double rv = bv - s;
-            a.q[i] = rv;
-            a.p_dst[i] = rv;
-            acc0 = fma(rv, rv, acc0);
-            acc1 = fma(bv, bv, acc1);
-        } else {
-            a.q[i] = s;
-            if (MODE == kSpmvDot) acc0 = fma(a.p_own[i], s, acc0);
-        }
-    }
+    if (lane < nrows) emit_row<MODE, T>(a, i, s, acc0, acc1);
 }
 
-template <int MODE>
+template <int MODE, class T>
 __device__ __forceinline__ void spmv_sliced_wave(const CsrDev &A, TileWalk &walk,
-                                                 const SpmvArgs &a, int wide, double &acc0,
+                                                 const SpmvArgs<T> &a, int wide, double &acc0,
                                                  double &acc1) {
     if (wide) {
-        for (int t = walk.next(); t >= 0; t = walk.next()) slice_wide<MODE>(A, a, t, acc0, acc1);
+        for (int t = walk.next(); t >= 0; t = walk.next()) slice_wide<MODE, T>(A, a, t, acc0, acc1);
         return;
     }
     int t = walk.next();
     if (t < 0) return;
-    SliceSet S0, S1;
-    slice_load(A, t, S0);
+    SliceSet<T> S0, S1;
+    slice_load<T>(A, t, S0);
     for (;;) {
         const int t1 = walk.next();
-        slice_step<MODE>(A, a, S0, t1 >= 0 ? t1 : t, S1, acc0, acc1);
+        slice_step<MODE, T>(A, a, S0, t1 >= 0 ? t1 : t, S1, acc0, acc1);
         if (t1 < 0) break;
         const int t2 = walk.next();
-        slice_step<MODE>(A, a, S1, t2 >= 0 ? t2 : t1, S0, acc0, acc1);
+        slice_step<MODE, T>(A, a, S1, t2 >= 0 ? t2 : t1, S0, acc0, acc1);
         if (t2 < 0) break;
         t = t2;
     }
 }
 
 // A row longer than kHugeRow: all threads of the workgroup on it.
-template <int MODE>
+template <int MODE, class T>
 __device__ __forceinline__ void spmv_row_wg(const CsrDev &A, int pos, bool identity,
-                                            const SpmvArgs &a, double &acc0, double &acc1,
+                                            const SpmvArgs<T> &a, double &acc0, double &acc1,
                                             double *sh) {
+    const T *__restrict__ vals = csr_vals<T>(A);
     const int row = identity ? pos : A.rows[pos];
     const int beg = A.rp[row], end = A.rp[row + 1];
-    double v = 0.0;
+    double v = 0.0;  // a long row is reduced in float64 whatever T is
 #pragma unroll 4
-    for (int k = beg + (int)threadIdx.x; k < end; k += kBlock) v = fma(A.val[k], a.p[A.ci[k]], v);
+    for (int k = beg + (int)threadIdx.x; k < end; k += kBlock)
+        v = fma((double)vals[k], (double)a.p[A.ci[k]], v);
     const double s = block_sum<kBlock>(v, sh);
-    if (threadIdx.x == 0) emit_row<MODE>(a, row, s, acc0, acc1);
+    if (threadIdx.x == 0) emit_row<MODE, T>(a, row, (T)s, acc0, acc1);
 }
 
 // TILE > 0: one bin of TILE lanes per row in natural row order;
-// TILE == 0: binned rows (any order); TILE == -1: stream tiles;
+// TILE == 0: binned rows (any order); TILE == -1: stream tiles (float64 only);
 // TILE == -2: sliced tiles of width <= kSliceMaxWidth; -3: wider slices.
-template <int MODE, int TILE>
+template <int MODE, int TILE, class T>
 __global__ __launch_bounds__(kBlock) void k_spmv(int32_t m, const int32_t *__restrict__ rp,
                                                  const int32_t *__restrict__ ci,
-                                                 const double *__restrict__ val,
+                                                 const T *__restrict__ val,
                                                  const int32_t *__restrict__ rows,
                                                  const int32_t *__restrict__ sell_off,
                                                  const int32_t *__restrict__ sell_ci,
-                                                 const double *__restrict__ sell_val, Schedule S,
-                                                 SpmvArgs a, double *__restrict__ out,
+                                                 const T *__restrict__ sell_val, Schedule S,
+                                                 SpmvArgs<T> a, double *__restrict__ out,
                                                  Partials in0, Partials in1,
                                                  DevState *__restrict__ st, int flags) {
-    const CsrDev A{m, rp, ci, val, rows, sell_off, sell_ci, sell_val};
+    CsrDev A{m, rp, ci, nullptr, rows, sell_off, sell_ci, nullptr, nullptr, nullptr};
+    if constexpr (sizeof(T) == 8) {
+        A.val = reinterpret_cast<const double *>(val);
+        A.sell_val = reinterpret_cast<const double *>(sell_val);
+    } else {
+        A.val32 = reinterpret_cast<const float *>(val);
+        A.sell_val32 = reinterpret_cast<const float *>(sell_val);
+    }
     __shared__ double sh[kWavesPerBlock];
     __shared__ double bc;
     __shared__ double s_prod[TILE == -1 ? kWavesPerBlock * kStreamNnz : 1];
@@ -467,17 +480,19 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int32_t m, const int32_t *__res
     double acc0 = 0.0, acc1 = 0.0;
     const bool identity = S.identity != 0;
     TileWalk walk(S.ntiles);
-    if (TILE == -2 || TILE == -3) {
-        spmv_sliced_wave<MODE>(A, walk, a, TILE == -3, acc0, acc1);
-    } else if (TILE < 0) {
-        double *lds = s_prod + (threadIdx.x / kWave) * kStreamNnz;
-        spmv_stream_wave<MODE>(A, walk, a, lds, acc0, acc1);
-    } else if (TILE > 0) {
+    if constexpr (TILE == -2 || TILE == -3) {
+        spmv_sliced_wave<MODE, T>(A, walk, a, TILE == -3, acc0, acc1);
+    } else if constexpr (TILE == -1) {
+        if constexpr (sizeof(T) == 8) {
+            double *lds = s_prod + (threadIdx.x / kWave) * kStreamNnz;
+            spmv_stream_wave<MODE>(A, walk, a, lds, acc0, acc1);
+        }
+    } else if constexpr (TILE > 0) {
         constexpr int L = TILE > 0 ? TILE : 1;
         constexpr int RW = rows_per_wave_tile(L);
         for (int t = walk.next(); t >= 0; t = walk.next()) {
             const int pos0 = t * RW;
-            spmv_wave_tile<L, MODE>(A, pos0, min(RW, A.m - pos0), true, a, acc0, acc1);
+            spmv_wave_tile<L, MODE, T>(A, pos0, min(RW, A.m - pos0), true, a, acc0, acc1);
         }
     } else {
         for (int t = walk.next(); t >= 0; t = walk.next()) {
@@ -488,17 +503,17 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int32_t m, const int32_t *__res
             const int pos0 = B.first + (t - B.tile_begin) * rw;
             const int cnt = min(rw, B.first + B.count - pos0);
             switch (B.lanes) {
-                case 1: spmv_wave_tile<1, MODE>(A, pos0, cnt, identity, a, acc0, acc1); break;
-                case 2: spmv_wave_tile<2, MODE>(A, pos0, cnt, identity, a, acc0, acc1); break;
-                case 4: spmv_wave_tile<4, MODE>(A, pos0, cnt, identity, a, acc0, acc1); break;
-                case 8: spmv_wave_tile<8, MODE>(A, pos0, cnt, identity, a, acc0, acc1); break;
-                case 16: spmv_wave_tile<16, MODE>(A, pos0, cnt, identity, a, acc0, acc1); break;
-                case 32: spmv_wave_tile<32, MODE>(A, pos0, cnt, identity, a, acc0, acc1); break;
-                default: spmv_wave_tile<64, MODE>(A, pos0, cnt, identity, a, acc0, acc1); break;
+                case 1: spmv_wave_tile<1, MODE, T>(A, pos0, cnt, identity, a, acc0, acc1); break;
+                case 2: spmv_wave_tile<2, MODE, T>(A, pos0, cnt, identity, a, acc0, acc1); break;
+                case 4: spmv_wave_tile<4, MODE, T>(A, pos0, cnt, identity, a, acc0, acc1); break;
+                case 8: spmv_wave_tile<8, MODE, T>(A, pos0, cnt, identity, a, acc0, acc1); break;
+                case 16: spmv_wave_tile<16, MODE, T>(A, pos0, cnt, identity, a, acc0, acc1); break;
+                case 32: spmv_wave_tile<32, MODE, T>(A, pos0, cnt, identity, a, acc0, acc1); break;
+                default: spmv_wave_tile<64, MODE, T>(A, pos0, cnt, identity, a, acc0, acc1); break;
             }
         }
         for (int hrow = blockIdx.x; hrow < S.huge_count; hrow += gridDim.x)
-            spmv_row_wg<MODE>(A, S.huge_first + hrow, identity, a, acc0, acc1, sh);
+            spmv_row_wg<MODE, T>(A, S.huge_first + hrow, identity, a, acc0, acc1, sh);
     }
     if (MODE == kSpmvPlain) return;
     const double s0 = block_sum<kBlock>(acc0, sh);
@@ -601,6 +616,122 @@ __global__ __launch_bounds__(kBlock) void k_update_p(int32_t m, const double *__
         p2[i] = pv;
     }
     if ((m & 1) && blockIdx.x == 0 && threadIdx.x == 0) p[m - 1] = fma(beta, p[m - 1], r[m - 1]);
+}
+
+// ---------------------------------------------------------------------------
+// Mixed precision: float32 r, p, q with float64 x and float64 sums.
+
+// x += alpha p (float64), r -= (float)alpha q (float32); partial r^T r in float64.
+__global__ __launch_bounds__(kBlock) void k_update_xr_mixed(int32_t m, double *__restrict__ x,
+                                                            float *__restrict__ r,
+                                                            const float *__restrict__ p,
+                                                            const float *__restrict__ q,
+                                                            double *__restrict__ out,
+                                                            Partials pq_in,
+                                                            DevState *__restrict__ st, int32_t k) {
+    __shared__ double sh[kWavesPerBlock];
+    __shared__ double bc;
+    if (st->done) return;
+    const double pq = reduce_partials(pq_in, sh, &bc);
+    if (!(pq > 0.0) || !isfinite(pq)) {
+        if (is_block0_thread0()) {
+            st->pq = pq;
+            st->iter = k;
+            st->done = kDoneBreakdown;
+        }
+        return;
+    }
+    const double alpha = st->rho[k & 1] / pq;
+    const float alpha32 = (float)alpha;
+    if (is_block0_thread0()) st->pq = pq;
+    double acc = 0.0;
+    const int64_t npair = m >> 1;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    double2 *x2 = reinterpret_cast<double2 *>(x);
+    float2 *r2 = reinterpret_cast<float2 *>(r);
+    const float2 *p2 = reinterpret_cast<const float2 *>(p);
+    const float2 *q2 = reinterpret_cast<const float2 *>(q);
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < npair; i += stride) {
+        const float2 pv = p2[i], qv = q2[i];
+        double2 xv = x2[i];
+        float2 rv = r2[i];
+        xv.x = fma(alpha, (double)pv.x, xv.x);
+        xv.y = fma(alpha, (double)pv.y, xv.y);
+        rv.x = fmaf(-alpha32, qv.x, rv.x);
+        rv.y = fmaf(-alpha32, qv.y, rv.y);
+        x2[i] = xv;
+        r2[i] = rv;
+        acc = fma((double)rv.x, (double)rv.x, acc);
+        acc = fma((double)rv.y, (double)rv.y, acc);
+    }
+    if ((m & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        const int32_t i = m - 1;
+        x[i] = fma(alpha, (double)p[i], x[i]);
+        const float rv = fmaf(-alpha32, q[i], r[i]);
+        r[i] = rv;
+        acc = fma((double)rv, (double)rv, acc);
+    }
+    const double s = block_sum<kBlock>(acc, sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+// p = r + (float)beta p, or a refinement request when the float32 residual has
+// dropped by delta since the last refinement or meets the tolerance.
+__global__ __launch_bounds__(kBlock) void k_update_p_mixed(int32_t m, const float *__restrict__ r,
+                                                           float *__restrict__ p, Partials rr_in,
+                                                           DevState *__restrict__ st,
+                                                           int device_coef, int32_t k,
+                                                           double beta_arg) {
+    __shared__ double sh[kWavesPerBlock];
+    __shared__ double bc;
+    double beta = beta_arg;
+    if (device_coef) {
+        if (st->done) return;
+        const double rr = reduce_partials(rr_in, sh, &bc);
+        const double rho_k = st->rho[k & 1];
+        const bool refine = sqrt(rr) < st->delta * st->rmax || sqrt(rr) < st->tol * sqrt(st->bb);
+        const bool maxed = k + 1 >= st->maxit;
+        if (is_block0_thread0()) {
+            st->rho[(k + 1) & 1] = rr;
+            st->rr = rr;
+            st->iter = k + 1;
+            if (refine) st->done = kDoneRefine;
+            else if (maxed) st->done = kDoneMaxit;
+        }
+        if (refine || maxed) return;
+        beta = rr / rho_k;
+    }
+    const float beta32 = (float)beta;
+    const int64_t npair = m >> 1;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    float2 *p2 = reinterpret_cast<float2 *>(p);
+    const float2 *r2 = reinterpret_cast<const float2 *>(r);
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < npair; i += stride) {
+        const float2 rv = r2[i];
+        float2 pv = p2[i];
+        pv.x = fmaf(beta32, pv.x, rv.x);
+        pv.y = fmaf(beta32, pv.y, rv.y);
+        p2[i] = pv;
+    }
+    if ((m & 1) && blockIdx.x == 0 && threadIdx.x == 0) p[m - 1] = fmaf(beta32, p[m - 1], r[m - 1]);
+}
+
+// r32 = (float) r64 (and p32 = r32 with init_p); partial r32^T r32 in float64.
+__global__ __launch_bounds__(kBlock) void k_convert_residual(int32_t m, const double *__restrict__ r64,
+                                                             float *__restrict__ r32,
+                                                             float *__restrict__ p32,
+                                                             double *__restrict__ out, int init_p) {
+    __shared__ double sh[kWavesPerBlock];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * kBlock) {
+        const float v = (float)r64[i];
+        r32[i] = v;
+        if (init_p) p32[i] = v;
+        acc = fma((double)v, (double)v, acc);
+    }
+    const double s = block_sum<kBlock>(acc, sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -715,16 +846,24 @@ __global__ void k_scatter(int32_t cnt, const int32_t *__restrict__ idx, const do
     if (i < cnt) dst[idx[i]] = src[i];
 }
 
-template <int MODE>
-void launch_spmv_mode(const CsrDev &A, const Schedule &S, int grid, const SpmvArgs &a, double *out,
-                      Partials in0, Partials in1, DevState *st, int flags, hipStream_t s) {
+template <int MODE, class T>
+void launch_spmv_mode(const CsrDev &A, const Schedule &S, int grid, const SpmvArgs<T> &a,
+                      double *out, Partials in0, Partials in1, DevState *st, int flags,
+                      hipStream_t s) {
     const int L = S.kind == kTileSliced ? (S.bins[0].lanes <= kSliceMaxWidth ? -2 : -3)
                   : S.kind == kTileStream ? -1
                   : (S.identity && S.nbins == 1 && S.huge_count == 0) ? S.bins[0].lanes : 0;
-#define CGMI_SPMV(FL)                                                                          \
-    hipLaunchKernelGGL((k_spmv<MODE, FL>), dim3(grid), dim3(kBlock), 0, s, A.m, A.rp, A.ci, \
-                       A.val, A.rows, A.sell_off, A.sell_ci, A.sell_val, S, a, out, in0, in1, st, \
-                       flags)
+    const T *val, *sval;
+    if constexpr (sizeof(T) == 8) {
+        val = reinterpret_cast<const T *>(A.val);
+        sval = reinterpret_cast<const T *>(A.sell_val);
+    } else {
+        val = reinterpret_cast<const T *>(A.val32);
+        sval = reinterpret_cast<const T *>(A.sell_val32);
+    }
+#define CGMI_SPMV(FL)                                                                             \
+    hipLaunchKernelGGL((k_spmv<MODE, FL, T>), dim3(grid), dim3(kBlock), 0, s, A.m, A.rp, A.ci, val, \
+                       A.rows, A.sell_off, A.sell_ci, sval, S, a, out, in0, in1, st, flags)
     switch (L) {
         case 1: CGMI_SPMV(1); break;
         case 2: CGMI_SPMV(2); break;
@@ -748,18 +887,40 @@ hipError_t launch_spmv(const CsrDev &A, const Schedule &S, int grid, const doubl
                        Partials in0, Partials in1, DevState *st, int mode, int k0_check,
                        hipStream_t s) {
     if (A.m == 0) return hipSuccess;
-    SpmvArgs a{p, q, p_own, b, p_dst};
+    SpmvArgs<double> a{p, q, p_own, b, p_dst};
     switch (mode) {
         case kSpmvPlain:
-            launch_spmv_mode<kSpmvPlain>(A, S, grid, a, nullptr, in0, in1, nullptr, 0, s);
+            launch_spmv_mode<kSpmvPlain, double>(A, S, grid, a, nullptr, in0, in1, nullptr, 0, s);
             break;
         case kSpmvDot: {
             const int flags = st ? (kFlagCheckDone | (k0_check ? kFlagFirstIter : 0)) : 0;
-            launch_spmv_mode<kSpmvDot>(A, S, grid, a, out_partials, in0, in1, st, flags, s);
+            launch_spmv_mode<kSpmvDot, double>(A, S, grid, a, out_partials, in0, in1, st, flags, s);
             break;
         }
         case kSpmvResidual:
-            launch_spmv_mode<kSpmvResidual>(A, S, grid, a, out_partials, in0, in1, nullptr, 0, s);
+            launch_spmv_mode<kSpmvResidual, double>(A, S, grid, a, out_partials, in0, in1, nullptr, 0,
+                                                    s);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv_f32(const CsrDev &A, const Schedule &S, int grid, const float *p, float *q,
+                           const float *p_own, double *out_partials, DevState *st, int mode,
+                           hipStream_t s) {
+    if (A.m == 0) return hipSuccess;
+    if (S.kind == kTileStream) return hipErrorInvalidValue;
+    SpmvArgs<float> a{p, q, p_own, nullptr, nullptr};
+    const Partials none{nullptr, 0};
+    switch (mode) {
+        case kSpmvPlain:
+            launch_spmv_mode<kSpmvPlain, float>(A, S, grid, a, nullptr, none, none, nullptr, 0, s);
+            break;
+        case kSpmvDot:
+            launch_spmv_mode<kSpmvDot, float>(A, S, grid, a, out_partials, none, none, st,
+                                              st ? kFlagCheckDone : 0, s);
             break;
         default:
             return hipErrorInvalidValue;
@@ -826,6 +987,32 @@ hipError_t launch_scatter(int32_t cnt, const int32_t *idx, const double *src, do
                           hipStream_t s) {
     if (cnt <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_scatter, dim3((cnt + 255) / 256), dim3(256), 0, s, cnt, idx, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_xr_mixed(int32_t m, int grid, double *x, float *r, const float *p,
+                                  const float *q, double *out_partials, Partials pq, DevState *st,
+                                  int32_t k, hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_update_xr_mixed, dim3(grid), dim3(kBlock), 0, s, m, x, r, p, q,
+                       out_partials, pq, st, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_p_mixed(int32_t m, int grid, const float *r, float *p, Partials rr,
+                                 DevState *st, int device_coef, int32_t k, double beta_arg,
+                                 hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_update_p_mixed, dim3(grid), dim3(kBlock), 0, s, m, r, p, rr, st,
+                       device_coef, k, beta_arg);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert_residual(int32_t m, int grid, const double *r64, float *r32, float *p32,
+                                   double *out_partials, int init_p, hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_convert_residual, dim3(grid), dim3(kBlock), 0, s, m, r64, r32, p32,
+                       out_partials, init_p);
     return hipGetLastError();
 }
 

@@ -290,3 +290,69 @@ def test_full_size_poisson3d_256(cg):
     true = np.linalg.norm(p.b - oracle.spmv(A, x500)) / np.linalg.norm(p.b)
     assert abs(res500["rel_res_true"] - true) <= 1e-6 * true
     assert true < 1e-2   # 500 CG steps on the 7-point Laplacian reduce the residual well below 1
+
+
+# ----------------------------------------------------------------------------- mixed precision
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("name", ["poisson3d_ragged", "random_spd_30k", "diffusion_100"])
+def test_spmv_f32_matches_oracle(cg, name, kind):
+    A = SPMV_CASES[name]()
+    x32 = np.random.default_rng(4).uniform(-1, 1, A.n).astype(np.float32)
+    ref = oracle.spmv_f32(A, x32)
+    with cg.Solver(A) as s:
+        s.set_opts(precision=cg.PREC_MIXED, spmv_kind=kind)
+        y = host(s.spmv_f32(torch.from_numpy(x32).cuda()))
+    absA = sp.csr_matrix((np.abs(A.val.astype(np.float32)), A.col, A.row_ptr), shape=(A.n, A.n))
+    scale = absA @ np.abs(x32).astype(np.float64) + 1e-30
+    L = int(np.diff(A.row_ptr).max())
+    assert np.max(np.abs(y.astype(np.float64) - ref) / scale) <= 2 * L * 2.0 ** -24
+    if kind == 0 and s_kind_used(A, 3):
+        # sliced rows are summed in float32 left to right: the oracle's order
+        assert np.array_equal(y, ref)
+
+
+MIXED_CASES = {
+    "random_spd_20k": lambda: I.random_spd_problem(20000, seed=3),
+    "poisson3d_32": lambda: I.poisson3d_problem(32),
+    "diffusion_64": lambda: I.diffusion_problem(64, seed=10_000),
+}
+
+
+@pytest.mark.parametrize("name", list(MIXED_CASES))
+def test_mixed_precision_matches_oracle(cg, name):
+    p = MIXED_CASES[name]()
+    print(f"[mixed] {name} n={p.A.n}", flush=True)
+    ref = oracle.cg_mixed(p.A, p.b, tol=1e-10, maxit=20000)
+    ref64 = oracle.cg(p.A, p.b, tol=1e-10, maxit=20000)
+    with cg.Solver(p.A) as s:
+        s.set_opts(precision=cg.PREC_MIXED)
+        x, res = s.solve(dev(p.b), tol=1e-10, maxit=20000)
+    x = host(x)
+    assert res["code"] == cg.CG_OK and ref["status"] == oracle.OK
+    # success is decided on the float64 true residual, recomputed here by the oracle
+    true = np.linalg.norm(p.b - oracle.spmv(p.A, x)) / np.linalg.norm(p.b)
+    assert true < 1e-10
+    assert res["fp64_residuals"] >= 2 and not res["fell_back"]
+    assert abs(res["iterations"] - ref["iterations"]) <= max(3, 0.1 * ref["iterations"])
+    kappa = kappa_of(name, p.A)
+    err = np.linalg.norm(x - ref64["x"]) / np.linalg.norm(ref64["x"])
+    print(f"[mixed] {name}: {res['iterations']} float32 iterations ({ref['iterations']} oracle), "
+          f"{res['fp64_residuals']} float64 residuals, error vs float64 solution {err:.2e}", flush=True)
+    assert err <= 2 * kappa * 1e-10
+
+
+def test_mixed_precision_edge_cases(cg):
+    p = I.poisson2d_problem(16)
+    n = p.A.n
+    with cg.Solver(p.A) as s:
+        s.set_opts(precision=cg.PREC_MIXED)
+        x, res = s.solve(dev(np.zeros(n)), dev(np.ones(n)))
+        assert res["code"] == cg.CG_OK and not host(x).any()
+        x, res = s.solve(dev(p.b), dev(p.xstar.copy()), tol=1e-8)
+        assert res["code"] == cg.CG_OK and res["iterations"] == 0
+        x, res = s.solve(dev(p.b), maxit=3)
+        assert res["code"] == cg.CG_MAXIT and res["iterations"] == 3
+    with cg.Solver(p.A, 0, n // 2) as s:
+        with pytest.raises(cg.CgError):
+            s.set_opts(precision=cg.PREC_MIXED)
