@@ -31,18 +31,22 @@ def spmv_algorithmic_bytes(n: int, nnz: int) -> int:
     return 12 * nnz + 4 * (n + 1) + 8 * n + 8 * n
 
 
+SPMV_SOURCES = ("kernels_cg.hip", "cgmi_internal.h")
+
+
 def kernel_source_hash() -> str:
+    """Hash of the sources that define the CG kernels (the counters in
+    profiles/traffic.json are valid only for these exact sources)."""
     h = hashlib.sha256()
-    for fn in sorted(os.listdir(os.path.join(ROOT, "paper_2608_09647_amd", "csrc"))):
-        if fn.endswith((".hip", ".h")):
-            with open(os.path.join(ROOT, "paper_2608_09647_amd", "csrc", fn), "rb") as f:
-                h.update(f.read())
+    for fn in SPMV_SOURCES:
+        with open(os.path.join(ROOT, "paper_2608_09647_amd", "csrc", fn), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(key: str):
+def measured_traffic(key: str, spmv_kind: int):
     """Per-launch HBM bytes from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources; else None."""
+    was taken on the current kernel sources with the same SpMV tiling; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -50,7 +54,7 @@ def measured_traffic(key: str):
         with open(path) as f:
             table = json.load(f)
         ent = table.get(key)
-        if ent and ent.get("source_hash") == kernel_source_hash():
+        if ent and ent.get("source_hash") == kernel_source_hash() and ent.get("spmv_kind") == spmv_kind:
             return ent.get("bytes_per_launch")
     except (OSError, ValueError):
         return None
@@ -195,10 +199,11 @@ def main() -> int:
                    "seed": 2},
         "spmv_gbs": achieved,
         "spmv_us": 1e6 * t_launch,
+        "spmv_kind": {1: "vector_bins", 2: "stream", 3: "sliced"}.get(res["spmv_kind"]),
         "rel_res_true": res["rel_res_true"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("spmv_poisson3d_256")},
+                     "traffic": measured_traffic("spmv_poisson3d_256", res["spmv_kind"])},
     }
     solver.close()
     del b, x

@@ -105,7 +105,8 @@ typedef struct cg_result {
     int64_t nnz_gpu, nnz_cpu;
     int32_t fell_back;       /* 1 if a preconditioned / mixed solve fell back to
                                 plain float64 CG                                 */
-    int32_t reserved;
+    int32_t spmv_kind;       /* SpMV tiling used on the GPU rows: 1 vector bins,
+                                2 stream tiles, 3 sliced tiles (0: no GPU rows)   */
 } cg_result;
 
 /* Create a solver for the n x n CSR matrix (host arrays, copied).  Rows

@@ -25,6 +25,11 @@ EXCHANGE_WHOLE, EXCHANGE_HALO = 0, 1
 EXPORTED = ["cg_create", "cg_destroy", "cg_set_stream", "cg_default_opts", "cg_set_opts",
             "cg_get_opts", "cg_spmv", "cg_spmv_f32", "cg_solve", "cg_slice_info", "cg_read_slice",
             "cg_last_error"]
+# include/cgmi_fsai.h
+EXPORTED_FSAI = ["cg_fsai_setup", "cg_set_fsai", "cg_fsai_factor_info", "cg_fsai_read_factor",
+                 "cg_fsai_trainer_create", "cg_fsai_trainer_destroy", "cg_fsai_loss_grad",
+                 "cg_fsai_train_step", "cg_fsai_get_params", "cg_fsai_features"]
+FSAI_NPARAMS = 5317
 
 
 class CgOpts(ctypes.Structure):
@@ -46,10 +51,10 @@ class CgResult(ctypes.Structure):
                 ("t_spmv", ctypes.c_double), ("n_spmv", ctypes.c_int32),
                 ("rows_gpu", ctypes.c_int32), ("rows_cpu", ctypes.c_int32),
                 ("nnz_gpu", ctypes.c_int64), ("nnz_cpu", ctypes.c_int64),
-                ("fell_back", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("fell_back", ctypes.c_int32), ("spmv_kind", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class CgError(RuntimeError):
@@ -94,6 +99,21 @@ def lib() -> ctypes.CDLL:
         L.cg_read_slice.restype = ctypes.c_int
         L.cg_last_error.argtypes = []
         L.cg_last_error.restype = ctypes.c_char_p
+        i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        L.cg_fsai_setup.argtypes = [_vp, _vp]
+        L.cg_set_fsai.argtypes = [_vp, i64, _vp, _vp, _vp]
+        L.cg_fsai_factor_info.argtypes = [_vp, ctypes.POINTER(i64)]
+        L.cg_fsai_read_factor.argtypes = [_vp, _vp, _vp, _vp]
+        L.cg_fsai_trainer_create.argtypes = [i32, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_vp)]
+        L.cg_fsai_trainer_destroy.argtypes = [_vp]
+        L.cg_fsai_trainer_destroy.restype = None
+        L.cg_fsai_loss_grad.argtypes = [_vp, _vp, i32, _vp, i32, _vp, ctypes.POINTER(dbl), _vp, _vp]
+        L.cg_fsai_train_step.argtypes = [_vp, i32, _vp, i32, _vp, dbl, ctypes.POINTER(dbl)]
+        L.cg_fsai_get_params.argtypes = [_vp, _vp]
+        L.cg_fsai_features.argtypes = [_vp, i32, _vp]
+        for name in EXPORTED_FSAI:
+            if name != "cg_fsai_trainer_destroy":
+                getattr(L, name).restype = ctypes.c_int
         _LIB = L
     return _LIB
 
@@ -221,3 +241,108 @@ class Solver:
         va = np.empty(max(nnz, 1), np.float64)
         _check(lib().cg_read_slice(self._h, rp.ctypes.data, ci.ctypes.data, va.ctypes.data))
         return rp, ci[:nnz], va[:nnz]
+
+    # ---- preconditioner (include/cgmi_fsai.h) --------------------------------
+    def set_fsai(self, G) -> None:
+        """Install an explicit factor G (CSR with row_ptr/col/val, or scipy CSR):
+        M^-1 = G^T G.  Select it with set_opts(precond=PC_FSAI)."""
+        rp, ci, va = _csr_arrays(G)
+        _check(lib().cg_set_fsai(self._h, int(rp[-1]), rp.ctypes.data, ci.ctypes.data, va.ctypes.data))
+
+    def fsai_setup(self, theta) -> None:
+        """Build the learned factor on the device from the network parameters."""
+        th = _params(theta)
+        _check(lib().cg_fsai_setup(self._h, th.ctypes.data))
+
+    def read_factor(self):
+        nnz = ctypes.c_int64()
+        _check(lib().cg_fsai_factor_info(self._h, ctypes.byref(nnz)))
+        rp = np.empty(self.n + 1, np.int32)
+        ci = np.empty(max(nnz.value, 1), np.int32)
+        va = np.empty(max(nnz.value, 1), np.float64)
+        _check(lib().cg_fsai_read_factor(self._h, rp.ctypes.data, ci.ctypes.data, va.ctypes.data))
+        return rp, ci[:nnz.value], va[:nnz.value]
+
+
+def _csr_arrays(M):
+    if hasattr(M, "indptr"):
+        M = M.tocsr()
+        M.sort_indices()
+        return (np.ascontiguousarray(M.indptr, np.int32), np.ascontiguousarray(M.indices, np.int32),
+                np.ascontiguousarray(M.data, np.float64))
+    return (np.ascontiguousarray(M.row_ptr, np.int32), np.ascontiguousarray(M.col, np.int32),
+            np.ascontiguousarray(M.val, np.float64))
+
+
+def _params(theta) -> np.ndarray:
+    th = np.ascontiguousarray(theta, dtype=np.float32).reshape(-1)
+    if th.size != FSAI_NPARAMS:
+        raise ValueError(f"theta must have {FSAI_NPARAMS} entries")
+    return th
+
+
+class FsaiTrainer:
+    """Device-resident training set for the learned factor (cg_fsai_trainer)."""
+
+    def __init__(self, systems, theta0):
+        self.sizes = [int(A.n) for A in systems]
+        arrs = [_csr_arrays(A) for A in systems]
+        k = len(arrs)
+        n = np.array(self.sizes, np.int32)
+        nnz = np.array([int(a[0][-1]) for a in arrs], np.int64)
+        ptrs = [(ctypes.c_void_p * k)(*[a[j].ctypes.data for a in arrs]) for j in range(3)]
+        th = _params(theta0)
+        t = ctypes.c_void_p()
+        _check(lib().cg_fsai_trainer_create(k, n.ctypes.data, nnz.ctypes.data, ptrs[0], ptrs[1], ptrs[2],
+                                            th.ctypes.data, ctypes.byref(t)))
+        self._t = t
+
+    def close(self):
+        if getattr(self, "_t", None):
+            lib().cg_fsai_trainer_destroy(self._t)
+            self._t = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _sample(sys, rows):
+        sys = np.ascontiguousarray(sys, np.int32).reshape(-1)
+        rows = np.ascontiguousarray(rows, np.int32)
+        if rows.ndim != 2 or rows.shape[0] != sys.size:
+            raise ValueError("rows must have shape (len(sys), rows_per_sys)")
+        return sys, rows
+
+    def loss_grad(self, sys, rows, theta=None, outputs: bool = False):
+        """(loss, grad[5317]) on the sampled rows (and the network outputs of
+        system sys[0], n x 5, if outputs)."""
+        sys, rows = self._sample(sys, rows)
+        loss = ctypes.c_double()
+        grad = np.empty(FSAI_NPARAMS, np.float32)
+        out = np.empty((self.sizes[int(sys[0])], 5), np.float32) if outputs else None
+        th = None if theta is None else _params(theta)
+        _check(lib().cg_fsai_loss_grad(self._t, None if th is None else th.ctypes.data, sys.size,
+                                       sys.ctypes.data, rows.shape[1], rows.ctypes.data,
+                                       ctypes.byref(loss), grad.ctypes.data,
+                                       None if out is None else out.ctypes.data))
+        return (loss.value, grad, out) if outputs else (loss.value, grad)
+
+    def step(self, sys, rows, lr: float) -> float:
+        sys, rows = self._sample(sys, rows)
+        loss = ctypes.c_double()
+        _check(lib().cg_fsai_train_step(self._t, sys.size, sys.ctypes.data, rows.shape[1],
+                                        rows.ctypes.data, float(lr), ctypes.byref(loss)))
+        return loss.value
+
+    def params(self) -> np.ndarray:
+        th = np.empty(FSAI_NPARAMS, np.float32)
+        _check(lib().cg_fsai_get_params(self._t, th.ctypes.data))
+        return th
+
+    def features(self, sys: int) -> np.ndarray:
+        f = np.empty((self.sizes[int(sys)], 12), np.float32)
+        _check(lib().cg_fsai_features(self._t, int(sys), f.ctypes.data))
+        return f

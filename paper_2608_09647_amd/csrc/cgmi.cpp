@@ -22,13 +22,16 @@
 #include <vector>
 
 #include "../../include/cgmi.h"
+#include "cgmi_host.h"
 #include "cgmi_internal.h"
 
 using namespace cgmi;
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
+
+namespace cgmi {
 
 int fail(int code, const char *fmt, ...) {
     char buf[512];
@@ -40,94 +43,23 @@ int fail(int code, const char *fmt, ...) {
     return code;
 }
 
-#define HIP_TRY(expr)                                                                  \
-    do {                                                                               \
-        hipError_t e_ = (expr);                                                        \
-        if (e_ != hipSuccess)                                                          \
-            return fail(CG_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));    \
-    } while (0)
+void clear_error() { g_err.clear(); }
+const char *error_message() { return g_err.c_str(); }
 
 double now() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
         .count();
 }
 
-template <class T>
-hipError_t dmalloc(T **p, size_t count) {
-    *p = nullptr;
-    if (count == 0) count = 1;
-    return hipMalloc(reinterpret_cast<void **>(p), sizeof(T) * count);
-}
+}  // namespace cgmi
 
-int lanes_for_length(int64_t len) {
-    int L = 1;
-    while (L < len && L < 64) L <<= 1;
-    return L;
-}
-
-}  // namespace
-
-struct cg_handle {
-    int dev = 0;
-    int32_t n = 0;
-    int64_t nnz = 0;
-    int32_t rb = 0, re = 0, m = 0;
-    int64_t nnz_gpu = 0, nnz_cpu = 0;
-    cg_opts opts{};
-    hipStream_t stream = nullptr;   // caller's stream (or null stream)
-    hipStream_t s_d2h = nullptr, s_h2d = nullptr;
-    int cus = 256;
-
-    // host copy of the matrix (the host complement uses its rows)
-    std::vector<int32_t> h_rp, h_ci;
-    std::vector<double> h_val;
-
-    // device: GPU row block, rebased
-    int32_t *d_rp = nullptr, *d_ci = nullptr, *d_rows = nullptr;
-    double *d_val = nullptr;
-    // sliced (slot-major) copy of the block, built when that tiling is chosen
-    int32_t *d_sell_off = nullptr, *d_sell_ci = nullptr;
-    double *d_sell_val = nullptr;
-    // mixed precision: float32 copies of the values and float32 inner vectors
-    float *d_val32 = nullptr, *d_sell_val32 = nullptr;
-    float *d_r32 = nullptr, *d_p32 = nullptr, *d_q32 = nullptr;
-    size_t sell_slots = 0;
-    Schedule sched{};
-    int spmv_grid = 0, vec_grid = 0;
-
-    // device vectors
-    double *d_pbuf = nullptr;  // allocation behind d_p
-    double *d_p = nullptr;     // full length n, d_p + rb is 16-byte aligned
-    double *d_x = nullptr, *d_r = nullptr, *d_q = nullptr;  // m each
-    double *d_part_setup = nullptr;  // 2 x spmv_grid: r^T r, b^T b of the residual kernel
-    double *d_part_pq = nullptr;     // spmv_grid
-    double *d_part_rr = nullptr;     // vec_grid
-    int grid_cap = 0;                // capacity of the partial buffers (workgroups)
-    std::vector<double> h_part;      // host copy of partials (split mode, true residual)
-    DevState *d_state = nullptr;
-    DevState *h_state = nullptr;  // pinned
-
-    // split mode
-    double *h_p = nullptr;  // pinned, length n
-    std::vector<double> h_x, h_r, h_q, h_b;
-    std::vector<int32_t> halo_d2h, halo_h2d;  // global column ids
-    int32_t *d_halo_d2h = nullptr, *d_halo_h2d = nullptr;
-    double *d_pack_d2h = nullptr, *d_pack_h2d = nullptr;
-    double *h_pack_d2h = nullptr, *h_pack_h2d = nullptr;  // pinned
-
-    CsrDev csr() const {
-        return CsrDev{m, d_rp, d_ci, d_val, sched.identity ? nullptr : d_rows,
-                      d_sell_off, d_sell_ci, d_sell_val, d_val32, d_sell_val32};
-    }
-    bool gpu_only() const { return rb == 0 && re == n && n > 0; }
-    bool host_only() const { return m == 0; }
-};
+#define HIP_TRY(expr) CGMI_HIP_TRY(expr)
 
 // ---------------------------------------------------------------------------
 // validation and schedule
 
-static int validate_csr(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *ci,
-                        const double *val) {
+int cgmi::validate_csr(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *ci,
+                       const double *val) {
     if (n < 0) return fail(CG_EINVAL, "n must be >= 0 (got %d)", n);
     if (nnz < 0 || nnz > INT32_MAX) return fail(CG_EINVAL, "nnz out of int32 range");
     if (n > 0 && !rp) return fail(CG_EINVAL, "row_ptr is NULL");
@@ -147,212 +79,33 @@ static int validate_csr(int32_t n, int64_t nnz, const int32_t *rp, const int32_t
     return CG_OK;
 }
 
-// Lanes-per-row classes for the GPU rows.  Rows of similar length keep their
-// natural order (one bin, no indirection); spread-out lengths are binned by
-// the power of two covering the row length, with a row list per bin, and rows
-// longer than kHugeRow go to a workgroup-per-row list at the end.
-static void build_schedule(cg_handle *h, std::vector<int32_t> &rows_out) {
-    Schedule S{};
-    const int32_t m = h->m;
-    rows_out.clear();
-    S.identity = 1;
-    if (m == 0) {
-        h->sched = S;
-        return;
-    }
-    auto len = [&](int32_t i) -> int64_t { return h->h_rp[h->rb + i + 1] - h->h_rp[h->rb + i]; };
-    int64_t maxlen = 0;
-    for (int32_t i = 0; i < m; ++i) maxlen = std::max<int64_t>(maxlen, len(i));
-    const double mean = (double)(h->h_rp[h->re] - h->h_rp[h->rb]) / (double)m;
-    if (h->opts.spmv_kind == 3 || (h->opts.spmv_kind == 0 && maxlen <= 64)) {
-        // sliced: 64-row slices padded to their longest row
-        const int32_t nt = (m + kWaveSize - 1) / kWaveSize;
-        int64_t slots = 0;
-        int maxw = 0;
-        for (int32_t t = 0; t < nt; ++t) {
-            int64_t w = 0;
-            for (int32_t i = t * kWaveSize; i < std::min(m, (t + 1) * kWaveSize); ++i) w = std::max(w, len(i));
-            w = std::max<int64_t>(w, 1);
-            slots += w * kWaveSize;
-            maxw = std::max<int>(maxw, (int)w);
-        }
-        const int64_t nnz_b = h->h_rp[h->re] - h->h_rp[h->rb];
-        if (slots < INT32_MAX && (h->opts.spmv_kind == 3 || slots <= nnz_b + nnz_b / 4)) {
-            S.kind = kTileSliced;
-            S.nbins = 1;
-            S.bins[0] = Bin{std::max(1, maxw), 0, m, 0};
-            S.ntiles = nt;
-            h->sched = S;
-            return;
-        }
-    }
-    if (h->opts.spmv_kind == 2 || (h->opts.spmv_kind == 0 && maxlen <= kStreamPerLane)) {
-        // short rows in natural order: stream tiles of 64 rows if every tile fits
-        bool fits = true;
-        for (int32_t r0 = 0; r0 < m && fits; r0 += kWaveSize) {
-            const int32_t r1 = std::min(m, r0 + kWaveSize);
-            const int32_t k0 = h->h_rp[h->rb + r0] - h->h_rp[h->rb];
-            fits = (k0 & 3) + (h->h_rp[h->rb + r1] - h->h_rp[h->rb + r0]) <= kStreamNnz;
-        }
-        if (fits) {
-            S.kind = kTileStream;
-            S.nbins = 1;
-            S.bins[0] = Bin{kWaveSize, 0, m, 0};
-            S.ntiles = (m + kWaveSize - 1) / kWaveSize;
-            h->sched = S;
-            return;
-        }
-    }
-    if (maxlen <= 64 && (double)maxlen <= 2.0 * mean + 1.0) {
-        const int L = lanes_for_length(maxlen);
-        S.nbins = 1;
-        S.bins[0] = Bin{L, 0, m, 0};
-        S.ntiles = (m + rows_per_wave_tile(L) - 1) / rows_per_wave_tile(L);
-        h->sched = S;
-        return;
-    }
-    static const int classes[7] = {1, 2, 4, 8, 16, 32, 64};
-    std::vector<std::vector<int32_t>> lists(7);
-    std::vector<int32_t> huge;
-    for (int32_t i = 0; i < m; ++i) {
-        const int64_t l = len(i);
-        if (l > kHugeRow) {
-            huge.push_back(i);
-            continue;
-        }
-        const int L = lanes_for_length(l);
-        int c = 0;
-        while (classes[c] != L) ++c;
-        lists[c].push_back(i);
-    }
-    S.identity = 0;
-    int nb = 0, tile = 0, pos = 0;
-    for (int c = 0; c < 7; ++c) {
-        if (lists[c].empty()) continue;
-        const int cnt = (int)lists[c].size();
-        S.bins[nb] = Bin{classes[c], pos, cnt, tile};
-        tile += (cnt + rows_per_wave_tile(classes[c]) - 1) / rows_per_wave_tile(classes[c]);
-        rows_out.insert(rows_out.end(), lists[c].begin(), lists[c].end());
-        pos += cnt;
-        ++nb;
-    }
-    S.nbins = nb;
-    S.ntiles = tile;
-    S.huge_first = pos;
-    S.huge_count = (int32_t)huge.size();
-    rows_out.insert(rows_out.end(), huge.begin(), huge.end());
-    h->sched = S;
-}
-
-// Build the SpMV schedule for the current options, upload its row list and
-// size the SpMV grid (a multiple of 8 workgroups: one share per XCD).
-static int build_sliced(cg_handle *h) {
-    if (h->d_sell_off) return CG_OK;  // built once per handle
-    const int32_t m = h->m, nt = h->sched.ntiles, base = h->h_rp[h->rb];
-    std::vector<int32_t> off((size_t)nt + 1, 0);
-    for (int32_t t = 0; t < nt; ++t) {
-        int32_t w = 0;
-        for (int32_t i = t * kWaveSize; i < std::min(m, (t + 1) * kWaveSize); ++i)
-            w = std::max(w, h->h_rp[h->rb + i + 1] - h->h_rp[h->rb + i]);
-        w = std::max(w, 1);  // every slice has a slot: its loads stay inside the allocation
-        off[t + 1] = off[t] + w * kWaveSize;
-    }
-    const size_t slots = (size_t)off[nt];
-    h->sell_slots = slots ? slots : 1;
-    std::vector<int32_t> sci(slots ? slots : 1, 0);
-    std::vector<double> sval(slots ? slots : 1, 0.0);
-    for (int32_t t = 0; t < nt; ++t) {
-        const int32_t w = (off[t + 1] - off[t]) / kWaveSize;
-        for (int32_t l = 0; l < kWaveSize; ++l) {
-            const int32_t i = t * kWaveSize + l;
-            const int32_t b = i < m ? h->h_rp[h->rb + i] - base : 0;
-            const int32_t len = i < m ? h->h_rp[h->rb + i + 1] - h->h_rp[h->rb + i] : 0;
-            // padding slots gather the row's own entry of p (never summed)
-            const int32_t pad_col = i < m ? h->rb + i : 0;
-            for (int32_t j = 0; j < w; ++j) {
-                const size_t k = (size_t)off[t] + (size_t)j * kWaveSize + l;
-                sci[k] = j < len ? h->h_ci[base + b + j] : pad_col;
-                sval[k] = j < len ? h->h_val[base + b + j] : 0.0;
-            }
-        }
-    }
-    hipError_t e = dmalloc(&h->d_sell_off, off.size());
-    if (e == hipSuccess) e = dmalloc(&h->d_sell_ci, sci.size());
-    if (e == hipSuccess) e = dmalloc(&h->d_sell_val, sval.size());
-    if (e == hipSuccess) e = hipMemcpy(h->d_sell_off, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(h->d_sell_ci, sci.data(), sizeof(int32_t) * sci.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(h->d_sell_val, sval.data(), sizeof(double) * sval.size(), hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-        hipFree(h->d_sell_off); hipFree(h->d_sell_ci); hipFree(h->d_sell_val);
-    hipFree(h->d_val32); hipFree(h->d_sell_val32); hipFree(h->d_r32); hipFree(h->d_p32); hipFree(h->d_q32);
-        h->d_sell_off = h->d_sell_ci = nullptr;
-        h->d_sell_val = nullptr;
-        return fail(CG_ENOMEM, "sliced layout upload failed: %s", hipGetErrorString(e));
-    }
-    return CG_OK;
-}
-
-// float32 copies of the block's values (CSR and, if built, sliced) and the
-// float32 inner vectors; built on first use of mixed precision.
-static int ensure_mixed(cg_handle *h) {
-    const size_t nv = (size_t)h->nnz_gpu + kStreamNnz;
-    hipError_t e = hipSuccess;
-    if (!h->d_val32) {
-        std::vector<float> v32(nv, 0.0f);
-        for (int64_t k = 0; k < h->nnz_gpu; ++k) v32[k] = (float)h->h_val[h->h_rp[h->rb] + k];
-        e = dmalloc(&h->d_val32, nv);
-        if (e == hipSuccess) e = hipMemcpy(h->d_val32, v32.data(), sizeof(float) * nv, hipMemcpyHostToDevice);
-    }
-    if (e == hipSuccess && h->d_sell_val && !h->d_sell_val32) {
-        std::vector<double> sv(h->sell_slots);
-        e = hipMemcpy(sv.data(), h->d_sell_val, sizeof(double) * sv.size(), hipMemcpyDeviceToHost);
-        std::vector<float> sv32(sv.size());
-        for (size_t k = 0; k < sv.size(); ++k) sv32[k] = (float)sv[k];
-        if (e == hipSuccess) e = dmalloc(&h->d_sell_val32, sv32.size());
-        if (e == hipSuccess)
-            e = hipMemcpy(h->d_sell_val32, sv32.data(), sizeof(float) * sv32.size(), hipMemcpyHostToDevice);
-    }
-    if (e == hipSuccess && !h->d_r32) {
-        e = dmalloc(&h->d_r32, (size_t)h->m + 2);
-        if (e == hipSuccess) e = dmalloc(&h->d_p32, (size_t)h->n + 2);
-        if (e == hipSuccess) e = dmalloc(&h->d_q32, (size_t)h->m + 2);
-    }
-    if (e != hipSuccess) return fail(CG_ENOMEM, "mixed-precision buffers: %s", hipGetErrorString(e));
-    return CG_OK;
-}
-
+// SpMV schedule of the GPU block for the current options.
 static int apply_schedule(cg_handle *h) {
-    std::vector<int32_t> rows;
-    build_schedule(h, rows);
-    if (h->sched.kind == kTileSliced) {
-        const int rc = build_sliced(h);
-        if (rc) return rc;
-    }
-    if (h->opts.precision == CG_PREC_MIXED) {
-        if (h->sched.kind == kTileStream)
-            return fail(CG_EINVAL, "stream tiles have no float32 variant: use spmv_kind 0, 1 or 3");
-        const int rc = ensure_mixed(h);
-        if (rc) return rc;
-    }
-    if (!rows.empty()) {
-        const hipError_t e = hipMemcpy(h->d_rows, rows.data(), sizeof(int32_t) * rows.size(),
-                                       hipMemcpyHostToDevice);
-        if (e != hipSuccess) return fail(CG_EDEVICE, "row list upload failed: %s", hipGetErrorString(e));
-    }
-    const int waves_needed = h->sched.ntiles + h->sched.huge_count * (kBlock / kWaveSize);
-    const int auto_grid = ((waves_needed / (kBlock / kWaveSize) + 8) / 8) * 8;
-    int g = h->opts.spmv_grid > 0 ? h->opts.spmv_grid : std::min(h->cus * 8, auto_grid);
-    g = std::min(g, h->grid_cap);
-    h->spmv_grid = std::max(8, (g / 8) * 8);
+    return dm_schedule(h->A, h->opts.spmv_kind, h->opts.spmv_grid, h->cus, h->grid_cap,
+                       h->opts.precision == CG_PREC_MIXED);
+}
+
+// float32 inner vectors of mixed precision (the float32 matrix copies are
+// made by dm_schedule).
+static int ensure_mixed_vectors(cg_handle *h) {
+    if (h->d_r32) return CG_OK;
+    hipError_t e = dmalloc(&h->d_r32, (size_t)h->m + 2);
+    if (e == hipSuccess) e = dmalloc(&h->d_p32, (size_t)h->n + 2);
+    if (e == hipSuccess) e = dmalloc(&h->d_q32, (size_t)h->m + 2);
+    if (e != hipSuccess) return fail(CG_ENOMEM, "mixed-precision vectors: %s", hipGetErrorString(e));
     return CG_OK;
 }
 
 static void free_device(cg_handle *h) {
-    hipFree(h->d_rp); hipFree(h->d_ci); hipFree(h->d_rows); hipFree(h->d_val);
-    hipFree(h->d_sell_off); hipFree(h->d_sell_ci); hipFree(h->d_sell_val);
-    hipFree(h->d_val32); hipFree(h->d_sell_val32); hipFree(h->d_r32); hipFree(h->d_p32); hipFree(h->d_q32);
+    fsai_free(h);
+    dm_free(h->A);
+    dm_free(h->G);
+    dm_free(h->GT);
+    hipFree(h->d_t); hipFree(h->d_z);
+    hipFree(h->d_r32); hipFree(h->d_p32); hipFree(h->d_q32);
     hipFree(h->d_pbuf); hipFree(h->d_x); hipFree(h->d_r); hipFree(h->d_q);
-    hipFree(h->d_part_setup); hipFree(h->d_part_pq); hipFree(h->d_part_rr); hipFree(h->d_state);
+    hipFree(h->d_part_setup); hipFree(h->d_part_pq); hipFree(h->d_part_rr); hipFree(h->d_part_rz);
+    hipFree(h->d_state);
     hipFree(h->d_halo_d2h); hipFree(h->d_halo_h2d); hipFree(h->d_pack_d2h); hipFree(h->d_pack_h2d);
     if (h->h_state) hipHostFree(h->h_state);
     if (h->h_p) hipHostFree(h->h_p);
@@ -378,11 +131,11 @@ extern "C" void cg_default_opts(cg_opts *o) {
     o->refine_delta = 0.01;
 }
 
-extern "C" const char *cg_last_error(void) { return g_err.c_str(); }
+extern "C" const char *cg_last_error(void) { return error_message(); }
 
 extern "C" int cg_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
                          const double *val, int32_t row_begin, int32_t row_end, cg_handle **out) {
-    g_err.clear();
+    clear_error();
     if (!out) return fail(CG_EINVAL, "out is NULL");
     *out = nullptr;
     int rc = validate_csr(n, nnz, row_ptr, col_idx, val);
@@ -416,15 +169,12 @@ extern "C" int cg_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const i
     h->cus = device_cu_count();
     const int m = h->m;
     // device copy of the GPU row block, row pointers rebased (Section 3.2)
-    std::vector<int32_t> rp_local((size_t)m + 1);
-    for (int32_t i = 0; i <= m; ++i) rp_local[i] = h->h_rp[h->rb + i] - h->h_rp[h->rb];
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
-    chk(dmalloc(&h->d_rp, (size_t)m + 1));
-    // padded: 16-byte stream-tile loads may run up to kStreamNnz entries past the end
-    chk(dmalloc(&h->d_ci, (size_t)h->nnz_gpu + kStreamNnz));
-    chk(dmalloc(&h->d_val, (size_t)h->nnz_gpu + kStreamNnz));
-    chk(dmalloc(&h->d_rows, (size_t)m));
+    {
+        const int rc2 = dm_upload(h->A, m, h->h_rp.data() + h->rb, h->h_ci.data(), h->h_val.data(), h->rb);
+        if (rc2) return bail(rc2);
+    }
     chk(dmalloc(&h->d_pbuf, (size_t)n + 2));
     chk(dmalloc(&h->d_x, (size_t)m + 1));
     chk(dmalloc(&h->d_r, (size_t)m + 1));
@@ -434,6 +184,7 @@ extern "C" int cg_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const i
     chk(dmalloc(&h->d_part_setup, 2 * (size_t)h->grid_cap));
     chk(dmalloc(&h->d_part_pq, (size_t)h->grid_cap));
     chk(dmalloc(&h->d_part_rr, (size_t)h->grid_cap));
+    chk(dmalloc(&h->d_part_rz, (size_t)h->grid_cap));
     try { h->h_part.assign(2 * (size_t)h->grid_cap, 0.0); } catch (...) { return bail(fail(CG_ENOMEM, "out of host memory")); }
     chk(dmalloc(&h->d_state, 1));
     if (e != hipSuccess) return bail(fail(CG_ENOMEM, "device allocation failed: %s", hipGetErrorString(e)));
@@ -441,24 +192,13 @@ extern "C" int cg_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const i
         return bail(fail(CG_ENOMEM, "pinned allocation failed"));
     // p + rb must be 16-byte aligned for the paired loads of the update kernels
     h->d_p = h->d_pbuf + (h->rb & 1);
-    chk(hipMemcpy(h->d_rp, rp_local.data(), sizeof(int32_t) * ((size_t)m + 1), hipMemcpyHostToDevice));
-    if (h->nnz_gpu) {
-        chk(hipMemcpy(h->d_ci, h->h_ci.data() + h->h_rp[h->rb], sizeof(int32_t) * h->nnz_gpu,
-                      hipMemcpyHostToDevice));
-        chk(hipMemcpy(h->d_val, h->h_val.data() + h->h_rp[h->rb], sizeof(double) * h->nnz_gpu,
-                      hipMemcpyHostToDevice));
-    }
-    // padding (and entry 0 of an empty block): column 0, value 0
-    chk(hipMemset(h->d_ci + h->nnz_gpu, 0, sizeof(int32_t) * kStreamNnz));
-    chk(hipMemset(h->d_val + h->nnz_gpu, 0, sizeof(double) * kStreamNnz));
-    if (e == hipSuccess) {
+    {
         const int rc2 = apply_schedule(h);
         if (rc2) return bail(rc2);
     }
     chk(hipMemset(h->d_state, 0, sizeof(DevState)));
     chk(hipMemset(h->d_pbuf, 0, sizeof(double) * ((size_t)n + 2)));
     if (e != hipSuccess) return bail(fail(CG_EDEVICE, "upload failed: %s", hipGetErrorString(e)));
-
     if (!h->gpu_only() && n > 0) {
         // split or host-only: host vectors, pinned p, exchange streams, halo lists
         try {
@@ -542,11 +282,17 @@ extern "C" int cg_set_opts(cg_handle *h, const cg_opts *o) {
     if ((o->precision != CG_PREC_FP64 || o->precond != CG_PC_NONE) && !h->gpu_only())
         return fail(CG_EINVAL, "mixed precision and preconditioning need a GPU-only handle");
     if (o->spmv_kind < 0 || o->spmv_kind > 3) return fail(CG_EINVAL, "unknown spmv_kind %d", o->spmv_kind);
+    if (o->precision == CG_PREC_MIXED && o->precond != CG_PC_NONE)
+        return fail(CG_EINVAL, "the preconditioned solve runs in float64 only");
     h->opts = *o;
     HIP_TRY(hipSetDevice(h->dev));
     HIP_TRY(h->stream ? hipStreamSynchronize(h->stream) : hipDeviceSynchronize());
-    const int rc = apply_schedule(h);
+    int rc = apply_schedule(h);
     if (rc) return rc;
+    if (o->precision == CG_PREC_MIXED) {
+        rc = ensure_mixed_vectors(h);
+        if (rc) return rc;
+    }
     return CG_OK;
 }
 
@@ -566,11 +312,11 @@ extern "C" int cg_slice_info(const cg_handle *h, int32_t *rows_gpu, int64_t *nnz
 extern "C" int cg_read_slice(const cg_handle *h, int32_t *row_ptr, int32_t *col_idx, double *val) {
     if (!h) return fail(CG_EINVAL, "handle is NULL");
     HIP_TRY(hipSetDevice(h->dev));
-    if (row_ptr) HIP_TRY(hipMemcpy(row_ptr, h->d_rp, sizeof(int32_t) * ((size_t)h->m + 1), hipMemcpyDeviceToHost));
+    if (row_ptr) HIP_TRY(hipMemcpy(row_ptr, h->A.d_rp, sizeof(int32_t) * ((size_t)h->m + 1), hipMemcpyDeviceToHost));
     if (h->nnz_gpu && col_idx)
-        HIP_TRY(hipMemcpy(col_idx, h->d_ci, sizeof(int32_t) * h->nnz_gpu, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(col_idx, h->A.d_ci, sizeof(int32_t) * h->nnz_gpu, hipMemcpyDeviceToHost));
     if (h->nnz_gpu && val)
-        HIP_TRY(hipMemcpy(val, h->d_val, sizeof(double) * h->nnz_gpu, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(val, h->A.d_val, sizeof(double) * h->nnz_gpu, hipMemcpyDeviceToHost));
     return CG_OK;
 }
 
@@ -623,7 +369,9 @@ double host_row_dot(const cg_handle *h, int32_t i, const double *p) {
 // ---------------------------------------------------------------------------
 // device helpers
 
-static int gpu_state_init(cg_handle *h, double tol, int32_t maxit) {
+namespace cgmi {
+
+int gpu_state_init(cg_handle *h, double tol, int32_t maxit) {
     DevState &s = *h->h_state;
     std::memset(&s, 0, sizeof s);
     s.tol = tol;
@@ -633,7 +381,7 @@ static int gpu_state_init(cg_handle *h, double tol, int32_t maxit) {
     return CG_OK;
 }
 
-static int gpu_state_read(cg_handle *h) {
+int gpu_state_read(cg_handle *h) {
     HIP_TRY(hipMemcpyAsync(h->h_state, h->d_state, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     return CG_OK;
@@ -641,8 +389,8 @@ static int gpu_state_read(cg_handle *h) {
 
 // Copy `count` partials (or two interleaved arrays of `count`) to the host and
 // sum each in workgroup order.
-static int sum_partials_host(cg_handle *h, const double *d_part, int count, int arrays, double *s0,
-                             double *s1) {
+int sum_partials_host(cg_handle *h, const double *d_part, int count, int arrays, double *s0,
+                      double *s1) {
     HIP_TRY(hipMemcpyAsync(h->h_part.data(), d_part, sizeof(double) * (size_t)count * arrays,
                            hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
@@ -655,24 +403,24 @@ static int sum_partials_host(cg_handle *h, const double *d_part, int count, int 
     return CG_OK;
 }
 
-static Partials no_partials() { return Partials{nullptr, 0}; }
-
 // ||b - A x||^2 and ||b||^2 over the GPU rows (x full length on the device).
-static int gpu_true_residual(cg_handle *h, const double *b_own, const double *x_full, double *rr,
-                             double *bb) {
-    HIP_TRY(launch_spmv(h->csr(), h->sched, h->spmv_grid, x_full, h->d_q, nullptr, b_own, h->d_q,
+int gpu_true_residual(cg_handle *h, const double *b_own, const double *x_full, double *rr,
+                      double *bb) {
+    HIP_TRY(launch_spmv(h->A.dev(), h->A.sched, h->A.grid, x_full, h->d_q, nullptr, b_own, h->d_q,
                         h->d_part_setup, no_partials(), no_partials(), nullptr, kSpmvResidual, 0,
                         h->stream));
-    return sum_partials_host(h, h->d_part_setup, h->spmv_grid, 2, rr, bb);
+    return sum_partials_host(h, h->d_part_setup, h->A.grid, 2, rr, bb);
 }
 
-static int status_of(int done) {
+int status_of(int done) {
     switch (done) {
         case kDoneConverged: return CG_OK;
         case kDoneBreakdown: return CG_EBREAKDOWN;
         default: return CG_MAXIT;
     }
 }
+
+}  // namespace cgmi
 
 // ---------------------------------------------------------------------------
 // GPU-only solve: alpha, beta and the stop test stay on the device; the host
@@ -691,15 +439,15 @@ static int solve_gpu_only(cg_handle *h, const double *b, double *x, double tol, 
     int n_spmv = 0;
     const double t0 = now();
     if (small) {
-        HIP_TRY(launch_cg_small(n, h->d_rp, h->d_ci, h->d_val, b, h->d_x, tol, maxit, h->d_state, st));
+        HIP_TRY(launch_cg_small(n, h->A.d_rp, h->A.d_ci, h->A.d_val, b, h->d_x, tol, maxit, h->d_state, st));
         rc = gpu_state_read(h);
         if (rc) return rc;
     } else {
-        const int Gs = h->spmv_grid, Gv = h->vec_grid;
+        const int Gs = h->A.grid, Gv = h->vec_grid;
         const Partials setup_rr{h->d_part_setup, Gs}, setup_bb{h->d_part_setup + Gs, Gs};
         const Partials pq{h->d_part_pq, Gs}, rr{h->d_part_rr, Gv};
         // r = b - A x, p = r (partials of r^T r and b^T b)
-        HIP_TRY(launch_spmv(h->csr(), h->sched, Gs, h->d_x, h->d_r, nullptr, b, h->d_p,
+        HIP_TRY(launch_spmv(h->A.dev(), h->A.sched, Gs, h->d_x, h->d_r, nullptr, b, h->d_p,
                             h->d_part_setup, no_partials(), no_partials(), nullptr, kSpmvResidual, 0, st));
         const int C = h->opts.check_every;
         std::vector<hipEvent_t> ev;
@@ -715,7 +463,7 @@ static int solve_gpu_only(cg_handle *h, const double *b, double *x, double tol, 
             for (int32_t j = 0; j < chunk; ++j) {
                 const int32_t kk = k + j;
                 if (h->opts.profile) HIP_TRY(hipEventRecord(ev[2 * j], st));
-                HIP_TRY(launch_spmv(h->csr(), h->sched, Gs, h->d_p, h->d_q, h->d_p, nullptr, nullptr,
+                HIP_TRY(launch_spmv(h->A.dev(), h->A.sched, Gs, h->d_p, h->d_q, h->d_p, nullptr, nullptr,
                                     h->d_part_pq, setup_rr, setup_bb, h->d_state, kSpmvDot, kk == 0, st));
                 if (h->opts.profile) HIP_TRY(hipEventRecord(ev[2 * j + 1], st));
                 if (maxit == 0) break;
@@ -783,17 +531,19 @@ static int solve_gpu_mixed(cg_handle *h, const double *b, double *x, double tol,
                            cg_result *res) {
     const int32_t n = h->n;
     hipStream_t st = h->stream;
-    const int Gs = h->spmv_grid, Gv = h->vec_grid;
+    const int Gs = h->A.grid, Gv = h->vec_grid;
     const Partials pq{h->d_part_pq, Gs}, rrp{h->d_part_rr, Gv};
     const double t0 = now();
     double t_spmv = 0.0;
     int n_spmv = 0;
+    int rc = ensure_mixed_vectors(h);
+    if (rc) return rc;
     HIP_TRY(hipMemcpyAsync(h->d_x, x, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
-    int rc = gpu_state_init(h, tol, maxit);
+    rc = gpu_state_init(h, tol, maxit);
     if (rc) return rc;
     // float64 true residual r64 = b - A x (into d_r) and its norm
     auto true_residual = [&](double *rr, double *bb) -> int {
-        HIP_TRY(launch_spmv(h->csr(), h->sched, Gs, h->d_x, h->d_r, nullptr, b, h->d_r,
+        HIP_TRY(launch_spmv(h->A.dev(), h->A.sched, Gs, h->d_x, h->d_r, nullptr, b, h->d_r,
                             h->d_part_setup, no_partials(), no_partials(), nullptr, kSpmvResidual, 0, st));
         return sum_partials_host(h, h->d_part_setup, Gs, 2, rr, bb);
     };
@@ -834,7 +584,7 @@ static int solve_gpu_mixed(cg_handle *h, const double *b, double *x, double tol,
             const int32_t chunk = std::min<int32_t>(C, maxit - k);
             for (int32_t j = 0; j < chunk; ++j) {
                 if (h->opts.profile) HIP_TRY(hipEventRecord(ev[2 * j], st));
-                HIP_TRY(launch_spmv_f32(h->csr(), h->sched, Gs, h->d_p32, h->d_q32, h->d_p32,
+                HIP_TRY(launch_spmv_f32(h->A.dev(), h->A.sched, Gs, h->d_p32, h->d_q32, h->d_p32,
                                         h->d_part_pq, h->d_state, kSpmvDot, st));
                 if (h->opts.profile) HIP_TRY(hipEventRecord(ev[2 * j + 1], st));
                 HIP_TRY(launch_update_xr_mixed(n, Gv, h->d_x, h->d_r32, h->d_p32, h->d_q32,
@@ -983,7 +733,7 @@ static int solve_split(cg_handle *h, const double *b, double *x, double tol, int
     const int32_t n = h->n, rb = h->rb, re = h->re, m = h->m;
     const bool gpu = m > 0;
     hipStream_t st = h->stream;
-    const int Gs = h->spmv_grid, Gv = h->vec_grid;
+    const int Gs = h->A.grid, Gv = h->vec_grid;
     SplitTimers tm;
     double *hx = h->h_x.data(), *hr = h->h_r.data(), *hq = h->h_q.data(), *hb = h->h_b.data();
     double *hp = h->h_p;
@@ -999,7 +749,7 @@ static int solve_split(cg_handle *h, const double *b, double *x, double tol, int
     }
     double t_g = now();
     if (gpu)
-        HIP_TRY(launch_spmv(h->csr(), h->sched, Gs, x, h->d_r, nullptr, b + rb, h->d_p + rb,
+        HIP_TRY(launch_spmv(h->A.dev(), h->A.sched, Gs, x, h->d_r, nullptr, b + rb, h->d_p + rb,
                             h->d_part_setup, no_partials(), no_partials(), nullptr, kSpmvResidual, 0, st));
     double t_c = now();
     const double rho_c = host_reduce(h, [&](int32_t i) {
@@ -1033,7 +783,7 @@ static int solve_split(cg_handle *h, const double *b, double *x, double tol, int
         // q = A p and p^T q: GPU rows and host rows at the same time
         t_g = now();
         if (gpu)
-            HIP_TRY(launch_spmv(h->csr(), h->sched, Gs, h->d_p, h->d_q, h->d_p + rb, nullptr, nullptr,
+            HIP_TRY(launch_spmv(h->A.dev(), h->A.sched, Gs, h->d_p, h->d_q, h->d_p + rb, nullptr, nullptr,
                                 h->d_part_pq, no_partials(), no_partials(), nullptr, kSpmvDot, 0, st));
         t_c = now();
         const double pq_c = host_reduce(h, [&](int32_t i) {
@@ -1127,7 +877,7 @@ static int solve_split(cg_handle *h, const double *b, double *x, double tol, int
 
 extern "C" int cg_solve(cg_handle *h, const double *b, double *x, double tol, int32_t maxit,
                         cg_result *res) {
-    g_err.clear();
+    clear_error();
     if (!h) return fail(CG_EINVAL, "handle is NULL");
     if (res) std::memset(res, 0, sizeof *res);
     if (!(tol >= 0.0)) return fail(CG_EINVAL, "tol must be >= 0");
@@ -1148,25 +898,39 @@ extern "C" int cg_solve(cg_handle *h, const double *b, double *x, double tol, in
     int rc;
     if (h->gpu_only()) {
         if (h->nnz == 0) return fail(CG_EINVAL, "matrix has no nonzeros");
-        if (h->opts.precision == CG_PREC_MIXED) rc = solve_gpu_mixed(h, b, x, tol, maxit, res);
-        else rc = solve_gpu_only(h, b, x, tol, maxit, res);
+        if (h->opts.precond == CG_PC_FSAI) {
+            if (!h->have_factor) return fail(CG_EINVAL, "precond is CG_PC_FSAI but no factor is installed");
+            rc = solve_gpu_pcg(h, b, x, tol, maxit, res);
+            if (rc == CG_EBREAKDOWN) {
+                // preconditioned breakdown (M not SPD in floating point): plain CG from x0
+                clear_error();
+                if (res) std::memset(res, 0, sizeof *res);
+                rc = solve_gpu_only(h, b, x, tol, maxit, res);
+                if (res) res->fell_back = 1;
+            }
+        } else if (h->opts.precision == CG_PREC_MIXED) {
+            rc = solve_gpu_mixed(h, b, x, tol, maxit, res);
+        } else {
+            rc = solve_gpu_only(h, b, x, tol, maxit, res);
+        }
     } else {
         rc = solve_split(h, b, x, tol, maxit, res);
     }
     if (res) {
         res->t_solve = now() - t0;
+        res->spmv_kind = h->m == 0 ? 0 : h->A.sched.kind == kTileSliced ? 3 : h->A.sched.kind == kTileStream ? 2 : 1;
         res->rows_gpu = h->m;
         res->rows_cpu = h->n - h->m;
         res->nnz_gpu = h->nnz_gpu;
         res->nnz_cpu = h->nnz_cpu;
         if (rc < 0 && res->status == 0) res->status = rc;
     }
-    if (rc == CG_EBREAKDOWN && g_err.empty()) g_err = "breakdown: p^T q <= 0 or not finite";
+    if (rc == CG_EBREAKDOWN && !*error_message()) fail(CG_EBREAKDOWN, "breakdown: p^T q <= 0 or not finite");
     return rc;
 }
 
 extern "C" int cg_spmv(cg_handle *h, const double *x, double *y) {
-    g_err.clear();
+    clear_error();
     if (!h) return fail(CG_EINVAL, "handle is NULL");
     if (h->n == 0) return CG_OK;
     if (!x || !y) return fail(CG_EINVAL, "x/y is NULL");
@@ -1177,7 +941,7 @@ extern "C" int cg_spmv(cg_handle *h, const double *x, double *y) {
             HIP_TRY(hipMemsetAsync(y, 0, sizeof(double) * n, h->stream));
             return CG_OK;
         }
-        HIP_TRY(launch_spmv(h->csr(), h->sched, h->spmv_grid, x, y, nullptr, nullptr, nullptr, nullptr,
+        HIP_TRY(launch_spmv(h->A.dev(), h->A.sched, h->A.grid, x, y, nullptr, nullptr, nullptr, nullptr,
                             no_partials(), no_partials(), nullptr, kSpmvPlain, 0, h->stream));
         return CG_OK;
     }
@@ -1186,7 +950,7 @@ extern "C" int cg_spmv(cg_handle *h, const double *x, double *y) {
     HIP_TRY(hipMemcpyAsync(hx, x, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     if (m > 0 && h->nnz_gpu > 0)
-        HIP_TRY(launch_spmv(h->csr(), h->sched, h->spmv_grid, x, y + rb, nullptr, nullptr, nullptr,
+        HIP_TRY(launch_spmv(h->A.dev(), h->A.sched, h->A.grid, x, y + rb, nullptr, nullptr, nullptr,
                             nullptr, no_partials(), no_partials(), nullptr, kSpmvPlain, 0, h->stream));
     else if (m > 0)
         HIP_TRY(hipMemsetAsync(y + rb, 0, sizeof(double) * m, h->stream));
@@ -1201,13 +965,13 @@ extern "C" int cg_spmv(cg_handle *h, const double *x, double *y) {
 }
 
 extern "C" int cg_spmv_f32(cg_handle *h, const float *x, float *y) {
-    g_err.clear();
+    clear_error();
     if (!h) return fail(CG_EINVAL, "handle is NULL");
-    if (!h->gpu_only() || h->opts.precision != CG_PREC_MIXED || !h->d_val32)
+    if (!h->gpu_only() || h->opts.precision != CG_PREC_MIXED || !h->A.d_val32)
         return fail(CG_EINVAL, "cg_spmv_f32 needs a GPU-only handle with mixed precision set");
     if (!x || !y) return fail(CG_EINVAL, "x/y is NULL");
     HIP_TRY(hipSetDevice(h->dev));
-    HIP_TRY(launch_spmv_f32(h->csr(), h->sched, h->spmv_grid, x, y, nullptr, nullptr, nullptr,
+    HIP_TRY(launch_spmv_f32(h->A.dev(), h->A.sched, h->A.grid, x, y, nullptr, nullptr, nullptr,
                             kSpmvPlain, h->stream));
     return CG_OK;
 }

@@ -1,0 +1,141 @@
+// Host-side internals shared by the runtime files (built by g++):
+// error reporting, device matrices (a CSR block uploaded with its SpMV
+// schedule), and the solver handle.
+#pragma once
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/cgmi.h"
+#include "cgmi_internal.h"
+
+namespace cgmi {
+
+int fail(int code, const char *fmt, ...);
+void clear_error();
+const char *error_message();
+double now();
+// Square CSR n x n with int32 indices, strictly increasing columns per row.
+int validate_csr(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *ci, const double *val);
+
+template <class T>
+hipError_t dmalloc(T **p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    return hipMalloc(reinterpret_cast<void **>(p), sizeof(T) * count);
+}
+
+#define CGMI_HIP_TRY(expr)                                                                      \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return ::cgmi::fail(CG_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+    } while (0)
+
+// A block of CSR rows on the device: rebased row pointers, global column
+// indices, float64 values (col/val padded by kStreamNnz entries), its SpMV
+// schedule, and on demand the sliced copy and float32 copies of the values.
+struct DevMatrix {
+    int32_t m = 0;
+    int64_t nnz = 0;
+    int32_t pad_col_base = 0;        // global index of local row 0 (sliced padding)
+    std::vector<int32_t> h_rp;       // rebased row pointers (m + 1)
+    std::vector<int32_t> h_ci;       // columns (nnz)
+    std::vector<double> h_val;       // values (nnz)
+    int32_t *d_rp = nullptr, *d_ci = nullptr, *d_rows = nullptr;
+    double *d_val = nullptr;
+    int32_t *d_sell_off = nullptr, *d_sell_ci = nullptr;
+    double *d_sell_val = nullptr;
+    size_t sell_slots = 0;
+    float *d_val32 = nullptr, *d_sell_val32 = nullptr;
+    Schedule sched{};
+    int grid = 8;
+    CsrDev dev() const {
+        return CsrDev{m, d_rp, d_ci, d_val, sched.identity ? nullptr : d_rows,
+                      d_sell_off, d_sell_ci, d_sell_val, d_val32, d_sell_val32};
+    }
+};
+
+// Copy the rows (row pointers rebased to start at 0 are computed here from
+// the global ones: rp[0..m] with rp[0] possibly > 0) and upload them.
+int dm_upload(DevMatrix &M, int32_t m, const int32_t *rp, const int32_t *ci, const double *val,
+              int32_t pad_col_base);
+// Choose the tiling (kind_opt: cg_opts.spmv_kind), build the row list or the
+// sliced copy, size the grid (0: automatic, a multiple of 8 up to grid_cap).
+int dm_schedule(DevMatrix &M, int kind_opt, int grid_opt, int cus, int grid_cap, bool need_f32);
+int dm_ensure_f32(DevMatrix &M);
+void dm_free(DevMatrix &M);
+
+}  // namespace cgmi
+
+// Solver handle (C ABI type).
+struct cg_handle {
+    int dev = 0;
+    int32_t n = 0;
+    int64_t nnz = 0;
+    int32_t rb = 0, re = 0, m = 0;
+    int64_t nnz_gpu = 0, nnz_cpu = 0;
+    cg_opts opts{};
+    hipStream_t stream = nullptr;   // caller's stream (or null stream)
+    hipStream_t s_d2h = nullptr, s_h2d = nullptr;
+    int cus = 256;
+
+    // host copy of the matrix (the host complement uses its rows)
+    std::vector<int32_t> h_rp, h_ci;
+    std::vector<double> h_val;
+
+    cgmi::DevMatrix A;               // the GPU row block
+    int vec_grid = 0;
+
+    // device vectors
+    double *d_pbuf = nullptr;  // allocation behind d_p
+    double *d_p = nullptr;     // full length n, d_p + rb is 16-byte aligned
+    double *d_x = nullptr, *d_r = nullptr, *d_q = nullptr;  // m each
+    double *d_part_setup = nullptr;  // 2 x grid: r^T r, b^T b of the residual kernel
+    double *d_part_pq = nullptr;
+    double *d_part_rr = nullptr;
+    double *d_part_rz = nullptr;
+    int grid_cap = 0;
+    std::vector<double> h_part;
+    cgmi::DevState *d_state = nullptr;
+    cgmi::DevState *h_state = nullptr;  // pinned
+
+    // mixed precision vectors
+    float *d_r32 = nullptr, *d_p32 = nullptr, *d_q32 = nullptr;
+
+    // preconditioner M^-1 = G^T G
+    cgmi::DevMatrix G, GT;
+    bool have_factor = false;
+    double *d_t = nullptr, *d_z = nullptr;
+    struct FsaiSetup *fsai = nullptr;   // learned-factor workspace (fsai.cpp)
+
+    // split mode
+    double *h_p = nullptr;  // pinned, length n
+    std::vector<double> h_x, h_r, h_q, h_b;
+    std::vector<int32_t> halo_d2h, halo_h2d;  // global column ids
+    int32_t *d_halo_d2h = nullptr, *d_halo_h2d = nullptr;
+    double *d_pack_d2h = nullptr, *d_pack_h2d = nullptr;
+    double *h_pack_d2h = nullptr, *h_pack_h2d = nullptr;  // pinned
+
+    bool gpu_only() const { return rb == 0 && re == n && n > 0; }
+    bool host_only() const { return m == 0; }
+};
+
+namespace cgmi {
+// Device-side CG helpers used by the solver variants (cgmi.cpp).
+int gpu_state_init(cg_handle *h, double tol, int32_t maxit);
+int gpu_state_read(cg_handle *h);
+int sum_partials_host(cg_handle *h, const double *d_part, int count, int arrays, double *s0,
+                      double *s1);
+int gpu_true_residual(cg_handle *h, const double *b_own, const double *x_full, double *rr,
+                      double *bb);
+inline Partials no_partials() { return Partials{nullptr, 0}; }
+int status_of(int done);
+// Preconditioned solve (fsai.cpp); on a breakdown it returns CG_EBREAKDOWN
+// with x untouched.
+int solve_gpu_pcg(cg_handle *h, const double *b, double *x, double tol, int32_t maxit,
+                  cg_result *res);
+void fsai_free(cg_handle *h);
+}  // namespace cgmi

@@ -106,7 +106,7 @@ struct Partials {
 enum { kSpmvPlain = 0, kSpmvDot = 1, kSpmvResidual = 2 };
 
 // q = A p on the block's rows.
-//   kSpmvPlain:    nothing else.
+//   kSpmvPlain:    nothing else (with st: nothing once the solve has stopped).
 //   kSpmvDot:      out_partials[wg] = sum p_own_i q_i.  With `k0_check`
 //                  (first iteration of a device-driven solve) every workgroup
 //                  first reduces the setup partials (r^T r in `in0`, b^T b in
@@ -157,6 +157,13 @@ hipError_t launch_update_xr(int32_t m, int grid, double *x, double *r, const dou
 hipError_t launch_update_p(int32_t m, int grid, const double *r, double *p_own, Partials rr,
                            DevState *st, int device_coef, int32_t k, double beta_arg,
                            hipStream_t s);
+
+// Preconditioned CG (z = M^-1 r): p = z + beta p, rho = r^T z from the rz
+// partials, the stop test on the rr partials; first = 1 is the setup step
+// (rho_0, ||b||^2 from bb, stop test at the top of iteration 0, p = z).
+hipError_t launch_update_p_pcg(int32_t m, int grid, const double *z, double *p, Partials rr,
+                               Partials rz, Partials bb, DevState *st, int first, int32_t k,
+                               hipStream_t s);
 
 // Whole-solve single-workgroup CG for small systems (p held in LDS).
 int small_path_max_rows();

@@ -1,0 +1,265 @@
+// devmatrix.cpp -- a CSR row block on the device with its SpMV schedule.
+#include <algorithm>
+#include <climits>
+#include <cstring>
+
+#include "cgmi_host.h"
+
+namespace cgmi {
+
+namespace {
+
+int lanes_for_length(int64_t len) {
+    int L = 1;
+    while (L < len && L < 64) L <<= 1;
+    return L;
+}
+
+void free_sliced(DevMatrix &M) {
+    (void)hipFree(M.d_sell_off);
+    (void)hipFree(M.d_sell_ci);
+    (void)hipFree(M.d_sell_val);
+    (void)hipFree(M.d_sell_val32);
+    M.d_sell_off = M.d_sell_ci = nullptr;
+    M.d_sell_val = nullptr;
+    M.d_sell_val32 = nullptr;
+    M.sell_slots = 0;
+}
+
+// Lanes-per-row classes.  Sliced tiles for rows of at most 64 nonzeros when
+// slicing pads by at most 25%; stream tiles when requested and every 64-row
+// tile fits; otherwise vector bins: rows of similar length keep their natural
+// order (one bin, no indirection), spread-out lengths are binned by the power
+// of two covering the row length (row list per bin), rows longer than
+// kHugeRow go to a workgroup-per-row list at the end.
+void build_schedule(const DevMatrix &M, int kind_opt, Schedule &S, std::vector<int32_t> &rows_out) {
+    S = Schedule{};
+    const int32_t m = M.m;
+    rows_out.clear();
+    S.identity = 1;
+    if (m == 0) return;
+    auto len = [&](int32_t i) -> int64_t { return M.h_rp[i + 1] - M.h_rp[i]; };
+    int64_t maxlen = 0;
+    for (int32_t i = 0; i < m; ++i) maxlen = std::max<int64_t>(maxlen, len(i));
+    const double mean = (double)M.h_rp[m] / (double)m;
+    if (kind_opt == 3 || (kind_opt == 0 && maxlen <= 64)) {
+        const int32_t nt = (m + kWaveSize - 1) / kWaveSize;
+        int64_t slots = 0;
+        int maxw = 0;
+        for (int32_t t = 0; t < nt; ++t) {
+            int64_t w = 0;
+            for (int32_t i = t * kWaveSize; i < std::min(m, (t + 1) * kWaveSize); ++i) w = std::max(w, len(i));
+            w = std::max<int64_t>(w, 1);
+            slots += w * kWaveSize;
+            maxw = std::max<int>(maxw, (int)w);
+        }
+        if (maxlen <= 64 && slots < INT32_MAX && (kind_opt == 3 || slots <= M.nnz + M.nnz / 4)) {
+            S.kind = kTileSliced;
+            S.nbins = 1;
+            S.bins[0] = Bin{std::max(1, maxw), 0, m, 0};
+            S.ntiles = nt;
+            return;
+        }
+    }
+    if (kind_opt == 2) {
+        bool fits = true;
+        for (int32_t r0 = 0; r0 < m && fits; r0 += kWaveSize) {
+            const int32_t r1 = std::min(m, r0 + kWaveSize);
+            fits = (M.h_rp[r0] & 3) + (M.h_rp[r1] - M.h_rp[r0]) <= kStreamNnz;
+        }
+        if (fits) {
+            S.kind = kTileStream;
+            S.nbins = 1;
+            S.bins[0] = Bin{kWaveSize, 0, m, 0};
+            S.ntiles = (m + kWaveSize - 1) / kWaveSize;
+            return;
+        }
+    }
+    if (maxlen <= 64 && (double)maxlen <= 2.0 * mean + 1.0) {
+        const int L = lanes_for_length(maxlen);
+        S.nbins = 1;
+        S.bins[0] = Bin{L, 0, m, 0};
+        S.ntiles = (m + rows_per_wave_tile(L) - 1) / rows_per_wave_tile(L);
+        return;
+    }
+    static const int classes[7] = {1, 2, 4, 8, 16, 32, 64};
+    std::vector<std::vector<int32_t>> lists(7);
+    std::vector<int32_t> huge;
+    for (int32_t i = 0; i < m; ++i) {
+        const int64_t l = len(i);
+        if (l > kHugeRow) {
+            huge.push_back(i);
+            continue;
+        }
+        const int L = lanes_for_length(l);
+        int c = 0;
+        while (classes[c] != L) ++c;
+        lists[c].push_back(i);
+    }
+    S.identity = 0;
+    int nb = 0, tile = 0, pos = 0;
+    for (int c = 0; c < 7; ++c) {
+        if (lists[c].empty()) continue;
+        const int cnt = (int)lists[c].size();
+        S.bins[nb] = Bin{classes[c], pos, cnt, tile};
+        tile += (cnt + rows_per_wave_tile(classes[c]) - 1) / rows_per_wave_tile(classes[c]);
+        rows_out.insert(rows_out.end(), lists[c].begin(), lists[c].end());
+        pos += cnt;
+        ++nb;
+    }
+    S.nbins = nb;
+    S.ntiles = tile;
+    S.huge_first = pos;
+    S.huge_count = (int32_t)huge.size();
+    rows_out.insert(rows_out.end(), huge.begin(), huge.end());
+}
+
+// Slot-major copy in slices of 64 rows padded to the slice's longest row
+// (at least one slot, so every load stays inside the allocation).  Padding
+// slots gather the row's own entry of the vector and are never summed.
+int build_sliced(DevMatrix &M) {
+    if (M.d_sell_off) return CG_OK;
+    const int32_t m = M.m, nt = M.sched.ntiles;
+    std::vector<int32_t> off((size_t)nt + 1, 0);
+    for (int32_t t = 0; t < nt; ++t) {
+        int32_t w = 0;
+        for (int32_t i = t * kWaveSize; i < std::min(m, (t + 1) * kWaveSize); ++i)
+            w = std::max(w, M.h_rp[i + 1] - M.h_rp[i]);
+        w = std::max(w, 1);
+        off[t + 1] = off[t] + w * kWaveSize;
+    }
+    const size_t slots = (size_t)off[nt];
+    std::vector<int32_t> sci(slots ? slots : 1, 0);
+    std::vector<double> sval(slots ? slots : 1, 0.0);
+    for (int32_t t = 0; t < nt; ++t) {
+        const int32_t w = (off[t + 1] - off[t]) / kWaveSize;
+        for (int32_t l = 0; l < kWaveSize; ++l) {
+            const int32_t i = t * kWaveSize + l;
+            const int32_t b = i < m ? M.h_rp[i] : 0;
+            const int32_t len = i < m ? M.h_rp[i + 1] - M.h_rp[i] : 0;
+            const int32_t pad_col = i < m ? M.pad_col_base + i : M.pad_col_base;
+            for (int32_t j = 0; j < w; ++j) {
+                const size_t k = (size_t)off[t] + (size_t)j * kWaveSize + l;
+                sci[k] = j < len ? M.h_ci[b + j] : pad_col;
+                sval[k] = j < len ? M.h_val[b + j] : 0.0;
+            }
+        }
+    }
+    hipError_t e = dmalloc(&M.d_sell_off, off.size());
+    if (e == hipSuccess) e = dmalloc(&M.d_sell_ci, sci.size());
+    if (e == hipSuccess) e = dmalloc(&M.d_sell_val, sval.size());
+    if (e == hipSuccess) e = hipMemcpy(M.d_sell_off, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(M.d_sell_ci, sci.data(), sizeof(int32_t) * sci.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(M.d_sell_val, sval.data(), sizeof(double) * sval.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        free_sliced(M);
+        return fail(CG_ENOMEM, "sliced layout upload failed: %s", hipGetErrorString(e));
+    }
+    M.sell_slots = sci.size();
+    return CG_OK;
+}
+
+}  // namespace
+
+int dm_upload(DevMatrix &M, int32_t m, const int32_t *rp, const int32_t *ci, const double *val,
+              int32_t pad_col_base) {
+    dm_free(M);
+    M.m = m;
+    M.pad_col_base = pad_col_base;
+    const int32_t base = m > 0 ? rp[0] : 0;
+    M.nnz = m > 0 ? (int64_t)rp[m] - base : 0;
+    try {
+        M.h_rp.resize((size_t)m + 1);
+        for (int32_t i = 0; i <= m; ++i) M.h_rp[i] = m > 0 ? rp[i] - base : 0;
+        M.h_ci.assign(ci + base, ci + base + M.nnz);
+        M.h_val.assign(val + base, val + base + M.nnz);
+    } catch (...) {
+        return fail(CG_ENOMEM, "out of host memory");
+    }
+    hipError_t e = dmalloc(&M.d_rp, (size_t)m + 1);
+    // padded: 16-byte stream-tile loads may run up to kStreamNnz entries past the end
+    if (e == hipSuccess) e = dmalloc(&M.d_ci, (size_t)M.nnz + kStreamNnz);
+    if (e == hipSuccess) e = dmalloc(&M.d_val, (size_t)M.nnz + kStreamNnz);
+    if (e == hipSuccess) e = dmalloc(&M.d_rows, (size_t)m);
+    if (e == hipSuccess)
+        e = hipMemcpy(M.d_rp, M.h_rp.data(), sizeof(int32_t) * ((size_t)m + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess && M.nnz)
+        e = hipMemcpy(M.d_ci, M.h_ci.data(), sizeof(int32_t) * M.nnz, hipMemcpyHostToDevice);
+    if (e == hipSuccess && M.nnz)
+        e = hipMemcpy(M.d_val, M.h_val.data(), sizeof(double) * M.nnz, hipMemcpyHostToDevice);
+    // padding (and entry 0 of an empty block): column 0, value 0
+    if (e == hipSuccess) e = hipMemset(M.d_ci + M.nnz, 0, sizeof(int32_t) * kStreamNnz);
+    if (e == hipSuccess) e = hipMemset(M.d_val + M.nnz, 0, sizeof(double) * kStreamNnz);
+    if (e != hipSuccess) {
+        dm_free(M);
+        return fail(CG_ENOMEM, "matrix upload failed: %s", hipGetErrorString(e));
+    }
+    return CG_OK;
+}
+
+int dm_ensure_f32(DevMatrix &M) {
+    hipError_t e = hipSuccess;
+    if (!M.d_val32) {
+        const size_t nv = (size_t)M.nnz + kStreamNnz;
+        std::vector<float> v32(nv, 0.0f);
+        for (int64_t k = 0; k < M.nnz; ++k) v32[k] = (float)M.h_val[k];
+        e = dmalloc(&M.d_val32, nv);
+        if (e == hipSuccess) e = hipMemcpy(M.d_val32, v32.data(), sizeof(float) * nv, hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess && M.d_sell_val && !M.d_sell_val32) {
+        std::vector<double> sv(M.sell_slots);
+        e = hipMemcpy(sv.data(), M.d_sell_val, sizeof(double) * sv.size(), hipMemcpyDeviceToHost);
+        std::vector<float> sv32(sv.size());
+        for (size_t k = 0; k < sv.size(); ++k) sv32[k] = (float)sv[k];
+        if (e == hipSuccess) e = dmalloc(&M.d_sell_val32, sv32.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(M.d_sell_val32, sv32.data(), sizeof(float) * sv32.size(), hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) return fail(CG_ENOMEM, "float32 copies: %s", hipGetErrorString(e));
+    return CG_OK;
+}
+
+int dm_schedule(DevMatrix &M, int kind_opt, int grid_opt, int cus, int grid_cap, bool need_f32) {
+    std::vector<int32_t> rows;
+    build_schedule(M, kind_opt, M.sched, rows);
+    if (M.sched.kind == kTileSliced) {
+        const int rc = build_sliced(M);
+        if (rc) return rc;
+    }
+    if (!rows.empty()) {
+        const hipError_t e = hipMemcpy(M.d_rows, rows.data(), sizeof(int32_t) * rows.size(),
+                                       hipMemcpyHostToDevice);
+        if (e != hipSuccess) return fail(CG_EDEVICE, "row list upload failed: %s", hipGetErrorString(e));
+    }
+    if (need_f32) {
+        if (M.sched.kind == kTileStream)
+            return fail(CG_EINVAL, "stream tiles have no float32 variant: use spmv_kind 0, 1 or 3");
+        const int rc = dm_ensure_f32(M);
+        if (rc) return rc;
+    }
+    const int waves_needed = M.sched.ntiles + M.sched.huge_count * (kBlock / kWaveSize);
+    const int auto_grid = ((waves_needed / (kBlock / kWaveSize) + 8) / 8) * 8;
+    int g = grid_opt > 0 ? grid_opt : std::min(cus * 8, auto_grid);
+    g = std::min(g, grid_cap);
+    M.grid = std::max(8, (g / 8) * 8);
+    return CG_OK;
+}
+
+void dm_free(DevMatrix &M) {
+    (void)hipFree(M.d_rp);
+    (void)hipFree(M.d_ci);
+    (void)hipFree(M.d_rows);
+    (void)hipFree(M.d_val);
+    (void)hipFree(M.d_val32);
+    free_sliced(M);
+    M.d_rp = M.d_ci = M.d_rows = nullptr;
+    M.d_val = nullptr;
+    M.d_val32 = nullptr;
+    M.m = 0;
+    M.nnz = 0;
+    M.h_rp.clear();
+    M.h_ci.clear();
+    M.h_val.clear();
+}
+
+}  // namespace cgmi

@@ -618,6 +618,64 @@ __global__ __launch_bounds__(kBlock) void k_update_p(int32_t m, const double *__
     if ((m & 1) && blockIdx.x == 0 && threadIdx.x == 0) p[m - 1] = fma(beta, p[m - 1], r[m - 1]);
 }
 
+// Preconditioned CG: p = z + beta p with rho = r^T z (z = M^-1 r); the stop
+// test is on r^T r.  first: setup step (after r = b - A x and z = M^-1 r):
+// rho_0 = r^T z, ||b||^2 from bb_in, the stop test at the top of iteration 0,
+// and p = z.  Otherwise after the x/r update of iteration k: a breakdown
+// (r^T z <= 0 or not finite while r != 0) ends the solve before the stop
+// test; workgroup 0 records iteration k+1.  b = 0 stops at once (x = 0).
+__global__ __launch_bounds__(kBlock) void k_update_p_pcg(int32_t m, const double *__restrict__ z,
+                                                         double *__restrict__ p, Partials rr_in,
+                                                         Partials rz_in, Partials bb_in,
+                                                         DevState *__restrict__ st, int first,
+                                                         int32_t k) {
+    __shared__ double sh[kWavesPerBlock];
+    __shared__ double bc;
+    if (st->done) return;
+    const double rr = reduce_partials(rr_in, sh, &bc);
+    const double rz = reduce_partials(rz_in, sh, &bc);
+    double beta = 0.0;
+    if (first) {
+        const double bb = reduce_partials(bb_in, sh, &bc);
+        const bool conv = stop_test(rr, bb, st->tol) || bb == 0.0;
+        const bool stop = conv || st->maxit <= 0;
+        if (is_block0_thread0()) {
+            st->rho[0] = rz;
+            st->rr = rr;
+            st->bb = bb;
+            st->iter = 0;
+            if (stop) st->done = conv ? kDoneConverged : kDoneMaxit;
+        }
+        if (stop) return;
+    } else {
+        const bool broke = (!(rz > 0.0) || !isfinite(rz)) && rr != 0.0;
+        const bool conv = stop_test(rr, st->bb, st->tol);
+        const bool maxed = k + 1 >= st->maxit;
+        beta = rz / st->rho[k & 1];
+        if (is_block0_thread0()) {
+            st->rho[(k + 1) & 1] = rz;
+            st->rr = rr;
+            st->iter = k + 1;
+            if (broke) st->done = kDoneBreakdown;
+            else if (conv) st->done = kDoneConverged;
+            else if (maxed) st->done = kDoneMaxit;
+        }
+        if (broke || conv || maxed) return;
+    }
+    const int64_t npair = m >> 1;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    double2 *p2 = reinterpret_cast<double2 *>(p);
+    const double2 *z2 = reinterpret_cast<const double2 *>(z);
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < npair; i += stride) {
+        const double2 zv = z2[i];
+        double2 pv = p2[i];
+        pv.x = fma(beta, pv.x, zv.x);
+        pv.y = fma(beta, pv.y, zv.y);
+        p2[i] = pv;
+    }
+    if ((m & 1) && blockIdx.x == 0 && threadIdx.x == 0) p[m - 1] = fma(beta, p[m - 1], z[m - 1]);
+}
+
 // ---------------------------------------------------------------------------
 // Mixed precision: float32 r, p, q with float64 x and float64 sums.
 
@@ -890,7 +948,8 @@ hipError_t launch_spmv(const CsrDev &A, const Schedule &S, int grid, const doubl
     SpmvArgs<double> a{p, q, p_own, b, p_dst};
     switch (mode) {
         case kSpmvPlain:
-            launch_spmv_mode<kSpmvPlain, double>(A, S, grid, a, nullptr, in0, in1, nullptr, 0, s);
+            launch_spmv_mode<kSpmvPlain, double>(A, S, grid, a, nullptr, in0, in1, st,
+                                                 st ? kFlagCheckDone : 0, s);
             break;
         case kSpmvDot: {
             const int flags = st ? (kFlagCheckDone | (k0_check ? kFlagFirstIter : 0)) : 0;
@@ -943,6 +1002,14 @@ hipError_t launch_update_p(int32_t m, int grid, const double *r, double *p_own, 
     if (m == 0) return hipSuccess;
     hipLaunchKernelGGL(k_update_p, dim3(grid), dim3(kBlock), 0, s, m, r, p_own, rr, st, device_coef,
                        k, beta_arg);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_p_pcg(int32_t m, int grid, const double *z, double *p, Partials rr,
+                               Partials rz, Partials bb, DevState *st, int first, int32_t k,
+                               hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_update_p_pcg, dim3(grid), dim3(kBlock), 0, s, m, z, p, rr, rz, bb, st, first, k);
     return hipGetLastError();
 }
 

@@ -1,0 +1,701 @@
+// kernels_fsai.hip -- learned FSAI preconditioner kernels for gfx950.
+//
+// Network 12 -> 64 -> 64 -> 5 on the matrix cores (v_mfma 16x16x16 bf16,
+// float32 accumulation).  Activations are kept transposed (units x rows): the
+// output fragment of one layer (lane l holds unit 4*(l/16)+v, row l%16) is
+// exactly the B-operand fragment of the next layer, so the forward pass needs
+// no shuffles; weights are A-operand fragments held in registers.  A wavefront
+// processes tiles of 16 rows.  The backward pass stages activations and
+// signals in wavefront-private LDS in [unit][row] order so the weight-gradient
+// products (a reduction over rows) read 4 consecutive rows per lane.
+//
+// Definitions (features, factor, loss) follow the header cgmi_fsai.h.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "cgmi_internal.h"
+#include "fsai_internal.h"
+
+namespace cgmi {
+
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kW = 64;
+
+// float -> bfloat16 bits, round to nearest, ties to even (finite inputs).
+__device__ __forceinline__ uint16_t bf16_bits(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_float(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__device__ __forceinline__ f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ f32x4 zero4() { return f32x4{0.f, 0.f, 0.f, 0.f}; }
+
+// Weight fragments (A operands) built from the float32 master parameters.
+struct Frags {
+    bf16x4 w1[4];      // W1: M-tile t (units 16t..), K = features (12 used of 16)
+    bf16x4 w2[4][4];   // W2: M-tile t (out units), k-step s (in units)
+    bf16x4 w3[4];      // W3: M = outputs (5 used of 16), k-step s
+};
+
+__device__ __forceinline__ void load_frags(const float *__restrict__ th, Frags &F) {
+    const int l = threadIdx.x & (kW - 1);
+    const int r = l & 15, q = l >> 4;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int k = 4 * q + v;
+            F.w1[t][v] = (short)(k < kFeat ? bf16_bits(th[kOffW1 + (16 * t + r) * kFeat + k]) : 0);
+        }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                F.w2[t][s][v] = (short)bf16_bits(th[kOffW2 + (16 * t + r) * kHidden + 16 * s + 4 * q + v]);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            F.w3[s][v] = (short)(r < kOut ? bf16_bits(th[kOffW3 + r * kHidden + 16 * s + 4 * q + v]) : 0);
+}
+
+struct Fwd {
+    f32x4 z1[4], z2[4];   // pre-activations (units 16t + 4q + v, row r)
+    bf16x4 h1[4], h2[4];  // bfloat16 activations as next-layer B fragments
+    f32x4 o;              // outputs 4q + v (valid < 5), row r
+};
+
+// Forward pass of one 16-row tile; fin: the lane's 4 feature bits (features
+// 4q..4q+3 of row r).
+__device__ __forceinline__ void forward_tile(const Frags &W, const float *__restrict__ th,
+                                             bf16x4 fin, Fwd &Y) {
+    const int l = threadIdx.x & (kW - 1);
+    const int q = l >> 4;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        Y.z1[t] = mfma(W.w1[t], fin, zero4());
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            Y.z1[t][v] += th[kOffB1 + 16 * t + 4 * q + v];
+            Y.h1[t][v] = (short)bf16_bits(fmaxf(Y.z1[t][v], 0.f));
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        f32x4 c = zero4();
+#pragma unroll
+        for (int s = 0; s < 4; ++s) c = mfma(W.w2[t][s], Y.h1[s], c);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            c[v] += th[kOffB2 + 16 * t + 4 * q + v];
+            Y.h2[t][v] = (short)bf16_bits(fmaxf(c[v], 0.f));
+        }
+        Y.z2[t] = c;
+    }
+    f32x4 c = zero4();
+#pragma unroll
+    for (int s = 0; s < 4; ++s) c = mfma(W.w3[s], Y.h2[s], c);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int o = 4 * q + v;
+        c[v] += o < kOut ? th[kOffB3 + o] : 0.f;
+    }
+    Y.o = c;
+}
+
+__device__ __forceinline__ bf16x4 load_feats(const uint16_t *__restrict__ feats, int64_t row) {
+    const int q = (threadIdx.x & (kW - 1)) >> 4;
+    const uint2 u = *reinterpret_cast<const uint2 *>(feats + row * kFeatPad + 4 * q);
+    bf16x4 b;
+    b[0] = (short)(u.x & 0xFFFF);
+    b[1] = (short)(u.x >> 16);
+    b[2] = (short)(u.y & 0xFFFF);
+    b[3] = (short)(u.y >> 16);
+    return b;
+}
+
+// ---------------------------------------------------------------------------
+// Stencil slots, scaled operator and features (thread per row).
+__global__ void k_fsai_prepare(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                               const double *__restrict__ val, int32_t *__restrict__ scol,
+                               float *__restrict__ sval, double *__restrict__ diag,
+                               uint16_t *__restrict__ feats, int32_t *__restrict__ err) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int col[kSlots];
+    double a[kSlots];
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s) {
+        col[s] = -1;
+        a[s] = 0.0;
+    }
+    int bad = 0;
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+        const int c = ci[k];
+        const int s = stencil_slot(i, c);
+        if (col[s] >= 0) bad = 1;
+        col[s] = c;
+        a[s] = val[k];
+    }
+    const double di = a[kSlotC];
+    if (col[kSlotC] < 0 || !(di > 0.0)) bad = 1;
+    if (bad) {
+        atomicAdd(err, 1);
+        return;
+    }
+    diag[i] = di;
+    float f[kFeatPad];
+#pragma unroll
+    for (int k = 0; k < kFeatPad; ++k) f[k] = 0.f;
+    scol[i * kSlots + kSlotC] = i;
+    sval[i * kSlots + kSlotC] = 1.f;
+    const int nb[4] = {kSlotW, kSlotE, kSlotS, kSlotN};
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int s = nb[m];
+        const int j = col[s];
+        scol[i * kSlots + s] = j;
+        if (j < 0) {
+            sval[i * kSlots + s] = 0.f;
+            f[8 + m] = 1.f;
+            continue;
+        }
+        double dj = 0.0;
+        for (int k = rp[j]; k < rp[j + 1]; ++k)
+            if (ci[k] == j) dj = val[k];
+        if (!(dj > 0.0)) {
+            atomicAdd(err, 1);
+            return;
+        }
+        const double ah = a[s] / sqrt(di * dj);
+        sval[i * kSlots + s] = (float)ah;
+        f[m] = (float)ah;
+        f[4 + m] = (float)log(dj / di);
+    }
+#pragma unroll
+    for (int k = 0; k < kFeatPad; ++k) feats[(int64_t)i * kFeatPad + k] = bf16_bits(f[k]);
+}
+
+// ---------------------------------------------------------------------------
+// Forward pass over a list of 16-row tiles.  Training: outputs to out[row][8].
+// Inference: the factor's values into G (CSR of tril(A)) and G^T.
+template <bool TRAIN>
+__global__ __launch_bounds__(256) void k_fsai_forward(int32_t ntiles, const int32_t *__restrict__ tiles,
+                                                      int64_t nrows, const uint16_t *__restrict__ feats,
+                                                      const float *__restrict__ th, float *__restrict__ out,
+                                                      const int32_t *__restrict__ scol,
+                                                      const double *__restrict__ diag,
+                                                      const int32_t *__restrict__ gpos,
+                                                      const int32_t *__restrict__ tpos,
+                                                      double *__restrict__ gval,
+                                                      double *__restrict__ gtval) {
+    Frags W;
+    load_frags(th, W);
+    const int l = threadIdx.x & (kW - 1);
+    const int r = l & 15, q = l >> 4;
+    const int wave = blockIdx.x * (blockDim.x / kW) + threadIdx.x / kW;
+    const int nwaves = gridDim.x * (blockDim.x / kW);
+    for (int t = wave; t < ntiles; t += nwaves) {
+        const int64_t row0 = tiles ? (int64_t)tiles[t] : (int64_t)t * 16;
+        const int64_t row = row0 + r;
+        const bf16x4 fin = row < nrows ? load_feats(feats, row) : bf16x4{0, 0, 0, 0};
+        Fwd Y;
+        forward_tile(W, th, fin, Y);
+        if (row >= nrows) continue;
+        if (TRAIN) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int o = 4 * q + v;
+                if (o < kOut) out[row * kOutPad + o] = Y.o[v];
+            }
+        } else if (q == 0) {
+            // lanes 0..15 hold o_C, o_W, o_E, o_S of their row
+            const double oc = Y.o[0], ow = Y.o[1], os = Y.o[3];
+            const double sp = oc > 30.0 ? oc : log1p(exp(oc));
+            const double gt[3] = {sp + kEpsDiag, ow, os};   // C, W, S
+            const int slots[3] = {kSlotC, kSlotW, kSlotS};
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                const int p = gpos[row * 3 + m];
+                if (p < 0) continue;
+                const int j = scol[row * kSlots + slots[m]];
+                const double g = gt[m] / sqrt(diag[j]);
+                gval[p] = g;
+                gtval[tpos[p]] = g;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Loss and dL/dG~ on sampled rows (thread per sample).  G~ of a row is read
+// from the network outputs; A_hat from the slot tables.  dG~ accumulates with
+// float atomics (order-dependent rounding only).
+struct GRow {
+    int col[3];      // C, W, S columns (-1 absent)
+    float val[3];
+};
+
+__device__ __forceinline__ GRow g_row(int64_t base, int j, const float *__restrict__ out,
+                                      const int32_t *__restrict__ scol) {
+    GRow g;
+    const float *o = out + (base + j) * kOutPad;
+    const float oc = o[0];
+    g.col[0] = j;
+    g.val[0] = (oc > 30.f ? oc : log1pf(expf(oc))) + (float)kEpsDiag;
+    g.col[1] = scol[(base + j) * kSlots + kSlotW];
+    g.val[1] = g.col[1] >= 0 ? o[1] : 0.f;
+    g.col[2] = scol[(base + j) * kSlots + kSlotS];
+    g.val[2] = g.col[2] >= 0 ? o[3] : 0.f;
+    return g;
+}
+
+__device__ __forceinline__ float ahat(int64_t base, int row, int colj, const int32_t *__restrict__ scol,
+                                      const float *__restrict__ sval) {
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s)
+        if (scol[(base + row) * kSlots + s] == colj) return sval[(base + row) * kSlots + s];
+    return 0.f;
+}
+
+constexpr int kMaxU = 16;   // support of a row of G~ A_hat (5-point: at most 13)
+constexpr int kMaxJ = 32;   // candidate rows j
+
+__global__ __launch_bounds__(256) void k_fsai_loss(int32_t nsamp, const int32_t *__restrict__ samp_row,
+                                                   const int64_t *__restrict__ samp_base,
+                                                   const int32_t *__restrict__ samp_n,
+                                                   const float *__restrict__ out,
+                                                   const int32_t *__restrict__ scol,
+                                                   const float *__restrict__ sval,
+                                                   float *__restrict__ dg, float coef,
+                                                   double *__restrict__ partials) {
+    __shared__ double sh[4];
+    double loss = 0.0;
+    const int sidx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sidx < nsamp) {
+        const int i = samp_row[sidx];
+        const int64_t base = samp_base[sidx];
+        const int n = samp_n[sidx];
+        const GRow gi = g_row(base, i, out, scol);
+        // u = row i of G~ A_hat
+        int ucol[kMaxU];
+        float uval[kMaxU];
+        int nu = 0;
+        for (int a = 0; a < 3; ++a) {
+            const int k = gi.col[a];
+            if (k < 0) continue;
+            for (int s = 0; s < kSlots; ++s) {
+                const int c = scol[(base + k) * kSlots + s];
+                if (c < 0) continue;
+                const float v = gi.val[a] * sval[(base + k) * kSlots + s];
+                int p = 0;
+                while (p < nu && ucol[p] != c) ++p;
+                if (p == nu && nu < kMaxU) {
+                    ucol[nu] = c;
+                    uval[nu] = 0.f;
+                    ++nu;
+                }
+                if (p < kMaxU) uval[p] += v;
+            }
+        }
+        // candidate rows j: those whose G~ pattern {j, W(j), S(j)} meets supp(u)
+        int jr[kMaxJ];
+        int nj = 0;
+        for (int p = 0; p < nu; ++p) {
+            const int c = ucol[p];
+            const int cand[3] = {c, c + 1, -1};
+            int cands[3] = {cand[0], cand[1], -1};
+            // the row whose S slot is c: the N neighbour of c
+            const int nn = scol[(base + c) * kSlots + kSlotN];
+            cands[2] = nn;
+            for (int m = 0; m < 3; ++m) {
+                const int j = cands[m];
+                if (j < 0 || j >= n) continue;
+                const GRow gj = g_row(base, j, out, scol);
+                if (gj.col[0] != c && gj.col[1] != c && gj.col[2] != c) continue;
+                int x = 0;
+                while (x < nj && jr[x] != j) ++x;
+                if (x == nj && nj < kMaxJ) jr[nj++] = j;
+            }
+        }
+        float gi_acc[3] = {0.f, 0.f, 0.f};
+        for (int x = 0; x < nj; ++x) {
+            const int j = jr[x];
+            const GRow gj = g_row(base, j, out, scol);
+            float mij = 0.f;
+            for (int b = 0; b < 3; ++b) {
+                if (gj.col[b] < 0) continue;
+                for (int p = 0; p < nu; ++p)
+                    if (ucol[p] == gj.col[b]) mij += gj.val[b] * uval[p];
+            }
+            const float e = mij - (j == i ? 1.f : 0.f);
+            loss += (double)e * (double)e;
+            // dG~[j, b] += coef * e * u_b
+            for (int b = 0; b < 3; ++b) {
+                if (gj.col[b] < 0) continue;
+                float ub = 0.f;
+                for (int p = 0; p < nu; ++p)
+                    if (ucol[p] == gj.col[b]) ub = uval[p];
+                atomicAdd(&dg[(base + j) * 3 + b], coef * e * ub);
+            }
+            // dG~[i, b] += coef * e * (G~ A_hat)_{j, col_b(i)}
+            for (int b = 0; b < 3; ++b) {
+                const int cb = gi.col[b];
+                if (cb < 0) continue;
+                float w = 0.f;
+                for (int s = 0; s < 3; ++s) {
+                    const int cs = gj.col[s];
+                    if (cs < 0) continue;
+                    w += gj.val[s] * ahat(base, cs, cb, scol, sval);
+                }
+                gi_acc[b] += coef * e * w;
+            }
+        }
+        for (int b = 0; b < 3; ++b)
+            if (gi.col[b] >= 0) atomicAdd(&dg[(base + i) * 3 + b], gi_acc[b]);
+    }
+    // per-block loss partial
+    double v = loss;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) partials[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// dL/do from dL/dG~ (thread per row of the listed systems' row range).
+__global__ void k_fsai_dout(int64_t row0, int32_t n, const float *__restrict__ out,
+                            const float *__restrict__ dg, const int32_t *__restrict__ scol,
+                            float *__restrict__ dout) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t r = row0 + i;
+    const float oc = out[r * kOutPad];
+    const float sig = 1.f / (1.f + expf(-oc));
+    float *d = dout + r * kOutPad;
+    d[0] = dg[r * 3 + 0] * sig;
+    d[1] = scol[r * kSlots + kSlotW] >= 0 ? dg[r * 3 + 1] : 0.f;
+    d[2] = 0.f;
+    d[3] = scol[r * kSlots + kSlotS] >= 0 ? dg[r * 3 + 2] : 0.f;
+    d[4] = 0.f;
+}
+
+// ---------------------------------------------------------------------------
+// Backward pass over a list of 16-row tiles; one partial gradient per
+// workgroup (waves added in order through LDS).
+struct alignas(16) WaveLds {   // 8-byte loads of 4 consecutive entries
+    uint16_t fT[16][16];    // [feature][row]
+    uint16_t h1T[64][16];   // [unit][row]
+    uint16_t h2T[64][16];
+    uint16_t d1T[64][16];   // dz1
+    uint16_t d2T[64][16];   // dz2
+    uint16_t d3T[16][16];   // dz3 (outputs padded to 16)
+};
+
+__device__ __forceinline__ bf16x4 lds4(const uint16_t *p) {
+    const uint2 u = *reinterpret_cast<const uint2 *>(p);
+    bf16x4 b;
+    b[0] = (short)(u.x & 0xFFFF);
+    b[1] = (short)(u.x >> 16);
+    b[2] = (short)(u.y & 0xFFFF);
+    b[3] = (short)(u.y >> 16);
+    return b;
+}
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(256) void k_fsai_backward(int32_t ntiles, const int32_t *__restrict__ tiles,
+                                                       const uint16_t *__restrict__ feats,
+                                                       const float *__restrict__ th,
+                                                       const float *__restrict__ dout,
+                                                       float *__restrict__ gpart) {
+    __shared__ WaveLds L[4];
+    __shared__ float acc[kNParams];
+    const int l = threadIdx.x & (kW - 1);
+    const int r = l & 15, q = l >> 4;
+    const int wv = threadIdx.x / kW;
+    WaveLds &S = L[wv];
+    Frags W;
+    load_frags(th, W);
+    // transposed weights for the backward products (A operands)
+    bf16x4 w3t[4];     // W3^T: M-tile t (units), K = outputs
+    bf16x4 w2t[4][4];  // W2^T: M-tile t (in units), k-step s (out units)
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int o = 4 * q + v;
+            w3t[t][v] = (short)(o < kOut ? bf16_bits(th[kOffW3 + o * kHidden + 16 * t + r]) : 0);
+        }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                w2t[t][s][v] = (short)bf16_bits(th[kOffW2 + (16 * s + 4 * q + v) * kHidden + 16 * t + r]);
+    f32x4 gw1[4], gw2[4][4], gw3[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        gw1[t] = zero4();
+        gw3[t] = zero4();
+#pragma unroll
+        for (int s = 0; s < 4; ++s) gw2[t][s] = zero4();
+    }
+    float gb1[4][4], gb2[4][4], gb3[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) gb1[t][v] = gb2[t][v] = 0.f;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) gb3[v] = 0.f;
+
+    const int wave = blockIdx.x * 4 + wv;
+    const int nwaves = gridDim.x * 4;
+    for (int tt = wave; tt < ntiles; tt += nwaves) {
+        const int64_t row = (int64_t)tiles[tt] + r;
+        const bf16x4 fin = load_feats(feats, row);
+        Fwd Y;
+        forward_tile(W, th, fin, Y);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) S.fT[4 * q + v][r] = (uint16_t)fin[v];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                S.h1T[16 * t + 4 * q + v][r] = (uint16_t)Y.h1[t][v];
+                S.h2T[16 * t + 4 * q + v][r] = (uint16_t)Y.h2[t][v];
+            }
+        // dz3 (outputs 4q+v of row r)
+        bf16x4 d3;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int o = 4 * q + v;
+            const float g = o < kOut ? dout[row * kOutPad + o] : 0.f;
+            gb3[v] += g;
+            d3[v] = (short)bf16_bits(g);
+            S.d3T[o][r] = (uint16_t)d3[v];
+        }
+        // dz2 = (W3^T dz3) * (z2 > 0)
+        bf16x4 d2[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const f32x4 c = mfma(w3t[t], d3, zero4());
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float g = Y.z2[t][v] > 0.f ? c[v] : 0.f;
+                gb2[t][v] += g;
+                d2[t][v] = (short)bf16_bits(g);
+                S.d2T[16 * t + 4 * q + v][r] = (uint16_t)d2[t][v];
+            }
+        }
+        // dz1 = (W2^T dz2) * (z1 > 0)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            f32x4 c = zero4();
+#pragma unroll
+            for (int s = 0; s < 4; ++s) c = mfma(w2t[t][s], d2[s], c);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float g = Y.z1[t][v] > 0.f ? c[v] : 0.f;
+                gb1[t][v] += g;
+                S.d1T[16 * t + 4 * q + v][r] = bf16_bits(g);
+            }
+        }
+        wave_sync();
+        // weight gradients: sums over the tile's 16 rows
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const bf16x4 a1 = lds4(&S.d1T[16 * t + r][4 * q]);
+            gw1[t] = mfma(a1, lds4(&S.fT[r][4 * q]), gw1[t]);
+            const bf16x4 a2 = lds4(&S.d2T[16 * t + r][4 * q]);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) gw2[t][s] = mfma(a2, lds4(&S.h1T[16 * s + r][4 * q]), gw2[t][s]);
+            gw3[t] = mfma(lds4(&S.d3T[r][4 * q]), lds4(&S.h2T[16 * t + r][4 * q]), gw3[t]);
+        }
+        wave_sync();
+    }
+    // bias sums: reduce over the 16 rows held by lanes r = 0..15
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int m = 1; m < 16; m <<= 1) {
+                gb1[t][v] += __shfl_xor(gb1[t][v], m, 64);
+                gb2[t][v] += __shfl_xor(gb2[t][v], m, 64);
+            }
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int m = 1; m < 16; m <<= 1) gb3[v] += __shfl_xor(gb3[v], m, 64);
+    // add the four wavefronts' gradients in order
+    for (int p = threadIdx.x; p < kNParams; p += blockDim.x) acc[p] = 0.f;
+    __syncthreads();
+    for (int w = 0; w < 4; ++w) {
+        if (wv == w) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int u = 16 * t + 4 * q + v;  // row of the gradient tile
+                    if (r < kFeat) acc[kOffW1 + u * kFeat + r] += gw1[t][v];
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) acc[kOffW2 + u * kHidden + 16 * s + r] += gw2[t][s][v];
+                    const int o = 4 * q + v;
+                    if (o < kOut) acc[kOffW3 + o * kHidden + 16 * t + r] += gw3[t][v];
+                    if (r == 0) {
+                        acc[kOffB1 + u] += gb1[t][v];
+                        acc[kOffB2 + u] += gb2[t][v];
+                    }
+                }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int o = 4 * q + v;
+                if (r == 0 && o < kOut) acc[kOffB3 + o] += gb3[v];
+            }
+        }
+        __syncthreads();
+    }
+    for (int p = threadIdx.x; p < kNParams; p += blockDim.x)
+        gpart[(int64_t)blockIdx.x * kNParams + p] = acc[p];
+}
+
+// Sum of the workgroup gradients in order; Adam step when t_step > 0, else the
+// gradient is only written to grad_out.
+__global__ void k_fsai_adam(int32_t nparts, const float *__restrict__ gpart, float *__restrict__ theta,
+                            float *__restrict__ m, float *__restrict__ v, float *__restrict__ grad_out,
+                            int32_t t_step, float lr) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= kNParams) return;
+    float g = 0.f;
+    for (int b = 0; b < nparts; ++b) g += gpart[(int64_t)b * kNParams + p];
+    if (grad_out) grad_out[p] = g;
+    if (t_step <= 0) return;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float mm = b1 * m[p] + (1.f - b1) * g;
+    const float vv = b2 * v[p] + (1.f - b2) * g * g;
+    m[p] = mm;
+    v[p] = vv;
+    const float mh = mm / (1.f - powf(b1, (float)t_step));
+    const float vh = vv / (1.f - powf(b2, (float)t_step));
+    theta[p] -= lr * mh / (sqrtf(vh) + 1e-8f);
+}
+
+// Thread per (slice, lane): copy the row's values into its slots.
+__global__ void k_sell_refresh(int32_t m, int32_t ntiles, const int32_t *__restrict__ rp,
+                               const int32_t *__restrict__ sell_off, const double *__restrict__ val,
+                               double *__restrict__ sell_val) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t t = (int32_t)(g / 64), l = (int32_t)(g % 64);
+    if (t >= ntiles) return;
+    const int32_t i = t * 64 + l;
+    if (i >= m) return;
+    const int32_t b = rp[i], len = rp[i + 1] - rp[i];
+    const int32_t w = (sell_off[t + 1] - sell_off[t]) / 64;
+    for (int32_t j = 0; j < len && j < w; ++j) sell_val[(int64_t)sell_off[t] + (int64_t)j * 64 + l] = val[b + j];
+}
+
+__global__ void k_fill_f32(int64_t n, float *__restrict__ p, float v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+}  // namespace
+
+// ---- launch wrappers -------------------------------------------------------
+
+hipError_t fsai_prepare(int32_t n, const int32_t *rp, const int32_t *ci, const double *val,
+                        int32_t *scol, float *sval, double *diag, uint16_t *feats, int32_t *err,
+                        hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fsai_prepare, dim3((n + 255) / 256), dim3(256), 0, s, n, rp, ci, val, scol,
+                       sval, diag, feats, err);
+    return hipGetLastError();
+}
+
+hipError_t fsai_forward_outputs(int32_t ntiles, const int32_t *tiles, int64_t nrows,
+                                const uint16_t *feats, const float *theta, float *out, hipStream_t s) {
+    if (ntiles <= 0) return hipSuccess;
+    const int grid = (ntiles + 3) / 4 < 1024 ? (ntiles + 3) / 4 : 1024;
+    hipLaunchKernelGGL(k_fsai_forward<true>, dim3(grid), dim3(256), 0, s, ntiles, tiles, nrows, feats,
+                       theta, out, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t fsai_forward_factor(int32_t n, const uint16_t *feats, const float *theta,
+                               const int32_t *scol, const double *diag, const int32_t *gpos,
+                               const int32_t *tpos, double *gval, double *gtval, hipStream_t s) {
+    const int32_t ntiles = (n + 15) / 16;
+    if (ntiles <= 0) return hipSuccess;
+    const int grid = (ntiles + 3) / 4 < 2048 ? (ntiles + 3) / 4 : 2048;
+    hipLaunchKernelGGL(k_fsai_forward<false>, dim3(grid), dim3(256), 0, s, ntiles, nullptr, (int64_t)n,
+                       feats, theta, nullptr, scol, diag, gpos, tpos, gval, gtval);
+    return hipGetLastError();
+}
+
+hipError_t fsai_loss(int32_t nsamp, const int32_t *samp_row, const int64_t *samp_base,
+                     const int32_t *samp_n, const float *out, const int32_t *scol, const float *sval,
+                     float *dg, float coef, double *partials, hipStream_t s) {
+    if (nsamp <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fsai_loss, dim3((nsamp + 255) / 256), dim3(256), 0, s, nsamp, samp_row,
+                       samp_base, samp_n, out, scol, sval, dg, coef, partials);
+    return hipGetLastError();
+}
+
+hipError_t fsai_dout(int64_t row0, int32_t n, const float *out, const float *dg, const int32_t *scol,
+                     float *dout, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fsai_dout, dim3((n + 255) / 256), dim3(256), 0, s, row0, n, out, dg, scol, dout);
+    return hipGetLastError();
+}
+
+hipError_t fsai_backward(int32_t ntiles, const int32_t *tiles, const uint16_t *feats, const float *theta,
+                         const float *dout, float *gpart, int32_t grid, hipStream_t s) {
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fsai_backward, dim3(grid), dim3(256), 0, s, ntiles, tiles, feats, theta, dout,
+                       gpart);
+    return hipGetLastError();
+}
+
+hipError_t fsai_adam(int32_t nparts, const float *gpart, float *theta, float *m, float *v,
+                     float *grad_out, int32_t t_step, float lr, hipStream_t s) {
+    hipLaunchKernelGGL(k_fsai_adam, dim3((kNParams + 255) / 256), dim3(256), 0, s, nparts, gpart, theta,
+                       m, v, grad_out, t_step, lr);
+    return hipGetLastError();
+}
+
+hipError_t sell_refresh(int32_t m, int32_t ntiles, const int32_t *rp, const int32_t *sell_off,
+                        const double *val, double *sell_val, hipStream_t s) {
+    if (m <= 0 || ntiles <= 0) return hipSuccess;
+    const int64_t threads = (int64_t)ntiles * 64;
+    hipLaunchKernelGGL(k_sell_refresh, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, m, ntiles,
+                       rp, sell_off, val, sell_val);
+    return hipGetLastError();
+}
+
+hipError_t fill_f32(int64_t n, float *p, float v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t g = (n + 255) / 256;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)g), dim3(256), 0, s, n, p, v);
+    return hipGetLastError();
+}
+
+}  // namespace cgmi

@@ -33,7 +33,7 @@ def test_header_symbols_are_exported(cg):
     L = cg.lib()
     for name in sorted(declared):
         assert hasattr(L, name), f"{name} declared in include/ but not exported"
-    assert set(cg.EXPORTED) <= declared
+    assert set(cg.EXPORTED) | set(cg.EXPORTED_FSAI) == declared
 
 
 def test_default_opts(cg):
@@ -103,3 +103,46 @@ def test_product_path_does_not_reach_the_oracle():
                 text = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in text and "from oracle" not in text, fn
                 assert "liboracle" not in text and "cg_oracle" not in text, fn
+
+
+def test_fsai_entry_points_reject_bad_input(cg):
+    L = cg.lib()
+    rp = np.array([0, 1], np.int32)
+    ci = np.array([0], np.int32)
+    va = np.array([1.0])
+    assert L.cg_set_fsai(None, 1, rp.ctypes.data, ci.ctypes.data, va.ctypes.data) == cg.CG_EINVAL
+    assert L.cg_fsai_setup(None, None) == cg.CG_EINVAL
+    nnz = ctypes.c_int64()
+    assert L.cg_fsai_factor_info(None, ctypes.byref(nnz)) == cg.CG_EINVAL
+    t = ctypes.c_void_p()
+    theta = np.zeros(cg.FSAI_NPARAMS, np.float32)
+    n = np.array([1], np.int32)
+    nz = np.array([1], np.int64)
+    bad_rp = np.array([1, 1], np.int32)       # row_ptr[0] != 0
+    ptr = lambda a: (ctypes.c_void_p * 1)(a.ctypes.data)
+    assert L.cg_fsai_trainer_create(1, n.ctypes.data, nz.ctypes.data, ptr(bad_rp), ptr(ci), ptr(va),
+                                    theta.ctypes.data, ctypes.byref(t)) == cg.CG_EINVAL
+    assert "row_ptr" in cg.last_error()
+    assert L.cg_fsai_trainer_create(0, n.ctypes.data, nz.ctypes.data, ptr(rp), ptr(ci), ptr(va),
+                                    theta.ctypes.data, ctypes.byref(t)) == cg.CG_EINVAL
+    assert L.cg_fsai_train_step(None, 1, None, 1, None, 1e-3, None) == cg.CG_EINVAL
+    L.cg_fsai_trainer_destroy(None)
+
+
+def test_init_params_layout():
+    from paper_2608_09647_amd import fsai
+    th = fsai.init_params(0)
+    assert th.dtype == np.float32 and th.size == 5317
+    # biases are zero, weights within the Glorot limits
+    assert np.all(th[768:832] == 0) and np.all(th[4928:4992] == 0) and np.all(th[5312:] == 0)
+    assert np.abs(th[:768]).max() <= np.sqrt(6 / 76) and np.abs(th[832:4928]).max() <= np.sqrt(6 / 128)
+    assert np.array_equal(th, fsai.init_params(0)) and not np.array_equal(th, fsai.init_params(1))
+
+
+def test_sampling_is_distinct():
+    from paper_2608_09647_amd import fsai
+    rng = np.random.default_rng(0)
+    sys, rows = fsai.sample(rng, [100, 50, 70], 2, 40)
+    assert sys.size == 2 and len(set(sys.tolist())) == 2 and rows.shape == (2, 40)
+    for s, r in zip(sys, rows):
+        assert len(set(r.tolist())) == 40 and r.max() < [100, 50, 70][s]
