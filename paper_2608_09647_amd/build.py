@@ -11,8 +11,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libcgmi.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-HIP_SOURCES = ["kernels_cg.hip", "kernels_fsai.hip"]
-HOST_SOURCES = ["cgmi.cpp", "devmatrix.cpp", "fsai.cpp"]
+HIP_SOURCES = ["kernels_cg.hip", "kernels_fsai.hip", "kernels_batch.hip"]
+HOST_SOURCES = ["cgmi.cpp", "devmatrix.cpp", "fsai.cpp", "batch.cpp"]
 
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
                # keep packed-float32 instructions out of the device code

@@ -30,6 +30,10 @@ EXPORTED_FSAI = ["cg_fsai_setup", "cg_set_fsai", "cg_fsai_factor_info", "cg_fsai
                  "cg_fsai_trainer_create", "cg_fsai_trainer_destroy", "cg_fsai_loss_grad",
                  "cg_fsai_train_step", "cg_fsai_get_params", "cg_fsai_features"]
 FSAI_NPARAMS = 5317
+# include/cgmi_batch.h
+EXPORTED_BATCH = ["cg_batch_create", "cg_batch_destroy", "cg_batch_set_stream", "cg_batch_layout",
+                  "cg_batch_default_sched", "cg_batch_set_sched", "cg_batch_get_sched", "cg_batch_solve"]
+BATCH_MAX_RHS = 16
 
 
 class CgOpts(ctypes.Structure):
@@ -52,6 +56,29 @@ class CgResult(ctypes.Structure):
                 ("rows_gpu", ctypes.c_int32), ("rows_cpu", ctypes.c_int32),
                 ("nnz_gpu", ctypes.c_int64), ("nnz_cpu", ctypes.c_int64),
                 ("fell_back", ctypes.c_int32), ("spmv_kind", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class BatchSched(ctypes.Structure):
+    _fields_ = [("blocks_per_cu", ctypes.c_int32), ("rows_per_thread", ctypes.c_int32),
+                ("team_exponent", ctypes.c_double), ("max_team", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+class BatchResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32),
+                ("rel_res_recur", ctypes.c_double), ("rel_res_true", ctypes.c_double)]
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [("t_kernel", ctypes.c_double), ("grid", ctypes.c_int32),
+                ("teams_multi", ctypes.c_int32), ("max_team", ctypes.c_int32),
+                ("barriers", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -114,6 +141,19 @@ def lib() -> ctypes.CDLL:
         for name in EXPORTED_FSAI:
             if name != "cg_fsai_trainer_destroy":
                 getattr(L, name).restype = ctypes.c_int
+        L.cg_batch_create.argtypes = [i32, _vp, _vp, _vp, _vp, _vp, i32, ctypes.POINTER(_vp)]
+        L.cg_batch_destroy.argtypes = [_vp]
+        L.cg_batch_destroy.restype = None
+        L.cg_batch_set_stream.argtypes = [_vp, _vp]
+        L.cg_batch_layout.argtypes = [_vp, _vp]
+        L.cg_batch_default_sched.argtypes = [ctypes.POINTER(BatchSched)]
+        L.cg_batch_default_sched.restype = None
+        L.cg_batch_set_sched.argtypes = [_vp, ctypes.POINTER(BatchSched)]
+        L.cg_batch_get_sched.argtypes = [_vp, ctypes.POINTER(BatchSched)]
+        L.cg_batch_solve.argtypes = [_vp, _vp, _vp, dbl, i32, _vp, ctypes.POINTER(BatchStats)]
+        for name in ("cg_batch_create", "cg_batch_set_stream", "cg_batch_layout", "cg_batch_set_sched",
+                     "cg_batch_get_sched", "cg_batch_solve"):
+            getattr(L, name).restype = ctypes.c_int
         _LIB = L
     return _LIB
 
@@ -346,3 +386,91 @@ class FsaiTrainer:
         f = np.empty((self.sizes[int(sys)], 12), np.float32)
         _check(lib().cg_fsai_features(self._t, int(sys), f.ctypes.data))
         return f
+
+
+# ---- batched persistent solve (include/cgmi_batch.h) ---------------------------
+def default_batch_sched() -> BatchSched:
+    s = BatchSched()
+    lib().cg_batch_default_sched(ctypes.byref(s))
+    return s
+
+
+class Batch:
+    """Many systems x nrhs right-hand sides solved by one persistent launch.
+    Vectors are CUDA float64 tensors of shape (n_total, nrhs); system k owns
+    rows offsets[k]:offsets[k+1]."""
+
+    def __init__(self, systems, nrhs: int):
+        arrs = [_csr_arrays(A) for A in systems]
+        k = len(arrs)
+        self.nsys, self.nrhs = k, int(nrhs)
+        n = np.array([int(A.n) for A in systems], np.int32)
+        nnz = np.array([int(a[0][-1]) for a in arrs], np.int64)
+        ptrs = [(ctypes.c_void_p * k)(*[a[j].ctypes.data for a in arrs]) for j in range(3)]
+        b = ctypes.c_void_p()
+        _check(lib().cg_batch_create(k, n.ctypes.data, nnz.ctypes.data, ptrs[0], ptrs[1], ptrs[2],
+                                     self.nrhs, ctypes.byref(b)))
+        self._b = b
+        off = np.empty(k + 1, np.int64)
+        _check(lib().cg_batch_layout(self._b, off.ctypes.data))
+        self.offsets = off
+        self.n_total = int(off[-1])
+        self.set_stream(torch.cuda.current_stream())
+
+    def close(self):
+        if getattr(self, "_b", None):
+            lib().cg_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_stream(self, stream):
+        ptr = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream or 0)
+        _check(lib().cg_batch_set_stream(self._b, ctypes.c_void_p(ptr)))
+
+    @property
+    def sched(self) -> BatchSched:
+        s = BatchSched()
+        _check(lib().cg_batch_get_sched(self._b, ctypes.byref(s)))
+        return s
+
+    def set_sched(self, sched: BatchSched | None = None, **kw) -> None:
+        s = self.sched if sched is None else sched
+        for key, v in kw.items():
+            if not hasattr(s, key):
+                raise KeyError(key)
+            setattr(s, key, v)
+        _check(lib().cg_batch_set_sched(self._b, ctypes.byref(s)))
+
+    def solve(self, B, X=None, tol: float = 1e-10, maxit: int = 10000, check: bool = True):
+        """Returns (X, results[nsys, nrhs] as a numpy structured array, stats dict, code)."""
+        shape = (self.n_total * self.nrhs,)
+        if X is None:
+            X = torch.zeros_like(B)
+        for t, name in ((B, "B"), (X, "X")):
+            if t.dim() != 2 or tuple(t.shape) != (self.n_total, self.nrhs):
+                raise ValueError(f"{name} must have shape ({self.n_total}, {self.nrhs})")
+        res = (BatchResult * (self.nsys * self.nrhs))()
+        st = BatchStats()
+        code = lib().cg_batch_solve(self._b, _dev_f64(B.view(-1), shape[0], "B"),
+                                    _dev_f64(X.view(-1), shape[0], "X"), float(tol), int(maxit),
+                                    res, ctypes.byref(st))
+        if check:
+            _check(code, allow=(CG_OK, CG_MAXIT, CG_EBREAKDOWN))
+        out = np.zeros((self.nsys, self.nrhs), dtype=[("status", np.int32), ("iterations", np.int32),
+                                                      ("rel_res_recur", np.float64),
+                                                      ("rel_res_true", np.float64)])
+        flat = out.reshape(-1)
+        for i in range(flat.size):
+            flat[i] = (res[i].status, res[i].iterations, res[i].rel_res_recur, res[i].rel_res_true)
+        return X, out, st.as_dict(), code

@@ -1,0 +1,356 @@
+// batch.cpp -- host side of the batched persistent solve: stacking of the
+// systems, team assignment from the schedule, the cooperative launch and the
+// per-pair results.
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/cgmi_batch.h"
+#include "batch_internal.h"
+#include "cgmi_host.h"
+
+using namespace cgmi;
+
+#define HIP_TRY(expr) CGMI_HIP_TRY(expr)
+
+struct cg_batch {
+    int dev = 0;
+    hipStream_t stream = nullptr;
+    int32_t nsys = 0, nrhs = 0;
+    int64_t n_total = 0, nnz_total = 0;
+    std::vector<int64_t> row_off;   // nsys + 1
+    int cus = 256;
+    cg_batch_sched sched{};
+    // device
+    int32_t *d_rp = nullptr, *d_ci = nullptr;
+    double *d_val = nullptr;
+    double *d_R = nullptr, *d_P = nullptr, *d_Q = nullptr;
+    double *d_part = nullptr;
+    int32_t *d_bar = nullptr, *d_err = nullptr, *d_episodes = nullptr;
+    int32_t *d_wg_sys = nullptr, *d_wg_rank = nullptr, *d_team_first = nullptr, *d_team_size = nullptr;
+    int64_t *d_row_off = nullptr;
+    BatchOutDev *d_out = nullptr;
+    int grid_cap = 0;                // workgroups the buffers are sized for
+    // current team assignment
+    int grid = 0;
+    std::vector<int32_t> team_size;
+};
+
+namespace {
+
+void batch_free(cg_batch *b) {
+    for (void *p : {(void *)b->d_rp, (void *)b->d_ci, (void *)b->d_val, (void *)b->d_R, (void *)b->d_P,
+                    (void *)b->d_Q, (void *)b->d_part, (void *)b->d_bar, (void *)b->d_err,
+                    (void *)b->d_episodes, (void *)b->d_wg_sys, (void *)b->d_wg_rank,
+                    (void *)b->d_team_first, (void *)b->d_team_size, (void *)b->d_row_off,
+                    (void *)b->d_out})
+        (void)hipFree(p);
+    delete b;
+}
+
+int validate_sched(const cg_batch_sched *s) {
+    if (!s) return fail(CG_EINVAL, "schedule is NULL");
+    if (s->blocks_per_cu < 1 || s->blocks_per_cu > 64) return fail(CG_EINVAL, "blocks_per_cu must be in [1, 64]");
+    if (s->rows_per_thread != 1 && s->rows_per_thread != 2) return fail(CG_EINVAL, "rows_per_thread must be 1 or 2");
+    if (!(s->team_exponent >= 0.0 && s->team_exponent <= 3.0))
+        return fail(CG_EINVAL, "team_exponent must be in [0, 3]");
+    if (s->max_team < 0) return fail(CG_EINVAL, "max_team must be >= 0");
+    return CG_OK;
+}
+
+// Team sizes: the grid's workgroups shared in proportion to n_k^exponent,
+// at least one per system and at most one per 16 rows (or max_team).
+int assign_teams(cg_batch *b, const cg_batch_sched &s) {
+    const int occ = batch_blocks_per_cu(s.rows_per_thread);
+    if (occ <= 0) return fail(CG_EDEVICE, "occupancy query of the batched kernel failed");
+    const int resident = occ * b->cus;
+    int grid = std::min(s.blocks_per_cu, occ) * b->cus;
+    grid = std::min(grid, b->grid_cap);
+    if (b->nsys > std::min(resident, b->grid_cap))
+        return fail(CG_EINVAL, "%d systems exceed the %d workgroups one launch can keep resident", b->nsys,
+                    std::min(resident, b->grid_cap));
+    grid = std::max(grid, b->nsys);
+    std::vector<double> wgt(b->nsys);
+    std::vector<int32_t> cap(b->nsys), T(b->nsys, 1);
+    double wsum = 0.0;
+    for (int k = 0; k < b->nsys; ++k) {
+        const int64_t n = b->row_off[k + 1] - b->row_off[k];
+        wgt[k] = std::pow((double)n, s.team_exponent);
+        wsum += wgt[k];
+        int64_t c = std::max<int64_t>(1, n / kBatchRowsPerStep);
+        if (s.max_team > 0) c = std::min<int64_t>(c, s.max_team);
+        cap[k] = (int32_t)std::min<int64_t>(c, grid);
+    }
+    // one workgroup per system, the remaining grid - nsys shared in
+    // proportion to w_k (largest remainder), never above cap_k: sum(T) <= grid
+    const int extra = grid - b->nsys;
+    int used = b->nsys;
+    std::vector<double> want(b->nsys);
+    for (int k = 0; k < b->nsys; ++k) {
+        want[k] = extra * wgt[k] / (wsum > 0 ? wsum : 1.0);
+        const int32_t add = std::min<int32_t>(cap[k] - 1, (int32_t)std::floor(want[k]));
+        T[k] = 1 + std::max<int32_t>(0, add);
+        used += T[k] - 1;
+    }
+    std::vector<int> order(b->nsys);
+    for (int k = 0; k < b->nsys; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return want[x] - (T[x] - 1) > want[y] - (T[y] - 1); });
+    for (int idx = 0; used < grid && idx < b->nsys; ++idx) {
+        const int k = order[idx];
+        if (T[k] < cap[k] && want[k] - (T[k] - 1) > 0.0) {
+            ++T[k];
+            ++used;
+        }
+    }
+    if (used > grid || used > b->grid_cap) return fail(CG_EDEVICE, "team assignment exceeds the grid");
+    std::vector<int32_t> wg_sys(used), wg_rank(used), first(b->nsys);
+    int w = 0;
+    for (int k = 0; k < b->nsys; ++k) {
+        first[k] = w;
+        for (int r = 0; r < T[k]; ++r, ++w) {
+            wg_sys[w] = k;
+            wg_rank[w] = r;
+        }
+    }
+    HIP_TRY(hipMemcpy(b->d_wg_sys, wg_sys.data(), sizeof(int32_t) * used, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(b->d_wg_rank, wg_rank.data(), sizeof(int32_t) * used, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(b->d_team_first, first.data(), sizeof(int32_t) * b->nsys, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(b->d_team_size, T.data(), sizeof(int32_t) * b->nsys, hipMemcpyHostToDevice));
+    b->grid = used;
+    b->team_size = T;
+    b->sched = s;
+    return CG_OK;
+}
+
+}  // namespace
+
+extern "C" void cg_batch_default_sched(cg_batch_sched *s) {
+    if (!s) return;
+    s->blocks_per_cu = 4;
+    s->rows_per_thread = 1;
+    s->team_exponent = 1.0;
+    s->max_team = 0;
+    s->reserved = 0;
+}
+
+extern "C" int cg_batch_create(int32_t nsys, const int32_t *n, const int64_t *nnz,
+                               const int32_t *const *row_ptr, const int32_t *const *col,
+                               const double *const *val, int32_t nrhs, cg_batch **out) {
+    clear_error();
+    if (!out) return fail(CG_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (nsys <= 0) return fail(CG_EINVAL, "nsys must be >= 1");
+    if (nrhs < 1 || nrhs > CG_BATCH_MAX_RHS) return fail(CG_EINVAL, "nrhs must be in [1, %d]", CG_BATCH_MAX_RHS);
+    if (!n || !nnz || !row_ptr || !col || !val) return fail(CG_EINVAL, "NULL argument");
+    int64_t rows = 0, ents = 0;
+    for (int32_t k = 0; k < nsys; ++k) {
+        if (n[k] <= 0) return fail(CG_EINVAL, "system %d is empty", k);
+        const int rc = validate_csr(n[k], nnz[k], row_ptr[k], col[k], val[k]);
+        if (rc) return rc;
+        rows += n[k];
+        ents += nnz[k];
+    }
+    if (rows >= INT32_MAX || ents >= INT32_MAX) return fail(CG_EINVAL, "stacked systems exceed int32 indices");
+    if (rows * (int64_t)nrhs >= ((int64_t)1 << 40)) return fail(CG_EINVAL, "vectors too large");
+    cg_batch *b = new (std::nothrow) cg_batch();
+    if (!b) return fail(CG_ENOMEM, "out of host memory");
+    auto bail = [&](int code) {
+        batch_free(b);
+        return code;
+    };
+    if (hipGetDevice(&b->dev) != hipSuccess) return bail(fail(CG_EDEVICE, "no HIP device"));
+    b->cus = device_cu_count();
+    b->nsys = nsys;
+    b->nrhs = nrhs;
+    b->n_total = rows;
+    b->nnz_total = ents;
+    std::vector<int32_t> rp, ci;
+    std::vector<double> va;
+    try {
+        b->row_off.assign((size_t)nsys + 1, 0);
+        rp.resize((size_t)rows + 1);
+        ci.resize((size_t)ents);
+        va.resize((size_t)ents);
+    } catch (...) {
+        return bail(fail(CG_ENOMEM, "out of host memory"));
+    }
+    int64_t r = 0, z = 0;
+    for (int32_t k = 0; k < nsys; ++k) {
+        b->row_off[k] = r;
+        for (int32_t i = 0; i < n[k]; ++i) rp[r + i] = (int32_t)(z + row_ptr[k][i]);
+        for (int64_t e = 0; e < nnz[k]; ++e) {
+            ci[z + e] = (int32_t)(r + col[k][e]);
+            va[z + e] = val[k][e];
+        }
+        r += n[k];
+        z += nnz[k];
+    }
+    b->row_off[nsys] = r;
+    rp[r] = (int32_t)z;
+    const int occ = std::max(batch_blocks_per_cu(1), batch_blocks_per_cu(2));
+    if (occ <= 0) return bail(fail(CG_EDEVICE, "occupancy query of the batched kernel failed"));
+    b->grid_cap = std::max(occ * b->cus, nsys);
+    const size_t vec = (size_t)rows * nrhs;
+    hipError_t e = dmalloc(&b->d_rp, (size_t)rows + 1);
+    if (e == hipSuccess) e = dmalloc(&b->d_ci, (size_t)ents);
+    if (e == hipSuccess) e = dmalloc(&b->d_val, (size_t)ents);
+    if (e == hipSuccess) e = dmalloc(&b->d_R, vec);
+    if (e == hipSuccess) e = dmalloc(&b->d_P, vec);
+    if (e == hipSuccess) e = dmalloc(&b->d_Q, vec);
+    if (e == hipSuccess) e = dmalloc(&b->d_part, (size_t)b->grid_cap * kBatchSlots * kBatchLanes);
+    if (e == hipSuccess) e = dmalloc(&b->d_bar, (size_t)nsys);
+    if (e == hipSuccess) e = dmalloc(&b->d_err, 1);
+    if (e == hipSuccess) e = dmalloc(&b->d_episodes, (size_t)nsys);
+    if (e == hipSuccess) e = dmalloc(&b->d_wg_sys, (size_t)b->grid_cap);
+    if (e == hipSuccess) e = dmalloc(&b->d_wg_rank, (size_t)b->grid_cap);
+    if (e == hipSuccess) e = dmalloc(&b->d_team_first, (size_t)nsys);
+    if (e == hipSuccess) e = dmalloc(&b->d_team_size, (size_t)nsys);
+    if (e == hipSuccess) e = dmalloc(&b->d_row_off, (size_t)nsys + 1);
+    if (e == hipSuccess) e = dmalloc(&b->d_out, (size_t)nsys * nrhs);
+    if (e != hipSuccess) return bail(fail(CG_ENOMEM, "batch allocation failed: %s", hipGetErrorString(e)));
+    e = hipMemcpy(b->d_rp, rp.data(), sizeof(int32_t) * rp.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && ents) e = hipMemcpy(b->d_ci, ci.data(), sizeof(int32_t) * ci.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && ents) e = hipMemcpy(b->d_val, va.data(), sizeof(double) * va.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_row_off, b->row_off.data(), sizeof(int64_t) * b->row_off.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return bail(fail(CG_EDEVICE, "batch upload failed: %s", hipGetErrorString(e)));
+    cg_batch_sched s;
+    cg_batch_default_sched(&s);
+    const int rc = assign_teams(b, s);
+    if (rc) return bail(rc);
+    *out = b;
+    return CG_OK;
+}
+
+extern "C" void cg_batch_destroy(cg_batch *b) {
+    if (!b) return;
+    (void)hipSetDevice(b->dev);
+    (void)(b->stream ? hipStreamSynchronize(b->stream) : hipDeviceSynchronize());
+    batch_free(b);
+}
+
+extern "C" int cg_batch_set_stream(cg_batch *b, void *hip_stream) {
+    clear_error();
+    if (!b) return fail(CG_EINVAL, "batch is NULL");
+    b->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    return CG_OK;
+}
+
+extern "C" int cg_batch_layout(const cg_batch *b, int64_t *row_offset) {
+    clear_error();
+    if (!b || !row_offset) return fail(CG_EINVAL, "NULL argument");
+    std::memcpy(row_offset, b->row_off.data(), sizeof(int64_t) * b->row_off.size());
+    return CG_OK;
+}
+
+extern "C" int cg_batch_set_sched(cg_batch *b, const cg_batch_sched *s) {
+    clear_error();
+    if (!b) return fail(CG_EINVAL, "batch is NULL");
+    int rc = validate_sched(s);
+    if (rc) return rc;
+    HIP_TRY(hipSetDevice(b->dev));
+    HIP_TRY(b->stream ? hipStreamSynchronize(b->stream) : hipDeviceSynchronize());
+    return assign_teams(b, *s);
+}
+
+extern "C" int cg_batch_get_sched(const cg_batch *b, cg_batch_sched *s) {
+    clear_error();
+    if (!b || !s) return fail(CG_EINVAL, "NULL argument");
+    *s = b->sched;
+    return CG_OK;
+}
+
+extern "C" int cg_batch_solve(cg_batch *b, const double *B, double *X, double tol, int32_t maxit,
+                              cg_batch_result *res, cg_batch_stats *stats) {
+    clear_error();
+    if (!b) return fail(CG_EINVAL, "batch is NULL");
+    if (!B || !X) return fail(CG_EINVAL, "B/X is NULL");
+    if (!(tol >= 0.0)) return fail(CG_EINVAL, "tol must be >= 0");
+    if (maxit < 0) return fail(CG_EINVAL, "maxit must be >= 0");
+    HIP_TRY(hipSetDevice(b->dev));
+    hipStream_t st = b->stream;
+    HIP_TRY(hipMemsetAsync(b->d_bar, 0, sizeof(int32_t) * b->nsys, st));
+    HIP_TRY(hipMemsetAsync(b->d_err, 0, sizeof(int32_t), st));
+    int rate_khz = 0;
+    if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, b->dev) != hipSuccess || rate_khz <= 0)
+        rate_khz = 100000;
+    BatchArgs a{};
+    a.rp = b->d_rp;
+    a.ci = b->d_ci;
+    a.val = b->d_val;
+    a.B = B;
+    a.X = X;
+    a.R = b->d_R;
+    a.P = b->d_P;
+    a.Q = b->d_Q;
+    a.part = b->d_part;
+    a.bar = b->d_bar;
+    a.err = b->d_err;
+    a.wg_sys = b->d_wg_sys;
+    a.wg_rank = b->d_wg_rank;
+    a.team_first = b->d_team_first;
+    a.team_size = b->d_team_size;
+    a.row_off = b->d_row_off;
+    a.out = b->d_out;
+    a.episodes = b->d_episodes;
+    a.nrhs = b->nrhs;
+    a.maxit = maxit;
+    a.tol = tol;
+    a.timeout_ticks = (int64_t)rate_khz * 1000 * 20;   // 20 s for one team wait
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, st));
+    const hipError_t le = launch_batch_cg(a, b->grid, b->sched.rows_per_thread, st);
+    if (le != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return fail(CG_EDEVICE, "persistent launch of %d workgroups failed: %s", b->grid, hipGetErrorString(le));
+    }
+    HIP_TRY(hipEventRecord(e1, st));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    int32_t err = 0;
+    HIP_TRY(hipMemcpy(&err, b->d_err, sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (err) return fail(CG_EDEVICE, "a team barrier timed out; the launch was abandoned");
+    std::vector<BatchOutDev> o((size_t)b->nsys * b->nrhs);
+    std::vector<int32_t> ep(b->nsys);
+    HIP_TRY(hipMemcpy(o.data(), b->d_out, sizeof(BatchOutDev) * o.size(), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(ep.data(), b->d_episodes, sizeof(int32_t) * ep.size(), hipMemcpyDeviceToHost));
+    int rc = CG_OK;
+    for (const BatchOutDev &r : o) {
+        if (r.status == CG_EBREAKDOWN) rc = CG_EBREAKDOWN;
+        else if (r.status == CG_MAXIT && rc == CG_OK) rc = CG_MAXIT;
+    }
+    if (res)
+        for (size_t i = 0; i < o.size(); ++i) {
+            res[i].status = o[i].status;
+            res[i].iterations = o[i].iterations;
+            res[i].rel_res_recur = o[i].rel_res_recur;
+            res[i].rel_res_true = o[i].rel_res_true;
+        }
+    if (stats) {
+        stats->t_kernel = 1e-3 * ms;
+        stats->grid = b->grid;
+        int multi = 0, mx = 0, bar = 0;
+        for (int k = 0; k < b->nsys; ++k) {
+            multi += b->team_size[k] > 1;
+            if (b->team_size[k] > mx) {
+                mx = b->team_size[k];
+                bar = ep[k];
+            }
+        }
+        stats->teams_multi = multi;
+        stats->max_team = mx;
+        stats->barriers = bar;
+    }
+    if (rc == CG_EBREAKDOWN) fail(CG_EBREAKDOWN, "some right-hand side broke down (p^T q <= 0 or not finite)");
+    return rc;
+}
