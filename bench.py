@@ -134,12 +134,13 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="poisson3d_256",
                     choices=["poisson3d_256", "poisson3d_256_split", "poisson2d_64", "random_spd_2m",
-                             "diffusion_1024"])
+                             "diffusion_1024", "batch_256"])
     ap.add_argument("--share", type=float, default=0.5, help="GPU row share for the split config")
     ap.add_argument("--iters", type=int, default=500, help="fixed CG iterations per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--train-steps", type=int, default=2000, help="learned-FSAI training steps")
     ap.add_argument("--train-fields", type=int, default=2000, help="128x128 training fields")
+    ap.add_argument("--batch-iters", type=int, default=30, help="fixed iterations per batched step")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the hot path runs on a single MI355X "
@@ -155,6 +156,8 @@ def main() -> int:
         return bench_mixed(args)
     if args.config == "diffusion_1024":
         return bench_learned(args)
+    if args.config == "batch_256":
+        return bench_batch(args)
     if args.config == "poisson2d_64":
         return bench_small(args)
     if args.config == "poisson3d_256_split":
@@ -431,6 +434,157 @@ def bench_learned(args) -> int:
         line["cpu_baseline"] = cpu_baseline_pcg(prob, theta, out["learned"]["iterations"])
     print(json.dumps(line), flush=True)
     return 0
+
+
+def batch_algorithmic_bytes(n_total: int, nnz_total: int, nrhs: int) -> int:
+    """Per batched iteration: the matrix once (int32 col + float64 val per
+    nonzero, row pointers) and six float64 vector passes per right-hand side
+    and row (p gathered, q written, x and r read and written)."""
+    return 12 * nnz_total + 4 * (n_total + 1) + 8 * 6 * nrhs * n_total
+
+
+def bench_batch(args) -> int:
+    """256 uneven 2-D diffusion systems (sides 32..512) x 16 right-hand sides:
+    fixed-work throughput of the one-launch batched solve (schedule from the
+    autotuner table, or tuned here), against one cg_solve per (system,
+    right-hand side); plus a to-1e-10 comparison on the sub-batch of systems
+    with side <= 64, where every pair's separate solve is timed."""
+    import numpy as np
+    import torch
+    from paper_2608_09647_amd import autotune, cgmi, inputs as I
+
+    t0 = time.perf_counter()
+    probs = I.batch_problem(256, 16, seed=5)
+    systems = [p.A for p in probs]
+    n_total = sum(A.n for A in systems)
+    nnz_total = sum(A.nnz for A in systems)
+    print(f"[bench] batch of {len(systems)} systems, n_total={n_total}, nnz={nnz_total} "
+          f"({time.perf_counter() - t0:.1f}s)", file=sys.stderr, flush=True)
+    B = torch.from_numpy(np.ascontiguousarray(np.concatenate([p.b for p in probs], axis=0))).cuda()
+    X = torch.zeros_like(B)
+    batch = cgmi.Batch(systems, 16)
+    sched = autotune.batch_schedule(batch, systems, B, store=False,
+                                    log=lambda s: print(f"[bench] tune {s}", file=sys.stderr, flush=True))
+    print(f"[bench] schedule {sched}", file=sys.stderr, flush=True)
+    K = args.batch_iters
+    for _ in range(args.warmup):
+        X.zero_()
+        batch.solve(B, X, tol=0.0, maxit=K)
+    torch.cuda.synchronize()
+    t_kernel = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        X.zero_()
+        _, res, st, _ = batch.solve(B, X, tol=0.0, maxit=K)
+        t_kernel.append(st["t_kernel"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    assert np.all(res["iterations"] == K)
+    pairs = len(systems) * 16
+    value = pairs * K * args.steps / elapsed
+    bytes_it = batch_algorithmic_bytes(n_total, nnz_total, 16)
+    achieved = bytes_it * K / float(np.mean(t_kernel)) / 1e9
+    print(f"[bench] batched: {args.steps} x {K} iterations in {elapsed:.3f}s, stats {st}",
+          file=sys.stderr, flush=True)
+    batch.close()
+    del X
+
+    # one solve per launch: sampled systems (by size), K iterations, one RHS
+    order = np.argsort([A.n for A in systems])
+    sample = sorted(set(order[np.linspace(0, len(order) - 1, 9).astype(int)].tolist()))
+    per_n = []
+    for k in sample:
+        A = systems[k]
+        s = cgmi.Solver(A)
+        b1 = torch.from_numpy(np.ascontiguousarray(probs[k].b[:, 0])).cuda()
+        x1 = torch.zeros_like(b1)
+        s.solve(b1, x1, tol=0.0, maxit=K)
+        _, _, ts = _timed_solve(s, b1, torch.zeros_like(b1), 0.0, K, 3)
+        per_n.append((A.n, float(np.median(ts))))
+        s.close()
+    ns, ts = zip(*per_n)
+    est = 16 * float(np.sum(np.interp([A.n for A in systems], ns, ts)))
+    single = {"sampled_systems": [int(k) for k in sample], "seconds_per_solve": dict(
+        (str(int(n)), t) for n, t in per_n), "estimated_seconds_all_pairs": est,
+        "estimated_pair_iterations_per_s": pairs * K / est}
+    print(f"[bench] one solve per launch (estimated from {len(sample)} sizes): {est:.3f}s",
+          file=sys.stderr, flush=True)
+
+    # to tolerance on the small-system sub-batch, every pair's solve timed
+    small = [k for k in range(len(systems)) if probs[k].meta["side"] <= 64]
+    tol_cmp = None
+    if small:
+        sub = [systems[k] for k in small]
+        Bs = torch.from_numpy(np.ascontiguousarray(np.concatenate([probs[k].b for k in small], axis=0))).cuda()
+        bt = cgmi.Batch(sub, 16)
+        autotune.batch_schedule(bt, sub, Bs, store=False)
+        bt.solve(Bs, torch.zeros_like(Bs), tol=1e-10, maxit=200000)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, rs, _, code = bt.solve(Bs, torch.zeros_like(Bs), tol=1e-10, maxit=200000)
+        torch.cuda.synchronize()
+        t_b = time.perf_counter() - t1
+        bt.close()
+        t_sep, its = 0.0, 0
+        for k in small:
+            s = cgmi.Solver(systems[k])
+            for j in range(16):
+                bj = torch.from_numpy(np.ascontiguousarray(probs[k].b[:, j])).cuda()
+                xj = torch.zeros_like(bj)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                _, r1 = s.solve(bj, xj, tol=1e-10, maxit=200000)
+                torch.cuda.synchronize()
+                t_sep += time.perf_counter() - t1
+                its += r1["iterations"]
+            s.close()
+        tol_cmp = {"systems": len(small), "pairs": 16 * len(small), "batched_seconds": t_b,
+                   "separate_seconds": t_sep, "speedup": t_sep / t_b,
+                   "batched_max_iterations": int(rs["iterations"].max()),
+                   "separate_total_iterations": its, "all_converged": bool(np.all(rs["status"] == 0)),
+                   "max_rel_res_true": float(rs["rel_res_true"].max())}
+        print(f"[bench] to 1e-10, sides <= 64: {tol_cmp}", file=sys.stderr, flush=True)
+
+    line = _line("CG iters/s + SpMV GB/s (%HBM peak); time to 1e-10 residual, plain vs learned-PC",
+                 value, "iter/s", args, 1e3 * elapsed / args.steps,
+                 {"workload": "batch_256_diffusion2d_sides_32-512_16rhs_fp64_fixed_work",
+                  "systems": len(systems), "nrhs": 16, "n_total": n_total, "nnz_total": nnz_total,
+                  "iterations_per_step": K, "seed": 5},
+                 value_meaning="(system, right-hand side) CG iterations per second, one persistent launch per step",
+                 schedule=sched, kernel_seconds=float(np.mean(t_kernel)),
+                 one_solve_per_launch=single,
+                 speedup_vs_one_solve_per_launch=est / (elapsed / args.steps),
+                 to_tolerance_small_systems=tol_cmp,
+                 roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": None})
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_batch(systems, probs, K, pairs)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def cpu_baseline_batch(systems, probs, K: int, pairs: int, target_s: float = 12.0) -> dict:
+    """The oracle's CG on one right-hand side of sampled systems for K
+    iterations; the batch's pair-iterations per second estimated from the
+    per-row cost."""
+    import numpy as np
+    import oracle
+    order = np.argsort([A.n for A in systems])
+    picks = order[np.linspace(0, len(order) - 1, 5).astype(int)]
+    secs, row_its, done = 0.0, 0, []
+    rounds = 0
+    while secs < target_s and rounds < 200:   # whole passes over the sampled systems
+        for k in picks:
+            t0 = time.perf_counter()
+            oracle.cg(systems[k], probs[k].b[:, rounds % 16], tol=0.0, maxit=K)
+            secs += time.perf_counter() - t0
+            row_its += systems[k].n * K
+        rounds += 1
+    n_total = sum(A.n for A in systems)
+    est = secs / row_its * n_total * 16 * K     # seconds for every pair, K iterations
+    return {"value": pairs * K / est, "unit": "iter/s", "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": f"{rounds} passes of {K} fixed-work CG iterations over one right-hand side of "
+                      f"systems {list(map(int, picks))} ({secs:.1f} s), scaled by rows to all 256 x 16 pairs"}
 
 
 def cpu_baseline_pcg(prob, theta, iterations: int, target_s: float = 12.0) -> dict:
