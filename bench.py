@@ -217,7 +217,7 @@ def main() -> int:
                    "seed": 2},
         "spmv_gbs": achieved,
         "spmv_us": 1e6 * t_launch,
-        "spmv_kind": {1: "vector_bins", 2: "stream", 3: "sliced"}.get(res["spmv_kind"]),
+        "spmv_kind": {1: "vector_bins", 2: "stream", 3: "sliced", 4: "sliced_dict"}.get(res["spmv_kind"]),
         "rel_res_true": res["rel_res_true"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,

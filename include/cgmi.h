@@ -75,9 +75,14 @@ typedef struct cg_opts {
                               rows, nonzeros loaded flat; used only when every
                               tile fits, else 1), 3 sliced tiles (64-row slices
                               stored slot-major, one lane per row; rows of at
-                              most 64 nonzeros, else 1).  Automatic picks 3
-                              when rows have <= 64 nonzeros and slicing pads by
-                              <= 25%, else 1.                                   */
+                              most 64 nonzeros, else 1), 4 dictionary-sliced
+                              tiles (the sliced layout with a 1-byte index per
+                              slot into a per-slice table of at most 15 column
+                              offsets; rows of at most 8 nonzeros, else 3).
+                              Automatic picks 4 when rows have <= 8 nonzeros
+                              and every slice fits the table, else 3 when rows
+                              have <= 64 nonzeros and slicing pads by <= 25%,
+                              else 1.                                           */
     int32_t reserved;      /* must be 0                                         */
     double refine_delta;   /* mixed precision: a float64 refinement is made
                               when the float32 residual drops by this factor    */
@@ -106,7 +111,8 @@ typedef struct cg_result {
     int32_t fell_back;       /* 1 if a preconditioned / mixed solve fell back to
                                 plain float64 CG                                 */
     int32_t spmv_kind;       /* SpMV tiling used on the GPU rows: 1 vector bins,
-                                2 stream tiles, 3 sliced tiles (0: no GPU rows)   */
+                                2 stream tiles, 3 sliced tiles, 4 dictionary-
+                                sliced tiles (0: no GPU rows)                    */
 } cg_result;
 
 /* Create a solver for the n x n CSR matrix (host arrays, copied).  Rows

@@ -281,7 +281,7 @@ extern "C" int cg_set_opts(cg_handle *h, const cg_opts *o) {
         return fail(CG_EINVAL, "refine_delta must be in (0, 1)");
     if ((o->precision != CG_PREC_FP64 || o->precond != CG_PC_NONE) && !h->gpu_only())
         return fail(CG_EINVAL, "mixed precision and preconditioning need a GPU-only handle");
-    if (o->spmv_kind < 0 || o->spmv_kind > 3) return fail(CG_EINVAL, "unknown spmv_kind %d", o->spmv_kind);
+    if (o->spmv_kind < 0 || o->spmv_kind > 4) return fail(CG_EINVAL, "unknown spmv_kind %d", o->spmv_kind);
     if (o->precision == CG_PREC_MIXED && o->precond != CG_PC_NONE)
         return fail(CG_EINVAL, "the preconditioned solve runs in float64 only");
     h->opts = *o;
@@ -918,7 +918,8 @@ extern "C" int cg_solve(cg_handle *h, const double *b, double *x, double tol, in
     }
     if (res) {
         res->t_solve = now() - t0;
-        res->spmv_kind = h->m == 0 ? 0 : h->A.sched.kind == kTileSliced ? 3 : h->A.sched.kind == kTileStream ? 2 : 1;
+        static const int kind_code[4] = {1, 2, 3, 4};   // kTileVector .. kTileSlicedDict
+        res->spmv_kind = h->m == 0 ? 0 : kind_code[h->A.sched.kind];
         res->rows_gpu = h->m;
         res->rows_cpu = h->n - h->m;
         res->nnz_gpu = h->nnz_gpu;

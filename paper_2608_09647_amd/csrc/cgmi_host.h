@@ -50,11 +50,14 @@ struct DevMatrix {
     double *d_sell_val = nullptr;
     size_t sell_slots = 0;
     float *d_val32 = nullptr, *d_sell_val32 = nullptr;
+    uint32_t *d_sell_idx = nullptr;   // dictionary-sliced layout
+    int32_t *d_sell_dict = nullptr;
     Schedule sched{};
     int grid = 8;
     CsrDev dev() const {
         return CsrDev{m, d_rp, d_ci, d_val, sched.identity ? nullptr : d_rows,
-                      d_sell_off, d_sell_ci, d_sell_val, d_val32, d_sell_val32};
+                      d_sell_off, d_sell_ci, d_sell_val, d_val32, d_sell_val32,
+                      d_sell_idx, d_sell_dict, pad_col_base};
     }
 };
 
@@ -62,8 +65,11 @@ struct DevMatrix {
 // the global ones: rp[0..m] with rp[0] possibly > 0) and upload them.
 int dm_upload(DevMatrix &M, int32_t m, const int32_t *rp, const int32_t *ci, const double *val,
               int32_t pad_col_base);
-// Choose the tiling (kind_opt: cg_opts.spmv_kind), build the row list or the
-// sliced copy, size the grid (0: automatic, a multiple of 8 up to grid_cap).
+// Choose the tiling (kind_opt: cg_opts.spmv_kind; 4 asks for dictionary
+// slices, used when every slice has at most 15 distinct column offsets and
+// rows of at most kSliceMaxWidth entries, else plain slices), build the row
+// list or the sliced copies, size the grid (0: automatic, a multiple of 8 up
+// to grid_cap).
 int dm_schedule(DevMatrix &M, int kind_opt, int grid_opt, int cus, int grid_cap, bool need_f32);
 int dm_ensure_f32(DevMatrix &M);
 void dm_free(DevMatrix &M);

@@ -56,7 +56,15 @@ constexpr int kStreamNnz = kWaveSize * kStreamPerLane;
 // rows stored slot-major (slot j of every row of the slice, then slot j+1,
 // ...), padded to the slice's longest row; slice t starts at sell_off[t].
 constexpr int kSliceMaxWidth = 8;  // widths up to this take the unrolled path
-enum { kTileVector = 0, kTileStream = 1, kTileSliced = 2 };
+// Dictionary-sliced tiles (kind kTileSlicedDict): the sliced layout's values
+// with the columns replaced by 4 bits per slot.  Slice t keeps up to 15
+// distinct column offsets (column - global row) in sell_dict[16t .. 16t+14]
+// (entry 15 is 0); nibble j of sell_idx[64t + l] is the dictionary index of
+// slot j of lane l's row, or kDictPad (padding: gathers the row's own entry,
+// never summed).  Widths up to kSliceMaxWidth (8 nibbles) only.
+constexpr int kDictSize = 16;
+constexpr uint32_t kDictPad = 0xFu;
+enum { kTileVector = 0, kTileStream = 1, kTileSliced = 2, kTileSlicedDict = 3 };
 
 struct Schedule {
     Bin bins[kMaxBins];
@@ -65,7 +73,7 @@ struct Schedule {
     int32_t identity;     // 1: the row list is 0..m-1 (no indirection)
     int32_t huge_first;   // rows longer than kHugeRow: positions in the row list
     int32_t huge_count;
-    int32_t kind;         // kTileVector or kTileStream (identity order only)
+    int32_t kind;         // kTileVector, kTileStream, kTileSliced or kTileSlicedDict
 };
 
 // Rows per group of lanes and per wavefront tile for a lanes-per-row class:
@@ -91,6 +99,9 @@ struct CsrDev {
     const double *sell_val;   //   slot-major values
     const float *val32;       // float32 copies of the values (mixed precision)
     const float *sell_val32;
+    const uint32_t *sell_idx; // dictionary-sliced layout: packed slot bytes
+    const int32_t *sell_dict; //   per-slice column offsets
+    int32_t col_base;         // global index of local row 0
 };
 
 // Partial sums of one reduction: one value per workgroup of the kernel that

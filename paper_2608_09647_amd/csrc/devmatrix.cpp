@@ -20,10 +20,50 @@ void free_sliced(DevMatrix &M) {
     (void)hipFree(M.d_sell_ci);
     (void)hipFree(M.d_sell_val);
     (void)hipFree(M.d_sell_val32);
+    (void)hipFree(M.d_sell_idx);
+    (void)hipFree(M.d_sell_dict);
     M.d_sell_off = M.d_sell_ci = nullptr;
     M.d_sell_val = nullptr;
     M.d_sell_val32 = nullptr;
+    M.d_sell_idx = nullptr;
+    M.d_sell_dict = nullptr;
     M.sell_slots = 0;
+}
+
+// Dictionary of column offsets (column - global row) of each 64-row slice;
+// false if some slice has more than kDictSize - 1 distinct offsets or a row
+// longer than kSliceMaxWidth.  dict: kDictSize entries per slice (unused and
+// entry kDictSize-1 are 0); idx: one word of 8 nibbles per lane and slice.
+bool build_dict(const DevMatrix &M, std::vector<int32_t> &dict, std::vector<uint32_t> &idx) {
+    const int32_t m = M.m, nt = (m + kWaveSize - 1) / kWaveSize;
+    dict.assign((size_t)nt * kDictSize, 0);
+    idx.assign((size_t)nt * kWaveSize, 0);
+    for (int32_t t = 0; t < nt; ++t) {
+        int32_t *d = &dict[(size_t)t * kDictSize];
+        int nd = 0;
+        for (int32_t l = 0; l < kWaveSize; ++l) {
+            const int32_t i = t * kWaveSize + l;
+            const int32_t len = i < m ? M.h_rp[i + 1] - M.h_rp[i] : 0;
+            if (len > kSliceMaxWidth) return false;
+            uint32_t w = 0;
+            for (int j = 0; j < kSliceMaxWidth; ++j) {
+                uint32_t nib = kDictPad;
+                if (j < len) {
+                    const int32_t off = M.h_ci[M.h_rp[i] + j] - (M.pad_col_base + i);
+                    int e = 0;
+                    while (e < nd && d[e] != off) ++e;
+                    if (e == nd) {
+                        if (nd == kDictSize - 1) return false;
+                        d[nd++] = off;
+                    }
+                    nib = (uint32_t)e;
+                }
+                w |= nib << (4 * j);
+            }
+            idx[(size_t)t * kWaveSize + l] = w;
+        }
+    }
+    return true;
 }
 
 // Lanes-per-row classes.  Sliced tiles for rows of at most 64 nonzeros when
@@ -42,7 +82,7 @@ void build_schedule(const DevMatrix &M, int kind_opt, Schedule &S, std::vector<i
     int64_t maxlen = 0;
     for (int32_t i = 0; i < m; ++i) maxlen = std::max<int64_t>(maxlen, len(i));
     const double mean = (double)M.h_rp[m] / (double)m;
-    if (kind_opt == 3 || (kind_opt == 0 && maxlen <= 64)) {
+    if (kind_opt == 4 || kind_opt == 3 || (kind_opt == 0 && maxlen <= 64)) {
         const int32_t nt = (m + kWaveSize - 1) / kWaveSize;
         int64_t slots = 0;
         int maxw = 0;
@@ -53,8 +93,9 @@ void build_schedule(const DevMatrix &M, int kind_opt, Schedule &S, std::vector<i
             slots += w * kWaveSize;
             maxw = std::max<int>(maxw, (int)w);
         }
-        if (maxlen <= 64 && slots < INT32_MAX && (kind_opt == 3 || slots <= M.nnz + M.nnz / 4)) {
-            S.kind = kTileSliced;
+        if (maxlen <= 64 && slots < INT32_MAX && (kind_opt >= 3 || slots <= M.nnz + M.nnz / 4)) {
+            S.kind = (kind_opt == 4 || kind_opt == 0) && maxlen <= kSliceMaxWidth ? kTileSlicedDict
+                                                                                : kTileSliced;
             S.nbins = 1;
             S.bins[0] = Bin{std::max(1, maxw), 0, m, 0};
             S.ntiles = nt;
@@ -222,7 +263,28 @@ int dm_ensure_f32(DevMatrix &M) {
 int dm_schedule(DevMatrix &M, int kind_opt, int grid_opt, int cus, int grid_cap, bool need_f32) {
     std::vector<int32_t> rows;
     build_schedule(M, kind_opt, M.sched, rows);
-    if (M.sched.kind == kTileSliced) {
+    if (M.sched.kind == kTileSlicedDict && !M.d_sell_idx) {
+        std::vector<int32_t> dict;
+        std::vector<uint32_t> idx;
+        bool ok = false;
+        try {
+            ok = build_dict(M, dict, idx);
+        } catch (...) {
+            return fail(CG_ENOMEM, "out of host memory");
+        }
+        if (ok) {
+            hipError_t e = dmalloc(&M.d_sell_dict, dict.size());
+            if (e == hipSuccess) e = dmalloc(&M.d_sell_idx, idx.size());
+            if (e == hipSuccess)
+                e = hipMemcpy(M.d_sell_dict, dict.data(), sizeof(int32_t) * dict.size(), hipMemcpyHostToDevice);
+            if (e == hipSuccess)
+                e = hipMemcpy(M.d_sell_idx, idx.data(), sizeof(uint32_t) * idx.size(), hipMemcpyHostToDevice);
+            if (e != hipSuccess) return fail(CG_ENOMEM, "dictionary layout upload failed: %s", hipGetErrorString(e));
+        } else {
+            M.sched.kind = kTileSliced;   // too many distinct offsets: plain slices
+        }
+    }
+    if (M.sched.kind == kTileSliced || M.sched.kind == kTileSlicedDict) {
         const int rc = build_sliced(M);
         if (rc) return rc;
     }

@@ -419,6 +419,95 @@ __device__ __forceinline__ void spmv_sliced_wave(const CsrDev &A, TileWalk &walk
     }
 }
 
+// Dictionary-sliced tiles: as the sliced tiles, but the column of slot j of
+// lane l is col_base + row + dict[nibble j]: 4 bits per slot instead of a
+// 4-byte column, and no row-pointer loads (padding is a reserved nibble).
+// Lanes hold the 16 dictionary entries of the slice in a register (lane d and
+// its copies d+16, d+32, d+48 hold entry d) and fetch them with a cross-lane
+// permute.  Same row order and rounding as the sliced tiles.
+template <class T>
+struct DictSet {
+    int r0, nrows, off, width;
+    uint32_t idx;
+    int dict;
+    T v[kSliceMaxWidth];
+};
+
+template <class T>
+__device__ __forceinline__ void dict_load(const CsrDev &A, int t, DictSet<T> &S) {
+    const T *__restrict__ svals = sell_vals<T>(A);
+    const int lane = threadIdx.x & (kWave - 1);
+    S.r0 = __builtin_amdgcn_readfirstlane(t * kWave);
+    S.nrows = min(kWave, A.m - S.r0);
+    S.off = A.sell_off[t];
+    S.width = (A.sell_off[t + 1] - S.off) / kWave;
+    S.idx = A.sell_idx[(int64_t)t * kWave + lane];
+    S.dict = A.sell_dict[t * kDictSize + (lane & (kDictSize - 1))];
+#pragma unroll
+    for (int j = 0; j < kSliceMaxWidth; ++j) {
+        const int k = S.off + (j < S.width ? j : 0) * kWave + lane;
+        S.v[j] = svals[k];
+    }
+}
+
+template <int MODE, class T>
+__device__ __forceinline__ void dict_step(const CsrDev &A, const SpmvArgs<T> &a, const DictSet<T> &S,
+                                          int tn, DictSet<T> &N, double &acc0, double &acc1) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int myrow = S.r0 + min(lane, S.nrows - 1);
+    const int gcol = A.col_base + myrow;
+    T pv[kSliceMaxWidth];
+    uint32_t valid = 0;
+#pragma unroll
+    for (int j = 0; j < kSliceMaxWidth; ++j) {
+        const uint32_t b = (S.idx >> (4 * j)) & 0xFu;
+        const int o = __shfl(S.dict, (int)b, kWave);
+        valid |= b == kDictPad ? 0u : (1u << j);
+        pv[j] = a.p[gcol + o];
+    }
+    T pown = T(0), bv = T(0);
+    if (MODE == kSpmvDot) pown = a.p_own[myrow];
+    if (MODE == kSpmvResidual) bv = a.b[myrow];
+    dict_load<T>(A, tn, N);
+    T s = T(0);
+    {
+#pragma clang fp contract(off)
+#pragma unroll
+        for (int j = 0; j < kSliceMaxWidth; ++j)
+            if (valid & (1u << j)) s = s + S.v[j] * pv[j];  // rounded product, then the sum
+    }
+    if (lane < S.nrows) {
+        if (MODE == kSpmvResidual) {
+            const T rv = bv - s;
+            a.q[myrow] = rv;
+            a.p_dst[myrow] = rv;
+            acc0 = fma((double)rv, (double)rv, acc0);
+            acc1 = fma((double)bv, (double)bv, acc1);
+        } else {
+            a.q[myrow] = s;
+            if (MODE == kSpmvDot) acc0 = fma((double)pown, (double)s, acc0);
+        }
+    }
+}
+
+template <int MODE, class T>
+__device__ __forceinline__ void spmv_dict_wave(const CsrDev &A, TileWalk &walk, const SpmvArgs<T> &a,
+                                               double &acc0, double &acc1) {
+    int t = walk.next();
+    if (t < 0) return;
+    DictSet<T> S0, S1;
+    dict_load<T>(A, t, S0);
+    for (;;) {
+        const int t1 = walk.next();
+        dict_step<MODE, T>(A, a, S0, t1 >= 0 ? t1 : t, S1, acc0, acc1);
+        if (t1 < 0) break;
+        const int t2 = walk.next();
+        dict_step<MODE, T>(A, a, S1, t2 >= 0 ? t2 : t1, S0, acc0, acc1);
+        if (t2 < 0) break;
+        t = t2;
+    }
+}
+
 // A row longer than kHugeRow: all threads of the workgroup on it.
 template <int MODE, class T>
 __device__ __forceinline__ void spmv_row_wg(const CsrDev &A, int pos, bool identity,
@@ -437,7 +526,8 @@ __device__ __forceinline__ void spmv_row_wg(const CsrDev &A, int pos, bool ident
 
 // TILE > 0: one bin of TILE lanes per row in natural row order;
 // TILE == 0: binned rows (any order); TILE == -1: stream tiles (float64 only);
-// TILE == -2: sliced tiles of width <= kSliceMaxWidth; -3: wider slices.
+// TILE == -2: sliced tiles of width <= kSliceMaxWidth; -3: wider slices;
+// TILE == -4: dictionary-sliced tiles.
 template <int MODE, int TILE, class T>
 __global__ __launch_bounds__(kBlock) void k_spmv(int32_t m, const int32_t *__restrict__ rp,
                                                  const int32_t *__restrict__ ci,
@@ -445,11 +535,14 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int32_t m, const int32_t *__res
                                                  const int32_t *__restrict__ rows,
                                                  const int32_t *__restrict__ sell_off,
                                                  const int32_t *__restrict__ sell_ci,
-                                                 const T *__restrict__ sell_val, Schedule S,
-                                                 SpmvArgs<T> a, double *__restrict__ out,
+                                                 const T *__restrict__ sell_val,
+                                                 const uint32_t *__restrict__ sell_idx,
+                                                 const int32_t *__restrict__ sell_dict, int32_t col_base,
+                                                 Schedule S, SpmvArgs<T> a, double *__restrict__ out,
                                                  Partials in0, Partials in1,
                                                  DevState *__restrict__ st, int flags) {
-    CsrDev A{m, rp, ci, nullptr, rows, sell_off, sell_ci, nullptr, nullptr, nullptr};
+    CsrDev A{m, rp, ci, nullptr, rows, sell_off, sell_ci, nullptr, nullptr, nullptr,
+             sell_idx, sell_dict, col_base};
     if constexpr (sizeof(T) == 8) {
         A.val = reinterpret_cast<const double *>(val);
         A.sell_val = reinterpret_cast<const double *>(sell_val);
@@ -482,6 +575,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int32_t m, const int32_t *__res
     TileWalk walk(S.ntiles);
     if constexpr (TILE == -2 || TILE == -3) {
         spmv_sliced_wave<MODE, T>(A, walk, a, TILE == -3, acc0, acc1);
+    } else if constexpr (TILE == -4) {
+        spmv_dict_wave<MODE, T>(A, walk, a, acc0, acc1);
     } else if constexpr (TILE == -1) {
         if constexpr (sizeof(T) == 8) {
             double *lds = s_prod + (threadIdx.x / kWave) * kStreamNnz;
@@ -908,7 +1003,8 @@ template <int MODE, class T>
 void launch_spmv_mode(const CsrDev &A, const Schedule &S, int grid, const SpmvArgs<T> &a,
                       double *out, Partials in0, Partials in1, DevState *st, int flags,
                       hipStream_t s) {
-    const int L = S.kind == kTileSliced ? (S.bins[0].lanes <= kSliceMaxWidth ? -2 : -3)
+    const int L = S.kind == kTileSlicedDict ? -4
+                  : S.kind == kTileSliced ? (S.bins[0].lanes <= kSliceMaxWidth ? -2 : -3)
                   : S.kind == kTileStream ? -1
                   : (S.identity && S.nbins == 1 && S.huge_count == 0) ? S.bins[0].lanes : 0;
     const T *val, *sval;
@@ -921,7 +1017,8 @@ void launch_spmv_mode(const CsrDev &A, const Schedule &S, int grid, const SpmvAr
     }
 #define CGMI_SPMV(FL)                                                                             \
     hipLaunchKernelGGL((k_spmv<MODE, FL, T>), dim3(grid), dim3(kBlock), 0, s, A.m, A.rp, A.ci, val, \
-                       A.rows, A.sell_off, A.sell_ci, sval, S, a, out, in0, in1, st, flags)
+                       A.rows, A.sell_off, A.sell_ci, sval, A.sell_idx, A.sell_dict, A.col_base, S, a,  \
+                       out, in0, in1, st, flags)
     switch (L) {
         case 1: CGMI_SPMV(1); break;
         case 2: CGMI_SPMV(2); break;
@@ -933,6 +1030,7 @@ void launch_spmv_mode(const CsrDev &A, const Schedule &S, int grid, const SpmvAr
         case -1: CGMI_SPMV(-1); break;
         case -2: CGMI_SPMV(-2); break;
         case -3: CGMI_SPMV(-3); break;
+        case -4: CGMI_SPMV(-4); break;
         default: CGMI_SPMV(0); break;
     }
 #undef CGMI_SPMV

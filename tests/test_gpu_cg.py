@@ -81,7 +81,13 @@ def test_spmv_matches_oracle(cg, name):
     np.testing.assert_allclose(y, ref, rtol=0, atol=1e-12 * (np.abs(ref).max() + 1))
 
 
-@pytest.mark.parametrize("kind", [1, 2, 3])
+def used_kind(s, n):
+    """The tiling the solver runs (reported by a solve that stops at once)."""
+    _, res = s.solve(dev(np.ones(n)), tol=0.0, maxit=0, check=False)
+    return res["spmv_kind"]
+
+
+@pytest.mark.parametrize("kind", [1, 2, 3, 4])
 @pytest.mark.parametrize("name", ["poisson2d_64", "poisson3d_ragged", "diffusion_100", "tiny_7",
                                   "random_spd_30k", "tiny_1"])
 def test_spmv_tilings_match_oracle(cg, name, kind):
@@ -91,11 +97,41 @@ def test_spmv_tilings_match_oracle(cg, name, kind):
     with cg.Solver(A) as s:
         s.set_opts(spmv_kind=kind)
         y = host(s.spmv(dev(x)))
+        used = used_kind(s, A.n)
     assert spmv_err(A, x, y, ref) <= 1e-12
     if kind in (2, 3) and s_kind_used(A, kind):
-        # stream and sliced tiles sum each row left to right with rounded
-        # products: the oracle's own order, so the bits agree
+        assert used == kind
+    if kind == 4:
+        assert used == (4 if np.diff(A.row_ptr).max() <= 8 else 3 if np.diff(A.row_ptr).max() <= 64 else 1)
+    if used in (2, 3, 4):
+        # stream, sliced and dictionary-sliced tiles sum each row left to
+        # right with rounded products: the oracle's own order, so the bits agree
         assert np.array_equal(y, ref)
+
+
+def test_dictionary_slices_fall_back_on_many_offsets(cg):
+    """Rows of <= 8 entries whose 64-row slices use more than 15 distinct
+    column offsets take plain slices."""
+    n = 4096
+    rng = np.random.default_rng(2)
+    rows, cols = [np.arange(n)], [np.arange(n)]
+    for _ in range(2):          # two random perfect matchings: rows of <= 3 entries
+        perm = rng.permutation(n)
+        a, b = perm[0::2], perm[1::2]
+        rows += [a, b]
+        cols += [b, a]
+    r, cidx = np.concatenate(rows), np.concatenate(cols)
+    v = np.where(r == cidx, 8.0, -0.5)
+    S = sp.csr_matrix((v, (r, cidx)), shape=(n, n))
+    S.sum_duplicates()
+    S.sort_indices()
+    assert np.diff(S.indptr).max() <= 8
+    A = I.CSR(n, S.indptr.astype(np.int32), S.indices.astype(np.int32), S.data)
+    x = rng.uniform(-1, 1, n)
+    with cg.Solver(A) as s:
+        s.set_opts(spmv_kind=4)
+        assert used_kind(s, n) == 3
+        assert np.array_equal(host(s.spmv(dev(x))), oracle.spmv(A, x))
 
 
 def s_kind_used(A, kind):
@@ -294,7 +330,7 @@ def test_full_size_poisson3d_256(cg):
 
 # ----------------------------------------------------------------------------- mixed precision
 
-@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("kind", [0, 1, 3, 4])
 @pytest.mark.parametrize("name", ["poisson3d_ragged", "random_spd_30k", "diffusion_100"])
 def test_spmv_f32_matches_oracle(cg, name, kind):
     A = SPMV_CASES[name]()
@@ -303,11 +339,12 @@ def test_spmv_f32_matches_oracle(cg, name, kind):
     with cg.Solver(A) as s:
         s.set_opts(precision=cg.PREC_MIXED, spmv_kind=kind)
         y = host(s.spmv_f32(torch.from_numpy(x32).cuda()))
+        used = used_kind(s, A.n)
     absA = sp.csr_matrix((np.abs(A.val.astype(np.float32)), A.col, A.row_ptr), shape=(A.n, A.n))
     scale = absA @ np.abs(x32).astype(np.float64) + 1e-30
     L = int(np.diff(A.row_ptr).max())
     assert np.max(np.abs(y.astype(np.float64) - ref) / scale) <= 2 * L * 2.0 ** -24
-    if kind == 0 and s_kind_used(A, 3):
+    if used in (3, 4):
         # sliced rows are summed in float32 left to right: the oracle's order
         assert np.array_equal(y, ref)
 
