@@ -141,6 +141,8 @@ def main() -> int:
     ap.add_argument("--train-steps", type=int, default=2000, help="learned-FSAI training steps")
     ap.add_argument("--train-fields", type=int, default=2000, help="128x128 training fields")
     ap.add_argument("--batch-iters", type=int, default=30, help="fixed iterations per batched step")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="only the timed path of the workload (no comparison solves), for profilers")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the hot path runs on a single MI355X "
@@ -408,6 +410,10 @@ def bench_learned(args) -> int:
     torch.cuda.synchronize()
     cold_setup = time.perf_counter() - t1
     s.close()
+    if args.profile_run:
+        run("learned", learned, args.steps, args.warmup, cgmi.PC_FSAI)
+        print(json.dumps({"profile_run": "diffusion_1024", "learned": out["learned"]}), flush=True)
+        return 0
     run("plain", plain, args.steps, args.warmup)
     run("learned", learned, args.steps, args.warmup, cgmi.PC_FSAI)
     out["learned"]["cold_setup_seconds"] = cold_setup
@@ -488,6 +494,10 @@ def bench_batch(args) -> int:
           file=sys.stderr, flush=True)
     batch.close()
     del X
+    if args.profile_run:
+        print(json.dumps({"profile_run": "batch_256", "pair_iterations_per_s": value,
+                          "kernel_seconds": float(np.mean(t_kernel)), "stats": st}), flush=True)
+        return 0
 
     # one solve per launch: sampled systems (by size), K iterations, one RHS
     order = np.argsort([A.n for A in systems])
