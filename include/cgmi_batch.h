@@ -19,8 +19,9 @@
  * right-hand sides fastest, so the nrhs values of one row are contiguous.
  *
  * Conventions as in cgmi.h: host CSR arrays are copied by cg_batch_create;
- * B and X are device pointers (float64, n_total x nrhs); X holds the initial
- * guess on entry and the solution on return.  A stream set with
+ * B and X are device pointers (float64, n_total x nrhs, 16-byte aligned when
+ * two right-hand sides per lane are used); X holds the initial guess on entry
+ * and the solution on return.  A stream set with
  * cg_batch_set_stream is used for every launch; cg_batch_solve blocks.
  */
 #ifndef CGMI_BATCH_H
@@ -44,7 +45,9 @@ typedef struct cg_batch_sched {
     int32_t rows_per_thread;/* rows a thread advances per step: 1 or 2 */
     double team_exponent;   /* team size of system k proportional to n_k^team_exponent */
     int32_t max_team;       /* upper bound on a team's workgroups (0: none) */
-    int32_t reserved;
+    int32_t rhs_per_lane;   /* right-hand sides per lane: 1, or 2 (16-byte
+                               loads; needs an even nrhs, else 1 is used);
+                               0: 2 when nrhs is even */
 } cg_batch_sched;
 
 /* Per (system, right-hand side) outcome, index k * nrhs + j. */

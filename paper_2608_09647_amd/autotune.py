@@ -73,7 +73,8 @@ def lookup(signature: str, path: str = TABLE):
 
 # ----------------------------------------------------------------------------- batch
 
-BATCH_SPACE = {"blocks_per_cu": [2, 4, 8], "rows_per_thread": [1, 2], "team_exponent": [0.75, 1.0, 1.25]}
+BATCH_SPACE = {"blocks_per_cu": [4, 8], "rows_per_thread": [1, 2], "team_exponent": [1.0, 1.25],
+               "rhs_per_lane": [1, 2]}
 
 
 def batch_candidates(space: dict | None = None) -> list:

@@ -64,10 +64,10 @@ class CgResult(ctypes.Structure):
 class BatchSched(ctypes.Structure):
     _fields_ = [("blocks_per_cu", ctypes.c_int32), ("rows_per_thread", ctypes.c_int32),
                 ("team_exponent", ctypes.c_double), ("max_team", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("rhs_per_lane", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class BatchResult(ctypes.Structure):

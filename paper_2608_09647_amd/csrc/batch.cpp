@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -58,13 +59,18 @@ int validate_sched(const cg_batch_sched *s) {
     if (!(s->team_exponent >= 0.0 && s->team_exponent <= 3.0))
         return fail(CG_EINVAL, "team_exponent must be in [0, 3]");
     if (s->max_team < 0) return fail(CG_EINVAL, "max_team must be >= 0");
+    if (s->rhs_per_lane < 0 || s->rhs_per_lane > 2) return fail(CG_EINVAL, "rhs_per_lane must be 0, 1 or 2");
     return CG_OK;
 }
 
 // Team sizes: the grid's workgroups shared in proportion to n_k^exponent,
 // at least one per system and at most one per 16 rows (or max_team).
+int lanes_variant(const cg_batch *b, const cg_batch_sched &s) {
+    return (s.rhs_per_lane == 1 || (b->nrhs & 1)) ? 1 : 2;
+}
+
 int assign_teams(cg_batch *b, const cg_batch_sched &s) {
-    const int occ = batch_blocks_per_cu(s.rows_per_thread);
+    const int occ = batch_blocks_per_cu(s.rows_per_thread, lanes_variant(b, s));
     if (occ <= 0) return fail(CG_EDEVICE, "occupancy query of the batched kernel failed");
     const int resident = occ * b->cus;
     int grid = std::min(s.blocks_per_cu, occ) * b->cus;
@@ -134,7 +140,7 @@ extern "C" void cg_batch_default_sched(cg_batch_sched *s) {
     s->rows_per_thread = 1;
     s->team_exponent = 1.0;
     s->max_team = 0;
-    s->reserved = 0;
+    s->rhs_per_lane = 0;
 }
 
 extern "C" int cg_batch_create(int32_t nsys, const int32_t *n, const int64_t *nnz,
@@ -191,7 +197,9 @@ extern "C" int cg_batch_create(int32_t nsys, const int32_t *n, const int64_t *nn
     }
     b->row_off[nsys] = r;
     rp[r] = (int32_t)z;
-    const int occ = std::max(batch_blocks_per_cu(1), batch_blocks_per_cu(2));
+    int occ = 0;
+    for (int u = 1; u <= 2; ++u)
+        for (int v = 1; v <= 2; ++v) occ = std::max(occ, batch_blocks_per_cu(u, v));
     if (occ <= 0) return bail(fail(CG_EDEVICE, "occupancy query of the batched kernel failed"));
     b->grid_cap = std::max(occ * b->cus, nsys);
     const size_t vec = (size_t)rows * nrhs;
@@ -305,7 +313,18 @@ extern "C" int cg_batch_solve(cg_batch *b, const double *B, double *X, double to
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     HIP_TRY(hipEventRecord(e0, st));
-    const hipError_t le = launch_batch_cg(a, b->grid, b->sched.rows_per_thread, st);
+    int V = lanes_variant(b, b->sched);
+    if (V == 2 && ((reinterpret_cast<uintptr_t>(B) | reinterpret_cast<uintptr_t>(X)) & 15)) {
+        // unaligned vectors: one right-hand side per lane, if that variant
+        // keeps the grid resident
+        if (batch_blocks_per_cu(b->sched.rows_per_thread, 1) * b->cus < b->grid) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return fail(CG_EINVAL, "B and X must be 16-byte aligned for this schedule");
+        }
+        V = 1;
+    }
+    const hipError_t le = launch_batch_cg(a, b->grid, b->sched.rows_per_thread, V, st);
     if (le != hipSuccess) {
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);

@@ -41,9 +41,12 @@ struct BatchArgs {
     int64_t timeout_ticks;      // wall-clock ticks a team wait may take
 };
 
-// Occupancy of the persistent kernel (workgroups per compute unit).
-int batch_blocks_per_cu(int rows_per_thread);
+// Occupancy of the persistent kernel (workgroups per compute unit) for a
+// variant: rows a thread advances per step (1, 2), right-hand sides per lane
+// (1; 2 needs an even nrhs and 16-byte aligned vectors).
+int batch_blocks_per_cu(int rows_per_thread, int rhs_per_lane);
 // Cooperative launch of the persistent kernel over `grid` workgroups.
-hipError_t launch_batch_cg(const BatchArgs &a, int grid, int rows_per_thread, hipStream_t s);
+hipError_t launch_batch_cg(const BatchArgs &a, int grid, int rows_per_thread, int rhs_per_lane,
+                           hipStream_t s);
 
 }  // namespace cgmi

@@ -13,10 +13,11 @@
 //   C: stop test and beta = r^T r / rho (team sum), p = r + beta p.
 // Every workgroup of a team sums the team's partials itself in a fixed order,
 // so all of them take identical decisions (and results are reproducible for
-// a fixed schedule).  A barrier is a counter in device memory: each
-// workgroup's waves make their stores visible at device scope (release
-// fence), one thread adds 1 and waits until the team's count is reached,
-// then the waves invalidate stale cache lines (acquire fence).  A wait is
+// a fixed schedule).  A barrier is a counter in device memory: each wave
+// waits until its stores have reached the L2, then one thread per workgroup
+// writes the L2 back (device-scope release fence), adds 1 and waits until the
+// team's count is reached, and invalidates stale cache lines (device-scope
+// acquire fence) before the workgroup reads what the team wrote.  A wait is
 // bounded by a wall-clock limit; on expiry the error flag ends every team.
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -44,13 +45,23 @@ struct Shared {
     int ok;
 };
 
-// Partial sum over the workgroup for each right-hand side j (lanes with the
-// same j are 16 apart), stored at dst[0..15] by threads 0..15.
-__device__ __forceinline__ void wg_partial(double v, double *dst, Shared &S) {
-    v += __shfl_xor(v, 16, 64);
-    v += __shfl_xor(v, 32, 64);
+// Partial sum over the workgroup for each right-hand side: a lane holds V
+// consecutive right-hand sides j0 .. j0+V-1 (acc[v] for j0 + v); lanes with
+// the same j0 are 16/V apart.  Stored at dst[0..15] by threads 0..15.
+template <int V>
+__device__ __forceinline__ void wg_partial(const double (&acc)[V], double *dst, Shared &S) {
+    constexpr int LPR = kL / V;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (lane < kL) S.red[wv][lane] = v;
+    double v[V];
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+        v[q] = acc[q];
+#pragma unroll
+        for (int o = LPR; o < 64; o <<= 1) v[q] += __shfl_xor(v[q], o, 64);
+    }
+    if (lane < LPR)
+#pragma unroll
+        for (int q = 0; q < V; ++q) S.red[wv][lane * V + q] = v[q];
     __syncthreads();
     if (threadIdx.x < kL) {
         double s = S.red[0][threadIdx.x];
@@ -86,10 +97,13 @@ __device__ __forceinline__ bool team_sync(const BatchArgs &a, int sys, int T, in
         __syncthreads();
         return true;
     }
-    __threadfence();
+    // every wave's stores have reached the L2 before the barrier; one thread
+    // then writes the L2 back (release) for the whole workgroup
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
         int ok = 1;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __hip_atomic_fetch_add(&a.bar[sys], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const int target = episode * T;
         const uint64_t t0 = wall_clock64();
@@ -105,10 +119,12 @@ __device__ __forceinline__ bool team_sync(const BatchArgs &a, int sys, int T, in
             }
             __builtin_amdgcn_s_sleep(2);
         }
+        // acquire: stale lines of this compute unit's caches are dropped
+        // before any wave of the workgroup reads what the team wrote
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         S.ok = ok;
     }
     __syncthreads();
-    __threadfence();
     return S.ok != 0;
 }
 
@@ -116,19 +132,75 @@ __device__ __forceinline__ bool stop_test(double rr, double bb, double tol) {
     return sqrt(rr) < tol * sqrt(bb) || rr == 0.0;
 }
 
-// sum_k val[k] * v[col[k] * nr + j] for one row, in CSR order, each product
-// and sum rounded separately (as the oracle's SpMV).
-__device__ __forceinline__ double row_dot(const BatchArgs &a, int64_t row, const double *__restrict__ v,
-                                          int nr, int j) {
-#pragma clang fp contract(off)
-    const int k0 = a.rp[row], k1 = a.rp[row + 1];
-    double s = 0.0;
-    for (int k = k0; k < k1; ++k) s += a.val[k] * v[(int64_t)a.ci[k] * nr + j];
-    return s;
+// V consecutive float64 values at p[idx] (16-byte aligned when V = 2).
+template <int V>
+__device__ __forceinline__ void ldv(const double *__restrict__ p, int64_t idx, double (&o)[V]) {
+    if constexpr (V == 2) {
+        const double2 t = *reinterpret_cast<const double2 *>(p + idx);
+        o[0] = t.x;
+        o[1] = t.y;
+    } else {
+        o[0] = p[idx];
+    }
+}
+template <int V>
+__device__ __forceinline__ void stv(double *__restrict__ p, int64_t idx, const double (&v)[V]) {
+    if constexpr (V == 2) {
+        *reinterpret_cast<double2 *>(p + idx) = double2{v[0], v[1]};
+    } else {
+        p[idx] = v[0];
+    }
 }
 
-template <int U>
+// sum_k val[k] * v[col[k] * nr + j0 + q] for one row and the lane's V
+// right-hand sides, in CSR order, each product and sum rounded separately (as
+// the oracle's SpMV).  Rows of up to kShort entries load all their columns
+// and values first (clamped indices, all independent), then issue all
+// gathers, so a row costs two memory round trips instead of one per entry;
+// longer rows take a plain loop.
+constexpr int kShort = 8;
+
+template <int V>
+__device__ __forceinline__ void row_dot(const BatchArgs &a, int64_t row, const double *__restrict__ v,
+                                        int nr, int j0, double (&s)[V]) {
+#pragma clang fp contract(off)
+    const int k0 = a.rp[row], k1 = a.rp[row + 1];
+    const int len = k1 - k0;
+#pragma unroll
+    for (int q = 0; q < V; ++q) s[q] = 0.0;
+    if (len <= 0) return;
+    if (len <= kShort) {
+        int c[kShort];
+        double w[kShort], pv[kShort][V];
+#pragma unroll
+        for (int e = 0; e < kShort; ++e) {
+            const int k = k0 + (e < len ? e : 0);
+            c[e] = a.ci[k];
+            w[e] = a.val[k];
+        }
+#pragma unroll
+        for (int e = 0; e < kShort; ++e) ldv<V>(v, (int64_t)c[e] * nr + j0, pv[e]);
+#pragma unroll
+        for (int e = 0; e < kShort; ++e)
+            if (e < len)
+#pragma unroll
+                for (int q = 0; q < V; ++q) s[q] += w[e] * pv[e][q];
+        return;
+    }
+    for (int k = k0; k < k1; ++k) {
+        double pv[V];
+        ldv<V>(v, (int64_t)a.ci[k] * nr + j0, pv);
+#pragma unroll
+        for (int q = 0; q < V; ++q) s[q] += a.val[k] * pv[q];
+    }
+}
+
+// U: rows a thread advances per step; V: right-hand sides per lane (2 needs
+// an even nrhs and 16-byte aligned vectors).
+template <int U, int V>
 __global__ __launch_bounds__(kT) void k_batch_cg(BatchArgs a) {
+    constexpr int LPR = kL / V;          // lanes per row
+    constexpr int RS = kT / LPR;         // rows per workgroup step
     __shared__ Shared S;
     const int w = blockIdx.x;
     const int sys = a.wg_sys[w];
@@ -137,31 +209,38 @@ __global__ __launch_bounds__(kT) void k_batch_cg(BatchArgs a) {
     const int64_t off = a.row_off[sys], n = a.row_off[sys + 1] - off;
     const int64_t lo = off + n * rank / T, hi = off + n * (rank + 1) / T;
     const int nr = a.nrhs;
-    const int j = threadIdx.x & (kL - 1), rsub = threadIdx.x >> 4;
-    const bool lane_on = j < nr;
+    const int j0 = (threadIdx.x % LPR) * V, rsub = threadIdx.x / LPR;
+    const bool lane_on = j0 < nr;
     double *mypart = a.part + (int64_t)w * kBatchSlots * kL;
     int episode = 0;
 
     // setup: r = b - A x, p = r; partial r^T r and b^T b
     {
-        double arr = 0.0, abb = 0.0;
+        double arr[V], abb[V];
+#pragma unroll
+        for (int q = 0; q < V; ++q) arr[q] = abb[q] = 0.0;
         if (lane_on)
-            for (int64_t r0 = lo; r0 < hi; r0 += kRS * U)
+            for (int64_t r0 = lo; r0 < hi; r0 += RS * U)
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const int64_t row = r0 + u * kRS + rsub;
+                    const int64_t row = r0 + u * RS + rsub;
                     if (row < hi) {
-                        const double s = row_dot(a, row, a.X, nr, j);
-                        const int64_t idx = row * nr + j;
-                        const double bv = a.B[idx], rv = bv - s;
-                        a.R[idx] = rv;
-                        a.P[idx] = rv;
-                        arr = fma(rv, rv, arr);
-                        abb = fma(bv, bv, abb);
+                        double s[V], bv[V], rv[V];
+                        row_dot<V>(a, row, a.X, nr, j0, s);
+                        const int64_t idx = row * nr + j0;
+                        ldv<V>(a.B, idx, bv);
+#pragma unroll
+                        for (int q = 0; q < V; ++q) {
+                            rv[q] = bv[q] - s[q];
+                            arr[q] = fma(rv[q], rv[q], arr[q]);
+                            abb[q] = fma(bv[q], bv[q], abb[q]);
+                        }
+                        stv<V>(a.R, idx, rv);
+                        stv<V>(a.P, idx, rv);
                     }
                 }
-        wg_partial(arr, mypart + kSlotRR * kL, S);
-        wg_partial(abb, mypart + kSlotBB * kL, S);
+        wg_partial<V>(arr, mypart + kSlotRR * kL, S);
+        wg_partial<V>(abb, mypart + kSlotBB * kL, S);
     }
     if (!team_sync(a, sys, T, episode, S)) return;
     team_sum(a, first, T, kSlotRR, S);
@@ -195,21 +274,33 @@ __global__ __launch_bounds__(kT) void k_batch_cg(BatchArgs a) {
     for (int k = 0; S.any; ++k) {
         // A: q = A p, partial p^T q
         {
-            const bool on = lane_on && S.active[j];
-            double acc = 0.0;
-            if (on)
-                for (int64_t r0 = lo; r0 < hi; r0 += kRS * U)
+            bool on[V];
+            bool any_on = false;
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+                on[q] = lane_on && S.active[j0 + q];
+                any_on |= on[q];
+            }
+            double acc[V];
+#pragma unroll
+            for (int q = 0; q < V; ++q) acc[q] = 0.0;
+            if (any_on)
+                for (int64_t r0 = lo; r0 < hi; r0 += RS * U)
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
-                        const int64_t row = r0 + u * kRS + rsub;
+                        const int64_t row = r0 + u * RS + rsub;
                         if (row < hi) {
-                            const double s = row_dot(a, row, a.P, nr, j);
-                            const int64_t idx = row * nr + j;
-                            a.Q[idx] = s;
-                            acc = fma(a.P[idx], s, acc);
+                            double s[V], pv[V];
+                            row_dot<V>(a, row, a.P, nr, j0, s);
+                            const int64_t idx = row * nr + j0;
+                            stv<V>(a.Q, idx, s);
+                            ldv<V>(a.P, idx, pv);
+#pragma unroll
+                            for (int q = 0; q < V; ++q)
+                                if (on[q]) acc[q] = fma(pv[q], s[q], acc[q]);
                         }
                     }
-            wg_partial(acc, mypart + kSlotPQ * kL, S);
+            wg_partial<V>(acc, mypart + kSlotPQ * kL, S);
         }
         if (!team_sync(a, sys, T, episode, S)) return;
         team_sum(a, first, T, kSlotPQ, S);
@@ -230,23 +321,41 @@ __global__ __launch_bounds__(kT) void k_batch_cg(BatchArgs a) {
         __syncthreads();
         // B: x += alpha p, r -= alpha q, partial r^T r
         {
-            const bool on = lane_on && S.active[j];
-            const double alpha = S.alpha[j];
-            double acc = 0.0;
-            if (on)
-                for (int64_t r0 = lo; r0 < hi; r0 += kRS * U)
+            bool on[V];
+            bool any_on = false;
+            double alpha[V], acc[V];
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+                on[q] = lane_on && S.active[j0 + q];
+                any_on |= on[q];
+                alpha[q] = on[q] ? S.alpha[j0 + q] : 0.0;
+                acc[q] = 0.0;
+            }
+            if (any_on)
+                for (int64_t r0 = lo; r0 < hi; r0 += RS * U)
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
-                        const int64_t row = r0 + u * kRS + rsub;
+                        const int64_t row = r0 + u * RS + rsub;
                         if (row < hi) {
-                            const int64_t idx = row * nr + j;
-                            a.X[idx] = fma(alpha, a.P[idx], a.X[idx]);
-                            const double rv = fma(-alpha, a.Q[idx], a.R[idx]);
-                            a.R[idx] = rv;
-                            acc = fma(rv, rv, acc);
+                            const int64_t idx = row * nr + j0;
+                            double xv[V], pv[V], qv[V], rv[V];
+                            ldv<V>(a.X, idx, xv);
+                            ldv<V>(a.P, idx, pv);
+                            ldv<V>(a.Q, idx, qv);
+                            ldv<V>(a.R, idx, rv);
+#pragma unroll
+                            for (int q = 0; q < V; ++q) {
+                                if (on[q]) {
+                                    xv[q] = fma(alpha[q], pv[q], xv[q]);
+                                    rv[q] = fma(-alpha[q], qv[q], rv[q]);
+                                    acc[q] = fma(rv[q], rv[q], acc[q]);
+                                }
+                            }
+                            stv<V>(a.X, idx, xv);
+                            stv<V>(a.R, idx, rv);
                         }
                     }
-            wg_partial(acc, mypart + kSlotRR * kL, S);
+            wg_partial<V>(acc, mypart + kSlotRR * kL, S);
         }
         if (!team_sync(a, sys, T, episode, S)) return;
         team_sum(a, first, T, kSlotRR, S);
@@ -278,16 +387,29 @@ __global__ __launch_bounds__(kT) void k_batch_cg(BatchArgs a) {
         if (!S.any) break;
         // C: p = r + beta p
         {
-            const bool on = lane_on && S.active[j];
-            const double beta = S.beta[j];
-            if (on)
-                for (int64_t r0 = lo; r0 < hi; r0 += kRS * U)
+            bool on[V];
+            bool any_on = false;
+            double beta[V];
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+                on[q] = lane_on && S.active[j0 + q];
+                any_on |= on[q];
+                beta[q] = S.beta[j0 + q];
+            }
+            if (any_on)
+                for (int64_t r0 = lo; r0 < hi; r0 += RS * U)
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
-                        const int64_t row = r0 + u * kRS + rsub;
+                        const int64_t row = r0 + u * RS + rsub;
                         if (row < hi) {
-                            const int64_t idx = row * nr + j;
-                            a.P[idx] = fma(beta, a.P[idx], a.R[idx]);
+                            const int64_t idx = row * nr + j0;
+                            double pv[V], rv[V];
+                            ldv<V>(a.P, idx, pv);
+                            ldv<V>(a.R, idx, rv);
+#pragma unroll
+                            for (int q = 0; q < V; ++q)
+                                if (on[q]) pv[q] = fma(beta[q], pv[q], rv[q]);
+                            stv<V>(a.P, idx, pv);
                         }
                     }
         }
@@ -295,19 +417,30 @@ __global__ __launch_bounds__(kT) void k_batch_cg(BatchArgs a) {
     }
 
     // b = 0: the solution is x = 0
-    if (lane_on && S.zero_b[j])
-        for (int64_t row = lo + rsub; row < hi; row += kRS) a.X[row * nr + j] = 0.0;
+    if (lane_on)
+        for (int64_t row = lo + rsub; row < hi; row += RS)
+#pragma unroll
+            for (int q = 0; q < V; ++q)
+                if (S.zero_b[j0 + q]) a.X[row * nr + j0 + q] = 0.0;
     if (!team_sync(a, sys, T, episode, S)) return;
     // true residual ||b - A x||^2
     {
-        double acc = 0.0;
+        double acc[V];
+#pragma unroll
+        for (int q = 0; q < V; ++q) acc[q] = 0.0;
         if (lane_on)
-            for (int64_t row = lo + rsub; row < hi; row += kRS) {
-                const int64_t idx = row * nr + j;
-                const double rv = a.B[idx] - row_dot(a, row, a.X, nr, j);
-                acc = fma(rv, rv, acc);
+            for (int64_t row = lo + rsub; row < hi; row += RS) {
+                const int64_t idx = row * nr + j0;
+                double s[V], bv[V];
+                row_dot<V>(a, row, a.X, nr, j0, s);
+                ldv<V>(a.B, idx, bv);
+#pragma unroll
+                for (int q = 0; q < V; ++q) {
+                    const double rv = bv[q] - s[q];
+                    acc[q] = fma(rv, rv, acc[q]);
+                }
             }
-        wg_partial(acc, mypart + kSlotTrue * kL, S);
+        wg_partial<V>(acc, mypart + kSlotTrue * kL, S);
     }
     if (!team_sync(a, sys, T, episode, S)) return;
     team_sum(a, first, T, kSlotTrue, S);
@@ -326,22 +459,30 @@ __global__ __launch_bounds__(kT) void k_batch_cg(BatchArgs a) {
     }
 }
 
-}  // namespace
-
-int batch_blocks_per_cu(int rows_per_thread) {
+template <int U, int V>
+int occupancy_of() {
     int nb = 0;
-    const hipError_t e = rows_per_thread == 2
-        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_cg<2>, kT, 0)
-        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_cg<1>, kT, 0);
-    return e == hipSuccess ? nb : 0;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_cg<U, V>, kT, 0) == hipSuccess ? nb : 0;
 }
 
-hipError_t launch_batch_cg(const BatchArgs &a, int grid, int rows_per_thread, hipStream_t s) {
+}  // namespace
+
+int batch_blocks_per_cu(int rows_per_thread, int rhs_per_lane) {
+    if (rhs_per_lane == 2) return rows_per_thread == 2 ? occupancy_of<2, 2>() : occupancy_of<1, 2>();
+    return rows_per_thread == 2 ? occupancy_of<2, 1>() : occupancy_of<1, 1>();
+}
+
+hipError_t launch_batch_cg(const BatchArgs &a, int grid, int rows_per_thread, int rhs_per_lane, hipStream_t s) {
     if (grid <= 0) return hipSuccess;
     BatchArgs args = a;
     void *params[] = {&args};
-    const void *fn = rows_per_thread == 2 ? reinterpret_cast<const void *>(k_batch_cg<2>)
-                                          : reinterpret_cast<const void *>(k_batch_cg<1>);
+    const void *fn;
+    if (rhs_per_lane == 2)
+        fn = rows_per_thread == 2 ? reinterpret_cast<const void *>(k_batch_cg<2, 2>)
+                                  : reinterpret_cast<const void *>(k_batch_cg<1, 2>);
+    else
+        fn = rows_per_thread == 2 ? reinterpret_cast<const void *>(k_batch_cg<2, 1>)
+                                  : reinterpret_cast<const void *>(k_batch_cg<1, 1>);
     return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kT), params, 0, s);
 }
 

@@ -72,7 +72,7 @@ SYSTEMS = [
 @pytest.fixture(scope="module")
 def mixed_batch():
     systems = [f() for f in SYSTEMS]
-    nrhs = 5
+    nrhs = 6            # even: two right-hand sides per lane unless the schedule says 1
     xs, bs = make_batch(systems, nrhs, seed=1)
     refs = [[oracle.cg(A, bs[k][:, j], tol=1e-10, maxit=20000) for j in range(nrhs)]
             for k, A in enumerate(systems)]
@@ -81,7 +81,8 @@ def mixed_batch():
 
 @pytest.mark.parametrize("sched", [{}, {"rows_per_thread": 2}, {"blocks_per_cu": 1},
                                    {"blocks_per_cu": 8, "team_exponent": 2.0},
-                                   {"max_team": 1}])
+                                   {"max_team": 1}, {"rhs_per_lane": 1},
+                                   {"rhs_per_lane": 1, "rows_per_thread": 2, "blocks_per_cu": 8}])
 def test_batch_matches_oracle_per_pair(cg, mixed_batch, sched):
     systems, nrhs, bs, refs, kappas = mixed_batch
     print(f"[batch] sched={sched} n={[A.n for A in systems]}", flush=True)
@@ -196,3 +197,27 @@ def test_full_size_batch_sampled_against_oracle(cg):
         # rounding-order differences grow with the conditioning of these
         # high-contrast fields; the residual norms agree closely
         assert abs(r_gpu - r_ref) <= 1e-6 * r_ref and dx <= 1e-5, (k, j)
+
+
+def test_unaligned_vectors_use_one_rhs_per_lane(cg):
+    systems = [field(30, 31), I.poisson2d(20)]
+    nrhs = 4
+    xs, bs = make_batch(systems, nrhs, seed=7)
+    Bh = stack(systems, bs)
+    with cg.Batch(systems, nrhs) as b:
+        b.set_sched(blocks_per_cu=2)
+        B = torch.from_numpy(Bh).cuda()
+        X, res, st, code = b.solve(B, torch.zeros_like(B), tol=1e-10, maxit=20000)
+        # the same values 8 bytes off 16-byte alignment
+        buf_b = torch.empty(B.numel() + 1, dtype=torch.float64, device="cuda")
+        buf_x = torch.zeros(B.numel() + 1, dtype=torch.float64, device="cuda")
+        Bu = buf_b[1:].view(B.shape)
+        Bu.copy_(B)
+        Xu = buf_x[1:].view(B.shape)
+        assert Bu.data_ptr() % 16 == 8
+        Xu, res_u, st_u, code_u = b.solve(Bu, Xu, tol=1e-10, maxit=20000)
+        torch.cuda.synchronize()
+    assert code == cg.CG_OK and code_u == cg.CG_OK
+    it, it_u = res["iterations"].astype(int), res_u["iterations"].astype(int)
+    assert np.all(np.abs(it - it_u) <= np.maximum(2, 0.05 * it))   # other summation order
+    assert np.all(res_u["rel_res_true"] <= 1.01e-10)
