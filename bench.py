@@ -73,6 +73,25 @@ def _sample_iterations(run, cap: int, target_s: float) -> int:
     return max(3, min(cap, int(target_s / per_it)))
 
 
+def measured_copy_gbs(reps: int = 5) -> float:
+    """Bandwidth of a plain device copy of 1 GiB (read + write bytes / time),
+    the achievable-peak reference next to the 8 TB/s specification."""
+    import torch
+    a = torch.ones(2 ** 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * a.numel() * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def cpu_baseline_cg(problem, iters_hint: int, target_s: float = 12.0) -> dict:
     """The oracle's CG, untouched, on a bounded sample: a fixed number of CG
     iterations of the same system, all host threads for its row loops."""
@@ -201,6 +220,7 @@ def main() -> int:
     spmv_bytes = spmv_algorithmic_bytes(A.n, A.nnz)
     t_launch = t_spmv / max(n_spmv, 1)
     achieved = spmv_bytes / t_launch / 1e9
+    copy_gbs = measured_copy_gbs()
     line = {
         "metric": "CG iters/s + SpMV GB/s (%HBM peak); time to 1e-10 residual, plain vs learned-PC",
         "value": iters / elapsed,
@@ -219,6 +239,8 @@ def main() -> int:
                    "seed": 2},
         "spmv_gbs": achieved,
         "spmv_us": 1e6 * t_launch,
+        "hbm_copy_gbs_measured": copy_gbs,
+        "spmv_frac_of_measured_copy": achieved / copy_gbs,
         "spmv_kind": {1: "vector_bins", 2: "stream", 3: "sliced", 4: "sliced_dict"}.get(res["spmv_kind"]),
         "rel_res_true": res["rel_res_true"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
