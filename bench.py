@@ -165,7 +165,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the hot path runs on a single MI355X "
-              "(multi-GPU row sharding is described in DESIGN.md, not run).", file=sys.stderr)
+              "(sharding rows across GPUs is a design, not a measured path).", file=sys.stderr)
         return 2
 
     import numpy as np
@@ -241,7 +241,8 @@ def main() -> int:
         "spmv_us": 1e6 * t_launch,
         "hbm_copy_gbs_measured": copy_gbs,
         "spmv_frac_of_measured_copy": achieved / copy_gbs,
-        "spmv_kind": {1: "vector_bins", 2: "stream", 3: "sliced", 4: "sliced_dict"}.get(res["spmv_kind"]),
+        "spmv_kind": {1: "vector_bins", 2: "stream", 3: "sliced", 4: "sliced_dict",
+                      5: "column_blocks"}.get(res["spmv_kind"]),
         "rel_res_true": res["rel_res_true"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,

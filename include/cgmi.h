@@ -76,14 +76,20 @@ typedef struct cg_opts {
                               tile fits, else 1), 3 sliced tiles (64-row slices
                               stored slot-major, one lane per row; rows of at
                               most 64 nonzeros, else 1), 4 dictionary-sliced
-                              tiles (the sliced layout with a 1-byte index per
+                              tiles (the sliced layout with a 4-bit index per
                               slot into a per-slice table of at most 15 column
-                              offsets; rows of at most 8 nonzeros, else 3).
-                              Automatic picks 4 when rows have <= 8 nonzeros
-                              and every slice fits the table, else 3 when rows
-                              have <= 64 nonzeros and slicing pads by <= 25%,
-                              else 1.                                           */
-    int32_t reserved;      /* must be 0                                         */
+                              offsets; rows of at most 8 nonzeros, else 3),
+                              5 column blocks (one accumulating vector-bin pass
+                              per block of spmv_colblock columns, so gathers
+                              from p stay in the L2; for scattered columns).
+                              Automatic picks 5 when more than half of the
+                              entries lie farther than 262,144 columns from the
+                              diagonal and the vector spans at least two blocks,
+                              else 4 when rows have <= 8 nonzeros and every
+                              slice fits the table, else 3 when rows have <= 64
+                              nonzeros and slicing pads by <= 25%, else 1.      */
+    int32_t spmv_colblock; /* columns per block of the column-blocked tiling
+                              (spmv_kind 5); 0: 262,144 (2 MB of float64 p)     */
     double refine_delta;   /* mixed precision: a float64 refinement is made
                               when the float32 residual drops by this factor    */
 } cg_opts;
@@ -112,7 +118,7 @@ typedef struct cg_result {
                                 plain float64 CG                                 */
     int32_t spmv_kind;       /* SpMV tiling used on the GPU rows: 1 vector bins,
                                 2 stream tiles, 3 sliced tiles, 4 dictionary-
-                                sliced tiles (0: no GPU rows)                    */
+                                sliced tiles, 5 column blocks (0: no GPU rows)   */
 } cg_result;
 
 /* Create a solver for the n x n CSR matrix (host arrays, copied).  Rows

@@ -131,7 +131,7 @@ def batch_schedule(batch: "cgmi.Batch", systems, B, tune_if_missing: bool = True
 
 # ----------------------------------------------------------------------------- single-system SpMV tiling
 
-SPMV_KINDS = {1: "vector_bins", 2: "stream", 3: "sliced", 4: "sliced_dict"}
+SPMV_KINDS = {1: "vector_bins", 2: "stream", 3: "sliced", 4: "sliced_dict", 5: "column_blocks"}
 
 
 def tune_spmv(solver: "cgmi.Solver", b, iters: int = 20, grids=(0, 2048, 4096), log=None) -> dict:

@@ -41,7 +41,7 @@ class CgOpts(ctypes.Structure):
                 ("exchange", ctypes.c_int32), ("host_threads", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("profile", ctypes.c_int32),
                 ("small_path", ctypes.c_int32), ("spmv_grid", ctypes.c_int32),
-                ("spmv_kind", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("spmv_kind", ctypes.c_int32), ("spmv_colblock", ctypes.c_int32),
                 ("refine_delta", ctypes.c_double)]
 
 

@@ -1,6 +1,8 @@
-// cgmi.cpp -- host runtime of libcgmi: C ABI, CSR validation, row split,
-// SpMV schedule, GPU-only solve driver and the split (coscheduled) driver
-// with the host complement on OpenMP threads.
+// cgmi.cpp -- host runtime of libcgmi: C ABI, CSR validation, row split, the
+// GPU-only solve loops (float64 and mixed precision) and the split
+// (coscheduled) solve with the host complement on OpenMP threads.  The device
+// matrix and its SpMV schedule are in devmatrix.cpp, the preconditioned solve
+// in fsai.cpp, the batched solve in batch.cpp.
 //
 // Section 3.2: the GPU owns the contiguous row block [row_begin, row_end);
 // the host owns the rest.  Section 3.3: one host thread drives the GPU while
@@ -82,7 +84,7 @@ int cgmi::validate_csr(int32_t n, int64_t nnz, const int32_t *rp, const int32_t 
 // SpMV schedule of the GPU block for the current options.
 static int apply_schedule(cg_handle *h) {
     return dm_schedule(h->A, h->opts.spmv_kind, h->opts.spmv_grid, h->cus, h->grid_cap,
-                       h->opts.precision == CG_PREC_MIXED);
+                       h->opts.precision == CG_PREC_MIXED, h->opts.spmv_colblock);
 }
 
 // float32 inner vectors of mixed precision (the float32 matrix copies are
@@ -127,7 +129,7 @@ extern "C" void cg_default_opts(cg_opts *o) {
     o->small_path = 1;
     o->spmv_grid = 0;
     o->spmv_kind = 0;
-    o->reserved = 0;
+    o->spmv_colblock = 0;
     o->refine_delta = 0.01;
 }
 
@@ -281,7 +283,8 @@ extern "C" int cg_set_opts(cg_handle *h, const cg_opts *o) {
         return fail(CG_EINVAL, "refine_delta must be in (0, 1)");
     if ((o->precision != CG_PREC_FP64 || o->precond != CG_PC_NONE) && !h->gpu_only())
         return fail(CG_EINVAL, "mixed precision and preconditioning need a GPU-only handle");
-    if (o->spmv_kind < 0 || o->spmv_kind > 4) return fail(CG_EINVAL, "unknown spmv_kind %d", o->spmv_kind);
+    if (o->spmv_kind < 0 || o->spmv_kind > 5) return fail(CG_EINVAL, "unknown spmv_kind %d", o->spmv_kind);
+    if (o->spmv_colblock < 0) return fail(CG_EINVAL, "spmv_colblock must be >= 0");
     if (o->precision == CG_PREC_MIXED && o->precond != CG_PC_NONE)
         return fail(CG_EINVAL, "the preconditioned solve runs in float64 only");
     h->opts = *o;
@@ -918,7 +921,7 @@ extern "C" int cg_solve(cg_handle *h, const double *b, double *x, double tol, in
     }
     if (res) {
         res->t_solve = now() - t0;
-        static const int kind_code[4] = {1, 2, 3, 4};   // kTileVector .. kTileSlicedDict
+        static const int kind_code[5] = {1, 2, 3, 4, 5};   // kTileVector .. kTileColBlocked
         res->spmv_kind = h->m == 0 ? 0 : kind_code[h->A.sched.kind];
         res->rows_gpu = h->m;
         res->rows_cpu = h->n - h->m;

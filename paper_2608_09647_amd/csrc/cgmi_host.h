@@ -52,12 +52,15 @@ struct DevMatrix {
     float *d_val32 = nullptr, *d_sell_val32 = nullptr;
     uint32_t *d_sell_idx = nullptr;   // dictionary-sliced layout
     int32_t *d_sell_dict = nullptr;
+    std::vector<DevMatrix> blocks;    // column-blocked layout: one CSR per column block
+    ColBlocks *cb = nullptr;          //   and their launch operands
+    int32_t block_cols = 0;           //   columns per block
     Schedule sched{};
     int grid = 8;
     CsrDev dev() const {
         return CsrDev{m, d_rp, d_ci, d_val, sched.identity ? nullptr : d_rows,
                       d_sell_off, d_sell_ci, d_sell_val, d_val32, d_sell_val32,
-                      d_sell_idx, d_sell_dict, pad_col_base};
+                      d_sell_idx, d_sell_dict, pad_col_base, cb};
     }
 };
 
@@ -67,10 +70,12 @@ int dm_upload(DevMatrix &M, int32_t m, const int32_t *rp, const int32_t *ci, con
               int32_t pad_col_base);
 // Choose the tiling (kind_opt: cg_opts.spmv_kind; 4 asks for dictionary
 // slices, used when every slice has at most 15 distinct column offsets and
-// rows of at most kSliceMaxWidth entries, else plain slices), build the row
-// list or the sliced copies, size the grid (0: automatic, a multiple of 8 up
-// to grid_cap).
-int dm_schedule(DevMatrix &M, int kind_opt, int grid_opt, int cus, int grid_cap, bool need_f32);
+// rows of at most kSliceMaxWidth entries, else plain slices; 5 asks for
+// column blocks of block_cols columns, 0: kColBlockCols), build the row list,
+// the sliced copies or the column blocks, size the grid (0: automatic, a
+// multiple of 8 up to grid_cap).
+int dm_schedule(DevMatrix &M, int kind_opt, int grid_opt, int cus, int grid_cap, bool need_f32,
+                int32_t block_cols = 0);
 int dm_ensure_f32(DevMatrix &M);
 void dm_free(DevMatrix &M);
 

@@ -64,7 +64,15 @@ constexpr int kSliceMaxWidth = 8;  // widths up to this take the unrolled path
 // never summed).  Widths up to kSliceMaxWidth (8 nibbles) only.
 constexpr int kDictSize = 16;
 constexpr uint32_t kDictPad = 0xFu;
-enum { kTileVector = 0, kTileStream = 1, kTileSliced = 2, kTileSlicedDict = 3 };
+// Column-blocked tiles (kind kTileColBlocked): for matrices whose columns
+// scatter over a vector larger than the L2, the entries are split by column
+// block (kColBlockCols columns, about 2 MB of float64 p) into one CSR per
+// block; q = A p runs as one pass per block (vector bins over the rows with
+// entries in the block, q accumulated), so every pass gathers from a segment
+// of p that stays in each XCD's L2.
+constexpr int kMaxColBlocks = 64;
+constexpr int32_t kColBlockCols = 1 << 18;
+enum { kTileVector = 0, kTileStream = 1, kTileSliced = 2, kTileSlicedDict = 3, kTileColBlocked = 4 };
 
 struct Schedule {
     Bin bins[kMaxBins];
@@ -102,6 +110,17 @@ struct CsrDev {
     const uint32_t *sell_idx; // dictionary-sliced layout: packed slot bytes
     const int32_t *sell_dict; //   per-slice column offsets
     int32_t col_base;         // global index of local row 0
+    const struct ColBlocks *cb;  // column-blocked layout (host memory; launch side only)
+};
+
+// Per-block operands of the column-blocked tiling (kept on the host by the
+// launcher; each block's CSR has all m rows, its row list only those with
+// entries in the block).
+struct ColBlocks {
+    int32_t nb;
+    CsrDev dev[kMaxColBlocks];
+    Schedule sched[kMaxColBlocks];
+    int32_t grid[kMaxColBlocks];
 };
 
 // Partial sums of one reduction: one value per workgroup of the kernel that
@@ -114,7 +133,7 @@ struct Partials {
 // ---- launch wrappers (kernels_cg.hip) ------------------------------------
 // Every wrapper returns the hipError_t of the launch.
 
-enum { kSpmvPlain = 0, kSpmvDot = 1, kSpmvResidual = 2 };
+enum { kSpmvPlain = 0, kSpmvDot = 1, kSpmvResidual = 2, kSpmvAccum = 3 };
 
 // q = A p on the block's rows.
 //   kSpmvPlain:    nothing else (with st: nothing once the solve has stopped).

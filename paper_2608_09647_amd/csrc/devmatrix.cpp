@@ -15,6 +15,13 @@ int lanes_for_length(int64_t len) {
     return L;
 }
 
+void free_blocks(DevMatrix &M) {
+    for (DevMatrix &B : M.blocks) dm_free(B);
+    M.blocks.clear();
+    delete M.cb;
+    M.cb = nullptr;
+}
+
 void free_sliced(DevMatrix &M) {
     (void)hipFree(M.d_sell_off);
     (void)hipFree(M.d_sell_ci);
@@ -66,22 +73,48 @@ bool build_dict(const DevMatrix &M, std::vector<int32_t> &dict, std::vector<uint
     return true;
 }
 
+// Column blocks when most entries lie farther than a block width from the
+// diagonal of a vector of at least two blocks (gathers would miss the L2).
 // Lanes-per-row classes.  Sliced tiles for rows of at most 64 nonzeros when
 // slicing pads by at most 25%; stream tiles when requested and every 64-row
 // tile fits; otherwise vector bins: rows of similar length keep their natural
 // order (one bin, no indirection), spread-out lengths are binned by the power
 // of two covering the row length (row list per bin), rows longer than
 // kHugeRow go to a workgroup-per-row list at the end.
-void build_schedule(const DevMatrix &M, int kind_opt, Schedule &S, std::vector<int32_t> &rows_out) {
+void build_schedule(const DevMatrix &M, int kind_opt, Schedule &S, std::vector<int32_t> &rows_out,
+                    bool skip_empty = false) {
     S = Schedule{};
     const int32_t m = M.m;
     rows_out.clear();
     S.identity = 1;
     if (m == 0) return;
+    if (kind_opt == 5) {
+        // column blocks: the per-block schedules are built separately; the
+        // parent keeps 64-row tiles for sizing the grid of its start/finish kernels
+        S.kind = kTileColBlocked;
+        S.ntiles = (m + kWaveSize - 1) / kWaveSize;
+        return;
+    }
     auto len = [&](int32_t i) -> int64_t { return M.h_rp[i + 1] - M.h_rp[i]; };
     int64_t maxlen = 0;
     for (int32_t i = 0; i < m; ++i) maxlen = std::max<int64_t>(maxlen, len(i));
     const double mean = (double)M.h_rp[m] / (double)m;
+    if (kind_opt == 0 && !skip_empty) {
+        // scattered columns over a vector of at least two blocks: column blocks
+        int64_t far = 0;
+        int32_t ncols = 0;
+        for (int32_t i = 0; i < m; ++i)
+            for (int32_t k = M.h_rp[i]; k < M.h_rp[i + 1]; ++k) {
+                const int64_t d = (int64_t)M.h_ci[k] - (M.pad_col_base + i);
+                far += (d > kColBlockCols || d < -kColBlockCols);
+                ncols = std::max(ncols, M.h_ci[k] + 1);
+            }
+        if (ncols >= 2 * kColBlockCols && 2 * far > M.nnz) {
+            S.kind = kTileColBlocked;
+            S.ntiles = (m + kWaveSize - 1) / kWaveSize;
+            return;
+        }
+    }
     if (kind_opt == 4 || kind_opt == 3 || (kind_opt == 0 && maxlen <= 64)) {
         const int32_t nt = (m + kWaveSize - 1) / kWaveSize;
         int64_t slots = 0;
@@ -116,7 +149,7 @@ void build_schedule(const DevMatrix &M, int kind_opt, Schedule &S, std::vector<i
             return;
         }
     }
-    if (maxlen <= 64 && (double)maxlen <= 2.0 * mean + 1.0) {
+    if (!skip_empty && maxlen <= 64 && (double)maxlen <= 2.0 * mean + 1.0) {
         const int L = lanes_for_length(maxlen);
         S.nbins = 1;
         S.bins[0] = Bin{L, 0, m, 0};
@@ -128,6 +161,7 @@ void build_schedule(const DevMatrix &M, int kind_opt, Schedule &S, std::vector<i
     std::vector<int32_t> huge;
     for (int32_t i = 0; i < m; ++i) {
         const int64_t l = len(i);
+        if (l == 0 && skip_empty) continue;
         if (l > kHugeRow) {
             huge.push_back(i);
             continue;
@@ -200,6 +234,70 @@ int build_sliced(DevMatrix &M) {
     return CG_OK;
 }
 
+// Column blocks of block_cols columns: block b holds, for every row, the
+// row's entries with columns in [b block_cols, (b+1) block_cols) (a
+// contiguous sub-range, columns being sorted), uploaded as its own CSR with
+// a vector-bin schedule over its non-empty rows.
+int build_blocks(DevMatrix &M, int32_t block_cols, int cus, int grid_cap, bool need_f32) {
+    if (M.cb && M.block_cols == block_cols) return CG_OK;
+    free_blocks(M);
+    M.block_cols = block_cols;
+    const int32_t m = M.m;
+    int32_t ncols = 0;
+    for (int32_t c : M.h_ci) ncols = std::max(ncols, c + 1);
+    const int32_t nb = std::max(1, (ncols + block_cols - 1) / block_cols);
+    if (nb > kMaxColBlocks) return fail(CG_EINVAL, "%d column blocks exceed %d", nb, kMaxColBlocks);
+    ColBlocks *cb = new (std::nothrow) ColBlocks();
+    if (!cb) return fail(CG_ENOMEM, "out of host memory");
+    M.cb = cb;
+    cb->nb = nb;
+    M.blocks.resize(nb);
+    std::vector<int32_t> cur(M.h_rp.begin(), M.h_rp.end() - 1);   // per-row cursor
+    std::vector<int32_t> rp, ci;
+    std::vector<double> va;
+    for (int32_t b = 0; b < nb; ++b) {
+        const int64_t lim = (int64_t)(b + 1) * block_cols;
+        try {
+            rp.assign((size_t)m + 1, 0);
+            ci.clear();
+            va.clear();
+            for (int32_t i = 0; i < m; ++i) {
+                int32_t k = cur[i];
+                while (k < M.h_rp[i + 1] && M.h_ci[k] < lim) {
+                    ci.push_back(M.h_ci[k]);
+                    va.push_back(M.h_val[k]);
+                    ++k;
+                }
+                cur[i] = k;
+                rp[i + 1] = (int32_t)ci.size();
+            }
+        } catch (...) {
+            return fail(CG_ENOMEM, "out of host memory");
+        }
+        DevMatrix &B = M.blocks[b];
+        int rc = dm_upload(B, m, rp.data(), ci.data(), va.data(), M.pad_col_base);
+        if (rc) return rc;
+        std::vector<int32_t> rows;
+        build_schedule(B, 1, B.sched, rows, true);
+        if (!rows.empty()) {
+            const hipError_t e = hipMemcpy(B.d_rows, rows.data(), sizeof(int32_t) * rows.size(),
+                                           hipMemcpyHostToDevice);
+            if (e != hipSuccess) return fail(CG_EDEVICE, "row list upload failed: %s", hipGetErrorString(e));
+        }
+        if (need_f32) {
+            rc = dm_ensure_f32(B);
+            if (rc) return rc;
+        }
+        const int waves = B.sched.ntiles + B.sched.huge_count * (kBlock / kWaveSize);
+        const int g = std::min(cus * 8, ((waves / (kBlock / kWaveSize) + 8) / 8) * 8);
+        B.grid = std::max(8, (std::min(g, grid_cap) / 8) * 8);
+        cb->dev[b] = B.dev();
+        cb->sched[b] = B.sched;
+        cb->grid[b] = B.grid;
+    }
+    return CG_OK;
+}
+
 }  // namespace
 
 int dm_upload(DevMatrix &M, int32_t m, const int32_t *rp, const int32_t *ci, const double *val,
@@ -260,9 +358,21 @@ int dm_ensure_f32(DevMatrix &M) {
     return CG_OK;
 }
 
-int dm_schedule(DevMatrix &M, int kind_opt, int grid_opt, int cus, int grid_cap, bool need_f32) {
+int dm_schedule(DevMatrix &M, int kind_opt, int grid_opt, int cus, int grid_cap, bool need_f32,
+                int32_t block_cols) {
     std::vector<int32_t> rows;
     build_schedule(M, kind_opt, M.sched, rows);
+    if (M.sched.kind == kTileColBlocked) {
+        const int32_t bc = block_cols > 0 ? block_cols : kColBlockCols;
+        if (M.cb && M.block_cols == bc && need_f32)
+            for (int b = 0; b < M.cb->nb; ++b) {
+                const int rc = dm_ensure_f32(M.blocks[b]);
+                if (rc) return rc;
+                M.cb->dev[b] = M.blocks[b].dev();
+            }
+        const int rc = build_blocks(M, bc, cus, grid_cap, need_f32);
+        if (rc) return rc;
+    }
     if (M.sched.kind == kTileSlicedDict && !M.d_sell_idx) {
         std::vector<int32_t> dict;
         std::vector<uint32_t> idx;
@@ -308,6 +418,7 @@ int dm_schedule(DevMatrix &M, int kind_opt, int grid_opt, int cus, int grid_cap,
 }
 
 void dm_free(DevMatrix &M) {
+    free_blocks(M);
     (void)hipFree(M.d_rp);
     (void)hipFree(M.d_ci);
     (void)hipFree(M.d_rows);

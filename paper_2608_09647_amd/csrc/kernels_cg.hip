@@ -114,6 +114,8 @@ __device__ __forceinline__ void emit_row(const SpmvArgs<T> &a, int row, T s, dou
         a.p_dst[row] = rv;
         acc0 = fma((double)rv, (double)rv, acc0);
         acc1 = fma((double)bv, (double)bv, acc1);
+    } else if (MODE == kSpmvAccum) {
+        a.q[row] = a.q[row] + s;
     } else {
         a.q[row] = s;
         if (MODE == kSpmvDot) acc0 = fma((double)a.p_own[row], (double)s, acc0);
@@ -278,7 +280,7 @@ __device__ __forceinline__ void stream_step(const CsrDev &A, const SpmvArgs<doub
             acc0 = fma(rv, rv, acc0);
             acc1 = fma(bv, bv, acc1);
         } else {
-            a.q[myrow] = s;
+            a.q[myrow] = MODE == kSpmvAccum ? (a.q[myrow] + s) : s;
             if (MODE == kSpmvDot) acc0 = fma(pown, s, acc0);
         }
     }
@@ -367,7 +369,7 @@ __device__ __forceinline__ void slice_step(const CsrDev &A, const SpmvArgs<T> &a
             acc0 = fma((double)rv, (double)rv, acc0);
             acc1 = fma((double)bv, (double)bv, acc1);
         } else {
-            a.q[myrow] = s;
+            a.q[myrow] = MODE == kSpmvAccum ? T(a.q[myrow] + s) : s;
             if (MODE == kSpmvDot) acc0 = fma((double)pown, (double)s, acc0);
         }
     }
@@ -484,7 +486,7 @@ __device__ __forceinline__ void dict_step(const CsrDev &A, const SpmvArgs<T> &a,
             acc0 = fma((double)rv, (double)rv, acc0);
             acc1 = fma((double)bv, (double)bv, acc1);
         } else {
-            a.q[myrow] = s;
+            a.q[myrow] = MODE == kSpmvAccum ? T(a.q[myrow] + s) : s;
             if (MODE == kSpmvDot) acc0 = fma((double)pown, (double)s, acc0);
         }
     }
@@ -610,7 +612,65 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int32_t m, const int32_t *__res
         for (int hrow = blockIdx.x; hrow < S.huge_count; hrow += gridDim.x)
             spmv_row_wg<MODE, T>(A, S.huge_first + hrow, identity, a, acc0, acc1, sh);
     }
-    if (MODE == kSpmvPlain) return;
+    if (MODE == kSpmvPlain || MODE == kSpmvAccum) return;
+    const double s0 = block_sum<kBlock>(acc0, sh);
+    double s1 = 0.0;
+    if (MODE == kSpmvResidual) s1 = block_sum<kBlock>(acc1, sh);
+    if (threadIdx.x == 0) {
+        out[blockIdx.x] = s0;
+        if (MODE == kSpmvResidual) out[gridDim.x + blockIdx.x] = s1;
+    }
+}
+
+// Column-blocked SpMV, first and last kernels.  Start: the early exit and
+// first-iteration stop test of k_spmv, then q = 0.  Finish: the mode's
+// epilogue on the accumulated q = A p (p^T q partials, or the residual
+// b - A p with its partial sums), one partial per workgroup in row order.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_blocked_start(int32_t m, T *__restrict__ q, Partials in0,
+                                                          Partials in1, DevState *__restrict__ st,
+                                                          int flags) {
+    __shared__ double sh[kWavesPerBlock];
+    __shared__ double bc;
+    if (flags & kFlagCheckDone) {
+        if (st->done) return;
+        if (flags & kFlagFirstIter) {
+            const double rr = reduce_partials(in0, sh, &bc);
+            const double bb = reduce_partials(in1, sh, &bc);
+            const bool conv = stop_test(rr, bb, st->tol);
+            const bool stop = conv || st->maxit <= 0;
+            if (is_block0_thread0()) {
+                st->rho[0] = rr;
+                st->rr = rr;
+                st->bb = bb;
+                if (stop) st->done = conv ? kDoneConverged : kDoneMaxit;
+            }
+            if (stop) return;
+        }
+    }
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += (int64_t)gridDim.x * kBlock)
+        q[i] = T(0);
+}
+
+template <int MODE, class T>
+__global__ __launch_bounds__(kBlock) void k_blocked_finish(int32_t m, SpmvArgs<T> a, double *__restrict__ out,
+                                                           DevState *__restrict__ st, int flags) {
+    __shared__ double sh[kWavesPerBlock];
+    if ((flags & kFlagCheckDone) && st->done) return;
+    double acc0 = 0.0, acc1 = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += (int64_t)gridDim.x * kBlock) {
+        const T s = a.q[i];
+        if (MODE == kSpmvResidual) {
+            const T bv = a.b[i];
+            const T rv = bv - s;
+            a.q[i] = rv;
+            a.p_dst[i] = rv;
+            acc0 = fma((double)rv, (double)rv, acc0);
+            acc1 = fma((double)bv, (double)bv, acc1);
+        } else {
+            acc0 = fma((double)a.p_own[i], (double)s, acc0);
+        }
+    }
     const double s0 = block_sum<kBlock>(acc0, sh);
     double s1 = 0.0;
     if (MODE == kSpmvResidual) s1 = block_sum<kBlock>(acc1, sh);
@@ -1036,6 +1096,24 @@ void launch_spmv_mode(const CsrDev &A, const Schedule &S, int grid, const SpmvAr
 #undef CGMI_SPMV
 }
 
+// q = A p as one accumulating pass per column block, between the start and
+// finish kernels (same grid as the caller's partials).
+template <class T>
+void launch_spmv_blocked(const CsrDev &A, int grid, const SpmvArgs<T> &a, int mode, double *out,
+                         Partials in0, Partials in1, DevState *st, int flags, hipStream_t s) {
+    const ColBlocks &B = *A.cb;
+    hipLaunchKernelGGL(k_blocked_start<T>, dim3(grid), dim3(kBlock), 0, s, A.m, a.q, in0, in1, st, flags);
+    const int bflags = st ? kFlagCheckDone : 0;
+    const Partials none{nullptr, 0};
+    for (int b = 0; b < B.nb; ++b)
+        launch_spmv_mode<kSpmvAccum, T>(B.dev[b], B.sched[b], B.grid[b], a, nullptr, none, none, st, bflags, s);
+    if (mode == kSpmvDot)
+        hipLaunchKernelGGL((k_blocked_finish<kSpmvDot, T>), dim3(grid), dim3(kBlock), 0, s, A.m, a, out, st, bflags);
+    else if (mode == kSpmvResidual)
+        hipLaunchKernelGGL((k_blocked_finish<kSpmvResidual, T>), dim3(grid), dim3(kBlock), 0, s, A.m, a, out, st,
+                           bflags);
+}
+
 }  // namespace
 
 hipError_t launch_spmv(const CsrDev &A, const Schedule &S, int grid, const double *p, double *q,
@@ -1044,6 +1122,12 @@ hipError_t launch_spmv(const CsrDev &A, const Schedule &S, int grid, const doubl
                        hipStream_t s) {
     if (A.m == 0) return hipSuccess;
     SpmvArgs<double> a{p, q, p_own, b, p_dst};
+    if (S.kind == kTileColBlocked) {
+        if (!A.cb || mode < kSpmvPlain || mode > kSpmvResidual) return hipErrorInvalidValue;
+        const int flags = st ? (kFlagCheckDone | (mode == kSpmvDot && k0_check ? kFlagFirstIter : 0)) : 0;
+        launch_spmv_blocked<double>(A, grid, a, mode, out_partials, in0, in1, st, flags, s);
+        return hipGetLastError();
+    }
     switch (mode) {
         case kSpmvPlain:
             launch_spmv_mode<kSpmvPlain, double>(A, S, grid, a, nullptr, in0, in1, st,
@@ -1071,6 +1155,11 @@ hipError_t launch_spmv_f32(const CsrDev &A, const Schedule &S, int grid, const f
     if (S.kind == kTileStream) return hipErrorInvalidValue;
     SpmvArgs<float> a{p, q, p_own, nullptr, nullptr};
     const Partials none{nullptr, 0};
+    if (S.kind == kTileColBlocked) {
+        if (!A.cb || (mode != kSpmvPlain && mode != kSpmvDot)) return hipErrorInvalidValue;
+        launch_spmv_blocked<float>(A, grid, a, mode, out_partials, none, none, st, st ? kFlagCheckDone : 0, s);
+        return hipGetLastError();
+    }
     switch (mode) {
         case kSpmvPlain:
             launch_spmv_mode<kSpmvPlain, float>(A, S, grid, a, nullptr, none, none, nullptr, 0, s);

@@ -1,6 +1,6 @@
 """GPU parity: libcgmi (C ABI, HIP kernels) against the CPU oracle.
 
-Bars (derived in the design doc from the arithmetic):
+Bars (derived from the arithmetic):
 * SpMV: max_i |y_i - yhat_i| / sum_k |a_ik x_k| <= 1e-12 (sum-order bound for
   rows of up to ~2000 nonzeros is ~2.3e-13); bit-exact on integer inputs.
 * Row split / device slice: bit-exact.
@@ -87,7 +87,7 @@ def used_kind(s, n):
     return res["spmv_kind"]
 
 
-@pytest.mark.parametrize("kind", [1, 2, 3, 4])
+@pytest.mark.parametrize("kind", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("name", ["poisson2d_64", "poisson3d_ragged", "diffusion_100", "tiny_7",
                                   "random_spd_30k", "tiny_1"])
 def test_spmv_tilings_match_oracle(cg, name, kind):
@@ -103,10 +103,53 @@ def test_spmv_tilings_match_oracle(cg, name, kind):
         assert used == kind
     if kind == 4:
         assert used == (4 if np.diff(A.row_ptr).max() <= 8 else 3 if np.diff(A.row_ptr).max() <= 64 else 1)
+    if kind == 5:
+        assert used == 5
     if used in (2, 3, 4):
         # stream, sliced and dictionary-sliced tiles sum each row left to
         # right with rounded products: the oracle's own order, so the bits agree
         assert np.array_equal(y, ref)
+
+
+@pytest.mark.parametrize("cols", [97, 1000, 4096])
+@pytest.mark.parametrize("name", ["random_spd_30k", "arrowhead_3000", "poisson3d_ragged"])
+def test_column_blocks_match_oracle(cg, name, cols):
+    """Column blocks of `cols` columns (many blocks on small matrices; the
+    arrowhead's dense row goes to the workgroup-per-row bin of block 0)."""
+    A = SPMV_CASES[name]()
+    x = np.random.default_rng(5).uniform(-1, 1, A.n)
+    ref = oracle.spmv(A, x)
+    if (A.n + cols - 1) // cols > 64:
+        cols = (A.n + 63) // 64
+    with cg.Solver(A) as s:
+        s.set_opts(spmv_kind=5, spmv_colblock=cols)
+        y = host(s.spmv(dev(x)))
+        assert used_kind(s, A.n) == 5
+    assert spmv_err(A, x, y, ref) <= 1e-12
+
+
+def test_column_blocks_cg_mixed_and_split(cg):
+    p = I.random_spd_problem(20000, seed=3)
+    ref = oracle.cg(p.A, p.b, tol=1e-10, maxit=20000)
+    refm = oracle.cg_mixed(p.A, p.b, tol=1e-10, maxit=20000)
+    for opts in ({}, {"precision": cg.PREC_MIXED}):
+        with cg.Solver(p.A) as s:
+            s.set_opts(spmv_kind=5, spmv_colblock=3000, **opts)
+            x, res = s.solve(dev(p.b), tol=1e-10, maxit=20000)
+        r = refm if opts else ref
+        print(f"[colblock] {opts} it={res['iterations']} oracle={r['iterations']}", flush=True)
+        assert res["code"] == cg.CG_OK and res["spmv_kind"] == 5
+        assert abs(res["iterations"] - r["iterations"]) <= max(2, 0.05 * r["iterations"])
+        true = np.linalg.norm(p.b - oracle.spmv(p.A, host(x))) / np.linalg.norm(p.b)
+        assert true <= 1.01e-10
+    # split rows: the GPU block [rb, re) with global columns split into blocks
+    n = p.A.n
+    with cg.Solver(p.A, 5000, 15000) as s:
+        s.set_opts(spmv_kind=5, spmv_colblock=4000)
+        x, res = s.solve(dev(p.b), tol=1e-10, maxit=20000)
+    assert res["code"] == cg.CG_OK
+    assert abs(res["iterations"] - ref["iterations"]) <= max(2, 0.05 * ref["iterations"])
+    assert np.linalg.norm(p.b - oracle.spmv(p.A, host(x))) / np.linalg.norm(p.b) <= 1.01e-10
 
 
 def test_dictionary_slices_fall_back_on_many_offsets(cg):
@@ -330,7 +373,7 @@ def test_full_size_poisson3d_256(cg):
 
 # ----------------------------------------------------------------------------- mixed precision
 
-@pytest.mark.parametrize("kind", [0, 1, 3, 4])
+@pytest.mark.parametrize("kind", [0, 1, 3, 4, 5])
 @pytest.mark.parametrize("name", ["poisson3d_ragged", "random_spd_30k", "diffusion_100"])
 def test_spmv_f32_matches_oracle(cg, name, kind):
     A = SPMV_CASES[name]()
