@@ -65,7 +65,9 @@ struct DevMatrix {
 };
 
 // Copy the rows (row pointers rebased to start at 0 are computed here from
-// the global ones: rp[0..m] with rp[0] possibly > 0) and upload them.
+// the global ones: rp[0..m] with rp[0] possibly > 0) and upload them.  val
+// may be null: the values are then zero on the device until their owner
+// writes them there (d_val, d_sell_val), and no host copy is kept.
 int dm_upload(DevMatrix &M, int32_t m, const int32_t *rp, const int32_t *ci, const double *val,
               int32_t pad_col_base);
 // Choose the tiling (kind_opt: cg_opts.spmv_kind; 4 asks for dictionary

@@ -1,5 +1,8 @@
 // devmatrix.cpp -- a CSR row block on the device with its SpMV schedule.
+#include <omp.h>
+
 #include <algorithm>
+#include <atomic>
 #include <climits>
 #include <cstring>
 
@@ -41,12 +44,25 @@ void free_sliced(DevMatrix &M) {
 // false if some slice has more than kDictSize - 1 distinct offsets or a row
 // longer than kSliceMaxWidth.  dict: kDictSize entries per slice (unused and
 // entry kDictSize-1 are 0); idx: one word of 8 nibbles per lane and slice.
+bool dict_slice(const DevMatrix &M, int32_t t, int32_t *d, uint32_t *idx_t);
+
 bool build_dict(const DevMatrix &M, std::vector<int32_t> &dict, std::vector<uint32_t> &idx) {
     const int32_t m = M.m, nt = (m + kWaveSize - 1) / kWaveSize;
     dict.assign((size_t)nt * kDictSize, 0);
     idx.assign((size_t)nt * kWaveSize, 0);
+    std::atomic<bool> ok{true};
+#pragma omp parallel for schedule(static)
     for (int32_t t = 0; t < nt; ++t) {
-        int32_t *d = &dict[(size_t)t * kDictSize];
+        if (!ok.load(std::memory_order_relaxed)) continue;
+        if (!dict_slice(M, t, &dict[(size_t)t * kDictSize], &idx[(size_t)t * kWaveSize])) ok = false;
+    }
+    return ok.load();
+}
+
+// Dictionary and packed indices of slice t; false if it does not fit.
+bool dict_slice(const DevMatrix &M, int32_t t, int32_t *d, uint32_t *idx_t) {
+    const int32_t m = M.m;
+    {
         int nd = 0;
         for (int32_t l = 0; l < kWaveSize; ++l) {
             const int32_t i = t * kWaveSize + l;
@@ -67,7 +83,7 @@ bool build_dict(const DevMatrix &M, std::vector<int32_t> &dict, std::vector<uint
                 }
                 w |= nib << (4 * j);
             }
-            idx[(size_t)t * kWaveSize + l] = w;
+            idx_t[l] = w;
         }
     }
     return true;
@@ -97,12 +113,14 @@ void build_schedule(const DevMatrix &M, int kind_opt, Schedule &S, std::vector<i
     }
     auto len = [&](int32_t i) -> int64_t { return M.h_rp[i + 1] - M.h_rp[i]; };
     int64_t maxlen = 0;
+#pragma omp parallel for reduction(max : maxlen) schedule(static)
     for (int32_t i = 0; i < m; ++i) maxlen = std::max<int64_t>(maxlen, len(i));
     const double mean = (double)M.h_rp[m] / (double)m;
     if (kind_opt == 0 && !skip_empty) {
         // scattered columns over a vector of at least two blocks: column blocks
         int64_t far = 0;
         int32_t ncols = 0;
+#pragma omp parallel for reduction(+ : far) reduction(max : ncols) schedule(static)
         for (int32_t i = 0; i < m; ++i)
             for (int32_t k = M.h_rp[i]; k < M.h_rp[i + 1]; ++k) {
                 const int64_t d = (int64_t)M.h_ci[k] - (M.pad_col_base + i);
@@ -119,6 +137,7 @@ void build_schedule(const DevMatrix &M, int kind_opt, Schedule &S, std::vector<i
         const int32_t nt = (m + kWaveSize - 1) / kWaveSize;
         int64_t slots = 0;
         int maxw = 0;
+#pragma omp parallel for reduction(+ : slots) reduction(max : maxw) schedule(static)
         for (int32_t t = 0; t < nt; ++t) {
             int64_t w = 0;
             for (int32_t i = t * kWaveSize; i < std::min(m, (t + 1) * kWaveSize); ++i) w = std::max(w, len(i));
@@ -192,20 +211,24 @@ void build_schedule(const DevMatrix &M, int kind_opt, Schedule &S, std::vector<i
 // Slot-major copy in slices of 64 rows padded to the slice's longest row
 // (at least one slot, so every load stays inside the allocation).  Padding
 // slots gather the row's own entry of the vector and are never summed.
-int build_sliced(DevMatrix &M) {
-    if (M.d_sell_off) return CG_OK;
+int build_sliced(DevMatrix &M, bool with_cols) {
+    if (M.d_sell_off && (M.d_sell_ci || !with_cols)) return CG_OK;
     const int32_t m = M.m, nt = M.sched.ntiles;
     std::vector<int32_t> off((size_t)nt + 1, 0);
+#pragma omp parallel for schedule(static)
     for (int32_t t = 0; t < nt; ++t) {
         int32_t w = 0;
         for (int32_t i = t * kWaveSize; i < std::min(m, (t + 1) * kWaveSize); ++i)
             w = std::max(w, M.h_rp[i + 1] - M.h_rp[i]);
-        w = std::max(w, 1);
-        off[t + 1] = off[t] + w * kWaveSize;
+        off[t + 1] = std::max(w, 1) * kWaveSize;
     }
-    const size_t slots = (size_t)off[nt];
-    std::vector<int32_t> sci(slots ? slots : 1, 0);
-    std::vector<double> sval(slots ? slots : 1, 0.0);
+    for (int32_t t = 0; t < nt; ++t) off[t + 1] += off[t];
+    const size_t slots = (size_t)off[nt] ? (size_t)off[nt] : 1;
+    const bool first = !M.d_sell_off;
+    const bool host_vals = !M.h_val.empty();
+    std::vector<int32_t> sci(with_cols ? slots : 0, 0);
+    std::vector<double> sval(first && host_vals ? slots : 0, 0.0);
+#pragma omp parallel for schedule(static)
     for (int32_t t = 0; t < nt; ++t) {
         const int32_t w = (off[t + 1] - off[t]) / kWaveSize;
         for (int32_t l = 0; l < kWaveSize; ++l) {
@@ -215,22 +238,32 @@ int build_sliced(DevMatrix &M) {
             const int32_t pad_col = i < m ? M.pad_col_base + i : M.pad_col_base;
             for (int32_t j = 0; j < w; ++j) {
                 const size_t k = (size_t)off[t] + (size_t)j * kWaveSize + l;
-                sci[k] = j < len ? M.h_ci[b + j] : pad_col;
-                sval[k] = j < len ? M.h_val[b + j] : 0.0;
+                if (with_cols) sci[k] = j < len ? M.h_ci[b + j] : pad_col;
+                if (!sval.empty()) sval[k] = j < len ? M.h_val[b + j] : 0.0;
             }
         }
     }
-    hipError_t e = dmalloc(&M.d_sell_off, off.size());
-    if (e == hipSuccess) e = dmalloc(&M.d_sell_ci, sci.size());
-    if (e == hipSuccess) e = dmalloc(&M.d_sell_val, sval.size());
-    if (e == hipSuccess) e = hipMemcpy(M.d_sell_off, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(M.d_sell_ci, sci.data(), sizeof(int32_t) * sci.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(M.d_sell_val, sval.data(), sizeof(double) * sval.size(), hipMemcpyHostToDevice);
+    hipError_t e = hipSuccess;
+    if (first) {
+        e = dmalloc(&M.d_sell_off, off.size());
+        if (e == hipSuccess) e = dmalloc(&M.d_sell_val, slots);
+        if (e == hipSuccess)
+            e = hipMemcpy(M.d_sell_off, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice);
+        // values from the host copy, or zero until the owner writes them on the device
+        if (e == hipSuccess)
+            e = host_vals ? hipMemcpy(M.d_sell_val, sval.data(), sizeof(double) * slots, hipMemcpyHostToDevice)
+                          : hipMemset(M.d_sell_val, 0, sizeof(double) * slots);
+        M.sell_slots = slots;
+    }
+    if (e == hipSuccess && with_cols) {
+        e = dmalloc(&M.d_sell_ci, slots);
+        if (e == hipSuccess)
+            e = hipMemcpy(M.d_sell_ci, sci.data(), sizeof(int32_t) * slots, hipMemcpyHostToDevice);
+    }
     if (e != hipSuccess) {
         free_sliced(M);
         return fail(CG_ENOMEM, "sliced layout upload failed: %s", hipGetErrorString(e));
     }
-    M.sell_slots = sci.size();
     return CG_OK;
 }
 
@@ -311,7 +344,8 @@ int dm_upload(DevMatrix &M, int32_t m, const int32_t *rp, const int32_t *ci, con
         M.h_rp.resize((size_t)m + 1);
         for (int32_t i = 0; i <= m; ++i) M.h_rp[i] = m > 0 ? rp[i] - base : 0;
         M.h_ci.assign(ci + base, ci + base + M.nnz);
-        M.h_val.assign(val + base, val + base + M.nnz);
+        if (val) M.h_val.assign(val + base, val + base + M.nnz);
+        else M.h_val.clear();
     } catch (...) {
         return fail(CG_ENOMEM, "out of host memory");
     }
@@ -324,8 +358,10 @@ int dm_upload(DevMatrix &M, int32_t m, const int32_t *rp, const int32_t *ci, con
         e = hipMemcpy(M.d_rp, M.h_rp.data(), sizeof(int32_t) * ((size_t)m + 1), hipMemcpyHostToDevice);
     if (e == hipSuccess && M.nnz)
         e = hipMemcpy(M.d_ci, M.h_ci.data(), sizeof(int32_t) * M.nnz, hipMemcpyHostToDevice);
-    if (e == hipSuccess && M.nnz)
-        e = hipMemcpy(M.d_val, M.h_val.data(), sizeof(double) * M.nnz, hipMemcpyHostToDevice);
+    if (e == hipSuccess && M.nnz) {
+        if (val) e = hipMemcpy(M.d_val, M.h_val.data(), sizeof(double) * M.nnz, hipMemcpyHostToDevice);
+        else e = hipMemset(M.d_val, 0, sizeof(double) * M.nnz);
+    }
     // padding (and entry 0 of an empty block): column 0, value 0
     if (e == hipSuccess) e = hipMemset(M.d_ci + M.nnz, 0, sizeof(int32_t) * kStreamNnz);
     if (e == hipSuccess) e = hipMemset(M.d_val + M.nnz, 0, sizeof(double) * kStreamNnz);
@@ -341,7 +377,15 @@ int dm_ensure_f32(DevMatrix &M) {
     if (!M.d_val32) {
         const size_t nv = (size_t)M.nnz + kStreamNnz;
         std::vector<float> v32(nv, 0.0f);
-        for (int64_t k = 0; k < M.nnz; ++k) v32[k] = (float)M.h_val[k];
+        std::vector<double> dv;
+        const double *hv = M.h_val.data();
+        if (M.h_val.empty() && M.nnz) {   // values live on the device only
+            dv.resize((size_t)M.nnz);
+            e = hipMemcpy(dv.data(), M.d_val, sizeof(double) * dv.size(), hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return fail(CG_EDEVICE, "float32 copies: %s", hipGetErrorString(e));
+            hv = dv.data();
+        }
+        for (int64_t k = 0; k < M.nnz; ++k) v32[k] = (float)hv[k];
         e = dmalloc(&M.d_val32, nv);
         if (e == hipSuccess) e = hipMemcpy(M.d_val32, v32.data(), sizeof(float) * nv, hipMemcpyHostToDevice);
     }
@@ -395,7 +439,8 @@ int dm_schedule(DevMatrix &M, int kind_opt, int grid_opt, int cus, int grid_cap,
         }
     }
     if (M.sched.kind == kTileSliced || M.sched.kind == kTileSlicedDict) {
-        const int rc = build_sliced(M);
+        // the dictionary tiles read no columns from the sliced copy
+        const int rc = build_sliced(M, M.sched.kind == kTileSliced);
         if (rc) return rc;
     }
     if (!rows.empty()) {

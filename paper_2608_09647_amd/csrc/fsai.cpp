@@ -12,6 +12,8 @@
 // The learned factor's values come from the network on the device
 // (kernels_fsai.hip); the host only builds the structure (tril(A), its
 // transpose, and the slot-to-position maps) once per handle.
+#include <omp.h>
+
 #include <algorithm>
 #include <climits>
 #include <cmath>
@@ -68,7 +70,8 @@ void transpose(int32_t n, const int32_t *rp, const int32_t *ci, const double *va
         }
 }
 
-// Upload G and G^T (schedules chosen automatically) and the work vectors.
+// Upload G and G^T (schedules chosen automatically) and the work vectors;
+// g_val null: the values are written on the device later.
 int install_factor(cg_handle *h, const int32_t *g_rp, const int32_t *g_ci, const double *g_val,
                    std::vector<int32_t> *tpos) {
     HostCsr T;
@@ -80,7 +83,7 @@ int install_factor(cg_handle *h, const int32_t *g_rp, const int32_t *g_ci, const
     h->have_factor = false;
     int rc = dm_upload(h->G, h->n, g_rp, g_ci, g_val, 0);
     if (!rc) rc = dm_schedule(h->G, 0, 0, h->cus, h->grid_cap, false);
-    if (!rc) rc = dm_upload(h->GT, h->n, T.rp.data(), T.ci.data(), T.val.data(), 0);
+    if (!rc) rc = dm_upload(h->GT, h->n, T.rp.data(), T.ci.data(), g_val ? T.val.data() : nullptr, 0);
     if (!rc) rc = dm_schedule(h->GT, 0, 0, h->cus, h->grid_cap, false);
     if (rc) return rc;
     if (!h->d_t) {
@@ -248,30 +251,54 @@ namespace {
 int build_learned_structure(cg_handle *h) {
     const int32_t n = h->n;
     std::vector<int32_t> g_rp, g_ci, gpos, tpos;
-    std::vector<double> zeros;
     try {
         g_rp.assign((size_t)n + 1, 0);
         gpos.assign((size_t)n * 3, -1);
+        // pass 1 (rows in parallel): check the stencil, count tril entries;
+        // the first offending row is reported
+        int32_t bad_row = INT32_MAX, bad_kind = 0;
+#pragma omp parallel for schedule(static)
         for (int32_t i = 0; i < n; ++i) {
             int seen[kSlots] = {0, 0, 0, 0, 0};
+            int kind = 0, cnt = 0;
             for (int32_t k = h->h_rp[i]; k < h->h_rp[i + 1]; ++k) {
                 const int s = stencil_slot(i, h->h_ci[k]);
-                if (seen[s]++) return fail(CG_EINVAL, "row %d is not a 5-point stencil row", i);
+                if (seen[s]++) kind = 1;
                 if (h->h_ci[k] > i) continue;
-                if (s == kSlotC && !(h->h_val[k] > 0.0))
-                    return fail(CG_EINVAL, "diagonal of row %d is not positive", i);
-                const int m = s == kSlotC ? 0 : s == kSlotW ? 1 : 2;
-                gpos[(size_t)i * 3 + m] = (int32_t)g_ci.size();
-                g_ci.push_back(h->h_ci[k]);
+                if (s == kSlotC && !(h->h_val[k] > 0.0)) kind = kind ? kind : 2;
+                ++cnt;
             }
-            if (!seen[kSlotC]) return fail(CG_EINVAL, "row %d has no diagonal entry", i);
-            g_rp[i + 1] = (int32_t)g_ci.size();
+            if (!seen[kSlotC] && !kind) kind = 3;
+            g_rp[i + 1] = cnt;
+            if (kind) {
+#pragma omp critical(cgmi_fsai_bad_row)
+                if (i < bad_row) {
+                    bad_row = i;
+                    bad_kind = kind;
+                }
+            }
         }
-        zeros.assign(g_ci.size(), 0.0);
+        if (bad_kind == 1) return fail(CG_EINVAL, "row %d is not a 5-point stencil row", bad_row);
+        if (bad_kind == 2) return fail(CG_EINVAL, "diagonal of row %d is not positive", bad_row);
+        if (bad_kind == 3) return fail(CG_EINVAL, "row %d has no diagonal entry", bad_row);
+        for (int32_t i = 0; i < n; ++i) g_rp[i + 1] += g_rp[i];
+        g_ci.resize((size_t)g_rp[n]);
+        // pass 2: columns and slot positions
+#pragma omp parallel for schedule(static)
+        for (int32_t i = 0; i < n; ++i) {
+            int32_t p = g_rp[i];
+            for (int32_t k = h->h_rp[i]; k < h->h_rp[i + 1]; ++k) {
+                if (h->h_ci[k] > i) continue;
+                const int s = stencil_slot(i, h->h_ci[k]);
+                const int m = s == kSlotC ? 0 : s == kSlotW ? 1 : 2;
+                gpos[(size_t)i * 3 + m] = p;
+                g_ci[p++] = h->h_ci[k];
+            }
+        }
     } catch (...) {
         return fail(CG_ENOMEM, "out of host memory");
     }
-    int rc = install_factor(h, g_rp.data(), g_ci.data(), zeros.data(), &tpos);
+    int rc = install_factor(h, g_rp.data(), g_ci.data(), nullptr, &tpos);   // values come from the device
     if (rc) return rc;
     FsaiSetup *f = new (std::nothrow) FsaiSetup();
     if (!f) return fail(CG_ENOMEM, "out of host memory");
