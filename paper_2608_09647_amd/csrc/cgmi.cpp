@@ -103,7 +103,7 @@ static void free_device(cg_handle *h) {
     dm_free(h->A);
     dm_free(h->G);
     dm_free(h->GT);
-    hipFree(h->d_t); hipFree(h->d_z);
+    hipFree(h->d_t); hipFree(h->d_z); hipFree(h->d_r2);
     hipFree(h->d_r32); hipFree(h->d_p32); hipFree(h->d_q32);
     hipFree(h->d_pbuf); hipFree(h->d_x); hipFree(h->d_r); hipFree(h->d_q);
     hipFree(h->d_part_setup); hipFree(h->d_part_pq); hipFree(h->d_part_rr); hipFree(h->d_part_rz);

@@ -122,6 +122,8 @@ struct cg_handle {
     cgmi::DevMatrix G, GT;
     bool have_factor = false;
     double *d_t = nullptr, *d_z = nullptr;
+    double *d_r2 = nullptr;            // second r buffer of the fused x/r + G kernel
+    int g_width = 0;                   // G's longest row rounded up to 1, 2, 4, 8 (0: not fused)
     struct FsaiSetup *fsai = nullptr;   // learned-factor workspace (fsai.cpp)
 
     // split mode

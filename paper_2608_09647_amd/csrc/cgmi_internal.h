@@ -188,6 +188,17 @@ hipError_t launch_update_p(int32_t m, int grid, const double *r, double *p_own, 
                            DevState *st, int device_coef, int32_t k, double beta_arg,
                            hipStream_t s);
 
+// Preconditioned CG, x/r update fused with t = G r_new for a factor G of at
+// most `width` <= kFusedGWidth entries per row (CSR grp/gci/gval, rows
+// rebased, columns < m): x += alpha p, r_new = r_old - alpha q (another buffer than r_old),
+// t = G r_new, out_partials[wg] = sum r_new_i^2; alpha = rho_k / sum(pq),
+// breakdown recorded in st as by launch_update_xr.
+constexpr int kFusedGWidth = 8;
+hipError_t launch_pcg_xr_g(int32_t m, int grid, int width, const int32_t *grp, const int32_t *gci,
+                           const double *gval, double *x, const double *r_old, double *r_new, const double *p,
+                           const double *q, double *t, double *out_partials, Partials pq, DevState *st, int32_t k,
+                           hipStream_t s);
+
 // Preconditioned CG (z = M^-1 r): p = z + beta p, rho = r^T z from the rz
 // partials, the stop test on the rr partials; first = 1 is the setup step
 // (rho_0, ||b||^2 from bb, stop test at the top of iteration 0, p = z).

@@ -2,9 +2,10 @@
 //
 // The solve is the CG recurrence of Algorithm 1 with the preconditioned
 // residual z = G^T (G r): rho = r^T z drives alpha and beta, the stop test
-// stays on ||r|| / ||b||.  One iteration is five kernels on the stream:
-//   q = A p (p^T q partials); x += alpha p, r -= alpha q (r^T r partials);
-//   t = G r; z = G^T t (r^T z partials); p = z + beta p (stop test).
+// stays on ||r|| / ||b||.  One iteration is four kernels on the stream:
+//   q = A p (p^T q partials); x += alpha p, r -= alpha q with t = G r in the
+//   same kernel (r^T r partials; G rows of at most 8 entries, else two
+//   kernels); z = G^T t (r^T z partials); p = z + beta p (stop test).
 // As in the unpreconditioned solve every scalar is reduced from the previous
 // kernel's per-workgroup partials, so alpha, beta and the decisions never
 // leave the device; the host polls the state every check_every iterations.
@@ -89,8 +90,14 @@ int install_factor(cg_handle *h, const int32_t *g_rp, const int32_t *g_ci, const
     if (!h->d_t) {
         hipError_t e = dmalloc(&h->d_t, (size_t)h->n + 2);
         if (e == hipSuccess) e = dmalloc(&h->d_z, (size_t)h->n + 2);
+        if (e == hipSuccess) e = dmalloc(&h->d_r2, (size_t)h->n + 2);
         if (e != hipSuccess) return fail(CG_ENOMEM, "preconditioner vectors: %s", hipGetErrorString(e));
     }
+    int32_t maxlen = 0;
+    for (int32_t i = 0; i < h->n; ++i) maxlen = std::max(maxlen, g_rp[i + 1] - g_rp[i]);
+    h->g_width = 0;
+    for (int w = 1; w <= kFusedGWidth && !h->g_width; w <<= 1)
+        if (maxlen <= w) h->g_width = w;
     return CG_OK;
 }
 
@@ -147,6 +154,7 @@ int solve_gpu_pcg(cg_handle *h, const double *b, double *x, double tol, int32_t 
         ev.resize(2 * (size_t)C);
         for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
     }
+    double *const rbuf[2] = {h->d_r, h->d_r2};   // r of iterations k (even) and k (odd)
     int32_t k = 0;
     bool running = maxit > 0;
     if (!running) rc = gpu_state_read(h);
@@ -158,11 +166,20 @@ int solve_gpu_pcg(cg_handle *h, const double *b, double *x, double tol, int32_t 
             HIP_TRY(launch_spmv(h->A.dev(), h->A.sched, Ga, h->d_p, h->d_q, h->d_p, nullptr, nullptr,
                                 h->d_part_pq, none, none, h->d_state, kSpmvDot, 0, st));
             if (h->opts.profile) HIP_TRY(hipEventRecord(ev[2 * j + 1], st));
-            HIP_TRY(launch_update_xr(n, Gv, h->d_x, h->d_r, h->d_p, h->d_q, h->d_part_rr, pq, h->d_state, 1,
-                                     kk, 0.0, st));
-            HIP_TRY(launch_spmv(h->G.dev(), h->G.sched, Gg, h->d_r, h->d_t, nullptr, nullptr, nullptr,
-                                nullptr, none, none, h->d_state, kSpmvPlain, 0, st));
-            HIP_TRY(launch_spmv(h->GT.dev(), h->GT.sched, Gt, h->d_t, h->d_z, h->d_r, nullptr, nullptr,
+            double *r_now = h->d_r;
+            if (h->g_width) {
+                // x/r update and t = G r in one kernel; r alternates between two buffers
+                const double *r_old = rbuf[kk & 1];
+                r_now = rbuf[(kk + 1) & 1];
+                HIP_TRY(launch_pcg_xr_g(n, Gv, h->g_width, h->G.d_rp, h->G.d_ci, h->G.d_val, h->d_x, r_old, r_now,
+                                        h->d_p, h->d_q, h->d_t, h->d_part_rr, pq, h->d_state, kk, st));
+            } else {
+                HIP_TRY(launch_update_xr(n, Gv, h->d_x, h->d_r, h->d_p, h->d_q, h->d_part_rr, pq, h->d_state, 1,
+                                         kk, 0.0, st));
+                HIP_TRY(launch_spmv(h->G.dev(), h->G.sched, Gg, h->d_r, h->d_t, nullptr, nullptr, nullptr,
+                                    nullptr, none, none, h->d_state, kSpmvPlain, 0, st));
+            }
+            HIP_TRY(launch_spmv(h->GT.dev(), h->GT.sched, Gt, h->d_t, h->d_z, r_now, nullptr, nullptr,
                                 h->d_part_rz, none, none, h->d_state, kSpmvDot, 0, st));
             HIP_TRY(launch_update_p_pcg(n, Gv, h->d_z, h->d_p, rr, rz, none, h->d_state, 0, kk, st));
         }

@@ -680,6 +680,65 @@ __global__ __launch_bounds__(kBlock) void k_blocked_finish(int32_t m, SpmvArgs<T
     }
 }
 
+// Preconditioned CG: the x/r update fused with t = G r_new (G of at most W
+// entries per row, CSR; W = 1, 2, 4 or 8).  Thread per row: r_new = r - alpha q
+// and x += alpha p for the row (r_new into the other r buffer, so neighbours
+// still read r), and t_i = sum_k G_ik r_new_k with r_new_k formed on the fly
+// by the same fma as its owner (identical bits), summed in CSR order with
+// rounded products; partial r_new^T r_new per workgroup.  alpha and the
+// breakdown test as in k_update_xr.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_pcg_xr_g(int32_t m, const int32_t *__restrict__ grp,
+                                                     const int32_t *__restrict__ gci,
+                                                     const double *__restrict__ gval, double *__restrict__ x,
+                                                     const double *__restrict__ r_old, double *__restrict__ r_new,
+                                                     const double *__restrict__ p, const double *__restrict__ q,
+                                                     double *__restrict__ t, double *__restrict__ out,
+                                                     Partials pq_in, DevState *__restrict__ st, int32_t k) {
+    __shared__ double sh[kWavesPerBlock];
+    __shared__ double bc;
+    if (st->done) return;
+    const double pq = reduce_partials(pq_in, sh, &bc);
+    if (!(pq > 0.0) || !isfinite(pq)) {
+        if (is_block0_thread0()) {
+            st->pq = pq;
+            st->iter = k;
+            st->done = kDoneBreakdown;
+        }
+        return;
+    }
+    const double alpha = st->rho[k & 1] / pq;
+    if (is_block0_thread0()) st->pq = pq;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += (int64_t)gridDim.x * kBlock) {
+        const double rv = fma(-alpha, q[i], r_old[i]);
+        x[i] = fma(alpha, p[i], x[i]);
+        r_new[i] = rv;
+        acc = fma(rv, rv, acc);
+        const int k0 = grp[i], len = grp[i + 1] - k0;
+        int c[W];
+        double w[W], rn[W];
+#pragma unroll
+        for (int e = 0; e < W; ++e) {
+            const int kk = k0 + (e < len ? e : 0);
+            c[e] = gci[kk];
+            w[e] = gval[kk];
+        }
+#pragma unroll
+        for (int e = 0; e < W; ++e) rn[e] = fma(-alpha, q[c[e]], r_old[c[e]]);
+        double s = 0.0;
+        {
+#pragma clang fp contract(off)
+#pragma unroll
+            for (int e = 0; e < W; ++e)
+                if (e < len) s = s + w[e] * rn[e];
+        }
+        t[i] = s;
+    }
+    const double s = block_sum<kBlock>(acc, sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
 // x += alpha p, r -= alpha q; partial r^T r per workgroup.
 __global__ __launch_bounds__(kBlock) void k_update_xr(int32_t m, double *__restrict__ x,
                                                       double *__restrict__ r,
@@ -1189,6 +1248,23 @@ hipError_t launch_update_p(int32_t m, int grid, const double *r, double *p_own, 
     if (m == 0) return hipSuccess;
     hipLaunchKernelGGL(k_update_p, dim3(grid), dim3(kBlock), 0, s, m, r, p_own, rr, st, device_coef,
                        k, beta_arg);
+    return hipGetLastError();
+}
+
+hipError_t launch_pcg_xr_g(int32_t m, int grid, int width, const int32_t *grp, const int32_t *gci,
+                           const double *gval, double *x, const double *r_old, double *r_new, const double *p,
+                           const double *q, double *t, double *out_partials, Partials pq, DevState *st, int32_t k,
+                           hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    if (width < 0 || width > kFusedGWidth) return hipErrorInvalidValue;
+#define CGMI_PCG_XR_G(W)                                                                            \
+    hipLaunchKernelGGL(k_pcg_xr_g<W>, dim3(grid), dim3(kBlock), 0, s, m, grp, gci, gval, x, r_old, r_new, p, \
+                       q, t, out_partials, pq, st, k)
+    if (width <= 1) CGMI_PCG_XR_G(1);
+    else if (width <= 2) CGMI_PCG_XR_G(2);
+    else if (width <= 4) CGMI_PCG_XR_G(4);
+    else CGMI_PCG_XR_G(8);
+#undef CGMI_PCG_XR_G
     return hipGetLastError();
 }
 
