@@ -442,7 +442,10 @@ static int solve_gpu_only(cg_handle *h, const double *b, double *x, double tol, 
     int n_spmv = 0;
     const double t0 = now();
     if (small) {
-        HIP_TRY(launch_cg_small(n, h->A.d_rp, h->A.d_ci, h->A.d_val, b, h->d_x, tol, maxit, h->d_state, st));
+        int32_t max_len = 0;
+        for (int32_t i = 0; i < n; ++i) max_len = std::max(max_len, h->A.h_rp[i + 1] - h->A.h_rp[i]);
+        HIP_TRY(launch_cg_small(n, h->A.d_rp, h->A.d_ci, h->A.d_val, b, h->d_x, tol, maxit, h->d_state,
+                                max_len, st));
         rc = gpu_state_read(h);
         if (rc) return rc;
     } else {

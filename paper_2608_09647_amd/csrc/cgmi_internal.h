@@ -210,7 +210,7 @@ hipError_t launch_update_p_pcg(int32_t m, int grid, const double *z, double *p, 
 int small_path_max_rows();
 hipError_t launch_cg_small(int32_t n, const int32_t *rp, const int32_t *ci, const double *val,
                            const double *b, double *x, double tol, int32_t maxit, DevState *st,
-                           hipStream_t s);
+                           int32_t max_row_len, hipStream_t s);
 
 // Gather / scatter of p entries for the halo exchange.
 hipError_t launch_gather(int32_t cnt, const int32_t *idx, const double *src, double *dst,

@@ -257,6 +257,69 @@ def test_cg_matches_oracle(cg, name, small_path):
     check_cg(p.A, p.b, host(x), res, ref, 1e-10, kappa_of(name, p.A))
 
 
+
+# One case per single-workgroup variant: rows per thread (n up to 1024, 2048,
+# 4096) x longest row (register-resident rows up to 8 / 24, 8 / 12, 5 entries,
+# else the CSR variant that reads the rows from memory at every product).
+# The random matrices take diagonal shift 1 (condition numbers of a few
+# hundred).  Fixed-work iterates are compared against the oracle's with a bar
+# of 4x the distance between two other correct float64 CGs (the oracle's and
+# one with scipy products and BLAS dots): rows of hundreds of entries whose
+# diagonal cancels their off-diagonal sum move the iterates by ~1e-9 under a
+# mere change of summation order.
+SMALL_CASES = {
+    "rpt1_len5": (1, 5, 5, "poisson2d", lambda: I.poisson2d(30)),
+    "rpt1_len9_24": (1, 9, 24, "random", lambda: I.random_spd_lognormal(1000, 1, mean_degree=6, sigma=0.3,
+                                                                      max_degree=8, shift=1.0)),
+    "rpt1_csr": (1, 25, 10**9, "random", lambda: I.random_spd_lognormal(1000, 0, shift=1.0)),
+    "rpt2_len7": (2, 1, 8, "poisson3d", lambda: I.poisson3d(12)),
+    "rpt2_len9_12": (2, 9, 12, "random", lambda: I.random_spd_lognormal(2000, 1, mean_degree=2, sigma=0.2,
+                                                                      max_degree=3, shift=1.0)),
+    "rpt2_csr": (2, 13, 10**9, "random", lambda: I.random_spd_lognormal(2000, 0, shift=1.0)),
+    "rpt4_len5": (4, 1, 5, "poisson2d", lambda: I.poisson2d(60)),
+    "rpt4_csr": (4, 6, 10**9, "poisson3d", lambda: I.poisson3d(15)),
+}
+
+
+@pytest.mark.parametrize("name", list(SMALL_CASES))
+def test_small_path_variants_match_oracle(cg, name):
+    rpt, lo, hi, family, make = SMALL_CASES[name]
+    A = make()
+    L = int(np.diff(A.row_ptr).max())
+    assert -(-A.n // 1024) == rpt and lo <= L <= hi, (A.n, L)   # the case reaches the intended variant
+    xs = I.uniform_vector(A.n, [17, 1])
+    b = I.rhs_of(A, xs)
+    print(f"[small] {name} n={A.n} longest row {L}", flush=True)
+    if family == "random":   # diagonal shift 1: smallest eigenvalue 1, Gershgorin above
+        kappa = np.max(np.add.reduceat(np.abs(A.val), A.row_ptr[:-1]))
+    else:
+        kappa = kappa_of(family, A)
+    ref = oracle.cg(A, b, tol=1e-10, maxit=20000)
+    fixed = oracle.cg(A, b, tol=0.0, maxit=30)
+    S = A.scipy()
+    xa, r, rho = np.zeros(A.n), b.copy(), b @ b
+    pa = r.copy()
+    for _ in range(30):
+        q = S @ pa
+        alpha = rho / (pa @ q)
+        xa += alpha * pa
+        r -= alpha * q
+        rho, rho_old = r @ r, rho
+        pa = r + (rho / rho_old) * pa
+    spread = np.linalg.norm(xa - fixed["x"]) / np.linalg.norm(fixed["x"])
+    spread_res = abs(np.sqrt(rho) / np.linalg.norm(b) - fixed["rel_res_recur"]) / fixed["rel_res_recur"]
+    with cg.Solver(A) as s:
+        s.set_opts(small_path=1)
+        x, res = s.solve(dev(b), tol=1e-10, maxit=20000)
+        check_cg(A, b, host(x), res, ref, 1e-10, kappa)
+        x, res = s.solve(dev(b), tol=0.0, maxit=30)
+        assert res["iterations"] == 30 and res["status"] == oracle.MAXIT
+        x = host(x)
+        assert np.linalg.norm(x - fixed["x"]) / np.linalg.norm(fixed["x"]) <= max(1e-11, 4 * spread), spread
+        assert (abs(res["rel_res_recur"] - fixed["rel_res_recur"])
+                <= max(1e-8, 4 * spread_res) * fixed["rel_res_recur"]), spread_res
+
+
 def test_cg_fixed_work_tracks_oracle(cg):
     p = I.poisson3d_problem(32)
     ref = oracle.cg(p.A, p.b, tol=0.0, maxit=60)
