@@ -153,8 +153,12 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="poisson3d_256",
                     choices=["poisson3d_256", "poisson3d_256_split", "poisson2d_64", "random_spd_2m",
-                             "diffusion_1024", "batch_256"])
+                             "diffusion_1024", "batch_256", "split_sweep"])
     ap.add_argument("--share", type=float, default=0.5, help="GPU row share for the split config")
+    ap.add_argument("--sweep-matrix", default="poisson3d_256", choices=["poisson3d_256", "random_spd_2m"],
+                    help="system of the split_sweep config")
+    ap.add_argument("--by-nnz", action="store_true",
+                    help="split_sweep: place the split at a share of the nonzeros instead of the rows")
     ap.add_argument("--iters", type=int, default=500, help="fixed CG iterations per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--train-steps", type=int, default=2000, help="learned-FSAI training steps")
@@ -183,6 +187,8 @@ def main() -> int:
         return bench_small(args)
     if args.config == "poisson3d_256_split":
         return bench_split(args)
+    if args.config == "split_sweep":
+        return bench_split_sweep(args)
     t0 = time.perf_counter()
     prob = I.poisson3d_problem(256, seed=2)
     A = prob.A
@@ -302,34 +308,131 @@ def bench_small(args) -> int:
     return 0
 
 
-def bench_split(args) -> int:
-    """256^3 Poisson with the GPU owning the first share of rows and host
-    threads the rest, p exchanged every iteration (whole segments and halo)."""
+SPLIT_MODES = (("whole", 0), ("halo", 1), ("mapped", 2), ("managed", 3))
+
+
+def _split_run(cgmi, s, b, iters, warmup, steps, exchange):
+    """Fixed-work split solves in one memory mode; None when the mode is not
+    available on this device (the library's error message instead)."""
     import numpy as np
     import torch
-    from paper_2608_09647_amd import inputs as I, cgmi
+    try:
+        s.set_opts(exchange=exchange)
+    except cgmi.CgError as e:
+        return {"unavailable": str(e)}
+    _timed_solve(s, b, torch.zeros_like(b), 0.0, iters, max(1, warmup))
+    _, res, times = _timed_solve(s, b, torch.zeros_like(b), 0.0, iters, steps)
+    sec = float(np.mean(times))
+    return {"seconds": sec, "seconds_per_iter": sec / iters, "iter_per_s": iters / sec,
+            **{k: res[k] for k in ("iterations", "t_gpu", "t_cpu", "t_barrier", "t_d2h", "t_h2d",
+                                    "rows_gpu", "rows_cpu", "nnz_gpu", "nnz_cpu")}}
+
+
+def bench_split(args) -> int:
+    """256^3 Poisson with the GPU owning the first share of rows and host
+    threads the rest; p made visible by each memory mode of Section 3.4
+    (explicit copy of whole segments or of the halo, mapped host memory,
+    managed memory where the device supports it)."""
+    import numpy as np
+    import torch
+    from paper_2608_09647_amd import inputs as I, cgmi, split
     prob = I.poisson3d_problem(256, seed=2)
     n = prob.A.n
-    n_gpu = int(np.floor(args.share * n + 0.5))
+    n_gpu = split.rows_for_share(n, args.share)
     iters = min(args.iters, 50)
     b = torch.from_numpy(prob.b).cuda()
     res_all = {}
-    for name, ex in (("whole", 0), ("halo", 1)):
-        s = cgmi.Solver(prob.A, 0, n_gpu)
-        s.set_opts(exchange=ex)
-        _timed_solve(s, b, torch.zeros_like(b), 0.0, iters, max(1, args.warmup))
-        _, res, times = _timed_solve(s, b, torch.zeros_like(b), 0.0, iters, args.steps)
-        res_all[name] = {"seconds": float(np.mean(times)), "iter_per_s": iters / float(np.mean(times)),
-                         **{k: res[k] for k in ("t_gpu", "t_cpu", "t_barrier", "t_d2h", "t_h2d",
-                                                 "rows_gpu", "rows_cpu", "nnz_gpu", "nnz_cpu")}}
-        s.close()
-        print(f"[bench] split {name}: {res_all[name]}", file=sys.stderr, flush=True)
-    best = max(res_all.values(), key=lambda r: r["iter_per_s"])
-    line = _line("CG iters/s, split rows (GPU share + host complement, explicit p exchange)",
+    with cgmi.Solver(prob.A, 0, n_gpu) as s:
+        for name, ex in SPLIT_MODES:
+            res_all[name] = _split_run(cgmi, s, b, iters, args.warmup, args.steps, ex)
+            print(f"[bench] split {name}: {res_all[name]}", file=sys.stderr, flush=True)
+    ran = {k: v for k, v in res_all.items() if "seconds" in v}
+    best = max(ran.values(), key=lambda r: r["iter_per_s"])
+    line = _line("CG iters/s, split rows (GPU share + host complement, p made visible each iteration)",
                  best["iter_per_s"], "iter/s", args, 1e3 * best["seconds"],
                  {"workload": f"poisson3d_7pt_256^3_fp64_cg_split_g{args.share}",
                   "n": n, "nnz": prob.A.nnz, "iterations_per_step": iters,
-                  "row_share_gpu": args.share}, exchange=res_all)
+                  "row_share_gpu": args.share}, exchange=res_all,
+                 best_mode=max(ran, key=lambda k: ran[k]["iter_per_s"]))
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def bench_split_sweep(args) -> int:
+    """The paper's protocol on one synthetic system: every GPU row share of
+    the sweep under every memory mode (Section 4.1), fixed work, the 1.25x
+    competitive classification, and the planner's automatic choice fitted
+    from the g = 0.5 runs alone, checked against the sweep."""
+    import numpy as np
+    import torch
+    from paper_2608_09647_amd import inputs as I, cgmi, split
+    if args.sweep_matrix == "random_spd_2m":
+        prob = I.random_spd_problem(2_000_000, seed=3)
+    else:
+        prob = I.poisson3d_problem(256, seed=2)
+    A, n = prob.A, prob.A.n
+    iters = min(args.iters, 30)
+    steps = max(1, min(args.steps, 2))
+    b = torch.from_numpy(prob.b).cuda()
+    rows_fn = (lambda g: split.rows_for_nnz_share(A.row_ptr, g)) if args.by_nnz else \
+        (lambda g: split.rows_for_share(n, g))
+    managed_ok = None
+    sweep = {}
+    for g in split.SHARES:
+        rows = rows_fn(g)
+        if rows == 0:
+            modes = (("host", 0),)
+        elif rows == n:
+            modes = (("device", 0), ("mapped", 2), ("managed", 3))
+        else:
+            modes = SPLIT_MODES
+        with cgmi.Solver(A, 0, rows) as s:
+            s.set_opts(host_threads=0)
+            for name, ex in modes:
+                if name == "managed" and managed_ok is False:
+                    continue
+                r = _split_run(cgmi, s, b, iters, 1, steps, ex)
+                if name == "managed" and managed_ok is None:
+                    managed_ok = "seconds" in r
+                if "seconds" in r:
+                    sweep[f"g{g:.2f}/{name}"] = {"share": g, "mode": name, **r}
+                    print(f"[bench] sweep g={g:.2f} {name}: {1e3 * r['seconds_per_iter']:.2f} ms/iter",
+                          file=sys.stderr, flush=True)
+    times = {k: v["seconds_per_iter"] for k, v in sweep.items()}
+    flags = split.competitive(times)
+    for k in sweep:
+        sweep[k]["competitive"] = flags[k]
+    best_key = min(times, key=times.get)
+    # planner: models fitted from the g = 0.5 runs only
+    models = {}
+    for name, _ in SPLIT_MODES:
+        r = sweep.get(f"g0.50/{name}")
+        if r is not None:
+            models[name] = split.IterationModel.fit(r, r["seconds"], A.nnz)
+    choice = split.choose_config(models, A.row_ptr, by_nnz=args.by_nnz)
+    g_c = choice["share"]
+    mode_c = choice["mode"]
+    if g_c == 0.0:
+        key_c = "g0.00/host"
+    elif g_c == 1.0:
+        key_c = f"g1.00/{'mapped' if mode_c in ('mapped', 'managed') else 'device'}"
+    else:
+        key_c = f"g{g_c:.2f}/{mode_c}"
+    measured_c = times.get(key_c)
+    auto = {"mode": mode_c, "share": g_c, "rows_gpu": choice["rows_gpu"],
+            "predicted_seconds_per_iter": choice["predicted"], "measured_key": key_c,
+            "measured_seconds_per_iter": measured_c,
+            "ratio_to_best": None if measured_c is None else measured_c / times[best_key],
+            "competitive": None if measured_c is None else flags[key_c],
+            "models": {m: vars(md) for m, md in models.items()}}
+    print(f"[bench] best {best_key}; planner chose {key_c} ({auto['ratio_to_best']})", file=sys.stderr,
+          flush=True)
+    line = _line("CG iters/s, best configuration of the GPU-share x memory-mode sweep",
+                 1.0 / times[best_key], "iter/s", args, 1e3 * iters * times[best_key],
+                 {"workload": f"{prob.name}_split_sweep", "n": n, "nnz": A.nnz,
+                  "iterations_per_solve": iters, "shares": list(split.SHARES),
+                  "split_by": "nnz" if args.by_nnz else "rows"},
+                 best=best_key, managed_supported=bool(managed_ok), sweep=sweep, planner=auto)
     print(json.dumps(line), flush=True)
     return 0
 

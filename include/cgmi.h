@@ -6,8 +6,9 @@
  * x += alpha p, r -= alpha q, r^T r update, and p = r + beta p
  * (Algorithm 1).  A contiguous block of rows [row_begin, row_end) runs on the
  * GPU; the remaining rows (the host complement) run on host threads, and the
- * shared search direction p is exchanged by explicit copies every iteration
- * (Section 3.2 row split, Section 3.4 explicit-copy mode).
+ * shared search direction p is made visible to both sides every iteration by
+ * explicit copies, or held once in mapped host memory or managed memory
+ * (Section 3.2 row split, Section 3.4 memory execution modes).
  *
  * Conventions for every entry point
  *   - Matrices: CSR, int32 row pointers and column indices, float64 values,
@@ -46,7 +47,12 @@ enum {
 
 enum { CG_PREC_FP64 = 0, CG_PREC_MIXED = 1 };         /* cg_opts.precision */
 enum { CG_PC_NONE = 0, CG_PC_FSAI = 1 };              /* cg_opts.precond   */
-enum { CG_EXCHANGE_WHOLE = 0, CG_EXCHANGE_HALO = 1 };  /* cg_opts.exchange  */
+enum {                                                /* cg_opts.exchange  */
+    CG_EXCHANGE_WHOLE = 0,
+    CG_EXCHANGE_HALO = 1,
+    CG_EXCHANGE_MAPPED = 2,
+    CG_EXCHANGE_MANAGED = 3
+};
 
 typedef struct cg_handle cg_handle;
 
@@ -58,10 +64,26 @@ typedef struct cg_opts {
                               updates).  GPU-only handles.                       */
     int32_t precond;       /* CG_PC_NONE, or CG_PC_FSAI: M^-1 = G^T G with the
                               factor installed by cg_set_fsai.  GPU-only.        */
-    int32_t exchange;      /* split mode: CG_EXCHANGE_WHOLE copies the whole
-                              GPU-owned / host-owned segments of p each
-                              iteration (Section 3.4); CG_EXCHANGE_HALO copies
-                              only the entries the other side's rows read.      */
+    int32_t exchange;      /* how p is made visible to the GPU and the host
+                              (Section 3.4 memory execution modes).
+                              CG_EXCHANGE_WHOLE: separate host and device
+                              copies; the whole GPU-owned / host-owned segments
+                              are copied each iteration (explicit copy).
+                              CG_EXCHANGE_HALO: explicit copy of only the
+                              entries the other side's rows read.
+                              CG_EXCHANGE_MAPPED: one copy of p in page-locked,
+                              coherent host memory; kernels read and write it
+                              through its device address, host threads through
+                              its host address; nothing is copied.
+                              CG_EXCHANGE_MANAGED: one copy of p in managed
+                              memory (hipMallocManaged), used in place by both
+                              sides; CG_EINVAL where the device reports no
+                              managed-memory support.
+                              MAPPED and MANAGED hold p in that memory for
+                              GPU-only handles too (then the single-workgroup
+                              path, which keeps p in LDS, is not used); they
+                              need CG_PREC_FP64 and CG_PC_NONE.  cg_set_opts
+                              allocates the shared p when the mode is chosen. */
     int32_t host_threads;  /* host complement threads (0: all available)        */
     int32_t check_every;   /* GPU-only: iterations queued between host polls of
                               the device convergence flag (>= 1)                */

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcgmi.so"
 CG_OK, CG_MAXIT, CG_EINVAL, CG_ENOMEM, CG_EDEVICE, CG_EBREAKDOWN = 0, 1, -1, -2, -3, -4
 PREC_FP64, PREC_MIXED = 0, 1
 PC_NONE, PC_FSAI = 0, 1
-EXCHANGE_WHOLE, EXCHANGE_HALO = 0, 1
+EXCHANGE_WHOLE, EXCHANGE_HALO, EXCHANGE_MAPPED, EXCHANGE_MANAGED = 0, 1, 2, 3
 
 # Every symbol the public header declares (checked by the tests).
 EXPORTED = ["cg_create", "cg_destroy", "cg_set_stream", "cg_default_opts", "cg_set_opts",

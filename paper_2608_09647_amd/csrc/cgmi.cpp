@@ -98,7 +98,47 @@ static int ensure_mixed_vectors(cg_handle *h) {
     return CG_OK;
 }
 
+static void free_shared_p(cg_handle *h) {
+    if (h->shared_mode == CG_EXCHANGE_MAPPED && h->h_pshared) hipHostFree(h->h_pshared);
+    if (h->shared_mode == CG_EXCHANGE_MANAGED && h->d_pshared) hipFree(h->d_pshared);
+    h->h_pshared = h->d_pshared = nullptr;
+    h->shared_mode = -1;
+}
+
+// Allocate p where the host and the GPU both address it (Section 3.4 mapped
+// and managed modes): page-locked coherent host memory mapped into the
+// device's address space, or managed memory.  Zero-filled by the host.
+static int ensure_shared_p(cg_handle *h, int mode) {
+    if (h->shared_mode == mode) return CG_OK;
+    free_shared_p(h);
+    const size_t bytes = sizeof(double) * ((size_t)h->n + 2);
+    if (mode == CG_EXCHANGE_MAPPED) {
+        void *hp = nullptr, *dp = nullptr;
+        if (hipHostMalloc(&hp, bytes, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
+            return fail(CG_ENOMEM, "mapped host allocation of p failed");
+        if (hipHostGetDevicePointer(&dp, hp, 0) != hipSuccess) {
+            hipHostFree(hp);
+            return fail(CG_EDEVICE, "no device address for the mapped p");
+        }
+        h->h_pshared = static_cast<double *>(hp);
+        h->d_pshared = static_cast<double *>(dp);
+    } else {
+        int managed = 0;
+        HIP_TRY(hipDeviceGetAttribute(&managed, hipDeviceAttributeManagedMemory, h->dev));
+        if (!managed) return fail(CG_EINVAL, "the device reports no managed-memory support");
+        void *mp = nullptr;
+        const size_t granule = 4096;   // managed allocations come in 4 KiB pages
+        if (hipMallocManaged(&mp, (bytes + granule - 1) / granule * granule, hipMemAttachGlobal) != hipSuccess)
+            return fail(CG_ENOMEM, "managed allocation of p failed");
+        h->h_pshared = h->d_pshared = static_cast<double *>(mp);
+    }
+    h->shared_mode = mode;
+    std::memset(h->h_pshared, 0, bytes);
+    return CG_OK;
+}
+
 static void free_device(cg_handle *h) {
+    free_shared_p(h);
     fsai_free(h);
     dm_free(h->A);
     dm_free(h->G);
@@ -274,8 +314,11 @@ extern "C" int cg_set_opts(cg_handle *h, const cg_opts *o) {
         return fail(CG_EINVAL, "unknown precision %d", o->precision);
     if (o->precond != CG_PC_NONE && o->precond != CG_PC_FSAI)
         return fail(CG_EINVAL, "unknown preconditioner %d", o->precond);
-    if (o->exchange != CG_EXCHANGE_WHOLE && o->exchange != CG_EXCHANGE_HALO)
+    if (o->exchange < CG_EXCHANGE_WHOLE || o->exchange > CG_EXCHANGE_MANAGED)
         return fail(CG_EINVAL, "unknown exchange mode %d", o->exchange);
+    const bool shared = o->exchange == CG_EXCHANGE_MAPPED || o->exchange == CG_EXCHANGE_MANAGED;
+    if (shared && (o->precision != CG_PREC_FP64 || o->precond != CG_PC_NONE))
+        return fail(CG_EINVAL, "mapped and managed p need float64 CG without preconditioner");
     if (o->check_every < 1) return fail(CG_EINVAL, "check_every must be >= 1");
     if (o->host_threads < 0) return fail(CG_EINVAL, "host_threads must be >= 0");
     if (o->spmv_grid < 0) return fail(CG_EINVAL, "spmv_grid must be >= 0");
@@ -287,9 +330,13 @@ extern "C" int cg_set_opts(cg_handle *h, const cg_opts *o) {
     if (o->spmv_colblock < 0) return fail(CG_EINVAL, "spmv_colblock must be >= 0");
     if (o->precision == CG_PREC_MIXED && o->precond != CG_PC_NONE)
         return fail(CG_EINVAL, "the preconditioned solve runs in float64 only");
-    h->opts = *o;
     HIP_TRY(hipSetDevice(h->dev));
     HIP_TRY(h->stream ? hipStreamSynchronize(h->stream) : hipDeviceSynchronize());
+    if (shared && h->n > 0) {
+        const int rc0 = ensure_shared_p(h, o->exchange);
+        if (rc0) return rc0;
+    }
+    h->opts = *o;
     int rc = apply_schedule(h);
     if (rc) return rc;
     if (o->precision == CG_PREC_MIXED) {
@@ -434,7 +481,8 @@ static int solve_gpu_only(cg_handle *h, const double *b, double *x, double tol, 
     const int32_t n = h->n;
     hipStream_t st = h->stream;
     const bool small = h->opts.small_path && n <= small_path_max_rows() &&
-                       h->opts.precision == CG_PREC_FP64 && h->opts.precond == CG_PC_NONE;
+                       h->opts.precision == CG_PREC_FP64 && h->opts.precond == CG_PC_NONE &&
+                       !h->shared_p();
     HIP_TRY(hipMemcpyAsync(h->d_x, x, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
     int rc = gpu_state_init(h, tol, maxit);
     if (rc) return rc;
@@ -681,6 +729,7 @@ struct SplitTimers {
 
 // Make the updated p visible to both sides (Section 3.4, explicit copy).
 int exchange_p(cg_handle *h, SplitTimers &tm) {
+    if (h->shared_p()) return CG_OK;   // one copy of p, addressed by both sides
     const int32_t n = h->n, rb = h->rb, re = h->re;
     const bool halo = h->opts.exchange == CG_EXCHANGE_HALO;
     double t0 = now();
@@ -902,6 +951,17 @@ extern "C" int cg_solve(cg_handle *h, const double *b, double *x, double tol, in
     HIP_TRY(hipSetDevice(h->dev));
     const double t0 = now();
     int rc;
+    // mapped / managed modes: the solve's p is the shared allocation
+    struct PSwap {
+        cg_handle *h;
+        double *d_p, *h_p;
+        ~PSwap() { h->d_p = d_p; h->h_p = h_p; }
+    } swap{h, h->d_p, h->h_p};
+    if (h->shared_p()) {
+        if (h->shared_mode != h->opts.exchange) return fail(CG_EINVAL, "shared p not allocated");
+        h->d_p = h->d_pshared + (h->rb & 1);
+        h->h_p = h->h_pshared + (h->rb & 1);
+    }
     if (h->gpu_only()) {
         if (h->nnz == 0) return fail(CG_EINVAL, "matrix has no nonzeros");
         if (h->opts.precond == CG_PC_FSAI) {

@@ -134,6 +134,15 @@ struct cg_handle {
     double *d_pack_d2h = nullptr, *d_pack_h2d = nullptr;
     double *h_pack_d2h = nullptr, *h_pack_h2d = nullptr;  // pinned
 
+    // p held once where both sides address it (CG_EXCHANGE_MAPPED / _MANAGED):
+    // n + 2 doubles; the solve uses offset (rb & 1) so p + rb is 16-byte aligned
+    int shared_mode = -1;              // mode the allocation was made for (-1: none)
+    double *h_pshared = nullptr;       // host address
+    double *d_pshared = nullptr;       // device address of the same memory
+    bool shared_p() const {
+        return opts.exchange == CG_EXCHANGE_MAPPED || opts.exchange == CG_EXCHANGE_MANAGED;
+    }
+
     bool gpu_only() const { return rb == 0 && re == n && n > 0; }
     bool host_only() const { return m == 0; }
 };

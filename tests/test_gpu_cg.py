@@ -32,6 +32,19 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
 
 
+def managed_supported(cg) -> bool:
+    """Managed memory for p needs the device to report managed-memory
+    support (XNACK-off MI355X systems report none: the library then returns
+    CG_EINVAL for CG_EXCHANGE_MANAGED)."""
+    with cg.Solver(I.poisson2d(4)) as s:
+        try:
+            s.set_opts(exchange=cg.EXCHANGE_MANAGED)
+            return True
+        except cg.CgError as e:
+            assert "managed-memory support" in str(e)
+            return False
+
+
 def host(t):
     torch.cuda.synchronize()
     return t.cpu().numpy()
@@ -331,9 +344,11 @@ def test_cg_fixed_work_tracks_oracle(cg):
     assert abs(res["rel_res_recur"] - ref["rel_res_recur"]) <= 1e-6 * ref["rel_res_recur"]
 
 
-@pytest.mark.parametrize("exchange", [0, 1])
+@pytest.mark.parametrize("exchange", [0, 1, 2, 3])
 @pytest.mark.parametrize("frac", [0.0, 0.5, 1.0, "mid"])
 def test_split_modes_match_oracle(cg, frac, exchange):
+    if exchange == 3 and not managed_supported(cg):
+        pytest.skip("the device reports no managed-memory support")
     p = I.poisson3d_problem(20)
     n = p.A.n
     if frac == "mid":
@@ -351,15 +366,59 @@ def test_split_modes_match_oracle(cg, frac, exchange):
     check_cg(p.A, p.b, host(x), res, ref, 1e-10, lam.max() / lam.min())
 
 
-def test_split_whole_and_halo_exchange_agree_bitwise(cg):
+def test_split_memory_modes_agree_bitwise(cg):
+    """Explicit copies (whole, halo), mapped host memory and managed memory
+    only change where p lives: the same kernels and host loops see the same
+    values, so the iterates agree bit for bit."""
     p = I.random_spd_problem(8000, seed=4)
     xs = []
-    for exchange in (0, 1):
+    for exchange in (0, 1, 2, 3) if managed_supported(cg) else (0, 1, 2):
         with cg.Solver(p.A, 0, 5000) as s:
             s.set_opts(exchange=exchange, host_threads=3)
             x, res = s.solve(dev(p.b), tol=1e-10, maxit=3000)
             xs.append((host(x), res["iterations"]))
-    assert xs[0][1] == xs[1][1] and np.array_equal(xs[0][0], xs[1][0])
+            if exchange >= 2:
+                assert res["t_d2h"] < 0.5 and res["t_h2d"] < 0.5   # only the initial/final transfers
+    for xk, it in xs[1:]:
+        assert it == xs[0][1] and np.array_equal(xk, xs[0][0])
+
+
+@pytest.mark.parametrize("n_side", [24, 40])   # 576 rows (small-path size), 64,000 rows
+def test_gpu_only_shared_p_modes_bitwise(cg, n_side):
+    """GPU-only handles with p in mapped or managed memory run the
+    multi-kernel iteration on that memory: bitwise equal to the device-memory
+    solve with the single-workgroup path off."""
+    p = I.poisson2d_problem(n_side) if n_side == 24 else I.poisson3d_problem(n_side)
+    out = {}
+    modes = (0, 2, 3, 0) if managed_supported(cg) else (0, 2, 0)
+    with cg.Solver(p.A) as s:
+        for exchange in modes:
+            s.set_opts(exchange=exchange, small_path=0)
+            x, res = s.solve(dev(p.b), tol=1e-10, maxit=5000)
+            assert res["code"] == cg.CG_OK
+            out.setdefault(exchange, []).append((host(x), res["iterations"]))
+        s.set_opts(exchange=2, small_path=1)     # the mode overrides the LDS path
+        x, res = s.solve(dev(p.b), tol=1e-10, maxit=5000)
+        out[2].append((host(x), res["iterations"]))
+    ref_x, ref_it = out[0][0]
+    for runs in out.values():
+        for xk, it in runs:
+            assert it == ref_it and np.array_equal(xk, ref_x)
+
+
+def test_shared_p_modes_reject_unsupported_combinations(cg):
+    p = I.poisson2d_problem(16)
+    with cg.Solver(p.A) as s:
+        for exchange in (2, 3):   # rejected whether or not managed memory is supported
+            with pytest.raises(cg.CgError):
+                s.set_opts(exchange=exchange, precision=cg.PREC_MIXED)
+            with pytest.raises(cg.CgError):
+                s.set_opts(exchange=exchange, precond=cg.PC_FSAI)
+        with pytest.raises(cg.CgError):
+            s.set_opts(exchange=4)
+        # a rejected option leaves the handle as it was
+        x, res = s.solve(dev(p.b), tol=1e-10)
+        assert res["code"] == cg.CG_OK
 
 
 def test_split_spmv_matches_oracle(cg):
