@@ -427,12 +427,16 @@ def bench_split_sweep(args) -> int:
             "models": {m: vars(md) for m, md in models.items()}}
     print(f"[bench] best {best_key}; planner chose {key_c} ({auto['ratio_to_best']})", file=sys.stderr,
           flush=True)
+    # interconnect bound (Section 4.4) over the explicit-copy configurations
+    explicit = {k: v for k, v in sweep.items() if v["mode"] in ("host", "device", "whole", "halo")}
+    tb = split.transfer_bound_table(explicit)
     line = _line("CG iters/s, best configuration of the GPU-share x memory-mode sweep",
                  1.0 / times[best_key], "iter/s", args, 1e3 * iters * times[best_key],
                  {"workload": f"{prob.name}_split_sweep", "n": n, "nnz": A.nnz,
                   "iterations_per_solve": iters, "shares": list(split.SHARES),
                   "split_by": "nnz" if args.by_nnz else "rows"},
-                 best=best_key, managed_supported=bool(managed_ok), sweep=sweep, planner=auto)
+                 best=best_key, managed_supported=bool(managed_ok), sweep=sweep, planner=auto,
+                 transfer_bound=tb)
     print(json.dumps(line), flush=True)
     return 0
 

@@ -725,6 +725,13 @@ namespace {
 
 struct SplitTimers {
     double gpu = 0, cpu = 0, barrier = 0, d2h = 0, h2d = 0;
+    // HIP events around the current GPU phase: gpu sums the kernels' own
+    // time, not the time until the host (busy with its rows) looks
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    ~SplitTimers() {
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+    }
 };
 
 // Make the updated p visible to both sides (Section 3.4, explicit copy).
@@ -772,12 +779,14 @@ int exchange_p(cg_handle *h, SplitTimers &tm) {
     return CG_OK;
 }
 
-int wait_gpu(cg_handle *h, SplitTimers &tm, double gpu_started) {
+// Wait for the GPU phase bracketed by tm.ev0 / tm.ev1 and add its kernel time.
+int wait_gpu(cg_handle *h, SplitTimers &tm) {
     const double t0 = now();
     HIP_TRY(hipStreamSynchronize(h->stream));
-    const double t1 = now();
-    tm.barrier += t1 - t0;
-    tm.gpu += t1 - gpu_started;
+    tm.barrier += now() - t0;
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, tm.ev0, tm.ev1));
+    tm.gpu += 1e-3 * ms;
     return CG_OK;
 }
 
@@ -802,10 +811,14 @@ static int solve_split(cg_handle *h, const double *b, double *x, double tol, int
         HIP_TRY(hipStreamSynchronize(st));
         tm.d2h += now() - t0;
     }
-    double t_g = now();
-    if (gpu)
+    if (gpu) {
+        HIP_TRY(hipEventCreate(&tm.ev0));
+        HIP_TRY(hipEventCreate(&tm.ev1));
+        HIP_TRY(hipEventRecord(tm.ev0, st));
         HIP_TRY(launch_spmv(h->A.dev(), h->A.sched, Gs, x, h->d_r, nullptr, b + rb, h->d_p + rb,
                             h->d_part_setup, no_partials(), no_partials(), nullptr, kSpmvResidual, 0, st));
+        HIP_TRY(hipEventRecord(tm.ev1, st));
+    }
     double t_c = now();
     const double rho_c = host_reduce(h, [&](int32_t i) {
         const double rv = hb[i] - host_row_dot(h, i, hx);
@@ -817,7 +830,7 @@ static int solve_split(cg_handle *h, const double *b, double *x, double tol, int
     tm.cpu += now() - t_c;
     double rho = rho_c, bb = bb_c;
     if (gpu) {
-        if ((rc = wait_gpu(h, tm, t_g))) return rc;
+        if ((rc = wait_gpu(h, tm))) return rc;
         double rg = 0.0, bg = 0.0;
         if ((rc = sum_partials_host(h, h->d_part_setup, Gs, 2, &rg, &bg))) return rc;
         rho = rg + rho_c;
@@ -836,10 +849,12 @@ static int solve_split(cg_handle *h, const double *b, double *x, double tol, int
     for (k = 0; k < maxit; ++k) {
         if (std::sqrt(rho) < tol * bnorm || rho == 0.0) { status = CG_OK; break; }
         // q = A p and p^T q: GPU rows and host rows at the same time
-        t_g = now();
-        if (gpu)
+        if (gpu) {
+            HIP_TRY(hipEventRecord(tm.ev0, st));
             HIP_TRY(launch_spmv(h->A.dev(), h->A.sched, Gs, h->d_p, h->d_q, h->d_p + rb, nullptr, nullptr,
                                 h->d_part_pq, no_partials(), no_partials(), nullptr, kSpmvDot, 0, st));
+            HIP_TRY(hipEventRecord(tm.ev1, st));
+        }
         t_c = now();
         const double pq_c = host_reduce(h, [&](int32_t i) {
             const double s = host_row_dot(h, i, hp);
@@ -849,7 +864,7 @@ static int solve_split(cg_handle *h, const double *b, double *x, double tol, int
         tm.cpu += now() - t_c;
         double pq = pq_c;
         if (gpu) {
-            if ((rc = wait_gpu(h, tm, t_g))) return rc;
+            if ((rc = wait_gpu(h, tm))) return rc;
             double pg = 0.0;
             if ((rc = sum_partials_host(h, h->d_part_pq, Gs, 1, &pg, nullptr))) return rc;
             pq = pg + pq_c;
@@ -857,10 +872,12 @@ static int solve_split(cg_handle *h, const double *b, double *x, double tol, int
         if (!(pq > 0.0) || !std::isfinite(pq)) { status = CG_EBREAKDOWN; break; }
         const double alpha = rho / pq;
         // x += alpha p, r -= alpha q, r^T r
-        t_g = now();
-        if (gpu)
+        if (gpu) {
+            HIP_TRY(hipEventRecord(tm.ev0, st));
             HIP_TRY(launch_update_xr(m, Gv, h->d_x, h->d_r, h->d_p + rb, h->d_q, h->d_part_rr,
                                      no_partials(), nullptr, 0, k, alpha, st));
+            HIP_TRY(hipEventRecord(tm.ev1, st));
+        }
         t_c = now();
         const double rr_c = host_reduce(h, [&](int32_t i) {
             hx[i] = std::fma(alpha, hp[i], hx[i]);
@@ -871,7 +888,7 @@ static int solve_split(cg_handle *h, const double *b, double *x, double tol, int
         tm.cpu += now() - t_c;
         double rr = rr_c;
         if (gpu) {
-            if ((rc = wait_gpu(h, tm, t_g))) return rc;
+            if ((rc = wait_gpu(h, tm))) return rc;
             double rg = 0.0;
             if ((rc = sum_partials_host(h, h->d_part_rr, Gv, 1, &rg, nullptr))) return rc;
             rr = rg + rr_c;
@@ -880,9 +897,11 @@ static int solve_split(cg_handle *h, const double *b, double *x, double tol, int
         rho = rr;
         if (std::sqrt(rho) < tol * bnorm || rho == 0.0 || k + 1 == maxit) continue;  // p unused
         // p = r + beta p, then exchange
-        t_g = now();
-        if (gpu)
+        if (gpu) {
+            HIP_TRY(hipEventRecord(tm.ev0, st));
             HIP_TRY(launch_update_p(m, Gv, h->d_r, h->d_p + rb, no_partials(), nullptr, 0, k, beta, st));
+            HIP_TRY(hipEventRecord(tm.ev1, st));
+        }
         t_c = now();
         host_reduce(h, [&](int32_t i) {
             hp[i] = std::fma(beta, hp[i], hr[i]);
@@ -890,7 +909,7 @@ static int solve_split(cg_handle *h, const double *b, double *x, double tol, int
         });
         tm.cpu += now() - t_c;
         if (gpu) {
-            if ((rc = wait_gpu(h, tm, t_g))) return rc;
+            if ((rc = wait_gpu(h, tm))) return rc;
             if ((rc = exchange_p(h, tm))) return rc;
         }
     }

@@ -22,7 +22,11 @@ automatic choice:
   exchanged) and O the rest (reductions, synchronisation);
 * ``choose_split``: the candidate share with the smallest predicted time
   for one mode's model; ``choose_config`` the best (mode, share) over
-  several modes' models.
+  several modes' models;
+* ``transfer_bound``: the interconnect-bound estimate of Section 4.4, where
+  only the vector-transfer part of an explicit-copy run time is divided by
+  a bandwidth ratio R (the paper's R = 900 / 128, a coherent 900 GB/s link
+  over PCIe Gen5 x16's 128 GB/s, which is also this GPU's host link).
 
 Everything here is host arithmetic on timings; the solves it plans run in
 the library's kernels and host loops.
@@ -36,6 +40,7 @@ import numpy as np
 
 SHARES = (0.0, 0.25, 0.5, 0.75, 0.8, 0.85, 0.9, 0.95, 1.0)
 COMPETITIVE_FACTOR = 1.25
+LINK_RATIO = 900.0 / 128.0
 
 
 def rows_for_share(n: int, g: float) -> int:
@@ -120,3 +125,25 @@ def choose_config(models: dict, row_ptr, shares=SHARES, by_nnz: bool = False) ->
     mode = min(per, key=lambda m: per[m]["predicted"])
     best = {k: v for k, v in per[mode].items() if k != "table"}
     return {"mode": mode, **best, "per_mode": per}
+
+
+def transfer_bound(seconds: float, transfer_seconds: float, ratio: float = LINK_RATIO) -> float:
+    """Run time with the transfer component (initial, final and per-iteration
+    vector copies) scaled by 1 / ratio and everything else unchanged."""
+    if ratio <= 0:
+        raise ValueError("ratio must be positive")
+    if not 0.0 <= transfer_seconds <= seconds:
+        raise ValueError("the transfer time must lie within the run time")
+    return seconds - transfer_seconds + transfer_seconds / ratio
+
+
+def transfer_bound_table(runs: dict, ratio: float = LINK_RATIO) -> dict:
+    """runs: {key: {"seconds", "t_d2h", "t_h2d"}} of explicit-copy (or
+    transfer-free) configurations.  Returns the bound per key and the
+    preferred key before and after scaling."""
+    bound = {k: transfer_bound(r["seconds"], min(r["t_d2h"] + r["t_h2d"], r["seconds"]), ratio)
+             for k, r in runs.items()}
+    before = min(runs, key=lambda k: runs[k]["seconds"])
+    after = min(bound, key=bound.get)
+    return {"ratio": ratio, "bound_seconds": bound, "preferred_measured": before,
+            "preferred_bound": after, "preferred_changes": before != after}

@@ -88,3 +88,23 @@ def test_model_needs_a_split_probe():
     probe, secs = _probe(4e9, 1e9, 0.0, 0.0, 100, 100)
     with pytest.raises(ValueError):
         S.IterationModel.fit(probe, secs, 100)
+
+
+def test_transfer_bound_scales_only_the_transfer_part():
+    # by hand: T = 10, transfers 7 of it, R = 7 -> 3 + 1
+    assert S.transfer_bound(10.0, 7.0, 7.0) == pytest.approx(4.0)
+    assert S.transfer_bound(10.0, 0.0) == 10.0                  # nothing to scale
+    assert S.transfer_bound(10.0, 10.0, 2.0) == pytest.approx(5.0)
+    assert S.LINK_RATIO == pytest.approx(900 / 128)
+    for bad in ((10.0, 11.0, 2.0), (10.0, -1.0, 2.0), (10.0, 1.0, 0.0)):
+        with pytest.raises(ValueError):
+            S.transfer_bound(*bad)
+
+
+def test_transfer_bound_table_reports_a_moved_optimum():
+    runs = {"g1.00": {"seconds": 5.0, "t_d2h": 0.0, "t_h2d": 0.0},
+            "g0.75": {"seconds": 6.0, "t_d2h": 3.0, "t_h2d": 1.0}}   # transfer-heavy hybrid
+    tab = S.transfer_bound_table(runs, ratio=8.0)
+    assert tab["bound_seconds"]["g0.75"] == pytest.approx(2.0 + 0.5)
+    assert tab["preferred_measured"] == "g1.00" and tab["preferred_bound"] == "g0.75"
+    assert tab["preferred_changes"]
