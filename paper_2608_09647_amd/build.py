@@ -12,7 +12,7 @@ LIB = os.path.join(PKG, "libcgmi.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 HIP_SOURCES = ["kernels_cg.hip", "kernels_fsai.hip", "kernels_batch.hip"]
-HOST_SOURCES = ["cgmi.cpp", "devmatrix.cpp", "fsai.cpp", "batch.cpp"]
+HOST_SOURCES = ["cgmi.cpp", "devmatrix.cpp", "fsai.cpp", "batch.cpp", "mmio.cpp"]
 
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
                # keep packed-float32 instructions out of the device code

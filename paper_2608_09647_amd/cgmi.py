@@ -34,6 +34,15 @@ FSAI_NPARAMS = 5317
 EXPORTED_BATCH = ["cg_batch_create", "cg_batch_destroy", "cg_batch_set_stream", "cg_batch_layout",
                   "cg_batch_default_sched", "cg_batch_set_sched", "cg_batch_get_sched", "cg_batch_solve"]
 BATCH_MAX_RHS = 16
+# include/cgmi_io.h
+EXPORTED_IO = ["cg_mm_read", "cg_mm_free"]
+
+
+class MmMatrix(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.POINTER(ctypes.c_int32)), ("col", ctypes.POINTER(ctypes.c_int32)),
+                ("val", ctypes.POINTER(ctypes.c_double)), ("symmetric", ctypes.c_int32),
+                ("file_entries", ctypes.c_int64)]
 
 
 class CgOpts(ctypes.Structure):
@@ -154,6 +163,10 @@ def lib() -> ctypes.CDLL:
         for name in ("cg_batch_create", "cg_batch_set_stream", "cg_batch_layout", "cg_batch_set_sched",
                      "cg_batch_get_sched", "cg_batch_solve"):
             getattr(L, name).restype = ctypes.c_int
+        L.cg_mm_read.argtypes = [ctypes.c_char_p, i32, ctypes.POINTER(MmMatrix)]
+        L.cg_mm_read.restype = ctypes.c_int
+        L.cg_mm_free.argtypes = [ctypes.POINTER(MmMatrix)]
+        L.cg_mm_free.restype = None
         _LIB = L
     return _LIB
 
@@ -474,3 +487,22 @@ class Batch:
         for i in range(flat.size):
             flat[i] = (res[i].status, res[i].iterations, res[i].rel_res_recur, res[i].rel_res_true)
         return X, out, st.as_dict(), code
+
+
+def read_matrix_market(path: str, threads: int = 0):
+    """Read a Matrix Market coordinate file (real, integer or pattern;
+    general or symmetric, symmetric storage expanded) with the library's
+    reader; returns (inputs.CSR, info dict)."""
+    import numpy as np
+    from .inputs import CSR
+    m = MmMatrix()
+    _check(lib().cg_mm_read(os.fsencode(path), int(threads), ctypes.byref(m)))
+    try:
+        n, nnz = int(m.n), int(m.nnz)
+        rp = np.ctypeslib.as_array(m.row_ptr, shape=(n + 1,)).copy()
+        ci = np.ctypeslib.as_array(m.col, shape=(max(nnz, 1),))[:nnz].copy()
+        va = np.ctypeslib.as_array(m.val, shape=(max(nnz, 1),))[:nnz].copy()
+        info = {"symmetric": bool(m.symmetric), "file_entries": int(m.file_entries)}
+    finally:
+        lib().cg_mm_free(ctypes.byref(m))
+    return CSR(n, rp, ci, va), info

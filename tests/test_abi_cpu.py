@@ -33,7 +33,7 @@ def test_header_symbols_are_exported(cg):
     L = cg.lib()
     for name in sorted(declared):
         assert hasattr(L, name), f"{name} declared in include/ but not exported"
-    assert set(cg.EXPORTED) | set(cg.EXPORTED_FSAI) | set(cg.EXPORTED_BATCH) == declared
+    assert set(cg.EXPORTED) | set(cg.EXPORTED_FSAI) | set(cg.EXPORTED_BATCH) | set(cg.EXPORTED_IO) == declared
 
 
 def test_default_opts(cg):

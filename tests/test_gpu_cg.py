@@ -560,3 +560,21 @@ def test_mixed_precision_edge_cases(cg):
     with cg.Solver(p.A, 0, n // 2) as s:
         with pytest.raises(cg.CgError):
             s.set_opts(precision=cg.PREC_MIXED)
+
+
+def test_matrix_market_file_solves_like_the_generated_matrix(cg, tmp_path):
+    """A Poisson system written as a symmetric Matrix Market file (lower
+    triangle), read back by the library and solved on the GPU: the same CSR
+    as the generator's, and the oracle's CG result."""
+    import scipy.io
+    p = I.poisson3d_problem(20)
+    path = str(tmp_path / "poisson.mtx")
+    scipy.io.mmwrite(path, sp.tril(p.A.scipy(), format="coo"), symmetry="symmetric", precision=17)
+    A, info = cg.read_matrix_market(path)
+    assert info["symmetric"] and np.array_equal(A.row_ptr, p.A.row_ptr)
+    assert np.array_equal(A.col, p.A.col) and np.array_equal(A.val, p.A.val)
+    ref = oracle.cg(p.A, p.b, tol=1e-10, maxit=5000)
+    with cg.Solver(A) as s:
+        x, res = s.solve(dev(p.b), tol=1e-10, maxit=5000)
+    lam = 2 - 2 * np.cos(np.arange(1, 21) * np.pi / 21)
+    check_cg(p.A, p.b, host(x), res, ref, 1e-10, 3 * lam.max() / (3 * lam.min()))
