@@ -131,8 +131,10 @@ def bench_time_to_tol(args, prob, variants, metric, workload, extra=None):
     x0 = torch.zeros_like(b)
     out = {}
     xs = {}
+    from paper_2608_09647_amd import autotune
     for name, opts in variants.items():
         solver = cgmi.Solver(prob.A)
+        autotune.spmv_schedule(solver, prob.A, b, tune_if_missing=False)   # tabled SpMV tiling, if any
         solver.set_opts(**opts)
         _timed_solve(solver, b, x0, 1e-10, 200000, args.warmup)
         x, res, times = _timed_solve(solver, b, x0, 1e-10, 200000, args.steps)
@@ -203,6 +205,8 @@ def main() -> int:
     b = torch.from_numpy(prob.b).to(dev)
     x = torch.zeros_like(b)
     solver = cgmi.Solver(A)
+    from paper_2608_09647_amd import autotune
+    autotune.spmv_schedule(solver, A, b, tune_if_missing=False)   # tabled SpMV tiling, if any
     solver.set_opts(profile=1)
     for _ in range(args.warmup):
         x.zero_()
@@ -533,8 +537,11 @@ def bench_learned(args) -> int:
     x0 = torch.zeros_like(b)
     out = {}
 
+    from paper_2608_09647_amd import autotune
+
     def run(name, prepare, reps, warm, precond=cgmi.PC_NONE):
         s = cgmi.Solver(A)
+        autotune.spmv_schedule(s, A, b, tune_if_missing=False)   # tabled SpMV tiling, if any
         s.set_opts(profile=1, precond=precond)
         times, setups = [], []
         res = None

@@ -1,0 +1,149 @@
+"""Full-size parity in the configurations bench.py times: the random SPD
+system (n = 2M, column-blocked SpMV from the schedule table, float32 inner /
+float64 refined CG) and the 1024^2 diffusion system with a learned factor
+built on the device.  Outputs the oracle computes cheaply are compared in
+full (SpMV, the factor, fixed-work iterates); to-tolerance solves are checked
+through properties that hold at any size (the recomputed true residual)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import oracle.fsai as OF
+from paper_2608_09647_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def cg(require_gpu):
+    from paper_2608_09647_amd import cgmi
+    cgmi.lib()
+    return cgmi
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def spmv_err(A, x, y, ref):
+    """max_i |y_i - ref_i| / sum_k |a_ik x_k| (rounding-order bar of one row)."""
+    absA = sp.csr_matrix((np.abs(A.val), A.col, A.row_ptr), shape=(A.n, A.n))
+    return float(np.max(np.abs(y - ref) / (absA @ np.abs(x) + 1e-300)))
+
+
+def test_full_size_random_spd_2m(cg):
+    from paper_2608_09647_amd import autotune
+    p = I.random_spd_problem(2_000_000, seed=3)
+    A = p.A
+    L = int(np.diff(A.row_ptr).max())
+    print(f"[full] random SPD n={A.n} nnz={A.nnz} longest row {L}", flush=True)
+    x = np.random.default_rng(1).uniform(-1, 1, A.n)
+    x32 = x.astype(np.float32)
+    ref = oracle.spmv(A, x)
+    ref32 = oracle.spmv_f32(A, x32)
+    b = dev(p.b)
+    with cg.Solver(A) as s:
+        sched = autotune.spmv_schedule(s, A, b, tune_if_missing=False)
+        print(f"[full] schedule {sched}", flush=True)
+        y = host(s.spmv(dev(x)))
+        assert spmv_err(A, x, y, ref) <= 1e-12
+        # fixed-work float64 iterates against the oracle's
+        xg, _ = s.solve(b, tol=0.0, maxit=3)
+        x3 = host(xg)
+        # float32 product within the float32 rounding bar of a row
+        s.set_opts(precision=cg.PREC_MIXED)
+        y32 = host(s.spmv_f32(torch.from_numpy(x32).cuda())).astype(np.float64)
+        absA = sp.csr_matrix((np.abs(A.val.astype(np.float32)), A.col, A.row_ptr), shape=(A.n, A.n))
+        scale = absA @ np.abs(x32).astype(np.float64) + 1e-30
+        assert np.max(np.abs(y32 - ref32) / scale) <= 2 * L * 2.0 ** -24
+        # the benchmark's two solves to 1e-10
+        xm, rm = s.solve(b, tol=1e-10, maxit=20000)
+        s.set_opts(precision=cg.PREC_FP64)
+        xd, rd = s.solve(b, tol=1e-10, maxit=20000)
+        xm, xd = host(xm), host(xd)
+    # 3 fixed iterations against the oracle's; bar: 4x the distance between the
+    # oracle and a second correct float64 CG (scipy products, BLAS dots), the
+    # rows' cancelling sums being sensitive to the summation order
+    ora3 = oracle.cg(A, p.b, tol=0.0, maxit=3)
+    S = A.scipy()
+    xa, r, rho = np.zeros(A.n), p.b.copy(), p.b @ p.b
+    pa = r.copy()
+    for _ in range(3):
+        qv = S @ pa
+        alpha = rho / (pa @ qv)
+        xa += alpha * pa
+        r -= alpha * qv
+        rho, rho_old = r @ r, rho
+        pa = r + (rho / rho_old) * pa
+    del S, r, pa
+    spread = np.linalg.norm(xa - ora3["x"]) / np.linalg.norm(ora3["x"])
+    dx = np.linalg.norm(x3 - ora3["x"]) / np.linalg.norm(ora3["x"])
+    print(f"[full] 3 CG iterations: GPU vs oracle {dx:.2e} (CPU spread {spread:.2e})", flush=True)
+    assert dx <= max(1e-13, 4 * spread)
+    bn = np.linalg.norm(p.b)
+    for name, xs, r in (("mixed", xm, rm), ("fp64", xd, rd)):
+        true = np.linalg.norm(p.b - oracle.spmv(A, xs)) / bn
+        print(f"[full] {name}: {r['iterations']} iterations, {r['fp64_residuals']} float64 residuals, "
+              f"true {true:.3e}", flush=True)
+        assert r["code"] == cg.CG_OK and true <= 1e-10 * 1.01
+        assert abs(r["rel_res_true"] - true) <= 1e-3 * true
+    # smallest eigenvalue 0.01 exactly, largest below the Gershgorin bound
+    kappa = np.max(np.add.reduceat(np.abs(A.val), A.row_ptr[:-1])) / 0.01
+    assert np.linalg.norm(xm - xd) / np.linalg.norm(xd) <= 2 * kappa * 1e-10
+
+
+def test_full_size_diffusion_1024_learned_factor(cg):
+    from paper_2608_09647_amd import fsai
+    q = I.diffusion_problem(1024, seed=10_000)
+    A = q.A
+    th = fsai.init_params(0)
+    print(f"[full] diffusion 1024^2 n={A.n} nnz={A.nnz}", flush=True)
+    b = dev(q.b)
+    with cg.Solver(A) as s:
+        s.fsai_setup(th)
+        rp, ci, va = s.read_factor()
+        s.set_opts(precond=cg.PC_FSAI)
+        xg, res = s.solve(b, tol=0.0, maxit=30)
+        x30 = host(xg)
+        assert res["iterations"] == 30 and res["fell_back"] == 0
+    # the factor: every row against the oracle's network and assembly
+    o, _ = OF.mlp_forward(th.astype(np.float64), OF.features(A), round_bf16=True)
+    _, d = OF.scaled_operator(A)
+    G = OF.g_unscaled(OF.g_tilde(A, o), d).tocsr()
+    G.sort_indices()
+    assert np.array_equal(rp, G.indptr) and np.array_equal(ci, G.indices)
+    err = np.abs(va - G.data).max() / np.abs(G.data).max()
+    print(f"[full] factor max rel err {err:.3e}", flush=True)
+    assert err <= 2e-3
+    # 30 fixed PCG iterations with the device's own factor against the
+    # oracle's PCG with that factor; bar: 4x the distance between the oracle
+    # and a second correct float64 PCG (scipy products, BLAS dots)
+    Gd = sp.csr_matrix((va, ci, rp), shape=(A.n, A.n))
+    GT = Gd.T.tocsr()
+    GT.sort_indices()
+    c = lambda M: I.CSR(A.n, M.indptr.astype(np.int32), M.indices.astype(np.int32), M.data)  # noqa: E731
+    ref = oracle.pcg(A, c(Gd), c(GT), q.b, tol=0.0, maxit=30)
+    S = A.scipy()
+    xa, r = np.zeros(A.n), q.b.copy()
+    z = GT @ (Gd @ r)
+    pa, rz = z.copy(), r @ z
+    for _ in range(30):
+        qq = S @ pa
+        alpha = rz / (pa @ qq)
+        xa += alpha * pa
+        r -= alpha * qq
+        z = GT @ (Gd @ r)
+        rz, rz_old = r @ z, rz
+        pa = z + (rz / rz_old) * pa
+    spread = np.linalg.norm(xa - ref["x"]) / np.linalg.norm(ref["x"])
+    dx = np.linalg.norm(x30 - ref["x"]) / np.linalg.norm(ref["x"])
+    print(f"[full] 30 PCG iterations: GPU vs oracle {dx:.2e} (CPU spread {spread:.2e})", flush=True)
+    assert dx <= max(1e-11, 4 * spread)
