@@ -521,9 +521,8 @@ static int solve_gpu_only(cg_handle *h, const double *b, double *x, double tol, 
                                     h->d_part_pq, setup_rr, setup_bb, h->d_state, kSpmvDot, kk == 0, st));
                 if (h->opts.profile) HIP_TRY(hipEventRecord(ev[2 * j + 1], st));
                 if (maxit == 0) break;
-                HIP_TRY(launch_update_xr(n, Gv, h->d_x, h->d_r, h->d_p, h->d_q, h->d_part_rr, pq,
-                                         h->d_state, 1, kk, 0.0, st));
-                HIP_TRY(launch_update_p(n, Gv, h->d_r, h->d_p, rr, h->d_state, 1, kk, 0.0, st));
+                HIP_TRY(launch_update_r(n, Gv, h->d_r, h->d_q, h->d_part_rr, pq, h->d_state, kk, st));
+                HIP_TRY(launch_update_px(n, Gv, h->d_x, h->d_r, h->d_p, rr, h->d_state, kk, st));
             }
             const int32_t it0 = k;
             k += chunk;

@@ -202,6 +202,13 @@ hipError_t launch_pcg_xr_g(int32_t m, int grid, int width, const int32_t *grp, c
 // Preconditioned CG (z = M^-1 r): p = z + beta p, rho = r^T z from the rz
 // partials, the stop test on the rr partials; first = 1 is the setup step
 // (rho_0, ||b||^2 from bb, stop test at the top of iteration 0, p = z).
+// Float64 CG with device coefficients and the x update deferred to the p
+// update: r -= alpha q (partials of r^T r); then x += alpha p and, unless the
+// solve stops, p = r + beta p.  Vectors 16-byte aligned.
+hipError_t launch_update_r(int32_t m, int grid, double *r, const double *q, double *out, Partials pq,
+                           DevState *st, int32_t k, hipStream_t s);
+hipError_t launch_update_px(int32_t m, int grid, double *x, const double *r, double *p, Partials rr,
+                            DevState *st, int32_t k, hipStream_t s);
 hipError_t launch_update_p_pcg(int32_t m, int grid, const double *z, double *p, Partials rr,
                                Partials rz, Partials bb, DevState *st, int first, int32_t k,
                                hipStream_t s);

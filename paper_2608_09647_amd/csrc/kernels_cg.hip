@@ -832,6 +832,101 @@ __global__ __launch_bounds__(kBlock) void k_update_p(int32_t m, const double *__
     if ((m & 1) && blockIdx.x == 0 && threadIdx.x == 0) p[m - 1] = fma(beta, p[m - 1], r[m - 1]);
 }
 
+// Float64 CG with device coefficients, x update deferred by one kernel.
+// Algorithm 1 adds alpha p to x and subtracts alpha q from r in one step;
+// x is not read again before the p update, which reads the same p, so the
+// x update moves there: k_update_r forms r -= alpha q (partial r^T r per
+// workgroup, p^T q recorded for the next kernel), and k_update_px forms
+// x += alpha p with alpha recomputed from the same operands (bitwise the
+// same value), then p = r + beta p unless the solve stops.  The x/r kernel
+// no longer reads p: one pass over p per iteration less.
+__global__ __launch_bounds__(kBlock) void k_update_r(int32_t m, double *__restrict__ r,
+                                                     const double *__restrict__ q,
+                                                     double *__restrict__ out, Partials pq_in,
+                                                     DevState *__restrict__ st, int32_t k) {
+    __shared__ double sh[kWavesPerBlock];
+    __shared__ double bc;
+    if (st->done) return;
+    const double pq = reduce_partials(pq_in, sh, &bc);
+    if (!(pq > 0.0) || !isfinite(pq)) {
+        if (is_block0_thread0()) {
+            st->pq = pq;
+            st->iter = k;
+            st->done = kDoneBreakdown;
+        }
+        return;
+    }
+    const double alpha = st->rho[k & 1] / pq;
+    if (is_block0_thread0()) st->pq = pq;
+    double acc = 0.0;
+    const int64_t npair = m >> 1;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    double2 *r2 = reinterpret_cast<double2 *>(r);
+    const double2 *q2 = reinterpret_cast<const double2 *>(q);
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < npair; i += stride) {
+        double2 rv = r2[i];
+        const double2 qv = q2[i];
+        rv.x = fma(-alpha, qv.x, rv.x);
+        rv.y = fma(-alpha, qv.y, rv.y);
+        r2[i] = rv;
+        acc = fma(rv.x, rv.x, acc);
+        acc = fma(rv.y, rv.y, acc);
+    }
+    if ((m & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        const double rv = fma(-alpha, q[m - 1], r[m - 1]);
+        r[m - 1] = rv;
+        acc = fma(rv, rv, acc);
+    }
+    const double s = block_sum<kBlock>(acc, sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_update_px(int32_t m, double *__restrict__ x,
+                                                      const double *__restrict__ r,
+                                                      double *__restrict__ p, Partials rr_in,
+                                                      DevState *__restrict__ st, int32_t k) {
+    __shared__ double sh[kWavesPerBlock];
+    __shared__ double bc;
+    if (st->done) return;   // breakdown in k_update_r: x stays as it was
+    const double rr = reduce_partials(rr_in, sh, &bc);
+    const double rho_k = st->rho[k & 1];
+    const double alpha = rho_k / st->pq;
+    const double beta = rr / rho_k;
+    const bool conv = stop_test(rr, st->bb, st->tol);
+    const bool maxed = k + 1 >= st->maxit;
+    const bool stop = conv || maxed;
+    if (is_block0_thread0()) {
+        st->rho[(k + 1) & 1] = rr;
+        st->rr = rr;
+        st->iter = k + 1;
+        if (conv) st->done = kDoneConverged;
+        else if (maxed) st->done = kDoneMaxit;
+    }
+    const int64_t npair = m >> 1;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    double2 *x2 = reinterpret_cast<double2 *>(x);
+    double2 *p2 = reinterpret_cast<double2 *>(p);
+    const double2 *r2 = reinterpret_cast<const double2 *>(r);
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < npair; i += stride) {
+        double2 pv = p2[i];
+        double2 xv = x2[i];
+        xv.x = fma(alpha, pv.x, xv.x);
+        xv.y = fma(alpha, pv.y, xv.y);
+        x2[i] = xv;
+        if (!stop) {
+            const double2 rv = r2[i];
+            pv.x = fma(beta, pv.x, rv.x);
+            pv.y = fma(beta, pv.y, rv.y);
+            p2[i] = pv;
+        }
+    }
+    if ((m & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        const double pv = p[m - 1];
+        x[m - 1] = fma(alpha, pv, x[m - 1]);
+        if (!stop) p[m - 1] = fma(beta, pv, r[m - 1]);
+    }
+}
+
 // Preconditioned CG: p = z + beta p with rho = r^T z (z = M^-1 r); the stop
 // test is on r^T r.  first: setup step (after r = b - A x and z = M^-1 r):
 // rho_0 = r^T z, ||b||^2 from bb_in, the stop test at the top of iteration 0,
@@ -1436,6 +1531,20 @@ hipError_t launch_pcg_xr_g(int32_t m, int grid, int width, const int32_t *grp, c
     else if (width <= 4) CGMI_PCG_XR_G(4);
     else CGMI_PCG_XR_G(8);
 #undef CGMI_PCG_XR_G
+    return hipGetLastError();
+}
+
+hipError_t launch_update_r(int32_t m, int grid, double *r, const double *q, double *out, Partials pq,
+                           DevState *st, int32_t k, hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_update_r, dim3(grid), dim3(kBlock), 0, s, m, r, q, out, pq, st, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_px(int32_t m, int grid, double *x, const double *r, double *p, Partials rr,
+                            DevState *st, int32_t k, hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_update_px, dim3(grid), dim3(kBlock), 0, s, m, x, r, p, rr, st, k);
     return hipGetLastError();
 }
 
