@@ -9,8 +9,11 @@
 //
 // One iteration is three phases separated by team barriers:
 //   A: q = A p on the team's rows, partial p^T q per right-hand side;
-//   B: alpha = rho / p^T q (team sum), x += alpha p, r -= alpha q, partial r^T r;
-//   C: stop test and beta = r^T r / rho (team sum), p = r + beta p.
+//   B: alpha = rho / p^T q (team sum), r -= alpha q, partial r^T r;
+//   C: stop test and beta = r^T r / rho (team sum), x += alpha p for every
+//      right-hand side updated in B, p = r + beta p for those still running.
+// Algorithm 1 updates x with r; x is not read again before C, which reads
+// the same p, so the x update is done there and B does not read p.
 // Every workgroup of a team sums the team's partials itself in a fixed order,
 // so all of them take identical decisions (and results are reproducible for
 // a fixed schedule).  A barrier is a counter in device memory: each wave
@@ -41,7 +44,8 @@ struct Shared {
     double sum[kL];
     double rho[kL], bb[kL], alpha[kL], beta[kL], rr_last[kL];
     int active[kL], status[kL], iter[kL], zero_b[kL];
-    int any;
+    int upd[kL];   // updated r (and owes the x update) in this iteration's phase B
+    int any, any_upd;
     int ok;
 };
 
@@ -307,6 +311,7 @@ __global__ __launch_bounds__(kT) void k_batch_cg(BatchArgs a) {
         if (threadIdx.x < kL) {
             const int t = threadIdx.x;
             S.alpha[t] = 0.0;
+            S.upd[t] = 0;
             if (S.active[t]) {
                 const double pq = S.sum[t];
                 if (!(pq > 0.0) || !isfinite(pq)) {
@@ -315,11 +320,12 @@ __global__ __launch_bounds__(kT) void k_batch_cg(BatchArgs a) {
                     S.active[t] = 0;
                 } else {
                     S.alpha[t] = S.rho[t] / pq;
+                    S.upd[t] = 1;
                 }
             }
         }
         __syncthreads();
-        // B: x += alpha p, r -= alpha q, partial r^T r
+        // B: r -= alpha q, partial r^T r
         {
             bool on[V];
             bool any_on = false;
@@ -338,20 +344,16 @@ __global__ __launch_bounds__(kT) void k_batch_cg(BatchArgs a) {
                         const int64_t row = r0 + u * RS + rsub;
                         if (row < hi) {
                             const int64_t idx = row * nr + j0;
-                            double xv[V], pv[V], qv[V], rv[V];
-                            ldv<V>(a.X, idx, xv);
-                            ldv<V>(a.P, idx, pv);
+                            double qv[V], rv[V];
                             ldv<V>(a.Q, idx, qv);
                             ldv<V>(a.R, idx, rv);
 #pragma unroll
                             for (int q = 0; q < V; ++q) {
                                 if (on[q]) {
-                                    xv[q] = fma(alpha[q], pv[q], xv[q]);
                                     rv[q] = fma(-alpha[q], qv[q], rv[q]);
                                     acc[q] = fma(rv[q], rv[q], acc[q]);
                                 }
                             }
-                            stv<V>(a.X, idx, xv);
                             stv<V>(a.R, idx, rv);
                         }
                     }
@@ -379,40 +381,52 @@ __global__ __launch_bounds__(kT) void k_batch_cg(BatchArgs a) {
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            int any = 0;
-            for (int t = 0; t < kL; ++t) any |= S.active[t];
+            int any = 0, any_upd = 0;
+            for (int t = 0; t < kL; ++t) {
+                any |= S.active[t];
+                any_upd |= S.upd[t];
+            }
             S.any = any;
+            S.any_upd = any_upd;
         }
         __syncthreads();
-        if (!S.any) break;
-        // C: p = r + beta p
+        if (!S.any_upd) break;   // every right-hand side broke down in A: nothing owed
+        // C: x += alpha p (right-hand sides updated in B), p = r + beta p (still running)
         {
-            bool on[V];
-            bool any_on = false;
-            double beta[V];
+            bool on[V], up[V];
+            bool any_on = false, any_up = false;
+            double alpha[V], beta[V];
 #pragma unroll
             for (int q = 0; q < V; ++q) {
                 on[q] = lane_on && S.active[j0 + q];
+                up[q] = lane_on && S.upd[j0 + q];
                 any_on |= on[q];
+                any_up |= up[q];
+                alpha[q] = S.alpha[j0 + q];
                 beta[q] = S.beta[j0 + q];
             }
-            if (any_on)
+            if (any_up)
                 for (int64_t r0 = lo; r0 < hi; r0 += RS * U)
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
                         const int64_t row = r0 + u * RS + rsub;
                         if (row < hi) {
                             const int64_t idx = row * nr + j0;
-                            double pv[V], rv[V];
+                            double pv[V], xv[V], rv[V];
                             ldv<V>(a.P, idx, pv);
-                            ldv<V>(a.R, idx, rv);
+                            ldv<V>(a.X, idx, xv);
+                            if (any_on) ldv<V>(a.R, idx, rv);
 #pragma unroll
-                            for (int q = 0; q < V; ++q)
+                            for (int q = 0; q < V; ++q) {
+                                if (up[q]) xv[q] = fma(alpha[q], pv[q], xv[q]);
                                 if (on[q]) pv[q] = fma(beta[q], pv[q], rv[q]);
-                            stv<V>(a.P, idx, pv);
+                            }
+                            stv<V>(a.X, idx, xv);
+                            if (any_on) stv<V>(a.P, idx, pv);
                         }
                     }
         }
+        if (!S.any) break;       // the x updates above reach the team at the next barrier
         if (!team_sync(a, sys, T, episode, S)) return;
     }
 
