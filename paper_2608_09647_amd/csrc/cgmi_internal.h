@@ -82,7 +82,15 @@ struct Schedule {
     int32_t huge_first;   // rows longer than kHugeRow: positions in the row list
     int32_t huge_count;
     int32_t kind;         // kTileVector, kTileStream, kTileSliced or kTileSlicedDict
+    int32_t stream_nt;    // dictionary tiles: 1 = load the matrix and store q nontemporally
 };
+
+// A matrix whose streamed bytes exceed half the last-level cache (256 MB on
+// MI355X) cannot stay cached across products: its loads (and the q stores)
+// are issued nontemporally so that the gathered vector keeps the caches.
+// Smaller matrices are re-read from the cache every iteration and keep
+// ordinary loads.
+constexpr int64_t kStreamNtBytes = 128ll << 20;
 
 // Rows per group of lanes and per wavefront tile for a lanes-per-row class:
 // a wavefront holds 64/lanes groups; each group takes up to 8 rows per tile

@@ -443,6 +443,8 @@ int dm_schedule(DevMatrix &M, int kind_opt, int grid_opt, int cus, int grid_cap,
         const int rc = build_sliced(M, M.sched.kind == kTileSliced);
         if (rc) return rc;
     }
+    M.sched.stream_nt = M.sched.kind == kTileSlicedDict &&
+                        (int64_t)M.sell_slots * (int64_t)sizeof(double) + 4ll * M.m > kStreamNtBytes;
     if (!rows.empty()) {
         const hipError_t e = hipMemcpy(M.d_rows, rows.data(), sizeof(int32_t) * rows.size(),
                                        hipMemcpyHostToDevice);

@@ -435,7 +435,8 @@ struct DictSet {
     T v[kSliceMaxWidth];
 };
 
-template <class T>
+// NT: stream the slot values and index words (and store q) nontemporally.
+template <class T, bool NT>
 __device__ __forceinline__ void dict_load(const CsrDev &A, int t, DictSet<T> &S) {
     const T *__restrict__ svals = sell_vals<T>(A);
     const int lane = threadIdx.x & (kWave - 1);
@@ -443,16 +444,17 @@ __device__ __forceinline__ void dict_load(const CsrDev &A, int t, DictSet<T> &S)
     S.nrows = min(kWave, A.m - S.r0);
     S.off = A.sell_off[t];
     S.width = (A.sell_off[t + 1] - S.off) / kWave;
-    S.idx = A.sell_idx[(int64_t)t * kWave + lane];
+    const uint32_t *ip = &A.sell_idx[(int64_t)t * kWave + lane];
+    S.idx = NT ? __builtin_nontemporal_load(ip) : *ip;
     S.dict = A.sell_dict[t * kDictSize + (lane & (kDictSize - 1))];
 #pragma unroll
     for (int j = 0; j < kSliceMaxWidth; ++j) {
         const int k = S.off + (j < S.width ? j : 0) * kWave + lane;
-        S.v[j] = svals[k];
+        S.v[j] = NT ? __builtin_nontemporal_load(&svals[k]) : svals[k];
     }
 }
 
-template <int MODE, class T>
+template <int MODE, class T, bool NT>
 __device__ __forceinline__ void dict_step(const CsrDev &A, const SpmvArgs<T> &a, const DictSet<T> &S,
                                           int tn, DictSet<T> &N, double &acc0, double &acc1) {
     const int lane = threadIdx.x & (kWave - 1);
@@ -470,7 +472,7 @@ __device__ __forceinline__ void dict_step(const CsrDev &A, const SpmvArgs<T> &a,
     T pown = T(0), bv = T(0);
     if (MODE == kSpmvDot) pown = a.p_own[myrow];
     if (MODE == kSpmvResidual) bv = a.b[myrow];
-    dict_load<T>(A, tn, N);
+    dict_load<T, NT>(A, tn, N);
     T s = T(0);
     {
 #pragma clang fp contract(off)
@@ -486,25 +488,27 @@ __device__ __forceinline__ void dict_step(const CsrDev &A, const SpmvArgs<T> &a,
             acc0 = fma((double)rv, (double)rv, acc0);
             acc1 = fma((double)bv, (double)bv, acc1);
         } else {
-            a.q[myrow] = MODE == kSpmvAccum ? T(a.q[myrow] + s) : s;
+            if (MODE == kSpmvAccum) a.q[myrow] = T(a.q[myrow] + s);
+            else if (NT) __builtin_nontemporal_store(s, &a.q[myrow]);
+            else a.q[myrow] = s;
             if (MODE == kSpmvDot) acc0 = fma((double)pown, (double)s, acc0);
         }
     }
 }
 
-template <int MODE, class T>
+template <int MODE, class T, bool NT>
 __device__ __forceinline__ void spmv_dict_wave(const CsrDev &A, TileWalk &walk, const SpmvArgs<T> &a,
                                                double &acc0, double &acc1) {
     int t = walk.next();
     if (t < 0) return;
     DictSet<T> S0, S1;
-    dict_load<T>(A, t, S0);
+    dict_load<T, NT>(A, t, S0);
     for (;;) {
         const int t1 = walk.next();
-        dict_step<MODE, T>(A, a, S0, t1 >= 0 ? t1 : t, S1, acc0, acc1);
+        dict_step<MODE, T, NT>(A, a, S0, t1 >= 0 ? t1 : t, S1, acc0, acc1);
         if (t1 < 0) break;
         const int t2 = walk.next();
-        dict_step<MODE, T>(A, a, S1, t2 >= 0 ? t2 : t1, S0, acc0, acc1);
+        dict_step<MODE, T, NT>(A, a, S1, t2 >= 0 ? t2 : t1, S0, acc0, acc1);
         if (t2 < 0) break;
         t = t2;
     }
@@ -529,7 +533,8 @@ __device__ __forceinline__ void spmv_row_wg(const CsrDev &A, int pos, bool ident
 // TILE > 0: one bin of TILE lanes per row in natural row order;
 // TILE == 0: binned rows (any order); TILE == -1: stream tiles (float64 only);
 // TILE == -2: sliced tiles of width <= kSliceMaxWidth; -3: wider slices;
-// TILE == -4: dictionary-sliced tiles.
+// TILE == -4: dictionary-sliced tiles; -5: the same with the matrix streamed
+// nontemporally (matrices larger than the last-level cache can hold).
 template <int MODE, int TILE, class T>
 __global__ __launch_bounds__(kBlock) void k_spmv(int32_t m, const int32_t *__restrict__ rp,
                                                  const int32_t *__restrict__ ci,
@@ -577,8 +582,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int32_t m, const int32_t *__res
     TileWalk walk(S.ntiles);
     if constexpr (TILE == -2 || TILE == -3) {
         spmv_sliced_wave<MODE, T>(A, walk, a, TILE == -3, acc0, acc1);
-    } else if constexpr (TILE == -4) {
-        spmv_dict_wave<MODE, T>(A, walk, a, acc0, acc1);
+    } else if constexpr (TILE == -4 || TILE == -5) {
+        spmv_dict_wave<MODE, T, TILE == -5>(A, walk, a, acc0, acc1);
     } else if constexpr (TILE == -1) {
         if constexpr (sizeof(T) == 8) {
             double *lds = s_prod + (threadIdx.x / kWave) * kStreamNnz;
@@ -1388,7 +1393,7 @@ template <int MODE, class T>
 void launch_spmv_mode(const CsrDev &A, const Schedule &S, int grid, const SpmvArgs<T> &a,
                       double *out, Partials in0, Partials in1, DevState *st, int flags,
                       hipStream_t s) {
-    const int L = S.kind == kTileSlicedDict ? -4
+    const int L = S.kind == kTileSlicedDict ? (S.stream_nt ? -5 : -4)
                   : S.kind == kTileSliced ? (S.bins[0].lanes <= kSliceMaxWidth ? -2 : -3)
                   : S.kind == kTileStream ? -1
                   : (S.identity && S.nbins == 1 && S.huge_count == 0) ? S.bins[0].lanes : 0;
@@ -1416,6 +1421,7 @@ void launch_spmv_mode(const CsrDev &A, const Schedule &S, int grid, const SpmvAr
         case -2: CGMI_SPMV(-2); break;
         case -3: CGMI_SPMV(-3); break;
         case -4: CGMI_SPMV(-4); break;
+        case -5: CGMI_SPMV(-5); break;
         default: CGMI_SPMV(0); break;
     }
 #undef CGMI_SPMV
