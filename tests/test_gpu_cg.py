@@ -578,3 +578,24 @@ def test_matrix_market_file_solves_like_the_generated_matrix(cg, tmp_path):
         x, res = s.solve(dev(p.b), tol=1e-10, maxit=5000)
     lam = 2 - 2 * np.cos(np.arange(1, 21) * np.pi / 21)
     check_cg(p.A, p.b, host(x), res, ref, 1e-10, 3 * lam.max() / (3 * lam.min()))
+
+
+def test_paper_inputs_absolute_tolerance(cg):
+    """Algorithm 1's own inputs: b = 1, x0 = 0, stop when sqrt(rho) < tau with
+    tau and I_max from tests/golden/paper_constants.json.  The absolute test
+    is the relative one at tol = tau / ||b||."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")) as f:
+        g = json.load(f)["algorithm1_defaults"]
+    A = I.poisson3d(24)
+    b = np.ones(A.n)
+    tol = g["tau"] / np.linalg.norm(b)
+    ref = oracle.cg(A, b, tol=tol, maxit=g["i_max"])
+    with cg.Solver(A) as s:
+        x, res = s.solve(dev(b), tol=tol, maxit=g["i_max"])
+    assert res["code"] == cg.CG_OK and ref["status"] == oracle.OK
+    assert res["rel_res_recur"] * np.linalg.norm(b) < g["tau"]          # sqrt(rho) < tau
+    assert abs(res["iterations"] - ref["iterations"]) <= max(2, 0.05 * ref["iterations"])
+    lam = 2 - 2 * np.cos(np.arange(1, 25) * np.pi / 25)
+    assert np.linalg.norm(host(x) - ref["x"]) / np.linalg.norm(ref["x"]) <= 2 * (lam.max() / lam.min()) * tol * 10

@@ -108,3 +108,16 @@ def test_transfer_bound_table_reports_a_moved_optimum():
     assert tab["bound_seconds"]["g0.75"] == pytest.approx(2.0 + 0.5)
     assert tab["preferred_measured"] == "g1.00" and tab["preferred_bound"] == "g0.75"
     assert tab["preferred_changes"]
+
+
+def test_planner_constants_match_the_paper():
+    """tests/golden/paper_constants.json holds the values the paper prints."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")) as f:
+        g = json.load(f)
+    assert list(S.SHARES) == g["gpu_shares"]["value"]
+    assert S.COMPETITIVE_FACTOR == g["competitive_factor"]["value"]
+    lr = g["link_ratio"]
+    assert S.LINK_RATIO == lr["numerator_gbs"] / lr["denominator_gbs"]
+    assert round(S.LINK_RATIO, lr["digits"]) == lr["value"]
