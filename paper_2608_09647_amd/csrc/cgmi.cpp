@@ -483,20 +483,38 @@ static int solve_gpu_only(cg_handle *h, const double *b, double *x, double tol, 
     const bool small = h->opts.small_path && n <= small_path_max_rows() &&
                        h->opts.precision == CG_PREC_FP64 && h->opts.precond == CG_PC_NONE &&
                        !h->shared_p();
+    if (small) {
+        // one launch: x0 read from x, the solution and the true residual
+        // written by the kernel, one read-back of the state
+        if (h->max_row_len < 0) {
+            int32_t L = 0;
+            for (int32_t i = 0; i < n; ++i) L = std::max(L, h->A.h_rp[i + 1] - h->A.h_rp[i]);
+            h->max_row_len = L;
+        }
+        const double t0 = now();
+        HIP_TRY(launch_cg_small(n, h->A.d_rp, h->A.d_ci, h->A.d_val, b, x, tol, maxit, h->d_state,
+                                h->max_row_len, st));
+        const int rc = gpu_state_read(h);
+        if (rc) return rc;
+        const DevState &s = *h->h_state;
+        const int status = status_of(s.done);
+        if (res) {
+            res->status = status;
+            res->iterations = s.iter;
+            res->converged = status == CG_OK;
+            res->rel_res_recur = s.bb > 0.0 ? std::sqrt(s.rr) / std::sqrt(s.bb) : 0.0;
+            res->rel_res_true = s.bb > 0.0 ? std::sqrt(s.rr_true) / std::sqrt(s.bb) : 0.0;
+            res->t_gpu = now() - t0;
+        }
+        return status;
+    }
     HIP_TRY(hipMemcpyAsync(h->d_x, x, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
     int rc = gpu_state_init(h, tol, maxit);
     if (rc) return rc;
     double t_gpu = 0.0, t_spmv = 0.0;
     int n_spmv = 0;
     const double t0 = now();
-    if (small) {
-        int32_t max_len = 0;
-        for (int32_t i = 0; i < n; ++i) max_len = std::max(max_len, h->A.h_rp[i + 1] - h->A.h_rp[i]);
-        HIP_TRY(launch_cg_small(n, h->A.d_rp, h->A.d_ci, h->A.d_val, b, h->d_x, tol, maxit, h->d_state,
-                                max_len, st));
-        rc = gpu_state_read(h);
-        if (rc) return rc;
-    } else {
+    {
         const int Gs = h->A.grid, Gv = h->vec_grid;
         const Partials setup_rr{h->d_part_setup, Gs}, setup_bb{h->d_part_setup + Gs, Gs};
         const Partials pq{h->d_part_pq, Gs}, rr{h->d_part_rr, Gv};

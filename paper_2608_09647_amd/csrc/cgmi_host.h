@@ -101,6 +101,7 @@ struct cg_handle {
 
     cgmi::DevMatrix A;               // the GPU row block
     int vec_grid = 0;
+    int32_t max_row_len = -1;        // longest row (single-workgroup path; -1: not yet known)
 
     // device vectors
     double *d_pbuf = nullptr;  // allocation behind d_p

@@ -33,6 +33,7 @@ struct DevState {
     int32_t maxit;
     int32_t done;      // 0 running, 1 converged, 2 iteration limit, 3 breakdown
     int32_t nrefine;   // mixed precision: float64 residuals formed
+    double rr_true;    // single-workgroup solve: ||b - A x||^2 of the returned x
 };
 
 enum { kDoneRunning = 0, kDoneConverged = 1, kDoneMaxit = 2, kDoneBreakdown = 3, kDoneRefine = 4 };
@@ -221,7 +222,9 @@ hipError_t launch_update_p_pcg(int32_t m, int grid, const double *z, double *p, 
                                Partials rz, Partials bb, DevState *st, int first, int32_t k,
                                hipStream_t s);
 
-// Whole-solve single-workgroup CG for small systems (p held in LDS).
+// Whole-solve single-workgroup CG for small systems (kernels_small.hip; p
+// held in LDS): reads x0 from x and writes the solution there; leaves iter,
+// done, rr, bb and rr_true in st.
 int small_path_max_rows();
 hipError_t launch_cg_small(int32_t n, const int32_t *rp, const int32_t *ci, const double *val,
                            const double *b, double *x, double tol, int32_t maxit, DevState *st,

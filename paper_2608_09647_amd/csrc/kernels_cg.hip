@@ -1106,277 +1106,6 @@ __global__ __launch_bounds__(kBlock) void k_convert_residual(int32_t m, const do
     if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
-// ---------------------------------------------------------------------------
-// Small systems: the whole of Algorithm 1 in one workgroup of 1024 threads.
-// p lives in LDS (every row may read any entry); thread t owns rows
-// t, t + 1024, ... and keeps their x, r, q in registers.
-constexpr int kSmallThreads = 1024;
-constexpr int kSmallWaves = kSmallThreads / kWave;
-constexpr int kSmallMaxRpt = 4;  // more rows per thread spill registers at 1024 threads
-
-// One DPP move of a double (both 32-bit halves with the same lane pattern).
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
-}
-
-__device__ __forceinline__ double readlane_f64(double v, int lane) {
-    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
-                            __builtin_amdgcn_readlane(__double2loint(v), lane));
-}
-
-// Sum over the wave, the same value in every lane, without LDS: a butterfly
-// inside each row of 16 lanes (swap neighbours, swap pairs, mirror the half
-// rows, mirror the row) leaves every lane with its row's sum; the four row
-// sums are then read as scalars and added in a fixed order.
-__device__ __forceinline__ double wave_allsum_dpp(double v) {
-    v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
-    v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
-    v += dpp_f64<0x141>(v);  // row_half_mirror
-    v += dpp_f64<0x140>(v);  // row_mirror
-    return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
-}
-
-// Every thread gets the workgroup sum after ONE barrier: each wave posts its
-// partial, then every thread adds the kSmallWaves partials itself in the same
-// fixed order (so all threads hold bitwise the same value and branch alike).
-// Consecutive calls alternate between the two halves of red: a wave can only
-// overwrite a half after the next call's barrier, which every thread reaches
-// after it has read that half.
-__device__ __forceinline__ double small_allsum(double v, double (*red)[kSmallWaves], int &half) {
-    v = wave_allsum_dpp(v);
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    if (lane == 0) red[half][w] = v;
-    __syncthreads();
-    double s = red[half][0];
-#pragma unroll
-    for (int i = 1; i < kSmallWaves; ++i) s += red[half][i];
-    half ^= 1;
-    return s;
-}
-
-// Rows read from CSR in global memory at every product (any row length).
-template <int RPT>
-__global__ __launch_bounds__(kSmallThreads) void k_cg_small(int32_t n, const int32_t *__restrict__ rp,
-                                                            const int32_t *__restrict__ ci,
-                                                            const double *__restrict__ val,
-                                                            const double *__restrict__ b,
-                                                            double *__restrict__ x, double tol,
-                                                            int32_t maxit, DevState *__restrict__ st) {
-    extern __shared__ double s_p[];
-    __shared__ double red[2][kSmallWaves];
-    int half = 0;
-    const int t = threadIdx.x;
-    double xr[RPT], rr[RPT], qq[RPT];
-    int32_t r0[RPT], r1[RPT];
-    double acc_r = 0.0, acc_b = 0.0;
-    // r = b - A x, p = r, rho = r^T r, bb = b^T b
-#pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        const int i = t + j * kSmallThreads;
-        xr[j] = 0.0;
-        rr[j] = 0.0;
-        r0[j] = r1[j] = 0;
-        if (i < n) {
-            r0[j] = rp[i];
-            r1[j] = rp[i + 1];
-            double s = 0.0;
-            for (int k = r0[j]; k < r1[j]; ++k) s = fma(val[k], x[ci[k]], s);
-            xr[j] = x[i];
-            const double bv = b[i];
-            rr[j] = bv - s;
-            acc_r = fma(rr[j], rr[j], acc_r);
-            acc_b = fma(bv, bv, acc_b);
-            s_p[i] = rr[j];
-        }
-    }
-    double rho = small_allsum(acc_r, red, half);
-    const double bb = small_allsum(acc_b, red, half);
-    const double bnorm = sqrt(bb);
-    int status = kDoneMaxit;
-    int k = 0;
-    for (k = 0; k < maxit; ++k) {
-        if (sqrt(rho) < tol * bnorm || rho == 0.0) {
-            status = kDoneConverged;
-            break;
-        }
-        double acc = 0.0;
-#pragma unroll
-        for (int j = 0; j < RPT; ++j) {
-            const int i = t + j * kSmallThreads;
-            qq[j] = 0.0;
-            if (i < n) {
-                double s = 0.0;
-                for (int kk = r0[j]; kk < r1[j]; ++kk) s = fma(val[kk], s_p[ci[kk]], s);
-                qq[j] = s;
-                acc = fma(s_p[i], s, acc);
-            }
-        }
-        const double pq = small_allsum(acc, red, half);
-        if (!(pq > 0.0) || !isfinite(pq)) {
-            status = kDoneBreakdown;
-            break;
-        }
-        const double alpha = rho / pq;
-        acc = 0.0;
-#pragma unroll
-        for (int j = 0; j < RPT; ++j) {
-            const int i = t + j * kSmallThreads;
-            if (i < n) {
-                xr[j] = fma(alpha, s_p[i], xr[j]);
-                rr[j] = fma(-alpha, qq[j], rr[j]);
-                acc = fma(rr[j], rr[j], acc);
-            }
-        }
-        const double rho_new = small_allsum(acc, red, half);
-        const double beta = rho_new / rho;
-        rho = rho_new;
-#pragma unroll
-        for (int j = 0; j < RPT; ++j) {
-            const int i = t + j * kSmallThreads;
-            if (i < n) s_p[i] = fma(beta, s_p[i], rr[j]);
-        }
-        __syncthreads();
-    }
-    if (status == kDoneMaxit && (sqrt(rho) < tol * bnorm || rho == 0.0)) status = kDoneConverged;
-#pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        const int i = t + j * kSmallThreads;
-        if (i < n) x[i] = xr[j];
-    }
-    if (t == 0) {
-        st->iter = k;
-        st->done = status;
-        st->rho[0] = rho;
-        st->rr = rho;
-        st->bb = bb;
-    }
-}
-
-// Rows of at most W entries held in registers for the whole solve: the
-// product then reads only p (from LDS).  Column indices (below 2^16: the
-// small path has at most kSmallThreads * kSmallMaxRpt rows) are packed two to
-// a register.  Slots past a row's length hold column = the row itself and
-// value 0, which leaves the row's sum unchanged, so the entries are summed in
-// CSR order exactly as the CSR variant does.
-template <int RPT, int W>
-__global__ __launch_bounds__(kSmallThreads) void k_cg_small_reg(int32_t n, const int32_t *__restrict__ rp,
-                                                                const int32_t *__restrict__ ci,
-                                                                const double *__restrict__ val,
-                                                                const double *__restrict__ b,
-                                                                double *__restrict__ x, double tol,
-                                                                int32_t maxit, DevState *__restrict__ st) {
-    static_assert(kSmallThreads * kSmallMaxRpt <= 65536, "packed 16-bit columns");
-    constexpr int WP = (W + 1) / 2;
-    extern __shared__ double s_p[];
-    __shared__ double red[2][kSmallWaves];
-    int half = 0;
-    const int t = threadIdx.x;
-    double xr[RPT], rr[RPT], qq[RPT];
-    uint32_t colp[RPT][WP];
-    double a[RPT][W];
-    double acc_r = 0.0, acc_b = 0.0;
-#pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        const int i = t + j * kSmallThreads;
-        const int32_t beg = i < n ? rp[i] : 0;
-        const int32_t len = i < n ? rp[i + 1] - beg : 0;
-        const uint32_t self = i < n ? (uint32_t)i : 0u;
-#pragma unroll
-        for (int e = 0; e < WP; ++e) colp[j][e] = 0;
-#pragma unroll
-        for (int e = 0; e < W; ++e) {
-            const uint32_t c = e < len ? (uint32_t)ci[beg + e] : self;
-            colp[j][e / 2] |= c << (16 * (e & 1));
-            a[j][e] = e < len ? val[beg + e] : 0.0;
-        }
-    }
-#define CGMI_COL(j, e) ((colp[j][(e) / 2] >> (16 * ((e) & 1))) & 0xFFFFu)
-    // r = b - A x, p = r, rho = r^T r, bb = b^T b
-#pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        const int i = t + j * kSmallThreads;
-        xr[j] = 0.0;
-        rr[j] = 0.0;
-        if (i < n) {
-            double s = 0.0;
-#pragma unroll
-            for (int e = 0; e < W; ++e) s = fma(a[j][e], x[CGMI_COL(j, e)], s);
-            xr[j] = x[i];
-            const double bv = b[i];
-            rr[j] = bv - s;
-            acc_r = fma(rr[j], rr[j], acc_r);
-            acc_b = fma(bv, bv, acc_b);
-            s_p[i] = rr[j];
-        }
-    }
-    double rho = small_allsum(acc_r, red, half);
-    const double bb = small_allsum(acc_b, red, half);
-    const double bnorm = sqrt(bb);
-    int status = kDoneMaxit;
-    int k = 0;
-    for (k = 0; k < maxit; ++k) {
-        if (sqrt(rho) < tol * bnorm || rho == 0.0) {
-            status = kDoneConverged;
-            break;
-        }
-        double acc = 0.0;
-#pragma unroll
-        for (int j = 0; j < RPT; ++j) {
-            const int i = t + j * kSmallThreads;
-            qq[j] = 0.0;
-            if (i < n) {
-                double s = 0.0;
-#pragma unroll
-                for (int e = 0; e < W; ++e) s = fma(a[j][e], s_p[CGMI_COL(j, e)], s);
-                qq[j] = s;
-                acc = fma(s_p[i], s, acc);
-            }
-        }
-        const double pq = small_allsum(acc, red, half);
-        if (!(pq > 0.0) || !isfinite(pq)) {
-            status = kDoneBreakdown;
-            break;
-        }
-        const double alpha = rho / pq;
-        acc = 0.0;
-#pragma unroll
-        for (int j = 0; j < RPT; ++j) {
-            const int i = t + j * kSmallThreads;
-            if (i < n) {
-                xr[j] = fma(alpha, s_p[i], xr[j]);
-                rr[j] = fma(-alpha, qq[j], rr[j]);
-                acc = fma(rr[j], rr[j], acc);
-            }
-        }
-        const double rho_new = small_allsum(acc, red, half);
-        const double beta = rho_new / rho;
-        rho = rho_new;
-#pragma unroll
-        for (int j = 0; j < RPT; ++j) {
-            const int i = t + j * kSmallThreads;
-            if (i < n) s_p[i] = fma(beta, s_p[i], rr[j]);
-        }
-        __syncthreads();
-    }
-    if (status == kDoneMaxit && (sqrt(rho) < tol * bnorm || rho == 0.0)) status = kDoneConverged;
-#pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        const int i = t + j * kSmallThreads;
-        if (i < n) x[i] = xr[j];
-    }
-    if (t == 0) {
-        st->iter = k;
-        st->done = status;
-        st->rho[0] = rho;
-        st->rr = rho;
-        st->bb = bb;
-    }
-}
-#undef CGMI_COL
-
 __global__ void k_gather(int32_t cnt, const int32_t *__restrict__ idx, const double *__restrict__ src,
                          double *__restrict__ dst) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1559,42 +1288,6 @@ hipError_t launch_update_p_pcg(int32_t m, int grid, const double *z, double *p, 
                                hipStream_t s) {
     if (m == 0) return hipSuccess;
     hipLaunchKernelGGL(k_update_p_pcg, dim3(grid), dim3(kBlock), 0, s, m, z, p, rr, rz, bb, st, first, k);
-    return hipGetLastError();
-}
-
-int small_path_max_rows() {
-    static int cached = -1;
-    if (cached < 0) {
-        int dev = 0;
-        hipDeviceProp_t prop;
-        size_t lds = 64 * 1024;
-        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-            lds = prop.sharedMemPerBlock;
-        const int by_lds = (int)((lds > 1024 ? lds - 1024 : 0) / sizeof(double));
-        cached = by_lds < kSmallThreads * kSmallMaxRpt ? by_lds : kSmallThreads * kSmallMaxRpt;
-    }
-    return cached;
-}
-
-hipError_t launch_cg_small(int32_t n, const int32_t *rp, const int32_t *ci, const double *val,
-                           const double *b, double *x, double tol, int32_t maxit, DevState *st,
-                           int32_t max_row_len, hipStream_t s) {
-    if (n <= 0 || n > small_path_max_rows() || max_row_len < 0) return hipErrorInvalidValue;
-    const size_t lds = sizeof(double) * (size_t)n;
-    const int rpt = (n + kSmallThreads - 1) / kSmallThreads;
-    const int L = max_row_len;
-#define CGMI_SMALL(K)                                                                              \
-    hipLaunchKernelGGL(K, dim3(1), dim3(kSmallThreads), lds, s, n, rp, ci, val, b, x, tol, maxit, st)
-    // register-resident rows where RPT x W entries fit beside the vectors
-    if (rpt <= 1 && L <= 8) CGMI_SMALL((k_cg_small_reg<1, 8>));
-    else if (rpt <= 1 && L <= 24) CGMI_SMALL((k_cg_small_reg<1, 24>));
-    else if (rpt <= 2 && L <= 8) CGMI_SMALL((k_cg_small_reg<2, 8>));
-    else if (rpt <= 2 && L <= 12) CGMI_SMALL((k_cg_small_reg<2, 12>));
-    else if (rpt <= 4 && L <= 5) CGMI_SMALL((k_cg_small_reg<4, 5>));
-    else if (rpt <= 1) CGMI_SMALL(k_cg_small<1>);
-    else if (rpt <= 2) CGMI_SMALL(k_cg_small<2>);
-    else CGMI_SMALL(k_cg_small<4>);
-#undef CGMI_SMALL
     return hipGetLastError();
 }
 

@@ -272,7 +272,7 @@ def test_cg_matches_oracle(cg, name, small_path):
 
 
 # One case per single-workgroup variant: rows per thread (n up to 1024, 2048,
-# 4096) x longest row (register-resident rows up to 8 / 24, 8 / 12, 5 entries,
+# 4096) x longest row (register-resident rows up to 8 / 20, 8 / 12, 5 entries,
 # else the CSR variant that reads the rows from memory at every product).
 # The random matrices take diagonal shift 1 (condition numbers of a few
 # hundred).  Fixed-work iterates are compared against the oracle's with a bar
@@ -282,9 +282,9 @@ def test_cg_matches_oracle(cg, name, small_path):
 # mere change of summation order.
 SMALL_CASES = {
     "rpt1_len5": (1, 5, 5, "poisson2d", lambda: I.poisson2d(30)),
-    "rpt1_len9_24": (1, 9, 24, "random", lambda: I.random_spd_lognormal(1000, 1, mean_degree=6, sigma=0.3,
-                                                                      max_degree=8, shift=1.0)),
-    "rpt1_csr": (1, 25, 10**9, "random", lambda: I.random_spd_lognormal(1000, 0, shift=1.0)),
+    "rpt1_len9_20": (1, 9, 20, "random", lambda: I.random_spd_lognormal(1000, 1, mean_degree=5, sigma=0.3,
+                                                                      max_degree=6, shift=1.0)),
+    "rpt1_csr": (1, 21, 10**9, "random", lambda: I.random_spd_lognormal(1000, 0, shift=1.0)),
     "rpt2_len7": (2, 1, 8, "poisson3d", lambda: I.poisson3d(12)),
     "rpt2_len9_12": (2, 9, 12, "random", lambda: I.random_spd_lognormal(2000, 1, mean_degree=2, sigma=0.2,
                                                                       max_degree=3, shift=1.0)),
