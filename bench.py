@@ -582,6 +582,9 @@ def bench_learned(args) -> int:
     def jacobi(s, k):
         s.set_fsai(J)
 
+    def classic(s, k):
+        s.fsai_classic()
+
     # learned: a fresh handle per repetition would re-upload A; instead the
     # first (cold) setup is timed separately and each timed repetition
     # re-runs the device setup with the same parameters
@@ -602,6 +605,7 @@ def bench_learned(args) -> int:
     out["learned"]["seconds_with_cold_setup"] = out["learned"]["solve_seconds"] + cold_setup
     run("jacobi", jacobi, 1, 0, cgmi.PC_FSAI)
     run("untrained", untrained, 1, 0, cgmi.PC_FSAI)
+    run("classic_fsai", classic, 1, 0, cgmi.PC_FSAI)
     spmv_bytes = spmv_algorithmic_bytes(A.n, A.nnz)
     t_spmv = out["learned"]["spmv_us"] * 1e-6
     achieved = spmv_bytes / t_spmv / 1e9
@@ -612,7 +616,7 @@ def bench_learned(args) -> int:
                   "n": A.n, "nnz": A.nnz, "tol": 1e-10, "seed": 10_000,
                   "contrast": prob.meta["k_max"] / prob.meta["k_min"]},
                  higher=False, plain=out["plain"], learned=out["learned"], jacobi=out["jacobi"],
-                 untrained=out["untrained"], training=train,
+                 untrained=out["untrained"], classic_fsai=out["classic_fsai"], training=train,
                  speedup_vs_plain=out["plain"]["seconds"] / out["learned"]["seconds_with_cold_setup"],
                  roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": achieved / HBM_PEAK_GBS, "traffic": None,

@@ -49,6 +49,18 @@ int cg_fsai_setup(cg_handle *h, const float *theta);
 int cg_set_fsai(cg_handle *h, int64_t nnz, const int32_t *g_row_ptr, const int32_t *g_col,
                 const double *g_val);
 
+/* Install the classic (non-learned) FSAI factor of Kolotilina and Yeremin
+ * on the pattern of tril(A), the reference a learned factor is compared
+ * with: row i of G holds the solution g of A[P_i, P_i] g = e_i over its
+ * pattern P_i (the columns of row i of tril(A), i last), scaled by
+ * 1 / sqrt(g_i), so that G A G^T has a unit diagonal.  Each local system is
+ * solved by a Cholesky factorisation on host threads.  Any SPD matrix whose
+ * tril(A) rows have at most CG_FSAI_CLASSIC_MAX_ROW entries; CG_EINVAL for a
+ * longer row, a row without a diagonal entry, or a local system that is not
+ * positive definite.  GPU-only handles.  Blocking. */
+#define CG_FSAI_CLASSIC_MAX_ROW 8
+int cg_fsai_classic(cg_handle *h);
+
 /* Read back the installed factor's values (host, float64, nnz of G in CSR
  * order of the tril(A) pattern for a learned factor). */
 int cg_fsai_factor_info(const cg_handle *h, int64_t *nnz);

@@ -26,7 +26,7 @@ EXPORTED = ["cg_create", "cg_destroy", "cg_set_stream", "cg_default_opts", "cg_s
             "cg_get_opts", "cg_spmv", "cg_spmv_f32", "cg_solve", "cg_slice_info", "cg_read_slice",
             "cg_last_error"]
 # include/cgmi_fsai.h
-EXPORTED_FSAI = ["cg_fsai_setup", "cg_set_fsai", "cg_fsai_factor_info", "cg_fsai_read_factor",
+EXPORTED_FSAI = ["cg_fsai_setup", "cg_set_fsai", "cg_fsai_classic", "cg_fsai_factor_info", "cg_fsai_read_factor",
                  "cg_fsai_trainer_create", "cg_fsai_trainer_destroy", "cg_fsai_loss_grad",
                  "cg_fsai_train_step", "cg_fsai_get_params", "cg_fsai_features"]
 FSAI_NPARAMS = 5317
@@ -147,6 +147,7 @@ def lib() -> ctypes.CDLL:
         L.cg_fsai_train_step.argtypes = [_vp, i32, _vp, i32, _vp, dbl, ctypes.POINTER(dbl)]
         L.cg_fsai_get_params.argtypes = [_vp, _vp]
         L.cg_fsai_features.argtypes = [_vp, i32, _vp]
+        L.cg_fsai_classic.argtypes = [_vp]
         for name in EXPORTED_FSAI:
             if name != "cg_fsai_trainer_destroy":
                 getattr(L, name).restype = ctypes.c_int
@@ -306,6 +307,10 @@ class Solver:
         """Build the learned factor on the device from the network parameters."""
         th = _params(theta)
         _check(lib().cg_fsai_setup(self._h, th.ctypes.data))
+
+    def fsai_classic(self) -> None:
+        """Install the classic (non-learned) FSAI factor on tril(A)."""
+        _check(lib().cg_fsai_classic(self._h))
 
     def read_factor(self):
         nnz = ctypes.c_int64()

@@ -261,6 +261,97 @@ extern "C" int cg_set_fsai(cg_handle *h, int64_t nnz, const int32_t *g_row_ptr, 
     return CG_OK;
 }
 
+// Classic FSAI: per row, the Cholesky factor L of the local block
+// M = A[P, P] (columns of tril(A) row i, i last), then g = M^-1 e_last by
+// the two triangular solves; g_last = 1 / L_last,last^2, so the scaled row
+// g / sqrt(g_last) is g * L_last,last.
+extern "C" int cg_fsai_classic(cg_handle *h) {
+    clear_error();
+    int rc = check_gpu_handle(h);
+    if (rc) return rc;
+    const int32_t n = h->n;
+    constexpr int kMax = CG_FSAI_CLASSIC_MAX_ROW;
+    std::vector<int32_t> g_rp, g_ci;
+    std::vector<double> g_val;
+    try {
+        g_rp.assign((size_t)n + 1, 0);
+        int32_t bad_row = INT32_MAX, bad_kind = 0;
+#pragma omp parallel for schedule(static)
+        for (int32_t i = 0; i < n; ++i) {
+            int cnt = 0;
+            bool diag = false;
+            for (int32_t k = h->h_rp[i]; k < h->h_rp[i + 1] && h->h_ci[k] <= i; ++k) {
+                ++cnt;
+                diag = h->h_ci[k] == i;
+            }
+            g_rp[i + 1] = cnt;
+            const int kind = !diag ? 1 : cnt > kMax ? 2 : 0;
+            if (kind) {
+#pragma omp critical(cgmi_classic_bad_row)
+                if (i < bad_row) {
+                    bad_row = i;
+                    bad_kind = kind;
+                }
+            }
+        }
+        if (bad_kind == 1) return fail(CG_EINVAL, "row %d has no diagonal entry", bad_row);
+        if (bad_kind == 2)
+            return fail(CG_EINVAL, "row %d of tril(A) has more than %d entries", bad_row, kMax);
+        for (int32_t i = 0; i < n; ++i) g_rp[i + 1] += g_rp[i];
+        g_ci.resize((size_t)g_rp[n]);
+        g_val.resize((size_t)g_rp[n]);
+        bad_row = INT32_MAX;
+        // entry (r, c) of A by a scan of row r (columns ascending)
+        auto a_at = [&](int32_t r, int32_t c) {
+            for (int32_t k = h->h_rp[r]; k < h->h_rp[r + 1] && h->h_ci[k] <= c; ++k)
+                if (h->h_ci[k] == c) return h->h_val[k];
+            return 0.0;
+        };
+#pragma omp parallel for schedule(static)
+        for (int32_t i = 0; i < n; ++i) {
+            const int32_t b = g_rp[i];
+            const int m = g_rp[i + 1] - b;
+            int32_t P[kMax];
+            for (int e = 0; e < m; ++e) P[e] = g_ci[(size_t)b + e] = h->h_ci[h->h_rp[i] + e];
+            double L[kMax][kMax] = {};
+            bool ok = true;
+            for (int c = 0; c < m && ok; ++c) {
+                for (int r = c; r < m; ++r) {
+                    double v = a_at(P[r], P[c]);
+                    for (int k = 0; k < c; ++k) v -= L[r][k] * L[c][k];
+                    if (r == c) {
+                        if (!(v > 0.0)) {
+                            ok = false;
+                            break;
+                        }
+                        L[c][c] = std::sqrt(v);
+                    } else {
+                        L[r][c] = v / L[c][c];
+                    }
+                }
+            }
+            if (!ok) {
+#pragma omp critical(cgmi_classic_bad_row)
+                bad_row = std::min(bad_row, i);
+                continue;
+            }
+            double g[kMax];
+            g[m - 1] = 1.0 / (L[m - 1][m - 1] * L[m - 1][m - 1]);
+            for (int r = m - 2; r >= 0; --r) {
+                double v = 0.0;
+                for (int j = r + 1; j < m; ++j) v -= L[j][r] * g[j];
+                g[r] = v / L[r][r];
+            }
+            for (int e = 0; e < m; ++e) g_val[(size_t)b + e] = g[e] * L[m - 1][m - 1];
+        }
+        if (bad_row != INT32_MAX)
+            return fail(CG_EINVAL, "the local system of row %d is not positive definite", bad_row);
+    } catch (...) {
+        return fail(CG_ENOMEM, "out of host memory");
+    }
+    return cg_set_fsai(h, (int64_t)g_rp[n], g_rp.data(), g_ci.data(), g_val.data());
+}
+
 namespace {
 
 // Structure of the learned factor: G on the pattern of tril(A) and the

@@ -308,3 +308,68 @@ def test_training_reduces_loss_and_beats_plain_cg(cg):
     assert res["status"] == 0 and res["fell_back"] == 0
     assert res["iterations"] < plain["iterations"]
     assert res["rel_res_true"] <= 1.01e-10
+
+
+# ----------------------------------------------------------------------------- classic FSAI
+
+CLASSIC_CASES = {
+    "diffusion_40x36": lambda: field(40, 36, 51),
+    "poisson3d_12": lambda: I.poisson3d(12),
+    # tril rows of 8 entries at most (the classic factor's limit)
+    "random_short_rows": lambda: I.random_spd_lognormal(1500, 2, mean_degree=1.5, sigma=0.2, max_degree=2,
+                                                        shift=1.0),
+}
+
+
+@pytest.mark.parametrize("name", list(CLASSIC_CASES))
+def test_classic_fsai_factor_matches_oracle(cg, name):
+    A = CLASSIC_CASES[name]()
+    ref = OF.classic_fsai(A)
+    with cg.Solver(A) as s:
+        s.fsai_classic()
+        rp, ci, va = s.read_factor()
+    assert np.array_equal(rp, ref.indptr) and np.array_equal(ci, ref.indices)
+    # per-row local solves: Cholesky here, LU in the oracle
+    scale = np.repeat(np.maximum.reduceat(np.abs(ref.data), ref.indptr[:-1]), np.diff(ref.indptr))
+    err = np.max(np.abs(va - ref.data) / scale)
+    print(f"[classic] {name}: max row-relative difference {err:.2e}", flush=True)
+    assert err <= 1e-12
+    # unit diagonal of G A G^T (the defining property of the scaling)
+    G = sp.csr_matrix((va, ci, rp), shape=(A.n, A.n))
+    d = (G @ A.scipy() @ G.T).diagonal()
+    assert np.max(np.abs(d - 1.0)) <= 1e-12
+
+
+def test_pcg_with_classic_factor_matches_oracle(cg):
+    A = field(40, 40, 53)
+    b = I.rhs_of(A, I.uniform_vector(A.n, [53, 1]))
+    with cg.Solver(A) as s:
+        s.fsai_classic()
+        s.set_opts(precond=cg.PC_FSAI)
+        x, res = s.solve(dev(b), tol=1e-10, maxit=20000)
+        rp, ci, va = s.read_factor()
+    res2, ref = check_pcg_against_oracle(cg, A, b, sp.csr_matrix((va, ci, rp), shape=(A.n, A.n)))
+    assert res["iterations"] == res2["iterations"]
+    plain = oracle.cg(A, b, tol=1e-10, maxit=20000)
+    assert ref["iterations"] < plain["iterations"]
+
+
+def test_classic_fsai_rejections(cg):
+    long_rows = I.random_spd_lognormal(500, 0)                 # tril rows far longer than 8
+    with cg.Solver(long_rows) as s:
+        with pytest.raises(cg.CgError, match="more than"):
+            s.fsai_classic()
+    no_diag = I.poisson2d(6)
+    keep = no_diag.col != np.repeat(np.arange(no_diag.n), np.diff(no_diag.row_ptr))
+    keep[np.flatnonzero(~keep)[1:]] = True                     # drop the diagonal of row 0 only
+    rows = np.repeat(np.arange(no_diag.n), np.diff(no_diag.row_ptr))[keep]
+    M = I.CSR(no_diag.n, np.concatenate([[0], np.cumsum(np.bincount(rows, minlength=no_diag.n))]).astype(np.int32),
+              no_diag.col[keep], no_diag.val[keep])
+    with cg.Solver(M) as s:
+        with pytest.raises(cg.CgError, match="no diagonal"):
+            s.fsai_classic()
+    neg = I.poisson2d(6)
+    neg.val = np.where(neg.col == np.repeat(np.arange(neg.n), np.diff(neg.row_ptr)), -4.0, neg.val)
+    with cg.Solver(neg) as s:
+        with pytest.raises(cg.CgError, match="not positive definite"):
+            s.fsai_classic()
