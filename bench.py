@@ -287,7 +287,7 @@ def main() -> int:
         "hbm_copy_gbs_measured": copy_gbs,
         "spmv_frac_of_measured_copy": achieved / copy_gbs,
         "spmv_kind": {1: "vector_bins", 2: "stream", 3: "sliced", 4: "sliced_dict",
-                      5: "column_blocks"}.get(res["spmv_kind"]),
+                      5: "column_blocks", 6: "stencil_slices"}.get(res["spmv_kind"]),
         "rel_res_true": res["rel_res_true"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
@@ -507,7 +507,8 @@ def bench_matrix_market(args) -> int:
     sec = float(np.mean(times))
     gbs = spmv_algorithmic_bytes(A.n, A.nnz) / (spmv_us * 1e-6) / 1e9
     err = float(np.linalg.norm(x.cpu().numpy() - xs) / np.linalg.norm(xs))
-    kinds = {1: "vector_bins", 2: "stream", 3: "sliced", 4: "sliced_dict", 5: "column_blocks"}
+    kinds = {1: "vector_bins", 2: "stream", 3: "sliced", 4: "sliced_dict", 5: "column_blocks",
+             6: "stencil_slices"}
     line = _line("CG iters/s on a Matrix Market matrix (fixed work); time to 1e-10", res["iterations"] / sec,
                  "iter/s", args, 1e3 * sec,
                  {"workload": f"matrix_market:{os.path.basename(args.mtx)}", "n": A.n, "nnz": A.nnz,

@@ -103,13 +103,20 @@ typedef struct cg_opts {
                               offsets; rows of at most 8 nonzeros, else 3),
                               5 column blocks (one accumulating vector-bin pass
                               per block of spmv_colblock columns, so gathers
-                              from p stay in the L2; for scattered columns).
+                              from p stay in the L2; for scattered columns),
+                              6 stencil slices (slot j of a 64-row slice holds
+                              the entries at the slice's j-th column offset, so
+                              columns are row + a slice-uniform offset and a
+                              byte per row marks the present slots; rows of at
+                              most 8 nonzeros, at most 8 distinct offsets per
+                              slice, float64 with host values; else 4).
                               Automatic picks 5 when more than half of the
                               entries lie farther than 262,144 columns from the
                               diagonal and the vector spans at least two blocks,
-                              else 4 when rows have <= 8 nonzeros and every
-                              slice fits the table, else 3 when rows have <= 64
-                              nonzeros and slicing pads by <= 25%, else 1.      */
+                              else 6 where it applies, else 4 when rows have
+                              <= 8 nonzeros and every slice fits the table,
+                              else 3 when rows have <= 64 nonzeros and slicing
+                              pads by <= 25%, else 1.                          */
     int32_t spmv_colblock; /* columns per block of the column-blocked tiling
                               (spmv_kind 5); 0: 262,144 (2 MB of float64 p)     */
     double refine_delta;   /* mixed precision: a float64 refinement is made
@@ -140,7 +147,8 @@ typedef struct cg_result {
                                 plain float64 CG                                 */
     int32_t spmv_kind;       /* SpMV tiling used on the GPU rows: 1 vector bins,
                                 2 stream tiles, 3 sliced tiles, 4 dictionary-
-                                sliced tiles, 5 column blocks (0: no GPU rows)   */
+                                sliced tiles, 5 column blocks, 6 stencil slices
+                                (0: no GPU rows)                                 */
 } cg_result;
 
 /* Create a solver for the n x n CSR matrix (host arrays, copied).  Rows

@@ -131,7 +131,8 @@ def batch_schedule(batch: "cgmi.Batch", systems, B, tune_if_missing: bool = True
 
 # ----------------------------------------------------------------------------- single-system SpMV tiling
 
-SPMV_KINDS = {1: "vector_bins", 2: "stream", 3: "sliced", 4: "sliced_dict", 5: "column_blocks"}
+SPMV_KINDS = {1: "vector_bins", 2: "stream", 3: "sliced", 4: "sliced_dict", 5: "column_blocks",
+              6: "stencil_slices"}
 
 
 def tune_spmv(solver: "cgmi.Solver", b, iters: int = 20, grids=(0, 2048, 4096), log=None) -> dict:

@@ -326,7 +326,7 @@ extern "C" int cg_set_opts(cg_handle *h, const cg_opts *o) {
         return fail(CG_EINVAL, "refine_delta must be in (0, 1)");
     if ((o->precision != CG_PREC_FP64 || o->precond != CG_PC_NONE) && !h->gpu_only())
         return fail(CG_EINVAL, "mixed precision and preconditioning need a GPU-only handle");
-    if (o->spmv_kind < 0 || o->spmv_kind > 5) return fail(CG_EINVAL, "unknown spmv_kind %d", o->spmv_kind);
+    if (o->spmv_kind < 0 || o->spmv_kind > 6) return fail(CG_EINVAL, "unknown spmv_kind %d", o->spmv_kind);
     if (o->spmv_colblock < 0) return fail(CG_EINVAL, "spmv_colblock must be >= 0");
     if (o->precision == CG_PREC_MIXED && o->precond != CG_PC_NONE)
         return fail(CG_EINVAL, "the preconditioned solve runs in float64 only");
@@ -1020,7 +1020,7 @@ extern "C" int cg_solve(cg_handle *h, const double *b, double *x, double tol, in
     }
     if (res) {
         res->t_solve = now() - t0;
-        static const int kind_code[5] = {1, 2, 3, 4, 5};   // kTileVector .. kTileColBlocked
+        static const int kind_code[6] = {1, 2, 3, 4, 5, 6};   // kTileVector .. kTileStencil
         res->spmv_kind = h->m == 0 ? 0 : kind_code[h->A.sched.kind];
         res->rows_gpu = h->m;
         res->rows_cpu = h->n - h->m;

@@ -52,6 +52,10 @@ struct DevMatrix {
     float *d_val32 = nullptr, *d_sell_val32 = nullptr;
     uint32_t *d_sell_idx = nullptr;   // dictionary-sliced layout
     int32_t *d_sell_dict = nullptr;
+    int32_t *d_st_off = nullptr, *d_st_offs = nullptr;   // stencil-sliced layout
+    uint8_t *d_st_mask = nullptr;
+    double *d_st_val = nullptr;
+    size_t st_slots = 0;
     std::vector<DevMatrix> blocks;    // column-blocked layout: one CSR per column block
     ColBlocks *cb = nullptr;          //   and their launch operands
     int32_t block_cols = 0;           //   columns per block
@@ -60,7 +64,8 @@ struct DevMatrix {
     CsrDev dev() const {
         return CsrDev{m, d_rp, d_ci, d_val, sched.identity ? nullptr : d_rows,
                       d_sell_off, d_sell_ci, d_sell_val, d_val32, d_sell_val32,
-                      d_sell_idx, d_sell_dict, pad_col_base, cb};
+                      d_sell_idx, d_sell_dict, pad_col_base, cb,
+                      d_st_off, d_st_offs, d_st_mask, d_st_val};
     }
 };
 

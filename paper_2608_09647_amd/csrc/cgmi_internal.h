@@ -73,7 +73,16 @@ constexpr uint32_t kDictPad = 0xFu;
 // of p that stays in each XCD's L2.
 constexpr int kMaxColBlocks = 64;
 constexpr int32_t kColBlockCols = 1 << 18;
-enum { kTileVector = 0, kTileStream = 1, kTileSliced = 2, kTileSlicedDict = 3, kTileColBlocked = 4 };
+// Stencil slices (kind kTileStencil): each 64-row slice takes the sorted
+// union of its rows' column offsets (column - global row), at most
+// kSliceMaxWidth of them, in st_offs[8t .. 8t+7]; slot j of every row of the
+// slice holds the entry at offset st_offs[8t+j] (value 0 where the row has
+// none), so a slot's column is the row plus a slice-uniform offset, and bit j
+// of the row's byte st_mask[64t + l] says whether the entry exists.  Slots are
+// in ascending column order, so rows are summed exactly in CSR order.
+// Values slot-major from st_off[t], float64 only.
+enum { kTileVector = 0, kTileStream = 1, kTileSliced = 2, kTileSlicedDict = 3, kTileColBlocked = 4,
+       kTileStencil = 5 };
 
 struct Schedule {
     Bin bins[kMaxBins];
@@ -82,8 +91,8 @@ struct Schedule {
     int32_t identity;     // 1: the row list is 0..m-1 (no indirection)
     int32_t huge_first;   // rows longer than kHugeRow: positions in the row list
     int32_t huge_count;
-    int32_t kind;         // kTileVector, kTileStream, kTileSliced or kTileSlicedDict
-    int32_t stream_nt;    // dictionary tiles: 1 = load the matrix and store q nontemporally
+    int32_t kind;         // kTileVector .. kTileStencil
+    int32_t stream_nt;    // dictionary / stencil tiles: 1 = load the matrix and store q nontemporally
 };
 
 // A matrix whose streamed bytes exceed half the last-level cache (256 MB on
@@ -120,6 +129,10 @@ struct CsrDev {
     const int32_t *sell_dict; //   per-slice column offsets
     int32_t col_base;         // global index of local row 0
     const struct ColBlocks *cb;  // column-blocked layout (host memory; launch side only)
+    const int32_t *st_off;    // stencil slices: slice offsets into st_val (ntiles + 1)
+    const int32_t *st_offs;   //   per-slice column offsets (8 per slice)
+    const uint8_t *st_mask;   //   per-row slot bits
+    const double *st_val;     //   slot-major values
 };
 
 // Per-block operands of the column-blocked tiling (kept on the host by the

@@ -38,7 +38,105 @@ void free_sliced(DevMatrix &M) {
     M.d_sell_idx = nullptr;
     M.d_sell_dict = nullptr;
     M.sell_slots = 0;
+    (void)hipFree(M.d_st_off);
+    (void)hipFree(M.d_st_offs);
+    (void)hipFree(M.d_st_mask);
+    (void)hipFree(M.d_st_val);
+    M.d_st_off = M.d_st_offs = nullptr;
+    M.d_st_mask = nullptr;
+    M.d_st_val = nullptr;
+    M.st_slots = 0;
 }
+
+// Stencil-sliced copy (see kTileStencil): per 64-row slice the sorted union
+// of the rows' column offsets, slot j of each row at offset j (value 0 where
+// absent) and a byte of slot bits per row.  false (nothing uploaded) when a
+// slice has more than kSliceMaxWidth distinct offsets; needs the host values.
+int build_stencil(DevMatrix &M, bool *fits) {
+    *fits = false;
+    if (M.d_st_val) {
+        *fits = true;
+        return CG_OK;
+    }
+    const int32_t m = M.m, nt = (m + kWaveSize - 1) / kWaveSize;
+    constexpr int W = kSliceMaxWidth;
+    std::vector<int32_t> offs((size_t)nt * W, 0), width((size_t)nt, 1), off((size_t)nt + 1, 0);
+    std::atomic<bool> ok{true};
+#pragma omp parallel for schedule(static)
+    for (int32_t t = 0; t < nt; ++t) {
+        if (!ok.load(std::memory_order_relaxed)) continue;
+        int32_t u[W];
+        int nu = 0;
+        for (int32_t i = t * kWaveSize; i < std::min(m, (t + 1) * kWaveSize) && nu <= W; ++i)
+            for (int32_t k = M.h_rp[i]; k < M.h_rp[i + 1]; ++k) {
+                const int32_t o = M.h_ci[k] - (M.pad_col_base + i);
+                int e = 0;
+                while (e < nu && u[e] != o) ++e;
+                if (e == nu) {
+                    if (nu == W) {
+                        nu = W + 1;
+                        break;
+                    }
+                    u[nu++] = o;
+                }
+            }
+        if (nu > W) {
+            ok = false;
+            continue;
+        }
+        std::sort(u, u + nu);
+        for (int e = 0; e < nu; ++e) offs[(size_t)t * W + e] = u[e];
+        width[(size_t)t] = std::max(nu, 1);
+    }
+    if (!ok.load()) return CG_OK;
+    for (int32_t t = 0; t < nt; ++t) off[t + 1] = off[t] + width[(size_t)t] * kWaveSize;
+    if ((int64_t)off[nt] >= INT32_MAX) return CG_OK;
+    const size_t slots = (size_t)off[nt];
+    std::vector<double> sval(slots, 0.0);
+    std::vector<uint8_t> mask((size_t)nt * kWaveSize, 0);
+#pragma omp parallel for schedule(static)
+    for (int32_t t = 0; t < nt; ++t) {
+        const int32_t *u = &offs[(size_t)t * W];
+        const int w = width[(size_t)t];
+        for (int32_t l = 0; l < kWaveSize; ++l) {
+            const int32_t i = t * kWaveSize + l;
+            if (i >= m) break;
+            uint8_t bits = 0;
+            int e = 0;
+            for (int32_t k = M.h_rp[i]; k < M.h_rp[i + 1]; ++k) {
+                const int32_t o = M.h_ci[k] - (M.pad_col_base + i);
+                while (e < w && u[e] != o) ++e;   // offsets ascend with the columns
+                bits |= (uint8_t)(1u << e);
+                sval[(size_t)off[t] + (size_t)e * kWaveSize + l] = M.h_val[k];
+                ++e;
+            }
+            mask[(size_t)i] = bits;
+        }
+    }
+    hipError_t e = dmalloc(&M.d_st_off, off.size());
+    if (e == hipSuccess) e = dmalloc(&M.d_st_offs, offs.size());
+    if (e == hipSuccess) e = dmalloc(&M.d_st_mask, mask.size());
+    if (e == hipSuccess) e = dmalloc(&M.d_st_val, slots);
+    if (e == hipSuccess) e = hipMemcpy(M.d_st_off, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(M.d_st_offs, offs.data(), sizeof(int32_t) * offs.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(M.d_st_mask, mask.data(), mask.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(M.d_st_val, sval.data(), sizeof(double) * slots, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(M.d_st_off);
+        (void)hipFree(M.d_st_offs);
+        (void)hipFree(M.d_st_mask);
+        (void)hipFree(M.d_st_val);
+        M.d_st_off = M.d_st_offs = nullptr;
+        M.d_st_mask = nullptr;
+        M.d_st_val = nullptr;
+        return fail(CG_ENOMEM, "stencil layout upload failed: %s", hipGetErrorString(e));
+    }
+    M.st_slots = slots;
+    *fits = true;
+    return CG_OK;
+}
+
 
 // Dictionary of column offsets (column - global row) of each 64-row slice;
 // false if some slice has more than kDictSize - 1 distinct offsets or a row
@@ -405,7 +503,8 @@ int dm_ensure_f32(DevMatrix &M) {
 int dm_schedule(DevMatrix &M, int kind_opt, int grid_opt, int cus, int grid_cap, bool need_f32,
                 int32_t block_cols) {
     std::vector<int32_t> rows;
-    build_schedule(M, kind_opt, M.sched, rows);
+    // stencil slices (6) start from the dictionary choice and are upgraded below
+    build_schedule(M, kind_opt == 6 ? 4 : kind_opt, M.sched, rows);
     if (M.sched.kind == kTileColBlocked) {
         const int32_t bc = block_cols > 0 ? block_cols : kColBlockCols;
         if (M.cb && M.block_cols == bc && need_f32)
@@ -416,6 +515,15 @@ int dm_schedule(DevMatrix &M, int kind_opt, int grid_opt, int cus, int grid_cap,
             }
         const int rc = build_blocks(M, bc, cus, grid_cap, need_f32);
         if (rc) return rc;
+    }
+    // stencil slices where every slice has at most 8 distinct column offsets
+    // (float64 with host values); else the dictionary or plain slices
+    if ((kind_opt == 0 || kind_opt == 6) && !need_f32 && !M.h_val.empty() &&
+        (M.sched.kind == kTileSlicedDict || M.sched.kind == kTileSliced) && M.sched.bins[0].lanes <= kSliceMaxWidth) {
+        bool fits = false;
+        const int rc = build_stencil(M, &fits);
+        if (rc) return rc;
+        if (fits) M.sched.kind = kTileStencil;
     }
     if (M.sched.kind == kTileSlicedDict && !M.d_sell_idx) {
         std::vector<int32_t> dict;
@@ -443,8 +551,11 @@ int dm_schedule(DevMatrix &M, int kind_opt, int grid_opt, int cus, int grid_cap,
         const int rc = build_sliced(M, M.sched.kind == kTileSliced);
         if (rc) return rc;
     }
-    M.sched.stream_nt = M.sched.kind == kTileSlicedDict &&
-                        (int64_t)M.sell_slots * (int64_t)sizeof(double) + 4ll * M.m > kStreamNtBytes;
+    if (M.sched.kind == kTileStencil)
+        M.sched.stream_nt = (int64_t)M.st_slots * (int64_t)sizeof(double) + (int64_t)M.m > kStreamNtBytes;
+    else
+        M.sched.stream_nt = M.sched.kind == kTileSlicedDict &&
+                            (int64_t)M.sell_slots * (int64_t)sizeof(double) + 4ll * M.m > kStreamNtBytes;
     if (!rows.empty()) {
         const hipError_t e = hipMemcpy(M.d_rows, rows.data(), sizeof(int32_t) * rows.size(),
                                        hipMemcpyHostToDevice);

@@ -514,6 +514,68 @@ __device__ __forceinline__ void spmv_dict_wave(const CsrDev &A, TileWalk &walk, 
     }
 }
 
+// Stencil slices: slot j of a slice holds, for every row of the slice, the
+// entry at column row + offs[j], an offset the whole slice shares (scalar
+// loads per tile); bit j of the row's mask byte says whether the row has it.
+// Slots past the slice's width load nothing (a wave-uniform branch); a slot
+// the row lacks gathers the row's own entry of p and is not summed.  Rows are
+// summed in CSR order with rounded products (the slots ascend with the
+// column), so results are bit-exact against the oracle.  One tile at a time:
+// 54 registers, 8 waves per SIMD.  float64 only.
+template <int MODE, bool NT>
+__device__ __forceinline__ void spmv_sten_wave(const CsrDev &A, TileWalk &walk,
+                                               const SpmvArgs<double> &a, double &acc0, double &acc1) {
+    const int lane = threadIdx.x & (kWave - 1);
+    for (int t = walk.next(); t >= 0; t = walk.next()) {
+        const int r0 = __builtin_amdgcn_readfirstlane(t * kWave);
+        const int nrows = min(kWave, A.m - r0);
+        const int off = A.st_off[t];
+        const int width = (A.st_off[t + 1] - off) / kWave;
+        int offs[kSliceMaxWidth];
+#pragma unroll
+        for (int j = 0; j < kSliceMaxWidth; ++j) offs[j] = A.st_offs[t * kSliceMaxWidth + j];
+        const int myrow = r0 + min(lane, nrows - 1);
+        const int gcol = A.col_base + myrow;
+        const uint8_t *mp = &A.st_mask[(int64_t)t * kWave + lane];
+        const uint32_t mask = NT ? (uint32_t)__builtin_nontemporal_load(mp) : (uint32_t)*mp;
+        // slots past the slice's width (uniform across the wave) load nothing
+        double v[kSliceMaxWidth], pv[kSliceMaxWidth];
+#pragma unroll
+        for (int j = 0; j < kSliceMaxWidth; ++j) {
+            v[j] = pv[j] = 0.0;
+            if (j < width) {
+                const int k = off + j * kWave + lane;
+                v[j] = NT ? __builtin_nontemporal_load(&A.st_val[k]) : A.st_val[k];
+                pv[j] = a.p[(mask >> j) & 1u ? gcol + offs[j] : gcol];
+            }
+        }
+        double pown = 0.0, bv = 0.0;
+        if (MODE == kSpmvDot) pown = a.p_own[myrow];
+        if (MODE == kSpmvResidual) bv = a.b[myrow];
+        double s = 0.0;
+        {
+#pragma clang fp contract(off)
+#pragma unroll
+            for (int j = 0; j < kSliceMaxWidth; ++j)
+                if ((mask >> j) & 1u) s = s + v[j] * pv[j];  // rounded product, then the sum
+        }
+        if (lane < nrows) {
+            if (MODE == kSpmvResidual) {
+                const double rv = bv - s;
+                a.q[myrow] = rv;
+                a.p_dst[myrow] = rv;
+                acc0 = fma(rv, rv, acc0);
+                acc1 = fma(bv, bv, acc1);
+            } else {
+                if (MODE == kSpmvAccum) a.q[myrow] = a.q[myrow] + s;
+                else if (NT) __builtin_nontemporal_store(s, &a.q[myrow]);
+                else a.q[myrow] = s;
+                if (MODE == kSpmvDot) acc0 = fma(pown, s, acc0);
+            }
+        }
+    }
+}
+
 // A row longer than kHugeRow: all threads of the workgroup on it.
 template <int MODE, class T>
 __device__ __forceinline__ void spmv_row_wg(const CsrDev &A, int pos, bool identity,
@@ -534,7 +596,8 @@ __device__ __forceinline__ void spmv_row_wg(const CsrDev &A, int pos, bool ident
 // TILE == 0: binned rows (any order); TILE == -1: stream tiles (float64 only);
 // TILE == -2: sliced tiles of width <= kSliceMaxWidth; -3: wider slices;
 // TILE == -4: dictionary-sliced tiles; -5: the same with the matrix streamed
-// nontemporally (matrices larger than the last-level cache can hold).
+// nontemporally (matrices larger than the last-level cache can hold);
+// -6 / -7: stencil slices, cached / nontemporal (float64 only).
 template <int MODE, int TILE, class T>
 __global__ __launch_bounds__(kBlock) void k_spmv(int32_t m, const int32_t *__restrict__ rp,
                                                  const int32_t *__restrict__ ci,
@@ -545,11 +608,15 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int32_t m, const int32_t *__res
                                                  const T *__restrict__ sell_val,
                                                  const uint32_t *__restrict__ sell_idx,
                                                  const int32_t *__restrict__ sell_dict, int32_t col_base,
+                                                 const int32_t *__restrict__ st_off,
+                                                 const int32_t *__restrict__ st_offs,
+                                                 const uint8_t *__restrict__ st_mask,
+                                                 const double *__restrict__ st_val,
                                                  Schedule S, SpmvArgs<T> a, double *__restrict__ out,
                                                  Partials in0, Partials in1,
                                                  DevState *__restrict__ st, int flags) {
     CsrDev A{m, rp, ci, nullptr, rows, sell_off, sell_ci, nullptr, nullptr, nullptr,
-             sell_idx, sell_dict, col_base};
+             sell_idx, sell_dict, col_base, nullptr, st_off, st_offs, st_mask, st_val};
     if constexpr (sizeof(T) == 8) {
         A.val = reinterpret_cast<const double *>(val);
         A.sell_val = reinterpret_cast<const double *>(sell_val);
@@ -584,6 +651,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int32_t m, const int32_t *__res
         spmv_sliced_wave<MODE, T>(A, walk, a, TILE == -3, acc0, acc1);
     } else if constexpr (TILE == -4 || TILE == -5) {
         spmv_dict_wave<MODE, T, TILE == -5>(A, walk, a, acc0, acc1);
+    } else if constexpr (TILE == -6 || TILE == -7) {
+        if constexpr (sizeof(T) == 8) spmv_sten_wave<MODE, TILE == -7>(A, walk, a, acc0, acc1);
     } else if constexpr (TILE == -1) {
         if constexpr (sizeof(T) == 8) {
             double *lds = s_prod + (threadIdx.x / kWave) * kStreamNnz;
@@ -1122,7 +1191,8 @@ template <int MODE, class T>
 void launch_spmv_mode(const CsrDev &A, const Schedule &S, int grid, const SpmvArgs<T> &a,
                       double *out, Partials in0, Partials in1, DevState *st, int flags,
                       hipStream_t s) {
-    const int L = S.kind == kTileSlicedDict ? (S.stream_nt ? -5 : -4)
+    const int L = S.kind == kTileStencil ? (S.stream_nt ? -7 : -6)
+                  : S.kind == kTileSlicedDict ? (S.stream_nt ? -5 : -4)
                   : S.kind == kTileSliced ? (S.bins[0].lanes <= kSliceMaxWidth ? -2 : -3)
                   : S.kind == kTileStream ? -1
                   : (S.identity && S.nbins == 1 && S.huge_count == 0) ? S.bins[0].lanes : 0;
@@ -1136,7 +1206,8 @@ void launch_spmv_mode(const CsrDev &A, const Schedule &S, int grid, const SpmvAr
     }
 #define CGMI_SPMV(FL)                                                                             \
     hipLaunchKernelGGL((k_spmv<MODE, FL, T>), dim3(grid), dim3(kBlock), 0, s, A.m, A.rp, A.ci, val, \
-                       A.rows, A.sell_off, A.sell_ci, sval, A.sell_idx, A.sell_dict, A.col_base, S, a,  \
+                       A.rows, A.sell_off, A.sell_ci, sval, A.sell_idx, A.sell_dict, A.col_base,       \
+                       A.st_off, A.st_offs, A.st_mask, A.st_val, S, a,                                \
                        out, in0, in1, st, flags)
     switch (L) {
         case 1: CGMI_SPMV(1); break;
@@ -1151,6 +1222,8 @@ void launch_spmv_mode(const CsrDev &A, const Schedule &S, int grid, const SpmvAr
         case -3: CGMI_SPMV(-3); break;
         case -4: CGMI_SPMV(-4); break;
         case -5: CGMI_SPMV(-5); break;
+        case -6: CGMI_SPMV(-6); break;
+        case -7: CGMI_SPMV(-7); break;
         default: CGMI_SPMV(0); break;
     }
 #undef CGMI_SPMV
@@ -1212,7 +1285,7 @@ hipError_t launch_spmv_f32(const CsrDev &A, const Schedule &S, int grid, const f
                            const float *p_own, double *out_partials, DevState *st, int mode,
                            hipStream_t s) {
     if (A.m == 0) return hipSuccess;
-    if (S.kind == kTileStream) return hipErrorInvalidValue;
+    if (S.kind == kTileStream || S.kind == kTileStencil) return hipErrorInvalidValue;   // no float32 variant
     SpmvArgs<float> a{p, q, p_own, nullptr, nullptr};
     const Partials none{nullptr, 0};
     if (S.kind == kTileColBlocked) {

@@ -100,7 +100,22 @@ def used_kind(s, n):
     return res["spmv_kind"]
 
 
-@pytest.mark.parametrize("kind", [1, 2, 3, 4, 5])
+def stencil_applies(A):
+    """Whether every 64-row slice has at most 8 distinct column offsets
+    (column - row), so stencil slices (kind 6) apply."""
+    lens = np.diff(A.row_ptr)
+    if lens.max() > 8:
+        return False
+    rows = np.repeat(np.arange(A.n), lens)
+    off = A.col.astype(np.int64) - rows
+    for t in range(0, A.n, 64):
+        o = off[A.row_ptr[t]:A.row_ptr[min(A.n, t + 64)]]
+        if np.unique(o).size > 8:
+            return False
+    return True
+
+
+@pytest.mark.parametrize("kind", [1, 2, 3, 4, 5, 6])
 @pytest.mark.parametrize("name", ["poisson2d_64", "poisson3d_ragged", "diffusion_100", "tiny_7",
                                   "random_spd_30k", "tiny_1"])
 def test_spmv_tilings_match_oracle(cg, name, kind):
@@ -118,9 +133,11 @@ def test_spmv_tilings_match_oracle(cg, name, kind):
         assert used == (4 if np.diff(A.row_ptr).max() <= 8 else 3 if np.diff(A.row_ptr).max() <= 64 else 1)
     if kind == 5:
         assert used == 5
-    if used in (2, 3, 4):
-        # stream, sliced and dictionary-sliced tiles sum each row left to
-        # right with rounded products: the oracle's own order, so the bits agree
+    if kind == 6 and stencil_applies(A):
+        assert used == 6
+    if used in (2, 3, 4, 6):
+        # stream, sliced, dictionary-sliced and stencil tiles sum each row left
+        # to right with rounded products: the oracle's own order, so the bits agree
         assert np.array_equal(y, ref)
 
 
@@ -599,3 +616,49 @@ def test_paper_inputs_absolute_tolerance(cg):
     assert abs(res["iterations"] - ref["iterations"]) <= max(2, 0.05 * ref["iterations"])
     lam = 2 - 2 * np.cos(np.arange(1, 25) * np.pi / 25)
     assert np.linalg.norm(host(x) - ref["x"]) / np.linalg.norm(ref["x"]) <= 2 * (lam.max() / lam.min()) * tol * 10
+
+
+
+@pytest.mark.parametrize("name", ["poisson3d_24", "poisson3d_ragged", "poisson2d_64", "diffusion_100"])
+def test_stencil_slices_chosen_and_exact(cg, name):
+    """Stencil matrices take stencil slices automatically; SpMV bit-exact and
+    a fixed-work CG identical to the dictionary tiling's (same sums)."""
+    A = SPMV_CASES[name]()
+    assert stencil_applies(A)
+    x = np.random.default_rng(13).uniform(-1, 1, A.n)
+    b = I.rhs_of(A, I.uniform_vector(A.n, [13, 1]))
+    out = {}
+    for kind in (0, 4):
+        with cg.Solver(A) as s:
+            s.set_opts(spmv_kind=kind, small_path=0)
+            y = host(s.spmv(dev(x)))
+            used = used_kind(s, A.n)
+            xs, res = s.solve(dev(b), tol=0.0, maxit=25)
+            out[kind] = (used, y, host(xs))
+    assert out[0][0] == 6 and out[4][0] == 4
+    assert np.array_equal(out[0][1], oracle.spmv(A, x))
+    assert np.array_equal(out[0][1], out[4][1]) and np.array_equal(out[0][2], out[4][2])
+
+
+def test_stencil_slices_fall_back_on_many_offsets(cg):
+    """A slice with more than 8 distinct column offsets (rows of <= 8 entries)
+    is not stencil-sliced: kind 6 falls back to the dictionary tiles."""
+    n = 1024
+    rng = np.random.default_rng(4)
+    rows, cols = [np.arange(n)], [np.arange(n)]
+    for _ in range(3):
+        perm = rng.permutation(n)
+        a, b2 = perm[0::2], perm[1::2]
+        rows += [a, b2]
+        cols += [b2, a]
+    r, cidx = np.concatenate(rows), np.concatenate(cols)
+    S = sp.csr_matrix((np.where(r == cidx, 8.0, -0.5), (r, cidx)), shape=(n, n))
+    S.sum_duplicates()
+    S.sort_indices()
+    A = I.CSR(n, S.indptr.astype(np.int32), S.indices.astype(np.int32), S.data)
+    assert np.diff(A.row_ptr).max() <= 8 and not stencil_applies(A)
+    x = rng.uniform(-1, 1, n)
+    with cg.Solver(A) as s:
+        s.set_opts(spmv_kind=6)
+        assert used_kind(s, n) in (3, 4)
+        assert np.array_equal(host(s.spmv(dev(x))), oracle.spmv(A, x))
