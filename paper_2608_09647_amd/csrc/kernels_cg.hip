@@ -576,6 +576,84 @@ __device__ __forceinline__ void spmv_sten_wave(const CsrDev &A, TileWalk &walk,
     }
 }
 
+// Stencil slices, two rows per lane: a wave takes the slice pair (2u, 2u+1),
+// lanes 0-31 the first slice and 32-63 the second, each lane the row pair
+// (2h, 2h+1) of its slice, so values, p_own and q move in 16-byte loads and
+// stores.  Each half-wave reads its own slice's offsets; the slot loop runs to
+// the wider slice's width (uniform), a half past its own width loads nothing.
+// Every row is summed exactly as in spmv_sten_wave; the p^T q partial adds
+// the lane's two rows in order.  Plain and dot modes, with q and p_own
+// 16-byte aligned (checked by the launcher).
+typedef double dbl2v __attribute__((ext_vector_type(2)));
+
+template <int MODE, bool NT>
+__device__ __forceinline__ void spmv_sten2_wave(const CsrDev &A, TileWalk &walk, const SpmvArgs<double> &a,
+                                                double &acc0) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int half = lane >> 5, hl = lane & 31;
+    const int nt = (A.m + kWave - 1) / kWave;
+    for (int u = walk.next(); u >= 0; u = walk.next()) {
+        const int t0 = 2 * u;
+        const bool two = t0 + 1 < nt;                 // uniform: the pair has a second slice
+        const int t1 = two ? t0 + 1 : t0;
+        const int off0 = A.st_off[t0], w0 = (A.st_off[t0 + 1] - off0) / kWave;
+        const int off1 = A.st_off[t1], w1 = two ? (A.st_off[t1 + 1] - off1) / kWave : 0;
+        const int wmax = max(w0, w1);
+        const int ts = half ? t1 : t0;
+        const bool mine = !half || two;               // this half has a slice
+        const int off = half ? off1 : off0;
+        const int width = half ? w1 : w0;
+        const int ra = ts * kWave + 2 * hl;           // the lane's rows ra, ra + 1
+        const bool va = mine && ra < A.m, vb = mine && ra + 1 < A.m;
+        const int rca = min(ra, A.m - 1), rcb = min(ra + 1, A.m - 1);
+        const int ga = A.col_base + rca, gb = A.col_base + rcb;
+        int offs[kSliceMaxWidth];
+#pragma unroll
+        for (int j = 0; j < kSliceMaxWidth; ++j) offs[j] = A.st_offs[ts * kSliceMaxWidth + j];
+        const uint16_t *mp = reinterpret_cast<const uint16_t *>(&A.st_mask[(int64_t)ts * kWave + 2 * hl]);
+        const uint32_t m2 = mine ? (NT ? (uint32_t)__builtin_nontemporal_load(mp) : (uint32_t)*mp) : 0u;
+        const uint32_t ma = va ? (m2 & 0xFFu) : 0u, mb = vb ? (m2 >> 8) : 0u;
+        double sa = 0.0, sb = 0.0;
+        dbl2v v[kSliceMaxWidth];
+        double pa[kSliceMaxWidth], pb[kSliceMaxWidth];
+#pragma unroll
+        for (int j = 0; j < kSliceMaxWidth; ++j) {
+            v[j] = dbl2v{0.0, 0.0};
+            pa[j] = pb[j] = 0.0;
+            if (j < wmax) {
+                if (j < width) {
+                    const dbl2v *vp = reinterpret_cast<const dbl2v *>(&A.st_val[off + j * kWave + 2 * hl]);
+                    v[j] = NT ? __builtin_nontemporal_load(vp) : *vp;
+                }
+                pa[j] = a.p[(ma >> j) & 1u ? ga + offs[j] : ga];
+                pb[j] = a.p[(mb >> j) & 1u ? gb + offs[j] : gb];
+            }
+        }
+        {
+#pragma clang fp contract(off)
+#pragma unroll
+            for (int j = 0; j < kSliceMaxWidth; ++j) {
+                if ((ma >> j) & 1u) sa = sa + v[j].x * pa[j];  // rounded product, then the sum
+                if ((mb >> j) & 1u) sb = sb + v[j].y * pb[j];
+            }
+        }
+        if (va && vb) {
+            if (MODE == kSpmvDot) {
+                const dbl2v po = *reinterpret_cast<const dbl2v *>(&a.p_own[ra]);
+                acc0 = fma(po.x, sa, acc0);
+                acc0 = fma(po.y, sb, acc0);
+            }
+            dbl2v qv{sa, sb};
+            dbl2v *qp = reinterpret_cast<dbl2v *>(&a.q[ra]);
+            if (NT) __builtin_nontemporal_store(qv, qp);
+            else *qp = qv;
+        } else if (va) {   // the last row of an odd row count
+            if (MODE == kSpmvDot) acc0 = fma(a.p_own[ra], sa, acc0);
+            a.q[ra] = sa;
+        }
+    }
+}
+
 // A row longer than kHugeRow: all threads of the workgroup on it.
 template <int MODE, class T>
 __device__ __forceinline__ void spmv_row_wg(const CsrDev &A, int pos, bool identity,
@@ -597,7 +675,8 @@ __device__ __forceinline__ void spmv_row_wg(const CsrDev &A, int pos, bool ident
 // TILE == -2: sliced tiles of width <= kSliceMaxWidth; -3: wider slices;
 // TILE == -4: dictionary-sliced tiles; -5: the same with the matrix streamed
 // nontemporally (matrices larger than the last-level cache can hold);
-// -6 / -7: stencil slices, cached / nontemporal (float64 only).
+// -6 / -7: stencil slices, cached / nontemporal (float64 only); -8 / -9: the
+// same with two rows per lane and 16-byte accesses (plain and dot modes).
 template <int MODE, int TILE, class T>
 __global__ __launch_bounds__(kBlock) void k_spmv(int32_t m, const int32_t *__restrict__ rp,
                                                  const int32_t *__restrict__ ci,
@@ -646,13 +725,16 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int32_t m, const int32_t *__res
     }
     double acc0 = 0.0, acc1 = 0.0;
     const bool identity = S.identity != 0;
-    TileWalk walk(S.ntiles);
+    TileWalk walk(TILE == -8 || TILE == -9 ? (S.ntiles + 1) / 2 : S.ntiles);   // slice pairs
     if constexpr (TILE == -2 || TILE == -3) {
         spmv_sliced_wave<MODE, T>(A, walk, a, TILE == -3, acc0, acc1);
     } else if constexpr (TILE == -4 || TILE == -5) {
         spmv_dict_wave<MODE, T, TILE == -5>(A, walk, a, acc0, acc1);
     } else if constexpr (TILE == -6 || TILE == -7) {
         if constexpr (sizeof(T) == 8) spmv_sten_wave<MODE, TILE == -7>(A, walk, a, acc0, acc1);
+    } else if constexpr (TILE == -8 || TILE == -9) {
+        if constexpr (sizeof(T) == 8 && (MODE == kSpmvPlain || MODE == kSpmvDot))
+            spmv_sten2_wave<MODE, TILE == -9>(A, walk, a, acc0);
     } else if constexpr (TILE == -1) {
         if constexpr (sizeof(T) == 8) {
             double *lds = s_prod + (threadIdx.x / kWave) * kStreamNnz;
@@ -1191,7 +1273,10 @@ template <int MODE, class T>
 void launch_spmv_mode(const CsrDev &A, const Schedule &S, int grid, const SpmvArgs<T> &a,
                       double *out, Partials in0, Partials in1, DevState *st, int flags,
                       hipStream_t s) {
-    const int L = S.kind == kTileStencil ? (S.stream_nt ? -7 : -6)
+    // stencil slices with two rows per lane where the 16-byte accesses are aligned
+    const bool wide = sizeof(T) == 8 && (MODE == kSpmvPlain || MODE == kSpmvDot) &&
+                      ((uintptr_t)a.q & 15) == 0 && (MODE != kSpmvDot || ((uintptr_t)a.p_own & 15) == 0);
+    const int L = S.kind == kTileStencil ? (wide ? (S.stream_nt ? -9 : -8) : (S.stream_nt ? -7 : -6))
                   : S.kind == kTileSlicedDict ? (S.stream_nt ? -5 : -4)
                   : S.kind == kTileSliced ? (S.bins[0].lanes <= kSliceMaxWidth ? -2 : -3)
                   : S.kind == kTileStream ? -1
@@ -1224,6 +1309,8 @@ void launch_spmv_mode(const CsrDev &A, const Schedule &S, int grid, const SpmvAr
         case -5: CGMI_SPMV(-5); break;
         case -6: CGMI_SPMV(-6); break;
         case -7: CGMI_SPMV(-7); break;
+        case -8: CGMI_SPMV(-8); break;
+        case -9: CGMI_SPMV(-9); break;
         default: CGMI_SPMV(0); break;
     }
 #undef CGMI_SPMV
