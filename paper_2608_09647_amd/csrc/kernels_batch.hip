@@ -18,9 +18,10 @@
 // so all of them take identical decisions (and results are reproducible for
 // a fixed schedule).  A barrier is a counter in device memory: each wave
 // waits until its stores have reached the L2, then one thread per workgroup
-// writes the L2 back (device-scope release fence), adds 1 and waits until the
-// team's count is reached, and invalidates stale cache lines (device-scope
-// acquire fence) before the workgroup reads what the team wrote.  A wait is
+// writes the L2 back (device-scope release fence) and waits for the
+// write-back to finish, adds 1 and waits until the team's count is reached,
+// and invalidates stale cache lines (device-scope acquire fence), again
+// waiting for completion, before the workgroup reads what the team wrote.  A wait is
 // bounded by a wall-clock limit; on expiry the error flag ends every team.
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -108,6 +109,9 @@ __device__ __forceinline__ bool team_sync(const BatchArgs &a, int sys, int T, in
     if (threadIdx.x == 0) {
         int ok = 1;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        // the L2 write-back the fence starts must be complete before the
+        // counter moves; the fence alone leaves no wait for it here
+        __builtin_amdgcn_s_waitcnt(0);
         __hip_atomic_fetch_add(&a.bar[sys], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const int target = episode * T;
         const uint64_t t0 = wall_clock64();
@@ -126,6 +130,9 @@ __device__ __forceinline__ bool team_sync(const BatchArgs &a, int sys, int T, in
         // acquire: stale lines of this compute unit's caches are dropped
         // before any wave of the workgroup reads what the team wrote
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        // the invalidate must be complete before the other waves, released
+        // by the workgroup barrier below, issue their loads
+        __builtin_amdgcn_s_waitcnt(0);
         S.ok = ok;
     }
     __syncthreads();

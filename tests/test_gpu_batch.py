@@ -185,8 +185,17 @@ def test_full_size_batch_sampled_against_oracle(cg):
     X, res, st, code = run_batch(cg, systems, [p.b for p in probs], 16, tol=0.0, maxit=20)
     print(f"[full] stats {st}", flush=True)
     assert np.all(res["iterations"] == 20)
+    # same schedule, same bits: every pair of every system (a team member
+    # reading a stale line of p written by another would break this)
+    X2, _, st2, _ = run_batch(cg, systems, [p.b for p in probs], 16, tol=0.0, maxit=20)
+    assert st2["grid"] == st["grid"]
+    for k in range(256):
+        assert np.array_equal(X[k], X2[k]), k
     rng = np.random.default_rng(0)
-    for k in rng.choice(256, 4, replace=False):
+    # system 69 (129^2, vectors small enough to stay cache-resident) once
+    # returned a wrong iterate while the team barrier did not wait for its
+    # cache write-back
+    for k in list(rng.choice(256, 4, replace=False)) + [69]:
         j = int(rng.integers(16))
         A, b = systems[k], probs[k].b[:, j]
         ref = oracle.cg(A, b, tol=0.0, maxit=20)
