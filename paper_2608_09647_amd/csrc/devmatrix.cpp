@@ -107,7 +107,7 @@ int build_stencil(DevMatrix &M, bool *fits) {
                 const int32_t o = M.h_ci[k] - (M.pad_col_base + i);
                 while (e < w && u[e] != o) ++e;   // offsets ascend with the columns
                 bits |= (uint8_t)(1u << e);
-                sval[(size_t)off[t] + (size_t)e * kWaveSize + l] = M.h_val[k];
+                if (!M.h_val.empty()) sval[(size_t)off[t] + (size_t)e * kWaveSize + l] = M.h_val[k];
                 ++e;
             }
             mask[(size_t)i] = bits;
@@ -517,8 +517,9 @@ int dm_schedule(DevMatrix &M, int kind_opt, int grid_opt, int cus, int grid_cap,
         if (rc) return rc;
     }
     // stencil slices where every slice has at most 8 distinct column offsets
-    // (float64 with host values); else the dictionary or plain slices
-    if ((kind_opt == 0 || kind_opt == 6) && !need_f32 && !M.h_val.empty() &&
+    // (float64); else the dictionary or plain slices.  Without host values
+    // the slots hold zeros until the owner writes them on the device.
+    if ((kind_opt == 0 || kind_opt == 6) && !need_f32 &&
         (M.sched.kind == kTileSlicedDict || M.sched.kind == kTileSliced) && M.sched.bins[0].lanes <= kSliceMaxWidth) {
         bool fits = false;
         const int rc = build_stencil(M, &fits);

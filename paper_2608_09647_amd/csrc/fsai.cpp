@@ -458,9 +458,13 @@ extern "C" int cg_fsai_setup(cg_handle *h, const float *theta) {
     HIP_TRY(hipMemcpyAsync(f->d_theta, theta, sizeof(float) * kNParams, hipMemcpyHostToDevice, st));
     HIP_TRY(fsai_forward_factor(h->n, f->d_feats, f->d_theta, f->d_scol, f->d_diag, f->d_gpos, f->d_tpos,
                                 h->G.d_val, h->GT.d_val, st));
-    for (DevMatrix *M : {&h->G, &h->GT})
+    for (DevMatrix *M : {&h->G, &h->GT}) {
         if (M->sched.kind == kTileSliced || M->sched.kind == kTileSlicedDict)
             HIP_TRY(sell_refresh(M->m, M->sched.ntiles, M->d_rp, M->d_sell_off, M->d_val, M->d_sell_val, st));
+        if (M->sched.kind == kTileStencil)
+            HIP_TRY(stencil_refresh(M->m, (M->m + 63) / 64, M->d_rp, M->d_st_off, M->d_st_mask, M->d_val,
+                                    M->d_st_val, st));
+    }
     HIP_TRY(hipStreamSynchronize(st));
     h->have_factor = true;
     return CG_OK;

@@ -81,4 +81,10 @@ hipError_t fill_f32(int64_t n, float *p, float v, hipStream_t s);
 hipError_t sell_refresh(int32_t m, int32_t ntiles, const int32_t *rp, const int32_t *sell_off,
                         const double *val, double *sell_val, hipStream_t s);
 
+// Copy CSR values into the stencil-slice layout: the k-th entry of row i goes
+// to the slot of the k-th set bit of the row's mask (columns ascend, and so do
+// the slice's offsets).
+hipError_t stencil_refresh(int32_t m, int32_t ntiles, const int32_t *rp, const int32_t *st_off,
+                           const uint8_t *st_mask, const double *val, double *st_val, hipStream_t s);
+
 }  // namespace cgmi

@@ -612,6 +612,26 @@ __global__ void k_sell_refresh(int32_t m, int32_t ntiles, const int32_t *__restr
     for (int32_t j = 0; j < len && j < w; ++j) sell_val[(int64_t)sell_off[t] + (int64_t)j * 64 + l] = val[b + j];
 }
 
+// Thread per (slice, lane): scatter the row's values to the slots its mask
+// marks, in order.
+__global__ void k_stencil_refresh(int32_t m, int32_t ntiles, const int32_t *__restrict__ rp,
+                                  const int32_t *__restrict__ st_off, const uint8_t *__restrict__ st_mask,
+                                  const double *__restrict__ val, double *__restrict__ st_val) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t t = (int32_t)(g / 64), l = (int32_t)(g % 64);
+    if (t >= ntiles) return;
+    const int32_t i = t * 64 + l;
+    if (i >= m) return;
+    const int32_t b = rp[i], len = rp[i + 1] - rp[i];
+    const int32_t w = (st_off[t + 1] - st_off[t]) / 64;
+    uint32_t bits = st_mask[i];
+    for (int32_t k = 0; k < len && bits; ++k) {
+        const int32_t e = __builtin_ctz(bits);
+        bits &= bits - 1;
+        if (e < w) st_val[(int64_t)st_off[t] + (int64_t)e * 64 + l] = val[b + k];
+    }
+}
+
 __global__ void k_fill_f32(int64_t n, float *__restrict__ p, float v) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
@@ -687,6 +707,15 @@ hipError_t sell_refresh(int32_t m, int32_t ntiles, const int32_t *rp, const int3
     const int64_t threads = (int64_t)ntiles * 64;
     hipLaunchKernelGGL(k_sell_refresh, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, m, ntiles,
                        rp, sell_off, val, sell_val);
+    return hipGetLastError();
+}
+
+hipError_t stencil_refresh(int32_t m, int32_t ntiles, const int32_t *rp, const int32_t *st_off,
+                           const uint8_t *st_mask, const double *val, double *st_val, hipStream_t s) {
+    if (m <= 0 || ntiles <= 0) return hipSuccess;
+    const int64_t threads = (int64_t)ntiles * 64;
+    hipLaunchKernelGGL(k_stencil_refresh, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, m,
+                       ntiles, rp, st_off, st_mask, val, st_val);
     return hipGetLastError();
 }
 
