@@ -92,7 +92,8 @@ int build_stencil(DevMatrix &M, bool *fits) {
     for (int32_t t = 0; t < nt; ++t) off[t + 1] = off[t] + width[(size_t)t] * kWaveSize;
     if ((int64_t)off[nt] >= INT32_MAX) return CG_OK;
     const size_t slots = (size_t)off[nt];
-    std::vector<double> sval(slots, 0.0);
+    const bool host_vals = !M.h_val.empty();
+    std::vector<double> sval(host_vals ? slots : 0, 0.0);
     std::vector<uint8_t> mask((size_t)nt * kWaveSize, 0);
 #pragma omp parallel for schedule(static)
     for (int32_t t = 0; t < nt; ++t) {
@@ -107,7 +108,7 @@ int build_stencil(DevMatrix &M, bool *fits) {
                 const int32_t o = M.h_ci[k] - (M.pad_col_base + i);
                 while (e < w && u[e] != o) ++e;   // offsets ascend with the columns
                 bits |= (uint8_t)(1u << e);
-                if (!M.h_val.empty()) sval[(size_t)off[t] + (size_t)e * kWaveSize + l] = M.h_val[k];
+                if (host_vals) sval[(size_t)off[t] + (size_t)e * kWaveSize + l] = M.h_val[k];
                 ++e;
             }
             mask[(size_t)i] = bits;
@@ -121,7 +122,10 @@ int build_stencil(DevMatrix &M, bool *fits) {
     if (e == hipSuccess)
         e = hipMemcpy(M.d_st_offs, offs.data(), sizeof(int32_t) * offs.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(M.d_st_mask, mask.data(), mask.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(M.d_st_val, sval.data(), sizeof(double) * slots, hipMemcpyHostToDevice);
+    // values from the host copy, or zero until the owner writes them on the device
+    if (e == hipSuccess)
+        e = host_vals ? hipMemcpy(M.d_st_val, sval.data(), sizeof(double) * slots, hipMemcpyHostToDevice)
+                      : hipMemset(M.d_st_val, 0, sizeof(double) * slots);
     if (e != hipSuccess) {
         (void)hipFree(M.d_st_off);
         (void)hipFree(M.d_st_offs);
