@@ -66,11 +66,58 @@ __device__ __forceinline__ double block_allsum(double v, double *sh, double *bc)
     return s;
 }
 
+// This thread's share of a producer kernel's partials: entries t, t + kBlock,
+// t + 2 kBlock, ... added in that order.  The loads of eight entries are
+// issued together, so the sum costs one memory round trip per 8 kBlock
+// partials instead of one per entry.
+__device__ __forceinline__ double thread_partials(const Partials &P) {
+    double v = 0.0;
+    for (int base = threadIdx.x; base < P.count; base += 8 * kBlock) {
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = base + u * kBlock;
+            t[u] = i < P.count ? P.v[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (base + u * kBlock < P.count) v += t[u];
+    }
+    return v;
+}
+
 // Sum of a producer kernel's partials in a fixed order (same in every workgroup).
 __device__ __forceinline__ double reduce_partials(const Partials &P, double *sh, double *bc) {
-    double v = 0.0;
-    for (int i = threadIdx.x; i < P.count; i += kBlock) v += P.v[i];
-    return block_allsum<kBlock>(v, sh, bc);
+    return block_allsum<kBlock>(thread_partials(P), sh, bc);
+}
+
+// Two such sums with one set of workgroup barriers, each in the order of
+// reduce_partials.  sh: 2 kBlock/64 doubles; bc: 2 doubles.
+__device__ __forceinline__ void reduce_partials2(const Partials &P0, const Partials &P1, double *sh,
+                                                 double *bc, double &s0, double &s1) {
+    constexpr int NW = kBlock / kWave;
+    const double v0 = wave_sum(thread_partials(P0));
+    const double v1 = wave_sum(thread_partials(P1));
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    if (lane == 0) {
+        sh[w] = v0;
+        sh[NW + w] = v1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = sh[0], b = sh[NW];
+#pragma unroll
+        for (int i = 1; i < NW; ++i) {
+            a += sh[i];
+            b += sh[NW + i];
+        }
+        bc[0] = a;
+        bc[1] = b;
+    }
+    __syncthreads();
+    s0 = bc[0];
+    s1 = bc[1];
+    __syncthreads();
 }
 
 __device__ __forceinline__ bool stop_test(double rho, double bb, double tol) {
@@ -1094,14 +1141,14 @@ __global__ __launch_bounds__(kBlock) void k_update_p_pcg(int32_t m, const double
                                                          Partials rz_in, Partials bb_in,
                                                          DevState *__restrict__ st, int first,
                                                          int32_t k) {
-    __shared__ double sh[kWavesPerBlock];
-    __shared__ double bc;
+    __shared__ double sh[2 * kWavesPerBlock];
+    __shared__ double bc[2];
     if (st->done) return;
-    const double rr = reduce_partials(rr_in, sh, &bc);
-    const double rz = reduce_partials(rz_in, sh, &bc);
+    double rr, rz;
+    reduce_partials2(rr_in, rz_in, sh, bc, rr, rz);
     double beta = 0.0;
     if (first) {
-        const double bb = reduce_partials(bb_in, sh, &bc);
+        const double bb = reduce_partials(bb_in, sh, bc);
         const bool conv = stop_test(rr, bb, st->tol) || bb == 0.0;
         const bool stop = conv || st->maxit <= 0;
         if (is_block0_thread0()) {
