@@ -34,6 +34,10 @@ struct DevState {
     int32_t done;      // 0 running, 1 converged, 2 iteration limit, 3 breakdown
     int32_t nrefine;   // mixed precision: float64 residuals formed
     double rr_true;    // single-workgroup solve: ||b - A x||^2 of the returned x
+    int32_t r_iter;    // device-coefficient paths: k + 1 once r of iteration k is
+                       // updated (the deferred x update of iteration k runs only
+                       // then; it never reads `done`, which its own workgroup 0
+                       // may set while other workgroups have yet to start)
 };
 
 enum { kDoneRunning = 0, kDoneConverged = 1, kDoneMaxit = 2, kDoneBreakdown = 3, kDoneRefine = 4 };
@@ -210,20 +214,23 @@ hipError_t launch_update_p(int32_t m, int grid, const double *r, double *p_own, 
                            DevState *st, int device_coef, int32_t k, double beta_arg,
                            hipStream_t s);
 
-// Preconditioned CG, x/r update fused with t = G r_new for a factor G of at
+// Preconditioned CG, r update fused with t = G r_new for a factor G of at
 // most `width` <= kFusedGWidth entries per row (CSR grp/gci/gval, rows
-// rebased, columns < m): x += alpha p, r_new = r_old - alpha q (another buffer than r_old),
+// rebased, columns < m): r_new = r_old - alpha q (another buffer than r_old),
 // t = G r_new, out_partials[wg] = sum r_new_i^2; alpha = rho_k / sum(pq),
-// breakdown recorded in st as by launch_update_xr.
+// breakdown recorded in st as by launch_update_xr.  x is updated later, by
+// launch_update_p_pcg.  One row per thread: grid <= the partial buffers' size.
 constexpr int kFusedGWidth = 8;
 hipError_t launch_pcg_xr_g(int32_t m, int grid, int width, const int32_t *grp, const int32_t *gci,
-                           const double *gval, double *x, const double *r_old, double *r_new, const double *p,
-                           const double *q, double *t, double *out_partials, Partials pq, DevState *st, int32_t k,
+                           const double *gval, const double *r_old, double *r_new, const double *q,
+                           double *t, double *out_partials, Partials pq, DevState *st, int32_t k,
                            hipStream_t s);
 
 // Preconditioned CG (z = M^-1 r): p = z + beta p, rho = r^T z from the rz
 // partials, the stop test on the rr partials; first = 1 is the setup step
 // (rho_0, ||b||^2 from bb, stop test at the top of iteration 0, p = z).
+// x non-null (after launch_pcg_xr_g): x += alpha p first, alpha recomputed
+// as there, for every iteration whose r was updated, also the last one.
 // Float64 CG with device coefficients and the x update deferred to the p
 // update: r -= alpha q (partials of r^T r); then x += alpha p and, unless the
 // solve stops, p = r + beta p.  Vectors 16-byte aligned.
@@ -231,7 +238,7 @@ hipError_t launch_update_r(int32_t m, int grid, double *r, const double *q, doub
                            DevState *st, int32_t k, hipStream_t s);
 hipError_t launch_update_px(int32_t m, int grid, double *x, const double *r, double *p, Partials rr,
                             DevState *st, int32_t k, hipStream_t s);
-hipError_t launch_update_p_pcg(int32_t m, int grid, const double *z, double *p, Partials rr,
+hipError_t launch_update_p_pcg(int32_t m, int grid, const double *z, double *p, double *x, Partials rr,
                                Partials rz, Partials bb, DevState *st, int first, int32_t k,
                                hipStream_t s);
 

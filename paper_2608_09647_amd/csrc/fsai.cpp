@@ -131,9 +131,11 @@ int solve_gpu_pcg(cg_handle *h, const double *b, double *x, double tol, int32_t 
     const int32_t n = h->n;
     hipStream_t st = h->stream;
     const int Ga = h->A.grid, Gg = h->G.grid, Gt = h->GT.grid, Gv = h->vec_grid;
+    // the fused r/t kernel runs one row per thread
+    const int Gx = std::max(1, (int)std::min<int64_t>(h->grid_cap, ((int64_t)n + kBlock - 1) / kBlock));
     const Partials none = no_partials();
     const Partials setup_rr{h->d_part_setup, Ga}, setup_bb{h->d_part_setup + Ga, Ga};
-    const Partials pq{h->d_part_pq, Ga}, rr{h->d_part_rr, Gv}, rz{h->d_part_rz, Gt};
+    const Partials pq{h->d_part_pq, Ga}, rr{h->d_part_rr, h->g_width ? Gx : Gv}, rz{h->d_part_rz, Gt};
     HIP_TRY(hipMemcpyAsync(h->d_x, x, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
     int rc = gpu_state_init(h, tol, maxit);
     if (rc) return rc;
@@ -147,7 +149,7 @@ int solve_gpu_pcg(cg_handle *h, const double *b, double *x, double tol, int32_t 
                         none, none, nullptr, kSpmvPlain, 0, st));
     HIP_TRY(launch_spmv(h->GT.dev(), h->GT.sched, Gt, h->d_t, h->d_z, h->d_r, nullptr, nullptr,
                         h->d_part_rz, none, none, nullptr, kSpmvDot, 0, st));
-    HIP_TRY(launch_update_p_pcg(n, Gv, h->d_z, h->d_p, setup_rr, rz, setup_bb, h->d_state, 1, 0, st));
+    HIP_TRY(launch_update_p_pcg(n, Gv, h->d_z, h->d_p, nullptr, setup_rr, rz, setup_bb, h->d_state, 1, 0, st));
     const int C = h->opts.check_every;
     std::vector<hipEvent_t> ev;
     if (h->opts.profile) {
@@ -171,8 +173,8 @@ int solve_gpu_pcg(cg_handle *h, const double *b, double *x, double tol, int32_t 
                 // x/r update and t = G r in one kernel; r alternates between two buffers
                 const double *r_old = rbuf[kk & 1];
                 r_now = rbuf[(kk + 1) & 1];
-                HIP_TRY(launch_pcg_xr_g(n, Gv, h->g_width, h->G.d_rp, h->G.d_ci, h->G.d_val, h->d_x, r_old, r_now,
-                                        h->d_p, h->d_q, h->d_t, h->d_part_rr, pq, h->d_state, kk, st));
+                HIP_TRY(launch_pcg_xr_g(n, Gx, h->g_width, h->G.d_rp, h->G.d_ci, h->G.d_val, r_old, r_now,
+                                        h->d_q, h->d_t, h->d_part_rr, pq, h->d_state, kk, st));
             } else {
                 HIP_TRY(launch_update_xr(n, Gv, h->d_x, h->d_r, h->d_p, h->d_q, h->d_part_rr, pq, h->d_state, 1,
                                          kk, 0.0, st));
@@ -181,7 +183,9 @@ int solve_gpu_pcg(cg_handle *h, const double *b, double *x, double tol, int32_t 
             }
             HIP_TRY(launch_spmv(h->GT.dev(), h->GT.sched, Gt, h->d_t, h->d_z, r_now, nullptr, nullptr,
                                 h->d_part_rz, none, none, h->d_state, kSpmvDot, 0, st));
-            HIP_TRY(launch_update_p_pcg(n, Gv, h->d_z, h->d_p, rr, rz, none, h->d_state, 0, kk, st));
+            // x += alpha p here when the fused kernel formed r (it leaves x alone)
+            HIP_TRY(launch_update_p_pcg(n, Gv, h->d_z, h->d_p, h->g_width ? h->d_x : nullptr, rr, rz, none,
+                                        h->d_state, 0, kk, st));
         }
         const int32_t it0 = k;
         k += chunk;

@@ -883,19 +883,19 @@ __global__ __launch_bounds__(kBlock) void k_blocked_finish(int32_t m, SpmvArgs<T
     }
 }
 
-// Preconditioned CG: the x/r update fused with t = G r_new (G of at most W
+// Preconditioned CG: the r update fused with t = G r_new (G of at most W
 // entries per row, CSR; W = 1, 2, 4 or 8).  Thread per row: r_new = r - alpha q
-// and x += alpha p for the row (r_new into the other r buffer, so neighbours
-// still read r), and t_i = sum_k G_ik r_new_k with r_new_k formed on the fly
-// by the same fma as its owner (identical bits), summed in CSR order with
-// rounded products; partial r_new^T r_new per workgroup.  alpha and the
-// breakdown test as in k_update_xr.
+// for the row (into the other r buffer, so neighbours still read r), and
+// t_i = sum_k G_ik r_new_k with r_new_k formed on the fly by the same fma as
+// its owner (identical bits), summed in CSR order with rounded products;
+// partial r_new^T r_new per workgroup.  alpha and the breakdown test as in
+// k_update_xr.  x += alpha p is left to k_update_p_pcg, which reads p anyway.
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_pcg_xr_g(int32_t m, const int32_t *__restrict__ grp,
                                                      const int32_t *__restrict__ gci,
-                                                     const double *__restrict__ gval, double *__restrict__ x,
+                                                     const double *__restrict__ gval,
                                                      const double *__restrict__ r_old, double *__restrict__ r_new,
-                                                     const double *__restrict__ p, const double *__restrict__ q,
+                                                     const double *__restrict__ q,
                                                      double *__restrict__ t, double *__restrict__ out,
                                                      Partials pq_in, DevState *__restrict__ st, int32_t k) {
     __shared__ double sh[kWavesPerBlock];
@@ -911,11 +911,13 @@ __global__ __launch_bounds__(kBlock) void k_pcg_xr_g(int32_t m, const int32_t *_
         return;
     }
     const double alpha = st->rho[k & 1] / pq;
-    if (is_block0_thread0()) st->pq = pq;
+    if (is_block0_thread0()) {
+        st->pq = pq;
+        st->r_iter = k + 1;
+    }
     double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += (int64_t)gridDim.x * kBlock) {
         const double rv = fma(-alpha, q[i], r_old[i]);
-        x[i] = fma(alpha, p[i], x[i]);
         r_new[i] = rv;
         acc = fma(rv, rv, acc);
         const int k0 = grp[i], len = grp[i + 1] - k0;
@@ -965,7 +967,10 @@ __global__ __launch_bounds__(kBlock) void k_update_xr(int32_t m, double *__restr
             return;
         }
         alpha = st->rho[k & 1] / pq;
-        if (is_block0_thread0()) st->pq = pq;
+        if (is_block0_thread0()) {
+            st->pq = pq;
+            st->r_iter = k + 1;
+        }
     }
     double acc = 0.0;
     const int64_t npair = m >> 1;
@@ -1060,7 +1065,10 @@ __global__ __launch_bounds__(kBlock) void k_update_r(int32_t m, double *__restri
         return;
     }
     const double alpha = st->rho[k & 1] / pq;
-    if (is_block0_thread0()) st->pq = pq;
+    if (is_block0_thread0()) {
+        st->pq = pq;
+        st->r_iter = k + 1;
+    }
     double acc = 0.0;
     const int64_t npair = m >> 1;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
@@ -1090,7 +1098,10 @@ __global__ __launch_bounds__(kBlock) void k_update_px(int32_t m, double *__restr
                                                       DevState *__restrict__ st, int32_t k) {
     __shared__ double sh[kWavesPerBlock];
     __shared__ double bc;
-    if (st->done) return;   // breakdown in k_update_r: x stays as it was
+    // r of this iteration not updated (breakdown in k_update_r, or the solve
+    // stopped earlier): x stays as it was.  `done` is not read here: workgroup
+    // 0 of this kernel may set it before other workgroups start.
+    if (st->r_iter != k + 1) return;
     const double rr = reduce_partials(rr_in, sh, &bc);
     const double rho_k = st->rho[k & 1];
     const double alpha = rho_k / st->pq;
@@ -1133,37 +1144,44 @@ __global__ __launch_bounds__(kBlock) void k_update_px(int32_t m, double *__restr
 // Preconditioned CG: p = z + beta p with rho = r^T z (z = M^-1 r); the stop
 // test is on r^T r.  first: setup step (after r = b - A x and z = M^-1 r):
 // rho_0 = r^T z, ||b||^2 from bb_in, the stop test at the top of iteration 0,
-// and p = z.  Otherwise after the x/r update of iteration k: a breakdown
-// (r^T z <= 0 or not finite while r != 0) ends the solve before the stop
-// test; workgroup 0 records iteration k+1.  b = 0 stops at once (x = 0).
+// and p = z.  Otherwise after the r update of iteration k: x += alpha p when
+// x is given (alpha = rho_k / p^T q as the r update formed it), then a
+// breakdown (r^T z <= 0 or not finite while r != 0) ends the solve before
+// the stop test; workgroup 0 records iteration k+1.  b = 0 stops at once
+// (x = 0).
 __global__ __launch_bounds__(kBlock) void k_update_p_pcg(int32_t m, const double *__restrict__ z,
-                                                         double *__restrict__ p, Partials rr_in,
-                                                         Partials rz_in, Partials bb_in,
+                                                         double *__restrict__ p, double *__restrict__ x,
+                                                         Partials rr_in, Partials rz_in, Partials bb_in,
                                                          DevState *__restrict__ st, int first,
                                                          int32_t k) {
     __shared__ double sh[2 * kWavesPerBlock];
     __shared__ double bc[2];
-    if (st->done) return;
+    // after iteration k: only if its r was updated (see k_update_px for why
+    // `done` is not read)
+    if (first ? st->done != 0 : st->r_iter != k + 1) return;
     double rr, rz;
     reduce_partials2(rr_in, rz_in, sh, bc, rr, rz);
-    double beta = 0.0;
+    double beta = 0.0, alpha = 0.0;
+    bool stop = false;
     if (first) {
         const double bb = reduce_partials(bb_in, sh, bc);
         const bool conv = stop_test(rr, bb, st->tol) || bb == 0.0;
-        const bool stop = conv || st->maxit <= 0;
+        const bool stop0 = conv || st->maxit <= 0;
         if (is_block0_thread0()) {
             st->rho[0] = rz;
             st->rr = rr;
             st->bb = bb;
             st->iter = 0;
-            if (stop) st->done = conv ? kDoneConverged : kDoneMaxit;
+            if (stop0) st->done = conv ? kDoneConverged : kDoneMaxit;
         }
-        if (stop) return;
+        if (stop0) return;
     } else {
         const bool broke = (!(rz > 0.0) || !isfinite(rz)) && rr != 0.0;
         const bool conv = stop_test(rr, st->bb, st->tol);
         const bool maxed = k + 1 >= st->maxit;
-        beta = rz / st->rho[k & 1];
+        const double rho_k = st->rho[k & 1];
+        beta = rz / rho_k;
+        alpha = rho_k / st->pq;
         if (is_block0_thread0()) {
             st->rho[(k + 1) & 1] = rz;
             st->rr = rr;
@@ -1172,20 +1190,35 @@ __global__ __launch_bounds__(kBlock) void k_update_p_pcg(int32_t m, const double
             else if (conv) st->done = kDoneConverged;
             else if (maxed) st->done = kDoneMaxit;
         }
-        if (broke || conv || maxed) return;
+        stop = broke || conv || maxed;
     }
+    const bool upd_x = x && !first;
+    if (stop && !upd_x) return;
     const int64_t npair = m >> 1;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     double2 *p2 = reinterpret_cast<double2 *>(p);
+    double2 *x2 = reinterpret_cast<double2 *>(x);
     const double2 *z2 = reinterpret_cast<const double2 *>(z);
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < npair; i += stride) {
-        const double2 zv = z2[i];
         double2 pv = p2[i];
-        pv.x = fma(beta, pv.x, zv.x);
-        pv.y = fma(beta, pv.y, zv.y);
-        p2[i] = pv;
+        if (upd_x) {
+            double2 xv = x2[i];
+            xv.x = fma(alpha, pv.x, xv.x);
+            xv.y = fma(alpha, pv.y, xv.y);
+            x2[i] = xv;
+        }
+        if (!stop) {
+            const double2 zv = z2[i];
+            pv.x = fma(beta, pv.x, zv.x);
+            pv.y = fma(beta, pv.y, zv.y);
+            p2[i] = pv;
+        }
     }
-    if ((m & 1) && blockIdx.x == 0 && threadIdx.x == 0) p[m - 1] = fma(beta, p[m - 1], z[m - 1]);
+    if ((m & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        const double pv = p[m - 1];
+        if (upd_x) x[m - 1] = fma(alpha, pv, x[m - 1]);
+        if (!stop) p[m - 1] = fma(beta, pv, z[m - 1]);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1460,14 +1493,14 @@ hipError_t launch_update_p(int32_t m, int grid, const double *r, double *p_own, 
 }
 
 hipError_t launch_pcg_xr_g(int32_t m, int grid, int width, const int32_t *grp, const int32_t *gci,
-                           const double *gval, double *x, const double *r_old, double *r_new, const double *p,
-                           const double *q, double *t, double *out_partials, Partials pq, DevState *st, int32_t k,
+                           const double *gval, const double *r_old, double *r_new, const double *q,
+                           double *t, double *out_partials, Partials pq, DevState *st, int32_t k,
                            hipStream_t s) {
     if (m == 0) return hipSuccess;
     if (width < 0 || width > kFusedGWidth) return hipErrorInvalidValue;
 #define CGMI_PCG_XR_G(W)                                                                            \
-    hipLaunchKernelGGL(k_pcg_xr_g<W>, dim3(grid), dim3(kBlock), 0, s, m, grp, gci, gval, x, r_old, r_new, p, \
-                       q, t, out_partials, pq, st, k)
+    hipLaunchKernelGGL(k_pcg_xr_g<W>, dim3(grid), dim3(kBlock), 0, s, m, grp, gci, gval, r_old, r_new, q, t, \
+                       out_partials, pq, st, k)
     if (width <= 1) CGMI_PCG_XR_G(1);
     else if (width <= 2) CGMI_PCG_XR_G(2);
     else if (width <= 4) CGMI_PCG_XR_G(4);
@@ -1490,11 +1523,11 @@ hipError_t launch_update_px(int32_t m, int grid, double *x, const double *r, dou
     return hipGetLastError();
 }
 
-hipError_t launch_update_p_pcg(int32_t m, int grid, const double *z, double *p, Partials rr,
+hipError_t launch_update_p_pcg(int32_t m, int grid, const double *z, double *p, double *x, Partials rr,
                                Partials rz, Partials bb, DevState *st, int first, int32_t k,
                                hipStream_t s) {
     if (m == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_update_p_pcg, dim3(grid), dim3(kBlock), 0, s, m, z, p, rr, rz, bb, st, first, k);
+    hipLaunchKernelGGL(k_update_p_pcg, dim3(grid), dim3(kBlock), 0, s, m, z, p, x, rr, rz, bb, st, first, k);
     return hipGetLastError();
 }
 
