@@ -42,7 +42,8 @@ typedef struct cg_batch cg_batch;
 /* Schedule of the persistent launch (the autotuner's search space). */
 typedef struct cg_batch_sched {
     int32_t blocks_per_cu;  /* workgroups per compute unit (capped by occupancy) */
-    int32_t rows_per_thread;/* rows a thread advances per step: 1 or 2 */
+    int32_t rows_per_thread;/* rows a thread advances per step of the vector
+                               phases: 1 or 2 */
     double team_exponent;   /* team size of system k proportional to n_k^team_exponent */
     int32_t max_team;       /* upper bound on a team's workgroups (0: none) */
     int32_t rhs_per_lane;   /* right-hand sides per lane: 1, or 2 (16-byte

@@ -206,8 +206,94 @@ __device__ __forceinline__ void row_dot(const BatchArgs &a, int64_t row, const d
     }
 }
 
-// U: rows a thread advances per step; V: right-hand sides per lane (2 needs
-// an even nrhs and 16-byte aligned vectors).
+// Columns and values of a row of at most kPipe entries (clamped: entries
+// past the row repeat its first, an empty row reads entry 0).
+constexpr int kPipe = 6;
+
+__device__ __forceinline__ void row_cw(const BatchArgs &a, int k0, int len, int (&c)[kPipe],
+                                       double (&w)[kPipe]) {
+    const int base = len > 0 ? k0 : 0;
+#pragma unroll
+    for (int e = 0; e < kPipe; ++e) {
+        const int k = base + (e < len ? e : 0);
+        c[e] = a.ci[k];
+        w[e] = a.val[k];
+    }
+}
+
+// Phase A over the thread's rows lo + rsub, lo + rsub + RS, ...: q = A p and
+// the partial p^T q, with three rows in flight (while the current row's
+// gathers return, the next row's columns and values and the row pointers of
+// the one after are loading), so a row costs about one memory round trip
+// instead of three.  Sums as row_dot: CSR order, each product and sum
+// rounded; rows longer than kPipe go entry by entry in the same order.
+template <int V>
+__device__ __forceinline__ void spmv_rows_pipelined(const BatchArgs &a, int64_t lo, int64_t hi, int RS,
+                                                    int rsub, int nr, int j0, const bool (&on)[V],
+                                                    double (&acc)[V]) {
+#pragma clang fp contract(off)
+    int64_t row = lo + rsub;
+    if (row >= hi) return;
+    int k0c = a.rp[row], lenc = a.rp[row + 1] - k0c;
+    int cc[kPipe];
+    double wc[kPipe];
+    row_cw(a, k0c, lenc, cc, wc);
+    int k0n = 0, k1n = 0;
+    if (row + RS < hi) {
+        k0n = a.rp[row + RS];
+        k1n = a.rp[row + RS + 1];
+    }
+    for (; row < hi; row += RS) {
+        double pv[kPipe][V], po[V];
+#pragma unroll
+        for (int e = 0; e < kPipe; ++e) ldv<V>(a.P, (int64_t)cc[e] * nr + j0, pv[e]);
+        const int64_t idx = row * nr + j0;
+        ldv<V>(a.P, idx, po);
+        int cn[kPipe];
+        double wn[kPipe];
+        row_cw(a, k0n, k1n - k0n, cn, wn);
+        int k0nn = 0, k1nn = 0;
+        if (row + 2 * RS < hi) {
+            k0nn = a.rp[row + 2 * RS];
+            k1nn = a.rp[row + 2 * RS + 1];
+        }
+        double sv[V];
+#pragma unroll
+        for (int q = 0; q < V; ++q) sv[q] = 0.0;
+        if (lenc <= kPipe) {
+#pragma unroll
+            for (int e = 0; e < kPipe; ++e)
+                if (e < lenc)
+#pragma unroll
+                    for (int q = 0; q < V; ++q) sv[q] += wc[e] * pv[e][q];
+        } else {
+            for (int k = k0c; k < k0c + lenc; ++k) {
+                double g[V];
+                ldv<V>(a.P, (int64_t)a.ci[k] * nr + j0, g);
+                const double wk = a.val[k];
+#pragma unroll
+                for (int q = 0; q < V; ++q) sv[q] += wk * g[q];
+            }
+        }
+        stv<V>(a.Q, idx, sv);
+#pragma unroll
+        for (int q = 0; q < V; ++q)
+            if (on[q]) acc[q] = fma(po[q], sv[q], acc[q]);
+        k0c = k0n;
+        lenc = k1n - k0n;
+#pragma unroll
+        for (int e = 0; e < kPipe; ++e) {
+            cc[e] = cn[e];
+            wc[e] = wn[e];
+        }
+        k0n = k0nn;
+        k1n = k1nn;
+    }
+}
+
+// U: rows a thread advances per step in the setup and the vector phases B
+// and C (phase A keeps three rows in flight by itself); V: right-hand sides
+// per lane (2 needs an even nrhs and 16-byte aligned vectors).
 template <int U, int V>
 __global__ __launch_bounds__(kT) void k_batch_cg(BatchArgs a) {
     constexpr int LPR = kL / V;          // lanes per row
@@ -295,22 +381,7 @@ __global__ __launch_bounds__(kT) void k_batch_cg(BatchArgs a) {
             double acc[V];
 #pragma unroll
             for (int q = 0; q < V; ++q) acc[q] = 0.0;
-            if (any_on)
-                for (int64_t r0 = lo; r0 < hi; r0 += RS * U)
-#pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        const int64_t row = r0 + u * RS + rsub;
-                        if (row < hi) {
-                            double s[V], pv[V];
-                            row_dot<V>(a, row, a.P, nr, j0, s);
-                            const int64_t idx = row * nr + j0;
-                            stv<V>(a.Q, idx, s);
-                            ldv<V>(a.P, idx, pv);
-#pragma unroll
-                            for (int q = 0; q < V; ++q)
-                                if (on[q]) acc[q] = fma(pv[q], s[q], acc[q]);
-                        }
-                    }
+            if (any_on && lane_on) spmv_rows_pipelined<V>(a, lo, hi, RS, rsub, nr, j0, on, acc);
             wg_partial<V>(acc, mypart + kSlotPQ * kL, S);
         }
         if (!team_sync(a, sys, T, episode, S)) return;

@@ -144,6 +144,29 @@ def test_fixed_work_matches_oracle_iterates(cg):
             assert np.linalg.norm(X[k][:, j] - ref["x"]) <= 1e-9 * np.linalg.norm(ref["x"])
 
 
+def test_long_rows_match_oracle(cg):
+    """Rows longer than the row width phase A keeps in flight (7-point
+    stencil rows of 7 entries, random SPD rows of tens to hundreds) take its
+    entry-by-entry path; pairs against the oracle as above, multi-workgroup
+    teams included."""
+    systems = [I.poisson3d(10), I.random_spd_lognormal(1200, 7, mean_degree=20.0), I.poisson2d(18)]
+    assert max(np.diff(A.row_ptr).max() for A in systems[:2]) > 6
+    nrhs = 4
+    xs, bs = make_batch(systems, nrhs, seed=8)
+    X, res, st, code = run_batch(cg, systems, bs, nrhs, blocks_per_cu=8, team_exponent=1.0)
+    print(f"[batch] long rows stats {st}", flush=True)
+    assert code == cg.CG_OK
+    for k, A in enumerate(systems):
+        kap = kappa(A)
+        for j in range(nrhs):
+            ref = oracle.cg(A, bs[k][:, j], tol=1e-10, maxit=20000)
+            r = res[k, j]
+            assert ref["status"] == 0 and r["status"] == 0
+            assert abs(int(r["iterations"]) - ref["iterations"]) <= max(2, 0.05 * ref["iterations"]), (k, j)
+            assert r["rel_res_true"] <= 1.01e-10
+            assert np.linalg.norm(X[k][:, j] - ref["x"]) <= 2 * kap * 1e-10 * np.linalg.norm(ref["x"])
+
+
 def test_edge_cases(cg):
     A = field(20, 13)
     systems = [A, A]
