@@ -137,6 +137,7 @@ def cpu_baseline_cg(problem, iters_hint: int, target_s: float = 12.0) -> dict:
 def _timed_solve(solver, b, x0, tol, maxit, reps):
     import torch
     times, res = [], None
+    x = x0.clone()            # returned as is when reps = 0 (no warmup)
     for _ in range(reps):
         x = x0.clone()
         torch.cuda.synchronize()

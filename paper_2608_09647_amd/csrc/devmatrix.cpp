@@ -412,8 +412,26 @@ int build_blocks(DevMatrix &M, int32_t block_cols, int cus, int grid_cap, bool n
         DevMatrix &B = M.blocks[b];
         int rc = dm_upload(B, m, rp.data(), ci.data(), va.data(), M.pad_col_base);
         if (rc) return rc;
+        // Natural row order, L lanes per row with L the power of two covering
+        // half the block's mean row length, so each pass reads the row
+        // pointers and reads and writes q in whole lines; bins by row length
+        // (the row list) scattered those accesses, about 2.5x the compulsory
+        // L2 misses per pass at n = 2M.  A block with a row longer than
+        // kHugeRow keeps the bins (such rows take a whole workgroup there).
         std::vector<int32_t> rows;
-        build_schedule(B, 1, B.sched, rows, true);
+        int64_t bmax = 0;
+        for (int32_t i = 0; i < m; ++i) bmax = std::max<int64_t>(bmax, rp[i + 1] - rp[i]);
+        if (m > 0 && bmax <= kHugeRow) {
+            const int L = lanes_for_length(((int64_t)rp[m] + 2ll * m - 1) / (2ll * m));
+            Schedule &S = B.sched;
+            S = Schedule{};
+            S.identity = 1;
+            S.nbins = 1;
+            S.bins[0] = Bin{L, 0, m, 0};
+            S.ntiles = (m + rows_per_wave_tile(L) - 1) / rows_per_wave_tile(L);
+        } else {
+            build_schedule(B, 1, B.sched, rows, true);
+        }
         if (!rows.empty()) {
             const hipError_t e = hipMemcpy(B.d_rows, rows.data(), sizeof(int32_t) * rows.size(),
                                            hipMemcpyHostToDevice);

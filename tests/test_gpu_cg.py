@@ -144,13 +144,28 @@ def test_spmv_tilings_match_oracle(cg, name, kind):
 @pytest.mark.parametrize("cols", [97, 1000, 4096])
 @pytest.mark.parametrize("name", ["random_spd_30k", "arrowhead_3000", "poisson3d_ragged"])
 def test_column_blocks_match_oracle(cg, name, cols):
-    """Column blocks of `cols` columns (many blocks on small matrices; the
-    arrowhead's dense row goes to the workgroup-per-row bin of block 0)."""
+    """Column blocks of `cols` columns (many blocks on small matrices), each
+    walked in natural row order with lanes for half its mean row length; the
+    arrowhead's dense row loops in its lane group."""
     A = SPMV_CASES[name]()
     x = np.random.default_rng(5).uniform(-1, 1, A.n)
     ref = oracle.spmv(A, x)
     if (A.n + cols - 1) // cols > 64:
         cols = (A.n + 63) // 64
+    with cg.Solver(A) as s:
+        s.set_opts(spmv_kind=5, spmv_colblock=cols)
+        y = host(s.spmv(dev(x)))
+        assert used_kind(s, A.n) == 5
+    assert spmv_err(A, x, y, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("cols", [5000, 8192])
+def test_column_blocks_with_a_huge_row_keep_length_bins(cg, cols):
+    """A block holding a row longer than 4096 entries keeps the length bins,
+    where that row is reduced by a whole workgroup."""
+    A = arrowhead(6000, seed=3)
+    x = np.random.default_rng(6).uniform(-1, 1, A.n)
+    ref = oracle.spmv(A, x)
     with cg.Solver(A) as s:
         s.set_opts(spmv_kind=5, spmv_colblock=cols)
         y = host(s.spmv(dev(x)))
