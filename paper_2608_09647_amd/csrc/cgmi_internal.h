@@ -226,6 +226,14 @@ hipError_t launch_pcg_xr_g(int32_t m, int grid, int width, const int32_t *grp, c
                            double *t, double *out_partials, Partials pq, DevState *st, int32_t k,
                            hipStream_t s);
 
+// The same for a factor G in stencil slices (st_off/st_offs/st_mask/st_val as
+// built for the SpMV, columns = rows + offsets): identical results; grid a
+// multiple of 8, one 64-row slice per wavefront and step.
+hipError_t launch_pcg_xr_gs(int32_t m, int grid, const int32_t *st_off, const int32_t *st_offs,
+                            const uint8_t *st_mask, const double *st_val, const double *r_old, double *r_new,
+                            const double *q, double *t, double *out_partials, Partials pq, DevState *st,
+                            int32_t k, hipStream_t s);
+
 // Preconditioned CG (z = M^-1 r): p = z + beta p, rho = r^T z from the rz
 // partials, the stop test on the rr partials; first = 1 is the setup step
 // (rho_0, ||b||^2 from bb, stop test at the top of iteration 0, p = z).

@@ -131,8 +131,11 @@ int solve_gpu_pcg(cg_handle *h, const double *b, double *x, double tol, int32_t 
     const int32_t n = h->n;
     hipStream_t st = h->stream;
     const int Ga = h->A.grid, Gg = h->G.grid, Gt = h->GT.grid, Gv = h->vec_grid;
-    // the fused r/t kernel runs one row per thread
-    const int Gx = std::max(1, (int)std::min<int64_t>(h->grid_cap, ((int64_t)n + kBlock - 1) / kBlock));
+    // the fused r/t kernel: one row per thread (CSR), or one 64-row slice per
+    // wavefront (G in stencil slices; the grid a multiple of 8)
+    const bool g_sten = h->G.sched.kind == kTileStencil && h->G.d_st_val;
+    const int Gx = g_sten ? std::max(8, (int)std::min<int64_t>(h->grid_cap, ((((int64_t)n + kBlock - 1) / kBlock) + 7) / 8 * 8))
+                          : std::max(1, (int)std::min<int64_t>(h->grid_cap, ((int64_t)n + kBlock - 1) / kBlock));
     const Partials none = no_partials();
     const Partials setup_rr{h->d_part_setup, Ga}, setup_bb{h->d_part_setup + Ga, Ga};
     const Partials pq{h->d_part_pq, Ga}, rr{h->d_part_rr, h->g_width ? Gx : Gv}, rz{h->d_part_rz, Gt};
@@ -173,8 +176,12 @@ int solve_gpu_pcg(cg_handle *h, const double *b, double *x, double tol, int32_t 
                 // x/r update and t = G r in one kernel; r alternates between two buffers
                 const double *r_old = rbuf[kk & 1];
                 r_now = rbuf[(kk + 1) & 1];
-                HIP_TRY(launch_pcg_xr_g(n, Gx, h->g_width, h->G.d_rp, h->G.d_ci, h->G.d_val, r_old, r_now,
-                                        h->d_q, h->d_t, h->d_part_rr, pq, h->d_state, kk, st));
+                if (g_sten)
+                    HIP_TRY(launch_pcg_xr_gs(n, Gx, h->G.d_st_off, h->G.d_st_offs, h->G.d_st_mask, h->G.d_st_val,
+                                             r_old, r_now, h->d_q, h->d_t, h->d_part_rr, pq, h->d_state, kk, st));
+                else
+                    HIP_TRY(launch_pcg_xr_g(n, Gx, h->g_width, h->G.d_rp, h->G.d_ci, h->G.d_val, r_old, r_now,
+                                            h->d_q, h->d_t, h->d_part_rr, pq, h->d_state, kk, st));
             } else {
                 HIP_TRY(launch_update_xr(n, Gv, h->d_x, h->d_r, h->d_p, h->d_q, h->d_part_rr, pq, h->d_state, 1,
                                          kk, 0.0, st));

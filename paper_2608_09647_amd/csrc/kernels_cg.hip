@@ -92,12 +92,30 @@ __device__ __forceinline__ double reduce_partials(const Partials &P, double *sh,
 }
 
 // Two such sums with one set of workgroup barriers, each in the order of
-// reduce_partials.  sh: 2 kBlock/64 doubles; bc: 2 doubles.
+// reduce_partials; the loads of both arrays are issued together.
+// sh: 2 kBlock/64 doubles; bc: 2 doubles.
 __device__ __forceinline__ void reduce_partials2(const Partials &P0, const Partials &P1, double *sh,
                                                  double *bc, double &s0, double &s1) {
     constexpr int NW = kBlock / kWave;
-    const double v0 = wave_sum(thread_partials(P0));
-    const double v1 = wave_sum(thread_partials(P1));
+    double a0 = 0.0, a1 = 0.0;
+    const int cmax = max(P0.count, P1.count);
+    for (int base = threadIdx.x; base < cmax; base += 8 * kBlock) {
+        double t0[8], t1[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = base + u * kBlock;
+            t0[u] = i < P0.count ? P0.v[i] : 0.0;
+            t1[u] = i < P1.count ? P1.v[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = base + u * kBlock;
+            if (i < P0.count) a0 += t0[u];
+            if (i < P1.count) a1 += t1[u];
+        }
+    }
+    const double v0 = wave_sum(a0);
+    const double v1 = wave_sum(a1);
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     if (lane == 0) {
         sh[w] = v0;
@@ -944,6 +962,74 @@ __global__ __launch_bounds__(kBlock) void k_pcg_xr_g(int32_t m, const int32_t *_
     if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
+// The same with G in stencil slices (the layout of spmv_sten_wave): a
+// wavefront takes a 64-row slice, lane l row r0 + l; the columns of slot j are
+// the rows plus the slice's j-th offset, so no column index is loaded and all
+// gathers of a row issue at once.  Slots ascend with the column and absent
+// ones are skipped, so t_i is summed exactly as by k_pcg_xr_g.
+__global__ __launch_bounds__(kBlock) void k_pcg_xr_gs(int32_t m, const int32_t *__restrict__ st_off,
+                                                      const int32_t *__restrict__ st_offs,
+                                                      const uint8_t *__restrict__ st_mask,
+                                                      const double *__restrict__ st_val,
+                                                      const double *__restrict__ r_old, double *__restrict__ r_new,
+                                                      const double *__restrict__ q, double *__restrict__ t,
+                                                      double *__restrict__ out, Partials pq_in,
+                                                      DevState *__restrict__ st, int32_t k) {
+    __shared__ double sh[kWavesPerBlock];
+    __shared__ double bc;
+    if (st->done) return;
+    const double pq = reduce_partials(pq_in, sh, &bc);
+    if (!(pq > 0.0) || !isfinite(pq)) {
+        if (is_block0_thread0()) {
+            st->pq = pq;
+            st->iter = k;
+            st->done = kDoneBreakdown;
+        }
+        return;
+    }
+    const double alpha = st->rho[k & 1] / pq;
+    if (is_block0_thread0()) {
+        st->pq = pq;
+        st->r_iter = k + 1;
+    }
+    const int lane = threadIdx.x & (kWave - 1);
+    double acc = 0.0;
+    TileWalk walk((m + kWave - 1) / kWave);
+    for (int tl = walk.next(); tl >= 0; tl = walk.next()) {
+        const int r0 = __builtin_amdgcn_readfirstlane(tl * kWave);
+        const int nrows = min(kWave, m - r0);
+        const int row = r0 + min(lane, nrows - 1);
+        const int off = st_off[tl];
+        const int width = (st_off[tl + 1] - off) / kWave;
+        const uint32_t mask = st_mask[(int64_t)tl * kWave + lane];
+        const double rv = fma(-alpha, q[row], r_old[row]);
+        double w[kSliceMaxWidth], rn[kSliceMaxWidth];
+#pragma unroll
+        for (int j = 0; j < kSliceMaxWidth; ++j) {
+            w[j] = rn[j] = 0.0;
+            if (j < width) {   // uniform across the wavefront
+                const int c = (mask >> j) & 1u ? row + st_offs[tl * kSliceMaxWidth + j] : row;
+                w[j] = st_val[off + j * kWave + lane];
+                rn[j] = fma(-alpha, q[c], r_old[c]);
+            }
+        }
+        double s = 0.0;
+        {
+#pragma clang fp contract(off)
+#pragma unroll
+            for (int j = 0; j < kSliceMaxWidth; ++j)
+                if ((mask >> j) & 1u) s = s + w[j] * rn[j];
+        }
+        if (lane < nrows) {
+            r_new[row] = rv;
+            t[row] = s;
+            acc = fma(rv, rv, acc);
+        }
+    }
+    const double sum = block_sum<kBlock>(acc, sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = sum;
+}
+
 // x += alpha p, r -= alpha q; partial r^T r per workgroup.
 __global__ __launch_bounds__(kBlock) void k_update_xr(int32_t m, double *__restrict__ x,
                                                       double *__restrict__ r,
@@ -1506,6 +1592,17 @@ hipError_t launch_pcg_xr_g(int32_t m, int grid, int width, const int32_t *grp, c
     else if (width <= 4) CGMI_PCG_XR_G(4);
     else CGMI_PCG_XR_G(8);
 #undef CGMI_PCG_XR_G
+    return hipGetLastError();
+}
+
+hipError_t launch_pcg_xr_gs(int32_t m, int grid, const int32_t *st_off, const int32_t *st_offs,
+                            const uint8_t *st_mask, const double *st_val, const double *r_old, double *r_new,
+                            const double *q, double *t, double *out_partials, Partials pq, DevState *st,
+                            int32_t k, hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    if (grid < 8 || (grid & 7)) return hipErrorInvalidValue;   // the tile walk deals tiles out per XCD
+    hipLaunchKernelGGL(k_pcg_xr_gs, dim3(grid), dim3(kBlock), 0, s, m, st_off, st_offs, st_mask, st_val, r_old,
+                       r_new, q, t, out_partials, pq, st, k);
     return hipGetLastError();
 }
 
