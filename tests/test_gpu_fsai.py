@@ -227,6 +227,30 @@ def test_pcg_classic_fsai_matches_oracle(cg):
     assert ref["iterations"] < plain["iterations"]
 
 
+def random_lower_factor(n, per_row, seed):
+    """Lower-triangular factor with up to `per_row` entries per row at random
+    columns (positive diagonal, so M = G^T G is SPD): 64-row slices use far
+    more than 8 column offsets, so it stays in CSR."""
+    rng = np.random.default_rng(seed)
+    rows, cols, vals = [], [], []
+    for i in range(n):
+        k = min(i, per_row - 1)
+        cs = list(rng.choice(i, size=k, replace=False)) if k > 0 else []
+        rows += [i] * (k + 1)
+        cols += cs + [i]
+        vals += list(rng.uniform(-0.2, 0.2, k)) + [1.0 + rng.random()]
+    return sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+
+
+@pytest.mark.parametrize("per_row", [4, 12])
+def test_pcg_scattered_factor_matches_oracle(cg, per_row):
+    """A factor that does not fit stencil slices: the CSR form of the fused
+    r/t kernel (at most 8 entries per row), or the unfused x/r update, SpMV
+    with G and p update (more)."""
+    p = I.poisson2d_problem(40, seed=2)
+    check_pcg_against_oracle(cg, p.A, p.b, random_lower_factor(p.A.n, per_row, 11))
+
+
 def test_pcg_learned_factor_matches_oracle_with_same_factor(cg):
     A = field(44, 44, 52)
     b = I.rhs_of(A, I.uniform_vector(A.n, [52, 1]))
