@@ -916,7 +916,7 @@ static int solve_split(cg_handle *h, const double *b, double *x, double tol, int
         // p = r + beta p, then exchange
         if (gpu) {
             HIP_TRY(hipEventRecord(tm.ev0, st));
-            HIP_TRY(launch_update_p(m, Gv, h->d_r, h->d_p + rb, no_partials(), nullptr, 0, k, beta, st));
+            HIP_TRY(launch_update_p(m, Gv, h->d_r, h->d_p + rb, beta, st));
             HIP_TRY(hipEventRecord(tm.ev1, st));
         }
         t_c = now();

@@ -207,12 +207,9 @@ hipError_t launch_update_xr(int32_t m, int grid, double *x, double *r, const dou
                             const double *q, double *out_partials, Partials pq, DevState *st,
                             int device_coef, int32_t k, double alpha_arg, hipStream_t s);
 
-// p = r + beta p.  device_coef: rho_{k+1} = sum(rr), beta = rho_{k+1} / rho_k,
-// the stop test, and workgroup 0 records iteration k+1 in st; no update once
-// the solve has stopped.  Otherwise beta = beta_arg.
-hipError_t launch_update_p(int32_t m, int grid, const double *r, double *p_own, Partials rr,
-                           DevState *st, int device_coef, int32_t k, double beta_arg,
-                           hipStream_t s);
+// p = r + beta p with beta from the host (split mode; the device-coefficient
+// paths use launch_update_px and launch_update_p_pcg).
+hipError_t launch_update_p(int32_t m, int grid, const double *r, double *p_own, double beta, hipStream_t s);
 
 // Preconditioned CG, r update fused with t = G r_new for a factor G of at
 // most `width` <= kFusedGWidth entries per row (CSR grp/gci/gval, rows

@@ -1088,30 +1088,9 @@ __global__ __launch_bounds__(kBlock) void k_update_xr(int32_t m, double *__restr
     if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
-// p = r + beta p.
+// p = r + beta p with beta from the host (split mode).
 __global__ __launch_bounds__(kBlock) void k_update_p(int32_t m, const double *__restrict__ r,
-                                                     double *__restrict__ p, Partials rr_in,
-                                                     DevState *__restrict__ st, int device_coef,
-                                                     int32_t k, double beta_arg) {
-    __shared__ double sh[kWavesPerBlock];
-    __shared__ double bc;
-    double beta = beta_arg;
-    if (device_coef) {
-        if (st->done) return;
-        const double rr = reduce_partials(rr_in, sh, &bc);
-        const double rho_k = st->rho[k & 1];
-        beta = rr / rho_k;
-        const bool conv = stop_test(rr, st->bb, st->tol);
-        const bool maxed = k + 1 >= st->maxit;
-        if (is_block0_thread0()) {
-            st->rho[(k + 1) & 1] = rr;
-            st->rr = rr;
-            st->iter = k + 1;
-            if (conv) st->done = kDoneConverged;
-            else if (maxed) st->done = kDoneMaxit;
-        }
-        if (conv || maxed) return;
-    }
+                                                     double *__restrict__ p, double beta) {
     const int64_t npair = m >> 1;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     double2 *p2 = reinterpret_cast<double2 *>(p);
@@ -1569,12 +1548,9 @@ hipError_t launch_update_xr(int32_t m, int grid, double *x, double *r, const dou
     return hipGetLastError();
 }
 
-hipError_t launch_update_p(int32_t m, int grid, const double *r, double *p_own, Partials rr,
-                           DevState *st, int device_coef, int32_t k, double beta_arg,
-                           hipStream_t s) {
+hipError_t launch_update_p(int32_t m, int grid, const double *r, double *p_own, double beta, hipStream_t s) {
     if (m == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_update_p, dim3(grid), dim3(kBlock), 0, s, m, r, p_own, rr, st, device_coef,
-                       k, beta_arg);
+    hipLaunchKernelGGL(k_update_p, dim3(grid), dim3(kBlock), 0, s, m, r, p_own, beta);
     return hipGetLastError();
 }
 
