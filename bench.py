@@ -311,6 +311,42 @@ def _line(metric, value, unit, args, ms, config, higher=True, **extra):
     return d
 
 
+def profiled_spmv_us(prob, opts: dict) -> float:
+    """Mean SpMV time of one solve to 1e-10 with HIP events around every SpMV
+    (a separate solve, so the events stay out of the timed ones)."""
+    import torch
+    from paper_2608_09647_amd import autotune, cgmi
+    b = torch.from_numpy(prob.b).to(torch.device("cuda:0"))
+    with cgmi.Solver(prob.A) as s:
+        autotune.spmv_schedule(s, prob.A, b, tune_if_missing=False)
+        s.set_opts(profile=1, **opts)
+        _, res = s.solve(b, torch.zeros_like(b), tol=1e-10, maxit=200000)
+        torch.cuda.synchronize()
+    return 1e6 * res["t_spmv"] / max(res["n_spmv"], 1)
+
+
+def spmv_algorithmic_bytes_f32(n: int, nnz: int) -> int:
+    """Float32 CSR SpMV: 4-byte columns and values, row pointers, q written
+    and p read once (4 bytes each)."""
+    return 8 * nnz + 4 * (n + 1) + 8 * n
+
+
+def cpu_baseline_mixed(prob, iterations: int, target_s: float = 12.0) -> dict:
+    """The oracle's float32-inner CG with float64 refinement, fixed work on a
+    bounded number of inner iterations, scaled to the GPU solve's count."""
+    import oracle
+    k = _sample_iterations(lambda m: oracle.cg_mixed(prob.A, prob.b, tol=0.0, maxit=m), iterations,
+                           target_s)
+    t0 = time.perf_counter()
+    out = oracle.cg_mixed(prob.A, prob.b, tol=0.0, maxit=k)
+    dt = time.perf_counter() - t0
+    per_it = dt / max(out["iterations"], 1)
+    return {"value": per_it * iterations, "unit": "s", "cores": oracle.max_threads(), "kind": "oracle",
+            "host": host_info(),
+            "sample": f"{out['iterations']} fixed-work float32-inner iterations of the oracle's mixed "
+                      f"CG ({dt:.1f} s), scaled to the {iterations} iterations of the GPU solve"}
+
+
 def bench_mixed(args) -> int:
     """Random SPD n = 2M: float32-inner/float64-refined CG vs plain float64 CG to 1e-10."""
     import numpy as np
@@ -321,14 +357,29 @@ def bench_mixed(args) -> int:
                                 None, None)
     err = float(np.linalg.norm(xs["mixed"] - xs["fp64"]) / np.linalg.norm(xs["fp64"]))
     sp = out["fp64"]["seconds"] / out["mixed"]["seconds"]
+    # the mixed solve's dominant kernel is its float32 SpMV (column blocks)
+    us32 = profiled_spmv_us(prob, {"precision": 1})
+    us64 = profiled_spmv_us(prob, {})
+    n, nnz = prob.A.n, prob.A.nnz
+    a32 = spmv_algorithmic_bytes_f32(n, nnz) / (us32 * 1e-6) / 1e9
+    a64 = spmv_algorithmic_bytes(n, nnz) / (us64 * 1e-6) / 1e9
     line = _line("time to 1e-10 true relative residual: float32-inner/float64-refined CG "
                  "vs plain float64 CG", out["mixed"]["seconds"], "s", args,
                  1e3 * out["mixed"]["seconds"],
-                 {"workload": "random_spd_lognormal_n2M_mixed_vs_fp64", "n": prob.A.n,
-                  "nnz": prob.A.nnz, "tol": 1e-10, "seed": 3}, higher=False,
+                 {"workload": "random_spd_lognormal_n2M_mixed_vs_fp64", "n": n,
+                  "nnz": nnz, "tol": 1e-10, "seed": 3}, higher=False,
                  plain_fp64=out["fp64"], mixed=out["mixed"], speedup_vs_fp64=sp,
-                 mixed_rel_error_vs_fp64_solution=err)
+                 mixed_rel_error_vs_fp64_solution=err,
+                 spmv_us={"float32": us32, "float64": us64},
+                 spmv_gbs={"float32": a32, "float64": a64},
+                 roofline={"bound": "hbm", "achieved": a32, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": a32 / HBM_PEAK_GBS, "traffic": None,
+                           "note": "float32 column-blocked SpMV, CSR-algorithmic bytes "
+                                   "(8 nnz + 4 (n+1) + 8 n) per launch; its uniformly random "
+                                   "columns make it bound by L2 gathers, not HBM bytes"})
     line["dtype"] = "f32+f64"
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_mixed(prob, out["mixed"]["iterations"])
     print(json.dumps(line), flush=True)
     return 0
 
@@ -344,8 +395,25 @@ def bench_small(args) -> int:
                  best["iterations"] / best["seconds"], "iter/s", args, 1e3 * best["seconds"],
                  {"workload": "poisson2d_5pt_64x64_fp64_cg_to_1e-10", "n": prob.A.n,
                   "nnz": prob.A.nnz, "seed": 1}, paths=out)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_repeat(prob)
     print(json.dumps(line), flush=True)
     return 0
+
+
+def cpu_baseline_repeat(prob, target_s: float = 10.0) -> dict:
+    """The oracle's CG to 1e-10 on the same small system, repeated for about
+    target_s seconds (one solve takes milliseconds)."""
+    import oracle
+    its, solves = 0, 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < target_s:
+        its += oracle.cg(prob.A, prob.b, tol=1e-10, maxit=20000)["iterations"]
+        solves += 1
+    dt = time.perf_counter() - t0
+    return {"value": its / dt, "unit": "iter/s", "cores": oracle.max_threads(), "kind": "oracle",
+            "host": host_info(),
+            "sample": f"{solves} oracle solves to 1e-10 of the same system ({its} iterations, {dt:.1f} s)"}
 
 
 SPLIT_MODES = (("whole", 0), ("halo", 1), ("mapped", 2), ("managed", 3))
