@@ -510,10 +510,15 @@ def test_full_size_poisson3d_256(cg):
     print(f"[full] poisson3d 256^3 n={A.n} nnz={A.nnz}", flush=True)
     x = np.random.default_rng(2).uniform(-1, 1, A.n)
     ref = oracle.spmv(A, x)
+    from paper_2608_09647_amd import autotune
     with cg.Solver(A) as s:
+        sched = autotune.spmv_schedule(s, A, dev(p.b), tune_if_missing=False)
+        print(f"[full] schedule {sched}", flush=True)
         s.set_opts(profile=1)
         y = host(s.spmv(dev(x)))
-        assert spmv_err(A, x, y, ref) <= 1e-12
+        assert used_kind(s, A.n) == 6
+        # stencil slices sum every row in the oracle's order: equal bits
+        assert np.array_equal(y, ref)
         del y, ref
         xg, res = s.solve(dev(p.b), tol=0.0, maxit=3)
         x3 = host(xg)

@@ -107,7 +107,9 @@ def test_full_size_diffusion_1024_learned_factor(cg):
     th = fsai.init_params(0)
     print(f"[full] diffusion 1024^2 n={A.n} nnz={A.nnz}", flush=True)
     b = dev(q.b)
+    from paper_2608_09647_amd import autotune
     with cg.Solver(A) as s:
+        autotune.spmv_schedule(s, A, b, tune_if_missing=False)   # the benchmark's tiling
         s.fsai_setup(th)
         rp, ci, va = s.read_factor()
         s.set_opts(precond=cg.PC_FSAI)
