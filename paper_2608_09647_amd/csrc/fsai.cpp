@@ -19,6 +19,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <vector>
 
@@ -45,36 +46,82 @@ struct FsaiSetup {
 
 namespace {
 
+// Host array left uninitialised on allocation (its pages are first touched by
+// the parallel loops that fill it, not by one thread zeroing it).
+template <class T>
+struct HostArray {
+    std::unique_ptr<T[]> p;
+    size_t n = 0;
+    void alloc(size_t k) {
+        p.reset(k ? new T[k] : nullptr);
+        n = k;
+    }
+    T *data() { return p.get(); }
+    const T *data() const { return p.get(); }
+    size_t size() const { return n; }
+    T &operator[](size_t i) { return p[i]; }
+    const T &operator[](size_t i) const { return p[i]; }
+};
+
 struct HostCsr {
-    std::vector<int32_t> rp, ci;
-    std::vector<double> val;
+    std::vector<int32_t> rp;
+    HostArray<int32_t> ci;
+    HostArray<double> val;
 };
 
 // Transpose of an n x n CSR (columns of the result ascending); pos[k] is the
-// position of input entry k in the result.
+// position of input entry k in the result.  Host threads count the entries
+// of every column and scatter them (atomic cursors), then sort each result
+// row by column, so the layout does not depend on thread timing.  T.val is
+// left empty when val is null.
 void transpose(int32_t n, const int32_t *rp, const int32_t *ci, const double *val, HostCsr &T,
-               std::vector<int32_t> *pos) {
+               HostArray<int32_t> *pos) {
     const int64_t nnz = rp[n];
     T.rp.assign((size_t)n + 1, 0);
-    T.ci.resize((size_t)nnz);
-    T.val.resize((size_t)nnz);
-    if (pos) pos->resize((size_t)nnz);
-    for (int64_t k = 0; k < nnz; ++k) ++T.rp[(size_t)ci[k] + 1];
+    T.ci.alloc((size_t)nnz);
+    T.val.alloc(val ? (size_t)nnz : 0);
+    if (pos) pos->alloc((size_t)nnz);
+    HostArray<int32_t> src, next;
+    src.alloc((size_t)nnz);
+    next.alloc((size_t)n);
+    int32_t *cnt = T.rp.data();
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < nnz; ++k) __atomic_fetch_add(&cnt[ci[k] + 1], 1, __ATOMIC_RELAXED);
     for (int32_t j = 0; j < n; ++j) T.rp[j + 1] += T.rp[j];
-    std::vector<int32_t> next(T.rp.begin(), T.rp.end() - 1);
+#pragma omp parallel for schedule(static)
+    for (int32_t j = 0; j < n; ++j) next[j] = T.rp[j];
+#pragma omp parallel for schedule(static)
     for (int32_t i = 0; i < n; ++i)
         for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
-            const int32_t p = next[ci[k]]++;
+            const int32_t p = __atomic_fetch_add(&next[ci[k]], 1, __ATOMIC_RELAXED);
             T.ci[p] = i;
-            T.val[p] = val ? val[k] : 0.0;
-            if (pos) (*pos)[k] = p;
+            src[p] = k;
         }
+    // rows of the result by ascending column (insertion sort: short rows)
+#pragma omp parallel for schedule(dynamic, 4096)
+    for (int32_t j = 0; j < n; ++j)
+        for (int32_t a = T.rp[j] + 1; a < T.rp[j + 1]; ++a) {
+            const int32_t c = T.ci[a], sk = src[a];
+            int32_t b = a - 1;
+            while (b >= T.rp[j] && T.ci[b] > c) {
+                T.ci[b + 1] = T.ci[b];
+                src[b + 1] = src[b];
+                --b;
+            }
+            T.ci[b + 1] = c;
+            src[b + 1] = sk;
+        }
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < nnz; ++p) {
+        if (val) T.val[p] = val[src[p]];
+        if (pos) (*pos)[src[p]] = (int32_t)p;
+    }
 }
 
 // Upload G and G^T (schedules chosen automatically) and the work vectors;
 // g_val null: the values are written on the device later.
 int install_factor(cg_handle *h, const int32_t *g_rp, const int32_t *g_ci, const double *g_val,
-                   std::vector<int32_t> *tpos) {
+                   HostArray<int32_t> *tpos) {
     HostCsr T;
     try {
         transpose(h->n, g_rp, g_ci, g_val, T, tpos);
@@ -369,10 +416,11 @@ namespace {
 // positions of each row's C, W, S entries.
 int build_learned_structure(cg_handle *h) {
     const int32_t n = h->n;
-    std::vector<int32_t> g_rp, g_ci, gpos, tpos;
+    std::vector<int32_t> g_rp;
+    HostArray<int32_t> g_ci, gpos, tpos;
     try {
         g_rp.assign((size_t)n + 1, 0);
-        gpos.assign((size_t)n * 3, -1);
+        gpos.alloc((size_t)n * 3);
         // pass 1 (rows in parallel): check the stencil, count tril entries;
         // the first offending row is reported
         int32_t bad_row = INT32_MAX, bad_kind = 0;
@@ -401,10 +449,11 @@ int build_learned_structure(cg_handle *h) {
         if (bad_kind == 2) return fail(CG_EINVAL, "diagonal of row %d is not positive", bad_row);
         if (bad_kind == 3) return fail(CG_EINVAL, "row %d has no diagonal entry", bad_row);
         for (int32_t i = 0; i < n; ++i) g_rp[i + 1] += g_rp[i];
-        g_ci.resize((size_t)g_rp[n]);
-        // pass 2: columns and slot positions
+        g_ci.alloc((size_t)g_rp[n]);
+        // pass 2: columns and slot positions (-1: no such neighbour)
 #pragma omp parallel for schedule(static)
         for (int32_t i = 0; i < n; ++i) {
+            gpos[(size_t)i * 3] = gpos[(size_t)i * 3 + 1] = gpos[(size_t)i * 3 + 2] = -1;
             int32_t p = g_rp[i];
             for (int32_t k = h->h_rp[i]; k < h->h_rp[i + 1]; ++k) {
                 if (h->h_ci[k] > i) continue;
