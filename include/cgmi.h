@@ -101,15 +101,18 @@ typedef struct cg_opts {
                               tiles (the sliced layout with a 4-bit index per
                               slot into a per-slice table of at most 15 column
                               offsets; rows of at most 8 nonzeros, else 3),
-                              5 column blocks (one accumulating vector-bin pass
-                              per block of spmv_colblock columns, so gathers
-                              from p stay in the L2; for scattered columns),
+                              5 column blocks (one accumulating pass per block
+                              of spmv_colblock columns, so gathers from p stay
+                              in the L2; rows in natural order with lanes for
+                              half the block's mean row length, or length bins
+                              when a block has a row over 4096 entries; for
+                              scattered columns),
                               6 stencil slices (slot j of a 64-row slice holds
                               the entries at the slice's j-th column offset, so
                               columns are row + a slice-uniform offset and a
                               byte per row marks the present slots; rows of at
                               most 8 nonzeros, at most 8 distinct offsets per
-                              slice, float64 with host values; else 4).
+                              slice, float64; else 4).
                               Automatic picks 5 when more than half of the
                               entries lie farther than 262,144 columns from the
                               diagonal and the vector spans at least two blocks,
