@@ -221,7 +221,10 @@ extern "C" int cg_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const i
     chk(dmalloc(&h->d_x, (size_t)m + 1));
     chk(dmalloc(&h->d_r, (size_t)m + 1));
     chk(dmalloc(&h->d_q, (size_t)m + 1));
-    h->vec_grid = std::max(1, std::min(h->cus * 8, (int)(((int64_t)m / 2 + kBlock - 1) / kBlock)));
+    // vector kernels: pairs of rows per thread, at most 4 workgroups per CU
+    // (fewer partials for the next kernel to sum; measured as fast as 8 per CU
+    // at 256^3 and 9% faster per PCG iteration at 1024^2)
+    h->vec_grid = std::max(1, std::min(h->cus * 4, (int)(((int64_t)m / 2 + kBlock - 1) / kBlock)));
     h->grid_cap = std::max(h->cus * 16, 64);
     chk(dmalloc(&h->d_part_setup, 2 * (size_t)h->grid_cap));
     chk(dmalloc(&h->d_part_pq, (size_t)h->grid_cap));

@@ -178,10 +178,10 @@ int solve_gpu_pcg(cg_handle *h, const double *b, double *x, double tol, int32_t 
     const int32_t n = h->n;
     hipStream_t st = h->stream;
     const int Ga = h->A.grid, Gg = h->G.grid, Gt = h->GT.grid, Gv = h->vec_grid;
-    // the fused r/t kernel: one row per thread (CSR), or one 64-row slice per
+    // the fused r/t kernel: one row per thread (CSR), or two 64-row slices per
     // wavefront (G in stencil slices; the grid a multiple of 8)
     const bool g_sten = h->G.sched.kind == kTileStencil && h->G.d_st_val;
-    const int Gx = g_sten ? std::max(8, (int)std::min<int64_t>(h->grid_cap, ((((int64_t)n + kBlock - 1) / kBlock) + 7) / 8 * 8))
+    const int Gx = g_sten ? std::max(8, (int)std::min<int64_t>(h->grid_cap, ((((int64_t)n + 2 * kBlock - 1) / (2 * kBlock)) + 7) / 8 * 8))
                           : std::max(1, (int)std::min<int64_t>(h->grid_cap, ((int64_t)n + kBlock - 1) / kBlock));
     const Partials none = no_partials();
     const Partials setup_rr{h->d_part_setup, Ga}, setup_bb{h->d_part_setup + Ga, Ga};
