@@ -328,9 +328,13 @@ def test_training_reduces_loss_and_beats_plain_cg(cg):
     p = I.diffusion_problem(64, seed=10_000)
     plain = oracle.cg(p.A, p.b, tol=1e-10, maxit=50000)
     x, res = run_pcg(cg, p.A, p.b, theta=theta)
-    print(f"[gain] plain {plain['iterations']} learned {res['iterations']}", flush=True)
+    # the same network before training: what training itself gains
+    _, res0 = run_pcg(cg, p.A, p.b, theta=fsai.init_params(0))
+    print(f"[gain] plain {plain['iterations']} untrained {res0['iterations']} learned {res['iterations']}",
+          flush=True)
     assert res["status"] == 0 and res["fell_back"] == 0
     assert res["iterations"] < plain["iterations"]
+    assert res["iterations"] < res0["iterations"]
     assert res["rel_res_true"] <= 1.01e-10
 
 
