@@ -378,8 +378,19 @@ def bench_mixed(args) -> int:
                                    "(8 nnz + 4 (n+1) + 8 n) per launch; its uniformly random "
                                    "columns make it bound by L2 gathers, not HBM bytes"})
     line["dtype"] = "f32+f64"
+    line["rel_error_vs_xstar"] = {k: float(np.linalg.norm(xs[k] - prob.xstar) / np.linalg.norm(prob.xstar))
+                                  for k in ("fp64", "mixed")}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_mixed(prob, out["mixed"]["iterations"])
+        # each GPU solution against the float64 oracle's solution of the same system
+        import oracle
+        t0 = time.perf_counter()
+        ref = oracle.cg(prob.A, prob.b, tol=1e-10, maxit=200000)
+        dt = time.perf_counter() - t0
+        nref = float(np.linalg.norm(ref["x"]))
+        line["oracle_fp64"] = {"seconds": dt, "iterations": ref["iterations"],
+                               "rel_error": {k: float(np.linalg.norm(xs[k] - ref["x"]) / nref)
+                                             for k in ("fp64", "mixed")}}
     print(json.dumps(line), flush=True)
     return 0
 
