@@ -26,6 +26,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+SPMV_EVENT_STRIDE = 10
+
+
 def spmv_algorithmic_bytes(n: int, nnz: int) -> int:
     """int32 col + float64 val per nonzero, row pointers, q written once, p read once."""
     return 12 * nnz + 4 * (n + 1) + 8 * n + 8 * n
@@ -236,7 +239,9 @@ def main() -> int:
     solver = cgmi.Solver(A)
     from paper_2608_09647_amd import autotune
     autotune.spmv_schedule(solver, A, b, tune_if_missing=False)   # tabled SpMV tiling, if any
-    solver.set_opts(profile=1)
+    # HIP events around the SpMV of every SPMV_EVENT_STRIDE-th iteration of
+    # the timed steps (an event pair adds a few microseconds of stream time)
+    solver.set_opts(profile=SPMV_EVENT_STRIDE)
     for _ in range(args.warmup):
         x.zero_()
         solver.solve(b, x, tol=0.0, maxit=args.iters)
@@ -285,6 +290,7 @@ def main() -> int:
                    "seed": 2},
         "spmv_gbs": achieved,
         "spmv_us": 1e6 * t_launch,
+        "spmv_timed_launches": {"count": n_spmv, "every_nth_iteration": SPMV_EVENT_STRIDE},
         "hbm_copy_gbs_measured": copy_gbs,
         "spmv_frac_of_measured_copy": achieved / copy_gbs,
         "spmv_kind": {1: "vector_bins", 2: "stream", 3: "sliced", 4: "sliced_dict",

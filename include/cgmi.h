@@ -87,8 +87,12 @@ typedef struct cg_opts {
     int32_t host_threads;  /* host complement threads (0: all available)        */
     int32_t check_every;   /* GPU-only: iterations queued between host polls of
                               the device convergence flag (>= 1)                */
-    int32_t profile;       /* 1: time every SpMV launch of cg_solve with HIP
-                              events (cg_result.t_spmv / n_spmv)                */
+    int32_t profile;       /* P >= 1: time the SpMV launch of every P-th
+                              iteration of a GPU-only cg_solve with HIP events
+                              (cg_result.t_spmv / n_spmv over those launches;
+                              an event pair costs a few microseconds of stream
+                              time, so a sparse sample disturbs the solve
+                              less); 0: off                                      */
     int32_t small_path;    /* 1 (default): systems that fit one workgroup's LDS
                               run the whole solve in one single-workgroup kernel */
     int32_t spmv_grid;     /* workgroups of the SpMV kernels (0: automatic)      */

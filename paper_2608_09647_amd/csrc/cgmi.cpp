@@ -530,6 +530,8 @@ static int solve_gpu_only(cg_handle *h, const double *b, double *x, double tol, 
             ev.resize(2 * (size_t)C);
             for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
         }
+        const int P = h->opts.profile;   // events around the SpMV of every P-th iteration
+        auto sampled = [P](int32_t it) { return P > 0 && it % P == 0; };
         int32_t k = 0;
         bool running = true;
         while (running) {
@@ -537,10 +539,10 @@ static int solve_gpu_only(cg_handle *h, const double *b, double *x, double tol, 
             const int32_t chunk = maxit == 0 ? 1 : std::min<int32_t>(C, maxit - k);
             for (int32_t j = 0; j < chunk; ++j) {
                 const int32_t kk = k + j;
-                if (h->opts.profile) HIP_TRY(hipEventRecord(ev[2 * j], st));
+                if (sampled(kk)) HIP_TRY(hipEventRecord(ev[2 * j], st));
                 HIP_TRY(launch_spmv(h->A.dev(), h->A.sched, Gs, h->d_p, h->d_q, h->d_p, nullptr, nullptr,
                                     h->d_part_pq, setup_rr, setup_bb, h->d_state, kSpmvDot, kk == 0, st));
-                if (h->opts.profile) HIP_TRY(hipEventRecord(ev[2 * j + 1], st));
+                if (sampled(kk)) HIP_TRY(hipEventRecord(ev[2 * j + 1], st));
                 if (maxit == 0) break;
                 HIP_TRY(launch_update_r(n, Gv, h->d_r, h->d_q, h->d_part_rr, pq, h->d_state, kk, st));
                 HIP_TRY(launch_update_px(n, Gv, h->d_x, h->d_r, h->d_p, rr, h->d_state, kk, st));
@@ -555,6 +557,7 @@ static int solve_gpu_only(cg_handle *h, const double *b, double *x, double tol, 
                 int32_t ran = h->h_state->iter - it0 + (h->h_state->done == kDoneBreakdown ? 1 : 0);
                 ran = std::max(0, std::min<int32_t>(ran, chunk));
                 for (int32_t j = 0; j < ran; ++j) {
+                    if (!sampled(it0 + j)) continue;
                     float ms = 0.f;
                     HIP_TRY(hipEventElapsedTime(&ms, ev[2 * j], ev[2 * j + 1]));
                     t_spmv += 1e-3 * ms;
@@ -652,15 +655,18 @@ static int solve_gpu_mixed(cg_handle *h, const double *b, double *x, double tol,
             ev.resize(2 * (size_t)C);
             for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
         }
+        const int P = h->opts.profile;   // events around the SpMV of every P-th iteration
+        auto sampled = [P](int32_t it) { return P > 0 && it % P == 0; };
         double prev_true = std::sqrt(rr_true);
         int stalls = 0;
         while (k < maxit) {
             const int32_t chunk = std::min<int32_t>(C, maxit - k);
             for (int32_t j = 0; j < chunk; ++j) {
-                if (h->opts.profile) HIP_TRY(hipEventRecord(ev[2 * j], st));
+                const int32_t kk = k + j;
+                if (sampled(kk)) HIP_TRY(hipEventRecord(ev[2 * j], st));
                 HIP_TRY(launch_spmv_f32(h->A.dev(), h->A.sched, Gs, h->d_p32, h->d_q32, h->d_p32,
                                         h->d_part_pq, h->d_state, kSpmvDot, st));
-                if (h->opts.profile) HIP_TRY(hipEventRecord(ev[2 * j + 1], st));
+                if (sampled(kk)) HIP_TRY(hipEventRecord(ev[2 * j + 1], st));
                 HIP_TRY(launch_update_xr_mixed(n, Gv, h->d_x, h->d_r32, h->d_p32, h->d_q32,
                                                h->d_part_rr, pq, h->d_state, k + j, st));
                 HIP_TRY(launch_update_p_mixed(n, Gv, h->d_r32, h->d_p32, rrp, h->d_state, 1, k + j,
@@ -672,6 +678,7 @@ static int solve_gpu_mixed(cg_handle *h, const double *b, double *x, double tol,
             if (h->opts.profile) {
                 const int32_t ran = std::max(0, std::min<int32_t>(chunk, k - it0 + (S.done == kDoneBreakdown ? 1 : 0)));
                 for (int32_t j = 0; j < ran; ++j) {
+                    if (!sampled(it0 + j)) continue;
                     float ms = 0.f;
                     HIP_TRY(hipEventElapsedTime(&ms, ev[2 * j], ev[2 * j + 1]));
                     t_spmv += 1e-3 * ms;

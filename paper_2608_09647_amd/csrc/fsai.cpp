@@ -206,6 +206,8 @@ int solve_gpu_pcg(cg_handle *h, const double *b, double *x, double tol, int32_t 
         ev.resize(2 * (size_t)C);
         for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
     }
+    const int P = h->opts.profile;   // events around the SpMV of every P-th iteration
+    auto sampled = [P](int32_t it) { return P > 0 && it % P == 0; };
     double *const rbuf[2] = {h->d_r, h->d_r2};   // r of iterations k (even) and k (odd)
     int32_t k = 0;
     bool running = maxit > 0;
@@ -214,10 +216,10 @@ int solve_gpu_pcg(cg_handle *h, const double *b, double *x, double tol, int32_t 
         const int32_t chunk = std::min<int32_t>(C, maxit - k);
         for (int32_t j = 0; j < chunk; ++j) {
             const int32_t kk = k + j;
-            if (h->opts.profile) HIP_TRY(hipEventRecord(ev[2 * j], st));
+            if (sampled(kk)) HIP_TRY(hipEventRecord(ev[2 * j], st));
             HIP_TRY(launch_spmv(h->A.dev(), h->A.sched, Ga, h->d_p, h->d_q, h->d_p, nullptr, nullptr,
                                 h->d_part_pq, none, none, h->d_state, kSpmvDot, 0, st));
-            if (h->opts.profile) HIP_TRY(hipEventRecord(ev[2 * j + 1], st));
+            if (sampled(kk)) HIP_TRY(hipEventRecord(ev[2 * j + 1], st));
             double *r_now = h->d_r;
             if (h->g_width) {
                 // x/r update and t = G r in one kernel; r alternates between two buffers
@@ -250,6 +252,7 @@ int solve_gpu_pcg(cg_handle *h, const double *b, double *x, double tol, int32_t 
             int32_t ran = h->h_state->iter - it0 + (h->h_state->done == kDoneBreakdown ? 1 : 0);
             ran = std::max(0, std::min<int32_t>(ran, chunk));
             for (int32_t j = 0; j < ran; ++j) {
+                if (!sampled(it0 + j)) continue;
                 float ms = 0.f;
                 HIP_TRY(hipEventElapsedTime(&ms, ev[2 * j], ev[2 * j + 1]));
                 t_spmv += 1e-3 * ms;
