@@ -501,6 +501,22 @@ def test_deterministic_across_solves(cg):
     assert r1["iterations"] == r2["iterations"] and torch.equal(x1, x2)
 
 
+@pytest.mark.parametrize("stride", [1, 7])
+def test_spmv_event_sampling(cg, stride):
+    """cg_opts.profile = P times the SpMV of iterations 0, P, 2P, ...: the
+    count follows, the mean is positive, and the iterates are unchanged."""
+    p = I.poisson3d_problem(24)
+    b = dev(p.b)
+    with cg.Solver(p.A) as s:
+        s.set_opts(small_path=0)
+        x0, r0 = s.solve(b, tol=0.0, maxit=50)
+        s.set_opts(profile=stride, small_path=0)
+        x1, r1 = s.solve(b, tol=0.0, maxit=50)
+    assert r0["n_spmv"] == 0 and r1["n_spmv"] == (50 + stride - 1) // stride
+    assert r1["t_spmv"] > 0.0
+    assert torch.equal(x0, x1)
+
+
 def test_full_size_poisson3d_256(cg):
     """Full 256^3 size in the benchmark's launch configuration: SpMV against
     the oracle on every row; a fixed-work solve checked by properties that
