@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <utility>
 #include <new>
 #include <vector>
 
@@ -97,13 +98,25 @@ void transpose(int32_t n, const int32_t *rp, const int32_t *ci, const double *va
             T.ci[p] = i;
             src[p] = k;
         }
-    // rows of the result by ascending column (insertion sort: short rows)
+    // rows of the result by ascending column: insertion sort for short rows,
+    // a comparison sort for long ones (a dense column of the input)
 #pragma omp parallel for schedule(dynamic, 4096)
-    for (int32_t j = 0; j < n; ++j)
-        for (int32_t a = T.rp[j] + 1; a < T.rp[j + 1]; ++a) {
+    for (int32_t j = 0; j < n; ++j) {
+        const int32_t r0 = T.rp[j], r1 = T.rp[j + 1];
+        if (r1 - r0 > 32) {
+            std::vector<std::pair<int32_t, int32_t>> e((size_t)(r1 - r0));
+            for (int32_t a = r0; a < r1; ++a) e[(size_t)(a - r0)] = {T.ci[a], src[a]};
+            std::sort(e.begin(), e.end());
+            for (int32_t a = r0; a < r1; ++a) {
+                T.ci[a] = e[(size_t)(a - r0)].first;
+                src[a] = e[(size_t)(a - r0)].second;
+            }
+            continue;
+        }
+        for (int32_t a = r0 + 1; a < r1; ++a) {
             const int32_t c = T.ci[a], sk = src[a];
             int32_t b = a - 1;
-            while (b >= T.rp[j] && T.ci[b] > c) {
+            while (b >= r0 && T.ci[b] > c) {
                 T.ci[b + 1] = T.ci[b];
                 src[b + 1] = src[b];
                 --b;
@@ -111,6 +124,7 @@ void transpose(int32_t n, const int32_t *rp, const int32_t *ci, const double *va
             T.ci[b + 1] = c;
             src[b + 1] = sk;
         }
+    }
 #pragma omp parallel for schedule(static)
     for (int64_t p = 0; p < nnz; ++p) {
         if (val) T.val[p] = val[src[p]];
