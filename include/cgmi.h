@@ -205,6 +205,13 @@ int cg_solve(cg_handle *h, const double *b, double *x, double tol, int32_t maxit
 int cg_slice_info(const cg_handle *h, int32_t *rows_gpu, int64_t *nnz_gpu);
 int cg_read_slice(const cg_handle *h, int32_t *row_ptr, int32_t *col_idx, double *val);
 
+/* dst = src over n float64 values on the current device (device pointers,
+ * any alignment, must not overlap): a plain streaming copy, the achievable
+ * HBM bandwidth the SpMV's rate is reported against next to the
+ * specification.  Queued on hip_stream (a hipStream_t; NULL = null stream).
+ * CG_EINVAL for NULL pointers with n > 0 or n < 0. */
+int cg_hbm_copy(const double *src, double *dst, int64_t n, void *hip_stream);
+
 /* Message for the last error on this thread ("" if none). */
 const char *cg_last_error(void);
 

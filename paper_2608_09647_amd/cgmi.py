@@ -24,7 +24,7 @@ EXCHANGE_WHOLE, EXCHANGE_HALO, EXCHANGE_MAPPED, EXCHANGE_MANAGED = 0, 1, 2, 3
 # Every symbol the public header declares (checked by the tests).
 EXPORTED = ["cg_create", "cg_destroy", "cg_set_stream", "cg_default_opts", "cg_set_opts",
             "cg_get_opts", "cg_spmv", "cg_spmv_f32", "cg_solve", "cg_slice_info", "cg_read_slice",
-            "cg_last_error"]
+            "cg_hbm_copy", "cg_last_error"]
 # include/cgmi_fsai.h
 EXPORTED_FSAI = ["cg_fsai_setup", "cg_set_fsai", "cg_fsai_classic", "cg_fsai_factor_info", "cg_fsai_read_factor",
                  "cg_fsai_trainer_create", "cg_fsai_trainer_destroy", "cg_fsai_loss_grad",
@@ -135,6 +135,8 @@ def lib() -> ctypes.CDLL:
         L.cg_read_slice.restype = ctypes.c_int
         L.cg_last_error.argtypes = []
         L.cg_last_error.restype = ctypes.c_char_p
+        L.cg_hbm_copy.argtypes = [_vp, _vp, ctypes.c_int64, _vp]
+        L.cg_hbm_copy.restype = ctypes.c_int
         i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
         L.cg_fsai_setup.argtypes = [_vp, _vp]
         L.cg_set_fsai.argtypes = [_vp, i64, _vp, _vp, _vp]
@@ -492,6 +494,19 @@ class Batch:
         for i in range(flat.size):
             flat[i] = (res[i].status, res[i].iterations, res[i].rel_res_recur, res[i].rel_res_true)
         return X, out, st.as_dict(), code
+
+
+def hbm_copy(src, dst, stream=None) -> None:
+    """dst[:] = src[:] with the library's streaming copy kernel (float64
+    device tensors of equal length, contiguous); queued on `stream` (a
+    torch.cuda.Stream, default: torch's current stream)."""
+    n = src.numel()
+    if dst.numel() != n:
+        raise ValueError("src and dst must have the same length")
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    _check(lib().cg_hbm_copy(_dev_f64(src.view(-1), n, "src"), _dev_f64(dst.view(-1), n, "dst"), n,
+                             ctypes.c_void_p(stream.cuda_stream)))
 
 
 def read_matrix_market(path: str, threads: int = 0):

@@ -25,6 +25,7 @@
 
 #include "../../include/cgmi.h"
 #include "cgmi_host.h"
+#include "util_internal.h"
 #include "cgmi_internal.h"
 
 using namespace cgmi;
@@ -1040,6 +1041,18 @@ extern "C" int cg_solve(cg_handle *h, const double *b, double *x, double tol, in
     }
     if (rc == CG_EBREAKDOWN && !*error_message()) fail(CG_EBREAKDOWN, "breakdown: p^T q <= 0 or not finite");
     return rc;
+}
+
+extern "C" int cg_hbm_copy(const double *src, double *dst, int64_t n, void *hip_stream) {
+    clear_error();
+    if (n < 0) return fail(CG_EINVAL, "n must be >= 0");
+    if (n == 0) return CG_OK;
+    if (!src || !dst) return fail(CG_EINVAL, "src/dst is NULL");
+    int dev = 0, cus = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    HIP_TRY(launch_stream_copy(src, dst, n, std::max(8, cus * 16), static_cast<hipStream_t>(hip_stream)));
+    return CG_OK;
 }
 
 extern "C" int cg_spmv(cg_handle *h, const double *x, double *y) {

@@ -1,0 +1,13 @@
+// util_internal.h -- launcher of the streaming copy (kernels_util.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cgmi {
+
+// dst = src over n doubles (a plain streaming copy: the achievable-bandwidth
+// reference); any alignment, 16-byte pairs when both are aligned.
+hipError_t launch_stream_copy(const double *src, double *dst, int64_t n, int grid, hipStream_t s);
+
+}  // namespace cgmi

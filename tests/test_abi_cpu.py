@@ -146,3 +146,10 @@ def test_sampling_is_distinct():
     assert sys.size == 2 and len(set(sys.tolist())) == 2 and rows.shape == (2, 40)
     for s, r in zip(sys, rows):
         assert len(set(r.tolist())) == 40 and r.max() < [100, 50, 70][s]
+
+
+def test_hbm_copy_rejects_bad_arguments_before_any_device_call(cg):
+    L = cg.lib()
+    assert L.cg_hbm_copy(None, None, 0, None) == cg.CG_OK
+    assert L.cg_hbm_copy(None, None, 5, None) == cg.CG_EINVAL
+    assert L.cg_hbm_copy(None, None, -1, None) == cg.CG_EINVAL

@@ -501,6 +501,18 @@ def test_deterministic_across_solves(cg):
     assert r1["iterations"] == r2["iterations"] and torch.equal(x1, x2)
 
 
+@pytest.mark.parametrize("n", [1, 2, 1001, 1 << 20])
+@pytest.mark.parametrize("offset", [0, 1])
+def test_hbm_copy(cg, n, offset):
+    """The library's streaming copy: exact for any length and alignment
+    (offset 1: neither pointer 16-byte aligned)."""
+    src = torch.rand(n + offset, dtype=torch.float64, device="cuda")[offset:]
+    dst = torch.full((n + offset,), -1.0, dtype=torch.float64, device="cuda")[offset:]
+    cg.hbm_copy(src, dst)
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)
+
+
 @pytest.mark.parametrize("stride", [1, 7])
 def test_spmv_event_sampling(cg, stride):
     """cg_opts.profile = P times the SpMV of iterations 0, P, 2P, ...: the
