@@ -146,7 +146,7 @@ static void free_device(cg_handle *h) {
     dm_free(h->GT);
     hipFree(h->d_t); hipFree(h->d_z); hipFree(h->d_r2);
     hipFree(h->d_r32); hipFree(h->d_p32); hipFree(h->d_q32);
-    hipFree(h->d_pbuf); hipFree(h->d_x); hipFree(h->d_r); hipFree(h->d_q);
+    hipFree(h->d_pbuf); hipFree(h->d_p2); hipFree(h->d_x); hipFree(h->d_r); hipFree(h->d_q);
     hipFree(h->d_part_setup); hipFree(h->d_part_pq); hipFree(h->d_part_rr); hipFree(h->d_part_rz);
     hipFree(h->d_state);
     hipFree(h->d_halo_d2h); hipFree(h->d_halo_h2d); hipFree(h->d_pack_d2h); hipFree(h->d_pack_h2d);
@@ -533,6 +533,14 @@ static int solve_gpu_only(cg_handle *h, const double *b, double *x, double tol, 
         }
         const int P = h->opts.profile;   // events around the SpMV of every P-th iteration
         auto sampled = [P](int32_t it) { return P > 0 && it % P == 0; };
+        // x updated every other iteration from two p buffers (not with p in
+        // shared host memory, whose one buffer the other side reads)
+        const bool two_buf = !h->shared_p();
+        if (two_buf && !h->d_p2) {
+            const hipError_t e = dmalloc(&h->d_p2, (size_t)n + 2);
+            if (e != hipSuccess) return fail(CG_ENOMEM, "second p buffer: %s", hipGetErrorString(e));
+        }
+        double *const pbuf[2] = {h->d_p, h->d_p2};
         int32_t k = 0;
         bool running = true;
         while (running) {
@@ -541,12 +549,20 @@ static int solve_gpu_only(cg_handle *h, const double *b, double *x, double tol, 
             for (int32_t j = 0; j < chunk; ++j) {
                 const int32_t kk = k + j;
                 if (sampled(kk)) HIP_TRY(hipEventRecord(ev[2 * j], st));
-                HIP_TRY(launch_spmv(h->A.dev(), h->A.sched, Gs, h->d_p, h->d_q, h->d_p, nullptr, nullptr,
+                double *p_k = two_buf ? pbuf[kk & 1] : h->d_p;
+                HIP_TRY(launch_spmv(h->A.dev(), h->A.sched, Gs, p_k, h->d_q, p_k, nullptr, nullptr,
                                     h->d_part_pq, setup_rr, setup_bb, h->d_state, kSpmvDot, kk == 0, st));
                 if (sampled(kk)) HIP_TRY(hipEventRecord(ev[2 * j + 1], st));
                 if (maxit == 0) break;
-                HIP_TRY(launch_update_r(n, Gv, h->d_r, h->d_q, h->d_part_rr, pq, h->d_state, kk, st));
-                HIP_TRY(launch_update_px(n, Gv, h->d_x, h->d_r, h->d_p, rr, h->d_state, kk, st));
+                if (two_buf) {
+                    double *pc = pbuf[kk & 1], *po = pbuf[(kk + 1) & 1];
+                    HIP_TRY(launch_update_r_x(n, Gv, h->d_r, h->d_q, h->d_part_rr, pq, h->d_state, kk, h->d_x,
+                                              po, st));
+                    HIP_TRY(launch_update_pxb(n, Gv, h->d_x, h->d_r, pc, po, rr, h->d_state, kk, st));
+                } else {
+                    HIP_TRY(launch_update_r(n, Gv, h->d_r, h->d_q, h->d_part_rr, pq, h->d_state, kk, st));
+                    HIP_TRY(launch_update_px(n, Gv, h->d_x, h->d_r, h->d_p, rr, h->d_state, kk, st));
+                }
             }
             const int32_t it0 = k;
             k += chunk;

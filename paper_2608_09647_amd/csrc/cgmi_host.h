@@ -111,6 +111,8 @@ struct cg_handle {
     // device vectors
     double *d_pbuf = nullptr;  // allocation behind d_p
     double *d_p = nullptr;     // full length n, d_p + rb is 16-byte aligned
+    double *d_p2 = nullptr;    // GPU-only float64: the second p buffer of the
+                               // two-iteration x update (allocated on first use)
     double *d_x = nullptr, *d_r = nullptr, *d_q = nullptr;  // m each
     double *d_part_setup = nullptr;  // 2 x grid: r^T r, b^T b of the residual kernel
     double *d_part_pq = nullptr;

@@ -34,6 +34,7 @@ struct DevState {
     int32_t done;      // 0 running, 1 converged, 2 iteration limit, 3 breakdown
     int32_t nrefine;   // mixed precision: float64 residuals formed
     double rr_true;    // single-workgroup solve: ||b - A x||^2 of the returned x
+    double alpha_prev; // two-iteration x update: alpha of the last even iteration
     int32_t r_iter;    // device-coefficient paths: k + 1 once r of iteration k is
                        // updated (the deferred x update of iteration k runs only
                        // then; it never reads `done`, which its own workgroup 0
@@ -243,6 +244,16 @@ hipError_t launch_update_r(int32_t m, int grid, double *r, const double *q, doub
                            DevState *st, int32_t k, hipStream_t s);
 hipError_t launch_update_px(int32_t m, int grid, double *x, const double *r, double *p, Partials rr,
                             DevState *st, int32_t k, hipStream_t s);
+// The same with x updated every other iteration from two p buffers: p_k in
+// p_cur, p_{k+1} written to p_oth.  Even k: p update only (x owes alpha_k
+// p_k; on a stop x takes it at once); odd k: x += alpha_{k-1} p_{k-1}
+// (p_oth) then alpha_k p_k, the same fmas in the same order as one update
+// per iteration.  launch_update_r_x: as launch_update_r, and on a breakdown
+// at an odd k it adds the owed alpha_{k-1} p_prev to x.
+hipError_t launch_update_r_x(int32_t m, int grid, double *r, const double *q, double *out, Partials pq,
+                             DevState *st, int32_t k, double *x, const double *p_prev, hipStream_t s);
+hipError_t launch_update_pxb(int32_t m, int grid, double *x, const double *r, const double *p_cur,
+                             double *p_oth, Partials rr, DevState *st, int32_t k, hipStream_t s);
 hipError_t launch_update_p_pcg(int32_t m, int grid, const double *z, double *p, double *x, Partials rr,
                                Partials rz, Partials bb, DevState *st, int first, int32_t k,
                                hipStream_t s);

@@ -1116,7 +1116,9 @@ __global__ __launch_bounds__(kBlock) void k_update_p(int32_t m, const double *__
 __global__ __launch_bounds__(kBlock) void k_update_r(int32_t m, double *__restrict__ r,
                                                      const double *__restrict__ q,
                                                      double *__restrict__ out, Partials pq_in,
-                                                     DevState *__restrict__ st, int32_t k) {
+                                                     DevState *__restrict__ st, int32_t k,
+                                                     double *__restrict__ x,
+                                                     const double *__restrict__ p_prev) {
     __shared__ double sh[kWavesPerBlock];
     __shared__ double bc;
     if (st->done) return;
@@ -1126,6 +1128,11 @@ __global__ __launch_bounds__(kBlock) void k_update_r(int32_t m, double *__restri
             st->pq = pq;
             st->iter = k;
             st->done = kDoneBreakdown;
+        }
+        if (x) {   // two-iteration x update: x still owes alpha_{k-1} p_{k-1}
+            const double ap = st->alpha_prev;
+            for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += (int64_t)gridDim.x * kBlock)
+                x[i] = fma(ap, p_prev[i], x[i]);
         }
         return;
     }
@@ -1203,6 +1210,71 @@ __global__ __launch_bounds__(kBlock) void k_update_px(int32_t m, double *__restr
         const double pv = p[m - 1];
         x[m - 1] = fma(alpha, pv, x[m - 1]);
         if (!stop) p[m - 1] = fma(beta, pv, r[m - 1]);
+    }
+}
+
+// k_update_px with x updated every other iteration (two p buffers, see the
+// launcher's declaration): at an odd k the two owed terms are added with
+// the same two fmas, in the same order, as by k_update_px at k-1 and k.
+__global__ __launch_bounds__(kBlock) void k_update_pxb(int32_t m, double *__restrict__ x,
+                                                       const double *__restrict__ r,
+                                                       const double *__restrict__ p_cur,
+                                                       double *__restrict__ p_oth, Partials rr_in,
+                                                       DevState *__restrict__ st, int32_t k) {
+    __shared__ double sh[kWavesPerBlock];
+    __shared__ double bc;
+    if (st->r_iter != k + 1) return;   // as in k_update_px
+    const double rr = reduce_partials(rr_in, sh, &bc);
+    const double rho_k = st->rho[k & 1];
+    const double alpha = rho_k / st->pq;
+    const double beta = rr / rho_k;
+    const double alpha_prev = st->alpha_prev;   // written at k - 1 (odd k only)
+    const bool conv = stop_test(rr, st->bb, st->tol);
+    const bool maxed = k + 1 >= st->maxit;
+    const bool stop = conv || maxed;
+    const bool odd = k & 1;
+    if (is_block0_thread0()) {
+        st->rho[(k + 1) & 1] = rr;
+        st->rr = rr;
+        st->iter = k + 1;
+        if (conv) st->done = kDoneConverged;
+        else if (maxed) st->done = kDoneMaxit;
+        if (!odd && !stop) st->alpha_prev = alpha;
+    }
+    const int64_t npair = m >> 1;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    double2 *x2 = reinterpret_cast<double2 *>(x);
+    const double2 *pc2 = reinterpret_cast<const double2 *>(p_cur);
+    double2 *po2 = reinterpret_cast<double2 *>(p_oth);
+    const double2 *r2 = reinterpret_cast<const double2 *>(r);
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < npair; i += stride) {
+        const double2 pc = pc2[i];
+        if (odd) {
+            const double2 po = po2[i];
+            double2 xv = x2[i];
+            xv.x = fma(alpha, pc.x, fma(alpha_prev, po.x, xv.x));
+            xv.y = fma(alpha, pc.y, fma(alpha_prev, po.y, xv.y));
+            x2[i] = xv;
+        } else if (stop) {
+            double2 xv = x2[i];
+            xv.x = fma(alpha, pc.x, xv.x);
+            xv.y = fma(alpha, pc.y, xv.y);
+            x2[i] = xv;
+        }
+        if (!stop) {
+            const double2 rv = r2[i];
+            double2 pn;
+            pn.x = fma(beta, pc.x, rv.x);
+            pn.y = fma(beta, pc.y, rv.y);
+            po2[i] = pn;
+        }
+    }
+    if ((m & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        const int32_t i = m - 1;
+        const double pc = p_cur[i];
+        if (odd) x[i] = fma(alpha, pc, fma(alpha_prev, p_oth[i], x[i]));
+        else if (stop) x[i] = fma(alpha, pc, x[i]);
+        if (!stop) p_oth[i] = fma(beta, pc, r[i]);
     }
 }
 
@@ -1585,7 +1657,24 @@ hipError_t launch_pcg_xr_gs(int32_t m, int grid, const int32_t *st_off, const in
 hipError_t launch_update_r(int32_t m, int grid, double *r, const double *q, double *out, Partials pq,
                            DevState *st, int32_t k, hipStream_t s) {
     if (m == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_update_r, dim3(grid), dim3(kBlock), 0, s, m, r, q, out, pq, st, k);
+    hipLaunchKernelGGL(k_update_r, dim3(grid), dim3(kBlock), 0, s, m, r, q, out, pq, st, k, nullptr,
+                       nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_r_x(int32_t m, int grid, double *r, const double *q, double *out, Partials pq,
+                             DevState *st, int32_t k, double *x, const double *p_prev, hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    if ((k & 1) && (!x || !p_prev)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_update_r, dim3(grid), dim3(kBlock), 0, s, m, r, q, out, pq, st, k,
+                       (k & 1) ? x : nullptr, (k & 1) ? p_prev : nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_pxb(int32_t m, int grid, double *x, const double *r, const double *p_cur,
+                             double *p_oth, Partials rr, DevState *st, int32_t k, hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_update_pxb, dim3(grid), dim3(kBlock), 0, s, m, x, r, p_cur, p_oth, rr, st, k);
     return hipGetLastError();
 }
 

@@ -493,6 +493,26 @@ def test_cg_edge_cases(cg, small_path):
         assert res["code"] == cg.CG_EBREAKDOWN
 
 
+@pytest.mark.parametrize("case", ["odd_step", "even_step"])
+def test_breakdown_keeps_x_of_the_last_full_iteration(cg, case):
+    """Indefinite block-diagonal systems whose p^T q turns non-positive at
+    iteration 1 (odd) or 2 (even): x holds every update before the breakdown
+    (with x updated every other iteration, the odd case flushes the owed
+    term), as the oracle's run."""
+    n = 4998
+    dv, bv = ([1.0, -1.0], [1.0, 0.5]) if case == "odd_step" else ([1.0, 3.0, -1.0], [1.0, 1.0, 0.05])
+    reps = n // len(dv)
+    d, b = np.tile(dv, reps), np.tile(bv, reps)
+    A = I.CSR(d.size, np.arange(d.size + 1, dtype=np.int32), np.arange(d.size, dtype=np.int32), d)
+    ref = oracle.cg(A, b, tol=1e-12, maxit=100)
+    assert ref["status"] == cg.CG_EBREAKDOWN and ref["iterations"] == (1 if case == "odd_step" else 2)
+    with cg.Solver(A) as s:
+        s.set_opts(small_path=0)
+        x, res = s.solve(dev(b), tol=1e-12, maxit=100)
+    assert res["code"] == cg.CG_EBREAKDOWN and res["iterations"] == ref["iterations"]
+    assert np.linalg.norm(host(x) - ref["x"]) <= 1e-13 * np.linalg.norm(ref["x"])
+
+
 def test_deterministic_across_solves(cg):
     p = I.random_spd_problem(20000, seed=5)
     with cg.Solver(p.A) as s:
