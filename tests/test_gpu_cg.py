@@ -754,9 +754,10 @@ def test_stencil_slices_fall_back_on_many_offsets(cg):
 
 @pytest.mark.parametrize("shape", [(13, 11, 7), (9, 9, 9), (64, 2, 1), (65, 1, 1), (5, 5, 5), (8, 8, 3), (12, 12, 1)])
 def test_stencil_two_rows_per_lane_edges(cg, shape):
-    """Odd row counts (the last row alone), odd slice counts (a pair with one
-    slice) and single-slice systems: SpMV bit-exact, dot product and a solve
-    against the oracle."""
+    """Odd row counts (the last row alone, in the SpMV and in the x/p update
+    that works on pairs of entries), odd slice counts (a pair with one slice)
+    and single-slice systems: SpMV bit-exact, dot product and a multi-kernel
+    solve against the oracle."""
     A = I.poisson3d(*shape)
     assert stencil_applies(A)
     x = np.random.default_rng(17).uniform(-1, 1, A.n)
