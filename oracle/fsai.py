@@ -236,6 +236,29 @@ def network_loss(theta, A, rows, round_bf16: bool = True):
     return L, mlp_backward(theta, F, dO, round_bf16)
 
 
+def network_loss_multi(theta, systems, rows_list, round_bf16: bool = True):
+    """The training loss over several systems: the mean over every sampled
+    row of all systems together, (1/|S|) sum over S = S_1 + ... + S_k.  The
+    signal dL/do of each row therefore carries the factor 1/|S|, and the
+    backward pass runs once over all rows, so its bfloat16 rounding points see
+    that signal (rounding each system's own mean and averaging would round
+    differently).  Returns L and dL/dtheta."""
+    total = sum(np.asarray(r).size for r in rows_list)
+    F_all, dO_all, L = [], [], 0.0
+    for A, rows in zip(systems, rows_list):
+        rows = np.asarray(rows)
+        F = features(A)
+        o, _ = mlp_forward(theta, F, round_bf16)
+        Ahat, _ = scaled_operator(A)
+        Gt = g_tilde(A, o)
+        Lk, dG = loss_and_grad(Gt, Ahat, rows)          # mean over this system's rows
+        w = rows.size / total
+        L += w * Lk
+        F_all.append(F)
+        dO_all.append(w * grad_outputs(A, o, dG))
+    return L, mlp_backward(theta, np.concatenate(F_all), np.concatenate(dO_all), round_bf16)
+
+
 def adam_step(theta, m, v, g, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
     """One Adam update (step number t >= 1); returns (theta, m, v)."""
     m = beta1 * m + (1 - beta1) * g

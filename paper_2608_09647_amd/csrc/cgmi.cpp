@@ -556,8 +556,7 @@ static int solve_gpu_only(cg_handle *h, const double *b, double *x, double tol, 
                 if (maxit == 0) break;
                 if (two_buf) {
                     double *pc = pbuf[kk & 1], *po = pbuf[(kk + 1) & 1];
-                    HIP_TRY(launch_update_r_x(n, Gv, h->d_r, h->d_q, h->d_part_rr, pq, h->d_state, kk, h->d_x,
-                                              po, st));
+                    HIP_TRY(launch_update_r(n, Gv, h->d_r, h->d_q, h->d_part_rr, pq, h->d_state, kk, st));
                     HIP_TRY(launch_update_pxb(n, Gv, h->d_x, h->d_r, pc, po, rr, h->d_state, kk, st));
                 } else {
                     HIP_TRY(launch_update_r(n, Gv, h->d_r, h->d_q, h->d_part_rr, pq, h->d_state, kk, st));

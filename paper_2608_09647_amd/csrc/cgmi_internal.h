@@ -248,10 +248,8 @@ hipError_t launch_update_px(int32_t m, int grid, double *x, const double *r, dou
 // p_cur, p_{k+1} written to p_oth.  Even k: p update only (x owes alpha_k
 // p_k; on a stop x takes it at once); odd k: x += alpha_{k-1} p_{k-1}
 // (p_oth) then alpha_k p_k, the same fmas in the same order as one update
-// per iteration.  launch_update_r_x: as launch_update_r, and on a breakdown
-// at an odd k it adds the owed alpha_{k-1} p_prev to x.
-hipError_t launch_update_r_x(int32_t m, int grid, double *r, const double *q, double *out, Partials pq,
-                             DevState *st, int32_t k, double *x, const double *p_prev, hipStream_t s);
+// per iteration; after a breakdown in the r update of an odd k it adds the
+// owed alpha_{k-1} p_{k-1} to x instead.
 hipError_t launch_update_pxb(int32_t m, int grid, double *x, const double *r, const double *p_cur,
                              double *p_oth, Partials rr, DevState *st, int32_t k, hipStream_t s);
 hipError_t launch_update_p_pcg(int32_t m, int grid, const double *z, double *p, double *x, Partials rr,

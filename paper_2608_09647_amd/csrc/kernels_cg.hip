@@ -1113,12 +1113,15 @@ __global__ __launch_bounds__(kBlock) void k_update_p(int32_t m, const double *__
 // x += alpha p with alpha recomputed from the same operands (bitwise the
 // same value), then p = r + beta p unless the solve stops.  The x/r kernel
 // no longer reads p: one pass over p per iteration less.
+// On a breakdown only workgroup 0 acts (it records the state); a workgroup
+// that starts after that store sees `done` and returns, so no work that
+// every workgroup must do may hang on this branch.  The x term owed by the
+// two-iteration update is added by k_update_pxb, which reads the recorded
+// state after this kernel has completed.
 __global__ __launch_bounds__(kBlock) void k_update_r(int32_t m, double *__restrict__ r,
                                                      const double *__restrict__ q,
                                                      double *__restrict__ out, Partials pq_in,
-                                                     DevState *__restrict__ st, int32_t k,
-                                                     double *__restrict__ x,
-                                                     const double *__restrict__ p_prev) {
+                                                     DevState *__restrict__ st, int32_t k) {
     __shared__ double sh[kWavesPerBlock];
     __shared__ double bc;
     if (st->done) return;
@@ -1128,11 +1131,6 @@ __global__ __launch_bounds__(kBlock) void k_update_r(int32_t m, double *__restri
             st->pq = pq;
             st->iter = k;
             st->done = kDoneBreakdown;
-        }
-        if (x) {   // two-iteration x update: x still owes alpha_{k-1} p_{k-1}
-            const double ap = st->alpha_prev;
-            for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += (int64_t)gridDim.x * kBlock)
-                x[i] = fma(ap, p_prev[i], x[i]);
         }
         return;
     }
@@ -1223,7 +1221,17 @@ __global__ __launch_bounds__(kBlock) void k_update_pxb(int32_t m, double *__rest
                                                        DevState *__restrict__ st, int32_t k) {
     __shared__ double sh[kWavesPerBlock];
     __shared__ double bc;
-    if (st->r_iter != k + 1) return;   // as in k_update_px
+    if (st->r_iter != k + 1) {   // r of this iteration not updated (see k_update_px)
+        // A breakdown in this iteration's r update at an odd k: x still owes
+        // alpha_{k-1} p_{k-1} (in p_oth).  Both fields were written by the
+        // previous kernel, so every workgroup reads the same values.
+        if ((k & 1) && st->done == kDoneBreakdown && st->iter == k) {
+            const double ap = st->alpha_prev;
+            for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += (int64_t)gridDim.x * kBlock)
+                x[i] = fma(ap, p_oth[i], x[i]);
+        }
+        return;
+    }
     const double rr = reduce_partials(rr_in, sh, &bc);
     const double rho_k = st->rho[k & 1];
     const double alpha = rho_k / st->pq;
@@ -1657,17 +1665,7 @@ hipError_t launch_pcg_xr_gs(int32_t m, int grid, const int32_t *st_off, const in
 hipError_t launch_update_r(int32_t m, int grid, double *r, const double *q, double *out, Partials pq,
                            DevState *st, int32_t k, hipStream_t s) {
     if (m == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_update_r, dim3(grid), dim3(kBlock), 0, s, m, r, q, out, pq, st, k, nullptr,
-                       nullptr);
-    return hipGetLastError();
-}
-
-hipError_t launch_update_r_x(int32_t m, int grid, double *r, const double *q, double *out, Partials pq,
-                             DevState *st, int32_t k, double *x, const double *p_prev, hipStream_t s) {
-    if (m == 0) return hipSuccess;
-    if ((k & 1) && (!x || !p_prev)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_update_r, dim3(grid), dim3(kBlock), 0, s, m, r, q, out, pq, st, k,
-                       (k & 1) ? x : nullptr, (k & 1) ? p_prev : nullptr);
+    hipLaunchKernelGGL(k_update_r, dim3(grid), dim3(kBlock), 0, s, m, r, q, out, pq, st, k);
     return hipGetLastError();
 }
 

@@ -82,6 +82,23 @@ def test_features_match_oracle(cg):
     tr.close()
 
 
+def assert_blockwise_close(got, ref, tag, rtol=1e-4):
+    """Every parameter block (W1, b1, W2, b2, W3, b3) element by element:
+    |got - ref| <= rtol * max |ref block|.  Both sides round the same operands
+    to bfloat16 at the same points; the kernel accumulates in float32 and the
+    oracle in float64, so entries differ by float32 accumulation error."""
+    k = 0
+    for name, shape in OF.SHAPES:
+        size = int(np.prod(shape))
+        gb, rb = got[k:k + size], ref[k:k + size]
+        scale = np.abs(rb).max()
+        err = np.abs(gb - rb).max()
+        print(f"[{tag}] {name}: max |diff| {err:.3e} of max |g| {scale:.3e}", flush=True)
+        assert err <= rtol * scale, (name, err, scale)
+        k += size
+    assert k == got.size == ref.size
+
+
 def test_forward_outputs_match_oracle(cg):
     A = field(40, 30, 5)
     th = theta_with_biases(1)
@@ -108,6 +125,7 @@ def test_loss_and_gradient_match_oracle(cg, seed):
     cos = float(grad @ g / (np.linalg.norm(grad) * np.linalg.norm(g)))
     print(f"[grad] loss {loss:.6e} ref {L:.6e} grad rel {rel:.3e} cos {cos:.6f}", flush=True)
     assert abs(loss - L) <= 1e-4 * L
+    assert_blockwise_close(grad, g, "grad")
     assert rel <= 1e-2 and cos >= 0.999
     # the unused outputs (E, N) get no gradient
     assert grad[5312 + 2] == 0 and grad[5312 + 4] == 0
@@ -121,13 +139,14 @@ def test_multi_system_loss_is_sample_weighted_mean(cg):
     rows = np.stack([rng.choice(A.n, 96, replace=False) for A in systems]).astype(np.int32)
     tr = cg.FsaiTrainer(systems, th)
     loss, grad = tr.loss_grad([0, 1, 2], rows)
-    Ls, gs = zip(*[OF.network_loss(th.astype(np.float64), A, r, round_bf16=True)
-                   for A, r in zip(systems, rows)])
-    L = float(np.mean(Ls))
-    g = np.mean(gs, axis=0)
+    # the mean over all sampled rows: one backward pass whose bfloat16
+    # rounding sees each row's signal with the factor 1/|S| of the whole sample
+    L, g = OF.network_loss_multi(th.astype(np.float64), systems, list(rows), round_bf16=True)
+    Ls = [OF.network_loss(th.astype(np.float64), A, r, round_bf16=True)[0] for A, r in zip(systems, rows)]
     rel = np.linalg.norm(grad - g) / np.linalg.norm(g)
     print(f"[multi] loss {loss:.6e} ref {L:.6e} grad rel {rel:.3e}", flush=True)
     assert abs(loss - L) <= 1e-4 * L and rel <= 1e-2
+    assert_blockwise_close(grad, g, "multi")
     # a subset of systems in another order gives the same as those systems alone
     loss2, _ = tr.loss_grad([2, 0], rows[[2, 0]])
     assert abs(loss2 - (Ls[2] + Ls[0]) / 2) <= 1e-4 * loss2

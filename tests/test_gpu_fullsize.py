@@ -1,7 +1,8 @@
 """Full-size parity in the configurations bench.py times: the random SPD
 system (n = 2M, column-blocked SpMV from the schedule table, float32 inner /
 float64 refined CG) and the 1024^2 diffusion system with a learned factor
-built on the device.  Outputs the oracle computes cheaply are compared in
+built on the device; the 256^3 Poisson system split in half between the GPU
+and the host.  Outputs the oracle computes cheaply are compared in
 full (SpMV, the factor, fixed-work iterates); to-tolerance solves are checked
 through properties that hold at any size (the recomputed true residual)."""
 import numpy as np
@@ -149,3 +150,60 @@ def test_full_size_diffusion_1024_learned_factor(cg):
     dx = np.linalg.norm(x30 - ref["x"]) / np.linalg.norm(ref["x"])
     print(f"[full] 30 PCG iterations: GPU vs oracle {dx:.2e} (CPU spread {spread:.2e})", flush=True)
     assert dx <= max(1e-11, 4 * spread)
+
+
+def test_full_size_poisson3d_256_half_split(cg):
+    """256^3 Poisson with the GPU on rows [0, 8,388,608) and the host on the
+    rest (Section 3.2), p exchanged each iteration by whole segments and by
+    halo (Section 3.4): the device slice read back bit for bit, the split
+    SpMV equal to the oracle's on every row, and five fixed iterations
+    against the oracle's; whole and halo exchange give the same bits."""
+    p = I.poisson3d_problem(256)
+    A = p.A
+    rb, re = 0, oracle.split_rows(A.n, 0.5)
+    assert re == 8_388_608
+    x = np.random.default_rng(2).uniform(-1, 1, A.n)
+    ref = oracle.spmv(A, x)
+    orp, oci, ova = oracle.row_slice(A, rb, re)
+    assert orp[-1] == 58_523_648
+    runs = {}
+    for exchange in (0, 1):   # whole segments, halo
+        print(f"[split256] rows [{rb},{re}) exchange={exchange}", flush=True)
+        with cg.Solver(A, rb, re) as s:
+            rows, nnz = s.slice_info()
+            assert rows == re - rb and nnz == 58_523_648
+            if exchange == 0:
+                rp, ci, va = s.read_slice()
+                assert np.array_equal(rp, orp) and np.array_equal(ci, oci) and np.array_equal(va, ova)
+                del rp, ci, va
+            s.set_opts(exchange=exchange)
+            y = host(s.spmv(dev(x)))
+            # GPU stencil slices and host rows both sum in CSR order: equal bits
+            assert np.array_equal(y, ref)
+            del y
+            xg, res = s.solve(dev(p.b), tol=0.0, maxit=5)
+            runs[exchange] = host(xg)
+            assert res["iterations"] == 5 and res["code"] == cg.CG_MAXIT
+            assert res["rows_gpu"] == re - rb and res["rows_cpu"] == A.n - (re - rb)
+            assert res["nnz_gpu"] == 58_523_648 and res["nnz_cpu"] == A.nnz - 58_523_648
+            assert res["t_d2h"] > 0.0 and res["t_h2d"] > 0.0
+            print(f"[split256] exchange={exchange}: t_solve {res['t_solve']:.3f} s, t_gpu {res['t_gpu']:.3f}, "
+                  f"t_cpu {res['t_cpu']:.3f}, t_d2h {res['t_d2h']:.4f}, t_h2d {res['t_h2d']:.4f}", flush=True)
+    del orp, oci, ova, ref
+    assert np.array_equal(runs[0], runs[1])
+    ora = oracle.cg(A, p.b, tol=0.0, maxit=5)
+    # a second correct float64 CG (scipy products, BLAS dots) sets the bar
+    S = A.scipy()
+    xa, r, rho = np.zeros(A.n), p.b.copy(), p.b @ p.b
+    pa = r.copy()
+    for _ in range(5):
+        qv = S @ pa
+        alpha = rho / (pa @ qv)
+        xa += alpha * pa
+        r -= alpha * qv
+        rho, rho_old = r @ r, rho
+        pa = r + (rho / rho_old) * pa
+    spread = np.linalg.norm(xa - ora["x"]) / np.linalg.norm(ora["x"])
+    dx = np.linalg.norm(runs[0] - ora["x"]) / np.linalg.norm(ora["x"])
+    print(f"[split256] 5 CG iterations: split vs oracle {dx:.2e} (CPU spread {spread:.2e})", flush=True)
+    assert dx <= max(1e-13, 4 * spread)

@@ -88,6 +88,83 @@ def test_spmv_thread_count_does_not_change_bits():
     assert np.array_equal(y1, y2)
 
 
+# float32 SpMV (the inner product of the mixed-precision solve).  Each pin is
+# also run against a copy of the routine with a planted slip, which it must
+# reject, so the pin is known to see that kind of mistake.
+
+U32 = 2.0 ** -24    # unit roundoff of float32
+
+
+def _spmv_f32_f64_accumulator(A, x32):
+    """Planted slip: float32 operands, but products and sums in float64."""
+    v = A.val.astype(np.float32).astype(np.float64)
+    x = np.asarray(x32, dtype=np.float32).astype(np.float64)
+    y = np.empty(A.n, dtype=np.float32)
+    for i in range(A.n):
+        s = 0.0
+        for k in range(A.row_ptr[i], A.row_ptr[i + 1]):
+            s += v[k] * x[A.col[k]]
+        y[i] = np.float32(s)
+    return y
+
+
+def _f32_rounding_rows():
+    """Two rows whose float32 results follow by hand from IEEE rounding.
+    Row 0: 1 + 2^-24 + 2^-24 with x = 1; in float32 each 2^-24 is half an
+    ulp of 1 and is lost (ties to even), so the sum is 1; summed in float64
+    and rounded at the end it would be 1 + 2^-23.
+    Row 1: -(1 + 2^-11) * 1 + (1 + 2^-12)^2; the exact second product
+    1 + 2^-11 + 2^-24 rounds (tie, to even) to 1 + 2^-11 in float32, so the
+    row is exactly 0; with a float64 (or fused) product the 2^-24 survives."""
+    a = 1.0 + 2.0 ** -12                            # exact in float32
+    x = np.array([1.0, a, 1.0, 1.0], dtype=np.float32)
+    rp = np.array([0, 3, 5, 5, 5], dtype=np.int32)
+    ci = np.array([0, 2, 3, 0, 1], dtype=np.int32)
+    val = np.array([1.0, U32, U32, -(1.0 + 2.0 ** -11), a])
+    A = I.CSR(4, rp, ci, val)
+    return A, x, np.array([1.0, 0.0, 0.0, 0.0], dtype=np.float32)
+
+
+def test_spmv_f32_rounds_every_product_and_sum_in_float32():
+    A, x, want = _f32_rounding_rows()
+    assert np.array_equal(oracle.spmv_f32(A, x), want)
+    assert oracle.spmv_f32(A, x).dtype == np.float32
+    assert not np.array_equal(_spmv_f32_f64_accumulator(A, x), want)
+
+
+def test_spmv_f32_integer_inputs_are_exact():
+    """Poisson 6/-1 with integer x in [-1000, 1000]: every partial sum is an
+    integer below 2^24, exact in float32 in any order."""
+    A = I.poisson3d(8)
+    xi = np.random.default_rng(4).integers(-1000, 1001, size=A.n)
+    S = sp.csr_matrix((A.val.astype(np.int64), A.col, A.row_ptr), shape=(A.n, A.n))
+    exact = (S @ xi).astype(np.float32)
+    assert np.array_equal(oracle.spmv_f32(A, xi.astype(np.float32)), exact)
+
+
+def test_spmv_f32_within_float32_sum_order_bound():
+    """Against a float64 dense matvec of the float32-rounded operands: the
+    error of a row of L rounded products summed in float32 is at most
+    gamma_L = L u / (1 - L u) times sum |a_ik x_k| (u = 2^-24); and it is far
+    above float64's, so a float64 accumulator would show."""
+    rng = np.random.default_rng(5)
+    n = 200
+    M = rng.standard_normal((n, n)) * (rng.random((n, n)) < 0.3)
+    A = csr_from_dense(M)
+    M32 = M.astype(np.float32).astype(np.float64)
+    x32 = rng.standard_normal(n).astype(np.float32)
+    ref = M32 @ x32.astype(np.float64)
+    L = int(np.diff(A.row_ptr).max())
+    gam = L * U32 / (1 - L * U32)
+    bound = gam * (np.abs(M32) @ np.abs(x32.astype(np.float64)))
+    y = oracle.spmv_f32(A, x32).astype(np.float64)
+    assert np.all(np.abs(y - ref) <= bound)
+    # float32 rounding really happens: the error is well above float64's bound
+    assert np.abs(y - ref).max() > 1e3 * L * EPS * np.abs(ref).max()
+    assert np.abs(_spmv_f32_f64_accumulator(A, x32).astype(np.float64) - ref).max() <= \
+        U32 * np.abs(ref).max()
+
+
 def test_dot_small_exact():
     assert oracle.dot(np.array([1.0, 2.0, 3.0]), np.array([4.0, -5.0, 6.0])) == 12.0
     assert oracle.dot(np.zeros(0), np.zeros(0)) == 0.0

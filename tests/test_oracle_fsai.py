@@ -171,11 +171,71 @@ def test_whole_chain_gradient_matches_finite_differences():
         assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(fd))
 
 
+def test_multi_system_loss_weights_and_gradient():
+    """The loss over several systems is the mean over all their sampled rows:
+    with unequal row counts its finite differences match the gradient; one
+    system reduces to network_loss bit for bit; a system listed twice with
+    the same rows gives the single system's loss and gradient (weights 1/2)."""
+    systems = [I.diffusion2d(I.log_normal_field(5, 5, [5, 0])),
+               I.diffusion2d(I.log_normal_field(6, 4, [6, 0]))]
+    rows = [np.array([0, 6, 12, 18, 24]), np.array([1, 9, 22])]
+    rng = np.random.default_rng(9)
+    th = fsai.glorot_init(rng)
+    L, g = fsai.network_loss_multi(th, systems, rows, round_bf16=False)
+    Ls = [fsai.network_loss(th, A, r, round_bf16=False)[0] for A, r in zip(systems, rows)]
+    assert abs(L - (5 * Ls[0] + 3 * Ls[1]) / 8) <= 1e-14 * L
+    h = 1e-6
+    for k in rng.choice(fsai.N_PARAMS, 30, replace=False):
+        tp, tm = th.copy(), th.copy()
+        tp[k] += h
+        tm[k] -= h
+        fd = (fsai.network_loss_multi(tp, systems, rows, False)[0]
+              - fsai.network_loss_multi(tm, systems, rows, False)[0]) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(fd))
+    for rb in (False, True):
+        L1, g1 = fsai.network_loss(th, systems[0], rows[0], rb)
+        Lm, gm = fsai.network_loss_multi(th, systems[:1], rows[:1], rb)
+        assert Lm == L1 and np.array_equal(gm, g1)
+        L2, g2 = fsai.network_loss_multi(th, [systems[0]] * 2, [rows[0]] * 2, rb)
+        assert abs(L2 - L1) <= 1e-15 * L1 and np.allclose(g2, g1, rtol=1e-13, atol=1e-16)
+
+
 def test_adam_first_step_closed_form():
     g = np.array([0.5, -2.0, 1e-12, 0.0])
     th, m, v = fsai.adam_step(np.zeros(4), np.zeros(4), np.zeros(4), g, t=1, lr=1e-3)
     # m_hat = g, v_hat = g^2: the step is lr * g / (|g| + eps)
     assert np.allclose(th, -1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0)
+
+
+def _adam_bias_slip(theta, m, v, g, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """Planted slip: bias correction with beta^1 instead of beta^t."""
+    m = beta1 * m + (1 - beta1) * g
+    v = beta2 * v + (1 - beta2) * g * g
+    return theta - lr * (m / (1 - beta1)) / (np.sqrt(v / (1 - beta2)) + eps), m, v
+
+
+def _adam_constant_gradient_ok(step):
+    """With the same gradient g at every step, the bias-corrected moments are
+    exactly g and g^2 at every t (m_t = (1 - beta1^t) g, v_t = (1 - beta2^t)
+    g^2), so step t moves theta by -lr g / (|g| + eps): after t steps theta
+    = theta_0 - t lr g / (|g| + eps)."""
+    g = np.array([0.5, -2.0, 3e-3, 1e-12, 0.0])
+    th0 = np.array([0.1, -0.2, 0.3, 0.0, 1.0])
+    lr = 1e-3
+    th, m, v = th0.copy(), np.zeros(5), np.zeros(5)
+    ok = True
+    for t in range(1, 6):
+        th, m, v = step(th, m, v, g, t, lr=lr)
+        want = th0 - t * lr * g / (np.abs(g) + 1e-8)
+        ok &= bool(np.allclose(th, want, rtol=0, atol=1e-12 * t))
+        ok &= bool(np.allclose(m, (1 - 0.9 ** t) * g, rtol=1e-13, atol=0))
+        ok &= bool(np.allclose(v, (1 - 0.999 ** t) * g * g, rtol=1e-12, atol=0))
+    return ok
+
+
+def test_adam_constant_gradient_closed_form_steps_1_to_5():
+    assert _adam_constant_gradient_ok(fsai.adam_step)
+    assert not _adam_constant_gradient_ok(_adam_bias_slip)
 
 
 def test_classic_fsai_unit_diagonal_and_gain():
