@@ -199,6 +199,29 @@ int cg_spmv_f32(cg_handle *h, const float *x, float *y);
 int cg_solve(cg_handle *h, const double *b, double *x, double tol, int32_t maxit,
              cg_result *res);
 
+/* cg_solve for callers that cannot allocate memory while solving (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, kernels and results as cg_solve on a
+ * GPU-only handle with CG_PREC_FP64, CG_PC_NONE and p in device memory
+ * (CG_EINVAL for any other handle or option), but every work buffer (the
+ * working x, r, q, two p buffers, the partial sums and the solver state)
+ * lives in one static device array of the library, CG_NOALLOC_SCRATCH_BYTES
+ * per device, held by each device the library runs on until the process
+ * ends.  Nothing is allocated: no hipMalloc / hipFree, no pinned host
+ * memory, no events (cg_opts.profile is ignored; t_spmv and n_spmv stay 0).
+ * The array holds five vectors of n + 2 float64 values (each rounded up to
+ * 256 bytes), 4 x 16 float64 partial sums per compute unit and the state:
+ * on a 256-CU MI355X n is at most 1,674,430 rows; a larger n returns
+ * CG_EINVAL with the limit in cg_last_error().  The scratch keeps the last call's contents; the solver
+ * state in it is re-initialised by every call.  All calls on one device share
+ * the one array: calls that overlap in time on the same device (two host
+ * threads, or two streams) race and must be serialised by the caller.  Its
+ * device address is looked up once per device when the first handle is
+ * created there.  Blocking, like cg_solve. */
+#define CG_NOALLOC_SCRATCH_BYTES (64u << 20)
+int cg_solve_noalloc(cg_handle *h, const double *b, double *x, double tol, int32_t maxit,
+                     cg_result *res);
+
 /* Bit-exact readback of the GPU row block as uploaded: rows + 1 rebased row
  * pointers, nnz_gpu columns and values (host buffers sized by the caller from
  * cg_result / cg_slice_info).  For checking the row split. */

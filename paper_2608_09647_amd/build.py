@@ -11,7 +11,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libcgmi.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-HIP_SOURCES = ["kernels_cg.hip", "kernels_small.hip", "kernels_fsai.hip", "kernels_batch.hip", "kernels_util.hip"]
+HIP_SOURCES = ["kernels_cg.hip", "kernels_small.hip", "kernels_fsai.hip", "kernels_batch.hip", "kernels_util.hip",
+               "scratch.hip"]
 HOST_SOURCES = ["cgmi.cpp", "devmatrix.cpp", "fsai.cpp", "batch.cpp", "mmio.cpp"]
 
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

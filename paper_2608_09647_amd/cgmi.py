@@ -23,8 +23,9 @@ EXCHANGE_WHOLE, EXCHANGE_HALO, EXCHANGE_MAPPED, EXCHANGE_MANAGED = 0, 1, 2, 3
 
 # Every symbol the public header declares (checked by the tests).
 EXPORTED = ["cg_create", "cg_destroy", "cg_set_stream", "cg_default_opts", "cg_set_opts",
-            "cg_get_opts", "cg_spmv", "cg_spmv_f32", "cg_solve", "cg_slice_info", "cg_read_slice",
-            "cg_hbm_copy", "cg_last_error"]
+            "cg_get_opts", "cg_spmv", "cg_spmv_f32", "cg_solve", "cg_solve_noalloc", "cg_slice_info",
+            "cg_read_slice", "cg_hbm_copy", "cg_last_error"]
+NOALLOC_SCRATCH_BYTES = 64 << 20
 # include/cgmi_fsai.h
 EXPORTED_FSAI = ["cg_fsai_setup", "cg_set_fsai", "cg_fsai_classic", "cg_fsai_factor_info", "cg_fsai_read_factor",
                  "cg_fsai_trainer_create", "cg_fsai_trainer_destroy", "cg_fsai_loss_grad",
@@ -129,6 +130,9 @@ def lib() -> ctypes.CDLL:
         L.cg_solve.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int32,
                                ctypes.POINTER(CgResult)]
         L.cg_solve.restype = ctypes.c_int
+        L.cg_solve_noalloc.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int32,
+                                       ctypes.POINTER(CgResult)]
+        L.cg_solve_noalloc.restype = ctypes.c_int
         L.cg_slice_info.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]
         L.cg_slice_info.restype = ctypes.c_int
         L.cg_read_slice.argtypes = [_vp, _vp, _vp, _vp]
@@ -278,6 +282,18 @@ class Solver:
         res = CgResult()
         code = lib().cg_solve(self._h, _dev_f64(b, self.n, "b"), _dev_f64(x, self.n, "x"),
                               float(tol), int(maxit), ctypes.byref(res))
+        if check:
+            _check(code, allow=(CG_OK, CG_MAXIT, CG_EBREAKDOWN))
+        out = res.as_dict()
+        out["code"] = code
+        return x, out
+
+    def solve_noalloc(self, b, x, tol: float = 1e-10, maxit: int = 10000, check: bool = True):
+        """cg_solve_noalloc: as solve, with the library's static scratch as the
+        only work memory; x (the initial guess, overwritten) must be given."""
+        res = CgResult()
+        code = lib().cg_solve_noalloc(self._h, _dev_f64(b, self.n, "b"), _dev_f64(x, self.n, "x"),
+                                      float(tol), int(maxit), ctypes.byref(res))
         if check:
             _check(code, allow=(CG_OK, CG_MAXIT, CG_EBREAKDOWN))
         out = res.as_dict()

@@ -209,6 +209,9 @@ extern "C" int cg_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const i
         return code;
     };
     if (hipGetDevice(&h->dev) != hipSuccess) return bail(fail(CG_EDEVICE, "no HIP device"));
+    // device address of the static scratch of cg_solve_noalloc, once per
+    // device (a failure is kept and reported by that entry point)
+    (void)scratch_setup();
     h->cus = device_cu_count();
     const int m = h->m;
     // device copy of the GPU row block, row pointers rebased (Section 3.2)
@@ -480,8 +483,44 @@ int status_of(int done) {
 // GPU-only solve: alpha, beta and the stop test stay on the device; the host
 // queues iterations in chunks and polls the device state between chunks.
 
-static int solve_gpu_only(cg_handle *h, const double *b, double *x, double tol, int32_t maxit,
-                          cg_result *res) {
+namespace {
+
+// Device buffers of one plain float64 GPU-only solve: the handle's own, or
+// carved from the library's static scratch (cg_solve_noalloc).
+struct PlainWork {
+    double *x, *r, *q;        // n each: working x, residual, A p
+    double *p, *p2;           // n each; p2 null: x updated every iteration from p
+    double *part_setup;       // 2 x A.grid: r^T r, b^T b of the residual kernel
+    double *part_pq;          // A.grid
+    double *part_rr;          // vec_grid
+    DevState *state;          // device state
+    DevState *h_state;        // host copy, read at poll points
+    bool events;              // HIP events allowed (SpMV timing, cg_opts.profile)
+    bool state_kernel;        // initialise the state with a kernel (no host staging)
+};
+
+int work_state_init(cg_handle *h, const PlainWork &w, double tol, int32_t maxit) {
+    if (w.state_kernel) {
+        HIP_TRY(launch_state_init(w.state, tol, maxit, h->opts.refine_delta, h->stream));
+        return CG_OK;
+    }
+    DevState &s = *w.h_state;
+    std::memset(&s, 0, sizeof s);
+    s.tol = tol;
+    s.maxit = maxit;
+    s.delta = h->opts.refine_delta;
+    HIP_TRY(hipMemcpyAsync(w.state, w.h_state, sizeof(DevState), hipMemcpyHostToDevice, h->stream));
+    return CG_OK;
+}
+
+int work_state_read(cg_handle *h, const PlainWork &w) {
+    HIP_TRY(hipMemcpyAsync(w.h_state, w.state, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return CG_OK;
+}
+
+int solve_plain(cg_handle *h, const PlainWork &w, const double *b, double *x, double tol, int32_t maxit,
+                cg_result *res) {
     const int32_t n = h->n;
     hipStream_t st = h->stream;
     const bool small = h->opts.small_path && n <= small_path_max_rows() &&
@@ -496,11 +535,11 @@ static int solve_gpu_only(cg_handle *h, const double *b, double *x, double tol, 
             h->max_row_len = L;
         }
         const double t0 = now();
-        HIP_TRY(launch_cg_small(n, h->A.d_rp, h->A.d_ci, h->A.d_val, b, x, tol, maxit, h->d_state,
+        HIP_TRY(launch_cg_small(n, h->A.d_rp, h->A.d_ci, h->A.d_val, b, x, tol, maxit, w.state,
                                 h->max_row_len, st));
-        const int rc = gpu_state_read(h);
+        const int rc = work_state_read(h, w);
         if (rc) return rc;
-        const DevState &s = *h->h_state;
+        const DevState &s = *w.h_state;
         const int status = status_of(s.done);
         if (res) {
             res->status = status;
@@ -512,35 +551,31 @@ static int solve_gpu_only(cg_handle *h, const double *b, double *x, double tol, 
         }
         return status;
     }
-    HIP_TRY(hipMemcpyAsync(h->d_x, x, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
-    int rc = gpu_state_init(h, tol, maxit);
+    HIP_TRY(hipMemcpyAsync(w.x, x, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    int rc = work_state_init(h, w, tol, maxit);
     if (rc) return rc;
     double t_gpu = 0.0, t_spmv = 0.0;
     int n_spmv = 0;
     const double t0 = now();
     {
         const int Gs = h->A.grid, Gv = h->vec_grid;
-        const Partials setup_rr{h->d_part_setup, Gs}, setup_bb{h->d_part_setup + Gs, Gs};
-        const Partials pq{h->d_part_pq, Gs}, rr{h->d_part_rr, Gv};
+        const Partials setup_rr{w.part_setup, Gs}, setup_bb{w.part_setup + Gs, Gs};
+        const Partials pq{w.part_pq, Gs}, rr{w.part_rr, Gv};
         // r = b - A x, p = r (partials of r^T r and b^T b)
-        HIP_TRY(launch_spmv(h->A.dev(), h->A.sched, Gs, h->d_x, h->d_r, nullptr, b, h->d_p,
-                            h->d_part_setup, no_partials(), no_partials(), nullptr, kSpmvResidual, 0, st));
+        HIP_TRY(launch_spmv(h->A.dev(), h->A.sched, Gs, w.x, w.r, nullptr, b, w.p,
+                            w.part_setup, no_partials(), no_partials(), nullptr, kSpmvResidual, 0, st));
         const int C = h->opts.check_every;
+        const int P = w.events ? h->opts.profile : 0;   // events around the SpMV of every P-th iteration
         std::vector<hipEvent_t> ev;
-        if (h->opts.profile) {
+        if (P) {
             ev.resize(2 * (size_t)C);
             for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
         }
-        const int P = h->opts.profile;   // events around the SpMV of every P-th iteration
         auto sampled = [P](int32_t it) { return P > 0 && it % P == 0; };
         // x updated every other iteration from two p buffers (not with p in
         // shared host memory, whose one buffer the other side reads)
-        const bool two_buf = !h->shared_p();
-        if (two_buf && !h->d_p2) {
-            const hipError_t e = dmalloc(&h->d_p2, (size_t)n + 2);
-            if (e != hipSuccess) return fail(CG_ENOMEM, "second p buffer: %s", hipGetErrorString(e));
-        }
-        double *const pbuf[2] = {h->d_p, h->d_p2};
+        const bool two_buf = w.p2 != nullptr;
+        double *const pbuf[2] = {w.p, w.p2};
         int32_t k = 0;
         bool running = true;
         while (running) {
@@ -549,28 +584,27 @@ static int solve_gpu_only(cg_handle *h, const double *b, double *x, double tol, 
             for (int32_t j = 0; j < chunk; ++j) {
                 const int32_t kk = k + j;
                 if (sampled(kk)) HIP_TRY(hipEventRecord(ev[2 * j], st));
-                double *p_k = two_buf ? pbuf[kk & 1] : h->d_p;
-                HIP_TRY(launch_spmv(h->A.dev(), h->A.sched, Gs, p_k, h->d_q, p_k, nullptr, nullptr,
-                                    h->d_part_pq, setup_rr, setup_bb, h->d_state, kSpmvDot, kk == 0, st));
+                double *p_k = two_buf ? pbuf[kk & 1] : w.p;
+                HIP_TRY(launch_spmv(h->A.dev(), h->A.sched, Gs, p_k, w.q, p_k, nullptr, nullptr,
+                                    w.part_pq, setup_rr, setup_bb, w.state, kSpmvDot, kk == 0, st));
                 if (sampled(kk)) HIP_TRY(hipEventRecord(ev[2 * j + 1], st));
                 if (maxit == 0) break;
+                HIP_TRY(launch_update_r(n, Gv, w.r, w.q, w.part_rr, pq, w.state, kk, st));
                 if (two_buf) {
                     double *pc = pbuf[kk & 1], *po = pbuf[(kk + 1) & 1];
-                    HIP_TRY(launch_update_r(n, Gv, h->d_r, h->d_q, h->d_part_rr, pq, h->d_state, kk, st));
-                    HIP_TRY(launch_update_pxb(n, Gv, h->d_x, h->d_r, pc, po, rr, h->d_state, kk, st));
+                    HIP_TRY(launch_update_pxb(n, Gv, w.x, w.r, pc, po, rr, w.state, kk, st));
                 } else {
-                    HIP_TRY(launch_update_r(n, Gv, h->d_r, h->d_q, h->d_part_rr, pq, h->d_state, kk, st));
-                    HIP_TRY(launch_update_px(n, Gv, h->d_x, h->d_r, h->d_p, rr, h->d_state, kk, st));
+                    HIP_TRY(launch_update_px(n, Gv, w.x, w.r, w.p, rr, w.state, kk, st));
                 }
             }
             const int32_t it0 = k;
             k += chunk;
-            rc = gpu_state_read(h);
+            rc = work_state_read(h, w);
             if (rc) break;
-            running = h->h_state->done == kDoneRunning && k < maxit;
-            if (h->opts.profile) {
+            running = w.h_state->done == kDoneRunning && k < maxit;
+            if (P) {
                 // time only SpMVs that did work (iterations it0 .. iter, plus a breakdown step)
-                int32_t ran = h->h_state->iter - it0 + (h->h_state->done == kDoneBreakdown ? 1 : 0);
+                int32_t ran = w.h_state->iter - it0 + (w.h_state->done == kDoneBreakdown ? 1 : 0);
                 ran = std::max(0, std::min<int32_t>(ran, chunk));
                 for (int32_t j = 0; j < ran; ++j) {
                     if (!sampled(it0 + j)) continue;
@@ -585,7 +619,7 @@ static int solve_gpu_only(cg_handle *h, const double *b, double *x, double tol, 
         if (rc) return rc;
     }
     t_gpu = now() - t0;
-    DevState s = *h->h_state;
+    DevState s = *w.h_state;
     if (s.bb == 0.0) {  // b = 0: the solution is x = 0
         HIP_TRY(hipMemsetAsync(x, 0, sizeof(double) * n, st));
         HIP_TRY(hipStreamSynchronize(st));
@@ -596,9 +630,12 @@ static int solve_gpu_only(cg_handle *h, const double *b, double *x, double tol, 
         }
         return CG_OK;
     }
-    HIP_TRY(hipMemcpyAsync(x, h->d_x, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(x, w.x, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    // true residual ||b - A x||^2 and ||b||^2 (q as the output scratch)
+    HIP_TRY(launch_spmv(h->A.dev(), h->A.sched, h->A.grid, x, w.q, nullptr, b, w.q, w.part_setup,
+                        no_partials(), no_partials(), nullptr, kSpmvResidual, 0, st));
     double rr_true = 0.0, bb = 0.0;
-    rc = gpu_true_residual(h, b, x, &rr_true, &bb);
+    rc = sum_partials_host(h, w.part_setup, h->A.grid, 2, &rr_true, &bb);
     if (rc) return rc;
     const int status = status_of(s.done == kDoneRunning ? kDoneMaxit : s.done);
     if (res) {
@@ -612,6 +649,23 @@ static int solve_gpu_only(cg_handle *h, const double *b, double *x, double tol, 
         res->n_spmv = n_spmv;
     }
     return status;
+}
+
+}  // namespace
+
+static int solve_gpu_only(cg_handle *h, const double *b, double *x, double tol, int32_t maxit,
+                          cg_result *res) {
+    // x updated every other iteration from two p buffers (not with p in
+    // shared host memory, whose one buffer the other side reads)
+    const bool two_buf = !h->shared_p();
+    if (two_buf && !h->d_p2) {
+        const hipError_t e = dmalloc(&h->d_p2, (size_t)h->n + 2);
+        if (e != hipSuccess) return fail(CG_ENOMEM, "second p buffer: %s", hipGetErrorString(e));
+    }
+    const PlainWork w{h->d_x, h->d_r, h->d_q, h->d_p, two_buf ? h->d_p2 : nullptr,
+                      h->d_part_setup, h->d_part_pq, h->d_part_rr, h->d_state, h->h_state,
+                      true, false};
+    return solve_plain(h, w, b, x, tol, maxit, res);
 }
 
 // ---------------------------------------------------------------------------
@@ -990,6 +1044,64 @@ static int solve_split(cg_handle *h, const double *b, double *x, double tol, int
         res->t_h2d = tm.h2d;
     }
     return status;
+}
+
+static_assert(CG_NOALLOC_SCRATCH_BYTES == kScratchBytes, "scratch size in cgmi.h and cgmi_internal.h");
+
+// Plain float64 GPU-only CG with every work buffer in the library's static
+// scratch: no device allocation, no pinned host memory, no events.
+extern "C" int cg_solve_noalloc(cg_handle *h, const double *b, double *x, double tol, int32_t maxit,
+                                cg_result *res) {
+    clear_error();
+    if (!h) return fail(CG_EINVAL, "handle is NULL");
+    if (res) std::memset(res, 0, sizeof *res);
+    if (!(tol >= 0.0)) return fail(CG_EINVAL, "tol must be >= 0");
+    if (maxit < 0) return fail(CG_EINVAL, "maxit must be >= 0");
+    if (h->n > 0 && (!b || !x)) return fail(CG_EINVAL, "b/x is NULL");
+    if (!h->gpu_only()) return fail(CG_EINVAL, "cg_solve_noalloc needs a GPU-only handle (rows [0, n))");
+    if (h->opts.precision != CG_PREC_FP64 || h->opts.precond != CG_PC_NONE || h->shared_p())
+        return fail(CG_EINVAL, "cg_solve_noalloc runs plain float64 CG with p in device memory");
+    if (res) {
+        res->rows_gpu = h->m;
+        res->nnz_gpu = h->nnz_gpu;
+    }
+    if (h->n == 0) {
+        if (res) res->converged = 1;
+        return CG_OK;
+    }
+    if (h->nnz == 0) return fail(CG_EINVAL, "matrix has no nonzeros");
+    // carve the scratch: five vectors, three partial arrays, the state
+    const size_t vec_bytes = (sizeof(double) * ((size_t)h->n + 2) + 255) & ~size_t(255);
+    const size_t part = sizeof(double) * (size_t)h->grid_cap;
+    const size_t need = 5 * vec_bytes + 4 * part + ((sizeof(DevState) + 255) & ~size_t(255));
+    void *base = nullptr;
+    size_t have = 0;
+    HIP_TRY(hipSetDevice(h->dev));
+    HIP_TRY(scratch_region(h->dev, &base, &have));
+    if (need > have) {
+        const size_t per_vec = ((have - 4 * part - 256) / 5) & ~size_t(255);
+        return fail(CG_EINVAL, "n = %d needs %zu bytes of scratch; the static scratch holds %zu (at most %zu rows)",
+                    h->n, need, have, per_vec / sizeof(double) - 2);
+    }
+    unsigned char *c = static_cast<unsigned char *>(base);
+    auto take = [&c](size_t bytes) { unsigned char *r = c; c += bytes; return reinterpret_cast<double *>(r); };
+    double *vx = take(vec_bytes), *vr = take(vec_bytes), *vq = take(vec_bytes);
+    double *vp = take(vec_bytes), *vp2 = take(vec_bytes);
+    double *ps = take(2 * part), *ppq = take(part), *prr = take(part);
+    DevState *dst = reinterpret_cast<DevState *>(take(sizeof(DevState)));
+    DevState hs{};
+    const PlainWork w{vx, vr, vq, vp, vp2, ps, ppq, prr, dst, &hs, false, true};
+    const double t0 = now();
+    const int rc = solve_plain(h, w, b, x, tol, maxit, res);
+    if (res) {
+        res->t_solve = now() - t0;
+        static const int kind_code[6] = {1, 2, 3, 4, 5, 6};   // kTileVector .. kTileStencil
+        res->spmv_kind = kind_code[h->A.sched.kind];
+        res->rows_gpu = h->m;
+        res->nnz_gpu = h->nnz_gpu;
+        if (rc < 0 && res->status == 0) res->status = rc;
+    }
+    return rc;
 }
 
 extern "C" int cg_solve(cg_handle *h, const double *b, double *x, double tol, int32_t maxit,

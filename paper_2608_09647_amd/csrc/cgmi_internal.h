@@ -272,4 +272,15 @@ hipError_t launch_scatter(int32_t cnt, const int32_t *idx, const double *src, do
 
 int device_cu_count();
 
+// The library's static device scratch (scratch.hip), used by the entry point
+// that allocates nothing: kScratchBytes per device, 256-byte aligned.
+// scratch_setup() looks up the array's device address for the current
+// device (once per device; later calls return the first result);
+// scratch_region() returns it for device `dev` after that.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+hipError_t scratch_setup();
+hipError_t scratch_region(int dev, void **ptr, size_t *bytes);
+// Writes a fresh DevState (zeros, tol, maxit, delta) with a one-thread kernel.
+hipError_t launch_state_init(DevState *st, double tol, int32_t maxit, double delta, hipStream_t s);
+
 }  // namespace cgmi

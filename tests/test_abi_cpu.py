@@ -84,6 +84,7 @@ def test_destroy_null_is_noop(cg):
 def test_null_handle_errors(cg):
     r = cg.CgResult()
     assert cg.lib().cg_solve(None, None, None, 1e-10, 10, ctypes.byref(r)) == cg.CG_EINVAL
+    assert cg.lib().cg_solve_noalloc(None, None, None, 1e-10, 10, ctypes.byref(r)) == cg.CG_EINVAL
     assert cg.lib().cg_spmv(None, None, None) == cg.CG_EINVAL
     o = cg.default_opts()
     assert cg.lib().cg_set_opts(None, ctypes.byref(o)) == cg.CG_EINVAL
