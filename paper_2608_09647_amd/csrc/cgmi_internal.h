@@ -138,6 +138,7 @@ struct CsrDev {
     const int32_t *st_offs;   //   per-slice column offsets (8 per slice)
     const uint8_t *st_mask;   //   per-row slot bits
     const double *st_val;     //   slot-major values
+    const uint8_t *sell_len;  // sliced layout: row lengths, one byte per row (64 per slice)
 };
 
 // Per-block operands of the column-blocked tiling (kept on the host by the

@@ -32,6 +32,8 @@ void free_sliced(DevMatrix &M) {
     (void)hipFree(M.d_sell_val32);
     (void)hipFree(M.d_sell_idx);
     (void)hipFree(M.d_sell_dict);
+    (void)hipFree(M.d_sell_len);
+    M.d_sell_len = nullptr;
     M.d_sell_off = M.d_sell_ci = nullptr;
     M.d_sell_val = nullptr;
     M.d_sell_val32 = nullptr;
@@ -330,6 +332,9 @@ int build_sliced(DevMatrix &M, bool with_cols) {
     const bool host_vals = !M.h_val.empty();
     std::vector<int32_t> sci(with_cols ? slots : 0, 0);
     std::vector<double> sval(first && host_vals ? slots : 0, 0.0);
+    // row lengths for the two-rows-per-lane tiles (rows up to 255 entries;
+    // those tiles take slices of at most kSliceMaxWidth slots)
+    std::vector<uint8_t> slen(with_cols ? (size_t)nt * kWaveSize : 0, 0);
 #pragma omp parallel for schedule(static)
     for (int32_t t = 0; t < nt; ++t) {
         const int32_t w = (off[t + 1] - off[t]) / kWaveSize;
@@ -338,6 +343,7 @@ int build_sliced(DevMatrix &M, bool with_cols) {
             const int32_t b = i < m ? M.h_rp[i] : 0;
             const int32_t len = i < m ? M.h_rp[i + 1] - M.h_rp[i] : 0;
             const int32_t pad_col = i < m ? M.pad_col_base + i : M.pad_col_base;
+            if (with_cols) slen[(size_t)i] = (uint8_t)std::min(len, 255);
             for (int32_t j = 0; j < w; ++j) {
                 const size_t k = (size_t)off[t] + (size_t)j * kWaveSize + l;
                 if (with_cols) sci[k] = j < len ? M.h_ci[b + j] : pad_col;
@@ -361,6 +367,8 @@ int build_sliced(DevMatrix &M, bool with_cols) {
         e = dmalloc(&M.d_sell_ci, slots);
         if (e == hipSuccess)
             e = hipMemcpy(M.d_sell_ci, sci.data(), sizeof(int32_t) * slots, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = dmalloc(&M.d_sell_len, slen.size());
+        if (e == hipSuccess) e = hipMemcpy(M.d_sell_len, slen.data(), slen.size(), hipMemcpyHostToDevice);
     }
     if (e != hipSuccess) {
         free_sliced(M);
@@ -576,6 +584,9 @@ int dm_schedule(DevMatrix &M, int kind_opt, int grid_opt, int cus, int grid_cap,
     }
     if (M.sched.kind == kTileStencil)
         M.sched.stream_nt = (int64_t)M.st_slots * (int64_t)sizeof(double) + (int64_t)M.m > kStreamNtBytes;
+    else if (M.sched.kind == kTileSliced)
+        M.sched.stream_nt = (int64_t)M.sell_slots * (int64_t)(sizeof(double) + sizeof(int32_t)) + M.m >
+                            kStreamNtBytes;
     else
         M.sched.stream_nt = M.sched.kind == kTileSlicedDict &&
                             (int64_t)M.sell_slots * (int64_t)sizeof(double) + 4ll * M.m > kStreamNtBytes;

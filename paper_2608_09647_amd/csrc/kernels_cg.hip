@@ -719,6 +719,124 @@ __device__ __forceinline__ void spmv_sten2_wave(const CsrDev &A, TileWalk &walk,
     }
 }
 
+// Sliced tiles, two rows per lane (float64, slices of at most kSliceMaxWidth
+// slots, plain and dot modes): a wave takes the slice pair (2u, 2u+1) as
+// spmv_sten2_wave does, lanes 0-31 the first slice and 32-63 the second, each
+// lane the row pair (2h, 2h+1) of its slice.  Slot j's values move in one
+// 16-byte load and its columns in one 8-byte load per lane; each row's length
+// comes from one byte per row (no row-pointer loads), so padding slots are
+// skipped.  A lane gathers its two rows' slot-j entries, so one gather
+// instruction of the wave covers slot j of 128 consecutive rows.  The columns
+// of the wave's next slice pair are loaded while the current pair's gathers
+// and values are in flight (two register sets alternate, so no register move
+// waits on a load), which leaves one memory round trip per pair.  Every row
+// is summed left to right with rounded products, as in slice_step (bit-exact
+// against the oracle).  NT: the matrix is loaded and q stored nontemporally.
+struct Sliced2Geo {
+    int off, width, wmax, ra;
+    bool va, vb, mine;
+};
+
+template <bool NT>
+__device__ __forceinline__ void sliced2_cols(const CsrDev &A, int u, Sliced2Geo &G, int2 (&c)[kSliceMaxWidth]) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int half = lane >> 5, hl = lane & 31;
+    const int nt = (A.m + kWave - 1) / kWave;
+    const int t0 = 2 * u;
+    const bool two = t0 + 1 < nt;                 // uniform: the pair has a second slice
+    const int t1 = two ? t0 + 1 : t0;
+    const int off0 = A.sell_off[t0], w0 = (A.sell_off[t0 + 1] - off0) / kWave;
+    const int off1 = A.sell_off[t1], w1 = two ? (A.sell_off[t1 + 1] - off1) / kWave : 0;
+    G.wmax = max(w0, w1);
+    const int ts = half ? t1 : t0;
+    G.mine = !half || two;                        // this half has a slice
+    G.off = half ? off1 : off0;
+    G.width = half ? w1 : w0;
+    G.ra = ts * kWave + 2 * hl;                   // the lane's rows ra, ra + 1
+    G.va = G.mine && G.ra < A.m;
+    G.vb = G.mine && G.ra + 1 < A.m;
+    const int ga = A.col_base + min(G.ra, A.m - 1);   // a column every lane may gather
+#pragma unroll
+    for (int j = 0; j < kSliceMaxWidth; ++j) {
+        c[j] = make_int2(ga, ga);
+        if (j < G.wmax && j < G.width) {
+            const int2 *cp = reinterpret_cast<const int2 *>(&A.sell_ci[G.off + j * kWave + 2 * hl]);
+            c[j] = NT ? make_int2(__builtin_nontemporal_load(&cp->x), __builtin_nontemporal_load(&cp->y)) : *cp;
+        }
+    }
+}
+
+template <int MODE, bool NT>
+__device__ __forceinline__ void sliced2_step(const CsrDev &A, const SpmvArgs<double> &a, const Sliced2Geo &G,
+                                             const int2 (&c)[kSliceMaxWidth], int un, Sliced2Geo &Gn,
+                                             int2 (&cn)[kSliceMaxWidth], double &acc0) {
+    const int hl = threadIdx.x & 31;
+    dbl2v v[kSliceMaxWidth];
+    double pa[kSliceMaxWidth], pb[kSliceMaxWidth];
+#pragma unroll
+    for (int j = 0; j < kSliceMaxWidth; ++j) {
+        v[j] = dbl2v{0.0, 0.0};
+        pa[j] = pb[j] = 0.0;
+        if (j < G.wmax) {
+            pa[j] = a.p[c[j].x];
+            pb[j] = a.p[c[j].y];
+            if (j < G.width) {
+                const dbl2v *vp = reinterpret_cast<const dbl2v *>(&A.sell_val[G.off + j * kWave + 2 * hl]);
+                v[j] = NT ? __builtin_nontemporal_load(vp) : *vp;
+            }
+        }
+    }
+    const int ts = G.ra & ~(kWave - 1);
+    const uint16_t *lp = reinterpret_cast<const uint16_t *>(&A.sell_len[(int64_t)ts + 2 * hl]);
+    const uint32_t l2 = G.mine ? (NT ? (uint32_t)__builtin_nontemporal_load(lp) : (uint32_t)*lp) : 0u;
+    // the next pair's columns (past the last pair: this pair's again, discarded)
+    sliced2_cols<NT>(A, un, Gn, cn);
+    const int la = G.va ? (int)(l2 & 0xFFu) : 0, lb = G.vb ? (int)(l2 >> 8) : 0;
+    double sa = 0.0, sb = 0.0;
+    {
+#pragma clang fp contract(off)
+#pragma unroll
+        for (int j = 0; j < kSliceMaxWidth; ++j) {
+            if (j < la) sa = sa + v[j].x * pa[j];  // rounded product, then the sum
+            if (j < lb) sb = sb + v[j].y * pb[j];
+        }
+    }
+    const int ra = G.ra;
+    if (G.va && G.vb) {
+        if (MODE == kSpmvDot) {
+            const dbl2v po = *reinterpret_cast<const dbl2v *>(&a.p_own[ra]);
+            acc0 = fma(po.x, sa, acc0);
+            acc0 = fma(po.y, sb, acc0);
+        }
+        dbl2v qv{sa, sb};
+        dbl2v *qp = reinterpret_cast<dbl2v *>(&a.q[ra]);
+        if (NT) __builtin_nontemporal_store(qv, qp);
+        else *qp = qv;
+    } else if (G.va) {   // the last row of an odd row count
+        if (MODE == kSpmvDot) acc0 = fma(a.p_own[ra], sa, acc0);
+        a.q[ra] = sa;
+    }
+}
+
+template <int MODE, bool NT>
+__device__ __forceinline__ void spmv_sliced2_wave(const CsrDev &A, TileWalk &walk, const SpmvArgs<double> &a,
+                                                  double &acc0) {
+    int u = walk.next();
+    if (u < 0) return;
+    Sliced2Geo G0, G1;
+    int2 c0[kSliceMaxWidth], c1[kSliceMaxWidth];
+    sliced2_cols<NT>(A, u, G0, c0);
+    for (;;) {
+        const int u1 = walk.next();
+        sliced2_step<MODE, NT>(A, a, G0, c0, u1 >= 0 ? u1 : u, G1, c1, acc0);
+        if (u1 < 0) break;
+        const int u2 = walk.next();
+        sliced2_step<MODE, NT>(A, a, G1, c1, u2 >= 0 ? u2 : u1, G0, c0, acc0);
+        if (u2 < 0) break;
+        u = u2;
+    }
+}
+
 // A row longer than kHugeRow: all threads of the workgroup on it.
 template <int MODE, class T>
 __device__ __forceinline__ void spmv_row_wg(const CsrDev &A, int pos, bool identity,
@@ -741,7 +859,9 @@ __device__ __forceinline__ void spmv_row_wg(const CsrDev &A, int pos, bool ident
 // TILE == -4: dictionary-sliced tiles; -5: the same with the matrix streamed
 // nontemporally (matrices larger than the last-level cache can hold);
 // -6 / -7: stencil slices, cached / nontemporal (float64 only); -8 / -9: the
-// same with two rows per lane and 16-byte accesses (plain and dot modes).
+// same with two rows per lane and 16-byte accesses (plain and dot modes);
+// -10 / -11: sliced tiles with two rows per lane, cached / nontemporal
+// (float64, plain and dot modes).
 template <int MODE, int TILE, class T>
 __global__ __launch_bounds__(kBlock) void k_spmv(int32_t m, const int32_t *__restrict__ rp,
                                                  const int32_t *__restrict__ ci,
@@ -756,11 +876,12 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int32_t m, const int32_t *__res
                                                  const int32_t *__restrict__ st_offs,
                                                  const uint8_t *__restrict__ st_mask,
                                                  const double *__restrict__ st_val,
+                                                 const uint8_t *__restrict__ sell_len,
                                                  Schedule S, SpmvArgs<T> a, double *__restrict__ out,
                                                  Partials in0, Partials in1,
                                                  DevState *__restrict__ st, int flags) {
     CsrDev A{m, rp, ci, nullptr, rows, sell_off, sell_ci, nullptr, nullptr, nullptr,
-             sell_idx, sell_dict, col_base, nullptr, st_off, st_offs, st_mask, st_val};
+             sell_idx, sell_dict, col_base, nullptr, st_off, st_offs, st_mask, st_val, sell_len};
     if constexpr (sizeof(T) == 8) {
         A.val = reinterpret_cast<const double *>(val);
         A.sell_val = reinterpret_cast<const double *>(sell_val);
@@ -790,7 +911,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int32_t m, const int32_t *__res
     }
     double acc0 = 0.0, acc1 = 0.0;
     const bool identity = S.identity != 0;
-    TileWalk walk(TILE == -8 || TILE == -9 ? (S.ntiles + 1) / 2 : S.ntiles);   // slice pairs
+    TileWalk walk(TILE <= -8 && TILE >= -11 ? (S.ntiles + 1) / 2 : S.ntiles);   // slice pairs
     if constexpr (TILE == -2 || TILE == -3) {
         spmv_sliced_wave<MODE, T>(A, walk, a, TILE == -3, acc0, acc1);
     } else if constexpr (TILE == -4 || TILE == -5) {
@@ -800,6 +921,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int32_t m, const int32_t *__res
     } else if constexpr (TILE == -8 || TILE == -9) {
         if constexpr (sizeof(T) == 8 && (MODE == kSpmvPlain || MODE == kSpmvDot))
             spmv_sten2_wave<MODE, TILE == -9>(A, walk, a, acc0);
+    } else if constexpr (TILE == -10 || TILE == -11) {
+        if constexpr (sizeof(T) == 8 && (MODE == kSpmvPlain || MODE == kSpmvDot))
+            spmv_sliced2_wave<MODE, TILE == -11>(A, walk, a, acc0);
     } else if constexpr (TILE == -1) {
         if constexpr (sizeof(T) == 8) {
             double *lds = s_prod + (threadIdx.x / kWave) * kStreamNnz;
@@ -1503,7 +1627,9 @@ void launch_spmv_mode(const CsrDev &A, const Schedule &S, int grid, const SpmvAr
                       ((uintptr_t)a.q & 15) == 0 && (MODE != kSpmvDot || ((uintptr_t)a.p_own & 15) == 0);
     const int L = S.kind == kTileStencil ? (wide ? (S.stream_nt ? -9 : -8) : (S.stream_nt ? -7 : -6))
                   : S.kind == kTileSlicedDict ? (S.stream_nt ? -5 : -4)
-                  : S.kind == kTileSliced ? (S.bins[0].lanes <= kSliceMaxWidth ? -2 : -3)
+                  : S.kind == kTileSliced ? (S.bins[0].lanes <= kSliceMaxWidth
+                                                 ? (wide && A.sell_len ? (S.stream_nt ? -11 : -10) : -2)
+                                                 : -3)
                   : S.kind == kTileStream ? -1
                   : (S.identity && S.nbins == 1 && S.huge_count == 0) ? S.bins[0].lanes : 0;
     const T *val, *sval;
@@ -1517,7 +1643,7 @@ void launch_spmv_mode(const CsrDev &A, const Schedule &S, int grid, const SpmvAr
 #define CGMI_SPMV(FL)                                                                             \
     hipLaunchKernelGGL((k_spmv<MODE, FL, T>), dim3(grid), dim3(kBlock), 0, s, A.m, A.rp, A.ci, val, \
                        A.rows, A.sell_off, A.sell_ci, sval, A.sell_idx, A.sell_dict, A.col_base,       \
-                       A.st_off, A.st_offs, A.st_mask, A.st_val, S, a,                                \
+                       A.st_off, A.st_offs, A.st_mask, A.st_val, A.sell_len, S, a,                    \
                        out, in0, in1, st, flags)
     switch (L) {
         case 1: CGMI_SPMV(1); break;
@@ -1536,6 +1662,8 @@ void launch_spmv_mode(const CsrDev &A, const Schedule &S, int grid, const SpmvAr
         case -7: CGMI_SPMV(-7); break;
         case -8: CGMI_SPMV(-8); break;
         case -9: CGMI_SPMV(-9); break;
+        case -10: CGMI_SPMV(-10); break;
+        case -11: CGMI_SPMV(-11); break;
         default: CGMI_SPMV(0); break;
     }
 #undef CGMI_SPMV

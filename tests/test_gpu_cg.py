@@ -693,6 +693,24 @@ def test_paper_inputs_absolute_tolerance(cg):
 
 
 
+@pytest.mark.parametrize("name", ["poisson3d_ragged", "diffusion_100", "poisson2d_64"])
+def test_sliced_pairs_track_stencil_pairs_bitwise(cg, name):
+    """Plain slices with two rows per lane (columns streamed, a length byte per
+    row) and stencil slices with two rows per lane sum every row in CSR order
+    and walk the same slice pairs with the same grid, so p^T q is added in the
+    same order: fixed-work CG iterates are equal bit for bit."""
+    A = SPMV_CASES[name]()
+    b = I.rhs_of(A, I.uniform_vector(A.n, [17, 1]))
+    out = {}
+    for kind in (3, 6):
+        with cg.Solver(A) as s:
+            s.set_opts(spmv_kind=kind, small_path=0)
+            xs, res = s.solve(dev(b), tol=0.0, maxit=31)
+            out[kind] = (res["spmv_kind"], host(xs))
+    assert out[3][0] == 3 and out[6][0] == 6
+    assert np.array_equal(out[3][1], out[6][1])
+
+
 @pytest.mark.parametrize("name", ["poisson3d_24", "poisson3d_ragged", "poisson2d_64", "diffusion_100"])
 def test_stencil_slices_chosen_and_exact(cg, name):
     """Stencil matrices take stencil slices automatically; SpMV bit-exact
