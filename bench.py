@@ -35,21 +35,23 @@ def spmv_algorithmic_bytes(n: int, nnz: int) -> int:
 
 
 SPMV_SOURCES = ("kernels_cg.hip", "cgmi_internal.h")
+BATCH_SOURCES = ("kernels_batch.hip", "batch_internal.h")
 
 
-def kernel_source_hash() -> str:
-    """Hash of the sources that define the CG kernels (the counters in
+def kernel_source_hash(sources=SPMV_SOURCES) -> str:
+    """Hash of the sources that define a kernel (the counters in
     profiles/traffic.json are valid only for these exact sources)."""
     h = hashlib.sha256()
-    for fn in SPMV_SOURCES:
+    for fn in sources:
         with open(os.path.join(ROOT, "paper_2608_09647_amd", "csrc", fn), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(key: str, spmv_kind: int):
+def measured_traffic(key: str, spmv_kind, sources=SPMV_SOURCES):
     """Per-launch HBM bytes from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources with the same SpMV tiling; else None."""
+    was taken on the current kernel sources with the same SpMV tiling (None:
+    no tiling to match); else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -57,7 +59,7 @@ def measured_traffic(key: str, spmv_kind: int):
         with open(path) as f:
             table = json.load(f)
         ent = table.get(key)
-        if ent and ent.get("source_hash") == kernel_source_hash() and ent.get("spmv_kind") == spmv_kind:
+        if ent and ent.get("source_hash") == kernel_source_hash(sources) and ent.get("spmv_kind") == spmv_kind:
             return ent.get("bytes_per_launch")
     except (OSError, ValueError):
         return None
@@ -223,6 +225,9 @@ def main() -> int:
     ap.add_argument("--batch-iters", type=int, default=30, help="fixed iterations per batched step")
     ap.add_argument("--profile-run", action="store_true",
                     help="only the timed path of the workload (no comparison solves), for profilers")
+    ap.add_argument("--batch-launch", default="cooperative", choices=["cooperative", "ordinary"],
+                    help="launch form of the batched kernel (ordinary: for profilers that cannot "
+                         "follow cooperative launches)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the hot path runs on a single MI355X "
@@ -813,6 +818,9 @@ def bench_batch(args) -> int:
     batch = cgmi.Batch(systems, 16)
     sched = autotune.batch_schedule(batch, systems, B, store=False,
                                     log=lambda s: print(f"[bench] tune {s}", file=sys.stderr, flush=True))
+    if args.batch_launch == "ordinary":
+        batch.set_sched(launch=cgmi.BATCH_LAUNCH_ORDINARY)
+        sched = {"sched": batch.sched.as_dict(), "source": sched["source"]}
     print(f"[bench] schedule {sched}", file=sys.stderr, flush=True)
     K = args.batch_iters
     for _ in range(args.warmup):
@@ -831,38 +839,44 @@ def bench_batch(args) -> int:
     pairs = len(systems) * 16
     value = pairs * K * args.steps / elapsed
     bytes_it = batch_algorithmic_bytes(n_total, nnz_total, 16)
-    achieved = bytes_it * K / float(np.mean(t_kernel)) / 1e9
+    t_k = float(np.mean(t_kernel))
     print(f"[bench] batched: {args.steps} x {K} iterations in {elapsed:.3f}s, stats {st}",
           file=sys.stderr, flush=True)
     batch.close()
     del X
     if args.profile_run:
         print(json.dumps({"profile_run": "batch_256", "pair_iterations_per_s": value,
-                          "kernel_seconds": float(np.mean(t_kernel)), "stats": st}), flush=True)
+                          "kernel_seconds": t_k, "stats": st, "launch": args.batch_launch}), flush=True)
         return 0
 
-    # one solve per launch: sampled systems (by size), K iterations, one RHS
-    order = np.argsort([A.n for A in systems])
-    sample = sorted(set(order[np.linspace(0, len(order) - 1, 9).astype(int)].tolist()))
-    per_n = []
-    for k in sample:
-        A = systems[k]
+    # one cg_solve per (system, right-hand side), every pair timed at the
+    # same fixed work (K iterations), device-resident vectors
+    t_all, per_sys = 0.0, []
+    for k, A in enumerate(systems):
         s = cgmi.Solver(A)
-        b1 = torch.from_numpy(np.ascontiguousarray(probs[k].b[:, 0])).cuda()
-        x1 = torch.zeros_like(b1)
-        s.solve(b1, x1, tol=0.0, maxit=K)
-        _, _, ts = _timed_solve(s, b1, torch.zeros_like(b1), 0.0, K, 3)
-        per_n.append((A.n, float(np.median(ts))))
+        bk = torch.from_numpy(np.ascontiguousarray(probs[k].b.T)).cuda()   # 16 x n
+        xk = torch.zeros_like(bk[0])
+        s.solve(bk[0], xk, tol=0.0, maxit=K)                                 # warm: first-use setup
+        t_k_sys = 0.0
+        for j in range(16):
+            xk.zero_()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, r1 = s.solve(bk[j], xk, tol=0.0, maxit=K)
+            torch.cuda.synchronize()
+            t_k_sys += time.perf_counter() - t1
+            assert r1["iterations"] == K
         s.close()
-    ns, ts = zip(*per_n)
-    est = 16 * float(np.sum(np.interp([A.n for A in systems], ns, ts)))
-    single = {"sampled_systems": [int(k) for k in sample], "seconds_per_solve": dict(
-        (str(int(n)), t) for n, t in per_n), "estimated_seconds_all_pairs": est,
-        "estimated_pair_iterations_per_s": pairs * K / est}
-    print(f"[bench] one solve per launch (estimated from {len(sample)} sizes): {est:.3f}s",
-          file=sys.stderr, flush=True)
+        per_sys.append(t_k_sys)
+        t_all += t_k_sys
+    single = {"measured_seconds_all_pairs": t_all, "pairs": pairs, "iterations_per_pair": K,
+              "pair_iterations_per_s": pairs * K / t_all,
+              "seconds_largest_system_16_pairs": float(max(per_sys)),
+              "seconds_smallest_system_16_pairs": float(min(per_sys))}
+    print(f"[bench] one cg_solve per pair, all {pairs} pairs timed: {t_all:.3f}s", file=sys.stderr, flush=True)
 
-    # to tolerance on the small-system sub-batch, every pair's solve timed
+    # to tolerance on the small-system sub-batch, every pair's solve timed,
+    # repeated `steps` times (batched and separate alternating)
     small = [k for k in range(len(systems)) if probs[k].meta["side"] <= 64]
     tol_cmp = None
     if small:
@@ -871,44 +885,54 @@ def bench_batch(args) -> int:
         bt = cgmi.Batch(sub, 16)
         autotune.batch_schedule(bt, sub, Bs, store=False)
         bt.solve(Bs, torch.zeros_like(Bs), tol=1e-10, maxit=200000)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        _, rs, _, code = bt.solve(Bs, torch.zeros_like(Bs), tol=1e-10, maxit=200000)
-        torch.cuda.synchronize()
-        t_b = time.perf_counter() - t1
-        bt.close()
-        t_sep, its = 0.0, 0
-        for k in small:
-            s = cgmi.Solver(systems[k])
-            for j in range(16):
-                bj = torch.from_numpy(np.ascontiguousarray(probs[k].b[:, j])).cuda()
-                xj = torch.zeros_like(bj)
-                torch.cuda.synchronize()
-                t1 = time.perf_counter()
-                _, r1 = s.solve(bj, xj, tol=1e-10, maxit=200000)
-                torch.cuda.synchronize()
-                t_sep += time.perf_counter() - t1
-                its += r1["iterations"]
+        solvers = [cgmi.Solver(systems[k]) for k in small]
+        bsmall = [torch.from_numpy(np.ascontiguousarray(probs[k].b.T)).cuda() for k in small]
+        speedups, t_bs, t_seps = [], [], []
+        for _ in range(max(1, args.steps)):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, rs, _, code = bt.solve(Bs, torch.zeros_like(Bs), tol=1e-10, maxit=200000)
+            torch.cuda.synchronize()
+            t_b = time.perf_counter() - t1
+            t_sep, its = 0.0, 0
+            for s, bk in zip(solvers, bsmall):
+                for j in range(16):
+                    xj = torch.zeros_like(bk[j])
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    _, r1 = s.solve(bk[j], xj, tol=1e-10, maxit=200000)
+                    torch.cuda.synchronize()
+                    t_sep += time.perf_counter() - t1
+                    its += r1["iterations"]
+            speedups.append(t_sep / t_b)
+            t_bs.append(t_b)
+            t_seps.append(t_sep)
+        for s in solvers:
             s.close()
-        tol_cmp = {"systems": len(small), "pairs": 16 * len(small), "batched_seconds": t_b,
-                   "separate_seconds": t_sep, "speedup": t_sep / t_b,
+        bt.close()
+        tol_cmp = {"systems": len(small), "pairs": 16 * len(small), "runs": len(speedups),
+                   "batched_seconds_median": float(np.median(t_bs)),
+                   "separate_seconds_median": float(np.median(t_seps)),
+                   "speedup_min": float(min(speedups)), "speedup_median": float(np.median(speedups)),
+                   "speedup_max": float(max(speedups)),
                    "batched_max_iterations": int(rs["iterations"].max()),
                    "separate_total_iterations": its, "all_converged": bool(np.all(rs["status"] == 0)),
                    "max_rel_res_true": float(rs["rel_res_true"].max())}
         print(f"[bench] to 1e-10, sides <= 64: {tol_cmp}", file=sys.stderr, flush=True)
 
+    traffic = measured_traffic("batch_256", None, BATCH_SOURCES)
     line = _line("CG iters/s + SpMV GB/s (%HBM peak); time to 1e-10 residual, plain vs learned-PC",
                  value, "iter/s", args, 1e3 * elapsed / args.steps,
                  {"workload": "batch_256_diffusion2d_sides_32-512_16rhs_fp64_fixed_work",
                   "systems": len(systems), "nrhs": 16, "n_total": n_total, "nnz_total": nnz_total,
                   "iterations_per_step": K, "seed": 5},
                  value_meaning="(system, right-hand side) CG iterations per second, one persistent launch per step",
-                 schedule=sched, kernel_seconds=float(np.mean(t_kernel)),
+                 schedule=sched, kernel_seconds=t_k,
                  one_solve_per_launch=single,
-                 speedup_vs_one_solve_per_launch=est / (elapsed / args.steps),
+                 speedup_vs_one_solve_per_launch=t_all / (elapsed / args.steps),
                  to_tolerance_small_systems=tol_cmp,
-                 roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": achieved / HBM_PEAK_GBS, "traffic": None})
+                 roofline=roofline_hbm(bytes_it * K, t_k, traffic, kernel="k_batch_cg (whole launch)",
+                                       note="algorithmic bytes of all K iterations of one launch"))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_batch(systems, probs, K, pairs)
     print(json.dumps(line), flush=True)

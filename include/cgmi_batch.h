@@ -49,7 +49,21 @@ typedef struct cg_batch_sched {
     int32_t rhs_per_lane;   /* right-hand sides per lane: 1, or 2 (16-byte
                                loads; needs an even nrhs, else 1 is used);
                                0: 2 when nrhs is even */
+    int32_t launch;         /* CG_BATCH_LAUNCH_COOPERATIVE (default): a
+                               cooperative launch, whose workgroups the
+                               runtime guarantees to be resident together.
+                               CG_BATCH_LAUNCH_ORDINARY: an ordinary launch
+                               of the same grid, for tools that cannot follow
+                               cooperative launches (some profilers); the
+                               grid never exceeds the kernel's occupancy, so
+                               its workgroups are resident together on an
+                               otherwise idle device, and a team whose
+                               members never all arrive gives up after 20 s
+                               (CG_EDEVICE) instead of waiting forever. */
 } cg_batch_sched;
+
+#define CG_BATCH_LAUNCH_COOPERATIVE 0
+#define CG_BATCH_LAUNCH_ORDINARY 1
 
 /* Per (system, right-hand side) outcome, index k * nrhs + j. */
 typedef struct cg_batch_result {

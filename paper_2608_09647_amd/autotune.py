@@ -73,8 +73,11 @@ def lookup(signature: str, path: str = TABLE):
 
 # ----------------------------------------------------------------------------- batch
 
+# max_team bounds a system's team: every team barrier costs a round trip
+# through memory shared by the team's workgroups, so systems that converge
+# in many short iterations may run faster on fewer workgroups
 BATCH_SPACE = {"blocks_per_cu": [4, 8], "rows_per_thread": [1, 2], "team_exponent": [1.0, 1.25],
-               "rhs_per_lane": [1, 2]}
+               "rhs_per_lane": [1, 2], "max_team": [0, 8, 32]}
 
 
 def batch_candidates(space: dict | None = None) -> list:

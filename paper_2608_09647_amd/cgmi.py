@@ -35,6 +35,7 @@ FSAI_NPARAMS = 5317
 EXPORTED_BATCH = ["cg_batch_create", "cg_batch_destroy", "cg_batch_set_stream", "cg_batch_layout",
                   "cg_batch_default_sched", "cg_batch_set_sched", "cg_batch_get_sched", "cg_batch_solve"]
 BATCH_MAX_RHS = 16
+BATCH_LAUNCH_COOPERATIVE, BATCH_LAUNCH_ORDINARY = 0, 1
 # include/cgmi_io.h
 EXPORTED_IO = ["cg_mm_read", "cg_mm_free"]
 
@@ -74,7 +75,7 @@ class CgResult(ctypes.Structure):
 class BatchSched(ctypes.Structure):
     _fields_ = [("blocks_per_cu", ctypes.c_int32), ("rows_per_thread", ctypes.c_int32),
                 ("team_exponent", ctypes.c_double), ("max_team", ctypes.c_int32),
-                ("rhs_per_lane", ctypes.c_int32)]
+                ("rhs_per_lane", ctypes.c_int32), ("launch", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -60,6 +60,8 @@ int validate_sched(const cg_batch_sched *s) {
         return fail(CG_EINVAL, "team_exponent must be in [0, 3]");
     if (s->max_team < 0) return fail(CG_EINVAL, "max_team must be >= 0");
     if (s->rhs_per_lane < 0 || s->rhs_per_lane > 2) return fail(CG_EINVAL, "rhs_per_lane must be 0, 1 or 2");
+    if (s->launch != CG_BATCH_LAUNCH_COOPERATIVE && s->launch != CG_BATCH_LAUNCH_ORDINARY)
+        return fail(CG_EINVAL, "launch must be CG_BATCH_LAUNCH_COOPERATIVE or CG_BATCH_LAUNCH_ORDINARY");
     return CG_OK;
 }
 
@@ -141,6 +143,7 @@ extern "C" void cg_batch_default_sched(cg_batch_sched *s) {
     s->team_exponent = 1.0;
     s->max_team = 0;
     s->rhs_per_lane = 0;
+    s->launch = CG_BATCH_LAUNCH_COOPERATIVE;
 }
 
 extern "C" int cg_batch_create(int32_t nsys, const int32_t *n, const int64_t *nnz,
@@ -324,7 +327,10 @@ extern "C" int cg_batch_solve(cg_batch *b, const double *B, double *X, double to
         }
         V = 1;
     }
-    const hipError_t le = launch_batch_cg(a, b->grid, b->sched.rows_per_thread, V, st);
+    // the grid is within the kernel's occupancy (assign_teams), so every
+    // workgroup is resident at once in either launch form
+    const hipError_t le = launch_batch_cg(a, b->grid, b->sched.rows_per_thread, V,
+                                          b->sched.launch == CG_BATCH_LAUNCH_COOPERATIVE, st);
     if (le != hipSuccess) {
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);

@@ -45,8 +45,9 @@ struct BatchArgs {
 // variant: rows a thread advances per step (1, 2), right-hand sides per lane
 // (1; 2 needs an even nrhs and 16-byte aligned vectors).
 int batch_blocks_per_cu(int rows_per_thread, int rhs_per_lane);
-// Cooperative launch of the persistent kernel over `grid` workgroups.
-hipError_t launch_batch_cg(const BatchArgs &a, int grid, int rows_per_thread, int rhs_per_lane,
+// Launch of the persistent kernel over `grid` workgroups: cooperative, or
+// ordinary (cooperative = 0) for a grid already checked to be resident.
+hipError_t launch_batch_cg(const BatchArgs &a, int grid, int rows_per_thread, int rhs_per_lane, int cooperative,
                            hipStream_t s);
 
 }  // namespace cgmi

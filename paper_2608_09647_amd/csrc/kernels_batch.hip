@@ -95,6 +95,17 @@ __device__ __forceinline__ void team_sum(const BatchArgs &a, int first, int T, i
 
 // Barrier of the team of system `sys` (T workgroups).  Returns false when the
 // launch is being abandoned (time limit or error flag).
+//
+// Memory model: team members sit on different XCDs, whose L2 caches are not
+// coherent with each other, so what one workgroup writes must be released at
+// agent scope before the counter moves and acquired at agent scope before
+// another workgroup reads it.  Every wave issues its own agent-scope release
+// fence (its stores are written back past its XCD's L2 and complete before
+// the fence returns) before the workgroup barrier, so the one thread that
+// moves the counter does so after every wave's release; after the counter
+// reaches the team's count, thread 0 issues an agent-scope acquire fence and,
+// past the second workgroup barrier, every wave issues its own, so each
+// wave's following loads come after its own invalidation of stale lines.
 __device__ __forceinline__ bool team_sync(const BatchArgs &a, int sys, int T, int &episode,
                                           Shared &S) {
     ++episode;
@@ -102,16 +113,10 @@ __device__ __forceinline__ bool team_sync(const BatchArgs &a, int sys, int T, in
         __syncthreads();
         return true;
     }
-    // every wave's stores have reached the L2 before the barrier; one thread
-    // then writes the L2 back (release) for the whole workgroup
-    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (threadIdx.x == 0) {
         int ok = 1;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        // the L2 write-back the fence starts must be complete before the
-        // counter moves; the fence alone leaves no wait for it here
-        __builtin_amdgcn_s_waitcnt(0);
         __hip_atomic_fetch_add(&a.bar[sys], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const int target = episode * T;
         const uint64_t t0 = wall_clock64();
@@ -127,15 +132,11 @@ __device__ __forceinline__ bool team_sync(const BatchArgs &a, int sys, int T, in
             }
             __builtin_amdgcn_s_sleep(2);
         }
-        // acquire: stale lines of this compute unit's caches are dropped
-        // before any wave of the workgroup reads what the team wrote
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        // the invalidate must be complete before the other waves, released
-        // by the workgroup barrier below, issue their loads
-        __builtin_amdgcn_s_waitcnt(0);
         S.ok = ok;
     }
     __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return S.ok != 0;
 }
 
@@ -564,7 +565,8 @@ int batch_blocks_per_cu(int rows_per_thread, int rhs_per_lane) {
     return rows_per_thread == 2 ? occupancy_of<2, 1>() : occupancy_of<1, 1>();
 }
 
-hipError_t launch_batch_cg(const BatchArgs &a, int grid, int rows_per_thread, int rhs_per_lane, hipStream_t s) {
+hipError_t launch_batch_cg(const BatchArgs &a, int grid, int rows_per_thread, int rhs_per_lane, int cooperative,
+                          hipStream_t s) {
     if (grid <= 0) return hipSuccess;
     BatchArgs args = a;
     void *params[] = {&args};
@@ -575,7 +577,10 @@ hipError_t launch_batch_cg(const BatchArgs &a, int grid, int rows_per_thread, in
     else
         fn = rows_per_thread == 2 ? reinterpret_cast<const void *>(k_batch_cg<2, 1>)
                                   : reinterpret_cast<const void *>(k_batch_cg<1, 1>);
-    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kT), params, 0, s);
+    if (cooperative) return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kT), params, 0, s);
+    // ordinary launch of a grid the caller has checked to be resident (the
+    // team waits give up after their time limit if it were not)
+    return hipLaunchKernel(fn, dim3(grid), dim3(kT), params, 0, s);
 }
 
 }  // namespace cgmi
