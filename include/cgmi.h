@@ -16,8 +16,9 @@
  *     0 <= col < n, columns strictly increasing inside each row.  Passed as
  *     HOST pointers, borrowed only for the duration of the call: the library
  *     copies what it needs.
- *   - Vectors (b, x, y): DEVICE pointers to n float64 values on the handle's
- *     device (for example torch.cuda tensors), owned by the caller.
+ *   - Vectors (b, x, y): n float64 values owned by the caller: DEVICE
+ *     pointers on the handle's device (for example torch.cuda tensors) by
+ *     default, HOST pointers with cg_opts.vectors = CG_VECTORS_HOST.
  *   - Work is ordered on the handle's HIP stream (cg_set_stream; default:
  *     the null stream).  Calls that say "blocking" return after the stream
  *     has drained the work they queued.
@@ -128,7 +129,18 @@ typedef struct cg_opts {
                               (spmv_kind 5); 0: 262,144 (2 MB of float64 p)     */
     double refine_delta;   /* mixed precision: a float64 refinement is made
                               when the float32 residual drops by this factor    */
+    int32_t vectors;       /* CG_VECTORS_DEVICE (default): b, x, y of cg_spmv
+                              and cg_solve are device pointers.
+                              CG_VECTORS_HOST: they are host pointers; the
+                              library copies them to device buffers of its
+                              own (allocated on first use, n float64 each for
+                              b / x and x / y), runs the device path and
+                              copies the result back before returning (both
+                              calls then block).  cg_solve_noalloc takes
+                              device pointers only.                             */
 } cg_opts;
+
+enum { CG_VECTORS_DEVICE = 0, CG_VECTORS_HOST = 1 };  /* cg_opts.vectors   */
 
 /* Per-solve record.  Times in seconds.  Fields follow the per-pass record of
  * Section 4.1: solve time, iterations, convergence, residuals, CPU compute
@@ -178,8 +190,9 @@ void cg_default_opts(cg_opts *o);
 int cg_set_opts(cg_handle *h, const cg_opts *o);
 int cg_get_opts(const cg_handle *h, cg_opts *o);
 
-/* y = A x (Section 3.1, q_i = sum_j A_ij p_j) for all n rows.  x, y: device,
- * n float64 each, must not overlap.  GPU-only handles: queued on the stream
+/* y = A x (Section 3.1, q_i = sum_j A_ij p_j) for all n rows.  x, y: n
+ * float64 each (device pointers, or host pointers with CG_VECTORS_HOST), must
+ * not overlap.  GPU-only handles with device vectors: queued on the stream
  * and returns at once.  Otherwise blocking (the host rows are computed on
  * host threads from a copy of x). */
 int cg_spmv(cg_handle *h, const double *x, double *y);
@@ -191,8 +204,8 @@ int cg_spmv(cg_handle *h, const double *x, double *y);
  * stream. */
 int cg_spmv_f32(cg_handle *h, const float *x, float *y);
 
-/* Solve A x = b by CG (Algorithm 1): x (device, in/out) holds the initial
- * guess and receives the last iterate.  Stops at the top of an iteration when
+/* Solve A x = b by CG (Algorithm 1): x (in/out; device, or host with
+ * CG_VECTORS_HOST) holds the initial guess and receives the last iterate.  Stops at the top of an iteration when
  * sqrt(r^T r) < tol * ||b||_2 (tol = 0: fixed work of maxit iterations).
  * b == 0 gives x = 0.  Blocking.  res (may be NULL) receives the record.
  * Returns CG_OK, CG_MAXIT, CG_EBREAKDOWN or an error. */

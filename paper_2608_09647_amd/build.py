@@ -1,5 +1,18 @@
 """Build libcgmi.so in-tree: HIP kernels with hipcc for gfx950, the host
-runtime with g++ (OpenMP), linked by hipcc."""
+runtime with g++ (OpenMP), linked by hipcc.
+
+    python -m paper_2608_09647_amd.build                      # libcgmi.so
+    python -m paper_2608_09647_amd.build --sanitize address   # libcgmi_asan.so
+    python -m paper_2608_09647_amd.build --sanitize thread    # libcgmi_tsan.so
+
+The sanitizer builds instrument the host runtime only (the C ABI, argument
+validation, the Matrix Market reader, the host complement's OpenMP loops,
+the p exchange); the device code objects are the ordinary ones.  address:
+AddressSanitizer + UndefinedBehaviorSanitizer with g++; thread:
+ThreadSanitizer with LLVM's clang++ and its OpenMP runtime (whose barriers
+ThreadSanitizer understands through the libarcher tool).  Load one in place
+of libcgmi.so with CGMI_LIBRARY=<path> and the matching runtime preloaded
+(see README)."""
 import os
 import subprocess
 import sys
@@ -19,8 +32,20 @@ HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
                # keep packed-float32 instructions out of the device code
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                "-Wno-unused-command-line-argument"]
-GXX_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-fopenmp", "-D__HIP_PLATFORM_AMD__",
-             f"-I{ROCM}/include", "-Wall", "-Wno-unused-function", "-Wno-unused-result"]
+HOST_FLAGS = ["-std=c++17", "-fPIC", "-D__HIP_PLATFORM_AMD__", f"-I{ROCM}/include", "-Wall",
+              "-Wno-unused-function", "-Wno-unused-result"]
+GXX_FLAGS = ["-O3", "-fopenmp", *HOST_FLAGS]
+
+SANITIZERS = {
+    # name: (host compiler, compile flags, link flags, library file)
+    "address": ("g++", ["-O1", "-g", "-fno-omit-frame-pointer", "-fopenmp", "-fsanitize=address,undefined",
+                        "-fno-sanitize-recover=undefined", *HOST_FLAGS],
+                ["-fsanitize=address,undefined", "-fopenmp"], "libcgmi_asan.so"),
+    "thread": (f"{ROCM}/llvm/bin/clang++", ["-O1", "-g", "-fno-omit-frame-pointer", "-fopenmp=libomp",
+                                            "-fsanitize=thread", *HOST_FLAGS],
+               ["-fsanitize=thread", "-fopenmp=libomp", f"-L{ROCM}/llvm/lib", f"-Wl,-rpath,{ROCM}/llvm/lib"],
+               "libcgmi_tsan.so"),
+}
 
 
 def _run(cmd, verbose):
@@ -36,13 +61,18 @@ def _run(cmd, verbose):
         print("\n".join(msgs))
 
 
-def build(verbose: bool = False) -> str:
+def _device_objects(verbose):
     os.makedirs(BUILD, exist_ok=True)
     objs = []
     for src in HIP_SOURCES:
         obj = os.path.join(BUILD, src.replace(".hip", ".o"))
         _run(["hipcc", *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
         objs.append(obj)
+    return objs
+
+
+def build(verbose: bool = False) -> str:
+    objs = _device_objects(verbose)
     for src in HOST_SOURCES:
         obj = os.path.join(BUILD, src.replace(".cpp", ".host.o"))
         _run(["g++", *GXX_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
@@ -53,5 +83,25 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_sanitized(kind: str, verbose: bool = False) -> str:
+    """The library with its host runtime instrumented by a sanitizer (the
+    device objects are the ordinary ones); linked by the host compiler."""
+    cxx, cflags, lflags, name = SANITIZERS[kind]
+    objs = _device_objects(verbose)
+    for src in HOST_SOURCES:
+        obj = os.path.join(BUILD, src.replace(".cpp", f".{kind}.o"))
+        _run([cxx, *cflags, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
+        objs.append(obj)
+    lib = os.path.join(PKG, name)
+    tmp = lib + ".tmp"
+    _run([cxx, "-shared", "-fPIC", *objs, *lflags, f"-L{ROCM}/lib", "-lamdhip64", f"-Wl,-rpath,{ROCM}/lib",
+          "-o", tmp], verbose)
+    os.replace(tmp, lib)
+    return lib
+
+
 if __name__ == "__main__":
-    print(build(verbose=True))
+    if len(sys.argv) > 2 and sys.argv[1] == "--sanitize":
+        print(build_sanitized(sys.argv[2], verbose=True))
+    else:
+        print(build(verbose=True))

@@ -14,12 +14,16 @@ import numpy as np
 
 import torch  # noqa: F401  (loads the HIP runtime the library links against)
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcgmi.so")
+# CGMI_LIBRARY: load another build of the library (e.g. a sanitizer build
+# from build.py --sanitize) in place of the in-tree libcgmi.so
+LIB_PATH = os.environ.get("CGMI_LIBRARY") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                           "libcgmi.so")
 
 CG_OK, CG_MAXIT, CG_EINVAL, CG_ENOMEM, CG_EDEVICE, CG_EBREAKDOWN = 0, 1, -1, -2, -3, -4
 PREC_FP64, PREC_MIXED = 0, 1
 PC_NONE, PC_FSAI = 0, 1
 EXCHANGE_WHOLE, EXCHANGE_HALO, EXCHANGE_MAPPED, EXCHANGE_MANAGED = 0, 1, 2, 3
+VECTORS_DEVICE, VECTORS_HOST = 0, 1
 
 # Every symbol the public header declares (checked by the tests).
 EXPORTED = ["cg_create", "cg_destroy", "cg_set_stream", "cg_default_opts", "cg_set_opts",
@@ -53,7 +57,7 @@ class CgOpts(ctypes.Structure):
                 ("check_every", ctypes.c_int32), ("profile", ctypes.c_int32),
                 ("small_path", ctypes.c_int32), ("spmv_grid", ctypes.c_int32),
                 ("spmv_kind", ctypes.c_int32), ("spmv_colblock", ctypes.c_int32),
-                ("refine_delta", ctypes.c_double)]
+                ("refine_delta", ctypes.c_double), ("vectors", ctypes.c_int32)]
 
 
 class CgResult(ctypes.Structure):
@@ -211,6 +215,14 @@ def _dev_f64(t, n, name):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _host_f64(a, n, name):
+    if not isinstance(a, np.ndarray) or a.dtype != np.float64 or not a.flags.c_contiguous:
+        raise TypeError(f"{name} must be a C-contiguous float64 numpy array")
+    if a.size != n:
+        raise ValueError(f"{name} must have {n} elements")
+    return ctypes.c_void_p(a.ctypes.data)
+
+
 class Solver:
     """A cg_handle: the matrix on the GPU row block [row_begin, row_end)."""
 
@@ -295,6 +307,27 @@ class Solver:
         res = CgResult()
         code = lib().cg_solve_noalloc(self._h, _dev_f64(b, self.n, "b"), _dev_f64(x, self.n, "x"),
                                       float(tol), int(maxit), ctypes.byref(res))
+        if check:
+            _check(code, allow=(CG_OK, CG_MAXIT, CG_EBREAKDOWN))
+        out = res.as_dict()
+        out["code"] = code
+        return x, out
+
+    def spmv_host(self, x, y=None):
+        """cg_spmv with host vectors (numpy; needs set_opts(vectors=VECTORS_HOST))."""
+        if y is None:
+            y = np.empty_like(x)
+        _check(lib().cg_spmv(self._h, _host_f64(x, self.n, "x"), _host_f64(y, self.n, "y")))
+        return y
+
+    def solve_host(self, b, x=None, tol: float = 1e-10, maxit: int = 10000, check: bool = True):
+        """cg_solve with host vectors (numpy; needs set_opts(vectors=VECTORS_HOST)):
+        x (zeros if None) is overwritten with the solution."""
+        if x is None:
+            x = np.zeros_like(b)
+        res = CgResult()
+        code = lib().cg_solve(self._h, _host_f64(b, self.n, "b"), _host_f64(x, self.n, "x"),
+                              float(tol), int(maxit), ctypes.byref(res))
         if check:
             _check(code, allow=(CG_OK, CG_MAXIT, CG_EBREAKDOWN))
         out = res.as_dict()

@@ -147,6 +147,7 @@ static void free_device(cg_handle *h) {
     hipFree(h->d_t); hipFree(h->d_z); hipFree(h->d_r2);
     hipFree(h->d_r32); hipFree(h->d_p32); hipFree(h->d_q32);
     hipFree(h->d_pbuf); hipFree(h->d_p2); hipFree(h->d_x); hipFree(h->d_r); hipFree(h->d_q);
+    hipFree(h->d_vin); hipFree(h->d_vout);
     hipFree(h->d_part_setup); hipFree(h->d_part_pq); hipFree(h->d_part_rr); hipFree(h->d_part_rz);
     hipFree(h->d_state);
     hipFree(h->d_halo_d2h); hipFree(h->d_halo_h2d); hipFree(h->d_pack_d2h); hipFree(h->d_pack_h2d);
@@ -172,6 +173,7 @@ extern "C" void cg_default_opts(cg_opts *o) {
     o->spmv_kind = 0;
     o->spmv_colblock = 0;
     o->refine_delta = 0.01;
+    o->vectors = CG_VECTORS_DEVICE;
 }
 
 extern "C" const char *cg_last_error(void) { return error_message(); }
@@ -335,6 +337,8 @@ extern "C" int cg_set_opts(cg_handle *h, const cg_opts *o) {
         return fail(CG_EINVAL, "mixed precision and preconditioning need a GPU-only handle");
     if (o->spmv_kind < 0 || o->spmv_kind > 6) return fail(CG_EINVAL, "unknown spmv_kind %d", o->spmv_kind);
     if (o->spmv_colblock < 0) return fail(CG_EINVAL, "spmv_colblock must be >= 0");
+    if (o->vectors != CG_VECTORS_DEVICE && o->vectors != CG_VECTORS_HOST)
+        return fail(CG_EINVAL, "vectors must be CG_VECTORS_DEVICE or CG_VECTORS_HOST");
     if (o->precision == CG_PREC_MIXED && o->precond != CG_PC_NONE)
         return fail(CG_EINVAL, "the preconditioned solve runs in float64 only");
     HIP_TRY(hipSetDevice(h->dev));
@@ -1061,6 +1065,8 @@ extern "C" int cg_solve_noalloc(cg_handle *h, const double *b, double *x, double
     if (!h->gpu_only()) return fail(CG_EINVAL, "cg_solve_noalloc needs a GPU-only handle (rows [0, n))");
     if (h->opts.precision != CG_PREC_FP64 || h->opts.precond != CG_PC_NONE || h->shared_p())
         return fail(CG_EINVAL, "cg_solve_noalloc runs plain float64 CG with p in device memory");
+    if (h->opts.vectors != CG_VECTORS_DEVICE)
+        return fail(CG_EINVAL, "cg_solve_noalloc takes device vectors (cg_opts.vectors = CG_VECTORS_DEVICE)");
     if (res) {
         res->rows_gpu = h->m;
         res->nnz_gpu = h->nnz_gpu;
@@ -1104,8 +1110,44 @@ extern "C" int cg_solve_noalloc(cg_handle *h, const double *b, double *x, double
     return rc;
 }
 
+static int solve_impl(cg_handle *h, const double *b, double *x, double tol, int32_t maxit, cg_result *res);
+
+// Host-pointer vectors: device staging buffers of the handle (n float64
+// each, allocated on first use).
+static int ensure_staging(cg_handle *h) {
+    if (h->d_vin) return CG_OK;
+    hipError_t e = dmalloc(&h->d_vin, (size_t)h->n);
+    if (e == hipSuccess) e = dmalloc(&h->d_vout, (size_t)h->n);
+    if (e != hipSuccess) {
+        (void)hipFree(h->d_vin);
+        h->d_vin = h->d_vout = nullptr;
+        return fail(CG_ENOMEM, "staging buffers for host vectors: %s", hipGetErrorString(e));
+    }
+    return CG_OK;
+}
+
 extern "C" int cg_solve(cg_handle *h, const double *b, double *x, double tol, int32_t maxit,
                         cg_result *res) {
+    if (!h || h->opts.vectors != CG_VECTORS_HOST || h->n == 0 || !b || !x)
+        return solve_impl(h, b, x, tol, maxit, res);
+    clear_error();
+    HIP_TRY(hipSetDevice(h->dev));
+    int rc = ensure_staging(h);
+    if (rc) return rc;
+    const size_t bytes = sizeof(double) * (size_t)h->n;
+    const double t0 = now();
+    HIP_TRY(hipMemcpyAsync(h->d_vin, b, bytes, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(h->d_vout, x, bytes, hipMemcpyHostToDevice, h->stream));
+    rc = solve_impl(h, h->d_vin, h->d_vout, tol, maxit, res);
+    if (rc < 0 && rc != CG_EBREAKDOWN) return rc;
+    HIP_TRY(hipMemcpyAsync(x, h->d_vout, bytes, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (res) res->t_solve = now() - t0;   // including the vector copies
+    return rc;
+}
+
+static int solve_impl(cg_handle *h, const double *b, double *x, double tol, int32_t maxit,
+                      cg_result *res) {
     clear_error();
     if (!h) return fail(CG_EINVAL, "handle is NULL");
     if (res) std::memset(res, 0, sizeof *res);
@@ -1182,11 +1224,27 @@ extern "C" int cg_hbm_copy(const double *src, double *dst, int64_t n, void *hip_
     return CG_OK;
 }
 
+static int spmv_impl(cg_handle *h, const double *x, double *y);
+
 extern "C" int cg_spmv(cg_handle *h, const double *x, double *y) {
     clear_error();
     if (!h) return fail(CG_EINVAL, "handle is NULL");
     if (h->n == 0) return CG_OK;
     if (!x || !y) return fail(CG_EINVAL, "x/y is NULL");
+    if (h->opts.vectors != CG_VECTORS_HOST) return spmv_impl(h, x, y);
+    HIP_TRY(hipSetDevice(h->dev));
+    int rc = ensure_staging(h);
+    if (rc) return rc;
+    const size_t bytes = sizeof(double) * (size_t)h->n;
+    HIP_TRY(hipMemcpyAsync(h->d_vin, x, bytes, hipMemcpyHostToDevice, h->stream));
+    rc = spmv_impl(h, h->d_vin, h->d_vout);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(y, h->d_vout, bytes, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return CG_OK;
+}
+
+static int spmv_impl(cg_handle *h, const double *x, double *y) {
     HIP_TRY(hipSetDevice(h->dev));
     const int32_t n = h->n, rb = h->rb, re = h->re, m = h->m;
     if (h->gpu_only()) {

@@ -115,6 +115,8 @@ struct cg_handle {
     double *d_p2 = nullptr;    // GPU-only float64: the second p buffer of the
                                // two-iteration x update (allocated on first use)
     double *d_x = nullptr, *d_r = nullptr, *d_q = nullptr;  // m each
+    double *d_vin = nullptr, *d_vout = nullptr;  // n each: staging of host vectors
+                                                 // (CG_VECTORS_HOST; on first use)
     double *d_part_setup = nullptr;  // 2 x grid: r^T r, b^T b of the residual kernel
     double *d_part_pq = nullptr;
     double *d_part_rr = nullptr;

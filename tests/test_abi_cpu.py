@@ -40,6 +40,7 @@ def test_default_opts(cg):
     o = cg.default_opts()
     assert o.precision == cg.PREC_FP64 and o.precond == cg.PC_NONE
     assert o.exchange == cg.EXCHANGE_WHOLE and o.check_every >= 1 and 0 < o.refine_delta < 1
+    assert o.vectors == cg.VECTORS_DEVICE
 
 
 def _create(cg, n, rp, ci, va, rb=0, re=None):
@@ -91,8 +92,8 @@ def test_null_handle_errors(cg):
 
 
 def test_struct_sizes_match_header(cg):
-    # cg_opts: 10 x int32 + double; cg_result: as laid out in include/cgmi.h
-    assert ctypes.sizeof(cg.CgOpts) == 48
+    # cg_opts: 10 x int32 + double + int32 (padded); cg_result: as laid out in include/cgmi.h
+    assert ctypes.sizeof(cg.CgOpts) == 56
     assert ctypes.sizeof(cg.CgResult) == 128
 
 

@@ -809,3 +809,31 @@ def test_stencil_misaligned_output_uses_one_row_per_lane(cg):
         s.spmv(dev(x), y_odd)
         assert np.array_equal(host(y_odd), ref)
         assert np.array_equal(host(s.spmv(dev(x))), ref)
+
+
+@pytest.mark.parametrize("case", ["small_path", "multi_kernel", "split"])
+def test_host_vectors_match_device_vectors(cg, case):
+    """cg_opts.vectors = CG_VECTORS_HOST: b, x and y are host arrays, staged
+    through the library's own device buffers; results equal the device-pointer
+    calls bit for bit."""
+    p = I.poisson2d_problem(48) if case == "small_path" else I.poisson3d_problem(24)
+    n = p.A.n
+    rb, re = (0, n // 2) if case == "split" else (0, n)
+    x_in = np.random.default_rng(21).uniform(-1, 1, n)
+    with cg.Solver(p.A, rb, re) as s:
+        s.set_opts(host_threads=3)
+        y_dev = host(s.spmv(dev(x_in)))
+        x_dev, r_dev = s.solve(dev(p.b), tol=1e-10, maxit=5000)
+        x_dev = host(x_dev)
+        s.set_opts(vectors=cg.VECTORS_HOST, host_threads=3)
+        y_host = s.spmv_host(x_in)
+        x0 = np.zeros(n)
+        x_host, r_host = s.solve_host(p.b, x0, tol=1e-10, maxit=5000)
+        # a rejected use: the allocation-free solve takes device vectors only
+        if case != "split":
+            _, rn = s.solve_noalloc(dev(p.b), torch.zeros(n, dtype=torch.float64, device="cuda"), check=False)
+            assert rn["code"] == cg.CG_EINVAL
+    assert x_host is x0
+    assert np.array_equal(y_host, y_dev) and np.array_equal(x_host, x_dev)
+    assert r_host["code"] == r_dev["code"] == cg.CG_OK and r_host["iterations"] == r_dev["iterations"]
+    assert r_host["rel_res_true"] == r_dev["rel_res_true"]
