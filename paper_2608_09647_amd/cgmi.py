@@ -239,7 +239,10 @@ class Solver:
                                self.row_begin, self.row_end, ctypes.byref(h)))
         self._h = h
         del self._rp, self._ci, self._va   # the library holds its own copy
-        self.set_stream(torch.cuda.current_stream())
+        if self.row_begin < self.row_end or torch.cuda.is_available():
+            # the handle's work goes on torch's current stream (a host-only
+            # handle without a device has no stream)
+            self.set_stream(torch.cuda.current_stream())
 
     def close(self):
         if getattr(self, "_h", None):

@@ -210,7 +210,36 @@ extern "C" int cg_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const i
         delete h;
         return code;
     };
-    if (hipGetDevice(&h->dev) != hipSuccess) return bail(fail(CG_EDEVICE, "no HIP device"));
+    {
+        // A host-only handle (row_begin == row_end: the paper's CPU-only
+        // configuration) needs no device; without one it runs on host
+        // threads alone and takes host vectors.  Any GPU rows need a device.
+        int count = 0;
+        const bool have_dev = hipGetDeviceCount(&count) == hipSuccess && count > 0 &&
+                              hipGetDevice(&h->dev) == hipSuccess;
+        if (!have_dev && h->m == 0 && n > 0) {
+            h->nodev = true;
+            h->dev = -1;
+            h->opts.vectors = CG_VECTORS_HOST;
+            try {
+                h->h_x.assign(n, 0.0);
+                h->h_r.assign(n, 0.0);
+                h->h_q.assign(n, 0.0);
+                h->h_b.assign(n, 0.0);
+                h->h_p_store.assign(n, 0.0);
+            } catch (...) {
+                delete h;
+                return fail(CG_ENOMEM, "out of host memory");
+            }
+            h->h_p = h->h_p_store.data();
+            *out = h;
+            return CG_OK;
+        }
+        if (!have_dev) {
+            delete h;
+            return fail(CG_EDEVICE, "no HIP device (rows [%d, %d) are to run on the GPU)", row_begin, row_end);
+        }
+    }
     // device address of the static scratch of cg_solve_noalloc, once per
     // device (a failure is kept and reported by that entry point)
     (void)scratch_setup();
@@ -304,6 +333,10 @@ extern "C" int cg_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const i
 
 extern "C" void cg_destroy(cg_handle *h) {
     if (!h) return;
+    if (h->nodev) {
+        delete h;
+        return;
+    }
     hipSetDevice(h->dev);
     if (h->stream) hipStreamSynchronize(h->stream);
     else hipDeviceSynchronize();
@@ -339,6 +372,13 @@ extern "C" int cg_set_opts(cg_handle *h, const cg_opts *o) {
     if (o->spmv_colblock < 0) return fail(CG_EINVAL, "spmv_colblock must be >= 0");
     if (o->vectors != CG_VECTORS_DEVICE && o->vectors != CG_VECTORS_HOST)
         return fail(CG_EINVAL, "vectors must be CG_VECTORS_DEVICE or CG_VECTORS_HOST");
+    if (h->nodev) {
+        // a host-only handle without a device: host vectors, p in host memory
+        if (o->vectors != CG_VECTORS_HOST || shared)
+            return fail(CG_EINVAL, "a handle without a device takes host vectors and keeps p in host memory");
+        h->opts = *o;
+        return CG_OK;
+    }
     if (o->precision == CG_PREC_MIXED && o->precond != CG_PC_NONE)
         return fail(CG_EINVAL, "the preconditioned solve runs in float64 only");
     HIP_TRY(hipSetDevice(h->dev));
@@ -372,6 +412,10 @@ extern "C" int cg_slice_info(const cg_handle *h, int32_t *rows_gpu, int64_t *nnz
 
 extern "C" int cg_read_slice(const cg_handle *h, int32_t *row_ptr, int32_t *col_idx, double *val) {
     if (!h) return fail(CG_EINVAL, "handle is NULL");
+    if (h->m == 0) {   // no GPU rows: the rebased row pointers are {0}
+        if (row_ptr) row_ptr[0] = 0;
+        return CG_OK;
+    }
     HIP_TRY(hipSetDevice(h->dev));
     if (row_ptr) HIP_TRY(hipMemcpy(row_ptr, h->A.d_rp, sizeof(int32_t) * ((size_t)h->m + 1), hipMemcpyDeviceToHost));
     if (h->nnz_gpu && col_idx)
@@ -903,8 +947,14 @@ static int solve_split(cg_handle *h, const double *b, double *x, double tol, int
     double *hx = h->h_x.data(), *hr = h->h_r.data(), *hq = h->h_q.data(), *hb = h->h_b.data();
     double *hp = h->h_p;
     int rc = CG_OK;
+    // host-only handle with host vectors: b and x are read and written in
+    // place of device copies (no HIP call in the whole solve)
+    const bool host_io = !gpu && h->opts.vectors == CG_VECTORS_HOST;
     // initial transfers: b and x to the host, the GPU block of x to the device buffer
-    {
+    if (host_io) {
+        std::memcpy(hb, b, sizeof(double) * n);
+        std::memcpy(hx, x, sizeof(double) * n);
+    } else {
         const double t0 = now();
         HIP_TRY(hipMemcpyAsync(hb, b, sizeof(double) * n, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipMemcpyAsync(hx, x, sizeof(double) * n, hipMemcpyDeviceToHost, st));
@@ -942,8 +992,12 @@ static int solve_split(cg_handle *h, const double *b, double *x, double tol, int
     int status = CG_MAXIT;
     int32_t k = 0;
     if (bnorm == 0.0) {
-        HIP_TRY(hipMemsetAsync(x, 0, sizeof(double) * n, st));
-        HIP_TRY(hipStreamSynchronize(st));
+        if (host_io) {
+            std::memset(x, 0, sizeof(double) * n);
+        } else {
+            HIP_TRY(hipMemsetAsync(x, 0, sizeof(double) * n, st));
+            HIP_TRY(hipStreamSynchronize(st));
+        }
         if (res) { res->status = CG_OK; res->converged = 1; }
         return CG_OK;
     }
@@ -1016,7 +1070,9 @@ static int solve_split(cg_handle *h, const double *b, double *x, double tol, int
     }
     if (status == CG_MAXIT && (std::sqrt(rho) < tol * bnorm || rho == 0.0)) status = CG_OK;
     // final transfers: host rows of x and the GPU block back into the caller's x
-    {
+    if (host_io) {
+        std::memcpy(x, hx, sizeof(double) * n);
+    } else {
         const double t0 = now();
         if (rb > 0) HIP_TRY(hipMemcpyAsync(x, hx, sizeof(double) * rb, hipMemcpyHostToDevice, st));
         if (re < n) HIP_TRY(hipMemcpyAsync(x + re, hx + re, sizeof(double) * (n - re), hipMemcpyHostToDevice, st));
@@ -1128,7 +1184,9 @@ static int ensure_staging(cg_handle *h) {
 
 extern "C" int cg_solve(cg_handle *h, const double *b, double *x, double tol, int32_t maxit,
                         cg_result *res) {
-    if (!h || h->opts.vectors != CG_VECTORS_HOST || h->n == 0 || !b || !x)
+    // device vectors, or a host-only handle (its solve reads and writes host
+    // vectors directly)
+    if (!h || h->opts.vectors != CG_VECTORS_HOST || h->n == 0 || !b || !x || h->m == 0)
         return solve_impl(h, b, x, tol, maxit, res);
     clear_error();
     HIP_TRY(hipSetDevice(h->dev));
@@ -1164,7 +1222,7 @@ static int solve_impl(cg_handle *h, const double *b, double *x, double tol, int3
         if (res) res->converged = 1;
         return CG_OK;
     }
-    HIP_TRY(hipSetDevice(h->dev));
+    if (!h->nodev) HIP_TRY(hipSetDevice(h->dev));
     const double t0 = now();
     int rc;
     // mapped / managed modes: the solve's p is the shared allocation
@@ -1232,6 +1290,13 @@ extern "C" int cg_spmv(cg_handle *h, const double *x, double *y) {
     if (h->n == 0) return CG_OK;
     if (!x || !y) return fail(CG_EINVAL, "x/y is NULL");
     if (h->opts.vectors != CG_VECTORS_HOST) return spmv_impl(h, x, y);
+    if (h->m == 0) {   // host-only handle: every row on host threads, in place
+        host_reduce(h, [&](int32_t i) {
+            y[i] = host_row_dot(h, i, x);
+            return 0.0;
+        });
+        return CG_OK;
+    }
     HIP_TRY(hipSetDevice(h->dev));
     int rc = ensure_staging(h);
     if (rc) return rc;

@@ -138,7 +138,9 @@ struct cg_handle {
     struct FsaiSetup *fsai = nullptr;   // learned-factor workspace (fsai.cpp)
 
     // split mode
-    double *h_p = nullptr;  // pinned, length n
+    double *h_p = nullptr;  // pinned, length n (device-less handles: h_p_store)
+    std::vector<double> h_p_store;
+    bool nodev = false;     // host-only handle created without a HIP device
     std::vector<double> h_x, h_r, h_q, h_b;
     std::vector<int32_t> halo_d2h, halo_h2d;  // global column ids
     int32_t *d_halo_d2h = nullptr, *d_halo_h2d = nullptr;

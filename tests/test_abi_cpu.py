@@ -155,3 +155,28 @@ def test_hbm_copy_rejects_bad_arguments_before_any_device_call(cg):
     assert L.cg_hbm_copy(None, None, 0, None) == cg.CG_OK
     assert L.cg_hbm_copy(None, None, 5, None) == cg.CG_EINVAL
     assert L.cg_hbm_copy(None, None, -1, None) == cg.CG_EINVAL
+
+
+def test_host_only_handle_runs_on_host_threads(cg):
+    """A host-only handle (rows [0, 0): the paper's CPU-only configuration)
+    needs no device: with host vectors its SpMV and CG run on host threads
+    alone (also where no GPU is present), the SpMV equal to the oracle's bit
+    for bit (rows summed in CSR order), the solve meeting the oracle's bar."""
+    import oracle
+    from paper_2608_09647_amd import inputs as I
+    p = I.poisson3d_problem(16)
+    with cg.Solver(p.A, 0, 0) as s:
+        s.set_opts(vectors=cg.VECTORS_HOST, host_threads=3)
+        x_in = np.random.default_rng(3).uniform(-1, 1, p.A.n)
+        y = s.spmv_host(x_in)
+        x, res = s.solve_host(p.b, tol=1e-10, maxit=5000)
+        rows, nnz = s.slice_info()
+    assert rows == 0 and nnz == 0
+    assert np.array_equal(y, oracle.spmv(p.A, x_in))
+    ref = oracle.cg(p.A, p.b, tol=1e-10, maxit=5000)
+    assert res["code"] == cg.CG_OK and res["rows_cpu"] == p.A.n and res["rows_gpu"] == 0
+    assert abs(res["iterations"] - ref["iterations"]) <= 2
+    true = np.linalg.norm(p.b - oracle.spmv(p.A, x)) / np.linalg.norm(p.b)
+    assert true <= 1.01e-10 and abs(res["rel_res_true"] - true) <= 1e-3 * true
+    lam = 2 - 2 * np.cos(np.arange(1, 17) * np.pi / 17)
+    assert np.linalg.norm(x - ref["x"]) <= 2 * (lam.max() / lam.min()) * 1e-10 * np.linalg.norm(ref["x"])
