@@ -94,6 +94,17 @@ int cg_fsai_train_step(cg_fsai_trainer *t, int32_t nsel, const int32_t *sys,
 /* Current float32 master parameters (host, CG_FSAI_NPARAMS floats). */
 int cg_fsai_get_params(const cg_fsai_trainer *t, float *theta);
 
+/* The whole optimiser state, for checkpoints: the float32 master parameters,
+ * Adam's first and second moment estimates (CG_FSAI_NPARAMS floats each,
+ * host) and the number of Adam steps taken (the next step is step + 1).
+ * Any of the arrays may be NULL (not read / not written).  set: step >= 0.
+ * A trainer restored from a checkpoint continues as the one that wrote it
+ * (the next step uses step + 1 in the bias correction); its loss gradients
+ * are summed with float32 atomics, so two runs over the same samples agree
+ * to rounding, not bit for bit. */
+int cg_fsai_get_state(const cg_fsai_trainer *t, float *theta, float *m, float *v, int32_t *step);
+int cg_fsai_set_state(cg_fsai_trainer *t, const float *theta, const float *m, const float *v, int32_t step);
+
 /* Features of system sys as the device computed them (host, n x 12 floats,
  * each already rounded to bfloat16). */
 int cg_fsai_features(const cg_fsai_trainer *t, int32_t sys, float *feats);

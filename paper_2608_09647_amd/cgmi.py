@@ -33,7 +33,8 @@ NOALLOC_SCRATCH_BYTES = 64 << 20
 # include/cgmi_fsai.h
 EXPORTED_FSAI = ["cg_fsai_setup", "cg_set_fsai", "cg_fsai_classic", "cg_fsai_factor_info", "cg_fsai_read_factor",
                  "cg_fsai_trainer_create", "cg_fsai_trainer_destroy", "cg_fsai_loss_grad",
-                 "cg_fsai_train_step", "cg_fsai_get_params", "cg_fsai_features"]
+                 "cg_fsai_train_step", "cg_fsai_get_params", "cg_fsai_get_state", "cg_fsai_set_state",
+                 "cg_fsai_features"]
 FSAI_NPARAMS = 5317
 # include/cgmi_batch.h
 EXPORTED_BATCH = ["cg_batch_create", "cg_batch_destroy", "cg_batch_set_stream", "cg_batch_layout",
@@ -157,6 +158,8 @@ def lib() -> ctypes.CDLL:
         L.cg_fsai_loss_grad.argtypes = [_vp, _vp, i32, _vp, i32, _vp, ctypes.POINTER(dbl), _vp, _vp]
         L.cg_fsai_train_step.argtypes = [_vp, i32, _vp, i32, _vp, dbl, ctypes.POINTER(dbl)]
         L.cg_fsai_get_params.argtypes = [_vp, _vp]
+        L.cg_fsai_get_state.argtypes = [_vp, _vp, _vp, _vp, ctypes.POINTER(i32)]
+        L.cg_fsai_set_state.argtypes = [_vp, _vp, _vp, _vp, i32]
         L.cg_fsai_features.argtypes = [_vp, i32, _vp]
         L.cg_fsai_classic.argtypes = [_vp]
         for name in EXPORTED_FSAI:
@@ -454,6 +457,19 @@ class FsaiTrainer:
         th = np.empty(FSAI_NPARAMS, np.float32)
         _check(lib().cg_fsai_get_params(self._t, th.ctypes.data))
         return th
+
+    def state(self) -> dict:
+        """The optimiser state: theta, Adam's m and v (float32) and the step count."""
+        th, m, v = (np.empty(FSAI_NPARAMS, np.float32) for _ in range(3))
+        step = ctypes.c_int32()
+        _check(lib().cg_fsai_get_state(self._t, th.ctypes.data, m.ctypes.data, v.ctypes.data, ctypes.byref(step)))
+        return {"theta": th, "m": m, "v": v, "step": int(step.value)}
+
+    def set_state(self, theta, m, v, step: int) -> None:
+        arrs = [np.ascontiguousarray(a, np.float32) for a in (theta, m, v)]
+        if any(a.size != FSAI_NPARAMS for a in arrs):
+            raise ValueError(f"theta, m and v must have {FSAI_NPARAMS} entries")
+        _check(lib().cg_fsai_set_state(self._t, *(a.ctypes.data for a in arrs), int(step)))
 
     def features(self, sys: int) -> np.ndarray:
         f = np.empty((self.sizes[int(sys)], 12), np.float32)

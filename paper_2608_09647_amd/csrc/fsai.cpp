@@ -831,6 +831,32 @@ extern "C" int cg_fsai_get_params(const cg_fsai_trainer *t, float *theta) {
     return CG_OK;
 }
 
+extern "C" int cg_fsai_get_state(const cg_fsai_trainer *t, float *theta, float *m, float *v, int32_t *step) {
+    clear_error();
+    if (!t) return fail(CG_EINVAL, "NULL trainer");
+    HIP_TRY(hipSetDevice(t->dev));
+    if (t->stream) HIP_TRY(hipStreamSynchronize(t->stream));
+    if (theta) HIP_TRY(hipMemcpy(theta, t->d_theta, sizeof(float) * kNParams, hipMemcpyDeviceToHost));
+    if (m) HIP_TRY(hipMemcpy(m, t->d_m, sizeof(float) * kNParams, hipMemcpyDeviceToHost));
+    if (v) HIP_TRY(hipMemcpy(v, t->d_v, sizeof(float) * kNParams, hipMemcpyDeviceToHost));
+    if (step) *step = t->step;
+    return CG_OK;
+}
+
+extern "C" int cg_fsai_set_state(cg_fsai_trainer *t, const float *theta, const float *m, const float *v,
+                                 int32_t step) {
+    clear_error();
+    if (!t) return fail(CG_EINVAL, "NULL trainer");
+    if (step < 0) return fail(CG_EINVAL, "step must be >= 0");
+    HIP_TRY(hipSetDevice(t->dev));
+    if (t->stream) HIP_TRY(hipStreamSynchronize(t->stream));
+    if (theta) HIP_TRY(hipMemcpy(t->d_theta, theta, sizeof(float) * kNParams, hipMemcpyHostToDevice));
+    if (m) HIP_TRY(hipMemcpy(t->d_m, m, sizeof(float) * kNParams, hipMemcpyHostToDevice));
+    if (v) HIP_TRY(hipMemcpy(t->d_v, v, sizeof(float) * kNParams, hipMemcpyHostToDevice));
+    t->step = step;
+    return CG_OK;
+}
+
 extern "C" int cg_fsai_features(const cg_fsai_trainer *t, int32_t sys, float *feats) {
     clear_error();
     if (!t || !feats) return fail(CG_EINVAL, "NULL argument");

@@ -46,20 +46,54 @@ def sample(rng, sizes, nsel: int, rows_per: int):
     return sys, rows
 
 
-def train(trainer: "cgmi.FsaiTrainer", steps: int, nsel: int = 8, rows_per: int = 1024,
-          lr: float = 1e-3, seed: int = 0, lr_final: float | None = None, log=None) -> dict:
-    """Adam steps on random (system, rows) samples.  With lr_final the
-    learning rate decays geometrically from lr to lr_final.  Returns the loss
-    history and timing."""
+def _sampler(seed: int, start: int, sizes, nsel: int, rows_per: int):
+    """The sample generator of a run with this seed, advanced past its first
+    `start` steps (so a resumed run draws the samples the uninterrupted run
+    would have drawn)."""
     rng = np.random.default_rng([seed, 11])
+    for _ in range(start):
+        sample(rng, sizes, nsel, rows_per)
+    return rng
+
+
+def train(trainer: "cgmi.FsaiTrainer", steps: int, nsel: int = 8, rows_per: int = 1024,
+          lr: float = 1e-3, seed: int = 0, lr_final: float | None = None, log=None,
+          start: int = 0, total: int | None = None) -> dict:
+    """Adam steps on random (system, rows) samples.  With lr_final the
+    learning rate decays geometrically from lr to lr_final over `total`
+    steps (default: steps).  start > 0 resumes a run of `total` steps after
+    its first `start` steps (a trainer restored by load_checkpoint): the
+    samples and learning rates are those of the uninterrupted run.  Returns
+    the loss history and timing."""
+    total = steps + start if total is None else total
     rows_per = min(rows_per, min(trainer.sizes))
+    rng = _sampler(seed, start, trainer.sizes, nsel, rows_per)
     losses = []
     t0 = time.perf_counter()
-    decay = 1.0 if lr_final is None or steps <= 1 else (lr_final / lr) ** (1.0 / (steps - 1))
-    for k in range(steps):
+    decay = 1.0 if lr_final is None or total <= 1 else (lr_final / lr) ** (1.0 / (total - 1))
+    for k in range(start, start + steps):
         sys, rows = sample(rng, trainer.sizes, nsel, rows_per)
         losses.append(trainer.step(sys, rows, lr * decay ** k))
-        if log and (k % max(1, steps // 10) == 0 or k == steps - 1):
+        if log and (k % max(1, total // 10) == 0 or k == start + steps - 1):
             log(f"step {k}: loss {losses[-1]:.4e}")
-    return {"losses": losses, "seconds": time.perf_counter() - t0, "steps": steps,
-            "nsel": nsel, "rows_per": rows_per, "lr": lr, "lr_final": lr_final}
+    return {"losses": losses, "seconds": time.perf_counter() - t0, "steps": steps, "start": start,
+            "total": total, "nsel": nsel, "rows_per": rows_per, "lr": lr, "lr_final": lr_final}
+
+
+def save_checkpoint(path: str, trainer: "cgmi.FsaiTrainer", seed: int, **meta) -> None:
+    """theta, Adam's m and v, the step count and the sampling seed in one
+    .npz (plain arrays, no pickled objects); meta adds scalar settings."""
+    st = trainer.state()
+    extra = {k: np.asarray(v) for k, v in meta.items()}
+    np.savez(path, theta=st["theta"], m=st["m"], v=st["v"], step=np.int64(st["step"]),
+             seed=np.int64(seed), **extra)
+
+
+def load_checkpoint(path: str, trainer: "cgmi.FsaiTrainer" | None = None) -> dict:
+    """Read a checkpoint (allow_pickle off); with a trainer, restore its state."""
+    with np.load(path, allow_pickle=False) as z:
+        ck = {k: z[k] for k in z.files}
+    ck["step"], ck["seed"] = int(ck["step"]), int(ck["seed"])
+    if trainer is not None:
+        trainer.set_state(ck["theta"], ck["m"], ck["v"], ck["step"])
+    return ck

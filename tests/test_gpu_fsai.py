@@ -420,3 +420,41 @@ def test_classic_fsai_rejections(cg):
     with cg.Solver(neg) as s:
         with pytest.raises(cg.CgError, match="not positive definite"):
             s.fsai_classic()
+
+
+def test_checkpoint_round_trip_and_resume(cg, tmp_path):
+    """A checkpoint (theta, Adam m and v, step, seed in an .npz) restores the
+    optimiser state bit for bit into a fresh trainer; training 3 steps,
+    checkpointing, restoring and training 3 more follows the run of 6 steps
+    straight (same samples and learning rates; the loss gradient's float32
+    atomic sums round independently in each run)."""
+    from paper_2608_09647_amd import fsai
+    systems = [field(32, 32, 50 + k) for k in range(4)]
+    th = fsai.init_params(4)
+    kw = dict(nsel=2, rows_per=128, lr=1e-3, lr_final=5e-4, seed=9)
+    tr = cg.FsaiTrainer(systems, th)
+    full = fsai.train(tr, 6, **kw)
+    ref = tr.state()
+    tr.close()
+    tr = cg.FsaiTrainer(systems, th)
+    first = fsai.train(tr, 3, total=6, **kw)
+    saved = tr.state()
+    path = str(tmp_path / "fsai.npz")
+    fsai.save_checkpoint(path, tr, seed=kw["seed"], lr=kw["lr"])
+    tr.close()
+    tr = cg.FsaiTrainer(systems, fsai.init_params(123))   # another start: the checkpoint replaces it
+    ck = fsai.load_checkpoint(path, tr)
+    assert ck["step"] == 3 and ck["seed"] == 9 and float(ck["lr"]) == kw["lr"]
+    back = tr.state()
+    assert back["step"] == 3
+    for k in ("theta", "m", "v"):
+        assert np.array_equal(back[k], saved[k]), k
+    rest = fsai.train(tr, 3, start=ck["step"], total=6, **kw)
+    got = tr.state()
+    tr.close()
+    assert got["step"] == ref["step"] == 6
+    np.testing.assert_allclose(first["losses"] + rest["losses"], full["losses"], rtol=1e-5)
+    d = np.abs(got["theta"].astype(np.float64) - ref["theta"])
+    print(f"[ckpt] resumed vs straight: max |d theta| {d.max():.3e}, 99.9% {np.quantile(d, 0.999):.3e}",
+          flush=True)
+    assert np.quantile(d, 0.999) <= 0.05 * kw["lr"] and d.max() <= 6 * 2 * kw["lr"]
