@@ -382,6 +382,36 @@ def cpu_baseline_mixed(prob, iterations: int, target_s: float = 12.0) -> dict:
                       f"CG ({dt:.1f} s), scaled to the {iterations} iterations of the GPU solve"}
 
 
+def gather_ceiling(count: int, reps: int = 5) -> dict:
+    """The library's plain random gather (cg_gather) of `count` float64 values
+    with uniformly random int32 indices, from a vector of one column block
+    (262,144 values, 2 MB: held in each XCD's L2) and from the whole 2M
+    vector (16 MB: held in the last-level cache): gathers per second
+    (median of `reps` launches, HIP events on torch's stream)."""
+    import torch
+    from paper_2608_09647_amd import cgmi
+    out = {}
+    g = torch.Generator(device="cuda").manual_seed(17)
+    dst = torch.empty(count, dtype=torch.float64, device="cuda")
+    for name, size in (("l2_2MB", 262_144), ("llc_16MB", 2_000_000)):
+        src = torch.rand(size, dtype=torch.float64, device="cuda")
+        idx = torch.randint(0, size, (count,), dtype=torch.int32, device="cuda", generator=g)
+        cgmi.gather(src, idx, dst)
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            cgmi.gather(src, idx, dst)
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e-3)
+        t = sorted(ts)[len(ts) // 2]
+        out[name] = {"vector_bytes": 8 * size, "gathers": count, "seconds": t, "gathers_per_s": count / t,
+                     "bytes_per_s_idx_dst_gathered": 20 * count / t}
+        del src, idx
+    return out
+
+
 def bench_mixed(args) -> int:
     """Random SPD n = 2M: float32-inner/float64-refined CG vs plain float64 CG to 1e-10."""
     import numpy as np
@@ -398,6 +428,11 @@ def bench_mixed(args) -> int:
     n, nnz = prob.A.n, prob.A.nnz
     a32 = spmv_algorithmic_bytes_f32(n, nnz) / (us32 * 1e-6) / 1e9
     a64 = spmv_algorithmic_bytes(n, nnz) / (us64 * 1e-6) / 1e9
+    # the ceiling for SpMVs bound by random gathers: one column block's
+    # gathers from an L2-resident segment, scaled to the SpMV's nnz gathers
+    gc = gather_ceiling(nnz // 8)
+    t_g = nnz / gc["l2_2MB"]["gathers_per_s"]
+    print(f"[bench] gather ceiling {gc}", file=sys.stderr, flush=True)
     line = _line("time to 1e-10 true relative residual: float32-inner/float64-refined CG "
                  "vs plain float64 CG", out["mixed"]["seconds"], "s", args,
                  1e3 * out["mixed"]["seconds"],
@@ -407,6 +442,10 @@ def bench_mixed(args) -> int:
                  mixed_rel_error_vs_fp64_solution=err,
                  spmv_us={"float32": us32, "float64": us64},
                  spmv_gbs={"float32": a32, "float64": a64},
+                 gather_ceiling=gc,
+                 spmv_frac_of_gather_ceiling={"float64": 1e6 * t_g / us64, "float32": 1e6 * t_g / us32,
+                                              "meaning": "time of the library's plain gather of nnz "
+                                                         "values from a 2 MB vector / SpMV time"},
                  roofline={"bound": "hbm", "achieved": a32, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": a32 / HBM_PEAK_GBS, "traffic": None,
                            "note": "float32 column-blocked SpMV, CSR-algorithmic bytes "

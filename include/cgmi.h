@@ -248,6 +248,15 @@ int cg_read_slice(const cg_handle *h, int32_t *row_ptr, int32_t *col_idx, double
  * CG_EINVAL for NULL pointers with n > 0 or n < 0. */
 int cg_hbm_copy(const double *src, double *dst, int64_t n, void *hip_stream);
 
+/* dst[i] = src[idx[i]] for i < n on the current device (device pointers;
+ * idx int32; dst must not overlap src or idx): a plain random gather, eight
+ * 8-byte gathers in flight per thread, the achievable rate of gathers an
+ * SpMV with scattered columns is reported against (e.g. from a src that
+ * fits the L2 or the last-level cache).  Every idx[i] must lie in the src
+ * allocation: the indices are not checked on the device.  Queued on
+ * hip_stream.  CG_EINVAL for NULL pointers with n > 0 or n < 0. */
+int cg_gather(const double *src, const int32_t *idx, double *dst, int64_t n, void *hip_stream);
+
 /* Message for the last error on this thread ("" if none). */
 const char *cg_last_error(void);
 

@@ -28,7 +28,7 @@ VECTORS_DEVICE, VECTORS_HOST = 0, 1
 # Every symbol the public header declares (checked by the tests).
 EXPORTED = ["cg_create", "cg_destroy", "cg_set_stream", "cg_default_opts", "cg_set_opts",
             "cg_get_opts", "cg_spmv", "cg_spmv_f32", "cg_solve", "cg_solve_noalloc", "cg_slice_info",
-            "cg_read_slice", "cg_hbm_copy", "cg_last_error"]
+            "cg_read_slice", "cg_hbm_copy", "cg_gather", "cg_last_error"]
 NOALLOC_SCRATCH_BYTES = 64 << 20
 # include/cgmi_fsai.h
 EXPORTED_FSAI = ["cg_fsai_setup", "cg_set_fsai", "cg_fsai_classic", "cg_fsai_factor_info", "cg_fsai_read_factor",
@@ -147,6 +147,8 @@ def lib() -> ctypes.CDLL:
         L.cg_last_error.restype = ctypes.c_char_p
         L.cg_hbm_copy.argtypes = [_vp, _vp, ctypes.c_int64, _vp]
         L.cg_hbm_copy.restype = ctypes.c_int
+        L.cg_gather.argtypes = [_vp, _vp, _vp, ctypes.c_int64, _vp]
+        L.cg_gather.restype = ctypes.c_int
         i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
         L.cg_fsai_setup.argtypes = [_vp, _vp]
         L.cg_set_fsai.argtypes = [_vp, i64, _vp, _vp, _vp]
@@ -576,6 +578,21 @@ def hbm_copy(src, dst, stream=None) -> None:
         stream = torch.cuda.current_stream()
     _check(lib().cg_hbm_copy(_dev_f64(src.view(-1), n, "src"), _dev_f64(dst.view(-1), n, "dst"), n,
                              ctypes.c_void_p(stream.cuda_stream)))
+
+
+def gather(src, idx, dst, stream=None) -> None:
+    """dst[i] = src[idx[i]] with the library's gather kernel (device tensors:
+    float64 src and dst, int32 idx; every index must lie inside src)."""
+    if not (src.is_cuda and idx.is_cuda and dst.is_cuda) or idx.dtype != torch.int32 \
+            or src.dtype != torch.float64 or dst.dtype != torch.float64:
+        raise TypeError("src, dst: CUDA float64; idx: CUDA int32")
+    if idx.numel() != dst.numel() or not (src.is_contiguous() and idx.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("idx and dst must be contiguous with the same length")
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    ptr = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+    _check(lib().cg_gather(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(idx.data_ptr()),
+                           ctypes.c_void_p(dst.data_ptr()), int(idx.numel()), ctypes.c_void_p(ptr)))
 
 
 def read_matrix_market(path: str, threads: int = 0):

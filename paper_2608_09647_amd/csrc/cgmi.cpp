@@ -1282,6 +1282,20 @@ extern "C" int cg_hbm_copy(const double *src, double *dst, int64_t n, void *hip_
     return CG_OK;
 }
 
+extern "C" int cg_gather(const double *src, const int32_t *idx, double *dst, int64_t n, void *hip_stream) {
+    clear_error();
+    if (n < 0) return fail(CG_EINVAL, "n must be >= 0");
+    if (n == 0) return CG_OK;
+    if (!src || !idx || !dst) return fail(CG_EINVAL, "src/idx/dst is NULL");
+    int dev = 0, cus = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int64_t chunks = std::max<int64_t>(1, (n + 2047) / 2048);   // 8 entries per thread
+    const int grid = (int)std::min<int64_t>(chunks, (int64_t)std::max(8, cus * 16));
+    HIP_TRY(launch_gather_ref(src, idx, dst, n, grid, static_cast<hipStream_t>(hip_stream)));
+    return CG_OK;
+}
+
 static int spmv_impl(cg_handle *h, const double *x, double *y);
 
 extern "C" int cg_spmv(cg_handle *h, const double *x, double *y) {

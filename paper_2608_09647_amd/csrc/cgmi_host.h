@@ -51,6 +51,7 @@ struct DevMatrix {
     size_t sell_slots = 0;
     float *d_val32 = nullptr, *d_sell_val32 = nullptr;
     uint8_t *d_sell_len = nullptr;    // sliced layout: row lengths (ntiles x 64 bytes)
+    int32_t *d_tile_row = nullptr;    // adaptive stream tiles: first row of each tile
     uint32_t *d_sell_idx = nullptr;   // dictionary-sliced layout
     int32_t *d_sell_dict = nullptr;
     int32_t *d_st_off = nullptr, *d_st_offs = nullptr;   // stencil-sliced layout
@@ -66,7 +67,7 @@ struct DevMatrix {
         return CsrDev{m, d_rp, d_ci, d_val, sched.identity ? nullptr : d_rows,
                       d_sell_off, d_sell_ci, d_sell_val, d_val32, d_sell_val32,
                       d_sell_idx, d_sell_dict, pad_col_base, cb,
-                      d_st_off, d_st_offs, d_st_mask, d_st_val, d_sell_len};
+                      d_st_off, d_st_offs, d_st_mask, d_st_val, d_sell_len, d_tile_row};
     }
 };
 

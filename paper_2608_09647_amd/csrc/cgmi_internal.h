@@ -139,6 +139,7 @@ struct CsrDev {
     const uint8_t *st_mask;   //   per-row slot bits
     const double *st_val;     //   slot-major values
     const uint8_t *sell_len;  // sliced layout: row lengths, one byte per row (64 per slice)
+    const int32_t *tile_row;  // adaptive stream tiles: first row of each tile (ntiles + 1)
 };
 
 // Per-block operands of the column-blocked tiling (kept on the host by the

@@ -429,7 +429,40 @@ int build_blocks(DevMatrix &M, int32_t block_cols, int cus, int grid_cap, bool n
         std::vector<int32_t> rows;
         int64_t bmax = 0;
         for (int32_t i = 0; i < m; ++i) bmax = std::max<int64_t>(bmax, rp[i + 1] - rp[i]);
-        if (m > 0 && bmax <= kHugeRow) {
+        // Adaptive stream tiles when every row fits one: runs of at most 64
+        // rows whose entries span at most kStreamNnz slots from the first
+        // entry rounded down to a multiple of 4 (greedy, in row order).
+        // Every lane then keeps 8 gathers in flight and the entries move in
+        // 16-byte loads.
+        std::vector<int32_t> tiles;
+        bool fits = m > 0;
+        if (fits) {
+            auto span = [&](int32_t a, int32_t b) { return (rp[a] & 3) + (int64_t)rp[b] - rp[a]; };
+            tiles.push_back(0);
+            for (int32_t r0 = 0; r0 < m && fits;) {
+                int32_t r1 = r0 + 1;
+                if (span(r0, r1) > kStreamNnz) {
+                    fits = false;
+                    break;
+                }
+                while (r1 < m && r1 - r0 < kWaveSize && span(r0, r1 + 1) <= kStreamNnz) ++r1;
+                tiles.push_back(r1);
+                r0 = r1;
+            }
+        }
+        if (fits) {
+            Schedule &S = B.sched;
+            S = Schedule{};
+            S.kind = kTileStream;
+            S.identity = 1;
+            S.nbins = 1;
+            S.bins[0] = Bin{kWaveSize, 0, m, 0};
+            S.ntiles = (int32_t)tiles.size() - 1;
+            hipError_t e = dmalloc(&B.d_tile_row, tiles.size());
+            if (e == hipSuccess)
+                e = hipMemcpy(B.d_tile_row, tiles.data(), sizeof(int32_t) * tiles.size(), hipMemcpyHostToDevice);
+            if (e != hipSuccess) return fail(CG_ENOMEM, "tile rows upload failed: %s", hipGetErrorString(e));
+        } else if (m > 0 && bmax <= kHugeRow) {
             const int L = lanes_for_length(((int64_t)rp[m] + 2ll * m - 1) / (2ll * m));
             Schedule &S = B.sched;
             S = Schedule{};
@@ -611,6 +644,8 @@ int dm_schedule(DevMatrix &M, int kind_opt, int grid_opt, int cus, int grid_cap,
 
 void dm_free(DevMatrix &M) {
     free_blocks(M);
+    (void)hipFree(M.d_tile_row);
+    M.d_tile_row = nullptr;
     (void)hipFree(M.d_rp);
     (void)hipFree(M.d_ci);
     (void)hipFree(M.d_rows);

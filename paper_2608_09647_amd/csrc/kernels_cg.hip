@@ -374,6 +374,113 @@ __device__ __forceinline__ void spmv_stream_wave(const CsrDev &A, TileWalk &walk
     }
 }
 
+// Adaptive stream tiles (the column-block passes): as the stream tiles, but
+// tile t covers the rows [tile_row[t], tile_row[t+1]), at most 64 rows whose
+// entries span at most kStreamNnz slots counted from the first entry rounded
+// down to a multiple of 4, so rows of mixed lengths pack into full tiles and
+// every lane keeps 8 gathers in flight.  float64 (a slot group is an int4 of
+// columns and two 16-byte value pairs) or float32 (an int4 and a float4).
+// Products are rounded in T, parked in the wavefront's LDS and summed left to
+// right per row in T, the row's order; accumulate mode adds the sum to q only
+// for rows with entries in the pass.  Two pipeline stages alternate between
+// register sets as in spmv_stream_wave.
+template <class T>
+struct AStreamSet {
+    int r0, nrows, kb, rb_raw, re_raw;
+    int4 c[2];
+    T v[8];
+};
+
+template <class T>
+__device__ __forceinline__ void astream_load(const CsrDev &A, int t, AStreamSet<T> &S) {
+    const T *__restrict__ vals = csr_vals<T>(A);
+    const int lane = threadIdx.x & (kWave - 1);
+    S.r0 = __builtin_amdgcn_readfirstlane(A.tile_row[t]);
+    S.nrows = __builtin_amdgcn_readfirstlane(A.tile_row[t + 1]) - S.r0;
+    const int k0 = A.rp[S.r0];
+    const int k1 = A.rp[S.r0 + S.nrows];
+    S.kb = k0 & ~3;
+    const int span = k1 - S.kb;  // slots used by the tile
+    const int i = S.r0 + min(lane, S.nrows - 1);
+    S.rb_raw = A.rp[i];
+    S.re_raw = A.rp[i + 1];
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+        const int sb = 4 * lane + g * 4 * kWave;
+        const int k = S.kb + (sb < span ? sb : 0);
+        S.c[g] = *reinterpret_cast<const int4 *>(A.ci + k);
+        if constexpr (sizeof(T) == 8) {
+            const double2 a = *reinterpret_cast<const double2 *>(vals + k);
+            const double2 b = *reinterpret_cast<const double2 *>(vals + k + 2);
+            S.v[4 * g + 0] = a.x;
+            S.v[4 * g + 1] = a.y;
+            S.v[4 * g + 2] = b.x;
+            S.v[4 * g + 3] = b.y;
+        } else {
+            const float4 a = *reinterpret_cast<const float4 *>(vals + k);
+            S.v[4 * g + 0] = a.x;
+            S.v[4 * g + 1] = a.y;
+            S.v[4 * g + 2] = a.z;
+            S.v[4 * g + 3] = a.w;
+        }
+    }
+}
+
+template <int MODE, class T>
+__device__ __forceinline__ void astream_step(const CsrDev &A, const SpmvArgs<T> &a, T *lds,
+                                             const AStreamSet<T> &S, int tn, AStreamSet<T> &N,
+                                             double &acc0, double &acc1) {
+    const int lane = threadIdx.x & (kWave - 1);
+    T pv[8];
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+        pv[4 * g + 0] = a.p[S.c[g].x];
+        pv[4 * g + 1] = a.p[S.c[g].y];
+        pv[4 * g + 2] = a.p[S.c[g].z];
+        pv[4 * g + 3] = a.p[S.c[g].w];
+    }
+    astream_load<T>(A, tn, N);
+    // products of every slot (slots outside the tile are never read)
+    {
+#pragma clang fp contract(off)
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) lds[4 * lane + g * 4 * kWave + j] = S.v[4 * g + j] * pv[4 * g + j];
+    }
+    wave_lds_sync();
+    const int rb = S.rb_raw - S.kb, re = S.re_raw - S.kb;
+    T s = T(0);
+    for (int k = rb; k < re; ++k) s += lds[k];
+    if (lane < S.nrows) {
+        const int row = S.r0 + lane;
+        if (MODE == kSpmvAccum) {
+            if (re > rb) a.q[row] = a.q[row] + s;
+        } else {
+            emit_row<MODE, T>(a, row, s, acc0, acc1);
+        }
+    }
+    wave_lds_sync();
+}
+
+template <int MODE, class T>
+__device__ __forceinline__ void spmv_astream_wave(const CsrDev &A, TileWalk &walk, const SpmvArgs<T> &a, T *lds,
+                                                  double &acc0, double &acc1) {
+    int t = walk.next();
+    if (t < 0) return;
+    AStreamSet<T> S0, S1;
+    astream_load<T>(A, t, S0);
+    for (;;) {
+        const int t1 = walk.next();
+        astream_step<MODE, T>(A, a, lds, S0, t1 >= 0 ? t1 : t, S1, acc0, acc1);
+        if (t1 < 0) break;
+        const int t2 = walk.next();
+        astream_step<MODE, T>(A, a, lds, S1, t2 >= 0 ? t2 : t1, S0, acc0, acc1);
+        if (t2 < 0) break;
+        t = t2;
+    }
+}
+
 // Sliced tiles: lane l owns row r0+l of the 64-row slice; slot j of all 64
 // rows is contiguous, so the j-th col/val loads and the j-th gather of the
 // wavefront each touch 64 consecutive words (for a stencil, 64 consecutive
@@ -861,7 +968,8 @@ __device__ __forceinline__ void spmv_row_wg(const CsrDev &A, int pos, bool ident
 // -6 / -7: stencil slices, cached / nontemporal (float64 only); -8 / -9: the
 // same with two rows per lane and 16-byte accesses (plain and dot modes);
 // -10 / -11: sliced tiles with two rows per lane, cached / nontemporal
-// (float64, plain and dot modes).
+// (float64, plain and dot modes); -12: adaptive stream tiles (float64 and
+// float32).
 template <int MODE, int TILE, class T>
 __global__ __launch_bounds__(kBlock) void k_spmv(int32_t m, const int32_t *__restrict__ rp,
                                                  const int32_t *__restrict__ ci,
@@ -877,11 +985,12 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int32_t m, const int32_t *__res
                                                  const uint8_t *__restrict__ st_mask,
                                                  const double *__restrict__ st_val,
                                                  const uint8_t *__restrict__ sell_len,
+                                                 const int32_t *__restrict__ tile_row,
                                                  Schedule S, SpmvArgs<T> a, double *__restrict__ out,
                                                  Partials in0, Partials in1,
                                                  DevState *__restrict__ st, int flags) {
     CsrDev A{m, rp, ci, nullptr, rows, sell_off, sell_ci, nullptr, nullptr, nullptr,
-             sell_idx, sell_dict, col_base, nullptr, st_off, st_offs, st_mask, st_val, sell_len};
+             sell_idx, sell_dict, col_base, nullptr, st_off, st_offs, st_mask, st_val, sell_len, tile_row};
     if constexpr (sizeof(T) == 8) {
         A.val = reinterpret_cast<const double *>(val);
         A.sell_val = reinterpret_cast<const double *>(sell_val);
@@ -891,7 +1000,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int32_t m, const int32_t *__res
     }
     __shared__ double sh[kWavesPerBlock];
     __shared__ double bc;
-    __shared__ double s_prod[TILE == -1 ? kWavesPerBlock * kStreamNnz : 1];
+    __shared__ T s_prod[(TILE == -1 || TILE == -12) ? kWavesPerBlock * kStreamNnz : 1];
     if (flags & kFlagCheckDone) {
         if (st->done) return;
         if (flags & kFlagFirstIter) {
@@ -929,6 +1038,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int32_t m, const int32_t *__res
             double *lds = s_prod + (threadIdx.x / kWave) * kStreamNnz;
             spmv_stream_wave<MODE>(A, walk, a, lds, acc0, acc1);
         }
+    } else if constexpr (TILE == -12) {
+        T *lds = s_prod + (threadIdx.x / kWave) * kStreamNnz;
+        spmv_astream_wave<MODE, T>(A, walk, a, lds, acc0, acc1);
     } else if constexpr (TILE > 0) {
         constexpr int L = TILE > 0 ? TILE : 1;
         constexpr int RW = rows_per_wave_tile(L);
@@ -1630,7 +1742,7 @@ void launch_spmv_mode(const CsrDev &A, const Schedule &S, int grid, const SpmvAr
                   : S.kind == kTileSliced ? (S.bins[0].lanes <= kSliceMaxWidth
                                                  ? (wide && A.sell_len ? (S.stream_nt ? -11 : -10) : -2)
                                                  : -3)
-                  : S.kind == kTileStream ? -1
+                  : S.kind == kTileStream ? (A.tile_row ? -12 : -1)
                   : (S.identity && S.nbins == 1 && S.huge_count == 0) ? S.bins[0].lanes : 0;
     const T *val, *sval;
     if constexpr (sizeof(T) == 8) {
@@ -1643,7 +1755,7 @@ void launch_spmv_mode(const CsrDev &A, const Schedule &S, int grid, const SpmvAr
 #define CGMI_SPMV(FL)                                                                             \
     hipLaunchKernelGGL((k_spmv<MODE, FL, T>), dim3(grid), dim3(kBlock), 0, s, A.m, A.rp, A.ci, val, \
                        A.rows, A.sell_off, A.sell_ci, sval, A.sell_idx, A.sell_dict, A.col_base,       \
-                       A.st_off, A.st_offs, A.st_mask, A.st_val, A.sell_len, S, a,                    \
+                       A.st_off, A.st_offs, A.st_mask, A.st_val, A.sell_len, A.tile_row, S, a,        \
                        out, in0, in1, st, flags)
     switch (L) {
         case 1: CGMI_SPMV(1); break;
@@ -1664,6 +1776,7 @@ void launch_spmv_mode(const CsrDev &A, const Schedule &S, int grid, const SpmvAr
         case -9: CGMI_SPMV(-9); break;
         case -10: CGMI_SPMV(-10); break;
         case -11: CGMI_SPMV(-11); break;
+        case -12: CGMI_SPMV(-12); break;
         default: CGMI_SPMV(0); break;
     }
 #undef CGMI_SPMV
@@ -1725,7 +1838,8 @@ hipError_t launch_spmv_f32(const CsrDev &A, const Schedule &S, int grid, const f
                            const float *p_own, double *out_partials, DevState *st, int mode,
                            hipStream_t s) {
     if (A.m == 0) return hipSuccess;
-    if (S.kind == kTileStream || S.kind == kTileStencil) return hipErrorInvalidValue;   // no float32 variant
+    if ((S.kind == kTileStream && !A.tile_row) || S.kind == kTileStencil)
+        return hipErrorInvalidValue;   // no float32 variant
     SpmvArgs<float> a{p, q, p_own, nullptr, nullptr};
     const Partials none{nullptr, 0};
     if (S.kind == kTileColBlocked) {

@@ -539,6 +539,20 @@ def test_hbm_copy(cg, n, offset):
     assert torch.equal(src, dst)
 
 
+@pytest.mark.parametrize("n", [0, 1, 7, 1001, 1 << 20])
+@pytest.mark.parametrize("offset", [0, 1])
+def test_gather_reference(cg, n, offset):
+    """The library's random gather: dst = src[idx] exactly, any length and
+    alignment (offset 1: idx and dst not 16-byte aligned)."""
+    src = torch.rand(300_000, dtype=torch.float64, device="cuda")
+    g = torch.Generator(device="cuda").manual_seed(n + offset)
+    idx = torch.randint(0, src.numel(), (n + offset,), dtype=torch.int32, device="cuda", generator=g)[offset:]
+    dst = torch.full((n + offset,), -1.0, dtype=torch.float64, device="cuda")[offset:]
+    cg.gather(src, idx, dst)
+    torch.cuda.synchronize()
+    assert torch.equal(dst, src[idx.long()])
+
+
 @pytest.mark.parametrize("stride", [1, 7])
 def test_spmv_event_sampling(cg, stride):
     """cg_opts.profile = P times the SpMV of iterations 0, P, 2P, ...: the
