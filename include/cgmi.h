@@ -98,9 +98,11 @@ typedef struct cg_opts {
                               run the whole solve in one single-workgroup kernel */
     int32_t spmv_grid;     /* workgroups of the SpMV kernels (0: automatic)      */
     int32_t spmv_kind;     /* SpMV tiling: 0 automatic, 1 vector CSR row-length
-                              bins (L lanes per row), 2 stream tiles (64 short
-                              rows, nonzeros loaded flat; used only when every
-                              tile fits, else 1), 3 sliced tiles (64-row slices
+                              bins (L lanes per row), 2 stream tiles (runs of
+                              at most 64 rows with at most 509 nonzeros,
+                              loaded flat, 8 gathers in flight per lane; used
+                              only when every row fits, else 1), 3 sliced
+                              tiles (64-row slices
                               stored slot-major, one lane per row; rows of at
                               most 64 nonzeros, else 1), 4 dictionary-sliced
                               tiles (the sliced layout with a 4-bit index per
@@ -108,9 +110,11 @@ typedef struct cg_opts {
                               offsets; rows of at most 8 nonzeros, else 3),
                               5 column blocks (one accumulating pass per block
                               of spmv_colblock columns, so gathers from p stay
-                              in the L2; rows in natural order with lanes for
-                              half the block's mean row length, or length bins
-                              when a block has a row over 4096 entries; for
+                              in the L2; each pass on stream tiles when every
+                              row's entries in the block fit one, else rows
+                              in natural order with lanes for half the
+                              block's mean row length, or length bins when a
+                              block has a row over 4096 entries; for
                               scattered columns),
                               6 stencil slices (slot j of a 64-row slice holds
                               the entries at the slice's j-th column offset, so

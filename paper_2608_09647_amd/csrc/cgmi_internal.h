@@ -51,11 +51,12 @@ struct Bin {
     int32_t tile_begin;   // first wavefront tile of the bin (numbered over all bins)
 };
 
-// Stream tiles (kind kTileStream): 64 consecutive rows per wavefront tile
-// whose nonzeros are loaded flat by the wavefront in 16-byte groups counted
-// from the tile's first nonzero rounded down to a multiple of 4; a tile fits
-// when (k0 mod 4) + nnz(tile) <= kStreamNnz.  col/val allocations carry
-// kStreamNnz padding entries (column 0, value 0).
+// Stream tiles (kind kTileStream): runs of at most 64 consecutive rows per
+// wavefront tile (first rows in tile_row) whose nonzeros are loaded flat by
+// the wavefront in 16-byte groups counted from the tile's first nonzero
+// rounded down to a multiple of 4; a run fits when (k0 mod 4) + nnz(run) <=
+// kStreamNnz.  col/val allocations carry kStreamNnz padding entries (column
+// 0, value 0).
 constexpr int kStreamPerLane = 8;
 constexpr int kStreamNnz = kWaveSize * kStreamPerLane;
 // Sliced tiles (kind kTileSliced): the block is re-laid out in slices of 64

@@ -201,8 +201,48 @@ bool dict_slice(const DevMatrix &M, int32_t t, int32_t *d, uint32_t *idx_t) {
 // order (one bin, no indirection), spread-out lengths are binned by the power
 // of two covering the row length (row list per bin), rows longer than
 // kHugeRow go to a workgroup-per-row list at the end.
+// Adaptive stream tiles over rows [0, m) of a CSR (row pointers rp, m + 1):
+// runs of at most 64 rows whose entries span at most kStreamNnz slots from
+// the first entry rounded down to a multiple of 4, greedy in row order.
+// tiles receives the first row of every tile and m at the end; false when a
+// single row does not fit a tile.
+bool stream_tiles(const int32_t *rp, int32_t m, std::vector<int32_t> &tiles) {
+    tiles.clear();
+    if (m <= 0) return false;
+    auto span = [&](int32_t a, int32_t b) { return (rp[a] & 3) + (int64_t)rp[b] - rp[a]; };
+    tiles.push_back(0);
+    for (int32_t r0 = 0; r0 < m;) {
+        int32_t r1 = r0 + 1;
+        if (span(r0, r1) > kStreamNnz) {
+            tiles.clear();
+            return false;
+        }
+        while (r1 < m && r1 - r0 < kWaveSize && span(r0, r1 + 1) <= kStreamNnz) ++r1;
+        tiles.push_back(r1);
+        r0 = r1;
+    }
+    return true;
+}
+
+// Upload the tile list of adaptive stream tiles and make S their schedule.
+int set_stream_tiles(DevMatrix &M, Schedule &S, const std::vector<int32_t> &tiles) {
+    S = Schedule{};
+    S.kind = kTileStream;
+    S.identity = 1;
+    S.nbins = 1;
+    S.bins[0] = Bin{kWaveSize, 0, M.m, 0};
+    S.ntiles = (int32_t)tiles.size() - 1;
+    (void)hipFree(M.d_tile_row);
+    M.d_tile_row = nullptr;
+    hipError_t e = dmalloc(&M.d_tile_row, tiles.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(M.d_tile_row, tiles.data(), sizeof(int32_t) * tiles.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(CG_ENOMEM, "tile rows upload failed: %s", hipGetErrorString(e));
+    return CG_OK;
+}
+
 void build_schedule(const DevMatrix &M, int kind_opt, Schedule &S, std::vector<int32_t> &rows_out,
-                    bool skip_empty = false) {
+                    bool skip_empty = false, std::vector<int32_t> *tiles_out = nullptr) {
     S = Schedule{};
     const int32_t m = M.m;
     rows_out.clear();
@@ -258,19 +298,9 @@ void build_schedule(const DevMatrix &M, int kind_opt, Schedule &S, std::vector<i
             return;
         }
     }
-    if (kind_opt == 2) {
-        bool fits = true;
-        for (int32_t r0 = 0; r0 < m && fits; r0 += kWaveSize) {
-            const int32_t r1 = std::min(m, r0 + kWaveSize);
-            fits = (M.h_rp[r0] & 3) + (M.h_rp[r1] - M.h_rp[r0]) <= kStreamNnz;
-        }
-        if (fits) {
-            S.kind = kTileStream;
-            S.nbins = 1;
-            S.bins[0] = Bin{kWaveSize, 0, m, 0};
-            S.ntiles = (m + kWaveSize - 1) / kWaveSize;
-            return;
-        }
+    if (kind_opt == 2 && tiles_out && stream_tiles(M.h_rp.data(), m, *tiles_out)) {
+        S.kind = kTileStream;   // the caller uploads the tiles (set_stream_tiles)
+        return;
     }
     if (!skip_empty && maxlen <= 64 && (double)maxlen <= 2.0 * mean + 1.0) {
         const int L = lanes_for_length(maxlen);
@@ -429,39 +459,12 @@ int build_blocks(DevMatrix &M, int32_t block_cols, int cus, int grid_cap, bool n
         std::vector<int32_t> rows;
         int64_t bmax = 0;
         for (int32_t i = 0; i < m; ++i) bmax = std::max<int64_t>(bmax, rp[i + 1] - rp[i]);
-        // Adaptive stream tiles when every row fits one: runs of at most 64
-        // rows whose entries span at most kStreamNnz slots from the first
-        // entry rounded down to a multiple of 4 (greedy, in row order).
-        // Every lane then keeps 8 gathers in flight and the entries move in
-        // 16-byte loads.
+        // Adaptive stream tiles when every row fits one: every lane keeps 8
+        // gathers in flight and the entries move in 16-byte loads.
         std::vector<int32_t> tiles;
-        bool fits = m > 0;
-        if (fits) {
-            auto span = [&](int32_t a, int32_t b) { return (rp[a] & 3) + (int64_t)rp[b] - rp[a]; };
-            tiles.push_back(0);
-            for (int32_t r0 = 0; r0 < m && fits;) {
-                int32_t r1 = r0 + 1;
-                if (span(r0, r1) > kStreamNnz) {
-                    fits = false;
-                    break;
-                }
-                while (r1 < m && r1 - r0 < kWaveSize && span(r0, r1 + 1) <= kStreamNnz) ++r1;
-                tiles.push_back(r1);
-                r0 = r1;
-            }
-        }
-        if (fits) {
-            Schedule &S = B.sched;
-            S = Schedule{};
-            S.kind = kTileStream;
-            S.identity = 1;
-            S.nbins = 1;
-            S.bins[0] = Bin{kWaveSize, 0, m, 0};
-            S.ntiles = (int32_t)tiles.size() - 1;
-            hipError_t e = dmalloc(&B.d_tile_row, tiles.size());
-            if (e == hipSuccess)
-                e = hipMemcpy(B.d_tile_row, tiles.data(), sizeof(int32_t) * tiles.size(), hipMemcpyHostToDevice);
-            if (e != hipSuccess) return fail(CG_ENOMEM, "tile rows upload failed: %s", hipGetErrorString(e));
+        if (stream_tiles(rp.data(), m, tiles)) {
+            rc = set_stream_tiles(B, B.sched, tiles);
+            if (rc) return rc;
         } else if (m > 0 && bmax <= kHugeRow) {
             const int L = lanes_for_length(((int64_t)rp[m] + 2ll * m - 1) / (2ll * m));
             Schedule &S = B.sched;
@@ -567,7 +570,12 @@ int dm_schedule(DevMatrix &M, int kind_opt, int grid_opt, int cus, int grid_cap,
                 int32_t block_cols) {
     std::vector<int32_t> rows;
     // stencil slices (6) start from the dictionary choice and are upgraded below
-    build_schedule(M, kind_opt == 6 ? 4 : kind_opt, M.sched, rows);
+    std::vector<int32_t> tiles;
+    build_schedule(M, kind_opt == 6 ? 4 : kind_opt, M.sched, rows, false, &tiles);
+    if (M.sched.kind == kTileStream) {
+        const int rc = set_stream_tiles(M, M.sched, tiles);
+        if (rc) return rc;
+    }
     if (M.sched.kind == kTileColBlocked) {
         const int32_t bc = block_cols > 0 ? block_cols : kColBlockCols;
         if (M.cb && M.block_cols == bc && need_f32)
@@ -629,8 +637,6 @@ int dm_schedule(DevMatrix &M, int kind_opt, int grid_opt, int cus, int grid_cap,
         if (e != hipSuccess) return fail(CG_EDEVICE, "row list upload failed: %s", hipGetErrorString(e));
     }
     if (need_f32) {
-        if (M.sched.kind == kTileStream)
-            return fail(CG_EINVAL, "stream tiles have no float32 variant: use spmv_kind 0, 1 or 3");
         const int rc = dm_ensure_f32(M);
         if (rc) return rc;
     }

@@ -261,138 +261,35 @@ struct TileWalk {
     }
 };
 
-// Stream tiles: 64 consecutive rows whose nonzeros (at most kStreamNnz - 3)
-// are loaded flat by the wavefront with 16-byte loads, all independent.  The
-// products go to the wavefront's own LDS region and lane l then sums row r0+l
-// left to right (rounded products added in CSR order).  The loop is
-// software-pipelined over the wavefront's tiles: while the gathers of tile t
-// are in flight, the loads of tile t+1 are issued too.
-// One pipeline stage: a tile's bounds (uniform: scalar loads), the row bounds
-// of the lane's row, and the lane's 8 slots of the tile's col/val.  Slots are
-// counted from kb = k0 rounded down to a multiple of 4, so lane l loads slots
-// 4l..4l+3 and 256+4l..256+4l+3 with 16-byte loads (one int4 of columns and
-// two double2 of values per group); groups past the tile re-read the tile's
-// first group (cached) and their products are never summed.  The arrays are
-// padded so a group never reads past the allocation.
-struct StreamSet {
-    int r0, nrows, kb, rb_raw, re_raw;
-    int4 c[2];
-    double2 v[4];
-};
-
-__device__ __forceinline__ void stream_load(const CsrDev &A, int t, StreamSet &S) {
-    const int lane = threadIdx.x & (kWave - 1);
-    S.r0 = __builtin_amdgcn_readfirstlane(t * kWave);
-    S.nrows = min(kWave, A.m - S.r0);
-    const int k0 = A.rp[S.r0];
-    const int k1 = A.rp[S.r0 + S.nrows];
-    S.kb = k0 & ~3;
-    const int span = k1 - S.kb;  // slots used by the tile
-    const int i = S.r0 + min(lane, S.nrows - 1);
-    S.rb_raw = A.rp[i];
-    S.re_raw = A.rp[i + 1];
-#pragma unroll
-    for (int g = 0; g < 2; ++g) {
-        const int sb = 4 * lane + g * 4 * kWave;
-        const int k = S.kb + (sb < span ? sb : 0);
-        S.c[g] = *reinterpret_cast<const int4 *>(A.ci + k);
-        S.v[2 * g] = *reinterpret_cast<const double2 *>(A.val + k);
-        S.v[2 * g + 1] = *reinterpret_cast<const double2 *>(A.val + k + 2);
-    }
-}
-
 __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Gather for the loaded tile S, issue tile tn's loads into N, then finish S.
-template <int MODE>
-__device__ __forceinline__ void stream_step(const CsrDev &A, const SpmvArgs<double> &a, double *lds,
-                                            const StreamSet &S, int tn, StreamSet &N,
-                                            double &acc0, double &acc1) {
-    const int lane = threadIdx.x & (kWave - 1);
-    double pv[8];
-#pragma unroll
-    for (int g = 0; g < 2; ++g) {
-        pv[4 * g + 0] = a.p[S.c[g].x];
-        pv[4 * g + 1] = a.p[S.c[g].y];
-        pv[4 * g + 2] = a.p[S.c[g].z];
-        pv[4 * g + 3] = a.p[S.c[g].w];
-    }
-    const int myrow = S.r0 + min(lane, S.nrows - 1);
-    double pown = 0.0, bv = 0.0;
-    if (MODE == kSpmvDot) pown = a.p_own[myrow];
-    if (MODE == kSpmvResidual) bv = a.b[myrow];
-    stream_load(A, tn, N);
-    // products of every slot (slots outside the tile are never read)
-#pragma unroll
-    for (int g = 0; g < 2; ++g) {
-        double2 *d = reinterpret_cast<double2 *>(lds + 4 * lane + g * 4 * kWave);
-        d[0] = make_double2(S.v[2 * g].x * pv[4 * g + 0], S.v[2 * g].y * pv[4 * g + 1]);
-        d[1] = make_double2(S.v[2 * g + 1].x * pv[4 * g + 2], S.v[2 * g + 1].y * pv[4 * g + 3]);
-    }
-    wave_lds_sync();
-    const int rb = S.rb_raw - S.kb, re = S.re_raw - S.kb;
-    double s = 0.0;
-    for (int k = rb; k < re; ++k) s += lds[k];
-    if (lane < S.nrows) {
-        if (MODE == kSpmvResidual) {
-            const double rv = bv - s;
-            a.q[myrow] = rv;
-            a.p_dst[myrow] = rv;
-            acc0 = fma(rv, rv, acc0);
-            acc1 = fma(bv, bv, acc1);
-        } else {
-            a.q[myrow] = MODE == kSpmvAccum ? (a.q[myrow] + s) : s;
-            if (MODE == kSpmvDot) acc0 = fma(pown, s, acc0);
-        }
-    }
-    wave_lds_sync();
-}
-
-// The wavefront's tiles, two pipeline stages alternating between register
-// sets (no register moves, so no waits on loads still in flight).  Past the
-// last tile the prefetch re-reads the current tile and is discarded.
-template <int MODE>
-__device__ __forceinline__ void spmv_stream_wave(const CsrDev &A, TileWalk &walk,
-                                                 const SpmvArgs<double> &a, double *lds, double &acc0,
-                                                 double &acc1) {
-    int t = walk.next();
-    if (t < 0) return;
-    StreamSet S0, S1;
-    stream_load(A, t, S0);
-    for (;;) {
-        const int t1 = walk.next();
-        stream_step<MODE>(A, a, lds, S0, t1 >= 0 ? t1 : t, S1, acc0, acc1);
-        if (t1 < 0) break;
-        const int t2 = walk.next();
-        stream_step<MODE>(A, a, lds, S1, t2 >= 0 ? t2 : t1, S0, acc0, acc1);
-        if (t2 < 0) break;
-        t = t2;
-    }
-}
-
-// Adaptive stream tiles (the column-block passes): as the stream tiles, but
-// tile t covers the rows [tile_row[t], tile_row[t+1]), at most 64 rows whose
-// entries span at most kStreamNnz slots counted from the first entry rounded
-// down to a multiple of 4, so rows of mixed lengths pack into full tiles and
-// every lane keeps 8 gathers in flight.  float64 (a slot group is an int4 of
-// columns and two 16-byte value pairs) or float32 (an int4 and a float4).
-// Products are rounded in T, parked in the wavefront's LDS and summed left to
-// right per row in T, the row's order; accumulate mode adds the sum to q only
-// for rows with entries in the pass.  Two pipeline stages alternate between
-// register sets as in spmv_stream_wave.
+// Stream tiles: tile t covers the rows [tile_row[t], tile_row[t+1]), at most
+// 64 rows whose entries span at most kStreamNnz slots counted from the first
+// entry rounded down to a multiple of 4, so rows of mixed lengths pack into
+// full tiles.  The wavefront loads the tile's entries flat (lane l: slots
+// 4l..4l+3 and 256+4l..256+4l+3, 16-byte loads of an int4 of columns and of
+// the values: two double pairs, or one float4), keeps 8 gathers in flight per
+// lane, parks the products (rounded in T) in its own LDS region, and lane j
+// then sums row tile_row[t] + j left to right in T, the row's CSR order;
+// accumulate mode adds the sum to q only for rows with entries.  Slots past
+// the tile re-read the tile's first group (cached) and are never summed; the
+// arrays are padded so no load leaves the allocation.  The loop is
+// software-pipelined over the wavefront's tiles, two register sets
+// alternating: the loads of tile t+1 are issued while tile t's gathers are in
+// flight, and past the last tile the prefetch re-reads the current one.
 template <class T>
-struct AStreamSet {
+struct StreamSet {
     int r0, nrows, kb, rb_raw, re_raw;
     int4 c[2];
     T v[8];
 };
 
 template <class T>
-__device__ __forceinline__ void astream_load(const CsrDev &A, int t, AStreamSet<T> &S) {
+__device__ __forceinline__ void stream_load(const CsrDev &A, int t, StreamSet<T> &S) {
     const T *__restrict__ vals = csr_vals<T>(A);
     const int lane = threadIdx.x & (kWave - 1);
     S.r0 = __builtin_amdgcn_readfirstlane(A.tile_row[t]);
@@ -427,8 +324,8 @@ __device__ __forceinline__ void astream_load(const CsrDev &A, int t, AStreamSet<
 }
 
 template <int MODE, class T>
-__device__ __forceinline__ void astream_step(const CsrDev &A, const SpmvArgs<T> &a, T *lds,
-                                             const AStreamSet<T> &S, int tn, AStreamSet<T> &N,
+__device__ __forceinline__ void stream_step(const CsrDev &A, const SpmvArgs<T> &a, T *lds,
+                                             const StreamSet<T> &S, int tn, StreamSet<T> &N,
                                              double &acc0, double &acc1) {
     const int lane = threadIdx.x & (kWave - 1);
     T pv[8];
@@ -439,7 +336,7 @@ __device__ __forceinline__ void astream_step(const CsrDev &A, const SpmvArgs<T> 
         pv[4 * g + 2] = a.p[S.c[g].z];
         pv[4 * g + 3] = a.p[S.c[g].w];
     }
-    astream_load<T>(A, tn, N);
+    stream_load<T>(A, tn, N);
     // products of every slot (slots outside the tile are never read)
     {
 #pragma clang fp contract(off)
@@ -464,18 +361,18 @@ __device__ __forceinline__ void astream_step(const CsrDev &A, const SpmvArgs<T> 
 }
 
 template <int MODE, class T>
-__device__ __forceinline__ void spmv_astream_wave(const CsrDev &A, TileWalk &walk, const SpmvArgs<T> &a, T *lds,
+__device__ __forceinline__ void spmv_stream_wave(const CsrDev &A, TileWalk &walk, const SpmvArgs<T> &a, T *lds,
                                                   double &acc0, double &acc1) {
     int t = walk.next();
     if (t < 0) return;
-    AStreamSet<T> S0, S1;
-    astream_load<T>(A, t, S0);
+    StreamSet<T> S0, S1;
+    stream_load<T>(A, t, S0);
     for (;;) {
         const int t1 = walk.next();
-        astream_step<MODE, T>(A, a, lds, S0, t1 >= 0 ? t1 : t, S1, acc0, acc1);
+        stream_step<MODE, T>(A, a, lds, S0, t1 >= 0 ? t1 : t, S1, acc0, acc1);
         if (t1 < 0) break;
         const int t2 = walk.next();
-        astream_step<MODE, T>(A, a, lds, S1, t2 >= 0 ? t2 : t1, S0, acc0, acc1);
+        stream_step<MODE, T>(A, a, lds, S1, t2 >= 0 ? t2 : t1, S0, acc0, acc1);
         if (t2 < 0) break;
         t = t2;
     }
@@ -961,15 +858,14 @@ __device__ __forceinline__ void spmv_row_wg(const CsrDev &A, int pos, bool ident
 }
 
 // TILE > 0: one bin of TILE lanes per row in natural row order;
-// TILE == 0: binned rows (any order); TILE == -1: stream tiles (float64 only);
+// TILE == 0: binned rows (any order); TILE == -1: stream tiles;
 // TILE == -2: sliced tiles of width <= kSliceMaxWidth; -3: wider slices;
 // TILE == -4: dictionary-sliced tiles; -5: the same with the matrix streamed
 // nontemporally (matrices larger than the last-level cache can hold);
 // -6 / -7: stencil slices, cached / nontemporal (float64 only); -8 / -9: the
 // same with two rows per lane and 16-byte accesses (plain and dot modes);
 // -10 / -11: sliced tiles with two rows per lane, cached / nontemporal
-// (float64, plain and dot modes); -12: adaptive stream tiles (float64 and
-// float32).
+// (float64, plain and dot modes).
 template <int MODE, int TILE, class T>
 __global__ __launch_bounds__(kBlock) void k_spmv(int32_t m, const int32_t *__restrict__ rp,
                                                  const int32_t *__restrict__ ci,
@@ -1000,7 +896,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int32_t m, const int32_t *__res
     }
     __shared__ double sh[kWavesPerBlock];
     __shared__ double bc;
-    __shared__ T s_prod[(TILE == -1 || TILE == -12) ? kWavesPerBlock * kStreamNnz : 1];
+    __shared__ T s_prod[TILE == -1 ? kWavesPerBlock * kStreamNnz : 1];
     if (flags & kFlagCheckDone) {
         if (st->done) return;
         if (flags & kFlagFirstIter) {
@@ -1034,13 +930,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int32_t m, const int32_t *__res
         if constexpr (sizeof(T) == 8 && (MODE == kSpmvPlain || MODE == kSpmvDot))
             spmv_sliced2_wave<MODE, TILE == -11>(A, walk, a, acc0);
     } else if constexpr (TILE == -1) {
-        if constexpr (sizeof(T) == 8) {
-            double *lds = s_prod + (threadIdx.x / kWave) * kStreamNnz;
-            spmv_stream_wave<MODE>(A, walk, a, lds, acc0, acc1);
-        }
-    } else if constexpr (TILE == -12) {
         T *lds = s_prod + (threadIdx.x / kWave) * kStreamNnz;
-        spmv_astream_wave<MODE, T>(A, walk, a, lds, acc0, acc1);
+        spmv_stream_wave<MODE, T>(A, walk, a, lds, acc0, acc1);
     } else if constexpr (TILE > 0) {
         constexpr int L = TILE > 0 ? TILE : 1;
         constexpr int RW = rows_per_wave_tile(L);
@@ -1742,7 +1633,7 @@ void launch_spmv_mode(const CsrDev &A, const Schedule &S, int grid, const SpmvAr
                   : S.kind == kTileSliced ? (S.bins[0].lanes <= kSliceMaxWidth
                                                  ? (wide && A.sell_len ? (S.stream_nt ? -11 : -10) : -2)
                                                  : -3)
-                  : S.kind == kTileStream ? (A.tile_row ? -12 : -1)
+                  : S.kind == kTileStream ? -1
                   : (S.identity && S.nbins == 1 && S.huge_count == 0) ? S.bins[0].lanes : 0;
     const T *val, *sval;
     if constexpr (sizeof(T) == 8) {
@@ -1776,7 +1667,6 @@ void launch_spmv_mode(const CsrDev &A, const Schedule &S, int grid, const SpmvAr
         case -9: CGMI_SPMV(-9); break;
         case -10: CGMI_SPMV(-10); break;
         case -11: CGMI_SPMV(-11); break;
-        case -12: CGMI_SPMV(-12); break;
         default: CGMI_SPMV(0); break;
     }
 #undef CGMI_SPMV
@@ -1838,8 +1728,7 @@ hipError_t launch_spmv_f32(const CsrDev &A, const Schedule &S, int grid, const f
                            const float *p_own, double *out_partials, DevState *st, int mode,
                            hipStream_t s) {
     if (A.m == 0) return hipSuccess;
-    if ((S.kind == kTileStream && !A.tile_row) || S.kind == kTileStencil)
-        return hipErrorInvalidValue;   // no float32 variant
+    if (S.kind == kTileStencil) return hipErrorInvalidValue;   // no float32 variant
     SpmvArgs<float> a{p, q, p_own, nullptr, nullptr};
     const Partials none{nullptr, 0};
     if (S.kind == kTileColBlocked) {

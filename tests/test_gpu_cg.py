@@ -227,8 +227,10 @@ def s_kind_used(A, kind):
     lens = np.diff(A.row_ptr)
     if kind == 3:
         return lens.max() <= 64
+    # stream tiles: every row's entries fit one tile (512 slots from the
+    # row's first entry rounded down to a multiple of 4)
     rp = A.row_ptr.astype(np.int64)
-    return all((rp[r] & 3) + rp[min(A.n, r + 64)] - rp[r] <= 512 for r in range(0, A.n, 64))
+    return bool(np.all((rp[:-1] & 3) + np.diff(rp) <= 512))
 
 
 @pytest.mark.parametrize("name", ["poisson3d_ragged", "random_spd_30k", "arrowhead_3000"])
@@ -602,7 +604,7 @@ def test_full_size_poisson3d_256(cg):
 
 # ----------------------------------------------------------------------------- mixed precision
 
-@pytest.mark.parametrize("kind", [0, 1, 3, 4, 5])
+@pytest.mark.parametrize("kind", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("name", ["poisson3d_ragged", "random_spd_30k", "diffusion_100"])
 def test_spmv_f32_matches_oracle(cg, name, kind):
     A = SPMV_CASES[name]()
@@ -616,8 +618,8 @@ def test_spmv_f32_matches_oracle(cg, name, kind):
     scale = absA @ np.abs(x32).astype(np.float64) + 1e-30
     L = int(np.diff(A.row_ptr).max())
     assert np.max(np.abs(y.astype(np.float64) - ref) / scale) <= 2 * L * 2.0 ** -24
-    if used in (3, 4):
-        # sliced rows are summed in float32 left to right: the oracle's order
+    if used in (2, 3, 4):
+        # stream and sliced rows are summed in float32 left to right: the oracle's order
         assert np.array_equal(y, ref)
 
 
