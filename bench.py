@@ -225,6 +225,9 @@ def main() -> int:
     ap.add_argument("--batch-iters", type=int, default=30, help="fixed iterations per batched step")
     ap.add_argument("--profile-run", action="store_true",
                     help="only the timed path of the workload (no comparison solves), for profilers")
+    ap.add_argument("--spmv-kind", type=int, default=None,
+                    help="default workload: force this SpMV tiling (cg_opts.spmv_kind) instead of the "
+                         "tabled one, e.g. 3 for the generic sliced CSR tiling")
     ap.add_argument("--batch-launch", default="cooperative", choices=["cooperative", "ordinary"],
                     help="launch form of the batched kernel (ordinary: for profilers that cannot "
                          "follow cooperative launches)")
@@ -265,7 +268,10 @@ def main() -> int:
     x = torch.zeros_like(b)
     solver = cgmi.Solver(A)
     from paper_2608_09647_amd import autotune
-    autotune.spmv_schedule(solver, A, b, tune_if_missing=False)   # tabled SpMV tiling, if any
+    if args.spmv_kind is None:
+        autotune.spmv_schedule(solver, A, b, tune_if_missing=False)   # tabled SpMV tiling, if any
+    else:
+        solver.set_opts(spmv_kind=args.spmv_kind)
     # HIP events around the SpMV of every SPMV_EVENT_STRIDE-th iteration of
     # the timed steps (an event pair adds a few microseconds of stream time)
     solver.set_opts(profile=SPMV_EVENT_STRIDE)
@@ -314,6 +320,7 @@ def main() -> int:
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "poisson3d_7pt_256^3_fp64_cg_fixed_work", "n": A.n, "nnz": A.nnz,
+                   "spmv_kind_forced": args.spmv_kind,
                    "iterations_per_step": args.iters, "row_share_gpu": 1.0, "index": "int32",
                    "seed": 2},
         "spmv_gbs": achieved,
@@ -326,7 +333,9 @@ def main() -> int:
                       5: "column_blocks", 6: "stencil_slices"}.get(res["spmv_kind"]),
         "rel_res_true": res["rel_res_true"],
         "roofline": roofline_hbm(spmv_bytes, t_launch,
-                                 measured_traffic("spmv_poisson3d_256", res["spmv_kind"]),
+                                 measured_traffic("spmv_poisson3d_256" + (
+                                     "" if res["spmv_kind"] == 6 else f"_kind{res['spmv_kind']}"),
+                                     res["spmv_kind"]),
                                  kernel="k_spmv (dot mode)"),
     }
     solver.close()
