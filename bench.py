@@ -455,11 +455,13 @@ def bench_mixed(args) -> int:
                  spmv_frac_of_gather_ceiling={"float64": 1e6 * t_g / us64, "float32": 1e6 * t_g / us32,
                                               "meaning": "time of the library's plain gather of nnz "
                                                          "values from a 2 MB vector / SpMV time"},
-                 roofline={"bound": "hbm", "achieved": a32, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": a32 / HBM_PEAK_GBS, "traffic": None,
-                           "note": "float32 column-blocked SpMV, CSR-algorithmic bytes "
-                                   "(8 nnz + 4 (n+1) + 8 n) per launch; its uniformly random "
-                                   "columns make it bound by L2 gathers, not HBM bytes"})
+                 roofline=roofline_hbm(spmv_algorithmic_bytes_f32(n, nnz), us32 * 1e-6,
+                                       measured_traffic("spmv_random_spd_2m_f32", 5),
+                                       kernel="float32 column-blocked SpMV (start, 8 passes, finish)",
+                                       note="CSR-algorithmic bytes (8 nnz + 4 (n+1) + 8 n) per SpMV; its "
+                                            "uniformly random columns make it bound by L2 gathers: see "
+                                            "spmv_frac_of_gather_ceiling"),
+                 traffic_fp64_spmv=measured_traffic("spmv_random_spd_2m_f64", 5))
     line["dtype"] = "f32+f64"
     line["rel_error_vs_xstar"] = {k: float(np.linalg.norm(xs[k] - prob.xstar) / np.linalg.norm(prob.xstar))
                                   for k in ("fp64", "mixed")}
