@@ -1,13 +1,25 @@
 // kernels_fsai.hip -- learned FSAI preconditioner kernels for gfx950.
 //
-// Network 12 -> 64 -> 64 -> 5 on the matrix cores (v_mfma 16x16x16 bf16,
-// float32 accumulation).  Activations are kept transposed (units x rows): the
-// output fragment of one layer (lane l holds unit 4*(l/16)+v, row l%16) is
-// exactly the B-operand fragment of the next layer, so the forward pass needs
-// no shuffles; weights are A-operand fragments held in registers.  A wavefront
-// processes tiles of 16 rows.  The backward pass stages activations and
-// signals in wavefront-private LDS in [unit][row] order so the weight-gradient
-// products (a reduction over rows) read 4 consecutive rows per lane.
+// Network 12 -> 64 -> 64 -> 5 on the matrix cores, bfloat16 operands and
+// float32 accumulation.  Activations are kept transposed (units x rows): the
+// output fragment of a 16x16 product (lane l holds unit 4*(l/16)+v, row l%16)
+// is a B-operand fragment of the next layer, so the forward pass needs no
+// shuffles; weights are A-operand fragments held in registers.  A wavefront
+// processes tiles of 16 rows.
+//
+// The contractions over 64 hidden units (layers 2 and 3 forward, W2^T in the
+// backward pass) use the 16x16x32 form: its B operand (8 values per lane) is
+// the concatenation of two 16-unit output fragments, i.e. lane l carries the
+// units 32h + 16(j/4) + 4(l/16) + j%4, j = 0..7, and the weight fragments are
+// loaded in that same unit order.  The contraction index is only summed over,
+// so a common permutation of it in A and B leaves the product unchanged and
+// costs no data movement.  Contractions of length 16 (12 features, 5
+// outputs, and the weight gradients' sums over a tile's 16 rows) use the
+// 16x16x16 form, which they fill exactly.
+//
+// The backward pass stages activations and signals in wavefront-private LDS in
+// [unit][row] order so the weight-gradient products (a reduction over rows)
+// read 4 consecutive rows per lane.
 //
 // Definitions (features, factor, loss) follow the header cgmi_fsai.h.
 #include <hip/hip_runtime.h>
@@ -21,7 +33,9 @@ namespace cgmi {
 
 namespace {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x4 __attribute__((ext_vector_type(4)));   // bfloat16 bits
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16v8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kW = 64;
@@ -34,52 +48,97 @@ __device__ __forceinline__ uint16_t bf16_bits(float x) {
 }
 __device__ __forceinline__ float bf16_float(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
+// 16x16x16: lane l holds A[l%16][4(l/16)+v] and B[4(l/16)+v][l%16].
 __device__ __forceinline__ f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
+// 16x16x32: eight contraction entries per lane, in the same positions for A
+// and B.
+__device__ __forceinline__ f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16v8, a),
+                                                   __builtin_bit_cast(bf16v8, b), c, 0, 0, 0);
+}
+
+__device__ __forceinline__ bf16x8 cat(bf16x4 lo, bf16x4 hi) {
+    return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+}
+
+// Hidden unit carried by entry j of lane group q in contraction step h of a
+// 16x16x32 product over 64 units.
+__device__ __forceinline__ int unit32(int h, int q, int j) { return 32 * h + 16 * (j >> 2) + 4 * q + (j & 3); }
+
 __device__ __forceinline__ f32x4 zero4() { return f32x4{0.f, 0.f, 0.f, 0.f}; }
 
-// Weight fragments (A operands) built from the float32 master parameters.
-struct Frags {
-    bf16x4 w1[4];      // W1: M-tile t (units 16t..), K = features (12 used of 16)
-    bf16x4 w2[4][4];   // W2: M-tile t (out units), k-step s (in units)
-    bf16x4 w3[4];      // W3: M = outputs (5 used of 16), k-step s
+// The parameters of one workgroup, rounded to bfloat16 once and staged in LDS
+// zero-padded to 16-entry boundaries (features 12..15, outputs 5..15), so
+// every fragment entry below is an unconditional LDS read.
+struct ParamLds {
+    uint16_t w1[kHidden][16];     // W1 [unit][feature]
+    uint16_t w2[kHidden][kHidden];
+    uint16_t w3[16][kHidden];     // W3 [output][unit]
+    float b1[kHidden], b2[kHidden], b3[16];
 };
 
-__device__ __forceinline__ void load_frags(const float *__restrict__ th, Frags &F) {
+// All threads of the workgroup take part; ends with a workgroup barrier.
+__device__ __forceinline__ void stage_params(const float *__restrict__ th, ParamLds &P) {
+    for (int i = threadIdx.x; i < kHidden * 16; i += blockDim.x) {
+        const int u = i >> 4, k = i & 15;
+        P.w1[u][k] = k < kFeat ? bf16_bits(th[kOffW1 + u * kFeat + k]) : 0;
+        const int o = i >> 6, c = i & 63;
+        P.w3[o][c] = o < kOut ? bf16_bits(th[kOffW3 + o * kHidden + c]) : 0;
+    }
+    for (int i = threadIdx.x; i < kHidden * kHidden; i += blockDim.x) P.w2[i >> 6][i & 63] = bf16_bits(th[kOffW2 + i]);
+    for (int i = threadIdx.x; i < kHidden; i += blockDim.x) {
+        P.b1[i] = th[kOffB1 + i];
+        P.b2[i] = th[kOffB2 + i];
+        if (i < 16) P.b3[i] = i < kOut ? th[kOffB3 + i] : 0.f;
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ bf16x4 lds4(const uint16_t *p) {
+    const uint2 u = *reinterpret_cast<const uint2 *>(p);
+    bf16x4 b;
+    b[0] = (short)(u.x & 0xFFFF);
+    b[1] = (short)(u.x >> 16);
+    b[2] = (short)(u.y & 0xFFFF);
+    b[3] = (short)(u.y >> 16);
+    return b;
+}
+
+// Weight fragments (A operands).
+struct Frags {
+    bf16x4 w1[4];      // W1: M-tile t (units 16t..), K = features (12 used of 16)
+    bf16x8 w2[4][2];   // W2: M-tile t (out units), k-step h (in units unit32(h, ..))
+    bf16x8 w3[2];      // W3: M = outputs (5 used of 16), k-step h
+};
+
+__device__ __forceinline__ void load_frags(const ParamLds &P, Frags &F) {
     const int l = threadIdx.x & (kW - 1);
     const int r = l & 15, q = l >> 4;
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int k = 4 * q + v;
-            F.w1[t][v] = (short)(k < kFeat ? bf16_bits(th[kOffW1 + (16 * t + r) * kFeat + k]) : 0);
-        }
+    for (int t = 0; t < 4; ++t) F.w1[t] = lds4(&P.w1[16 * t + r][4 * q]);
+    // unit32(h, q, 0..3) and unit32(h, q, 4..7) are runs of 4 consecutive units
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+        for (int h = 0; h < 2; ++h)
+            F.w2[t][h] = cat(lds4(&P.w2[16 * t + r][unit32(h, q, 0)]), lds4(&P.w2[16 * t + r][unit32(h, q, 4)]));
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-                F.w2[t][s][v] = (short)bf16_bits(th[kOffW2 + (16 * t + r) * kHidden + 16 * s + 4 * q + v]);
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-            F.w3[s][v] = (short)(r < kOut ? bf16_bits(th[kOffW3 + r * kHidden + 16 * s + 4 * q + v]) : 0);
+    for (int h = 0; h < 2; ++h) F.w3[h] = cat(lds4(&P.w3[r][unit32(h, q, 0)]), lds4(&P.w3[r][unit32(h, q, 4)]));
 }
 
 struct Fwd {
     f32x4 z1[4], z2[4];   // pre-activations (units 16t + 4q + v, row r)
-    bf16x4 h1[4], h2[4];  // bfloat16 activations as next-layer B fragments
+    bf16x8 h1[2], h2[2];  // bfloat16 activations as 16x16x32 B fragments:
+                          // entry 4(t%2)+v of h[t/2] is unit 16t + 4q + v
     f32x4 o;              // outputs 4q + v (valid < 5), row r
 };
 
 // Forward pass of one 16-row tile; fin: the lane's 4 feature bits (features
 // 4q..4q+3 of row r).
-__device__ __forceinline__ void forward_tile(const Frags &W, const float *__restrict__ th,
+__device__ __forceinline__ void forward_tile(const Frags &W, const ParamLds &P,
                                              bf16x4 fin, Fwd &Y) {
     const int l = threadIdx.x & (kW - 1);
     const int q = l >> 4;
@@ -88,30 +147,27 @@ __device__ __forceinline__ void forward_tile(const Frags &W, const float *__rest
         Y.z1[t] = mfma(W.w1[t], fin, zero4());
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            Y.z1[t][v] += th[kOffB1 + 16 * t + 4 * q + v];
-            Y.h1[t][v] = (short)bf16_bits(fmaxf(Y.z1[t][v], 0.f));
+            Y.z1[t][v] += P.b1[16 * t + 4 * q + v];
+            Y.h1[t >> 1][4 * (t & 1) + v] = (short)bf16_bits(fmaxf(Y.z1[t][v], 0.f));
         }
     }
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         f32x4 c = zero4();
 #pragma unroll
-        for (int s = 0; s < 4; ++s) c = mfma(W.w2[t][s], Y.h1[s], c);
+        for (int h = 0; h < 2; ++h) c = mfma32(W.w2[t][h], Y.h1[h], c);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            c[v] += th[kOffB2 + 16 * t + 4 * q + v];
-            Y.h2[t][v] = (short)bf16_bits(fmaxf(c[v], 0.f));
+            c[v] += P.b2[16 * t + 4 * q + v];
+            Y.h2[t >> 1][4 * (t & 1) + v] = (short)bf16_bits(fmaxf(c[v], 0.f));
         }
         Y.z2[t] = c;
     }
     f32x4 c = zero4();
 #pragma unroll
-    for (int s = 0; s < 4; ++s) c = mfma(W.w3[s], Y.h2[s], c);
+    for (int h = 0; h < 2; ++h) c = mfma32(W.w3[h], Y.h2[h], c);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int o = 4 * q + v;
-        c[v] += o < kOut ? th[kOffB3 + o] : 0.f;
-    }
+    for (int v = 0; v < 4; ++v) c[v] += P.b3[4 * q + v];
     Y.o = c;
 }
 
@@ -201,8 +257,10 @@ __global__ __launch_bounds__(256) void k_fsai_forward(int32_t ntiles, const int3
                                                       const int32_t *__restrict__ tpos,
                                                       double *__restrict__ gval,
                                                       double *__restrict__ gtval) {
+    __shared__ ParamLds P;
+    stage_params(th, P);
     Frags W;
-    load_frags(th, W);
+    load_frags(P, W);
     const int l = threadIdx.x & (kW - 1);
     const int r = l & 15, q = l >> 4;
     const int wave = blockIdx.x * (blockDim.x / kW) + threadIdx.x / kW;
@@ -212,14 +270,13 @@ __global__ __launch_bounds__(256) void k_fsai_forward(int32_t ntiles, const int3
         const int64_t row = row0 + r;
         const bf16x4 fin = row < nrows ? load_feats(feats, row) : bf16x4{0, 0, 0, 0};
         Fwd Y;
-        forward_tile(W, th, fin, Y);
+        forward_tile(W, P, fin, Y);
         if (row >= nrows) continue;
         if (TRAIN) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int o = 4 * q + v;
-                if (o < kOut) out[row * kOutPad + o] = Y.o[v];
-            }
+            // outputs 0..7 of the row (5..7 are exact zeros: zero weights and bias)
+            if (q < kOutPad / 4)
+                *reinterpret_cast<float4 *>(out + row * kOutPad + 4 * q) =
+                    make_float4(Y.o[0], Y.o[1], Y.o[2], Y.o[3]);
         } else if (q == 0) {
             // lanes 0..15 hold o_C, o_W, o_E, o_S of their row
             const double oc = Y.o[0], ow = Y.o[1], os = Y.o[3];
@@ -404,16 +461,6 @@ struct alignas(16) WaveLds {   // 8-byte loads of 4 consecutive entries
     uint16_t d3T[16][16];   // dz3 (outputs padded to 16)
 };
 
-__device__ __forceinline__ bf16x4 lds4(const uint16_t *p) {
-    const uint2 u = *reinterpret_cast<const uint2 *>(p);
-    bf16x4 b;
-    b[0] = (short)(u.x & 0xFFFF);
-    b[1] = (short)(u.x >> 16);
-    b[2] = (short)(u.y & 0xFFFF);
-    b[3] = (short)(u.y >> 16);
-    return b;
-}
-
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -431,25 +478,23 @@ __global__ __launch_bounds__(256) void k_fsai_backward(int32_t ntiles, const int
     const int r = l & 15, q = l >> 4;
     const int wv = threadIdx.x / kW;
     WaveLds &S = L[wv];
+    __shared__ ParamLds P;
+    stage_params(th, P);
     Frags W;
-    load_frags(th, W);
+    load_frags(P, W);
     // transposed weights for the backward products (A operands)
-    bf16x4 w3t[4];     // W3^T: M-tile t (units), K = outputs
-    bf16x4 w2t[4][4];  // W2^T: M-tile t (in units), k-step s (out units)
+    bf16x4 w3t[4];     // W3^T: M-tile t (units), K = outputs (5 used of 16)
+    bf16x8 w2t[4][2];  // W2^T: M-tile t (in units), k-step h (out units unit32(h, ..))
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int o = 4 * q + v;
-            w3t[t][v] = (short)(o < kOut ? bf16_bits(th[kOffW3 + o * kHidden + 16 * t + r]) : 0);
-        }
+        for (int v = 0; v < 4; ++v) w3t[t][v] = (short)P.w3[4 * q + v][16 * t + r];
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-                w2t[t][s][v] = (short)bf16_bits(th[kOffW2 + (16 * s + 4 * q + v) * kHidden + 16 * t + r]);
+            for (int j = 0; j < 8; ++j) w2t[t][h][j] = (short)P.w2[unit32(h, q, j)][16 * t + r];
     f32x4 gw1[4], gw2[4][4], gw3[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -472,22 +517,24 @@ __global__ __launch_bounds__(256) void k_fsai_backward(int32_t ntiles, const int
         const int64_t row = (int64_t)tiles[tt] + r;
         const bf16x4 fin = load_feats(feats, row);
         Fwd Y;
-        forward_tile(W, th, fin, Y);
+        forward_tile(W, P, fin, Y);
 #pragma unroll
         for (int v = 0; v < 4; ++v) S.fT[4 * q + v][r] = (uint16_t)fin[v];
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                S.h1T[16 * t + 4 * q + v][r] = (uint16_t)Y.h1[t][v];
-                S.h2T[16 * t + 4 * q + v][r] = (uint16_t)Y.h2[t][v];
+                S.h1T[16 * t + 4 * q + v][r] = (uint16_t)Y.h1[t >> 1][4 * (t & 1) + v];
+                S.h2T[16 * t + 4 * q + v][r] = (uint16_t)Y.h2[t >> 1][4 * (t & 1) + v];
             }
         // dz3 (outputs 4q+v of row r)
         bf16x4 d3;
+        const float4 dq = *reinterpret_cast<const float4 *>(dout + row * kOutPad + 4 * (q & 1));
+        const float dv[4] = {dq.x, dq.y, dq.z, dq.w};
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int o = 4 * q + v;
-            const float g = o < kOut ? dout[row * kOutPad + o] : 0.f;
+            const float g = o < kOut ? dv[v] : 0.f;
             gb3[v] += g;
             d3[v] = (short)bf16_bits(g);
             S.d3T[o][r] = (uint16_t)d3[v];
@@ -510,7 +557,7 @@ __global__ __launch_bounds__(256) void k_fsai_backward(int32_t ntiles, const int
         for (int t = 0; t < 4; ++t) {
             f32x4 c = zero4();
 #pragma unroll
-            for (int s = 0; s < 4; ++s) c = mfma(w2t[t][s], d2[s], c);
+            for (int h = 0; h < 2; ++h) c = mfma32(w2t[t][h], cat(d2[2 * h], d2[2 * h + 1]), c);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const float g = Y.z1[t][v] > 0.f ? c[v] : 0.f;
