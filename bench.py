@@ -330,7 +330,7 @@ def main() -> int:
         "hbm_copy_gbs": copies,
         "spmv_frac_of_measured_copy": achieved / copy_gbs,
         "spmv_kind": {1: "vector_bins", 2: "stream", 3: "sliced", 4: "sliced_dict",
-                      5: "column_blocks", 6: "stencil_slices"}.get(res["spmv_kind"]),
+                      5: "column_blocks", 6: "stencil_slices", 7: "gap_slices"}.get(res["spmv_kind"]),
         "rel_res_true": res["rel_res_true"],
         "roofline": roofline_hbm(spmv_bytes, t_launch,
                                  measured_traffic("spmv_poisson3d_256" + (
@@ -673,7 +673,7 @@ def bench_matrix_market(args) -> int:
     gbs = spmv_algorithmic_bytes(A.n, A.nnz) / (spmv_us * 1e-6) / 1e9
     err = float(np.linalg.norm(x.cpu().numpy() - xs) / np.linalg.norm(xs))
     kinds = {1: "vector_bins", 2: "stream", 3: "sliced", 4: "sliced_dict", 5: "column_blocks",
-             6: "stencil_slices"}
+             6: "stencil_slices", 7: "gap_slices"}
     line = _line("CG iters/s on a Matrix Market matrix (fixed work); time to 1e-10", res["iterations"] / sec,
                  "iter/s", args, 1e3 * sec,
                  {"workload": f"matrix_market:{os.path.basename(args.mtx)}", "n": A.n, "nnz": A.nnz,

@@ -121,14 +121,22 @@ typedef struct cg_opts {
                               columns are row + a slice-uniform offset and a
                               byte per row marks the present slots; rows of at
                               most 8 nonzeros, at most 8 distinct offsets per
-                              slice, float64; else 4).
+                              slice, float64; else 4),
+                              7 gap-coded slices (the sliced layout of 3 with
+                              each row's first column as int32 and every
+                              further column as its gap to the previous one
+                              in 16 bits, read by the float64 plain and dot
+                              products; rows of at most 8 nonzeros whose
+                              consecutive columns lie at most 65,536 apart;
+                              else 3).
                               Automatic picks 5 when more than half of the
                               entries lie farther than 262,144 columns from the
                               diagonal and the vector spans at least two blocks,
                               else 6 where it applies, else 4 when rows have
                               <= 8 nonzeros and every slice fits the table,
-                              else 3 when rows have <= 64 nonzeros and slicing
-                              pads by <= 25%, else 1.                          */
+                              else 7 where it applies, else 3 when rows have
+                              <= 64 nonzeros and slicing pads by <= 25%,
+                              else 1.                                          */
     int32_t spmv_colblock; /* columns per block of the column-blocked tiling
                               (spmv_kind 5); 0: 262,144 (2 MB of float64 p)     */
     double refine_delta;   /* mixed precision: a float64 refinement is made
@@ -170,8 +178,8 @@ typedef struct cg_result {
                                 plain float64 CG                                 */
     int32_t spmv_kind;       /* SpMV tiling used on the GPU rows: 1 vector bins,
                                 2 stream tiles, 3 sliced tiles, 4 dictionary-
-                                sliced tiles, 5 column blocks, 6 stencil slices
-                                (0: no GPU rows)                                 */
+                                sliced tiles, 5 column blocks, 6 stencil slices,
+                                7 gap-coded slices (0: no GPU rows)              */
 } cg_result;
 
 /* Create a solver for the n x n CSR matrix (host arrays, copied).  Rows

@@ -135,7 +135,7 @@ def batch_schedule(batch: "cgmi.Batch", systems, B, tune_if_missing: bool = True
 # ----------------------------------------------------------------------------- single-system SpMV tiling
 
 SPMV_KINDS = {1: "vector_bins", 2: "stream", 3: "sliced", 4: "sliced_dict", 5: "column_blocks",
-              6: "stencil_slices"}
+              6: "stencil_slices", 7: "gap_slices"}
 
 
 def tune_spmv(solver: "cgmi.Solver", b, iters: int = 20, grids=(0, 1024, 2048, 4096), reps: int = 3,

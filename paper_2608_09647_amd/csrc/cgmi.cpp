@@ -88,6 +88,12 @@ static int apply_schedule(cg_handle *h) {
                        h->opts.precision == CG_PREC_MIXED, h->opts.spmv_colblock);
 }
 
+// The spmv_kind code of the tiling in use (cg_result.spmv_kind).
+static int kind_code(const DevMatrix &A) {
+    static const int code[6] = {1, 2, 3, 4, 5, 6};   // kTileVector .. kTileStencil
+    return A.sched.kind == kTileSliced && A.use_gap ? 7 : code[A.sched.kind];
+}
+
 // float32 inner vectors of mixed precision (the float32 matrix copies are
 // made by dm_schedule).
 static int ensure_mixed_vectors(cg_handle *h) {
@@ -368,7 +374,7 @@ extern "C" int cg_set_opts(cg_handle *h, const cg_opts *o) {
         return fail(CG_EINVAL, "refine_delta must be in (0, 1)");
     if ((o->precision != CG_PREC_FP64 || o->precond != CG_PC_NONE) && !h->gpu_only())
         return fail(CG_EINVAL, "mixed precision and preconditioning need a GPU-only handle");
-    if (o->spmv_kind < 0 || o->spmv_kind > 6) return fail(CG_EINVAL, "unknown spmv_kind %d", o->spmv_kind);
+    if (o->spmv_kind < 0 || o->spmv_kind > 7) return fail(CG_EINVAL, "unknown spmv_kind %d", o->spmv_kind);
     if (o->spmv_colblock < 0) return fail(CG_EINVAL, "spmv_colblock must be >= 0");
     if (o->vectors != CG_VECTORS_DEVICE && o->vectors != CG_VECTORS_HOST)
         return fail(CG_EINVAL, "vectors must be CG_VECTORS_DEVICE or CG_VECTORS_HOST");
@@ -1157,8 +1163,7 @@ extern "C" int cg_solve_noalloc(cg_handle *h, const double *b, double *x, double
     const int rc = solve_plain(h, w, b, x, tol, maxit, res);
     if (res) {
         res->t_solve = now() - t0;
-        static const int kind_code[6] = {1, 2, 3, 4, 5, 6};   // kTileVector .. kTileStencil
-        res->spmv_kind = kind_code[h->A.sched.kind];
+        res->spmv_kind = kind_code(h->A);
         res->rows_gpu = h->m;
         res->nnz_gpu = h->nnz_gpu;
         if (rc < 0 && res->status == 0) res->status = rc;
@@ -1258,8 +1263,7 @@ static int solve_impl(cg_handle *h, const double *b, double *x, double tol, int3
     }
     if (res) {
         res->t_solve = now() - t0;
-        static const int kind_code[6] = {1, 2, 3, 4, 5, 6};   // kTileVector .. kTileStencil
-        res->spmv_kind = h->m == 0 ? 0 : kind_code[h->A.sched.kind];
+        res->spmv_kind = h->m == 0 ? 0 : kind_code(h->A);
         res->rows_gpu = h->m;
         res->rows_cpu = h->n - h->m;
         res->nnz_gpu = h->nnz_gpu;

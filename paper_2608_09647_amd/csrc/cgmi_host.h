@@ -52,6 +52,10 @@ struct DevMatrix {
     float *d_val32 = nullptr, *d_sell_val32 = nullptr;
     uint8_t *d_sell_len = nullptr;    // sliced layout: row lengths (ntiles x 64 bytes)
     int32_t *d_tile_row = nullptr;    // adaptive stream tiles: first row of each tile
+    uint8_t *d_sell_lenx = nullptr;   // gap-coded slices: length and offset bits per row
+    uint16_t *d_sell_gap = nullptr;   //   16-bit column codes, slot-major
+    int8_t gap_state = 0;             //   0 unchecked, 1 built, -1 the pattern does not fit
+    bool use_gap = false;             //   the float64 paired tiles read them (spmv_kind 7)
     uint32_t *d_sell_idx = nullptr;   // dictionary-sliced layout
     int32_t *d_sell_dict = nullptr;
     int32_t *d_st_off = nullptr, *d_st_offs = nullptr;   // stencil-sliced layout
@@ -67,7 +71,8 @@ struct DevMatrix {
         return CsrDev{m, d_rp, d_ci, d_val, sched.identity ? nullptr : d_rows,
                       d_sell_off, d_sell_ci, d_sell_val, d_val32, d_sell_val32,
                       d_sell_idx, d_sell_dict, pad_col_base, cb,
-                      d_st_off, d_st_offs, d_st_mask, d_st_val, d_sell_len, d_tile_row};
+                      d_st_off, d_st_offs, d_st_mask, d_st_val, d_sell_len, d_tile_row,
+                      use_gap ? d_sell_lenx : nullptr, use_gap ? d_sell_gap : nullptr};
     }
 };
 

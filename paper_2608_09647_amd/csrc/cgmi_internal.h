@@ -63,6 +63,18 @@ constexpr int kStreamNnz = kWaveSize * kStreamPerLane;
 // rows stored slot-major (slot j of every row of the slice, then slot j+1,
 // ...), padded to the slice's longest row; slice t starts at sell_off[t].
 constexpr int kSliceMaxWidth = 8;  // widths up to this take the unrolled path
+// Gap-coded slices (spmv_kind 7; the sliced layout, float64 paired tiles):
+// 16-bit codes in sell_gap, slot-major like the values, and one byte per row
+// in sell_lenx (64 per slice): bits 0-3 the row's length, bits 4-7 bits
+// 16-19 of its first-column offset.  Slot 0 of a row holds bits 0-15 of that
+// offset, first column minus the row's global index as a 20-bit two's
+// complement number (an empty row, or a padding row of the last slice,
+// starts at the block's last row); slot j >= 1 holds column j minus column
+// j-1 minus 1 (0 in padding slots, which the kernel recognises by the
+// length: they gather the row's last entry again and are never summed).
+// Applies where rows have at most 8 entries, consecutive columns lie at most
+// 2^16 apart and first columns within 2^19 of the diagonal: 2 index bytes
+// per slot instead of 4.
 // Dictionary-sliced tiles (kind kTileSlicedDict): the sliced layout's values
 // with the columns replaced by 4 bits per slot.  Slice t keeps up to 15
 // distinct column offsets (column - global row) in sell_dict[16t .. 16t+14]
@@ -141,6 +153,8 @@ struct CsrDev {
     const double *st_val;     //   slot-major values
     const uint8_t *sell_len;  // sliced layout: row lengths, one byte per row (64 per slice)
     const int32_t *tile_row;  // adaptive stream tiles: first row of each tile (ntiles + 1)
+    const uint8_t *sell_lenx; // gap-coded slices: length and offset bits per row (64 per slice)
+    const uint16_t *sell_gap; //   slot-major 16-bit column codes
 };
 
 // Per-block operands of the column-blocked tiling (kept on the host by the

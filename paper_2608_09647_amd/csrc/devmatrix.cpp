@@ -48,6 +48,27 @@ void free_sliced(DevMatrix &M) {
     M.d_st_mask = nullptr;
     M.d_st_val = nullptr;
     M.st_slots = 0;
+    (void)hipFree(M.d_sell_lenx);
+    (void)hipFree(M.d_sell_gap);
+    M.d_sell_lenx = nullptr;
+    M.d_sell_gap = nullptr;
+    M.gap_state = 0;
+    M.use_gap = false;
+}
+
+// Slot offsets of the sliced layout: slice t holds max(1, longest row) slots
+// of 64 entries each.
+void slice_offsets(const DevMatrix &M, int32_t nt, std::vector<int32_t> &off) {
+    const int32_t m = M.m;
+    off.assign((size_t)nt + 1, 0);
+#pragma omp parallel for schedule(static)
+    for (int32_t t = 0; t < nt; ++t) {
+        int32_t w = 0;
+        for (int32_t i = t * kWaveSize; i < std::min(m, (t + 1) * kWaveSize); ++i)
+            w = std::max(w, M.h_rp[i + 1] - M.h_rp[i]);
+        off[t + 1] = std::max(w, 1) * kWaveSize;
+    }
+    for (int32_t t = 0; t < nt; ++t) off[t + 1] += off[t];
 }
 
 // Stencil-sliced copy (see kTileStencil): per 64-row slice the sorted union
@@ -277,7 +298,7 @@ void build_schedule(const DevMatrix &M, int kind_opt, Schedule &S, std::vector<i
             return;
         }
     }
-    if (kind_opt == 4 || kind_opt == 3 || (kind_opt == 0 && maxlen <= 64)) {
+    if (kind_opt == 4 || kind_opt == 3 || kind_opt == 7 || (kind_opt == 0 && maxlen <= 64)) {
         const int32_t nt = (m + kWaveSize - 1) / kWaveSize;
         int64_t slots = 0;
         int maxw = 0;
@@ -348,15 +369,8 @@ void build_schedule(const DevMatrix &M, int kind_opt, Schedule &S, std::vector<i
 int build_sliced(DevMatrix &M, bool with_cols) {
     if (M.d_sell_off && (M.d_sell_ci || !with_cols)) return CG_OK;
     const int32_t m = M.m, nt = M.sched.ntiles;
-    std::vector<int32_t> off((size_t)nt + 1, 0);
-#pragma omp parallel for schedule(static)
-    for (int32_t t = 0; t < nt; ++t) {
-        int32_t w = 0;
-        for (int32_t i = t * kWaveSize; i < std::min(m, (t + 1) * kWaveSize); ++i)
-            w = std::max(w, M.h_rp[i + 1] - M.h_rp[i]);
-        off[t + 1] = std::max(w, 1) * kWaveSize;
-    }
-    for (int32_t t = 0; t < nt; ++t) off[t + 1] += off[t];
+    std::vector<int32_t> off;
+    slice_offsets(M, nt, off);
     const size_t slots = (size_t)off[nt] ? (size_t)off[nt] : 1;
     const bool first = !M.d_sell_off;
     const bool host_vals = !M.h_val.empty();
@@ -404,6 +418,75 @@ int build_sliced(DevMatrix &M, bool with_cols) {
         free_sliced(M);
         return fail(CG_ENOMEM, "sliced layout upload failed: %s", hipGetErrorString(e));
     }
+    return CG_OK;
+}
+
+// Gap-coded columns of the sliced layout (see sell_lenx / sell_gap): built
+// when every code fits (rows of at most 15 entries, consecutive columns at
+// most 2^16 apart, first columns within 2^19 of the row's own index); *fits
+// says whether they apply.  An empty row, and a padding row of the last
+// slice, starts at the block's last row, a column every lane may gather.
+int build_gaps(DevMatrix &M, bool *fits) {
+    *fits = false;
+    if (M.gap_state < 0) return CG_OK;
+    if (M.gap_state > 0) {
+        *fits = true;
+        return CG_OK;
+    }
+    const int32_t m = M.m, nt = M.sched.ntiles;
+    // offset of row i's first column from its global index
+    auto first_off = [&](int32_t i) -> int64_t {
+        const int64_t own = (int64_t)M.pad_col_base + i;
+        if (i < m && M.h_rp[i + 1] > M.h_rp[i]) return (int64_t)M.h_ci[M.h_rp[i]] - own;
+        return (int64_t)M.pad_col_base + std::max(m - 1, 0) - own;
+    };
+    int bad = 0;
+#pragma omp parallel for reduction(| : bad) schedule(static)
+    for (int32_t i = 0; i < m; ++i) {
+        const int64_t o = first_off(i);
+        bad |= M.h_rp[i + 1] - M.h_rp[i] > 15 || o < -(1 << 19) || o >= (1 << 19);
+        for (int32_t k = M.h_rp[i] + 1; k < M.h_rp[i + 1]; ++k) {
+            const int64_t d = (int64_t)M.h_ci[k] - (int64_t)M.h_ci[k - 1];
+            bad |= d < 1 || d > 0x10000;
+        }
+    }
+    if (bad) {
+        M.gap_state = -1;
+        return CG_OK;
+    }
+    std::vector<int32_t> off;
+    slice_offsets(M, nt, off);
+    const size_t slots = (size_t)off[nt] ? (size_t)off[nt] : 1;
+    std::vector<uint16_t> code(slots, 0);
+    std::vector<uint8_t> lenx((size_t)nt * kWaveSize, 0);
+#pragma omp parallel for schedule(static)
+    for (int32_t t = 0; t < nt; ++t) {
+        const int32_t w = (off[t + 1] - off[t]) / kWaveSize;
+        for (int32_t l = 0; l < kWaveSize; ++l) {
+            const int32_t i = t * kWaveSize + l;
+            const int32_t b = i < m ? M.h_rp[i] : 0;
+            const int32_t len = i < m ? M.h_rp[i + 1] - M.h_rp[i] : 0;
+            const uint32_t o = (uint32_t)first_off(i) & 0xFFFFFu;   // 20-bit two's complement
+            lenx[(size_t)i] = (uint8_t)(len | ((o >> 16) << 4));
+            code[(size_t)off[t] + l] = (uint16_t)(o & 0xFFFFu);
+            for (int32_t j = 1; j < std::min(w, len); ++j)
+                code[(size_t)off[t] + (size_t)j * kWaveSize + l] = (uint16_t)(M.h_ci[b + j] - M.h_ci[b + j - 1] - 1);
+        }
+    }
+    hipError_t e = dmalloc(&M.d_sell_lenx, lenx.size() ? lenx.size() : 1);
+    if (e == hipSuccess) e = dmalloc(&M.d_sell_gap, code.size());
+    if (e == hipSuccess && !lenx.empty())
+        e = hipMemcpy(M.d_sell_lenx, lenx.data(), lenx.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(M.d_sell_gap, code.data(), sizeof(uint16_t) * code.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(M.d_sell_lenx);
+        (void)hipFree(M.d_sell_gap);
+        M.d_sell_lenx = nullptr;
+        M.d_sell_gap = nullptr;
+        return fail(CG_ENOMEM, "gap-coded columns upload failed: %s", hipGetErrorString(e));
+    }
+    M.gap_state = 1;
+    *fits = true;
     return CG_OK;
 }
 
@@ -623,10 +706,19 @@ int dm_schedule(DevMatrix &M, int kind_opt, int grid_opt, int cus, int grid_cap,
         const int rc = build_sliced(M, M.sched.kind == kTileSliced);
         if (rc) return rc;
     }
+    // gap-coded columns for the paired float64 tiles where the pattern allows
+    M.use_gap = false;
+    if (M.sched.kind == kTileSliced && (kind_opt == 0 || kind_opt == 7) &&
+        M.sched.bins[0].lanes <= kSliceMaxWidth) {
+        bool fits = false;
+        const int rc = build_gaps(M, &fits);
+        if (rc) return rc;
+        M.use_gap = fits;
+    }
     if (M.sched.kind == kTileStencil)
         M.sched.stream_nt = (int64_t)M.st_slots * (int64_t)sizeof(double) + (int64_t)M.m > kStreamNtBytes;
     else if (M.sched.kind == kTileSliced)
-        M.sched.stream_nt = (int64_t)M.sell_slots * (int64_t)(sizeof(double) + sizeof(int32_t)) + M.m >
+        M.sched.stream_nt = (int64_t)M.sell_slots * (int64_t)(sizeof(double) + (M.use_gap ? 2 : 4)) + M.m >
                             kStreamNtBytes;
     else
         M.sched.stream_nt = M.sched.kind == kTileSlicedDict &&

@@ -739,9 +739,15 @@ __device__ __forceinline__ void spmv_sten2_wave(const CsrDev &A, TileWalk &walk,
 struct Sliced2Geo {
     int off, width, wmax, ra;
     bool va, vb, mine;
+    uint32_t l2;   // GAP: the two rows' length bytes, loaded with the columns
 };
 
-template <bool NT>
+// GAP: the columns come as 16-bit codes (sell_lenx, sell_gap): one 4-byte
+// load of the two rows' codes per slot; slot 0 with the row's offset bits
+// gives its first column, and inside the row (slot < its length) each
+// further slot advances the column by its code plus one; past it the column
+// stays (a padding slot gathers the row's last entry again, never summed).
+template <bool NT, bool GAP>
 __device__ __forceinline__ void sliced2_cols(const CsrDev &A, int u, Sliced2Geo &G, int2 (&c)[kSliceMaxWidth]) {
     const int lane = threadIdx.x & (kWave - 1);
     const int half = lane >> 5, hl = lane & 31;
@@ -759,18 +765,47 @@ __device__ __forceinline__ void sliced2_cols(const CsrDev &A, int u, Sliced2Geo 
     G.ra = ts * kWave + 2 * hl;                   // the lane's rows ra, ra + 1
     G.va = G.mine && G.ra < A.m;
     G.vb = G.mine && G.ra + 1 < A.m;
-    const int ga = A.col_base + min(G.ra, A.m - 1);   // a column every lane may gather
+    if constexpr (GAP) {
+        // a half without a slice reads its partner's (ts == t0) bytes and slot
+        // 0 (G.off == off0), discards them and gathers a column every lane may
+        const uint16_t *lp = reinterpret_cast<const uint16_t *>(&A.sell_lenx[(int64_t)ts * kWave + 2 * hl]);
+        G.l2 = NT ? (uint32_t)__builtin_nontemporal_load(lp) : (uint32_t)*lp;
+        const uint32_t *g0p = reinterpret_cast<const uint32_t *>(&A.sell_gap[G.off + 2 * hl]);
+        const uint32_t g0 = NT ? __builtin_nontemporal_load(g0p) : *g0p;
+        // slot 0: 20-bit two's complement offsets from the rows' global
+        // indices, bits 16-19 from the bytes
+        const int oa = (int)((((G.l2 >> 4) & 0xFu) << 16) | (g0 & 0xFFFFu));
+        const int ob = (int)((((G.l2 >> 12) & 0xFu) << 16) | (g0 >> 16));
+        const int ga = A.col_base + min(G.ra, A.m - 1);
+        int2 cur = G.mine ? make_int2(A.col_base + G.ra + ((oa ^ 0x80000) - 0x80000),
+                                      A.col_base + G.ra + 1 + ((ob ^ 0x80000) - 0x80000))
+                          : make_int2(ga, ga);
+        c[0] = cur;
+        const int la = (int)(G.l2 & 0xFu), lb = (int)((G.l2 >> 8) & 0xFu);
 #pragma unroll
-    for (int j = 0; j < kSliceMaxWidth; ++j) {
-        c[j] = make_int2(ga, ga);
-        if (j < G.wmax && j < G.width) {
-            const int2 *cp = reinterpret_cast<const int2 *>(&A.sell_ci[G.off + j * kWave + 2 * hl]);
-            c[j] = NT ? make_int2(__builtin_nontemporal_load(&cp->x), __builtin_nontemporal_load(&cp->y)) : *cp;
+        for (int j = 1; j < kSliceMaxWidth; ++j) {
+            if (j < G.wmax && j < G.width) {
+                const uint32_t *gp = reinterpret_cast<const uint32_t *>(&A.sell_gap[G.off + j * kWave + 2 * hl]);
+                const uint32_t g = NT ? __builtin_nontemporal_load(gp) : *gp;
+                if (j < la) cur.x += (int)(g & 0xFFFFu) + 1;
+                if (j < lb) cur.y += (int)(g >> 16) + 1;
+            }
+            c[j] = cur;
+        }
+    } else {
+        const int ga = A.col_base + min(G.ra, A.m - 1);   // a column every lane may gather
+#pragma unroll
+        for (int j = 0; j < kSliceMaxWidth; ++j) {
+            c[j] = make_int2(ga, ga);
+            if (j < G.wmax && j < G.width) {
+                const int2 *cp = reinterpret_cast<const int2 *>(&A.sell_ci[G.off + j * kWave + 2 * hl]);
+                c[j] = NT ? make_int2(__builtin_nontemporal_load(&cp->x), __builtin_nontemporal_load(&cp->y)) : *cp;
+            }
         }
     }
 }
 
-template <int MODE, bool NT>
+template <int MODE, bool NT, bool GAP>
 __device__ __forceinline__ void sliced2_step(const CsrDev &A, const SpmvArgs<double> &a, const Sliced2Geo &G,
                                              const int2 (&c)[kSliceMaxWidth], int un, Sliced2Geo &Gn,
                                              int2 (&cn)[kSliceMaxWidth], double &acc0) {
@@ -790,12 +825,16 @@ __device__ __forceinline__ void sliced2_step(const CsrDev &A, const SpmvArgs<dou
             }
         }
     }
-    const int ts = G.ra & ~(kWave - 1);
-    const uint16_t *lp = reinterpret_cast<const uint16_t *>(&A.sell_len[(int64_t)ts + 2 * hl]);
-    const uint32_t l2 = G.mine ? (NT ? (uint32_t)__builtin_nontemporal_load(lp) : (uint32_t)*lp) : 0u;
+    uint32_t l2 = G.l2;
+    if constexpr (!GAP) {
+        const int ts = G.ra & ~(kWave - 1);
+        const uint16_t *lp = reinterpret_cast<const uint16_t *>(&A.sell_len[(int64_t)ts + 2 * hl]);
+        l2 = G.mine ? (NT ? (uint32_t)__builtin_nontemporal_load(lp) : (uint32_t)*lp) : 0u;
+    }
     // the next pair's columns (past the last pair: this pair's again, discarded)
-    sliced2_cols<NT>(A, un, Gn, cn);
-    const int la = G.va ? (int)(l2 & 0xFFu) : 0, lb = G.vb ? (int)(l2 >> 8) : 0;
+    sliced2_cols<NT, GAP>(A, un, Gn, cn);
+    const uint32_t lmask = GAP ? 0xFu : 0xFFu;   // gap-coded: the length is the low nibble
+    const int la = G.va ? (int)(l2 & lmask) : 0, lb = G.vb ? (int)((l2 >> 8) & lmask) : 0;
     double sa = 0.0, sb = 0.0;
     {
 #pragma clang fp contract(off)
@@ -822,20 +861,20 @@ __device__ __forceinline__ void sliced2_step(const CsrDev &A, const SpmvArgs<dou
     }
 }
 
-template <int MODE, bool NT>
+template <int MODE, bool NT, bool GAP>
 __device__ __forceinline__ void spmv_sliced2_wave(const CsrDev &A, TileWalk &walk, const SpmvArgs<double> &a,
                                                   double &acc0) {
     int u = walk.next();
     if (u < 0) return;
     Sliced2Geo G0, G1;
     int2 c0[kSliceMaxWidth], c1[kSliceMaxWidth];
-    sliced2_cols<NT>(A, u, G0, c0);
+    sliced2_cols<NT, GAP>(A, u, G0, c0);
     for (;;) {
         const int u1 = walk.next();
-        sliced2_step<MODE, NT>(A, a, G0, c0, u1 >= 0 ? u1 : u, G1, c1, acc0);
+        sliced2_step<MODE, NT, GAP>(A, a, G0, c0, u1 >= 0 ? u1 : u, G1, c1, acc0);
         if (u1 < 0) break;
         const int u2 = walk.next();
-        sliced2_step<MODE, NT>(A, a, G1, c1, u2 >= 0 ? u2 : u1, G0, c0, acc0);
+        sliced2_step<MODE, NT, GAP>(A, a, G1, c1, u2 >= 0 ? u2 : u1, G0, c0, acc0);
         if (u2 < 0) break;
         u = u2;
     }
@@ -865,7 +904,7 @@ __device__ __forceinline__ void spmv_row_wg(const CsrDev &A, int pos, bool ident
 // -6 / -7: stencil slices, cached / nontemporal (float64 only); -8 / -9: the
 // same with two rows per lane and 16-byte accesses (plain and dot modes);
 // -10 / -11: sliced tiles with two rows per lane, cached / nontemporal
-// (float64, plain and dot modes).
+// (float64, plain and dot modes); -12 / -13: the same with gap-coded columns.
 template <int MODE, int TILE, class T>
 __global__ __launch_bounds__(kBlock) void k_spmv(int32_t m, const int32_t *__restrict__ rp,
                                                  const int32_t *__restrict__ ci,
@@ -882,11 +921,14 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int32_t m, const int32_t *__res
                                                  const double *__restrict__ st_val,
                                                  const uint8_t *__restrict__ sell_len,
                                                  const int32_t *__restrict__ tile_row,
+                                                 const uint8_t *__restrict__ sell_lenx,
+                                                 const uint16_t *__restrict__ sell_gap,
                                                  Schedule S, SpmvArgs<T> a, double *__restrict__ out,
                                                  Partials in0, Partials in1,
                                                  DevState *__restrict__ st, int flags) {
     CsrDev A{m, rp, ci, nullptr, rows, sell_off, sell_ci, nullptr, nullptr, nullptr,
-             sell_idx, sell_dict, col_base, nullptr, st_off, st_offs, st_mask, st_val, sell_len, tile_row};
+             sell_idx, sell_dict, col_base, nullptr, st_off, st_offs, st_mask, st_val, sell_len, tile_row,
+             sell_lenx, sell_gap};
     if constexpr (sizeof(T) == 8) {
         A.val = reinterpret_cast<const double *>(val);
         A.sell_val = reinterpret_cast<const double *>(sell_val);
@@ -916,7 +958,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int32_t m, const int32_t *__res
     }
     double acc0 = 0.0, acc1 = 0.0;
     const bool identity = S.identity != 0;
-    TileWalk walk(TILE <= -8 && TILE >= -11 ? (S.ntiles + 1) / 2 : S.ntiles);   // slice pairs
+    TileWalk walk(TILE <= -8 && TILE >= -13 ? (S.ntiles + 1) / 2 : S.ntiles);   // slice pairs
     if constexpr (TILE == -2 || TILE == -3) {
         spmv_sliced_wave<MODE, T>(A, walk, a, TILE == -3, acc0, acc1);
     } else if constexpr (TILE == -4 || TILE == -5) {
@@ -926,9 +968,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int32_t m, const int32_t *__res
     } else if constexpr (TILE == -8 || TILE == -9) {
         if constexpr (sizeof(T) == 8 && (MODE == kSpmvPlain || MODE == kSpmvDot))
             spmv_sten2_wave<MODE, TILE == -9>(A, walk, a, acc0);
-    } else if constexpr (TILE == -10 || TILE == -11) {
+    } else if constexpr (TILE <= -10 && TILE >= -13) {
         if constexpr (sizeof(T) == 8 && (MODE == kSpmvPlain || MODE == kSpmvDot))
-            spmv_sliced2_wave<MODE, TILE == -11>(A, walk, a, acc0);
+            spmv_sliced2_wave<MODE, TILE == -11 || TILE == -13, TILE <= -12>(A, walk, a, acc0);
     } else if constexpr (TILE == -1) {
         T *lds = s_prod + (threadIdx.x / kWave) * kStreamNnz;
         spmv_stream_wave<MODE, T>(A, walk, a, lds, acc0, acc1);
@@ -1631,7 +1673,10 @@ void launch_spmv_mode(const CsrDev &A, const Schedule &S, int grid, const SpmvAr
     const int L = S.kind == kTileStencil ? (wide ? (S.stream_nt ? -9 : -8) : (S.stream_nt ? -7 : -6))
                   : S.kind == kTileSlicedDict ? (S.stream_nt ? -5 : -4)
                   : S.kind == kTileSliced ? (S.bins[0].lanes <= kSliceMaxWidth
-                                                 ? (wide && A.sell_len ? (S.stream_nt ? -11 : -10) : -2)
+                                                 ? (wide && A.sell_len
+                                                        ? (A.sell_gap ? (S.stream_nt ? -13 : -12)
+                                                                      : (S.stream_nt ? -11 : -10))
+                                                        : -2)
                                                  : -3)
                   : S.kind == kTileStream ? -1
                   : (S.identity && S.nbins == 1 && S.huge_count == 0) ? S.bins[0].lanes : 0;
@@ -1646,8 +1691,8 @@ void launch_spmv_mode(const CsrDev &A, const Schedule &S, int grid, const SpmvAr
 #define CGMI_SPMV(FL)                                                                             \
     hipLaunchKernelGGL((k_spmv<MODE, FL, T>), dim3(grid), dim3(kBlock), 0, s, A.m, A.rp, A.ci, val, \
                        A.rows, A.sell_off, A.sell_ci, sval, A.sell_idx, A.sell_dict, A.col_base,       \
-                       A.st_off, A.st_offs, A.st_mask, A.st_val, A.sell_len, A.tile_row, S, a,        \
-                       out, in0, in1, st, flags)
+                       A.st_off, A.st_offs, A.st_mask, A.st_val, A.sell_len, A.tile_row, A.sell_lenx,   \
+                       A.sell_gap, S, a, out, in0, in1, st, flags)
     switch (L) {
         case 1: CGMI_SPMV(1); break;
         case 2: CGMI_SPMV(2); break;
@@ -1667,6 +1712,8 @@ void launch_spmv_mode(const CsrDev &A, const Schedule &S, int grid, const SpmvAr
         case -9: CGMI_SPMV(-9); break;
         case -10: CGMI_SPMV(-10); break;
         case -11: CGMI_SPMV(-11); break;
+        case -12: CGMI_SPMV(-12); break;
+        case -13: CGMI_SPMV(-13); break;
         default: CGMI_SPMV(0); break;
     }
 #undef CGMI_SPMV

@@ -180,3 +180,17 @@ def test_host_only_handle_runs_on_host_threads(cg):
     assert true <= 1.01e-10 and abs(res["rel_res_true"] - true) <= 1e-3 * true
     lam = 2 - 2 * np.cos(np.arange(1, 17) * np.pi / 17)
     assert np.linalg.norm(x - ref["x"]) <= 2 * (lam.max() / lam.min()) * 1e-10 * np.linalg.norm(ref["x"])
+
+
+def test_spmv_kind_range(cg):
+    """Tilings 0..7 are accepted (on a host-only handle the choice only takes
+    effect once GPU rows exist); anything else is CG_EINVAL."""
+    from paper_2608_09647_amd import inputs as I
+    A = I.poisson2d(6)
+    with cg.Solver(A, 0, 0) as s:
+        for k in range(8):
+            s.set_opts(spmv_kind=k)
+        for bad in (8, -1):
+            with pytest.raises(cg.CgError) as e:
+                s.set_opts(spmv_kind=bad)
+            assert e.value.code == cg.CG_EINVAL and "spmv_kind" in str(e.value)

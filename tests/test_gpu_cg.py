@@ -74,6 +74,7 @@ SPMV_CASES = {
     "poisson2d_64": lambda: I.poisson2d(64),
     "poisson3d_24": lambda: I.poisson3d(24),
     "poisson3d_ragged": lambda: I.poisson3d(13, 11, 7),
+    "poisson3d_planes_256": lambda: I.poisson3d(256, 256, 3),   # column gaps up to 65,536
     "random_spd_30k": lambda: I.random_spd_lognormal(30000, seed=3),
     "diffusion_100": lambda: I.diffusion2d(I.log_normal_field(100, 100, [1, 0])),
     "arrowhead_3000": lambda: arrowhead(3000),
@@ -115,7 +116,25 @@ def stencil_applies(A):
     return True
 
 
-@pytest.mark.parametrize("kind", [1, 2, 3, 4, 5, 6])
+def gaps_apply(A):
+    """Whether gap-coded slices (kind 7) apply: rows of at most 8 entries,
+    consecutive columns at most 2^16 apart, and every row's first column
+    within 2^19 of its own index (20-bit two's complement offsets)."""
+    lens = np.diff(A.row_ptr)
+    if lens.max() > 8:
+        return False
+    d = np.diff(A.col.astype(np.int64))
+    inner = np.ones(A.nnz, bool)
+    inner[A.row_ptr[:-1][lens > 0]] = False   # each row's first entry has no gap
+    d = d[inner[1:]]
+    if not np.all((d >= 1) & (d <= 65536)):
+        return False
+    rows = np.flatnonzero(lens > 0)
+    off = A.col[A.row_ptr[rows]].astype(np.int64) - rows
+    return bool(np.all((off >= -(1 << 19)) & (off < (1 << 19))))
+
+
+@pytest.mark.parametrize("kind", [1, 2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("name", ["poisson2d_64", "poisson3d_ragged", "diffusion_100", "tiny_7",
                                   "random_spd_30k", "tiny_1"])
 def test_spmv_tilings_match_oracle(cg, name, kind):
@@ -135,9 +154,12 @@ def test_spmv_tilings_match_oracle(cg, name, kind):
         assert used == 5
     if kind == 6 and stencil_applies(A):
         assert used == 6
-    if used in (2, 3, 4, 6):
-        # stream, sliced, dictionary-sliced and stencil tiles sum each row left
-        # to right with rounded products: the oracle's own order, so the bits agree
+    if kind == 7:
+        assert used == (7 if gaps_apply(A) else 3 if np.diff(A.row_ptr).max() <= 64 else 1)
+    if used in (2, 3, 4, 6, 7):
+        # stream, sliced (plain or gap-coded columns), dictionary-sliced and
+        # stencil tiles sum each row left to right with rounded products: the
+        # oracle's own order, so the bits agree
         assert np.array_equal(y, ref)
 
 
@@ -604,7 +626,7 @@ def test_full_size_poisson3d_256(cg):
 
 # ----------------------------------------------------------------------------- mixed precision
 
-@pytest.mark.parametrize("kind", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("kind", [0, 1, 2, 3, 4, 5, 7])
 @pytest.mark.parametrize("name", ["poisson3d_ragged", "random_spd_30k", "diffusion_100"])
 def test_spmv_f32_matches_oracle(cg, name, kind):
     A = SPMV_CASES[name]()
@@ -618,7 +640,7 @@ def test_spmv_f32_matches_oracle(cg, name, kind):
     scale = absA @ np.abs(x32).astype(np.float64) + 1e-30
     L = int(np.diff(A.row_ptr).max())
     assert np.max(np.abs(y.astype(np.float64) - ref) / scale) <= 2 * L * 2.0 ** -24
-    if used in (2, 3, 4):
+    if used in (2, 3, 4, 7):
         # stream and sliced rows are summed in float32 left to right: the oracle's order
         assert np.array_equal(y, ref)
 
@@ -709,22 +731,81 @@ def test_paper_inputs_absolute_tolerance(cg):
 
 
 
-@pytest.mark.parametrize("name", ["poisson3d_ragged", "diffusion_100", "poisson2d_64"])
+@pytest.mark.parametrize("name", ["poisson3d_ragged", "diffusion_100", "poisson2d_64", "poisson3d_planes_256"])
 def test_sliced_pairs_track_stencil_pairs_bitwise(cg, name):
     """Plain slices with two rows per lane (columns streamed, a length byte per
-    row) and stencil slices with two rows per lane sum every row in CSR order
-    and walk the same slice pairs with the same grid, so p^T q is added in the
-    same order: fixed-work CG iterates are equal bit for bit."""
+    row), the same with gap-coded columns, and stencil slices with two rows
+    per lane sum every row in CSR order and walk the same slice pairs with the
+    same grid, so p^T q is added in the same order: fixed-work CG iterates are
+    equal bit for bit."""
     A = SPMV_CASES[name]()
     b = I.rhs_of(A, I.uniform_vector(A.n, [17, 1]))
     out = {}
-    for kind in (3, 6):
+    for kind in (3, 6, 7):
         with cg.Solver(A) as s:
             s.set_opts(spmv_kind=kind, small_path=0)
             xs, res = s.solve(dev(b), tol=0.0, maxit=31)
             out[kind] = (res["spmv_kind"], host(xs))
-    assert out[3][0] == 3 and out[6][0] == 6
+    assert out[3][0] == 3 and out[6][0] == 6 and out[7][0] == 7
     assert np.array_equal(out[3][1], out[6][1])
+    assert np.array_equal(out[7][1], out[6][1])
+
+
+def _csr_from_lists(n, rows):
+    """CSR of per-row (columns, values) lists, columns kept in the given order."""
+    rp = np.zeros(n + 1, np.int32)
+    rp[1:] = np.cumsum([len(c) for c, _ in rows])
+    ci = np.concatenate([np.asarray(c, np.int32) for c, _ in rows])
+    va = np.concatenate([np.asarray(v, np.float64) for _, v in rows])
+    return I.CSR(n, rp, ci, va)
+
+
+@pytest.mark.parametrize("case", ["gap_65536", "gap_65537", "first_524287", "first_524288",
+                                  "first_-524288", "first_-524289", "wide_rows", "odd_rows"])
+def test_gap_coded_slices_edges(cg, case):
+    """Gap-coded slices at the edge of their range: a gap of 65,536 (the
+    largest one coded) and of 65,537 (plain slices); a row's first column
+    2^19 - 1 and -2^19 from its own index (coded) and one further (plain
+    slices); rows of 9 entries (plain slices); and an odd row count with
+    empty rows (the last pair holds one slice, empty rows start at the last
+    row).  The SpMV is bit-exact against the oracle in every case."""
+    rng = np.random.default_rng(21)
+    if case.startswith(("gap_", "first_")):
+        kind, far = case.split("_")
+        far = int(far)
+        n = 70_000 if kind == "gap" else 600_000
+        rows = []
+        for i in range(n):
+            cols = sorted({i, max(0, i - 1), min(n - 1, i + 1)})
+            rows.append((cols, rng.uniform(-1, 1, len(cols))))
+        if kind == "gap":
+            rows[3] = ([3, 3 + far], [4.0, -0.5])    # row 3's gap
+        else:
+            r = 7 if far > 0 else 7 - far            # a row whose only column is r + far
+            rows[r] = ([r + far], [4.0])
+        expect = 7 if case in ("gap_65536", "first_524287", "first_-524288") else 3
+    elif case == "wide_rows":
+        n = 3000
+        rows = [(sorted(rng.choice(n, 9, replace=False)), rng.uniform(-1, 1, 9)) for _ in range(n)]
+        expect = 3
+    else:
+        n = 64 * 5 + 37
+        rows = []
+        for i in range(n):
+            if i % 7 == 3:
+                rows.append(([], []))
+            else:
+                cols = sorted(set(rng.choice(n, 4, replace=False)) | {i})
+                rows.append((cols, rng.uniform(-1, 1, len(cols))))
+        expect = 7
+    A = _csr_from_lists(n, rows)
+    assert gaps_apply(A) == (expect == 7)
+    x = rng.uniform(-1, 1, n)
+    ref = oracle.spmv(A, x)
+    with cg.Solver(A) as s:
+        s.set_opts(spmv_kind=7, small_path=0)
+        assert used_kind(s, n) == expect
+        assert np.array_equal(host(s.spmv(dev(x))), ref)
 
 
 @pytest.mark.parametrize("name", ["poisson3d_24", "poisson3d_ragged", "poisson2d_64", "diffusion_100"])
