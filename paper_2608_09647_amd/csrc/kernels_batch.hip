@@ -16,13 +16,14 @@
 // the same p, so the x update is done there and B does not read p.
 // Every workgroup of a team sums the team's partials itself in a fixed order,
 // so all of them take identical decisions (and results are reproducible for
-// a fixed schedule).  A barrier is a counter in device memory: each wave
-// waits until its stores have reached the L2, then one thread per workgroup
-// writes the L2 back (device-scope release fence) and waits for the
-// write-back to finish, adds 1 and waits until the team's count is reached,
-// and invalidates stale cache lines (device-scope acquire fence), again
-// waiting for completion, before the workgroup reads what the team wrote.  A wait is
-// bounded by a wall-clock limit; on expiry the error flag ends every team.
+// a fixed schedule).  A barrier is a counter in device memory: every wave
+// makes its stores visible device-wide (device-scope release fence), the
+// workgroup synchronises, one thread adds 1 to the team's counter and waits
+// until the team's count is reached, and device-scope acquire fences (the
+// waiting thread's, then every wave's after a second workgroup barrier)
+// drop stale cache lines before the workgroup reads what the team wrote.  A
+// wait is bounded by a wall-clock limit; on expiry the error flag ends every
+// team.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
