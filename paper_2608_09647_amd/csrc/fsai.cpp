@@ -582,16 +582,13 @@ struct cg_fsai_trainer {
     float *d_sval = nullptr;
     double *d_diag = nullptr;
     uint16_t *d_feats = nullptr;
-    float *d_out = nullptr, *d_dg = nullptr, *d_dout = nullptr;
+    float *d_out = nullptr, *d_dg = nullptr;
     float *d_theta = nullptr, *d_m = nullptr, *d_v = nullptr, *d_theta_eval = nullptr, *d_grad = nullptr;
     float *d_gpart = nullptr;
     double *d_lpart = nullptr;
     size_t lpart_cap = 0;
-    int32_t *d_tiles = nullptr;
-    size_t tiles_cap = 0;
-    int32_t *d_srow = nullptr, *d_sn = nullptr;
-    int64_t *d_sbase = nullptr;
-    size_t samp_cap = 0;
+    uint8_t *d_stage = nullptr;  // a step's tile list and samples, uploaded in one copy
+    size_t stage_cap = 0;
     int32_t step = 0;
 };
 
@@ -601,10 +598,9 @@ constexpr int kTrainGrid = 256;   // workgroups of the backward pass (gradient p
 
 void trainer_free(cg_fsai_trainer *t) {
     for (void *p : {(void *)t->d_scol, (void *)t->d_sval, (void *)t->d_diag, (void *)t->d_feats,
-                    (void *)t->d_out, (void *)t->d_dg, (void *)t->d_dout, (void *)t->d_theta, (void *)t->d_m,
+                    (void *)t->d_out, (void *)t->d_dg, (void *)t->d_theta, (void *)t->d_m,
                     (void *)t->d_v, (void *)t->d_theta_eval, (void *)t->d_grad, (void *)t->d_gpart,
-                    (void *)t->d_lpart, (void *)t->d_tiles, (void *)t->d_srow, (void *)t->d_sn,
-                    (void *)t->d_sbase})
+                    (void *)t->d_lpart, (void *)t->d_stage})
         (void)hipFree(p);
     delete t;
 }
@@ -639,42 +635,51 @@ int run_loss_grad(cg_fsai_trainer *t, const float *theta, int32_t nsel, const in
                 return fail(CG_EINVAL, "row %d out of range for system %d", row, sys[s]);
         }
     }
-    std::vector<int32_t> uniq(sys, sys + nsel), tiles, srow(nsamp), sn(nsamp);
-    std::vector<int64_t> sbase(nsamp);
+    std::vector<int32_t> uniq(sys, sys + nsel);
     std::sort(uniq.begin(), uniq.end());
     uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+    int64_t ntiles64 = 0;
+    for (int32_t s : uniq) ntiles64 += (t->n[s] + 15) / 16;
+    if (ntiles64 > INT32_MAX / 4) return fail(CG_EINVAL, "too many rows in one step");
+    const int32_t ntiles = (int32_t)ntiles64;
+    // staging: tiles (int32), sample rows (int32), system sizes (int32),
+    // system first rows (int64), each at an 8-byte aligned offset
+    auto up8 = [](size_t b) { return (b + 7) & ~(size_t)7; };
+    const size_t o_srow = up8(sizeof(int32_t) * (size_t)ntiles);
+    const size_t o_sn = up8(o_srow + sizeof(int32_t) * (size_t)nsamp);
+    const size_t o_sbase = up8(o_sn + sizeof(int32_t) * (size_t)nsamp);
+    const size_t bytes = o_sbase + sizeof(int64_t) * (size_t)nsamp;
+    std::vector<uint8_t> blob(bytes, 0);
+    int32_t *tiles = reinterpret_cast<int32_t *>(blob.data());
+    int32_t *srow = reinterpret_cast<int32_t *>(blob.data() + o_srow);
+    int32_t *sn = reinterpret_cast<int32_t *>(blob.data() + o_sn);
+    int64_t *sbase = reinterpret_cast<int64_t *>(blob.data() + o_sbase);
+    int32_t nt = 0;
     for (int32_t s : uniq)
-        for (int64_t r = 0; r < t->n[s]; r += 16) tiles.push_back((int32_t)(t->base[s] + r));
+        for (int64_t r = 0; r < t->n[s]; r += 16) tiles[nt++] = (int32_t)(t->base[s] + r);
     for (int32_t k = 0; k < nsamp; ++k) {
         const int32_t s = sys[k / rows_per_sys];
         srow[k] = rows[k];
         sbase[k] = t->base[s];
         sn[k] = t->n[s];
     }
-    const int32_t ntiles = (int32_t)tiles.size();
-    const int32_t lblocks = (nsamp + 255) / 256;
-    int rc = ensure_capacity(&t->d_tiles, t->tiles_cap, tiles.size());
-    if (!rc) {
-        size_t c1 = t->samp_cap, c2 = t->samp_cap, c3 = t->samp_cap;
-        rc = ensure_capacity(&t->d_srow, c1, (size_t)nsamp);
-        if (!rc) rc = ensure_capacity(&t->d_sn, c2, (size_t)nsamp);
-        if (!rc) rc = ensure_capacity(&t->d_sbase, c3, (size_t)nsamp);
-        if (!rc) t->samp_cap = std::min(c1, std::min(c2, c3));
-    }
+    const int32_t lblocks = fsai_loss_blocks(nsamp);
+    int rc = ensure_capacity(&t->d_stage, t->stage_cap, bytes);
     if (!rc) rc = ensure_capacity(&t->d_lpart, t->lpart_cap, (size_t)lblocks);
     if (rc) return rc;
+    const int32_t *d_tiles = reinterpret_cast<const int32_t *>(t->d_stage);
+    const int32_t *d_srow = reinterpret_cast<const int32_t *>(t->d_stage + o_srow);
+    const int32_t *d_sn = reinterpret_cast<const int32_t *>(t->d_stage + o_sn);
+    const int64_t *d_sbase = reinterpret_cast<const int64_t *>(t->d_stage + o_sbase);
     hipStream_t st = t->stream;
-    HIP_TRY(hipMemcpy(t->d_tiles, tiles.data(), sizeof(int32_t) * tiles.size(), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(t->d_srow, srow.data(), sizeof(int32_t) * nsamp, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(t->d_sn, sn.data(), sizeof(int32_t) * nsamp, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(t->d_sbase, sbase.data(), sizeof(int64_t) * nsamp, hipMemcpyHostToDevice));
-    HIP_TRY(fsai_forward_outputs(ntiles, t->d_tiles, t->rows, t->d_feats, theta, t->d_out, st));
-    for (int32_t s : uniq) HIP_TRY(fill_f32((int64_t)t->n[s] * 3, t->d_dg + t->base[s] * 3, 0.f, st));
-    HIP_TRY(fsai_loss(nsamp, t->d_srow, t->d_sbase, t->d_sn, t->d_out, t->d_scol, t->d_sval, t->d_dg,
+    HIP_TRY(hipMemcpyAsync(t->d_stage, blob.data(), bytes, hipMemcpyHostToDevice, st));
+    // outputs of every row of the sampled systems, their dL/dG~ cleared
+    HIP_TRY(fsai_forward_outputs(ntiles, d_tiles, t->rows, t->d_feats, theta, t->d_out, t->d_dg, st));
+    HIP_TRY(fsai_loss(nsamp, d_srow, d_sbase, d_sn, t->d_out, t->d_scol, t->d_sval, t->d_dg,
                       (float)(2.0 / nsamp), t->d_lpart, st));
-    for (int32_t s : uniq) HIP_TRY(fsai_dout(t->base[s], t->n[s], t->d_out, t->d_dg, t->d_scol, t->d_dout, st));
     const int32_t grid = std::max(1, std::min(kTrainGrid, (ntiles + 3) / 4));
-    HIP_TRY(fsai_backward(ntiles, t->d_tiles, t->d_feats, theta, t->d_dout, t->d_gpart, grid, st));
+    HIP_TRY(fsai_backward(ntiles, d_tiles, t->d_feats, theta, t->d_out, t->d_dg, t->d_scol, t->d_gpart, grid,
+                          st));
     HIP_TRY(fsai_adam(grid, t->d_gpart, t->d_theta, t->d_m, t->d_v, t->d_grad, adam_step, (float)lr, st));
     std::vector<double> lp((size_t)lblocks);
     HIP_TRY(hipMemcpyAsync(lp.data(), t->d_lpart, sizeof(double) * lblocks, hipMemcpyDeviceToHost, st));
@@ -735,7 +740,6 @@ extern "C" int cg_fsai_trainer_create(int32_t nsys, const int32_t *n, const int6
     if (e == hipSuccess) e = dmalloc(&t->d_feats, R * kFeatPad);
     if (e == hipSuccess) e = dmalloc(&t->d_out, R * kOutPad);
     if (e == hipSuccess) e = dmalloc(&t->d_dg, R * 3);
-    if (e == hipSuccess) e = dmalloc(&t->d_dout, R * kOutPad);
     if (e == hipSuccess) e = dmalloc(&t->d_theta, kNParams);
     if (e == hipSuccess) e = dmalloc(&t->d_m, kNParams);
     if (e == hipSuccess) e = dmalloc(&t->d_v, kNParams);
@@ -743,9 +747,9 @@ extern "C" int cg_fsai_trainer_create(int32_t nsys, const int32_t *n, const int6
     if (e == hipSuccess) e = dmalloc(&t->d_grad, kNParams);
     if (e == hipSuccess) e = dmalloc(&t->d_gpart, (size_t)kTrainGrid * kNParams);
     if (e != hipSuccess) return bail(fail(CG_ENOMEM, "trainer allocation: %s", hipGetErrorString(e)));
-    // padding rows: no features, no output gradient, no slots
+    // padding rows: no features and no slots (their dL/dG~ is cleared with
+    // the other rows of their tiles at every step)
     if (e == hipSuccess) e = hipMemset(t->d_feats, 0, sizeof(uint16_t) * R * kFeatPad);
-    if (e == hipSuccess) e = hipMemset(t->d_dout, 0, sizeof(float) * R * kOutPad);
     if (e == hipSuccess) e = hipMemset(t->d_scol, 0xFF, sizeof(int32_t) * R * kSlots);
     if (e == hipSuccess) e = hipMemset(t->d_m, 0, sizeof(float) * kNParams);
     if (e == hipSuccess) e = hipMemset(t->d_v, 0, sizeof(float) * kNParams);

@@ -44,10 +44,12 @@ hipError_t fsai_prepare(int32_t n, const int32_t *rp, const int32_t *ci, const d
                         int32_t *scol, float *sval, double *diag, uint16_t *feats, int32_t *err,
                         hipStream_t s);
 
-// Network outputs out[row][8] (0..4 valid) for the listed 16-row tiles
-// (tiles[t] = first row; rows >= nrows are skipped).
+// Network outputs out[row][8] (0..4 valid, 5..7 zero) for the listed 16-row
+// tiles (tiles[t] = first row; rows >= nrows are skipped); dg_zero[row][3]
+// of the same rows is set to 0.
 hipError_t fsai_forward_outputs(int32_t ntiles, const int32_t *tiles, int64_t nrows,
-                                const uint16_t *feats, const float *theta, float *out, hipStream_t s);
+                                const uint16_t *feats, const float *theta, float *out, float *dg_zero,
+                                hipStream_t s);
 
 // Inference for all n rows: G values into gval (CSR of tril(A); gpos[i][3]
 // = positions of the C, W, S entries of row i, -1 absent) and G^T values into
@@ -57,25 +59,26 @@ hipError_t fsai_forward_factor(int32_t n, const uint16_t *feats, const float *th
                                const int32_t *tpos, double *gval, double *gtval, hipStream_t s);
 
 // Loss terms and dL/dG~ (dg[row][3]: C, W, S; accumulated with atomics) of
-// the sampled rows; partials[block] = sum of squared entries of E.
+// the sampled rows, one wavefront per sample; partials[block] = sum of
+// squared entries of E, fsai_loss_blocks(nsamp) of them.
+inline int32_t fsai_loss_blocks(int32_t nsamp) {
+    const int32_t b = (nsamp + 3) / 4;
+    return b < 1 ? 1 : b > 2048 ? 2048 : b;
+}
 hipError_t fsai_loss(int32_t nsamp, const int32_t *samp_row, const int64_t *samp_base,
                      const int32_t *samp_n, const float *out, const int32_t *scol, const float *sval,
                      float *dg, float coef, double *partials, hipStream_t s);
 
-// dL/do of rows row0 .. row0 + n - 1.
-hipError_t fsai_dout(int64_t row0, int32_t n, const float *out, const float *dg, const int32_t *scol,
-                     float *dout, hipStream_t s);
-
 // Parameter gradient of the listed 16-row tiles: gpart[block][kNParams].
+// dL/do of a row is formed from dL/dG~ (dg), the outputs and the slot table.
 hipError_t fsai_backward(int32_t ntiles, const int32_t *tiles, const uint16_t *feats, const float *theta,
-                         const float *dout, float *gpart, int32_t grid, hipStream_t s);
+                         const float *out, const float *dg, const int32_t *scol, float *gpart, int32_t grid,
+                         hipStream_t s);
 
 // Sum of nparts gradient partials (in order) into grad_out (may be null);
 // with t_step >= 1 an Adam step on theta (m, v: moments).
 hipError_t fsai_adam(int32_t nparts, const float *gpart, float *theta, float *m, float *v,
                      float *grad_out, int32_t t_step, float lr, hipStream_t s);
-
-hipError_t fill_f32(int64_t n, float *p, float v, hipStream_t s);
 
 // Copy CSR values into the slot-major sliced layout (slices of 64 rows).
 hipError_t sell_refresh(int32_t m, int32_t ntiles, const int32_t *rp, const int32_t *sell_off,

@@ -256,7 +256,8 @@ __global__ __launch_bounds__(256) void k_fsai_forward(int32_t ntiles, const int3
                                                       const int32_t *__restrict__ gpos,
                                                       const int32_t *__restrict__ tpos,
                                                       double *__restrict__ gval,
-                                                      double *__restrict__ gtval) {
+                                                      double *__restrict__ gtval,
+                                                      float *__restrict__ dg_zero) {
     __shared__ ParamLds P;
     stage_params(th, P);
     Frags W;
@@ -273,10 +274,13 @@ __global__ __launch_bounds__(256) void k_fsai_forward(int32_t ntiles, const int3
         forward_tile(W, P, fin, Y);
         if (row >= nrows) continue;
         if (TRAIN) {
-            // outputs 0..7 of the row (5..7 are exact zeros: zero weights and bias)
+            // outputs 0..7 of the row (5..7 are exact zeros: zero weights and
+            // bias), and the row's dL/dG~ cleared for the loss to accumulate into
             if (q < kOutPad / 4)
                 *reinterpret_cast<float4 *>(out + row * kOutPad + 4 * q) =
                     make_float4(Y.o[0], Y.o[1], Y.o[2], Y.o[3]);
+            else if (q == 2)
+                for (int b = 0; b < 3; ++b) dg_zero[row * 3 + b] = 0.f;
         } else if (q == 0) {
             // lanes 0..15 hold o_C, o_W, o_E, o_S of their row
             const double oc = Y.o[0], ow = Y.o[1], os = Y.o[3];
@@ -297,9 +301,9 @@ __global__ __launch_bounds__(256) void k_fsai_forward(int32_t ntiles, const int3
 }
 
 // ---------------------------------------------------------------------------
-// Loss and dL/dG~ on sampled rows (thread per sample).  G~ of a row is read
-// from the network outputs; A_hat from the slot tables.  dG~ accumulates with
-// float atomics (order-dependent rounding only).
+// Loss and dL/dG~ on sampled rows, one wavefront per sample.  G~ of a row is
+// read from the network outputs; A_hat from the slot tables.  dG~
+// accumulates with float atomics (order-dependent rounding only).
 struct GRow {
     int col[3];      // C, W, S columns (-1 absent)
     float val[3];
@@ -327,8 +331,18 @@ __device__ __forceinline__ float ahat(int64_t base, int row, int colj, const int
     return 0.f;
 }
 
-constexpr int kMaxU = 16;   // support of a row of G~ A_hat (5-point: at most 13)
-constexpr int kMaxJ = 32;   // candidate rows j
+// Row i of G~ A_hat has at most 15 terms (G~ entry a of row i times slot s
+// of row col_a(i)); lane t = 5a + s holds term t's column and value, and
+// u_c is the sum, in term order, of the terms with column c.  The rows j
+// with (G~ A_hat G~^T)_ij possibly nonzero are those whose pattern {j, W(j),
+// S(j)} meets supp(u): for each term's column c, lane 3t + m proposes j =
+// c, c + 1 (the row whose W slot is c) or the row whose S slot is c, and
+// the lowest lane proposing a given j whose pattern holds c computes its
+// entry e_ij = (G~ A_hat G~^T)_ij - delta_ij, adds e_ij^2 to the loss and
+// its share of dL/dG~: coef e_ij u at j's columns into row j, and coef e_ij
+// (G~ A_hat)_{j, col_b(i)} into row i (summed over the wave, one atomic
+// per entry).
+constexpr int kLossTerms = 3 * kSlots;
 
 __global__ __launch_bounds__(256) void k_fsai_loss(int32_t nsamp, const int32_t *__restrict__ samp_row,
                                                    const int64_t *__restrict__ samp_base,
@@ -339,114 +353,95 @@ __global__ __launch_bounds__(256) void k_fsai_loss(int32_t nsamp, const int32_t 
                                                    float *__restrict__ dg, float coef,
                                                    double *__restrict__ partials) {
     __shared__ double sh[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     double loss = 0.0;
-    const int sidx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (sidx < nsamp) {
+    for (int sidx = blockIdx.x * 4 + wv; sidx < nsamp; sidx += gridDim.x * 4) {
         const int i = samp_row[sidx];
         const int64_t base = samp_base[sidx];
         const int n = samp_n[sidx];
         const GRow gi = g_row(base, i, out, scol);
-        // u = row i of G~ A_hat
-        int ucol[kMaxU];
-        float uval[kMaxU];
-        int nu = 0;
-        for (int a = 0; a < 3; ++a) {
-            const int k = gi.col[a];
-            if (k < 0) continue;
-            for (int s = 0; s < kSlots; ++s) {
-                const int c = scol[(base + k) * kSlots + s];
-                if (c < 0) continue;
-                const float v = gi.val[a] * sval[(base + k) * kSlots + s];
-                int p = 0;
-                while (p < nu && ucol[p] != c) ++p;
-                if (p == nu && nu < kMaxU) {
-                    ucol[nu] = c;
-                    uval[nu] = 0.f;
-                    ++nu;
-                }
-                if (p < kMaxU) uval[p] += v;
+        // term t of u (lanes 0..14; -1: absent)
+        int tcol = -1;
+        float tval = 0.f;
+        if (lane < kLossTerms) {
+            const int a = lane / kSlots, sl = lane % kSlots;
+            const int k = a == 0 ? gi.col[0] : a == 1 ? gi.col[1] : gi.col[2];
+            const float ga = a == 0 ? gi.val[0] : a == 1 ? gi.val[1] : gi.val[2];
+            if (k >= 0) {
+                tcol = scol[(base + k) * kSlots + sl];
+                if (tcol >= 0) tval = ga * sval[(base + k) * kSlots + sl];
             }
         }
-        // candidate rows j: those whose G~ pattern {j, W(j), S(j)} meets supp(u)
-        int jr[kMaxJ];
-        int nj = 0;
-        for (int p = 0; p < nu; ++p) {
-            const int c = ucol[p];
-            const int cand[3] = {c, c + 1, -1};
-            int cands[3] = {cand[0], cand[1], -1};
-            // the row whose S slot is c: the N neighbour of c
-            const int nn = scol[(base + c) * kSlots + kSlotN];
-            cands[2] = nn;
-            for (int m = 0; m < 3; ++m) {
-                const int j = cands[m];
-                if (j < 0 || j >= n) continue;
-                const GRow gj = g_row(base, j, out, scol);
-                if (gj.col[0] != c && gj.col[1] != c && gj.col[2] != c) continue;
-                int x = 0;
-                while (x < nj && jr[x] != j) ++x;
-                if (x == nj && nj < kMaxJ) jr[nj++] = j;
-            }
+        // candidate row of lane q = 3t + m
+        const int t = min(lane / 3, kLossTerms - 1), m = lane % 3;
+        const int c = __shfl(tcol, t, 64);
+        int j = -1;
+        if (lane < 3 * kLossTerms && c >= 0)
+            j = m == 0 ? c : m == 1 ? c + 1 : scol[(base + c) * kSlots + kSlotN];
+        GRow gj{{-1, -1, -1}, {0.f, 0.f, 0.f}};
+        if (j >= 0 && j < n) {
+            gj = g_row(base, j, out, scol);
+            if (gj.col[0] != c && gj.col[1] != c && gj.col[2] != c) j = -1;
+        } else {
+            j = -1;
         }
-        float gi_acc[3] = {0.f, 0.f, 0.f};
-        for (int x = 0; x < nj; ++x) {
-            const int j = jr[x];
-            const GRow gj = g_row(base, j, out, scol);
+        // the lowest lane proposing j owns it
+        bool own = j >= 0;
+        for (int q = 0; q < 3 * kLossTerms; ++q) {
+            const int jq = __shfl(j, q, 64);
+            if (q < lane && jq == j) own = false;
+        }
+        // u at j's columns (every lane takes part in the shuffles)
+        float ub[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < kLossTerms; ++q) {
+            const int cq = __shfl(tcol, q, 64);
+            const float vq = __shfl(tval, q, 64);
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                if (cq >= 0 && cq == gj.col[b]) ub[b] += vq;
+        }
+        float gacc[3] = {0.f, 0.f, 0.f};
+        if (own) {
             float mij = 0.f;
-            for (int b = 0; b < 3; ++b) {
-                if (gj.col[b] < 0) continue;
-                for (int p = 0; p < nu; ++p)
-                    if (ucol[p] == gj.col[b]) mij += gj.val[b] * uval[p];
-            }
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                if (gj.col[b] >= 0) mij += gj.val[b] * ub[b];
             const float e = mij - (j == i ? 1.f : 0.f);
             loss += (double)e * (double)e;
-            // dG~[j, b] += coef * e * u_b
-            for (int b = 0; b < 3; ++b) {
-                if (gj.col[b] < 0) continue;
-                float ub = 0.f;
-                for (int p = 0; p < nu; ++p)
-                    if (ucol[p] == gj.col[b]) ub = uval[p];
-                atomicAdd(&dg[(base + j) * 3 + b], coef * e * ub);
-            }
-            // dG~[i, b] += coef * e * (G~ A_hat)_{j, col_b(i)}
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                if (gj.col[b] >= 0) atomicAdd(&dg[(base + j) * 3 + b], coef * e * ub[b]);
+#pragma unroll
             for (int b = 0; b < 3; ++b) {
                 const int cb = gi.col[b];
                 if (cb < 0) continue;
                 float w = 0.f;
-                for (int s = 0; s < 3; ++s) {
-                    const int cs = gj.col[s];
+#pragma unroll
+                for (int s2 = 0; s2 < 3; ++s2) {
+                    const int cs = gj.col[s2];
                     if (cs < 0) continue;
-                    w += gj.val[s] * ahat(base, cs, cb, scol, sval);
+                    w += gj.val[s2] * ahat(base, cs, cb, scol, sval);
                 }
-                gi_acc[b] += coef * e * w;
+                gacc[b] = coef * e * w;
             }
         }
+#pragma unroll
         for (int b = 0; b < 3; ++b)
-            if (gi.col[b] >= 0) atomicAdd(&dg[(base + i) * 3 + b], gi_acc[b]);
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) gacc[b] += __shfl_xor(gacc[b], o, 64);
+        if (lane == 0)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                if (gi.col[b] >= 0) atomicAdd(&dg[(base + i) * 3 + b], gacc[b]);
     }
     // per-block loss partial
     double v = loss;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    if (lane == 0) sh[wv] = v;
     __syncthreads();
     if (threadIdx.x == 0) partials[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
-}
-
-// dL/do from dL/dG~ (thread per row of the listed systems' row range).
-__global__ void k_fsai_dout(int64_t row0, int32_t n, const float *__restrict__ out,
-                            const float *__restrict__ dg, const int32_t *__restrict__ scol,
-                            float *__restrict__ dout) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int64_t r = row0 + i;
-    const float oc = out[r * kOutPad];
-    const float sig = 1.f / (1.f + expf(-oc));
-    float *d = dout + r * kOutPad;
-    d[0] = dg[r * 3 + 0] * sig;
-    d[1] = scol[r * kSlots + kSlotW] >= 0 ? dg[r * 3 + 1] : 0.f;
-    d[2] = 0.f;
-    d[3] = scol[r * kSlots + kSlotS] >= 0 ? dg[r * 3 + 2] : 0.f;
-    d[4] = 0.f;
 }
 
 // ---------------------------------------------------------------------------
@@ -470,7 +465,9 @@ __device__ __forceinline__ void wave_sync() {
 __global__ __launch_bounds__(256) void k_fsai_backward(int32_t ntiles, const int32_t *__restrict__ tiles,
                                                        const uint16_t *__restrict__ feats,
                                                        const float *__restrict__ th,
-                                                       const float *__restrict__ dout,
+                                                       const float *__restrict__ out,
+                                                       const float *__restrict__ dg,
+                                                       const int32_t *__restrict__ scol,
                                                        float *__restrict__ gpart) {
     __shared__ WaveLds L[4];
     __shared__ float acc[kNParams];
@@ -528,13 +525,17 @@ __global__ __launch_bounds__(256) void k_fsai_backward(int32_t ntiles, const int
                 S.h2T[16 * t + 4 * q + v][r] = (uint16_t)Y.h2[t >> 1][4 * (t & 1) + v];
             }
         // dz3 (outputs 4q+v of row r)
+        // dL/do of row r from dL/dG~: through the softplus for C, directly for
+        // the W and S slots the row has, zero for the unused E and N
         bf16x4 d3;
-        const float4 dq = *reinterpret_cast<const float4 *>(dout + row * kOutPad + 4 * (q & 1));
-        const float dv[4] = {dq.x, dq.y, dq.z, dq.w};
+        const float oc = out[row * kOutPad];
+        const float sig = 1.f / (1.f + expf(-oc));
+        const float dv[4] = {dg[row * 3 + 0] * sig, scol[row * kSlots + kSlotW] >= 0 ? dg[row * 3 + 1] : 0.f,
+                             0.f, scol[row * kSlots + kSlotS] >= 0 ? dg[row * 3 + 2] : 0.f};
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int o = 4 * q + v;
-            const float g = o < kOut ? dv[v] : 0.f;
+            const float g = q == 0 ? dv[v] : 0.f;
             gb3[v] += g;
             d3[v] = (short)bf16_bits(g);
             S.d3T[o][r] = (uint16_t)d3[v];
@@ -624,24 +625,44 @@ __global__ __launch_bounds__(256) void k_fsai_backward(int32_t ntiles, const int
         gpart[(int64_t)blockIdx.x * kNParams + p] = acc[p];
 }
 
-// Sum of the workgroup gradients in order; Adam step when t_step > 0, else the
-// gradient is only written to grad_out.
-__global__ void k_fsai_adam(int32_t nparts, const float *__restrict__ gpart, float *__restrict__ theta,
-                            float *__restrict__ m, float *__restrict__ v, float *__restrict__ grad_out,
-                            int32_t t_step, float lr) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= kNParams) return;
+// Sum of the workgroup gradients in a fixed order; Adam step when t_step > 0,
+// else the gradient is only written to grad_out.  A workgroup takes 64
+// parameters; wave w sums, in order, the w-th quarter of the partials of
+// its lane's parameter (16 loads in flight per lane), and wave 0 adds the
+// four quarter sums in order.
+__global__ __launch_bounds__(256) void k_fsai_adam(int32_t nparts, const float *__restrict__ gpart,
+                                                   float *__restrict__ theta, float *__restrict__ m,
+                                                   float *__restrict__ v, float *__restrict__ grad_out,
+                                                   int32_t t_step, float lr) {
+    __shared__ float part[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int p = blockIdx.x * 64 + lane;
+    const int pc = p < kNParams ? p : kNParams - 1;
+    const int q = (nparts + 3) / 4;
+    const int b0 = min(nparts, w * q), b1 = min(nparts, b0 + q);
     float g = 0.f;
-    for (int b = 0; b < nparts; ++b) g += gpart[(int64_t)b * kNParams + p];
+    int b = b0;
+    for (; b + 16 <= b1; b += 16) {
+        float x[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) x[k] = gpart[(int64_t)(b + k) * kNParams + pc];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) g += x[k];
+    }
+    for (; b < b1; ++b) g += gpart[(int64_t)b * kNParams + pc];
+    part[w][lane] = g;
+    __syncthreads();
+    if (w != 0 || p >= kNParams) return;
+    g = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
     if (grad_out) grad_out[p] = g;
     if (t_step <= 0) return;
-    const float b1 = 0.9f, b2 = 0.999f;
-    const float mm = b1 * m[p] + (1.f - b1) * g;
-    const float vv = b2 * v[p] + (1.f - b2) * g * g;
+    const float be1 = 0.9f, be2 = 0.999f;
+    const float mm = be1 * m[p] + (1.f - be1) * g;
+    const float vv = be2 * v[p] + (1.f - be2) * g * g;
     m[p] = mm;
     v[p] = vv;
-    const float mh = mm / (1.f - powf(b1, (float)t_step));
-    const float vh = vv / (1.f - powf(b2, (float)t_step));
+    const float mh = mm / (1.f - powf(be1, (float)t_step));
+    const float vh = vv / (1.f - powf(be2, (float)t_step));
     theta[p] -= lr * mh / (sqrtf(vh) + 1e-8f);
 }
 
@@ -679,11 +700,6 @@ __global__ void k_stencil_refresh(int32_t m, int32_t ntiles, const int32_t *__re
     }
 }
 
-__global__ void k_fill_f32(int64_t n, float *__restrict__ p, float v) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = v;
-}
-
 }  // namespace
 
 // ---- launch wrappers -------------------------------------------------------
@@ -698,11 +714,12 @@ hipError_t fsai_prepare(int32_t n, const int32_t *rp, const int32_t *ci, const d
 }
 
 hipError_t fsai_forward_outputs(int32_t ntiles, const int32_t *tiles, int64_t nrows,
-                                const uint16_t *feats, const float *theta, float *out, hipStream_t s) {
+                                const uint16_t *feats, const float *theta, float *out, float *dg_zero,
+                                hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
     const int grid = (ntiles + 3) / 4 < 1024 ? (ntiles + 3) / 4 : 1024;
     hipLaunchKernelGGL(k_fsai_forward<true>, dim3(grid), dim3(256), 0, s, ntiles, tiles, nrows, feats,
-                       theta, out, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+                       theta, out, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, dg_zero);
     return hipGetLastError();
 }
 
@@ -713,7 +730,7 @@ hipError_t fsai_forward_factor(int32_t n, const uint16_t *feats, const float *th
     if (ntiles <= 0) return hipSuccess;
     const int grid = (ntiles + 3) / 4 < 2048 ? (ntiles + 3) / 4 : 2048;
     hipLaunchKernelGGL(k_fsai_forward<false>, dim3(grid), dim3(256), 0, s, ntiles, nullptr, (int64_t)n,
-                       feats, theta, nullptr, scol, diag, gpos, tpos, gval, gtval);
+                       feats, theta, nullptr, scol, diag, gpos, tpos, gval, gtval, nullptr);
     return hipGetLastError();
 }
 
@@ -721,29 +738,23 @@ hipError_t fsai_loss(int32_t nsamp, const int32_t *samp_row, const int64_t *samp
                      const int32_t *samp_n, const float *out, const int32_t *scol, const float *sval,
                      float *dg, float coef, double *partials, hipStream_t s) {
     if (nsamp <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fsai_loss, dim3((nsamp + 255) / 256), dim3(256), 0, s, nsamp, samp_row,
+    hipLaunchKernelGGL(k_fsai_loss, dim3(fsai_loss_blocks(nsamp)), dim3(256), 0, s, nsamp, samp_row,
                        samp_base, samp_n, out, scol, sval, dg, coef, partials);
     return hipGetLastError();
 }
 
-hipError_t fsai_dout(int64_t row0, int32_t n, const float *out, const float *dg, const int32_t *scol,
-                     float *dout, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fsai_dout, dim3((n + 255) / 256), dim3(256), 0, s, row0, n, out, dg, scol, dout);
-    return hipGetLastError();
-}
-
 hipError_t fsai_backward(int32_t ntiles, const int32_t *tiles, const uint16_t *feats, const float *theta,
-                         const float *dout, float *gpart, int32_t grid, hipStream_t s) {
+                         const float *out, const float *dg, const int32_t *scol, float *gpart, int32_t grid,
+                         hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fsai_backward, dim3(grid), dim3(256), 0, s, ntiles, tiles, feats, theta, dout,
-                       gpart);
+    hipLaunchKernelGGL(k_fsai_backward, dim3(grid), dim3(256), 0, s, ntiles, tiles, feats, theta, out, dg,
+                       scol, gpart);
     return hipGetLastError();
 }
 
 hipError_t fsai_adam(int32_t nparts, const float *gpart, float *theta, float *m, float *v,
                      float *grad_out, int32_t t_step, float lr, hipStream_t s) {
-    hipLaunchKernelGGL(k_fsai_adam, dim3((kNParams + 255) / 256), dim3(256), 0, s, nparts, gpart, theta,
+    hipLaunchKernelGGL(k_fsai_adam, dim3((kNParams + 63) / 64), dim3(256), 0, s, nparts, gpart, theta,
                        m, v, grad_out, t_step, lr);
     return hipGetLastError();
 }
@@ -763,14 +774,6 @@ hipError_t stencil_refresh(int32_t m, int32_t ntiles, const int32_t *rp, const i
     const int64_t threads = (int64_t)ntiles * 64;
     hipLaunchKernelGGL(k_stencil_refresh, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, m,
                        ntiles, rp, st_off, st_mask, val, st_val);
-    return hipGetLastError();
-}
-
-hipError_t fill_f32(int64_t n, float *p, float v, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    int64_t g = (n + 255) / 256;
-    if (g > 4096) g = 4096;
-    hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)g), dim3(256), 0, s, n, p, v);
     return hipGetLastError();
 }
 
