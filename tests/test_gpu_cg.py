@@ -784,14 +784,16 @@ def _csr_from_lists(n, rows):
 
 
 @pytest.mark.parametrize("case", ["gap_65536", "gap_65537", "first_524287", "first_524288",
-                                  "first_-524288", "first_-524289", "wide_rows", "odd_rows"])
+                                  "first_-524288", "first_-524289", "eight_per_row", "wide_rows",
+                                  "odd_rows"])
 def test_gap_coded_slices_edges(cg, case):
     """Gap-coded slices at the edge of their range: a gap of 65,536 (the
     largest one coded) and of 65,537 (plain slices); a row's first column
     2^19 - 1 and -2^19 from its own index (coded) and one further (plain
-    slices); rows of 9 entries (plain slices); and an odd row count with
-    empty rows (the last pair holds one slice, empty rows start at the last
-    row).  The SpMV is bit-exact against the oracle in every case."""
+    slices); rows of 8 entries (coded) and of 9 (plain slices); and an odd
+    row count with empty rows (the last pair holds one slice, empty rows
+    start at the last row).  The SpMV is bit-exact against the oracle in
+    every case."""
     rng = np.random.default_rng(21)
     if case.startswith(("gap_", "first_")):
         kind, far = case.split("_")
@@ -807,6 +809,10 @@ def test_gap_coded_slices_edges(cg, case):
             r = 7 if far > 0 else 7 - far            # a row whose only column is r + far
             rows[r] = ([r + far], [4.0])
         expect = 7 if case in ("gap_65536", "first_524287", "first_-524288") else 3
+    elif case == "eight_per_row":
+        n = 5000        # every row at the paired tiles' full width, 8 entries
+        rows = [(sorted(rng.choice(n, 8, replace=False)), rng.uniform(-1, 1, 8)) for _ in range(n)]
+        expect = 7
     elif case == "wide_rows":
         n = 3000
         rows = [(sorted(rng.choice(n, 9, replace=False)), rng.uniform(-1, 1, 9)) for _ in range(n)]
