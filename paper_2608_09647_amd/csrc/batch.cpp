@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <cstdlib>
 #include <new>
 #include <vector>
 
@@ -33,6 +34,7 @@ struct cg_batch {
     int32_t *d_bar = nullptr, *d_err = nullptr, *d_episodes = nullptr;
     int32_t *d_wg_sys = nullptr, *d_wg_rank = nullptr, *d_team_first = nullptr, *d_team_size = nullptr;
     int64_t *d_row_off = nullptr;
+    int32_t *d_strip = nullptr;      // [nsys] line length of a strip-ordered phase A (0: row order)
     BatchOutDev *d_out = nullptr;
     int grid_cap = 0;                // workgroups the buffers are sized for
     // current team assignment
@@ -47,9 +49,29 @@ void batch_free(cg_batch *b) {
                     (void *)b->d_Q, (void *)b->d_part, (void *)b->d_bar, (void *)b->d_err,
                     (void *)b->d_episodes, (void *)b->d_wg_sys, (void *)b->d_wg_rank,
                     (void *)b->d_team_first, (void *)b->d_team_size, (void *)b->d_row_off,
-                    (void *)b->d_out})
+                    (void *)b->d_strip, (void *)b->d_out})
         (void)hipFree(p);
     delete b;
+}
+
+// Line length D of a system whose rows form lines (a grid numbered line by
+// line): D is the largest column offset |col - row|, and applies when every
+// offset is below D/4 or within D/4 of D and D >= kStripMinLine; else 0
+// (phase A in row order).  Shorter lines keep their neighbour lines in the
+// L2 in row order already.
+constexpr int32_t kStripMinLine = 128;
+
+int32_t strip_line(int32_t n, const int32_t *rp, const int32_t *ci) {
+    int64_t D = 0;
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) D = std::max<int64_t>(D, std::llabs((int64_t)ci[k] - i));
+    if (D < kStripMinLine || D > INT32_MAX / 4) return 0;
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+            const int64_t o = std::llabs((int64_t)ci[k] - i);
+            if (!(4 * o < D || 4 * o > 3 * D)) return 0;
+        }
+    return (int32_t)D;
 }
 
 int validate_sched(const cg_batch_sched *s) {
@@ -221,6 +243,7 @@ extern "C" int cg_batch_create(int32_t nsys, const int32_t *n, const int64_t *nn
     if (e == hipSuccess) e = dmalloc(&b->d_team_first, (size_t)nsys);
     if (e == hipSuccess) e = dmalloc(&b->d_team_size, (size_t)nsys);
     if (e == hipSuccess) e = dmalloc(&b->d_row_off, (size_t)nsys + 1);
+    if (e == hipSuccess) e = dmalloc(&b->d_strip, (size_t)nsys);
     if (e == hipSuccess) e = dmalloc(&b->d_out, (size_t)nsys * nrhs);
     if (e != hipSuccess) return bail(fail(CG_ENOMEM, "batch allocation failed: %s", hipGetErrorString(e)));
     e = hipMemcpy(b->d_rp, rp.data(), sizeof(int32_t) * rp.size(), hipMemcpyHostToDevice);
@@ -228,6 +251,12 @@ extern "C" int cg_batch_create(int32_t nsys, const int32_t *n, const int64_t *nn
     if (e == hipSuccess && ents) e = hipMemcpy(b->d_val, va.data(), sizeof(double) * va.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(b->d_row_off, b->row_off.data(), sizeof(int64_t) * b->row_off.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        std::vector<int32_t> strip((size_t)nsys);
+#pragma omp parallel for schedule(dynamic)
+        for (int32_t k = 0; k < nsys; ++k) strip[(size_t)k] = strip_line(n[k], row_ptr[k], col[k]);
+        e = hipMemcpy(b->d_strip, strip.data(), sizeof(int32_t) * strip.size(), hipMemcpyHostToDevice);
+    }
     if (e != hipSuccess) return bail(fail(CG_EDEVICE, "batch upload failed: %s", hipGetErrorString(e)));
     cg_batch_sched s;
     cg_batch_default_sched(&s);
@@ -306,6 +335,7 @@ extern "C" int cg_batch_solve(cg_batch *b, const double *B, double *X, double to
     a.team_first = b->d_team_first;
     a.team_size = b->d_team_size;
     a.row_off = b->d_row_off;
+    a.strip = b->d_strip;
     a.out = b->d_out;
     a.episodes = b->d_episodes;
     a.nrhs = b->nrhs;

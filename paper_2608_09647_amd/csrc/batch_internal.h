@@ -33,6 +33,7 @@ struct BatchArgs {
     const int32_t *team_first;  // [nsys] first workgroup of the team
     const int32_t *team_size;   // [nsys]
     const int64_t *row_off;     // [nsys + 1]
+    const int32_t *strip;       // [nsys] line length D of a strip-ordered phase A (0: row order)
     BatchOutDev *out;           // [nsys * nrhs]
     int32_t *episodes;          // [nsys] barriers passed (statistics)
     int32_t nrhs;

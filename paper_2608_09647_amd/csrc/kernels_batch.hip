@@ -293,6 +293,103 @@ __device__ __forceinline__ void spmv_rows_pipelined(const BatchArgs &a, int64_t 
     }
 }
 
+// Phase A in strip order, for systems whose rows form lines of D rows (a
+// grid numbered line by line; the host sets D where every column offset is
+// either below D/4 or within D/4 of D): the workgroup's rows are visited as
+// columns x in [s RS, (s+1) RS) of the lines, strip s after strip s - 1,
+// each strip walked down the workgroup's lines.  A row's neighbours in the
+// lines above and below are then used within a few steps of each other, so
+// the gathered lines of p stay in the L2 of every workgroup at once (in row
+// order each workgroup keeps two whole lines in flight, 128 KB at D = 512
+// and 16 right-hand sides, more than an XCD's L2 holds for all its
+// workgroups).  Rows are summed as in spmv_rows_pipelined, three in flight;
+// only the order of the rows in the thread's partial p^T q changes.
+template <int V>
+__device__ __forceinline__ void spmv_rows_strips(const BatchArgs &a, int64_t off, int64_t lo, int64_t hi, int D,
+                                                 int RS, int rsub, int nr, int j0, const bool (&on)[V],
+                                                 double (&acc)[V]) {
+#pragma clang fp contract(off)
+    const int64_t l0 = lo - off, l1 = hi - off;       // local rows [l0, l1)
+    if (l1 <= l0) return;
+    const int64_t y0 = l0 / D, nlines = (l1 - 1) / D - y0 + 1;
+    const int nstrips = (D + RS - 1) / RS;
+    const int64_t nsteps = nlines * nstrips;
+    // global row of step t, or -1 (a column past the line, or outside [lo, hi))
+    auto row_at = [&](int64_t t) -> int64_t {
+        if (t >= nsteps) return -1;
+        const int64_t strip = t / nlines;
+        const int64_t x = strip * RS + rsub;
+        const int64_t r = (y0 + (t - strip * nlines)) * D + x;
+        return (x < D && r >= l0 && r < l1) ? off + r : -1;
+    };
+    int64_t row = row_at(0);
+    int k0c = 0, lenc = 0;
+    if (row >= 0) {
+        k0c = a.rp[row];
+        lenc = a.rp[row + 1] - k0c;
+    }
+    int cc[kPipe];
+    double wc[kPipe];
+    row_cw(a, k0c, lenc, cc, wc);
+    int64_t rown = row_at(1);
+    int k0n = 0, k1n = 0;
+    if (rown >= 0) {
+        k0n = a.rp[rown];
+        k1n = a.rp[rown + 1];
+    }
+    for (int64_t t = 0; t < nsteps; ++t) {
+        double pv[kPipe][V], po[V];
+#pragma unroll
+        for (int e = 0; e < kPipe; ++e) ldv<V>(a.P, (int64_t)cc[e] * nr + j0, pv[e]);
+        const int64_t idx = (row >= 0 ? row : lo) * nr + j0;
+        ldv<V>(a.P, idx, po);
+        int cn[kPipe];
+        double wn[kPipe];
+        row_cw(a, k0n, k1n - k0n, cn, wn);
+        const int64_t rownn = row_at(t + 2);
+        int k0nn = 0, k1nn = 0;
+        if (rownn >= 0) {
+            k0nn = a.rp[rownn];
+            k1nn = a.rp[rownn + 1];
+        }
+        double sv[V];
+#pragma unroll
+        for (int q = 0; q < V; ++q) sv[q] = 0.0;
+        if (lenc <= kPipe) {
+#pragma unroll
+            for (int e = 0; e < kPipe; ++e)
+                if (e < lenc)
+#pragma unroll
+                    for (int q = 0; q < V; ++q) sv[q] += wc[e] * pv[e][q];
+        } else {
+            for (int k = k0c; k < k0c + lenc; ++k) {
+                double g[V];
+                ldv<V>(a.P, (int64_t)a.ci[k] * nr + j0, g);
+                const double wk = a.val[k];
+#pragma unroll
+                for (int q = 0; q < V; ++q) sv[q] += wk * g[q];
+            }
+        }
+        if (row >= 0) {
+            stv<V>(a.Q, idx, sv);
+#pragma unroll
+            for (int q = 0; q < V; ++q)
+                if (on[q]) acc[q] = fma(po[q], sv[q], acc[q]);
+        }
+        row = rown;
+        rown = rownn;
+        k0c = k0n;
+        lenc = k1n - k0n;
+#pragma unroll
+        for (int e = 0; e < kPipe; ++e) {
+            cc[e] = cn[e];
+            wc[e] = wn[e];
+        }
+        k0n = k0nn;
+        k1n = k1nn;
+    }
+}
+
 // U: rows a thread advances per step in the setup and the vector phases B
 // and C (phase A keeps three rows in flight by itself); V: right-hand sides
 // per lane (2 needs an even nrhs and 16-byte aligned vectors).
@@ -383,7 +480,13 @@ __global__ __launch_bounds__(kT) void k_batch_cg(BatchArgs a) {
             double acc[V];
 #pragma unroll
             for (int q = 0; q < V; ++q) acc[q] = 0.0;
-            if (any_on && lane_on) spmv_rows_pipelined<V>(a, lo, hi, RS, rsub, nr, j0, on, acc);
+            if (any_on && lane_on) {
+                const int D = a.strip[sys];
+                if (D > 0)
+                    spmv_rows_strips<V>(a, off, lo, hi, D, RS, rsub, nr, j0, on, acc);
+                else
+                    spmv_rows_pipelined<V>(a, lo, hi, RS, rsub, nr, j0, on, acc);
+            }
             wg_partial<V>(acc, mypart + kSlotPQ * kL, S);
         }
         if (!team_sync(a, sys, T, episode, S)) return;
