@@ -100,6 +100,47 @@ def test_batch_matches_oracle_per_pair(cg, mixed_batch, sched):
             assert np.linalg.norm(X[k][:, j] - ref["x"]) <= 2 * kap * 1e-10 * np.linalg.norm(ref["x"])
 
 
+def kappa_sparse(A):
+    """Condition number from the extreme eigenvalues (shift-invert for the
+    smallest), for systems too large for a dense eigensolver."""
+    from scipy.sparse.linalg import eigsh
+    S = A.scipy().tocsc()
+    lmax = eigsh(S, k=1, which="LA", return_eigenvectors=False)[0]
+    lmin = eigsh(S, k=1, sigma=0.0, which="LM", return_eigenvectors=False)[0]
+    return float(lmax / lmin)
+
+
+@pytest.mark.parametrize("sched", [{"blocks_per_cu": 8, "team_exponent": 1.0},
+                                   {"rhs_per_lane": 1, "blocks_per_cu": 8, "team_exponent": 1.0},
+                                   {"max_team": 1}])
+def test_strip_ordered_spmv_matches_oracle_per_pair(cg, sched):
+    """Systems whose rows form lines of at least 128 (grids 130 and 160 wide)
+    take phase A in strip order: with teams that split them mid-line, strips
+    of 32 or 16 columns (two or one right-hand sides per lane) and whole
+    systems per workgroup, every pair matches the oracle's solution, and a
+    rerun gives the same bits."""
+    systems = [field(130, 11, 40), field(160, 12, 33), I.poisson2d(20)]
+    nrhs = 4
+    xs, bs = make_batch(systems, nrhs, seed=4)
+    kappas = [kappa_sparse(A) for A in systems]
+    print(f"[strip] sched={sched} n={[A.n for A in systems]} kappa={[f'{k:.3g}' for k in kappas]}", flush=True)
+    X, res, st, code = run_batch(cg, systems, bs, nrhs, **sched)
+    X2, _, _, _ = run_batch(cg, systems, bs, nrhs, **sched)
+    print(f"[strip] stats {st}", flush=True)
+    assert code == cg.CG_OK
+    if "max_team" not in sched:
+        assert st["max_team"] > 1
+    for k, A in enumerate(systems):
+        assert np.array_equal(X[k], X2[k])
+        for j in range(nrhs):
+            ref = oracle.cg(A, bs[k][:, j], tol=1e-10, maxit=20000)
+            r = res[k, j]
+            assert ref["status"] == 0 and r["status"] == 0
+            assert abs(int(r["iterations"]) - ref["iterations"]) <= max(2, 0.05 * ref["iterations"]), (k, j)
+            assert r["rel_res_true"] <= 1.01e-10
+            assert np.linalg.norm(X[k][:, j] - ref["x"]) <= 2 * kappas[k] * 1e-10 * np.linalg.norm(ref["x"])
+
+
 def test_multi_workgroup_teams_are_used(cg):
     systems = [field(45, 5), field(8, 1)]
     xs, bs = make_batch(systems, 3, seed=2)
