@@ -136,7 +136,9 @@ typedef struct cg_opts {
                               <= 8 nonzeros and every slice fits the table,
                               else 7 where it applies, else 3 when rows have
                               <= 64 nonzeros and slicing pads by <= 25%,
-                              else 1.                                          */
+                              else 2 where every row fits a run and the
+                              block has >= 262,144 rows of mean length <= 64
+                              or >= 131,072 of mean length <= 32, else 1.     */
     int32_t spmv_colblock; /* columns per block of the column-blocked tiling
                               (spmv_kind 5); 0: 262,144 (2 MB of float64 p)     */
     double refine_delta;   /* mixed precision: a float64 refinement is made

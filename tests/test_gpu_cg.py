@@ -489,6 +489,42 @@ def test_split_spmv_matches_oracle(cg):
         assert spmv_err(A, x, y, ref) <= 1e-12
 
 
+def test_automatic_stream_tiles_for_large_irregular_matrices(cg):
+    """A matrix of irregular short rows (mean 21, longest 123: slices would
+    pad 3.6x) with n >= 131,072 takes stream tiles automatically, whose SpMV
+    is bit-exact against the oracle (rows summed in CSR order); the same law
+    at 100,000 rows keeps the vector bins (rows reduced across lanes: within
+    the rounding bar).  Fixed-work CG tracks the oracle's in both."""
+    for n, want in ((140_000, 2), (100_000, 1)):
+        A = I.random_spd_lognormal(n, 4, mean_degree=10.0, max_degree=100)
+        x = np.random.default_rng(6).uniform(-1, 1, A.n)
+        b = A.scipy() @ np.ones(A.n)
+        with cg.Solver(A) as s:
+            assert used_kind(s, A.n) == want
+            y, ref_y = host(s.spmv(dev(x))), oracle.spmv(A, x)
+            assert spmv_err(A, x, y, ref_y) <= 1e-12
+            if want == 2:
+                assert np.array_equal(y, ref_y)
+            xs, res = s.solve(dev(b), tol=0.0, maxit=15)
+        ref = oracle.cg(A, b, tol=0.0, maxit=15)
+        assert res["iterations"] == 15
+        # bar: 4x the distance between the oracle and a second correct float64
+        # CG (scipy products, BLAS dots)
+        S = A.scipy()
+        xa, r, rho = np.zeros(A.n), b.copy(), b @ b
+        pa = r.copy()
+        for _ in range(15):
+            qv = S @ pa
+            alpha = rho / (pa @ qv)
+            xa += alpha * pa
+            r -= alpha * qv
+            rho, rho_old = r @ r, rho
+            pa = r + (rho / rho_old) * pa
+        nx = np.linalg.norm(ref["x"])
+        spread = np.linalg.norm(xa - ref["x"]) / nx
+        assert np.linalg.norm(host(xs) - ref["x"]) / nx <= max(1e-13, 4 * spread), spread
+
+
 @pytest.mark.parametrize("rb,re", [(0, 1001), (37, 990), (64, 700), (1000, 1001)])
 def test_split_gap_coded_slices(cg, rb, re):
     """Gap-coded slices on a GPU block that starts inside the matrix (their
