@@ -125,8 +125,8 @@ typedef struct cg_opts {
                               7 gap-coded slices (the sliced layout of 3 with
                               each row's first column as int32 and every
                               further column as its gap to the previous one
-                              in 16 bits, read by the float64 plain and dot
-                              products; rows of at most 8 nonzeros whose
+                              in 16 bits (all SpMV modes, float64 and
+                              float32); rows of at most 8 nonzeros whose
                               consecutive columns lie at most 65,536 apart;
                               else 3).
                               Automatic picks 5 when more than half of the

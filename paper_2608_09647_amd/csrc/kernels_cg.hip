@@ -392,7 +392,10 @@ struct SliceSet {
     T v[kSliceMaxWidth];
 };
 
-template <class T>
+// GAP: the columns from the gap-coded slices (sell_lenx, sell_gap) and the
+// row length from the length byte; rows past the block (last slice) decode
+// to the block's last row, a column every lane may gather.
+template <class T, bool GAP>
 __device__ __forceinline__ void slice_load(const CsrDev &A, int t, SliceSet<T> &S) {
     const T *__restrict__ svals = sell_vals<T>(A);
     const int lane = threadIdx.x & (kWave - 1);
@@ -400,17 +403,34 @@ __device__ __forceinline__ void slice_load(const CsrDev &A, int t, SliceSet<T> &
     S.nrows = min(kWave, A.m - S.r0);
     S.off = A.sell_off[t];
     S.width = (A.sell_off[t + 1] - S.off) / kWave;
-    const int i = S.r0 + min(lane, S.nrows - 1);
-    S.len = lane < S.nrows ? A.rp[i + 1] - A.rp[i] : 0;
+    if constexpr (GAP) {
+        const uint32_t lx = A.sell_lenx[(int64_t)S.r0 + lane];
+        S.len = lane < S.nrows ? (int)(lx & 0xFu) : 0;
+        const int o = (int)(((lx >> 4) << 16) | A.sell_gap[S.off + lane]);
+        int cur = A.col_base + S.r0 + lane + ((o ^ 0x80000) - 0x80000);
+        S.c[0] = cur;
+        S.v[0] = svals[S.off + lane];
 #pragma unroll
-    for (int j = 0; j < kSliceMaxWidth; ++j) {
-        const int k = S.off + (j < S.width ? j : 0) * kWave + lane;
-        S.c[j] = A.sell_ci[k];
-        S.v[j] = svals[k];
+        for (int j = 1; j < kSliceMaxWidth; ++j) {
+            const int k = S.off + (j < S.width ? j : 0) * kWave + lane;
+            const int g = (int)A.sell_gap[k];
+            if (j < S.len) cur += g + 1;
+            S.c[j] = cur;
+            S.v[j] = svals[k];
+        }
+    } else {
+        const int i = S.r0 + min(lane, S.nrows - 1);
+        S.len = lane < S.nrows ? A.rp[i + 1] - A.rp[i] : 0;
+#pragma unroll
+        for (int j = 0; j < kSliceMaxWidth; ++j) {
+            const int k = S.off + (j < S.width ? j : 0) * kWave + lane;
+            S.c[j] = A.sell_ci[k];
+            S.v[j] = svals[k];
+        }
     }
 }
 
-template <int MODE, class T>
+template <int MODE, class T, bool GAP>
 __device__ __forceinline__ void slice_step(const CsrDev &A, const SpmvArgs<T> &a,
                                            const SliceSet<T> &S, int tn, SliceSet<T> &N,
                                            double &acc0, double &acc1) {
@@ -422,7 +442,7 @@ __device__ __forceinline__ void slice_step(const CsrDev &A, const SpmvArgs<T> &a
     T pown = T(0), bv = T(0);
     if (MODE == kSpmvDot) pown = a.p_own[myrow];
     if (MODE == kSpmvResidual) bv = a.b[myrow];
-    slice_load<T>(A, tn, N);
+    slice_load<T, GAP>(A, tn, N);
     T s = T(0);
     {
 #pragma clang fp contract(off)
@@ -467,7 +487,7 @@ __device__ __forceinline__ void slice_wide(const CsrDev &A, const SpmvArgs<T> &a
     if (lane < nrows) emit_row<MODE, T>(a, i, s, acc0, acc1);
 }
 
-template <int MODE, class T>
+template <int MODE, class T, bool GAP>
 __device__ __forceinline__ void spmv_sliced_wave(const CsrDev &A, TileWalk &walk,
                                                  const SpmvArgs<T> &a, int wide, double &acc0,
                                                  double &acc1) {
@@ -478,13 +498,13 @@ __device__ __forceinline__ void spmv_sliced_wave(const CsrDev &A, TileWalk &walk
     int t = walk.next();
     if (t < 0) return;
     SliceSet<T> S0, S1;
-    slice_load<T>(A, t, S0);
+    slice_load<T, GAP>(A, t, S0);
     for (;;) {
         const int t1 = walk.next();
-        slice_step<MODE, T>(A, a, S0, t1 >= 0 ? t1 : t, S1, acc0, acc1);
+        slice_step<MODE, T, GAP>(A, a, S0, t1 >= 0 ? t1 : t, S1, acc0, acc1);
         if (t1 < 0) break;
         const int t2 = walk.next();
-        slice_step<MODE, T>(A, a, S1, t2 >= 0 ? t2 : t1, S0, acc0, acc1);
+        slice_step<MODE, T, GAP>(A, a, S1, t2 >= 0 ? t2 : t1, S0, acc0, acc1);
         if (t2 < 0) break;
         t = t2;
     }
@@ -904,7 +924,8 @@ __device__ __forceinline__ void spmv_row_wg(const CsrDev &A, int pos, bool ident
 // -6 / -7: stencil slices, cached / nontemporal (float64 only); -8 / -9: the
 // same with two rows per lane and 16-byte accesses (plain and dot modes);
 // -10 / -11: sliced tiles with two rows per lane, cached / nontemporal
-// (float64, plain and dot modes); -12 / -13: the same with gap-coded columns.
+// (float64, plain and dot modes); -12 / -13: the same with gap-coded columns;
+// -14: sliced tiles (one row per lane) with gap-coded columns.
 template <int MODE, int TILE, class T>
 __global__ __launch_bounds__(kBlock) void k_spmv(int32_t m, const int32_t *__restrict__ rp,
                                                  const int32_t *__restrict__ ci,
@@ -960,7 +981,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int32_t m, const int32_t *__res
     const bool identity = S.identity != 0;
     TileWalk walk(TILE <= -8 && TILE >= -13 ? (S.ntiles + 1) / 2 : S.ntiles);   // slice pairs
     if constexpr (TILE == -2 || TILE == -3) {
-        spmv_sliced_wave<MODE, T>(A, walk, a, TILE == -3, acc0, acc1);
+        spmv_sliced_wave<MODE, T, false>(A, walk, a, TILE == -3, acc0, acc1);
+    } else if constexpr (TILE == -14) {
+        spmv_sliced_wave<MODE, T, true>(A, walk, a, 0, acc0, acc1);
     } else if constexpr (TILE == -4 || TILE == -5) {
         spmv_dict_wave<MODE, T, TILE == -5>(A, walk, a, acc0, acc1);
     } else if constexpr (TILE == -6 || TILE == -7) {
@@ -1676,7 +1699,7 @@ void launch_spmv_mode(const CsrDev &A, const Schedule &S, int grid, const SpmvAr
                                                  ? (wide && A.sell_len
                                                         ? (A.sell_gap ? (S.stream_nt ? -13 : -12)
                                                                       : (S.stream_nt ? -11 : -10))
-                                                        : -2)
+                                                        : (A.sell_gap ? -14 : -2))
                                                  : -3)
                   : S.kind == kTileStream ? -1
                   : (S.identity && S.nbins == 1 && S.huge_count == 0) ? S.bins[0].lanes : 0;
@@ -1714,6 +1737,7 @@ void launch_spmv_mode(const CsrDev &A, const Schedule &S, int grid, const SpmvAr
         case -11: CGMI_SPMV(-11); break;
         case -12: CGMI_SPMV(-12); break;
         case -13: CGMI_SPMV(-13); break;
+        case -14: CGMI_SPMV(-14); break;
         default: CGMI_SPMV(0); break;
     }
 #undef CGMI_SPMV
