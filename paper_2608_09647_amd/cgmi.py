@@ -114,7 +114,7 @@ def lib() -> ctypes.CDLL:
     global _LIB
     if _LIB is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+            raise RuntimeError(f"{LIB_PATH} is not built; run python -m paper_2608_09647_amd.build first")
         L = ctypes.CDLL(LIB_PATH)
         L.cg_create.argtypes = [ctypes.c_int32, ctypes.c_int64, _vp, _vp, _vp, ctypes.c_int32,
                                 ctypes.c_int32, ctypes.POINTER(_vp)]
