@@ -228,6 +228,9 @@ def main() -> int:
     ap.add_argument("--spmv-kind", type=int, default=None,
                     help="default workload: force this SpMV tiling (cg_opts.spmv_kind) instead of the "
                          "tabled one, e.g. 3 for the generic sliced CSR tiling")
+    ap.add_argument("--fuse-dir", type=int, default=0, choices=[0, 1, 2],
+                    help="cg_opts.fuse_dir: automatic (0), the direction update inside the next SpMV (1) or in "
+                         "separate kernels (2)")
     ap.add_argument("--batch-launch", default="cooperative", choices=["cooperative", "ordinary"],
                     help="launch form of the batched kernel (ordinary: for profilers that cannot "
                          "follow cooperative launches)")
@@ -274,7 +277,7 @@ def main() -> int:
         solver.set_opts(spmv_kind=args.spmv_kind)
     # HIP events around the SpMV of every SPMV_EVENT_STRIDE-th iteration of
     # the timed steps (an event pair adds a few microseconds of stream time)
-    solver.set_opts(profile=SPMV_EVENT_STRIDE)
+    solver.set_opts(profile=SPMV_EVENT_STRIDE, fuse_dir=args.fuse_dir)
     for _ in range(args.warmup):
         x.zero_()
         solver.solve(b, x, tol=0.0, maxit=args.iters)
@@ -742,7 +745,7 @@ def bench_learned(args) -> int:
         autotune.spmv_schedule(s, A, b, tune_if_missing=False)   # tabled SpMV tiling, if any
         # timed solves without per-SpMV events; the SpMV time comes from one
         # more (profiled) solve where it is needed
-        s.set_opts(profile=0, precond=precond)
+        s.set_opts(profile=0, precond=precond, fuse_dir=args.fuse_dir)
         times, setups = [], []
         res = None
         spmv_us = None
@@ -769,9 +772,11 @@ def bench_learned(args) -> int:
         out[name] = {"seconds": float(np.mean(times)) + float(np.mean(setups)),
                      "solve_seconds": float(np.mean(times)), "setup_seconds": float(np.mean(setups)),
                      "iterations": res["iterations"], "status": res["code"], "fell_back": res["fell_back"],
-                     "rel_res_true": res["rel_res_true"], "rel_err_vs_xstar": err}
+                     "rel_res_true": res["rel_res_true"], "rel_err_vs_xstar": err,
+                     "fused_dir": res["fused_dir"]}
         if spmv_us is not None:
             out[name]["spmv_us"] = spmv_us
+            out[name]["spmv_launches_timed"] = pres["n_spmv"]
         print(f"[bench] {name}: {out[name]}", file=sys.stderr, flush=True)
 
     def plain(s, k):
@@ -818,6 +823,13 @@ def bench_learned(args) -> int:
     run("untrained", untrained, 1, 0, cgmi.PC_FSAI)
     run("classic_fsai", classic, 1, 0, cgmi.PC_FSAI)
     spmv_bytes = spmv_algorithmic_bytes(A.n, A.nnz)
+    kernel = "k_spmv (dot mode), A p"
+    if out["learned"]["fused_dir"]:
+        # iteration 0's SpMV alone; every later launch also reads z, writes
+        # p_{k+1} and reads and writes x (the direction update it carries)
+        nl = max(out["learned"]["spmv_launches_timed"], 1)
+        spmv_bytes += 32 * A.n * (nl - 1) / nl
+        kernel = "k_spmv_dir (A p with the direction update, z and x)"
     t_spmv = out["learned"]["spmv_us"] * 1e-6
     achieved = spmv_bytes / t_spmv / 1e9
     line = _line("CG iters/s + SpMV GB/s (%HBM peak); time to 1e-10 residual, plain vs learned-PC",
@@ -830,7 +842,8 @@ def bench_learned(args) -> int:
                  untrained=out["untrained"], classic_fsai=out["classic_fsai"], training=train,
                  speedup_vs_plain=out["plain"]["seconds"] / out["learned"]["seconds_with_cold_setup"],
                  roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kernel,
+                           "algorithmic_bytes_per_launch": int(spmv_bytes),
                            "note": "A, G, G^T and the vectors (~200 MB) fit the 256 MB last-level "
                                    "cache, so the HBM roofline does not bound this SpMV"})
     if not args.no_cpu_baseline:

@@ -152,9 +152,26 @@ typedef struct cg_opts {
                               copies the result back before returning (both
                               calls then block).  cg_solve_noalloc takes
                               device pointers only.                             */
+    int32_t fuse_dir;      /* GPU-only float64 solves whose A sits in stencil
+                              slices (spmv_kind 6): CG_FUSE_ON runs the
+                              direction update p = r + beta p (preconditioned:
+                              z + beta p) and the x update it carries inside
+                              the next iteration's SpMV, each gathered p entry
+                              formed on the fly (Algorithm 1's steps
+                              unchanged: the same operations on the same
+                              operands, so x, r, p and every reduction are
+                              bitwise those of separate kernels; it saves a
+                              launch and a pass over p, but gathers r as well
+                              as p); CG_FUSE_OFF: separate kernels;
+                              CG_FUSE_AUTO (default): fused for
+                              preconditioned solves of at most 2,097,152 GPU
+                              rows and plain ones of at most 262,144 (where
+                              the launch and pass it saves outweigh the extra
+                              gathers), separate above.                        */
 } cg_opts;
 
 enum { CG_VECTORS_DEVICE = 0, CG_VECTORS_HOST = 1 };  /* cg_opts.vectors   */
+enum { CG_FUSE_AUTO = 0, CG_FUSE_ON = 1, CG_FUSE_OFF = 2 };  /* cg_opts.fuse_dir */
 
 /* Per-solve record.  Times in seconds.  Fields follow the per-pass record of
  * Section 4.1: solve time, iterations, convergence, residuals, CPU compute
@@ -182,6 +199,8 @@ typedef struct cg_result {
                                 2 stream tiles, 3 sliced tiles, 4 dictionary-
                                 sliced tiles, 5 column blocks, 6 stencil slices,
                                 7 gap-coded slices (0: no GPU rows)              */
+    int32_t fused_dir;       /* 1 if the direction update ran inside the SpMV
+                                (cg_opts.fuse_dir)                               */
 } cg_result;
 
 /* Create a solver for the n x n CSR matrix (host arrays, copied).  Rows

@@ -24,6 +24,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 PC_NONE, PC_FSAI = 0, 1
 EXCHANGE_WHOLE, EXCHANGE_HALO, EXCHANGE_MAPPED, EXCHANGE_MANAGED = 0, 1, 2, 3
 VECTORS_DEVICE, VECTORS_HOST = 0, 1
+FUSE_AUTO, FUSE_ON, FUSE_OFF = 0, 1, 2
 
 # Every symbol the public header declares (checked by the tests).
 EXPORTED = ["cg_create", "cg_destroy", "cg_set_stream", "cg_default_opts", "cg_set_opts",
@@ -58,7 +59,8 @@ class CgOpts(ctypes.Structure):
                 ("check_every", ctypes.c_int32), ("profile", ctypes.c_int32),
                 ("small_path", ctypes.c_int32), ("spmv_grid", ctypes.c_int32),
                 ("spmv_kind", ctypes.c_int32), ("spmv_colblock", ctypes.c_int32),
-                ("refine_delta", ctypes.c_double), ("vectors", ctypes.c_int32)]
+                ("refine_delta", ctypes.c_double), ("vectors", ctypes.c_int32),
+                ("fuse_dir", ctypes.c_int32)]
 
 
 class CgResult(ctypes.Structure):
@@ -71,7 +73,8 @@ class CgResult(ctypes.Structure):
                 ("t_spmv", ctypes.c_double), ("n_spmv", ctypes.c_int32),
                 ("rows_gpu", ctypes.c_int32), ("rows_cpu", ctypes.c_int32),
                 ("nnz_gpu", ctypes.c_int64), ("nnz_cpu", ctypes.c_int64),
-                ("fell_back", ctypes.c_int32), ("spmv_kind", ctypes.c_int32)]
+                ("fell_back", ctypes.c_int32), ("spmv_kind", ctypes.c_int32),
+                ("fused_dir", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -180,6 +180,7 @@ extern "C" void cg_default_opts(cg_opts *o) {
     o->spmv_colblock = 0;
     o->refine_delta = 0.01;
     o->vectors = CG_VECTORS_DEVICE;
+    o->fuse_dir = CG_FUSE_AUTO;
 }
 
 extern "C" const char *cg_last_error(void) { return error_message(); }
@@ -378,6 +379,8 @@ extern "C" int cg_set_opts(cg_handle *h, const cg_opts *o) {
     if (o->spmv_colblock < 0) return fail(CG_EINVAL, "spmv_colblock must be >= 0");
     if (o->vectors != CG_VECTORS_DEVICE && o->vectors != CG_VECTORS_HOST)
         return fail(CG_EINVAL, "vectors must be CG_VECTORS_DEVICE or CG_VECTORS_HOST");
+    if (o->fuse_dir < CG_FUSE_AUTO || o->fuse_dir > CG_FUSE_OFF)
+        return fail(CG_EINVAL, "fuse_dir must be CG_FUSE_AUTO, CG_FUSE_ON or CG_FUSE_OFF");
     if (h->nodev) {
         // a host-only handle without a device: host vectors, p in host memory
         if (o->vectors != CG_VECTORS_HOST || shared)
@@ -573,6 +576,71 @@ int work_state_read(cg_handle *h, const PlainWork &w) {
     return CG_OK;
 }
 
+// Plain float64 CG with the direction update fused into the SpMV (two p
+// buffers, A in stencil slices): the SpMV of iteration 0, then per
+// iteration k the r update and one launch that ends iteration k (beta, the
+// stop test, p_{k+1}, the owed x terms) and runs the SpMV of iteration k+1.
+// The polls see the state the separate kernels leave.  With P >= 1 the
+// launch carrying the SpMV of every P-th iteration is timed (event slot j:
+// the launch queued at step j of a chunk; the last slot pair: iteration 0's).
+int plain_fused_loop(cg_handle *h, const PlainWork &w, double *const pbuf[2], int32_t maxit, int P,
+                     std::vector<hipEvent_t> &ev, double &t_spmv, int &n_spmv) {
+    const int32_t n = h->n;
+    hipStream_t st = h->stream;
+    const int Gs = h->A.grid, Gv = h->vec_grid;
+    const Partials pq{w.part_pq, Gs}, rr{w.part_rr, Gv};
+    const Partials setup_rr{w.part_setup, Gs}, setup_bb{w.part_setup + Gs, Gs};
+    const int C = h->opts.check_every;
+    auto sampled = [P](int32_t it) { return P > 0 && it % P == 0; };
+    if (P) {
+        ev.resize(2 * (size_t)C + 2);
+        for (auto &e : ev)
+            if (!e) HIP_TRY(hipEventCreate(&e));
+    }
+    hipEvent_t *const ev0 = P ? &ev[2 * (size_t)C] : nullptr;
+    if (sampled(0)) HIP_TRY(hipEventRecord(ev0[0], st));
+    HIP_TRY(launch_spmv(h->A.dev(), h->A.sched, Gs, pbuf[0], w.q, pbuf[0], nullptr, nullptr, w.part_pq,
+                        setup_rr, setup_bb, w.state, kSpmvDot, 1, st));
+    if (sampled(0)) HIP_TRY(hipEventRecord(ev0[1], st));
+    bool first_pending = sampled(0);
+    int32_t k = 0;
+    bool running = true;
+    while (running) {
+        const int32_t chunk = maxit == 0 ? 0 : std::min<int32_t>(C, maxit - k);
+        for (int32_t j = 0; j < chunk; ++j) {
+            const int32_t kk = k + j;
+            HIP_TRY(launch_update_r(n, Gv, w.r, w.q, w.part_rr, pq, w.state, kk, st));
+            if (sampled(kk + 1)) HIP_TRY(hipEventRecord(ev[2 * j], st));
+            HIP_TRY(launch_spmv_dir(h->A.dev(), h->A.sched, Gs, pbuf[kk & 1], w.r, pbuf[(kk + 1) & 1], w.x,
+                                    w.q, w.part_pq, rr, no_partials(), w.state, kk, 0, st));
+            if (sampled(kk + 1)) HIP_TRY(hipEventRecord(ev[2 * j + 1], st));
+        }
+        const int32_t it0 = k;
+        k += chunk;
+        const int rc = work_state_read(h, w);
+        if (rc) return rc;
+        const DevState &s = *w.h_state;
+        running = s.done == kDoneRunning && k < maxit;
+        float ms = 0.f;
+        if (first_pending) {
+            first_pending = false;
+            if (fused_spmv_ran(s, 0)) {
+                HIP_TRY(hipEventElapsedTime(&ms, ev0[0], ev0[1]));
+                t_spmv += 1e-3 * ms;
+                ++n_spmv;
+            }
+        }
+        for (int32_t j = 0; j < chunk; ++j) {
+            const int32_t i = it0 + j + 1;
+            if (!sampled(i) || !fused_spmv_ran(s, i)) continue;
+            HIP_TRY(hipEventElapsedTime(&ms, ev[2 * j], ev[2 * j + 1]));
+            t_spmv += 1e-3 * ms;
+            ++n_spmv;
+        }
+    }
+    return CG_OK;
+}
+
 int solve_plain(cg_handle *h, const PlainWork &w, const double *b, double *x, double tol, int32_t maxit,
                 cg_result *res) {
     const int32_t n = h->n;
@@ -610,6 +678,11 @@ int solve_plain(cg_handle *h, const PlainWork &w, const double *b, double *x, do
     if (rc) return rc;
     double t_gpu = 0.0, t_spmv = 0.0;
     int n_spmv = 0;
+    // x updated every other iteration from two p buffers (not with p in
+    // shared host memory, whose one buffer the other side reads)
+    const bool two_buf = w.p2 != nullptr;
+    const bool fused = two_buf && fuse_dir_wanted(h, false) &&
+                       spmv_dir_applies(h->A.dev(), h->A.sched, h->A.grid, w.p, w.r, w.p2, w.x, w.q);
     const double t0 = now();
     {
         const int Gs = h->A.grid, Gv = h->vec_grid;
@@ -626,12 +699,10 @@ int solve_plain(cg_handle *h, const PlainWork &w, const double *b, double *x, do
             for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
         }
         auto sampled = [P](int32_t it) { return P > 0 && it % P == 0; };
-        // x updated every other iteration from two p buffers (not with p in
-        // shared host memory, whose one buffer the other side reads)
-        const bool two_buf = w.p2 != nullptr;
         double *const pbuf[2] = {w.p, w.p2};
+        if (fused) rc = plain_fused_loop(h, w, pbuf, maxit, P, ev, t_spmv, n_spmv);
         int32_t k = 0;
-        bool running = true;
+        bool running = !fused;
         while (running) {
             // iteration k = 0 also runs the initial stop test; maxit = 0 runs only that test
             const int32_t chunk = maxit == 0 ? 1 : std::min<int32_t>(C, maxit - k);
@@ -701,6 +772,7 @@ int solve_plain(cg_handle *h, const PlainWork &w, const double *b, double *x, do
         res->t_gpu = t_gpu;
         res->t_spmv = t_spmv;
         res->n_spmv = n_spmv;
+        res->fused_dir = fused;
     }
     return status;
 }

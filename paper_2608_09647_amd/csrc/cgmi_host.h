@@ -175,6 +175,19 @@ int sum_partials_host(cg_handle *h, const double *d_part, int count, int arrays,
 int gpu_true_residual(cg_handle *h, const double *b_own, const double *x_full, double *rr,
                       double *bb);
 inline Partials no_partials() { return Partials{nullptr, 0}; }
+// GPU rows up to which CG_FUSE_AUTO fuses the direction update into the
+// SpMV (measured on 5- and 7-point systems).  Preconditioned: the separate
+// update reads z, p and x and writes p and x every iteration, and the fused
+// launch was faster at 1,048,576 rows.  Plain CG (x updated every other
+// iteration): faster at 262,144 rows, where launches dominate, slower from
+// 884,736 rows on, where the extra gathers of r cost more than the pass
+// over p they save.
+constexpr int32_t kFuseDirAutoRowsPcg = 1 << 21;
+constexpr int32_t kFuseDirAutoRowsCg = 1 << 18;
+inline bool fuse_dir_wanted(const cg_handle *h, bool pcg) {
+    const int32_t lim = pcg ? kFuseDirAutoRowsPcg : kFuseDirAutoRowsCg;
+    return h->opts.fuse_dir == CG_FUSE_ON || (h->opts.fuse_dir == CG_FUSE_AUTO && h->m <= lim);
+}
 int status_of(int done);
 // Preconditioned solve (fsai.cpp); on a breakdown it returns CG_EBREAKDOWN
 // with x untouched.

@@ -39,6 +39,7 @@ struct DevState {
                        // updated (the deferred x update of iteration k runs only
                        // then; it never reads `done`, which its own workgroup 0
                        // may set while other workgroups have yet to start)
+    int32_t spmv_iter; // fused direction update: the last iteration whose SpMV ran
 };
 
 enum { kDoneRunning = 0, kDoneConverged = 1, kDoneMaxit = 2, kDoneBreakdown = 3, kDoneRefine = 4 };
@@ -177,7 +178,7 @@ struct Partials {
 // ---- launch wrappers (kernels_cg.hip) ------------------------------------
 // Every wrapper returns the hipError_t of the launch.
 
-enum { kSpmvPlain = 0, kSpmvDot = 1, kSpmvResidual = 2, kSpmvAccum = 3 };
+enum { kSpmvPlain = 0, kSpmvDot = 1, kSpmvResidual = 2, kSpmvAccum = 3, kSpmvDir = 4 };
 
 // q = A p on the block's rows.
 //   kSpmvPlain:    nothing else (with st: nothing once the solve has stopped).
@@ -272,6 +273,32 @@ hipError_t launch_update_pxb(int32_t m, int grid, double *x, const double *r, co
 hipError_t launch_update_p_pcg(int32_t m, int grid, const double *z, double *p, double *x, Partials rr,
                                Partials rz, Partials bb, DevState *st, int first, int32_t k,
                                hipStream_t s);
+
+// The direction update of iteration k fused into the SpMV of iteration k+1
+// (GPU-only handles whose A sits in stencil slices): the coefficient step of
+// launch_update_pxb (pcg = 0; d = r, p_oth holds p_{k-1}) or of
+// launch_update_p_pcg (pcg = 1; d = z, x updated every iteration), then
+// q = A p_{k+1} with p_{k+1} = d + beta p_cur formed per gathered column and
+// written to p_oth, the owed x update, and out[wg] = the p^T q partial of
+// workgroup wg.  At a stop only x is completed.  Bitwise the results of the
+// separate kernels followed by launch_spmv(kSpmvDot) on the same grid.
+// spmv_dir_applies: the tiling, grid (a multiple of 8) and 16-byte
+// alignment the kernel needs; otherwise launch_spmv_dir returns
+// hipErrorInvalidValue.
+bool spmv_dir_applies(const CsrDev &A, const Schedule &S, int grid, const void *p_cur, const void *d,
+                      const void *p_oth, const void *x, const void *q);
+
+// With the direction update fused: did the SpMV of iteration i run?
+// Iteration 0's did unless the stop test at its top ended the solve; a later
+// one's (inside the launch that ended iteration i-1) iff that launch
+// recorded it.
+inline bool fused_spmv_ran(const DevState &s, int32_t i) {
+    if (i == 0) return !(s.iter == 0 && (s.done == kDoneConverged || s.done == kDoneMaxit));
+    return i <= s.spmv_iter;
+}
+hipError_t launch_spmv_dir(const CsrDev &A, const Schedule &S, int grid, const double *p_cur, const double *d,
+                           double *p_oth, double *x, double *q, double *out, Partials rr, Partials rz,
+                           DevState *st, int32_t k, int pcg, hipStream_t s);
 
 // Whole-solve single-workgroup CG for small systems (kernels_small.hip; p
 // held in LDS): reads x0 from x and writes the solution there; leaves iter,

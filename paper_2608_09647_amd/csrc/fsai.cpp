@@ -200,6 +200,10 @@ int solve_gpu_pcg(cg_handle *h, const double *b, double *x, double tol, int32_t 
     const Partials none = no_partials();
     const Partials setup_rr{h->d_part_setup, Ga}, setup_bb{h->d_part_setup + Ga, Ga};
     const Partials pq{h->d_part_pq, Ga}, rr{h->d_part_rr, h->g_width ? Gx : Gv}, rz{h->d_part_rz, Gt};
+    if (fuse_dir_wanted(h, true) && h->g_width && !h->d_p2) {   // second p buffer of the fused direction update
+        const hipError_t e = dmalloc(&h->d_p2, (size_t)h->n + 2);
+        if (e != hipSuccess) return fail(CG_ENOMEM, "second p buffer: %s", hipGetErrorString(e));
+    }
     HIP_TRY(hipMemcpyAsync(h->d_x, x, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
     int rc = gpu_state_init(h, tol, maxit);
     if (rc) return rc;
@@ -223,6 +227,26 @@ int solve_gpu_pcg(cg_handle *h, const double *b, double *x, double tol, int32_t 
     const int P = h->opts.profile;   // events around the SpMV of every P-th iteration
     auto sampled = [P](int32_t it) { return P > 0 && it % P == 0; };
     double *const rbuf[2] = {h->d_r, h->d_r2};   // r of iterations k (even) and k (odd)
+    // direction update fused into the next SpMV (x deferred, A in stencil
+    // slices): p alternates between two buffers; the SpMV of iteration k+1
+    // runs in the launch that ends iteration k (event slot j), iteration 0's
+    // before the loop (the last slot pair)
+    double *const pbuf[2] = {h->d_p, h->d_p2};
+    const bool fused = h->g_width && h->d_p2 && fuse_dir_wanted(h, true) &&
+                       spmv_dir_applies(h->A.dev(), h->A.sched, Ga, h->d_p, h->d_z, h->d_p2, h->d_x, h->d_q);
+    if (fused && P) {
+        ev.resize(2 * (size_t)C + 2);
+        for (auto &e : ev)
+            if (!e) HIP_TRY(hipEventCreate(&e));
+    }
+    bool first_pending = false;
+    if (fused && maxit > 0) {
+        first_pending = sampled(0);
+        if (first_pending) HIP_TRY(hipEventRecord(ev[2 * (size_t)C], st));
+        HIP_TRY(launch_spmv(h->A.dev(), h->A.sched, Ga, pbuf[0], h->d_q, pbuf[0], nullptr, nullptr, h->d_part_pq,
+                            none, none, h->d_state, kSpmvDot, 0, st));
+        if (first_pending) HIP_TRY(hipEventRecord(ev[2 * (size_t)C + 1], st));
+    }
     int32_t k = 0;
     bool running = maxit > 0;
     if (!running) rc = gpu_state_read(h);
@@ -230,10 +254,12 @@ int solve_gpu_pcg(cg_handle *h, const double *b, double *x, double tol, int32_t 
         const int32_t chunk = std::min<int32_t>(C, maxit - k);
         for (int32_t j = 0; j < chunk; ++j) {
             const int32_t kk = k + j;
-            if (sampled(kk)) HIP_TRY(hipEventRecord(ev[2 * j], st));
-            HIP_TRY(launch_spmv(h->A.dev(), h->A.sched, Ga, h->d_p, h->d_q, h->d_p, nullptr, nullptr,
-                                h->d_part_pq, none, none, h->d_state, kSpmvDot, 0, st));
-            if (sampled(kk)) HIP_TRY(hipEventRecord(ev[2 * j + 1], st));
+            if (!fused) {
+                if (sampled(kk)) HIP_TRY(hipEventRecord(ev[2 * j], st));
+                HIP_TRY(launch_spmv(h->A.dev(), h->A.sched, Ga, h->d_p, h->d_q, h->d_p, nullptr, nullptr,
+                                    h->d_part_pq, none, none, h->d_state, kSpmvDot, 0, st));
+                if (sampled(kk)) HIP_TRY(hipEventRecord(ev[2 * j + 1], st));
+            }
             double *r_now = h->d_r;
             if (h->g_width) {
                 // x/r update and t = G r in one kernel; r alternates between two buffers
@@ -253,16 +279,41 @@ int solve_gpu_pcg(cg_handle *h, const double *b, double *x, double tol, int32_t 
             }
             HIP_TRY(launch_spmv(h->GT.dev(), h->GT.sched, Gt, h->d_t, h->d_z, r_now, nullptr, nullptr,
                                 h->d_part_rz, none, none, h->d_state, kSpmvDot, 0, st));
-            // x += alpha p here when the fused kernel formed r (it leaves x alone)
-            HIP_TRY(launch_update_p_pcg(n, Gv, h->d_z, h->d_p, h->g_width ? h->d_x : nullptr, rr, rz, none,
-                                        h->d_state, 0, kk, st));
+            if (fused) {
+                if (sampled(kk + 1)) HIP_TRY(hipEventRecord(ev[2 * j], st));
+                HIP_TRY(launch_spmv_dir(h->A.dev(), h->A.sched, Ga, pbuf[kk & 1], h->d_z, pbuf[(kk + 1) & 1],
+                                        h->d_x, h->d_q, h->d_part_pq, rr, rz, h->d_state, kk, 1, st));
+                if (sampled(kk + 1)) HIP_TRY(hipEventRecord(ev[2 * j + 1], st));
+            } else {
+                // x += alpha p here when the fused kernel formed r (it leaves x alone)
+                HIP_TRY(launch_update_p_pcg(n, Gv, h->d_z, h->d_p, h->g_width ? h->d_x : nullptr, rr, rz, none,
+                                            h->d_state, 0, kk, st));
+            }
         }
         const int32_t it0 = k;
         k += chunk;
         rc = gpu_state_read(h);
         if (rc) break;
         running = h->h_state->done == kDoneRunning && k < maxit;
-        if (h->opts.profile) {
+        if (fused && P) {
+            const DevState &s = *h->h_state;
+            float ms = 0.f;
+            if (first_pending) {
+                first_pending = false;
+                if (fused_spmv_ran(s, 0)) {
+                    HIP_TRY(hipEventElapsedTime(&ms, ev[2 * (size_t)C], ev[2 * (size_t)C + 1]));
+                    t_spmv += 1e-3 * ms;
+                    ++n_spmv;
+                }
+            }
+            for (int32_t j = 0; j < chunk; ++j) {
+                const int32_t i = it0 + j + 1;
+                if (!sampled(i) || !fused_spmv_ran(s, i)) continue;
+                HIP_TRY(hipEventElapsedTime(&ms, ev[2 * j], ev[2 * j + 1]));
+                t_spmv += 1e-3 * ms;
+                ++n_spmv;
+            }
+        } else if (h->opts.profile) {
             int32_t ran = h->h_state->iter - it0 + (h->h_state->done == kDoneBreakdown ? 1 : 0);
             ran = std::max(0, std::min<int32_t>(ran, chunk));
             for (int32_t j = 0; j < ran; ++j) {
@@ -310,6 +361,7 @@ int solve_gpu_pcg(cg_handle *h, const double *b, double *x, double tol, int32_t 
         res->t_gpu = t_gpu;
         res->t_spmv = t_spmv;
         res->n_spmv = n_spmv;
+        res->fused_dir = fused;
     }
     return status;
 }

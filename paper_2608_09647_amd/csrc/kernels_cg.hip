@@ -673,11 +673,52 @@ __device__ __forceinline__ void spmv_sten_wave(const CsrDev &A, TileWalk &walk,
 // Every row is summed exactly as in spmv_sten_wave; the p^T q partial adds
 // the lane's two rows in order.  Plain and dot modes, with q and p_own
 // 16-byte aligned (checked by the launcher).
+//
+// Direction mode (kSpmvDir, k_spmv_dir): a.p holds p_k and the kernel
+// multiplies by p_{k+1} = d + beta p_k (d = r, or z = M^-1 r), formed on
+// the fly for every gathered column with the fma of the separate direction
+// update (so each value is bitwise that kernel's); each lane then writes
+// p_{k+1} of its own rows to D.p_oth, applies the owed x update with the
+// same fmas as the separate kernels, and adds p_{k+1}^T q for its rows.
+// D.p_oth holds p_{k-1} on entry (read for x, own rows only, before the
+// same lane overwrites it), so no lane reads what another writes.  The
+// lane's two rows read adjacent entries at each slot (the offset is the
+// slice's), so one 16-byte gather of p and one of d bring both rows'
+// operands (this mode gathers twice as much; single 8-byte gathers made
+// it slower); where only one of the rows has the slot, the pair starts one
+// entry below that row's column (at 0 for column 0), and where neither
+// has it, one below the first row, so the loads stay inside the vectors
+// when they have at least two entries (m >= 2, checked by the launcher).
 typedef double dbl2v __attribute__((ext_vector_type(2)));
+
+// Two consecutive float64 entries from an 8-byte aligned address (one
+// 16-byte load; the hardware takes unaligned vector loads).
+__device__ __forceinline__ dbl2v load_pair(const double *p) {
+    dbl2v v;
+    __builtin_memcpy(&v, p, sizeof v);
+    return v;
+}
+
+struct DirArgs {
+    const double *d;      // r, or z = M^-1 r (gathered and own rows)
+    double *p_oth;        // own rows: p_{k-1} in, p_{k+1} out
+    double *x;            // own rows
+    double beta, alpha, alpha_prev;
+    int xmode;            // 0: x untouched; 1: x += alpha p_k; 2: x += alpha_prev p_{k-1}, then alpha p_k
+};
+
+// x of one row after iteration k (mode as DirArgs::xmode): the fmas of
+// k_update_pxb and k_update_p_pcg.
+__device__ __forceinline__ double x_owed(int xmode, double x, double alpha, double pk, double alpha_prev,
+                                         double pprev) {
+    if (xmode == 2) return fma(alpha, pk, fma(alpha_prev, pprev, x));
+    if (xmode == 1) return fma(alpha, pk, x);
+    return x;
+}
 
 template <int MODE, bool NT>
 __device__ __forceinline__ void spmv_sten2_wave(const CsrDev &A, TileWalk &walk, const SpmvArgs<double> &a,
-                                                double &acc0) {
+                                                double &acc0, const DirArgs &D) {
     const int lane = threadIdx.x & (kWave - 1);
     const int half = lane >> 5, hl = lane & 31;
     const int nt = (A.m + kWave - 1) / kWave;
@@ -714,8 +755,20 @@ __device__ __forceinline__ void spmv_sten2_wave(const CsrDev &A, TileWalk &walk,
                     const dbl2v *vp = reinterpret_cast<const dbl2v *>(&A.st_val[off + j * kWave + 2 * hl]);
                     v[j] = NT ? __builtin_nontemporal_load(vp) : *vp;
                 }
-                pa[j] = a.p[(ma >> j) & 1u ? ga + offs[j] : ga];
-                pb[j] = a.p[(mb >> j) & 1u ? gb + offs[j] : gb];
+                if (MODE == kSpmvDir) {
+                    // the lane's two rows read adjacent columns (offsets are
+                    // slice-uniform): one 16-byte gather of p and of d each
+                    const bool ha = (ma >> j) & 1u, hb = (mb >> j) & 1u;
+                    const int ca = ga + offs[j], cb = gb + offs[j];
+                    const int at = ha ? (hb ? ca : max(ca - 1, 0)) : max((hb ? cb : ga) - 1, 0);
+                    const dbl2v w = load_pair(&a.p[at]), dv = load_pair(&D.d[at]);
+                    const dbl2v pn{fma(D.beta, w.x, dv.x), fma(D.beta, w.y, dv.y)};
+                    pa[j] = at == ca ? pn.x : pn.y;
+                    pb[j] = at + 1 == cb ? pn.y : pn.x;
+                } else {
+                    pa[j] = a.p[(ma >> j) & 1u ? ga + offs[j] : ga];
+                    pb[j] = a.p[(mb >> j) & 1u ? gb + offs[j] : gb];
+                }
             }
         }
         {
@@ -726,7 +779,35 @@ __device__ __forceinline__ void spmv_sten2_wave(const CsrDev &A, TileWalk &walk,
                 if ((mb >> j) & 1u) sb = sb + v[j].y * pb[j];
             }
         }
-        if (va && vb) {
+        if (MODE == kSpmvDir && va && vb) {
+            const dbl2v pk = *reinterpret_cast<const dbl2v *>(&a.p[ra]);
+            const dbl2v dv = *reinterpret_cast<const dbl2v *>(&D.d[ra]);
+            dbl2v *po = reinterpret_cast<dbl2v *>(&D.p_oth[ra]);
+            if (D.xmode) {
+                dbl2v *xp = reinterpret_cast<dbl2v *>(&D.x[ra]);
+                const dbl2v pp = D.xmode == 2 ? *po : dbl2v{0.0, 0.0};
+                dbl2v xv = *xp;
+                xv.x = x_owed(D.xmode, xv.x, D.alpha, pk.x, D.alpha_prev, pp.x);
+                xv.y = x_owed(D.xmode, xv.y, D.alpha, pk.y, D.alpha_prev, pp.y);
+                *xp = xv;
+            }
+            const dbl2v pn{fma(D.beta, pk.x, dv.x), fma(D.beta, pk.y, dv.y)};
+            *po = pn;
+            acc0 = fma(pn.x, sa, acc0);
+            acc0 = fma(pn.y, sb, acc0);
+            dbl2v qv{sa, sb};
+            dbl2v *qp = reinterpret_cast<dbl2v *>(&a.q[ra]);
+            if (NT) __builtin_nontemporal_store(qv, qp);
+            else *qp = qv;
+        } else if (MODE == kSpmvDir && va) {   // the last row of an odd row count
+            const double pk = a.p[ra];
+            if (D.xmode)
+                D.x[ra] = x_owed(D.xmode, D.x[ra], D.alpha, pk, D.alpha_prev, D.xmode == 2 ? D.p_oth[ra] : 0.0);
+            const double pn = fma(D.beta, pk, D.d[ra]);
+            D.p_oth[ra] = pn;
+            acc0 = fma(pn, sa, acc0);
+            a.q[ra] = sa;
+        } else if (va && vb) {
             if (MODE == kSpmvDot) {
                 const dbl2v po = *reinterpret_cast<const dbl2v *>(&a.p_own[ra]);
                 acc0 = fma(po.x, sa, acc0);
@@ -990,7 +1071,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int32_t m, const int32_t *__res
         if constexpr (sizeof(T) == 8) spmv_sten_wave<MODE, TILE == -7>(A, walk, a, acc0, acc1);
     } else if constexpr (TILE == -8 || TILE == -9) {
         if constexpr (sizeof(T) == 8 && (MODE == kSpmvPlain || MODE == kSpmvDot))
-            spmv_sten2_wave<MODE, TILE == -9>(A, walk, a, acc0);
+            spmv_sten2_wave<MODE, TILE == -9>(A, walk, a, acc0, DirArgs{});
     } else if constexpr (TILE <= -10 && TILE >= -13) {
         if constexpr (sizeof(T) == 8 && (MODE == kSpmvPlain || MODE == kSpmvDot))
             spmv_sliced2_wave<MODE, TILE == -11 || TILE == -13, TILE <= -12>(A, walk, a, acc0);
@@ -1403,6 +1484,51 @@ __global__ __launch_bounds__(kBlock) void k_update_px(int32_t m, double *__restr
     }
 }
 
+// The end of plain CG's iteration k with x updated every other iteration
+// (two p buffers): r^T r of the new residual from the r update's partials,
+// beta, the stop test; workgroup 0 records iteration k+1 (and alpha_k at an
+// even k that goes on).  Shared by k_update_pxb and k_spmv_dir.
+struct CgCoef {
+    double alpha, beta, alpha_prev;
+    bool stop, odd;
+};
+
+__device__ __forceinline__ CgCoef cg_coef(const Partials &rr_in, DevState *st, int32_t k, double *sh,
+                                          double *bc) {
+    CgCoef c;
+    const double rr = reduce_partials(rr_in, sh, bc);
+    const double rho_k = st->rho[k & 1];
+    c.alpha = rho_k / st->pq;
+    c.beta = rr / rho_k;
+    c.alpha_prev = st->alpha_prev;   // written at k - 1 (used at an odd k only)
+    const bool conv = stop_test(rr, st->bb, st->tol);
+    const bool maxed = k + 1 >= st->maxit;
+    c.stop = conv || maxed;
+    c.odd = k & 1;
+    if (is_block0_thread0()) {
+        st->rho[(k + 1) & 1] = rr;
+        st->rr = rr;
+        st->iter = k + 1;
+        if (conv) st->done = kDoneConverged;
+        else if (maxed) st->done = kDoneMaxit;
+        if (!c.odd && !c.stop) st->alpha_prev = c.alpha;
+    }
+    return c;
+}
+
+// r of iteration k not updated (see k_update_px): after a breakdown in that
+// r update at an odd k, x still owes alpha_{k-1} p_{k-1} (in p_oth).  Both
+// fields were written by the previous kernel, so every workgroup reads the
+// same values.
+__device__ __forceinline__ void cg_breakdown_flush(int32_t m, double *x, const double *p_oth,
+                                                   const DevState *st, int32_t k) {
+    if ((k & 1) && st->done == kDoneBreakdown && st->iter == k) {
+        const double ap = st->alpha_prev;
+        for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += (int64_t)gridDim.x * kBlock)
+            x[i] = fma(ap, p_oth[i], x[i]);
+    }
+}
+
 // k_update_px with x updated every other iteration (two p buffers, see the
 // launcher's declaration): at an odd k the two owed terms are added with
 // the same two fmas, in the same order, as by k_update_px at k-1 and k.
@@ -1413,34 +1539,13 @@ __global__ __launch_bounds__(kBlock) void k_update_pxb(int32_t m, double *__rest
                                                        DevState *__restrict__ st, int32_t k) {
     __shared__ double sh[kWavesPerBlock];
     __shared__ double bc;
-    if (st->r_iter != k + 1) {   // r of this iteration not updated (see k_update_px)
-        // A breakdown in this iteration's r update at an odd k: x still owes
-        // alpha_{k-1} p_{k-1} (in p_oth).  Both fields were written by the
-        // previous kernel, so every workgroup reads the same values.
-        if ((k & 1) && st->done == kDoneBreakdown && st->iter == k) {
-            const double ap = st->alpha_prev;
-            for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += (int64_t)gridDim.x * kBlock)
-                x[i] = fma(ap, p_oth[i], x[i]);
-        }
+    if (st->r_iter != k + 1) {
+        cg_breakdown_flush(m, x, p_oth, st, k);
         return;
     }
-    const double rr = reduce_partials(rr_in, sh, &bc);
-    const double rho_k = st->rho[k & 1];
-    const double alpha = rho_k / st->pq;
-    const double beta = rr / rho_k;
-    const double alpha_prev = st->alpha_prev;   // written at k - 1 (odd k only)
-    const bool conv = stop_test(rr, st->bb, st->tol);
-    const bool maxed = k + 1 >= st->maxit;
-    const bool stop = conv || maxed;
-    const bool odd = k & 1;
-    if (is_block0_thread0()) {
-        st->rho[(k + 1) & 1] = rr;
-        st->rr = rr;
-        st->iter = k + 1;
-        if (conv) st->done = kDoneConverged;
-        else if (maxed) st->done = kDoneMaxit;
-        if (!odd && !stop) st->alpha_prev = alpha;
-    }
+    const CgCoef c = cg_coef(rr_in, st, k, sh, &bc);
+    const double alpha = c.alpha, beta = c.beta, alpha_prev = c.alpha_prev;
+    const bool stop = c.stop, odd = c.odd;
     const int64_t npair = m >> 1;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     double2 *x2 = reinterpret_cast<double2 *>(x);
@@ -1478,6 +1583,29 @@ __global__ __launch_bounds__(kBlock) void k_update_pxb(int32_t m, double *__rest
     }
 }
 
+// The end of preconditioned CG's iteration k from r^T r and r^T z of the new
+// residual: alpha_k, beta, a breakdown (r^T z <= 0 or not finite while
+// r != 0) and the stop test; workgroup 0 records iteration k+1.  Returns
+// whether the solve stops.  Shared by k_update_p_pcg and k_spmv_dir.
+__device__ __forceinline__ bool pcg_coef(double rr, double rz, DevState *st, int32_t k, double &alpha,
+                                         double &beta) {
+    const bool broke = (!(rz > 0.0) || !isfinite(rz)) && rr != 0.0;
+    const bool conv = stop_test(rr, st->bb, st->tol);
+    const bool maxed = k + 1 >= st->maxit;
+    const double rho_k = st->rho[k & 1];
+    beta = rz / rho_k;
+    alpha = rho_k / st->pq;
+    if (is_block0_thread0()) {
+        st->rho[(k + 1) & 1] = rz;
+        st->rr = rr;
+        st->iter = k + 1;
+        if (broke) st->done = kDoneBreakdown;
+        else if (conv) st->done = kDoneConverged;
+        else if (maxed) st->done = kDoneMaxit;
+    }
+    return broke || conv || maxed;
+}
+
 // Preconditioned CG: p = z + beta p with rho = r^T z (z = M^-1 r); the stop
 // test is on r^T r.  first: setup step (after r = b - A x and z = M^-1 r):
 // rho_0 = r^T z, ||b||^2 from bb_in, the stop test at the top of iteration 0,
@@ -1513,21 +1641,7 @@ __global__ __launch_bounds__(kBlock) void k_update_p_pcg(int32_t m, const double
         }
         if (stop0) return;
     } else {
-        const bool broke = (!(rz > 0.0) || !isfinite(rz)) && rr != 0.0;
-        const bool conv = stop_test(rr, st->bb, st->tol);
-        const bool maxed = k + 1 >= st->maxit;
-        const double rho_k = st->rho[k & 1];
-        beta = rz / rho_k;
-        alpha = rho_k / st->pq;
-        if (is_block0_thread0()) {
-            st->rho[(k + 1) & 1] = rz;
-            st->rr = rr;
-            st->iter = k + 1;
-            if (broke) st->done = kDoneBreakdown;
-            else if (conv) st->done = kDoneConverged;
-            else if (maxed) st->done = kDoneMaxit;
-        }
-        stop = broke || conv || maxed;
+        stop = pcg_coef(rr, rz, st, k, alpha, beta);
     }
     const bool upd_x = x && !first;
     if (stop && !upd_x) return;
@@ -1556,6 +1670,69 @@ __global__ __launch_bounds__(kBlock) void k_update_p_pcg(int32_t m, const double
         if (upd_x) x[m - 1] = fma(alpha, pv, x[m - 1]);
         if (!stop) p[m - 1] = fma(beta, pv, z[m - 1]);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Direction update fused into the next SpMV (stencil slices, two rows per
+// lane; plain CG with two p buffers, or preconditioned CG with its x update
+// deferred).  One launch ends iteration k as k_update_pxb (PCG:
+// k_update_p_pcg) does, with the same coefficient step, and runs the SpMV of
+// iteration k+1 on p_{k+1} = d + beta p_k formed for every gathered column:
+// q = A p_{k+1}, p_{k+1} written to the other p buffer for the lane's own
+// rows, the owed x update there, and one p^T q partial per workgroup.  When
+// iteration k ends the solve, the launch only completes x, as the separate
+// kernel's stop path does, and records no partial.  x, p, q and the
+// partials are bitwise those of the separate kernels on the same grid.
+// Workgroup 0 records iteration k+1 in spmv_iter when its SpMV runs.
+template <bool NT, bool PCG>
+__global__ __launch_bounds__(kBlock) void k_spmv_dir(int32_t m, const int32_t *__restrict__ st_off,
+                                                     const int32_t *__restrict__ st_offs,
+                                                     const uint8_t *__restrict__ st_mask,
+                                                     const double *__restrict__ st_val,
+                                                     const double *__restrict__ p_cur,
+                                                     const double *__restrict__ d, double *p_oth,
+                                                     double *__restrict__ x, double *__restrict__ q,
+                                                     double *__restrict__ out, Partials rr_in, Partials rz_in,
+                                                     DevState *__restrict__ st, int32_t k) {
+    __shared__ double sh[2 * kWavesPerBlock];
+    __shared__ double bc[2];
+    if (st->r_iter != k + 1) {
+        if constexpr (!PCG) cg_breakdown_flush(m, x, p_oth, st, k);
+        return;
+    }
+    DirArgs D{d, p_oth, x, 0.0, 0.0, 0.0, 0};
+    bool stop;
+    if constexpr (PCG) {
+        double rr, rz;
+        reduce_partials2(rr_in, rz_in, sh, bc, rr, rz);
+        stop = pcg_coef(rr, rz, st, k, D.alpha, D.beta);
+        D.xmode = 1;
+    } else {
+        const CgCoef c = cg_coef(rr_in, st, k, sh, bc);
+        D.alpha = c.alpha;
+        D.beta = c.beta;
+        D.alpha_prev = c.alpha_prev;
+        stop = c.stop;
+        D.xmode = c.odd ? 2 : (stop ? 1 : 0);
+    }
+    if (stop) {
+        for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += (int64_t)gridDim.x * kBlock)
+            x[i] = x_owed(D.xmode, x[i], D.alpha, p_cur[i], D.alpha_prev, D.xmode == 2 ? p_oth[i] : 0.0);
+        return;
+    }
+    if (is_block0_thread0()) st->spmv_iter = k + 1;
+    CsrDev A{};
+    A.m = m;
+    A.st_off = st_off;
+    A.st_offs = st_offs;
+    A.st_mask = st_mask;
+    A.st_val = st_val;
+    const SpmvArgs<double> a{p_cur, q, nullptr, nullptr, nullptr};
+    double acc0 = 0.0;
+    TileWalk walk(((m + kWave - 1) / kWave + 1) / 2);   // slice pairs
+    spmv_sten2_wave<kSpmvDir, NT>(A, walk, a, acc0, D);
+    const double s0 = block_sum<kBlock>(acc0, sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = s0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1875,6 +2052,32 @@ hipError_t launch_update_pxb(int32_t m, int grid, double *x, const double *r, co
                              double *p_oth, Partials rr, DevState *st, int32_t k, hipStream_t s) {
     if (m == 0) return hipSuccess;
     hipLaunchKernelGGL(k_update_pxb, dim3(grid), dim3(kBlock), 0, s, m, x, r, p_cur, p_oth, rr, st, k);
+    return hipGetLastError();
+}
+
+bool spmv_dir_applies(const CsrDev &A, const Schedule &S, int grid, const void *p_cur, const void *d,
+                      const void *p_oth, const void *x, const void *q) {
+    auto a16 = [](const void *v) { return ((uintptr_t)v & 15) == 0; };
+    return S.kind == kTileStencil && A.st_val && A.col_base == 0 && A.m >= 2 && S.ntiles == (A.m + kWave - 1) / kWave &&
+           grid >= 8 && (grid & 7) == 0 && a16(p_cur) && a16(d) && a16(p_oth) && a16(x) && a16(q);
+}
+
+hipError_t launch_spmv_dir(const CsrDev &A, const Schedule &S, int grid, const double *p_cur, const double *d,
+                           double *p_oth, double *x, double *q, double *out, Partials rr, Partials rz,
+                           DevState *st, int32_t k, int pcg, hipStream_t s) {
+    if (A.m == 0) return hipSuccess;
+    if (!spmv_dir_applies(A, S, grid, p_cur, d, p_oth, x, q) || !st || !out) return hipErrorInvalidValue;
+#define CGMI_SPMV_DIR(NT, PCG)                                                                        \
+    hipLaunchKernelGGL((k_spmv_dir<NT, PCG>), dim3(grid), dim3(kBlock), 0, s, A.m, A.st_off, A.st_offs,  \
+                       A.st_mask, A.st_val, p_cur, d, p_oth, x, q, out, rr, rz, st, k)
+    if (S.stream_nt) {
+        if (pcg) CGMI_SPMV_DIR(true, true);
+        else CGMI_SPMV_DIR(true, false);
+    } else {
+        if (pcg) CGMI_SPMV_DIR(false, true);
+        else CGMI_SPMV_DIR(false, false);
+    }
+#undef CGMI_SPMV_DIR
     return hipGetLastError();
 }
 

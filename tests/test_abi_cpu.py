@@ -92,9 +92,9 @@ def test_null_handle_errors(cg):
 
 
 def test_struct_sizes_match_header(cg):
-    # cg_opts: 10 x int32 + double + int32 (padded); cg_result: as laid out in include/cgmi.h
+    # cg_opts: 10 x int32 + double + 2 x int32; cg_result: as laid out in include/cgmi.h
     assert ctypes.sizeof(cg.CgOpts) == 56
-    assert ctypes.sizeof(cg.CgResult) == 128
+    assert ctypes.sizeof(cg.CgResult) == 136
 
 
 def test_product_path_does_not_reach_the_oracle():
@@ -194,3 +194,18 @@ def test_spmv_kind_range(cg):
             with pytest.raises(cg.CgError) as e:
                 s.set_opts(spmv_kind=bad)
             assert e.value.code == cg.CG_EINVAL and "spmv_kind" in str(e.value)
+
+
+def test_fuse_dir_values(cg):
+    """cg_opts.fuse_dir: automatic by default; CG_FUSE_AUTO, _ON and _OFF are
+    accepted, anything else is CG_EINVAL."""
+    from paper_2608_09647_amd import inputs as I
+    A = I.poisson2d(6)
+    with cg.Solver(A, 0, 0) as s:
+        assert s.opts.fuse_dir == cg.FUSE_AUTO
+        for v in (cg.FUSE_AUTO, cg.FUSE_ON, cg.FUSE_OFF):
+            s.set_opts(fuse_dir=v)
+        for bad in (3, -1):
+            with pytest.raises(cg.CgError) as e:
+                s.set_opts(fuse_dir=bad)
+            assert e.value.code == cg.CG_EINVAL and "fuse_dir" in str(e.value)

@@ -591,15 +591,22 @@ def test_breakdown_keeps_x_of_the_last_full_iteration(cg, case, n):
     A = I.CSR(d.size, np.arange(d.size + 1, dtype=np.int32), np.arange(d.size, dtype=np.int32), d)
     ref = oracle.cg(A, b, tol=1e-12, maxit=100)
     assert ref["status"] == cg.CG_EBREAKDOWN and ref["iterations"] == (1 if case == "odd_step" else 2)
-    with cg.Solver(A) as s:
-        s.set_opts(small_path=0)
-        x, res = s.solve(dev(b), tol=1e-12, maxit=100)
-    assert res["code"] == cg.CG_EBREAKDOWN and res["iterations"] == ref["iterations"]
+    xs = []
+    for fuse in (cg.FUSE_ON, cg.FUSE_OFF):
+        with cg.Solver(A) as s:
+            s.set_opts(small_path=0, fuse_dir=fuse, spmv_kind=6)
+            x, res = s.solve(dev(b), tol=1e-12, maxit=100)
+        assert res["code"] == cg.CG_EBREAKDOWN and res["iterations"] == ref["iterations"]
+        assert res["fused_dir"] == (fuse == cg.FUSE_ON) and res["spmv_kind"] == 6
+        xs.append(host(x))
     # alpha and beta come from dot products over n entries summed in other
     # orders (relative error within n u each); a missing owed term would
     # be off by alpha p, of the order of x itself
     u = 2.0 ** -53
-    assert np.abs(host(x) - ref["x"]).max() <= 4 * n * u * np.abs(ref["x"]).max()
+    assert np.abs(xs[0] - ref["x"]).max() <= 4 * n * u * np.abs(ref["x"]).max()
+    # the direction update inside the SpMV flushes the owed term as the
+    # separate kernel does
+    assert np.array_equal(xs[0], xs[1])
 
 
 def test_deterministic_across_solves(cg):
@@ -636,20 +643,63 @@ def test_gather_reference(cg, n, offset):
     assert torch.equal(dst, src[idx.long()])
 
 
+@pytest.mark.parametrize("fuse", [1, 2])   # cg.FUSE_ON, cg.FUSE_OFF
 @pytest.mark.parametrize("stride", [1, 7])
-def test_spmv_event_sampling(cg, stride):
+def test_spmv_event_sampling(cg, stride, fuse):
     """cg_opts.profile = P times the SpMV of iterations 0, P, 2P, ...: the
-    count follows, the mean is positive, and the iterates are unchanged."""
+    count follows, the mean is positive, and the iterates are unchanged
+    (with the direction update inside the SpMV too, where the launch that
+    ends the last iteration runs no SpMV and is not counted)."""
     p = I.poisson3d_problem(24)
     b = dev(p.b)
     with cg.Solver(p.A) as s:
-        s.set_opts(small_path=0)
+        s.set_opts(small_path=0, fuse_dir=fuse)
         x0, r0 = s.solve(b, tol=0.0, maxit=50)
         s.set_opts(profile=stride, small_path=0)
         x1, r1 = s.solve(b, tol=0.0, maxit=50)
+        # a solve that converges: only SpMVs of iterations that ran
+        s.set_opts(profile=1, small_path=0)
+        x2, r2 = s.solve(b, tol=1e-8, maxit=10_000)
+    assert r1["fused_dir"] == (fuse == cg.FUSE_ON)
     assert r0["n_spmv"] == 0 and r1["n_spmv"] == (50 + stride - 1) // stride
     assert r1["t_spmv"] > 0.0
     assert torch.equal(x0, x1)
+    assert r2["converged"] == 1 and r2["n_spmv"] == r2["iterations"]
+
+
+FUSED_CASES = {
+    "poisson3d_24": lambda: I.poisson3d_problem(24),          # n even, 216 slices
+    "poisson2d_61": lambda: I.poisson2d_problem(61, seed=3),  # n odd: a last lane with one row
+    "poisson3d_65": lambda: I.poisson3d_problem(65, seed=4),  # n odd, 4,291 slices over the whole grid
+}
+
+
+@pytest.mark.parametrize("maxit,tol,every", [(1, 0.0, 32), (2, 0.0, 1), (3, 0.0, 2), (57, 0.0, 5),
+                                             (20000, 1e-10, 32)])
+@pytest.mark.parametrize("name", list(FUSED_CASES))
+def test_fused_direction_update_is_bitwise(cg, name, maxit, tol, every):
+    """cg_opts.fuse_dir: the end of iteration k (beta, the stop test,
+    p_{k+1}, the x terms owed every other iteration) inside the SpMV of
+    iteration k+1 gives bitwise the x, iteration count and residuals of the
+    separate kernels: stops at odd and even iterations, by the iteration
+    limit and by the tolerance, with polls after every iteration, every
+    other and every 5th.  The run is the oracle's within the CG bar."""
+    p = FUSED_CASES[name]()
+    out = []
+    for fuse in (cg.FUSE_OFF, cg.FUSE_ON):
+        with cg.Solver(p.A) as s:
+            s.set_opts(small_path=0, fuse_dir=fuse, check_every=every)
+            x, r = s.solve(dev(p.b), tol=tol, maxit=maxit)
+        out.append((host(x), r))
+    (x0, r0), (x1, r1) = out
+    print(f"[fused] {name} maxit={maxit} it={r1['iterations']} kind={r1['spmv_kind']}", flush=True)
+    assert r0["fused_dir"] == 0 and r1["fused_dir"] == 1 and r1["spmv_kind"] == 6
+    assert r0["code"] == r1["code"] and r0["iterations"] == r1["iterations"]
+    assert r0["rel_res_recur"] == r1["rel_res_recur"] and r0["rel_res_true"] == r1["rel_res_true"]
+    assert np.array_equal(x0, x1)
+    if maxit <= 3:
+        ref = oracle.cg(p.A, p.b, tol=0.0, maxit=maxit)
+        assert np.linalg.norm(x1 - ref["x"]) / np.linalg.norm(ref["x"]) <= 1e-13
 
 
 def test_full_size_poisson3d_256(cg):

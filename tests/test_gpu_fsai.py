@@ -285,6 +285,25 @@ def test_pcg_learned_factor_matches_oracle_with_same_factor(cg):
     assert res["iterations"] == res2["iterations"] and np.array_equal(x, x2)
 
 
+@pytest.mark.parametrize("maxit,tol", [(1, 0.0), (2, 0.0), (7, 0.0), (20000, 1e-10)])
+def test_pcg_fused_direction_update_is_bitwise(cg, maxit, tol):
+    """cg_opts.fuse_dir with the learned factor: the end of iteration k
+    (r^T z, beta, the stop test, x += alpha p_k, p_{k+1} = z + beta p_k)
+    inside the SpMV of iteration k+1 gives bitwise the separate kernels' x,
+    iterations and residuals (odd row count; stops at odd and even
+    iterations), and SpMV event sampling counts the same launches."""
+    A = field(61, 47, 53)
+    b = I.rhs_of(A, I.uniform_vector(A.n, [53, 1]))
+    th = theta_with_biases(5)
+    x0, r0 = run_pcg(cg, A, b, theta=th, tol=tol, maxit=maxit, fuse_dir=cg.FUSE_OFF, profile=3)
+    x1, r1 = run_pcg(cg, A, b, theta=th, tol=tol, maxit=maxit, fuse_dir=cg.FUSE_ON, profile=3)
+    assert r0["fused_dir"] == 0 and r1["fused_dir"] == 1 and r1["spmv_kind"] == 6
+    assert r0["status"] == r1["status"] and r0["iterations"] == r1["iterations"]
+    assert r0["rel_res_recur"] == r1["rel_res_recur"] and r0["rel_res_true"] == r1["rel_res_true"]
+    assert np.array_equal(x0, x1)
+    assert r0["n_spmv"] == r1["n_spmv"] == (min(maxit, r1["iterations"]) + 2) // 3
+
+
 def test_pcg_breakdown_falls_back_to_plain_cg(cg):
     p = I.poisson2d_problem(24, seed=1)
     G = sp.identity(p.A.n, format="lil")
