@@ -203,9 +203,12 @@ extern "C" int cg_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const i
     h->re = row_end;
     h->m = row_end - row_begin;
     try {
-        h->h_rp.assign(row_ptr, row_ptr + n + 1);
-        h->h_ci.assign(col_idx, col_idx + nnz);
-        h->h_val.assign(val, val + nnz);
+        h->h_rp.resize((size_t)n + 1);
+        par_copy(h->h_rp.data(), row_ptr, (size_t)n + 1);
+        h->h_ci.resize((size_t)nnz);
+        par_copy(h->h_ci.data(), col_idx, (size_t)nnz);
+        h->h_val.resize((size_t)nnz);
+        par_copy(h->h_val.data(), val, (size_t)nnz);
     } catch (...) {
         delete h;
         return fail(CG_ENOMEM, "out of host memory copying the matrix");

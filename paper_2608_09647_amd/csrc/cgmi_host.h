@@ -5,7 +5,11 @@
 #include <hip/hip_runtime_api.h>
 
 #include <cstdint>
+#include <cstring>
+#include <memory>
 #include <string>
+#include <type_traits>
+#include <utility>
 #include <vector>
 
 #include "../../include/cgmi.h"
@@ -19,6 +23,41 @@ const char *error_message();
 double now();
 // Square CSR n x n with int32 indices, strictly increasing columns per row.
 int validate_csr(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *ci, const double *val);
+
+// Allocator whose value-less construct leaves trivial elements
+// uninitialised, so resize() does not write (and fault in) every page from
+// one thread; the large host arrays are then filled by parallel loops
+// (par_copy), which also first-touch their pages in parallel.
+template <class T, class A = std::allocator<T>>
+struct NoInitAlloc : A {
+    template <class U>
+    struct rebind {
+        using other = NoInitAlloc<U, typename std::allocator_traits<A>::template rebind_alloc<U>>;
+    };
+    using A::A;
+    template <class U>
+    void construct(U *p) noexcept(std::is_nothrow_default_constructible<U>::value) {
+        ::new (static_cast<void *>(p)) U;
+    }
+    template <class U, class... Args>
+    void construct(U *p, Args &&...args) {
+        std::allocator_traits<A>::construct(static_cast<A &>(*this), p, std::forward<Args>(args)...);
+    }
+};
+template <class T>
+using HostVec = std::vector<T, NoInitAlloc<T>>;
+
+// dst[0, count) = src[0, count) by host threads in contiguous chunks.
+template <class T>
+void par_copy(T *dst, const T *src, size_t count) {
+    constexpr size_t kChunk = size_t(1) << 16;
+    const int64_t nchunks = (int64_t)((count + kChunk - 1) / kChunk);
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nchunks; ++c) {
+        const size_t b = (size_t)c * kChunk, e = std::min(count, b + kChunk);
+        std::memcpy(dst + b, src + b, sizeof(T) * (e - b));
+    }
+}
 
 template <class T>
 hipError_t dmalloc(T **p, size_t count) {
@@ -41,9 +80,9 @@ struct DevMatrix {
     int32_t m = 0;
     int64_t nnz = 0;
     int32_t pad_col_base = 0;        // global index of local row 0 (sliced padding)
-    std::vector<int32_t> h_rp;       // rebased row pointers (m + 1)
-    std::vector<int32_t> h_ci;       // columns (nnz)
-    std::vector<double> h_val;       // values (nnz)
+    HostVec<int32_t> h_rp;           // rebased row pointers (m + 1)
+    HostVec<int32_t> h_ci;           // columns (nnz)
+    HostVec<double> h_val;           // values (nnz)
     int32_t *d_rp = nullptr, *d_ci = nullptr, *d_rows = nullptr;
     double *d_val = nullptr;
     int32_t *d_sell_off = nullptr, *d_sell_ci = nullptr;
@@ -108,8 +147,8 @@ struct cg_handle {
     int cus = 256;
 
     // host copy of the matrix (the host complement uses its rows)
-    std::vector<int32_t> h_rp, h_ci;
-    std::vector<double> h_val;
+    cgmi::HostVec<int32_t> h_rp, h_ci;
+    cgmi::HostVec<double> h_val;
 
     cgmi::DevMatrix A;               // the GPU row block
     int vec_grid = 0;

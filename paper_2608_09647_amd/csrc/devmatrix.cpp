@@ -596,10 +596,15 @@ int dm_upload(DevMatrix &M, int32_t m, const int32_t *rp, const int32_t *ci, con
     M.nnz = m > 0 ? (int64_t)rp[m] - base : 0;
     try {
         M.h_rp.resize((size_t)m + 1);
+#pragma omp parallel for schedule(static)
         for (int32_t i = 0; i <= m; ++i) M.h_rp[i] = m > 0 ? rp[i] - base : 0;
-        M.h_ci.assign(ci + base, ci + base + M.nnz);
-        if (val) M.h_val.assign(val + base, val + base + M.nnz);
-        else M.h_val.clear();
+        M.h_ci.resize((size_t)M.nnz);
+        par_copy(M.h_ci.data(), ci + base, (size_t)M.nnz);
+        M.h_val.clear();
+        if (val) {
+            M.h_val.resize((size_t)M.nnz);
+            par_copy(M.h_val.data(), val + base, (size_t)M.nnz);
+        }
     } catch (...) {
         return fail(CG_ENOMEM, "out of host memory");
     }

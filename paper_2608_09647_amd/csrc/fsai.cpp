@@ -132,16 +132,60 @@ void transpose(int32_t n, const int32_t *rp, const int32_t *ci, const double *va
     }
 }
 
+// G^T of G = the pattern of tril(A) without a general transpose: where A's
+// pattern is symmetric, row j of G^T holds the entries of A's row j with
+// column >= j (ascending, as A's rows are).  pos[k] = position of G's entry
+// k in it.  Returns false (T unusable) when some entry (i, j) of G has no
+// (j, i) in A, i.e. the pattern is not symmetric; the caller then
+// transposes.  Each G entry maps to a distinct position and both have the
+// same count, so the map is the transpose's.
+bool upper_transpose(const cg_handle *h, const int32_t *g_rp, const int32_t *g_ci, HostCsr &T,
+                     HostArray<int32_t> &pos) {
+    const int32_t n = h->n;
+    const int32_t *arp = h->h_rp.data(), *aci = h->h_ci.data();
+    T.rp.assign((size_t)n + 1, 0);
+#pragma omp parallel for schedule(static)
+    for (int32_t j = 0; j < n; ++j) {
+        int32_t c = 0;
+        for (int32_t k = arp[j]; k < arp[j + 1]; ++k) c += aci[k] >= j;
+        T.rp[j + 1] = c;
+    }
+    for (int32_t j = 0; j < n; ++j) T.rp[j + 1] += T.rp[j];
+    if (T.rp[n] != g_rp[n]) return false;
+    T.ci.alloc((size_t)T.rp[n]);
+    T.val.alloc(0);
+    pos.alloc((size_t)g_rp[n]);
+#pragma omp parallel for schedule(static)
+    for (int32_t j = 0; j < n; ++j) {
+        int32_t p = T.rp[j];
+        for (int32_t k = arp[j]; k < arp[j + 1]; ++k)
+            if (aci[k] >= j) T.ci[p++] = aci[k];
+    }
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t k = g_rp[i]; k < g_rp[i + 1]; ++k) {
+            const int32_t j = g_ci[k];
+            int32_t q = T.rp[j];
+            while (q < T.rp[j + 1] && T.ci[q] < i) ++q;
+            if (q < T.rp[j + 1] && T.ci[q] == i) pos[k] = q;
+            else bad = 1;
+        }
+    return !bad;
+}
+
 // Upload G and G^T (schedules chosen automatically) and the work vectors;
-// g_val null: the values are written on the device later.
+// g_val null: the values are written on the device later.  pre: G^T's
+// structure and the positions already built (then tpos is not written).
 int install_factor(cg_handle *h, const int32_t *g_rp, const int32_t *g_ci, const double *g_val,
-                   HostArray<int32_t> *tpos) {
-    HostCsr T;
+                   HostArray<int32_t> *tpos, const HostCsr *pre = nullptr) {
+    HostCsr own;
     try {
-        transpose(h->n, g_rp, g_ci, g_val, T, tpos);
+        if (!pre) transpose(h->n, g_rp, g_ci, g_val, own, tpos);
     } catch (...) {
         return fail(CG_ENOMEM, "out of host memory");
     }
+    const HostCsr &T = pre ? *pre : own;
     h->have_factor = false;
     int rc = dm_upload(h->G, h->n, g_rp, g_ci, g_val, 0);
     if (!rc) rc = dm_schedule(h->G, 0, 0, h->cus, h->grid_cap, false);
@@ -535,7 +579,15 @@ int build_learned_structure(cg_handle *h) {
     } catch (...) {
         return fail(CG_ENOMEM, "out of host memory");
     }
-    int rc = install_factor(h, g_rp.data(), g_ci.data(), nullptr, &tpos);   // values come from the device
+    // G^T from A's upper triangle where A's pattern is symmetric, else by transposing G
+    HostCsr T;
+    bool direct = false;
+    try {
+        direct = upper_transpose(h, g_rp.data(), g_ci.data(), T, tpos);
+    } catch (...) {
+        return fail(CG_ENOMEM, "out of host memory");
+    }
+    int rc = install_factor(h, g_rp.data(), g_ci.data(), nullptr, &tpos, direct ? &T : nullptr);   // values come from the device
     if (rc) return rc;
     FsaiSetup *f = new (std::nothrow) FsaiSetup();
     if (!f) return fail(CG_ENOMEM, "out of host memory");

@@ -195,6 +195,36 @@ def test_learned_factor_matches_oracle(cg):
     assert err <= 2e-3
 
 
+def test_learned_factor_on_an_unsymmetric_pattern(cg):
+    """G^T's structure comes from A's upper triangle only where A's pattern
+    is symmetric.  With one entry above the diagonal missing (its mirror
+    kept), the setup transposes G instead: the factor is still on tril(A),
+    and fixed PCG steps equal those with the same factor installed from the
+    host (whose G^T is always transposed); with the pattern symmetric again
+    the same holds on the direct path."""
+    A = field(40, 36, 54)
+    M = A.scipy().tolil()
+    M[100, 101] = 0.0
+    M = M.tocsr()
+    M.eliminate_zeros()
+    M.sort_indices()
+    A2 = I.CSR(M.shape[0], M.indptr.astype(np.int32), M.indices.astype(np.int32), M.data.astype(np.float64))
+    b = I.rhs_of(A, I.uniform_vector(A.n, [54, 1]))
+    th = theta_with_biases(6)
+    for Am in (A2, A):
+        with cg.Solver(Am) as s:
+            s.fsai_setup(th)
+            rp, ci, va = s.read_factor()
+        L = sp.tril(Am.scipy()).tocsr()
+        L.sort_indices()
+        assert np.array_equal(rp, L.indptr) and np.array_equal(ci, L.indices)
+        G = sp.csr_matrix((va, ci, rp), shape=(Am.n, Am.n))
+        x1, r1 = run_pcg(cg, Am, b, theta=th, tol=0.0, maxit=40)
+        x2, r2 = run_pcg(cg, Am, b, G=as_csr(G), tol=0.0, maxit=40)
+        assert r1["iterations"] == r2["iterations"] and r1["fell_back"] == r2["fell_back"]
+        assert np.array_equal(x1, x2)
+
+
 def run_pcg(cg, A, b, G=None, theta=None, tol=1e-10, maxit=20000, x0=None, **opts):
     with cg.Solver(A) as s:
         if G is not None:
