@@ -674,6 +674,26 @@ FUSED_CASES = {
 }
 
 
+@pytest.mark.parametrize("n", [2, 3, 65, 130, 191])
+def test_fused_direction_update_tiny_chains(cg, n):
+    """The fused direction update on chains of 2 to 191 rows (one slice, a
+    slice pair with one slice, odd tails): bitwise the separate kernels, and
+    the solution within the CG bar of a dense solve."""
+    A = I.poisson2d(n, 1)
+    b = np.random.default_rng(n).uniform(-1, 1, n)
+    out = []
+    for fuse in (cg.FUSE_OFF, cg.FUSE_ON):
+        with cg.Solver(A) as s:
+            s.set_opts(small_path=0, fuse_dir=fuse, spmv_kind=6)
+            x, r = s.solve(dev(b), tol=1e-12, maxit=1000)
+        out.append((host(x), r))
+    (x0, r0), (x1, r1) = out
+    assert r1["fused_dir"] == 1 and r0["fused_dir"] == 0 and r1["spmv_kind"] == 6
+    assert r0["iterations"] == r1["iterations"] and np.array_equal(x0, x1)
+    xd = np.linalg.solve(A.scipy().toarray(), b)
+    assert np.linalg.norm(x1 - xd) <= 2 * 2.0 * 1e-12 * np.linalg.norm(xd) * 3   # kappa(A) < 3
+
+
 @pytest.mark.parametrize("maxit,tol,every", [(1, 0.0, 32), (2, 0.0, 1), (3, 0.0, 2), (57, 0.0, 5),
                                              (20000, 1e-10, 32)])
 @pytest.mark.parametrize("name", list(FUSED_CASES))
