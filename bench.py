@@ -832,6 +832,7 @@ def bench_learned(args) -> int:
         kernel = "k_spmv_dir (A p with the direction update, z and x)"
     t_spmv = out["learned"]["spmv_us"] * 1e-6
     achieved = spmv_bytes / t_spmv / 1e9
+    traffic = measured_traffic("pcg_learned_diffusion_1024", 6) if out["learned"]["fused_dir"] else None
     line = _line("CG iters/s + SpMV GB/s (%HBM peak); time to 1e-10 residual, plain vs learned-PC",
                  out["learned"]["seconds_with_cold_setup"], "s", args,
                  1e3 * out["learned"]["seconds_with_cold_setup"],
@@ -842,10 +843,13 @@ def bench_learned(args) -> int:
                  untrained=out["untrained"], classic_fsai=out["classic_fsai"], training=train,
                  speedup_vs_plain=out["plain"]["seconds"] / out["learned"]["seconds_with_cold_setup"],
                  roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kernel,
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
                            "algorithmic_bytes_per_launch": int(spmv_bytes),
+                           **({"achieved_measured_bytes": traffic / t_spmv / 1e9,
+                               "frac_measured_bytes": traffic / t_spmv / 1e9 / HBM_PEAK_GBS} if traffic else {}),
                            "note": "A, G, G^T and the vectors (~200 MB) fit the 256 MB last-level "
-                                   "cache, so the HBM roofline does not bound this SpMV"})
+                                   "cache, so the HBM roofline does not bound this SpMV; traffic counts "
+                                   "the bytes fetched and written past the L2, from that cache or HBM"})
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_pcg(prob, theta, out["learned"]["iterations"])
     print(json.dumps(line), flush=True)
