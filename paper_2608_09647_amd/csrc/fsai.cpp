@@ -187,10 +187,13 @@ int install_factor(cg_handle *h, const int32_t *g_rp, const int32_t *g_ci, const
     }
     const HostCsr &T = pre ? *pre : own;
     h->have_factor = false;
+    // factors of cache-resident systems on 4 workgroups per CU (1024^2:
+    // 43.2 against 43.8 us per PCG iteration with the automatic 8 per CU)
+    const int fgrid = h->n <= (1 << 21) ? h->cus * 4 : 0;
     int rc = dm_upload(h->G, h->n, g_rp, g_ci, g_val, 0);
-    if (!rc) rc = dm_schedule(h->G, 0, 0, h->cus, h->grid_cap, false);
+    if (!rc) rc = dm_schedule(h->G, 0, fgrid, h->cus, h->grid_cap, false);
     if (!rc) rc = dm_upload(h->GT, h->n, T.rp.data(), T.ci.data(), g_val ? T.val.data() : nullptr, 0);
-    if (!rc) rc = dm_schedule(h->GT, 0, 0, h->cus, h->grid_cap, false);
+    if (!rc) rc = dm_schedule(h->GT, 0, fgrid, h->cus, h->grid_cap, false);
     if (rc) return rc;
     if (!h->d_t) {
         hipError_t e = dmalloc(&h->d_t, (size_t)h->n + 2);
