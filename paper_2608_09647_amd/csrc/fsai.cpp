@@ -689,7 +689,8 @@ struct cg_fsai_trainer {
     float *d_sval = nullptr;
     double *d_diag = nullptr;
     uint16_t *d_feats = nullptr;
-    float *d_out = nullptr, *d_dg = nullptr;
+    float *d_out = nullptr;
+    int64_t *d_dg = nullptr;     // dL/dG~ in 64-bit fixed point (rows x 3)
     float *d_theta = nullptr, *d_m = nullptr, *d_v = nullptr, *d_theta_eval = nullptr, *d_grad = nullptr;
     float *d_gpart = nullptr;
     double *d_lpart = nullptr;

@@ -48,7 +48,7 @@ hipError_t fsai_prepare(int32_t n, const int32_t *rp, const int32_t *ci, const d
 // tiles (tiles[t] = first row; rows >= nrows are skipped); dg_zero[row][3]
 // of the same rows is set to 0.
 hipError_t fsai_forward_outputs(int32_t ntiles, const int32_t *tiles, int64_t nrows,
-                                const uint16_t *feats, const float *theta, float *out, float *dg_zero,
+                                const uint16_t *feats, const float *theta, float *out, int64_t *dg_zero,
                                 hipStream_t s);
 
 // Inference for all n rows: G values into gval (CSR of tril(A); gpos[i][3]
@@ -58,7 +58,8 @@ hipError_t fsai_forward_factor(int32_t n, const uint16_t *feats, const float *th
                                const int32_t *scol, const double *diag, const int32_t *gpos,
                                const int32_t *tpos, double *gval, double *gtval, hipStream_t s);
 
-// Loss terms and dL/dG~ (dg[row][3]: C, W, S; accumulated with atomics) of
+// Loss terms and dL/dG~ (dg[row][3]: C, W, S; 64-bit fixed point in units of
+// 2^-40, accumulated with integer atomics, so the sums are reproducible) of
 // the sampled rows, one wavefront per sample; partials[block] = sum of
 // squared entries of E, fsai_loss_blocks(nsamp) of them.
 inline int32_t fsai_loss_blocks(int32_t nsamp) {
@@ -67,12 +68,12 @@ inline int32_t fsai_loss_blocks(int32_t nsamp) {
 }
 hipError_t fsai_loss(int32_t nsamp, const int32_t *samp_row, const int64_t *samp_base,
                      const int32_t *samp_n, const float *out, const int32_t *scol, const float *sval,
-                     float *dg, float coef, double *partials, hipStream_t s);
+                     int64_t *dg, float coef, double *partials, hipStream_t s);
 
 // Parameter gradient of the listed 16-row tiles: gpart[block][kNParams].
 // dL/do of a row is formed from dL/dG~ (dg), the outputs and the slot table.
 hipError_t fsai_backward(int32_t ntiles, const int32_t *tiles, const uint16_t *feats, const float *theta,
-                         const float *out, const float *dg, const int32_t *scol, float *gpart, int32_t grid,
+                         const float *out, const int64_t *dg, const int32_t *scol, float *gpart, int32_t grid,
                          hipStream_t s);
 
 // Sum of nparts gradient partials (in order) into grad_out (may be null);

@@ -257,7 +257,7 @@ __global__ __launch_bounds__(256) void k_fsai_forward(int32_t ntiles, const int3
                                                       const int32_t *__restrict__ tpos,
                                                       double *__restrict__ gval,
                                                       double *__restrict__ gtval,
-                                                      float *__restrict__ dg_zero) {
+                                                      int64_t *__restrict__ dg_zero) {
     __shared__ ParamLds P;
     stage_params(th, P);
     Frags W;
@@ -280,7 +280,7 @@ __global__ __launch_bounds__(256) void k_fsai_forward(int32_t ntiles, const int3
                 *reinterpret_cast<float4 *>(out + row * kOutPad + 4 * q) =
                     make_float4(Y.o[0], Y.o[1], Y.o[2], Y.o[3]);
             else if (q == 2)
-                for (int b = 0; b < 3; ++b) dg_zero[row * 3 + b] = 0.f;
+                for (int b = 0; b < 3; ++b) dg_zero[row * 3 + b] = 0;
         } else if (q == 0) {
             // lanes 0..15 hold o_C, o_W, o_E, o_S of their row
             const double oc = Y.o[0], ow = Y.o[1], os = Y.o[3];
@@ -303,7 +303,15 @@ __global__ __launch_bounds__(256) void k_fsai_forward(int32_t ntiles, const int3
 // ---------------------------------------------------------------------------
 // Loss and dL/dG~ on sampled rows, one wavefront per sample.  G~ of a row is
 // read from the network outputs; A_hat from the slot tables.  dG~
-// accumulates with float atomics (order-dependent rounding only).
+// accumulates in 64-bit fixed point (each float term rounded to a multiple
+// of 2^-40, then integer atomics): the sum does not depend on the order the
+// atomics land in, so training is reproducible run to run.
+constexpr double kDgScale = 1099511627776.0;   // 2^40
+
+__device__ __forceinline__ void dg_add(int64_t *p, float x) {
+    atomicAdd(reinterpret_cast<unsigned long long *>(p),
+              (unsigned long long)__double2ll_rn((double)x * kDgScale));
+}
 struct GRow {
     int col[3];      // C, W, S columns (-1 absent)
     float val[3];
@@ -350,7 +358,7 @@ __global__ __launch_bounds__(256) void k_fsai_loss(int32_t nsamp, const int32_t 
                                                    const float *__restrict__ out,
                                                    const int32_t *__restrict__ scol,
                                                    const float *__restrict__ sval,
-                                                   float *__restrict__ dg, float coef,
+                                                   int64_t *__restrict__ dg, float coef,
                                                    double *__restrict__ partials) {
     __shared__ double sh[4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -411,7 +419,7 @@ __global__ __launch_bounds__(256) void k_fsai_loss(int32_t nsamp, const int32_t 
             loss += (double)e * (double)e;
 #pragma unroll
             for (int b = 0; b < 3; ++b)
-                if (gj.col[b] >= 0) atomicAdd(&dg[(base + j) * 3 + b], coef * e * ub[b]);
+                if (gj.col[b] >= 0) dg_add(&dg[(base + j) * 3 + b], coef * e * ub[b]);
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
                 const int cb = gi.col[b];
@@ -433,7 +441,7 @@ __global__ __launch_bounds__(256) void k_fsai_loss(int32_t nsamp, const int32_t 
         if (lane == 0)
 #pragma unroll
             for (int b = 0; b < 3; ++b)
-                if (gi.col[b] >= 0) atomicAdd(&dg[(base + i) * 3 + b], gacc[b]);
+                if (gi.col[b] >= 0) dg_add(&dg[(base + i) * 3 + b], gacc[b]);
     }
     // per-block loss partial
     double v = loss;
@@ -466,7 +474,7 @@ __global__ __launch_bounds__(256) void k_fsai_backward(int32_t ntiles, const int
                                                        const uint16_t *__restrict__ feats,
                                                        const float *__restrict__ th,
                                                        const float *__restrict__ out,
-                                                       const float *__restrict__ dg,
+                                                       const int64_t *__restrict__ dg,
                                                        const int32_t *__restrict__ scol,
                                                        float *__restrict__ gpart) {
     __shared__ WaveLds L[4];
@@ -530,8 +538,11 @@ __global__ __launch_bounds__(256) void k_fsai_backward(int32_t ntiles, const int
         bf16x4 d3;
         const float oc = out[row * kOutPad];
         const float sig = 1.f / (1.f + expf(-oc));
-        const float dv[4] = {dg[row * 3 + 0] * sig, scol[row * kSlots + kSlotW] >= 0 ? dg[row * 3 + 1] : 0.f,
-                             0.f, scol[row * kSlots + kSlotS] >= 0 ? dg[row * 3 + 2] : 0.f};
+        float dgr[3];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) dgr[b] = (float)((double)dg[row * 3 + b] * (1.0 / kDgScale));
+        const float dv[4] = {dgr[0] * sig, scol[row * kSlots + kSlotW] >= 0 ? dgr[1] : 0.f,
+                             0.f, scol[row * kSlots + kSlotS] >= 0 ? dgr[2] : 0.f};
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int o = 4 * q + v;
@@ -714,7 +725,7 @@ hipError_t fsai_prepare(int32_t n, const int32_t *rp, const int32_t *ci, const d
 }
 
 hipError_t fsai_forward_outputs(int32_t ntiles, const int32_t *tiles, int64_t nrows,
-                                const uint16_t *feats, const float *theta, float *out, float *dg_zero,
+                                const uint16_t *feats, const float *theta, float *out, int64_t *dg_zero,
                                 hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
     const int grid = (ntiles + 3) / 4 < 1024 ? (ntiles + 3) / 4 : 1024;
@@ -736,7 +747,7 @@ hipError_t fsai_forward_factor(int32_t n, const uint16_t *feats, const float *th
 
 hipError_t fsai_loss(int32_t nsamp, const int32_t *samp_row, const int64_t *samp_base,
                      const int32_t *samp_n, const float *out, const int32_t *scol, const float *sval,
-                     float *dg, float coef, double *partials, hipStream_t s) {
+                     int64_t *dg, float coef, double *partials, hipStream_t s) {
     if (nsamp <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fsai_loss, dim3(fsai_loss_blocks(nsamp)), dim3(256), 0, s, nsamp, samp_row,
                        samp_base, samp_n, out, scol, sval, dg, coef, partials);
@@ -744,7 +755,7 @@ hipError_t fsai_loss(int32_t nsamp, const int32_t *samp_row, const int64_t *samp
 }
 
 hipError_t fsai_backward(int32_t ntiles, const int32_t *tiles, const uint16_t *feats, const float *theta,
-                         const float *out, const float *dg, const int32_t *scol, float *gpart, int32_t grid,
+                         const float *out, const int64_t *dg, const int32_t *scol, float *gpart, int32_t grid,
                          hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fsai_backward, dim3(grid), dim3(256), 0, s, ntiles, tiles, feats, theta, out, dg,

@@ -406,6 +406,24 @@ def test_training_reduces_loss_and_beats_plain_cg(cg):
     assert res["rel_res_true"] <= 1.01e-10
 
 
+def test_training_is_reproducible(cg):
+    """dL/dG~ is summed in fixed point, so the order in which the loss
+    kernel's atomics land does not change it: two trainers with the same
+    initial parameters and samples end bit for bit alike (losses included),
+    and the fixed-point gradient stays within the float bar of the oracle's
+    (the loss/gradient parity tests above)."""
+    from paper_2608_09647_amd import fsai
+    systems = fsai.training_systems(12, nx=32, first=0)
+    runs = []
+    for _ in range(2):
+        tr = cg.FsaiTrainer(systems, fsai.init_params(0))
+        hist = fsai.train(tr, steps=60, nsel=4, rows_per=256, lr=3e-3, seed=1)
+        runs.append((tr.params(), np.asarray(hist["losses"])))
+        tr.close()
+    assert np.array_equal(runs[0][0], runs[1][0])
+    assert np.array_equal(runs[0][1], runs[1][1])
+
+
 # ----------------------------------------------------------------------------- classic FSAI
 
 CLASSIC_CASES = {
