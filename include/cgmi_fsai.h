@@ -99,9 +99,9 @@ int cg_fsai_get_params(const cg_fsai_trainer *t, float *theta);
  * host) and the number of Adam steps taken (the next step is step + 1).
  * Any of the arrays may be NULL (not read / not written).  set: step >= 0.
  * A trainer restored from a checkpoint continues as the one that wrote it
- * (the next step uses step + 1 in the bias correction); its loss gradients
- * are summed with float32 atomics, so two runs over the same samples agree
- * to rounding, not bit for bit. */
+ * (the next step uses step + 1 in the bias correction); the loss gradients
+ * are summed in 64-bit fixed point (order-independent), so a resumed run and
+ * an uninterrupted one over the same samples agree bit for bit. */
 int cg_fsai_get_state(const cg_fsai_trainer *t, float *theta, float *m, float *v, int32_t *step);
 int cg_fsai_set_state(cg_fsai_trainer *t, const float *theta, const float *m, const float *v, int32_t step);
 

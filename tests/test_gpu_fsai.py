@@ -493,8 +493,8 @@ def test_checkpoint_round_trip_and_resume(cg, tmp_path):
     """A checkpoint (theta, Adam m and v, step, seed in an .npz) restores the
     optimiser state bit for bit into a fresh trainer; training 3 steps,
     checkpointing, restoring and training 3 more follows the run of 6 steps
-    straight (same samples and learning rates; the loss gradient's float32
-    atomic sums round independently in each run)."""
+    straight bit for bit (same samples and learning rates; the loss gradient
+    is summed in fixed point, independent of the order of its atomics)."""
     from paper_2608_09647_amd import fsai
     systems = [field(32, 32, 50 + k) for k in range(4)]
     th = fsai.init_params(4)
@@ -520,8 +520,6 @@ def test_checkpoint_round_trip_and_resume(cg, tmp_path):
     got = tr.state()
     tr.close()
     assert got["step"] == ref["step"] == 6
-    np.testing.assert_allclose(first["losses"] + rest["losses"], full["losses"], rtol=1e-5)
-    d = np.abs(got["theta"].astype(np.float64) - ref["theta"])
-    print(f"[ckpt] resumed vs straight: max |d theta| {d.max():.3e}, 99.9% {np.quantile(d, 0.999):.3e}",
-          flush=True)
-    assert np.quantile(d, 0.999) <= 0.05 * kw["lr"] and d.max() <= 6 * 2 * kw["lr"]
+    assert first["losses"] + rest["losses"] == full["losses"]
+    for k in ("theta", "m", "v"):
+        assert np.array_equal(got[k], ref[k]), k
