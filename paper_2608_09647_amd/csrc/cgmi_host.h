@@ -4,6 +4,8 @@
 #pragma once
 #include <hip/hip_runtime_api.h>
 
+#include <omp.h>
+
 #include <cstdint>
 #include <cstring>
 #include <memory>
@@ -56,6 +58,38 @@ void par_copy(T *dst, const T *src, size_t count) {
     for (int64_t c = 0; c < nchunks; ++c) {
         const size_t b = (size_t)c * kChunk, e = std::min(count, b + kChunk);
         std::memcpy(dst + b, src + b, sizeof(T) * (e - b));
+    }
+}
+
+// a[i] += a[i - 1] for i = 1 .. n (a has n + 1 entries): a running sum by
+// host threads over contiguous blocks, then each block shifted by the sum
+// of the blocks before it.  Integer sums, so the result is the serial one.
+template <class T>
+void par_running_sum(T *a, int64_t n) {
+    const int nt = omp_get_max_threads();
+    if (n < (int64_t(1) << 16) || nt < 2) {
+        for (int64_t i = 0; i < n; ++i) a[i + 1] += a[i];
+        return;
+    }
+    std::vector<T> blk((size_t)nt + 1, T(0));
+#pragma omp parallel num_threads(nt)
+    {
+        const int t = omp_get_thread_num(), nth = omp_get_num_threads();
+        const int64_t lo = 1 + n * t / nth, hi = 1 + n * (t + 1) / nth;
+        T s = T(0);
+        for (int64_t i = lo; i < hi; ++i) {
+            s += a[i];
+            a[i] = s;
+        }
+        blk[(size_t)t + 1] = s;
+#pragma omp barrier
+#pragma omp single
+        {
+            blk[0] = a[0];
+            for (int u = 0; u < nth; ++u) blk[(size_t)u + 1] += blk[(size_t)u];
+        }
+        const T off = blk[(size_t)t];
+        for (int64_t i = lo; i < hi; ++i) a[i] += off;
     }
 }
 

@@ -65,7 +65,7 @@ struct HostArray {
 };
 
 struct HostCsr {
-    std::vector<int32_t> rp;
+    HostVec<int32_t> rp;
     HostArray<int32_t> ci;
     HostArray<double> val;
 };
@@ -78,7 +78,9 @@ struct HostCsr {
 void transpose(int32_t n, const int32_t *rp, const int32_t *ci, const double *val, HostCsr &T,
                HostArray<int32_t> *pos) {
     const int64_t nnz = rp[n];
-    T.rp.assign((size_t)n + 1, 0);
+    T.rp.resize((size_t)n + 1);
+#pragma omp parallel for schedule(static)
+    for (int32_t j = 0; j <= n; ++j) T.rp[j] = 0;
     T.ci.alloc((size_t)nnz);
     T.val.alloc(val ? (size_t)nnz : 0);
     if (pos) pos->alloc((size_t)nnz);
@@ -88,7 +90,7 @@ void transpose(int32_t n, const int32_t *rp, const int32_t *ci, const double *va
     int32_t *cnt = T.rp.data();
 #pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < nnz; ++k) __atomic_fetch_add(&cnt[ci[k] + 1], 1, __ATOMIC_RELAXED);
-    for (int32_t j = 0; j < n; ++j) T.rp[j + 1] += T.rp[j];
+    par_running_sum(T.rp.data(), n);
 #pragma omp parallel for schedule(static)
     for (int32_t j = 0; j < n; ++j) next[j] = T.rp[j];
 #pragma omp parallel for schedule(static)
@@ -143,14 +145,15 @@ bool upper_transpose(const cg_handle *h, const int32_t *g_rp, const int32_t *g_c
                      HostArray<int32_t> &pos) {
     const int32_t n = h->n;
     const int32_t *arp = h->h_rp.data(), *aci = h->h_ci.data();
-    T.rp.assign((size_t)n + 1, 0);
+    T.rp.resize((size_t)n + 1);
+    T.rp[0] = 0;   // the counts below write every other entry
 #pragma omp parallel for schedule(static)
     for (int32_t j = 0; j < n; ++j) {
         int32_t c = 0;
         for (int32_t k = arp[j]; k < arp[j + 1]; ++k) c += aci[k] >= j;
         T.rp[j + 1] = c;
     }
-    for (int32_t j = 0; j < n; ++j) T.rp[j + 1] += T.rp[j];
+    par_running_sum(T.rp.data(), n);
     if (T.rp[n] != g_rp[n]) return false;
     T.ci.alloc((size_t)T.rp[n]);
     T.val.alloc(0);
@@ -471,7 +474,7 @@ extern "C" int cg_fsai_classic(cg_handle *h) {
         if (bad_kind == 1) return fail(CG_EINVAL, "row %d has no diagonal entry", bad_row);
         if (bad_kind == 2)
             return fail(CG_EINVAL, "row %d of tril(A) has more than %d entries", bad_row, kMax);
-        for (int32_t i = 0; i < n; ++i) g_rp[i + 1] += g_rp[i];
+        par_running_sum(g_rp.data(), n);
         g_ci.resize((size_t)g_rp[n]);
         g_val.resize((size_t)g_rp[n]);
         bad_row = INT32_MAX;
@@ -532,10 +535,11 @@ namespace {
 // positions of each row's C, W, S entries.
 int build_learned_structure(cg_handle *h) {
     const int32_t n = h->n;
-    std::vector<int32_t> g_rp;
+    HostVec<int32_t> g_rp;
     HostArray<int32_t> g_ci, gpos, tpos;
     try {
-        g_rp.assign((size_t)n + 1, 0);
+        g_rp.resize((size_t)n + 1);
+        g_rp[0] = 0;   // pass 1 writes every other entry
         gpos.alloc((size_t)n * 3);
         // pass 1 (rows in parallel): check the stencil, count tril entries;
         // the first offending row is reported
@@ -564,7 +568,7 @@ int build_learned_structure(cg_handle *h) {
         if (bad_kind == 1) return fail(CG_EINVAL, "row %d is not a 5-point stencil row", bad_row);
         if (bad_kind == 2) return fail(CG_EINVAL, "diagonal of row %d is not positive", bad_row);
         if (bad_kind == 3) return fail(CG_EINVAL, "row %d has no diagonal entry", bad_row);
-        for (int32_t i = 0; i < n; ++i) g_rp[i + 1] += g_rp[i];
+        par_running_sum(g_rp.data(), n);
         g_ci.alloc((size_t)g_rp[n]);
         // pass 2: columns and slot positions (-1: no such neighbour)
 #pragma omp parallel for schedule(static)
