@@ -32,7 +32,9 @@ struct cg_batch {
     double *d_R = nullptr, *d_P = nullptr, *d_Q = nullptr;
     double *d_part = nullptr;
     int32_t *d_bar = nullptr, *d_err = nullptr, *d_episodes = nullptr;
-    int32_t *d_wg_sys = nullptr, *d_wg_rank = nullptr, *d_team_first = nullptr, *d_team_size = nullptr;
+    int32_t *d_wg_item = nullptr, *d_item_sys = nullptr, *d_item_rank = nullptr;
+    int32_t *d_team_first = nullptr, *d_team_size = nullptr;
+    int64_t item_cap = 0;       // entries of d_item_sys / d_item_rank
     int64_t *d_row_off = nullptr;
     int32_t *d_strip = nullptr;      // [nsys] line length of a strip-ordered phase A (0: row order)
     BatchOutDev *d_out = nullptr;
@@ -47,7 +49,7 @@ namespace {
 void batch_free(cg_batch *b) {
     for (void *p : {(void *)b->d_rp, (void *)b->d_ci, (void *)b->d_val, (void *)b->d_R, (void *)b->d_P,
                     (void *)b->d_Q, (void *)b->d_part, (void *)b->d_bar, (void *)b->d_err,
-                    (void *)b->d_episodes, (void *)b->d_wg_sys, (void *)b->d_wg_rank,
+                    (void *)b->d_episodes, (void *)b->d_wg_item, (void *)b->d_item_sys, (void *)b->d_item_rank,
                     (void *)b->d_team_first, (void *)b->d_team_size, (void *)b->d_row_off,
                     (void *)b->d_strip, (void *)b->d_out})
         (void)hipFree(p);
@@ -87,12 +89,18 @@ int validate_sched(const cg_batch_sched *s) {
     return CG_OK;
 }
 
-// Team sizes: the grid's workgroups shared in proportion to n_k^exponent,
-// at least one per system and at most one per 16 rows (or max_team).
 int lanes_variant(const cg_batch *b, const cg_batch_sched &s) {
     return (s.rhs_per_lane == 1 || (b->nrhs & 1)) ? 1 : 2;
 }
 
+// Workgroups per system, with w_k = n_k^exponent as a system's cost: the
+// smallest per-workgroup load L for which the batch fits the grid, where a
+// system heavier than L gets ceil(w_k / L) workgroups of its own (at most one
+// per 16 rows, at most max_team) and the lighter ones share workgroups of
+// capacity L (first fit, heaviest first; a workgroup then solves its systems
+// one after another).  Workgroups left over go, one at a time, to the team
+// with the largest load per workgroup that may still grow.  With few systems
+// every one is heavier than L and has a team of its own.
 int assign_teams(cg_batch *b, const cg_batch_sched &s) {
     const int occ = batch_blocks_per_cu(s.rows_per_thread, lanes_variant(b, s));
     if (occ <= 0) return fail(CG_EDEVICE, "occupancy query of the batched kernel failed");
@@ -103,54 +111,93 @@ int assign_teams(cg_batch *b, const cg_batch_sched &s) {
         return fail(CG_EINVAL, "%d systems exceed the %d workgroups one launch can keep resident", b->nsys,
                     std::min(resident, b->grid_cap));
     grid = std::max(grid, b->nsys);
-    std::vector<double> wgt(b->nsys);
-    std::vector<int32_t> cap(b->nsys), T(b->nsys, 1);
-    double wsum = 0.0;
-    for (int k = 0; k < b->nsys; ++k) {
+    const int nsys = b->nsys;
+    std::vector<double> wgt(nsys);
+    std::vector<int32_t> cap(nsys);
+    double wsum = 0.0, wmax = 0.0;
+    for (int k = 0; k < nsys; ++k) {
         const int64_t n = b->row_off[k + 1] - b->row_off[k];
-        wgt[k] = std::pow((double)n, s.team_exponent);
+        wgt[k] = std::pow((double)std::max<int64_t>(n, 1), s.team_exponent);
         wsum += wgt[k];
+        wmax = std::max(wmax, wgt[k]);
         int64_t c = std::max<int64_t>(1, n / kBatchRowsPerStep);
         if (s.max_team > 0) c = std::min<int64_t>(c, s.max_team);
         cap[k] = (int32_t)std::min<int64_t>(c, grid);
     }
-    // one workgroup per system, the remaining grid - nsys shared in
-    // proportion to w_k (largest remainder), never above cap_k: sum(T) <= grid
-    const int extra = grid - b->nsys;
-    int used = b->nsys;
-    std::vector<double> want(b->nsys);
-    for (int k = 0; k < b->nsys; ++k) {
-        want[k] = extra * wgt[k] / (wsum > 0 ? wsum : 1.0);
-        const int32_t add = std::min<int32_t>(cap[k] - 1, (int32_t)std::floor(want[k]));
-        T[k] = 1 + std::max<int32_t>(0, add);
-        used += T[k] - 1;
-    }
-    std::vector<int> order(b->nsys);
-    for (int k = 0; k < b->nsys; ++k) order[k] = k;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int x, int y) { return want[x] - (T[x] - 1) > want[y] - (T[y] - 1); });
-    for (int idx = 0; used < grid && idx < b->nsys; ++idx) {
-        const int k = order[idx];
-        if (T[k] < cap[k] && want[k] - (T[k] - 1) > 0.0) {
-            ++T[k];
-            ++used;
+    std::vector<int> order(nsys);
+    for (int k = 0; k < nsys; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return wgt[x] > wgt[y]; });
+    std::vector<int32_t> T(nsys), bin_of(nsys);
+    std::vector<double> bins;
+    // workgroups used at load L (T, bin_of and bins filled in)
+    auto plan = [&](double L) -> int64_t {
+        int64_t used = 0;
+        bins.clear();
+        for (int k : order) {
+            if (wgt[k] > L) {
+                T[k] = (int32_t)std::min<int64_t>(cap[k], (int64_t)std::ceil(wgt[k] / L));
+                bin_of[k] = -1;
+                used += T[k];
+                continue;
+            }
+            T[k] = 1;
+            size_t i = 0;
+            while (i < bins.size() && bins[i] + wgt[k] > L) ++i;
+            if (i == bins.size()) bins.push_back(0.0);
+            bins[i] += wgt[k];
+            bin_of[k] = (int32_t)i;
         }
+        return used + (int64_t)bins.size();
+    };
+    double lo = wsum / grid, hi = std::max(wmax, lo);
+    for (int it = 0; it < 60 && plan(lo) > grid; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (plan(mid) <= grid) hi = mid;
+        else lo = mid;
     }
-    if (used > grid || used > b->grid_cap) return fail(CG_EDEVICE, "team assignment exceeds the grid");
-    std::vector<int32_t> wg_sys(used), wg_rank(used), first(b->nsys);
+    int64_t used = plan(plan(lo) <= grid ? lo : hi);
+    if (used > grid) return fail(CG_EDEVICE, "team assignment exceeds the grid");
+    while (used < grid) {
+        int best = -1;
+        for (int k : order)
+            if (bin_of[k] < 0 && T[k] < cap[k] && (best < 0 || wgt[k] / T[k] > wgt[best] / T[best])) best = k;
+        if (best < 0) break;
+        ++T[best];
+        ++used;
+    }
+    // workgroups: the teams of their own (in system order), then the shared ones
+    const int nbins = (int)bins.size();
+    std::vector<int32_t> wg_item((size_t)used + 1), item_sys, item_rank, first(nsys);
+    std::vector<std::vector<int32_t>> in_bin((size_t)nbins);
+    for (int k = 0; k < nsys; ++k)
+        if (bin_of[k] >= 0) in_bin[(size_t)bin_of[k]].push_back(k);
     int w = 0;
-    for (int k = 0; k < b->nsys; ++k) {
+    for (int k = 0; k < nsys; ++k) {
+        if (bin_of[k] >= 0) continue;
         first[k] = w;
         for (int r = 0; r < T[k]; ++r, ++w) {
-            wg_sys[w] = k;
-            wg_rank[w] = r;
+            wg_item[(size_t)w] = (int32_t)item_sys.size();
+            item_sys.push_back(k);
+            item_rank.push_back(r);
         }
     }
-    HIP_TRY(hipMemcpy(b->d_wg_sys, wg_sys.data(), sizeof(int32_t) * used, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(b->d_wg_rank, wg_rank.data(), sizeof(int32_t) * used, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(b->d_team_first, first.data(), sizeof(int32_t) * b->nsys, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(b->d_team_size, T.data(), sizeof(int32_t) * b->nsys, hipMemcpyHostToDevice));
-    b->grid = used;
+    for (int i = 0; i < nbins; ++i, ++w) {
+        wg_item[(size_t)w] = (int32_t)item_sys.size();
+        for (int k : in_bin[(size_t)i]) {
+            first[k] = w;
+            item_sys.push_back(k);
+            item_rank.push_back(0);
+        }
+    }
+    wg_item[(size_t)used] = (int32_t)item_sys.size();
+    if (w != used || (int64_t)item_sys.size() > b->item_cap)
+        return fail(CG_EDEVICE, "team assignment exceeds the grid");
+    HIP_TRY(hipMemcpy(b->d_wg_item, wg_item.data(), sizeof(int32_t) * ((size_t)used + 1), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(b->d_item_sys, item_sys.data(), sizeof(int32_t) * item_sys.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(b->d_item_rank, item_rank.data(), sizeof(int32_t) * item_rank.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(b->d_team_first, first.data(), sizeof(int32_t) * nsys, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(b->d_team_size, T.data(), sizeof(int32_t) * nsys, hipMemcpyHostToDevice));
+    b->grid = (int)used;
     b->team_size = T;
     b->sched = s;
     return CG_OK;
@@ -238,8 +285,10 @@ extern "C" int cg_batch_create(int32_t nsys, const int32_t *n, const int64_t *nn
     if (e == hipSuccess) e = dmalloc(&b->d_bar, (size_t)nsys);
     if (e == hipSuccess) e = dmalloc(&b->d_err, 1);
     if (e == hipSuccess) e = dmalloc(&b->d_episodes, (size_t)nsys);
-    if (e == hipSuccess) e = dmalloc(&b->d_wg_sys, (size_t)b->grid_cap);
-    if (e == hipSuccess) e = dmalloc(&b->d_wg_rank, (size_t)b->grid_cap);
+    b->item_cap = (int64_t)b->grid_cap + nsys;   // one item per team member plus one per shared system
+    if (e == hipSuccess) e = dmalloc(&b->d_wg_item, (size_t)b->grid_cap + 1);
+    if (e == hipSuccess) e = dmalloc(&b->d_item_sys, (size_t)b->item_cap);
+    if (e == hipSuccess) e = dmalloc(&b->d_item_rank, (size_t)b->item_cap);
     if (e == hipSuccess) e = dmalloc(&b->d_team_first, (size_t)nsys);
     if (e == hipSuccess) e = dmalloc(&b->d_team_size, (size_t)nsys);
     if (e == hipSuccess) e = dmalloc(&b->d_row_off, (size_t)nsys + 1);
@@ -330,8 +379,9 @@ extern "C" int cg_batch_solve(cg_batch *b, const double *B, double *X, double to
     a.part = b->d_part;
     a.bar = b->d_bar;
     a.err = b->d_err;
-    a.wg_sys = b->d_wg_sys;
-    a.wg_rank = b->d_wg_rank;
+    a.wg_item = b->d_wg_item;
+    a.item_sys = b->d_item_sys;
+    a.item_rank = b->d_item_rank;
     a.team_first = b->d_team_first;
     a.team_size = b->d_team_size;
     a.row_off = b->d_row_off;

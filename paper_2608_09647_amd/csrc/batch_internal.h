@@ -28,9 +28,10 @@ struct BatchArgs {
     double *part;               // [grid][kBatchSlots][kBatchLanes] partial sums
     int32_t *bar;               // [nsys] team barrier counters (0 at launch)
     int32_t *err;               // [1] set when a team wait times out
-    const int32_t *wg_sys;      // [grid] system of the workgroup (-1: idle)
-    const int32_t *wg_rank;     // [grid] rank of the workgroup in its team
-    const int32_t *team_first;  // [nsys] first workgroup of the team
+    const int32_t *wg_item;     // [grid + 1] the workgroup's items are wg_item[w] .. wg_item[w+1]-1
+    const int32_t *item_sys;    // [items] system of an item
+    const int32_t *item_rank;   // [items] rank of the workgroup in that system's team
+    const int32_t *team_first;  // [nsys] first workgroup of the team (the hosting one for a team of one)
     const int32_t *team_size;   // [nsys]
     const int64_t *row_off;     // [nsys + 1]
     const int32_t *strip;       // [nsys] line length D of a strip-ordered phase A (0: row order)

@@ -7,6 +7,14 @@
 // contiguous 128-byte line and a gathered p_c of all right-hand sides is one
 // line per column c.
 //
+// A workgroup works through a list of items, each a (system, rank in its
+// team) pair, one after the other: heavy systems get teams of their own,
+// while light systems that a single workgroup solves are packed, several to
+// a workgroup, so that the grid's work evens out.  The host builds the lists
+// (first-fit decreasing on weights n_k^e); an item that belongs to a team of
+// more than one workgroup is always its workgroup's only item, so no team
+// barrier waits on a workgroup that is still busy with an earlier system.
+//
 // One iteration is three phases separated by team barriers:
 //   A: q = A p on the team's rows, partial p^T q per right-hand side;
 //   B: alpha = rho / p^T q (team sum), r -= alpha q, partial r^T r;
@@ -393,15 +401,15 @@ __device__ __forceinline__ void spmv_rows_strips(const BatchArgs &a, int64_t off
 // U: rows a thread advances per step in the setup and the vector phases B
 // and C (phase A keeps three rows in flight by itself); V: right-hand sides
 // per lane (2 needs an even nrhs and 16-byte aligned vectors).
+// One system's solve by this workgroup as member `rank` of its team (the
+// whole solve when the team is the workgroup alone).  False when the launch
+// is being abandoned (a team wait gave up).
 template <int U, int V>
-__global__ __launch_bounds__(kT) void k_batch_cg(BatchArgs a) {
+__device__ __forceinline__ bool batch_solve_one(const BatchArgs &a, int sys, int rank, Shared &S) {
     constexpr int LPR = kL / V;          // lanes per row
     constexpr int RS = kT / LPR;         // rows per workgroup step
-    __shared__ Shared S;
     const int w = blockIdx.x;
-    const int sys = a.wg_sys[w];
-    if (sys < 0) return;
-    const int T = a.team_size[sys], rank = a.wg_rank[w], first = a.team_first[sys];
+    const int T = a.team_size[sys], first = a.team_first[sys];
     const int64_t off = a.row_off[sys], n = a.row_off[sys + 1] - off;
     const int64_t lo = off + n * rank / T, hi = off + n * (rank + 1) / T;
     const int nr = a.nrhs;
@@ -438,7 +446,7 @@ __global__ __launch_bounds__(kT) void k_batch_cg(BatchArgs a) {
         wg_partial<V>(arr, mypart + kSlotRR * kL, S);
         wg_partial<V>(abb, mypart + kSlotBB * kL, S);
     }
-    if (!team_sync(a, sys, T, episode, S)) return;
+    if (!team_sync(a, sys, T, episode, S)) return false;
     team_sum(a, first, T, kSlotRR, S);
     if (threadIdx.x < kL) S.rr_last[threadIdx.x] = S.sum[threadIdx.x];
     __syncthreads();
@@ -489,7 +497,7 @@ __global__ __launch_bounds__(kT) void k_batch_cg(BatchArgs a) {
             }
             wg_partial<V>(acc, mypart + kSlotPQ * kL, S);
         }
-        if (!team_sync(a, sys, T, episode, S)) return;
+        if (!team_sync(a, sys, T, episode, S)) return false;
         team_sum(a, first, T, kSlotPQ, S);
         if (threadIdx.x < kL) {
             const int t = threadIdx.x;
@@ -542,7 +550,7 @@ __global__ __launch_bounds__(kT) void k_batch_cg(BatchArgs a) {
                     }
             wg_partial<V>(acc, mypart + kSlotRR * kL, S);
         }
-        if (!team_sync(a, sys, T, episode, S)) return;
+        if (!team_sync(a, sys, T, episode, S)) return false;
         team_sum(a, first, T, kSlotRR, S);
         if (threadIdx.x < kL) {
             const int t = threadIdx.x;
@@ -610,7 +618,7 @@ __global__ __launch_bounds__(kT) void k_batch_cg(BatchArgs a) {
                     }
         }
         if (!S.any) break;       // the x updates above reach the team at the next barrier
-        if (!team_sync(a, sys, T, episode, S)) return;
+        if (!team_sync(a, sys, T, episode, S)) return false;
     }
 
     // b = 0: the solution is x = 0
@@ -619,7 +627,7 @@ __global__ __launch_bounds__(kT) void k_batch_cg(BatchArgs a) {
 #pragma unroll
             for (int q = 0; q < V; ++q)
                 if (S.zero_b[j0 + q]) a.X[row * nr + j0 + q] = 0.0;
-    if (!team_sync(a, sys, T, episode, S)) return;
+    if (!team_sync(a, sys, T, episode, S)) return false;
     // true residual ||b - A x||^2
     {
         double acc[V];
@@ -639,7 +647,7 @@ __global__ __launch_bounds__(kT) void k_batch_cg(BatchArgs a) {
             }
         wg_partial<V>(acc, mypart + kSlotTrue * kL, S);
     }
-    if (!team_sync(a, sys, T, episode, S)) return;
+    if (!team_sync(a, sys, T, episode, S)) return false;
     team_sum(a, first, T, kSlotTrue, S);
     if (rank == 0) {
         if (threadIdx.x < nr) {
@@ -653,6 +661,24 @@ __global__ __launch_bounds__(kT) void k_batch_cg(BatchArgs a) {
             a.out[(int64_t)sys * nr + t] = o;
         }
         if (threadIdx.x == 0) a.episodes[sys] = episode;
+    }
+    return true;
+}
+
+// Each workgroup solves its list of systems one after another: a member of a
+// team of several workgroups has one, a workgroup hosting small systems
+// (teams of one) several, so their rows share workgroups instead of each
+// taking one.
+template <int U, int V>
+__global__ __launch_bounds__(kT) void k_batch_cg(BatchArgs a) {
+    __shared__ Shared S;
+    const int i0 = __builtin_amdgcn_readfirstlane(a.wg_item[blockIdx.x]);
+    const int i1 = __builtin_amdgcn_readfirstlane(a.wg_item[blockIdx.x + 1]);
+    for (int it = i0; it < i1; ++it) {
+        const int sys = __builtin_amdgcn_readfirstlane(a.item_sys[it]);
+        const int rank = __builtin_amdgcn_readfirstlane(a.item_rank[it]);
+        if (!batch_solve_one<U, V>(a, sys, rank, S)) return;
+        __syncthreads();   // S is set up afresh by the next system
     }
 }
 
