@@ -6,11 +6,13 @@
  * side (Algorithm 1): this runs Algorithm 1 independently for every pair
  * (system k, right-hand side j) -- its own alpha, beta, stop test and
  * iteration count -- with all pairs advancing inside a single kernel launch.
- * Every system is given a team of workgroups that owns a contiguous share of
- * its rows for the whole solve; a team synchronises through counters in
+ * A heavy system is given a team of workgroups that owns a contiguous share
+ * of its rows for the whole solve; a team synchronises through counters in
  * device memory between the phases of an iteration (q = A p with p^T q;
  * x/r update with r^T r; p update) and stops when all of its right-hand sides
- * have converged, broken down or reached maxit.  The launch is cooperative,
+ * have converged, broken down or reached maxit.  Light systems share
+ * workgroups: a workgroup solves its light systems one after another, so the
+ * number of systems is not bounded by the grid.  The launch is cooperative,
  * so every workgroup is resident; a wait that exceeds a time limit ends the
  * launch with CG_EDEVICE instead of hanging.
  *
@@ -81,8 +83,10 @@ typedef struct cg_batch_stats {
     int32_t barriers;       /* team barriers passed by the largest team */
 } cg_batch_stats;
 
-/* nsys systems (n[k] rows, nnz[k] entries, CSR with local column indices)
- * and nrhs right-hand sides each (1 <= nrhs <= CG_BATCH_MAX_RHS). */
+/* nsys >= 1 systems (n[k] rows, nnz[k] entries, CSR with local column
+ * indices) and nrhs right-hand sides each (1 <= nrhs <= CG_BATCH_MAX_RHS).
+ * nsys may exceed the workgroups of one launch (light systems share
+ * workgroups); the stacked row count and entry count must fit int32. */
 int cg_batch_create(int32_t nsys, const int32_t *n, const int64_t *nnz,
                     const int32_t *const *row_ptr, const int32_t *const *col,
                     const double *const *val, int32_t nrhs, cg_batch **out);

@@ -104,13 +104,8 @@ int lanes_variant(const cg_batch *b, const cg_batch_sched &s) {
 int assign_teams(cg_batch *b, const cg_batch_sched &s) {
     const int occ = batch_blocks_per_cu(s.rows_per_thread, lanes_variant(b, s));
     if (occ <= 0) return fail(CG_EDEVICE, "occupancy query of the batched kernel failed");
-    const int resident = occ * b->cus;
     int grid = std::min(s.blocks_per_cu, occ) * b->cus;
-    grid = std::min(grid, b->grid_cap);
-    if (b->nsys > std::min(resident, b->grid_cap))
-        return fail(CG_EINVAL, "%d systems exceed the %d workgroups one launch can keep resident", b->nsys,
-                    std::min(resident, b->grid_cap));
-    grid = std::max(grid, b->nsys);
+    grid = std::max(1, std::min(grid, b->grid_cap));
     const int nsys = b->nsys;
     std::vector<double> wgt(nsys);
     std::vector<int32_t> cap(nsys);
@@ -128,34 +123,53 @@ int assign_teams(cg_batch *b, const cg_batch_sched &s) {
     for (int k = 0; k < nsys; ++k) order[k] = k;
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return wgt[x] > wgt[y]; });
     std::vector<int32_t> T(nsys), bin_of(nsys);
-    std::vector<double> bins;
-    // workgroups used at load L (T, bin_of and bins filled in)
+    // First fit over the shared workgroups: a tree of the smallest load in
+    // each range of bins finds the leftmost bin with load + w <= L in
+    // O(log grid) (a rounded sum is monotone in the load, so the subtree
+    // test is exact); bins not yet opened hold load 0.
+    int leaves = 1;
+    while (leaves < grid + 1) leaves <<= 1;
+    std::vector<double> tree(2 * (size_t)leaves);
+    int nbins = 0;
+    // workgroups used at load L (T, bin_of, tree and nbins filled in);
+    // stops early, returning grid + 1, once the plan cannot fit the grid
     auto plan = [&](double L) -> int64_t {
         int64_t used = 0;
-        bins.clear();
+        std::fill(tree.begin(), tree.end(), 0.0);
+        nbins = 0;
         for (int k : order) {
-            if (wgt[k] > L) {
+            if (wgt[k] > L) {   // heavier than L: a team of its own (these come first)
                 T[k] = (int32_t)std::min<int64_t>(cap[k], (int64_t)std::ceil(wgt[k] / L));
                 bin_of[k] = -1;
                 used += T[k];
+                if (used > grid) return (int64_t)grid + 1;
                 continue;
             }
             T[k] = 1;
-            size_t i = 0;
-            while (i < bins.size() && bins[i] + wgt[k] > L) ++i;
-            if (i == bins.size()) bins.push_back(0.0);
-            bins[i] += wgt[k];
-            bin_of[k] = (int32_t)i;
+            size_t v = 1;
+            while (v < (size_t)leaves) v = tree[2 * v] + wgt[k] <= L ? 2 * v : 2 * v + 1;
+            const int i = (int)(v - (size_t)leaves);
+            if (i >= nbins) nbins = i + 1;
+            if (used + nbins > grid) return (int64_t)grid + 1;
+            tree[v] += wgt[k];
+            for (v >>= 1; v >= 1; v >>= 1) tree[v] = std::min(tree[2 * v], tree[2 * v + 1]);
+            bin_of[k] = i;
         }
-        return used + (int64_t)bins.size();
+        return used + nbins;
     };
+    // smallest load limit that fits: any L >= wmax places every system in
+    // shared workgroups, and L = wsum needs only one
     double lo = wsum / grid, hi = std::max(wmax, lo);
-    for (int it = 0; it < 60 && plan(lo) > grid; ++it) {
-        const double mid = 0.5 * (lo + hi);
-        if (plan(mid) <= grid) hi = mid;
-        else lo = mid;
-    }
-    int64_t used = plan(plan(lo) <= grid ? lo : hi);
+    if (plan(hi) > grid) hi = std::max(hi, 2.0 * wsum);
+    if (plan(lo) > grid)
+        for (int it = 0; it < 60; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (plan(mid) <= grid) hi = mid;
+            else lo = mid;
+        }
+    else
+        hi = lo;
+    int64_t used = plan(hi);
     if (used > grid) return fail(CG_EDEVICE, "team assignment exceeds the grid");
     while (used < grid) {
         int best = -1;
@@ -166,7 +180,6 @@ int assign_teams(cg_batch *b, const cg_batch_sched &s) {
         ++used;
     }
     // workgroups: the teams of their own (in system order), then the shared ones
-    const int nbins = (int)bins.size();
     std::vector<int32_t> wg_item((size_t)used + 1), item_sys, item_rank, first(nsys);
     std::vector<std::vector<int32_t>> in_bin((size_t)nbins);
     for (int k = 0; k < nsys; ++k)
@@ -273,7 +286,7 @@ extern "C" int cg_batch_create(int32_t nsys, const int32_t *n, const int64_t *nn
     for (int u = 1; u <= 2; ++u)
         for (int v = 1; v <= 2; ++v) occ = std::max(occ, batch_blocks_per_cu(u, v));
     if (occ <= 0) return bail(fail(CG_EDEVICE, "occupancy query of the batched kernel failed"));
-    b->grid_cap = std::max(occ * b->cus, nsys);
+    b->grid_cap = occ * b->cus;
     const size_t vec = (size_t)rows * nrhs;
     hipError_t e = dmalloc(&b->d_rp, (size_t)rows + 1);
     if (e == hipSuccess) e = dmalloc(&b->d_ci, (size_t)ents);

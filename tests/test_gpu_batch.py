@@ -149,6 +149,35 @@ def test_multi_workgroup_teams_are_used(cg):
     assert code == cg.CG_OK and np.all(res["rel_res_true"] <= 1.01e-10)
 
 
+@pytest.mark.parametrize("sched", [{}, {"blocks_per_cu": 1}, {"blocks_per_cu": 8, "rhs_per_lane": 1}])
+def test_more_systems_than_workgroups(cg, sched):
+    """Light systems share workgroups, so one launch holds more systems than
+    it has workgroups: 2,500 systems of 9 to 100 rows on a grid of at most
+    256 x occupancy.  Every pair meets the oracle's bar, and a system placed
+    twice (first and last, same right-hand sides) gives identical bits."""
+    rng = np.random.default_rng(11)
+    sides = rng.integers(3, 11, 2500)
+    systems = [field(int(s), 100 + i) for i, s in enumerate(sides)]
+    systems[-1] = systems[0]
+    nrhs = 2
+    xs, bs = make_batch(systems, nrhs, seed=12)
+    bs[-1] = bs[0].copy()
+    print(f"[batch] {len(systems)} systems, sched={sched}", flush=True)
+    X, res, st, code = run_batch(cg, systems, bs, nrhs, **sched)
+    print(f"[batch] stats {st}", flush=True)
+    assert code == cg.CG_OK and st["grid"] < len(systems)
+    assert np.array_equal(X[0], X[-1]) and np.array_equal(res[0], res[-1])
+    for k, A in enumerate(systems):
+        kap = kappa(A)
+        for j in range(nrhs):
+            ref = oracle.cg(A, bs[k][:, j], tol=1e-10, maxit=20000)
+            r = res[k, j]
+            assert ref["status"] == 0 and r["status"] == 0, (k, j)
+            assert abs(int(r["iterations"]) - ref["iterations"]) <= max(2, 0.05 * ref["iterations"]), (k, j)
+            assert r["rel_res_true"] <= 1.01e-10, (k, j)
+            assert np.linalg.norm(X[k][:, j] - ref["x"]) <= 2 * kap * 1e-10 * np.linalg.norm(ref["x"]), (k, j)
+
+
 def test_duplicate_systems_give_identical_bits(cg):
     A = field(30, 7)
     B2 = field(12, 8)
