@@ -24,6 +24,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X, all 256 compute units
+N_CUS = 256
 
 
 SPMV_EVENT_STRIDE = 10
@@ -161,7 +163,9 @@ def cpu_baseline_cg(problem, iters_hint: int, target_s: float = 12.0) -> dict:
                       f"({dt:.1f} s, including its setup residual and final true residual)"}
 
 
-def _timed_solve(solver, b, x0, tol, maxit, reps):
+def _timed_solve(solver, b, x0, tol, maxit, reps, ktimes=None):
+    """ktimes: when a list, the event-timed seconds of each solve's one
+    launch (single-workgroup path with cg_opts.profile) are appended."""
     import torch
     times, res = [], None
     x = x0.clone()            # returned as is when reps = 0 (no warmup)
@@ -172,6 +176,8 @@ def _timed_solve(solver, b, x0, tol, maxit, reps):
         _, res = solver.solve(b, x, tol=tol, maxit=maxit)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
+        if ktimes is not None and res["n_spmv"] == 1:
+            ktimes.append(res["t_spmv"])
     return x, res, times
 
 
@@ -192,12 +198,15 @@ def bench_time_to_tol(args, prob, variants, metric, workload, extra=None):
         autotune.spmv_schedule(solver, prob.A, b, tune_if_missing=False)   # tabled SpMV tiling, if any
         solver.set_opts(**opts)
         _timed_solve(solver, b, x0, 1e-10, 200000, args.warmup)
-        x, res, times = _timed_solve(solver, b, x0, 1e-10, 200000, args.steps)
+        ktimes = []
+        x, res, times = _timed_solve(solver, b, x0, 1e-10, 200000, args.steps, ktimes)
         xs[name] = x.cpu().numpy()
         out[name] = {"seconds": float(np.mean(times)), "min_seconds": float(np.min(times)),
                      "iterations": res["iterations"], "fp64_residuals": res["fp64_residuals"],
                      "rel_res_true": res["rel_res_true"], "status": res["code"],
                      "fell_back": res["fell_back"]}
+        if ktimes:
+            out[name]["kernel_seconds"] = float(np.mean(ktimes))
         solver.close()
         print(f"[bench] {name}: {out[name]}", file=sys.stderr, flush=True)
     return out, xs
@@ -487,13 +496,35 @@ def bench_small(args) -> int:
     """2D Poisson 64x64 to 1e-10, all rows on the GPU (single-workgroup path)."""
     from paper_2608_09647_amd import inputs as I
     prob = I.poisson2d_problem(64, seed=1)
+    # the third variant repeats the first with an event pair around its
+    # launch (kept out of the headline solves, where it would add stream time)
     out, _ = bench_time_to_tol(args, prob, {"small_path": {"small_path": 1},
-                                            "multi_kernel": {"small_path": 0}}, None, None)
+                                            "multi_kernel": {"small_path": 0},
+                                            "small_path_events": {"small_path": 1, "profile": 1}},
+                               None, None)
     best = out["small_path"]
+    # Roofline of the one launch: the solve is a single workgroup on one
+    # compute unit, with A in registers and p in LDS, so no HBM or chip-wide
+    # figure bounds it; it is priced against that unit's float64 vector rate
+    # (78.6 TFLOP/s over 256 CUs).  Algorithmic flops per iteration: the
+    # SpMV's 2 nnz, two dot products and three vector updates of 2 n each.
+    flops_it = 2 * prob.A.nnz + 10 * prob.A.n
+    cu_peak = FP64_VECTOR_PEAK_TFLOPS / N_CUS
+    ev = out["small_path_events"]
+    ks = ev.get("kernel_seconds")
+    ach = flops_it * ev["iterations"] / ks / 1e12 if ks else None
     line = _line("CG iterations/s to 1e-10 (2D Poisson 64x64)",
                  best["iterations"] / best["seconds"], "iter/s", args, 1e3 * best["seconds"],
                  {"workload": "poisson2d_5pt_64x64_fp64_cg_to_1e-10", "n": prob.A.n,
-                  "nnz": prob.A.nnz, "seed": 1}, paths=out)
+                  "nnz": prob.A.nnz, "seed": 1},
+                 roofline={"bound": "alu", "achieved": ach, "peak": cu_peak, "unit": "TFLOP/s",
+                           "frac": ach / cu_peak if ach else None, "traffic": None,
+                           "kernel": "k_cg_small (one launch per solve)", "launch_us": 1e6 * ks if ks else None,
+                           "flops_per_iteration": flops_it,
+                           "scope": "one compute unit: the whole solve is one workgroup",
+                           "note": "latency-bound: three workgroup barriers, two 16-term serial sums "
+                                   "and two float64 divisions per iteration"},
+                 paths=out)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_repeat(prob)
     print(json.dumps(line), flush=True)

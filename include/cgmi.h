@@ -93,7 +93,9 @@ typedef struct cg_opts {
                               (cg_result.t_spmv / n_spmv over those launches;
                               an event pair costs a few microseconds of stream
                               time, so a sparse sample disturbs the solve
-                              less); 0: off                                      */
+                              less); on the single-workgroup path the pair
+                              brackets the one launch of the whole solve
+                              (n_spmv = 1); 0: off                               */
     int32_t small_path;    /* 1 (default): systems that fit one workgroup's LDS
                               run the whole solve in one single-workgroup kernel */
     int32_t spmv_grid;     /* workgroups of the SpMV kernels (0: automatic)      */

@@ -659,9 +659,21 @@ int solve_plain(cg_handle *h, const PlainWork &w, const double *b, double *x, do
             for (int32_t i = 0; i < n; ++i) L = std::max(L, h->A.h_rp[i + 1] - h->A.h_rp[i]);
             h->max_row_len = L;
         }
+        // cg_opts.profile: an event pair around the one launch
+        struct EventPair {
+            hipEvent_t a = nullptr, b = nullptr;
+            ~EventPair() {
+                if (a) (void)hipEventDestroy(a);
+                if (b) (void)hipEventDestroy(b);
+            }
+        } evp;
+        const bool timed = w.events && h->opts.profile > 0 && hipEventCreate(&evp.a) == hipSuccess &&
+                           hipEventCreate(&evp.b) == hipSuccess;
         const double t0 = now();
+        if (timed) HIP_TRY(hipEventRecord(evp.a, st));
         HIP_TRY(launch_cg_small(n, h->A.d_rp, h->A.d_ci, h->A.d_val, b, x, tol, maxit, w.state,
                                 h->max_row_len, st));
+        if (timed) HIP_TRY(hipEventRecord(evp.b, st));
         const int rc = work_state_read(h, w);
         if (rc) return rc;
         const DevState &s = *w.h_state;
@@ -673,6 +685,12 @@ int solve_plain(cg_handle *h, const PlainWork &w, const double *b, double *x, do
             res->rel_res_recur = s.bb > 0.0 ? std::sqrt(s.rr) / std::sqrt(s.bb) : 0.0;
             res->rel_res_true = s.bb > 0.0 ? std::sqrt(s.rr_true) / std::sqrt(s.bb) : 0.0;
             res->t_gpu = now() - t0;
+            if (timed) {
+                float ms = 0.0f;
+                HIP_TRY(hipEventElapsedTime(&ms, evp.a, evp.b));
+                res->t_spmv = 1e-3 * ms;
+                res->n_spmv = 1;
+            }
         }
         return status;
     }

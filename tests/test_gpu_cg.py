@@ -1069,3 +1069,18 @@ def test_host_vectors_match_device_vectors(cg, case):
     assert np.array_equal(y_host, y_dev) and np.array_equal(x_host, x_dev)
     assert r_host["code"] == r_dev["code"] == cg.CG_OK and r_host["iterations"] == r_dev["iterations"]
     assert r_host["rel_res_true"] == r_dev["rel_res_true"]
+
+
+def test_small_path_launch_is_event_timed(cg):
+    """cg_opts.profile on the single-workgroup path: an event pair around the
+    one launch gives t_spmv (n_spmv = 1), within the host-timed t_gpu; the
+    solution is bitwise the one of the unprofiled solve."""
+    p = I.poisson2d_problem(64, seed=1)
+    with cg.Solver(p.A) as s:
+        s.set_opts(small_path=1)
+        x0, r0 = s.solve(dev(p.b), tol=1e-10, maxit=20000)
+        assert r0["n_spmv"] == 0 and r0["t_spmv"] == 0.0
+        s.set_opts(profile=1)
+        x1, r1 = s.solve(dev(p.b), tol=1e-10, maxit=20000)
+    assert r1["n_spmv"] == 1 and 0.0 < r1["t_spmv"] <= r1["t_gpu"]
+    assert r1["iterations"] == r0["iterations"] and np.array_equal(host(x0), host(x1))
